@@ -1,0 +1,395 @@
+/*
+ * kde_oracle.c -- plain, slow, brute-force CPU reference for ROI kernel
+ * density estimation (ScaleFree, arXiv 2601.20758, Section 3.1).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do. It shares no code, header or constant with the
+ * HIP implementation.
+ *
+ * Conventions (the readings of the paper that every function below follows):
+ *  - Grid nodes are vertex-centred on the closed box B: along axis k,
+ *    x_i = (float)(lo + (i * (hi - lo)) / (res - 1)) evaluated in double and
+ *    rounded once (Section 3.1 places nodes on a uniform grid over B and calls
+ *    their distance the node spacing s_k = (hi - lo) / (res - 1)).
+ *  - Linear node index x fastest: idx = x + y*res_x + z*res_x*res_y
+ *    (Algorithm 2 and Algorithm 4 index the density buffer this way).
+ *  - Support membership is decided in float32 on the float32 inputs by one
+ *    fixed operation sequence (the "canonical predicate"):
+ *        d_k = fl(x_nk - p_k);  u_k = fl(d_k * ih_k);
+ *        u2  = fl(fl(fl(u_x*u_x) + fl(u_y*u_y)) + fl(u_z*u_z));
+ *        member  <=>  u2 < c2
+ *    with ih_k = (float)(1 / h_k) the inverse bandwidth and c2 = 1 for the
+ *    Epanechnikov kernel (Eq. 4: zero for |x| >= 1, so the support boundary
+ *    is excluded) and c2 = 9 for the Gaussian truncated at 3h.
+ *    This is the per-axis scaled distance of Eq. 3 and Algorithm 2.
+ *  - Kernel values are computed in double from the same float inputs.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared.
+ * Every loop over particles runs in index order inside one thread, so results
+ * do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EPANECHNIKOV 0
+#define ORC_GAUSS_TRUNC3 1
+#define ORC_COUNT 2
+
+/* ------------------------------------------------------------------------ */
+/* Kernel normalisation constants.                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Epanechnikov in 3D: 15 / (8 pi), the prefactor of Eq. 2 and Eq. 7. */
+double orc_ck_epanechnikov(void) { return 15.0 / (8.0 * M_PI); }
+
+/* Probability that a 3D standard normal vector has norm < 3, i.e.
+ * P(chi^2_3 < 9) = erf(3/sqrt 2) - sqrt(2/pi) * 3 * exp(-9/2). */
+double orc_p_chi2_3_below_9(void) {
+  return erf(3.0 / sqrt(2.0)) - sqrt(2.0 / M_PI) * 3.0 * exp(-4.5);
+}
+
+/* Gaussian with sigma = h truncated at 3h and renormalised to unit mass:
+ * 1 / ((2 pi)^{3/2} P(chi^2_3 < 9)). The paper uses only the Epanechnikov
+ * kernel; the truncated Gaussian serves the per-point bandwidth workload. */
+double orc_ck_gauss_trunc3(void) {
+  return 1.0 / (pow(2.0 * M_PI, 1.5) * orc_p_chi2_3_below_9());
+}
+
+double orc_kernel_ck(int kernel) {
+  if (kernel == ORC_EPANECHNIKOV) return orc_ck_epanechnikov();
+  if (kernel == ORC_GAUSS_TRUNC3) return orc_ck_gauss_trunc3();
+  return 1.0;
+}
+
+float orc_kernel_c2(int kernel) {
+  return kernel == ORC_GAUSS_TRUNC3 ? 9.0f : 1.0f;
+}
+
+/* Kernel profile of the squared scaled distance u2 (double). Eq. 4 for the
+ * Epanechnikov kernel; exp(-u2/2) for the Gaussian; 1 for counting. */
+double orc_kernel_value(int kernel, double u2) {
+  if (kernel == ORC_EPANECHNIKOV) {
+    double v = 1.0 - u2;
+    return v > 0.0 ? v : 0.0;
+  }
+  if (kernel == ORC_GAUSS_TRUNC3) return exp(-0.5 * u2);
+  return 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid geometry.                                                           */
+/* ------------------------------------------------------------------------ */
+
+float orc_node_coord(double lo, double hi, int res, int i) {
+  return (float)(lo + ((double)i * (hi - lo)) / (double)(res - 1));
+}
+
+void orc_axis_coords(double lo, double hi, int res, float* out) {
+  for (int i = 0; i < res; ++i) out[i] = orc_node_coord(lo, hi, res, i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Canonical float32 membership predicate.                                  */
+/* ------------------------------------------------------------------------ */
+
+float orc_u2_f32(float xn, float yn, float zn, float px, float py, float pz,
+                 float ihx, float ihy, float ihz) {
+  volatile float dx = xn - px, dy = yn - py, dz = zn - pz;
+  volatile float ux = dx * ihx, uy = dy * ihy, uz = dz * ihz;
+  volatile float sx = ux * ux, sy = uy * uy, sz = uz * uz;
+  volatile float sxy = sx + sy;
+  volatile float s = sxy + sz;
+  return s;
+}
+
+/* Squared scaled distance in double from the same float inputs. */
+double orc_u2_f64(float xn, float yn, float zn, float px, float py, float pz,
+                  float ihx, float ihy, float ihz) {
+  double ux = ((double)xn - (double)px) * (double)ihx;
+  double uy = ((double)yn - (double)py) * (double)ihy;
+  double uz = ((double)zn - (double)pz) * (double)ihz;
+  return ux * ux + uy * uy + uz * uz;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density at grid nodes (Eq. 2 with a uniform bandwidth, Eq. 7 with a      */
+/* per-particle bandwidth).                                                 */
+/*                                                                          */
+/*  rho(n) = scale * sum_j [u2_f32(n, j) < c2] * w_j * K(u2_f64(n, j))      */
+/*                                                                          */
+/* pts      n x 3 float positions                                           */
+/* ih_pp    n x 3 per-particle inverse bandwidths, or NULL -> ih_u          */
+/* w_pp     n per-particle weights 1/(h_x h_y h_z), or NULL -> w_u          */
+/* include  n flags (nonzero = particle takes part), or NULL -> all         */
+/* nodes    node linear indices to evaluate (x fastest), count n_nodes      */
+/* scale    C_K * nu (nu = 1/N or 1)                                        */
+/* ------------------------------------------------------------------------ */
+void orc_density_nodes(const float* pts, int64_t n, const float* ih_pp,
+                       const double* w_pp, const float* ih_u, double w_u,
+                       const uint8_t* include, int kernel, const double* lo,
+                       const double* hi, const int* res, double scale,
+                       const int64_t* nodes, int64_t n_nodes, double* out) {
+  const float c2 = orc_kernel_c2(kernel);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_nodes; ++q) {
+    int64_t idx = nodes[q];
+    int ix = (int)(idx % res[0]);
+    int iy = (int)((idx / res[0]) % res[1]);
+    int iz = (int)(idx / ((int64_t)res[0] * res[1]));
+    float xn = orc_node_coord(lo[0], hi[0], res[0], ix);
+    float yn = orc_node_coord(lo[1], hi[1], res[1], iy);
+    float zn = orc_node_coord(lo[2], hi[2], res[2], iz);
+    double sum = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (include && !include[j]) continue;
+      const float* p = pts + 3 * j;
+      float ihx, ihy, ihz;
+      double w;
+      if (ih_pp) {
+        ihx = ih_pp[3 * j]; ihy = ih_pp[3 * j + 1]; ihz = ih_pp[3 * j + 2];
+      } else {
+        ihx = ih_u[0]; ihy = ih_u[1]; ihz = ih_u[2];
+      }
+      w = w_pp ? w_pp[j] : w_u;
+      float u2 = orc_u2_f32(xn, yn, zn, p[0], p[1], p[2], ihx, ihy, ihz);
+      if (!(u2 < c2)) continue;
+      if (kernel == ORC_COUNT) {
+        sum += 1.0;
+      } else {
+        double u2d = orc_u2_f64(xn, yn, zn, p[0], p[1], p[2], ihx, ihy, ihz);
+        sum += w * orc_kernel_value(kernel, u2d);
+      }
+    }
+    out[q] = kernel == ORC_COUNT ? sum : scale * sum;
+  }
+}
+
+/* Support set S(n) of each listed node: original particle indices in
+ * increasing order. Two-call protocol: with idx == NULL only counts are
+ * written (offsets[q+1] - offsets[q]); offsets has n_nodes + 1 entries. */
+void orc_candidates(const float* pts, int64_t n, const float* ih_pp,
+                    const float* ih_u, const uint8_t* include, int kernel,
+                    const double* lo, const double* hi, const int* res,
+                    const int64_t* nodes, int64_t n_nodes, int64_t* offsets,
+                    int64_t* idx_out) {
+  const float c2 = orc_kernel_c2(kernel);
+  if (!idx_out) offsets[0] = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t q = 0; q < n_nodes; ++q) {
+    int64_t idx = nodes[q];
+    int ix = (int)(idx % res[0]);
+    int iy = (int)((idx / res[0]) % res[1]);
+    int iz = (int)(idx / ((int64_t)res[0] * res[1]));
+    float xn = orc_node_coord(lo[0], hi[0], res[0], ix);
+    float yn = orc_node_coord(lo[1], hi[1], res[1], iy);
+    float zn = orc_node_coord(lo[2], hi[2], res[2], iz);
+    int64_t c = 0;
+    int64_t base = idx_out ? offsets[q] : 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (include && !include[j]) continue;
+      const float* p = pts + 3 * j;
+      const float* ih = ih_pp ? ih_pp + 3 * j : ih_u;
+      float u2 = orc_u2_f32(xn, yn, zn, p[0], p[1], p[2], ih[0], ih[1], ih[2]);
+      if (u2 < c2) {
+        if (idx_out) idx_out[base + c] = j;
+        ++c;
+      }
+    }
+    if (!idx_out) offsets[q + 1] = c;
+  }
+  if (!idx_out)
+    for (int64_t q = 0; q < n_nodes; ++q) offsets[q + 1] += offsets[q];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-point bandwidth from the k-th nearest neighbour.                     */
+/* h_j^2 = k-th smallest canonical float32 squared distance from particle j */
+/* to every other particle (self excluded by index; coincident particles    */
+/* count). Canonical squared distance:                                      */
+/*   d_k = fl(p_jk - p_ik); d2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)).  */
+/* ------------------------------------------------------------------------ */
+
+float orc_d2_f32(const float* a, const float* b) {
+  volatile float dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  volatile float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+  volatile float sxy = sx + sy;
+  volatile float s = sxy + sz;
+  return s;
+}
+
+static int cmp_float(const void* a, const void* b) {
+  float x = *(const float*)a, y = *(const float*)b;
+  return (x > y) - (x < y);
+}
+
+/* Returns 0 on success, -1 if n - 1 < k. */
+int orc_knn_h2(const float* pts, int64_t n, int k, const int64_t* queries,
+               int64_t n_queries, float* out) {
+  if (k < 1 || n - 1 < k) return -1;
+#pragma omp parallel
+  {
+    float* d = (float*)malloc(sizeof(float) * (size_t)(n - 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n_queries; ++q) {
+      int64_t j = queries[q];
+      int64_t m = 0;
+      for (int64_t i = 0; i < n; ++i)
+        if (i != j) d[m++] = orc_d2_f32(pts + 3 * j, pts + 3 * i);
+      /* full sort: plainest correct selection of the k-th smallest */
+      qsort(d, (size_t)m, sizeof(float), cmp_float);
+      out[q] = d[k - 1];
+    }
+    free(d);
+  }
+  return 0;
+}
+
+/* Per-point parameters of a per-particle isotropic bandwidth h_j = sqrt(h2_j):
+ * ih_j = (float)(1/h_j) on every axis and w_j = 1/h_j^3. A zero bandwidth
+ * (>= k+1 coincident particles) gives ih = FLT_MAX-like large value and
+ * w = 0, so the particle contributes nothing. */
+void orc_point_params_from_h2(const float* h2, int64_t n, float* ih3, double* w) {
+  for (int64_t j = 0; j < n; ++j) {
+    double h = sqrt((double)h2[j]);
+    if (h > 0.0) {
+      float ih = (float)(1.0 / h);
+      ih3[3 * j] = ih3[3 * j + 1] = ih3[3 * j + 2] = ih;
+      w[j] = 1.0 / (h * h * h);
+    } else {
+      ih3[3 * j] = ih3[3 * j + 1] = ih3[3 * j + 2] = 3.4028234663852886e38f;
+      w[j] = 0.0;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* MBE (Section 3.1): initial smoothing length, pilot, ASL, final.          */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* Percentile by linear interpolation between order statistics
+ * (Hyndman-Fan type 7): with v sorted ascending and pos = (n-1) q,
+ * P = v[floor(pos)] + (pos - floor(pos)) (v[floor(pos)+1] - v[floor(pos)]). */
+double orc_percentile_sorted(const double* v, int64_t n, double q) {
+  double pos = (double)(n - 1) * q;
+  int64_t i = (int64_t)floor(pos);
+  double f = pos - (double)i;
+  if (i + 1 >= n) return v[n - 1];
+  return v[i] + f * (v[i + 1] - v[i]);
+}
+
+double orc_percentile(const float* x, int64_t n, int stride, double q) {
+  double* v = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) v[i] = (double)x[i * stride];
+  qsort(v, (size_t)n, sizeof(double), cmp_double);
+  double r = orc_percentile_sorted(v, n, q);
+  free(v);
+  return r;
+}
+
+/* Node spacing s_k of the ROI grid. */
+double orc_spacing(double lo, double hi, int res) { return (hi - lo) / (double)(res - 1); }
+
+/* Eq. 1 over the particles inside B (pts_b: n_b x 3):
+ *   l_k = 2 (P80_k - P20_k) / ln(N_B),
+ * natural logarithm; a non-positive or non-finite result (N_B < 2 or
+ * P80 == P20) is replaced by the cap 5 s_k of Eq. 6. Rounded once to float. */
+void orc_mbe_initial_ell(const float* pts_b, int64_t n_b, const double* lo,
+                         const double* hi, const int* res, float* ell,
+                         int* degenerate_flags) {
+  *degenerate_flags = 0;
+  for (int k = 0; k < 3; ++k) {
+    double cap = 5.0 * orc_spacing(lo[k], hi[k], res[k]);
+    double l = NAN;
+    if (n_b >= 2) {
+      double p20 = orc_percentile(pts_b + k, n_b, 3, 0.20);
+      double p80 = orc_percentile(pts_b + k, n_b, 3, 0.80);
+      l = 2.0 * (p80 - p20) / log((double)n_b);
+    }
+    if (!(l > 0.0) || !isfinite(l)) {
+      l = cap;
+      *degenerate_flags |= 1 << k;
+    }
+    ell[k] = (float)l;
+  }
+}
+
+/* Trilinear interpolation of a node field (double, x fastest) at position p.
+ * f = (p - lo) (res - 1) / (hi - lo); cell i = floor(f) clamped to
+ * [0, res - 2]; t = f - i clamped to [0, 1]. */
+double orc_trilinear(const double* grid, const double* lo, const double* hi,
+                     const int* res, const float* p) {
+  int i[3];
+  double t[3];
+  for (int k = 0; k < 3; ++k) {
+    double f = ((double)p[k] - lo[k]) * (double)(res[k] - 1) / (hi[k] - lo[k]);
+    int c = (int)floor(f);
+    if (c < 0) c = 0;
+    if (c > res[k] - 2) c = res[k] - 2;
+    double tt = f - (double)c;
+    if (tt < 0.0) tt = 0.0;
+    if (tt > 1.0) tt = 1.0;
+    i[k] = c;
+    t[k] = tt;
+  }
+  double acc = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        double wgt = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) *
+                     (dz ? t[2] : 1.0 - t[2]);
+        int64_t idx = (int64_t)(i[0] + dx) +
+                      (int64_t)res[0] * ((int64_t)(i[1] + dy) + (int64_t)res[1] * (i[2] + dz));
+        acc += wgt * grid[idx];
+      }
+  return acc;
+}
+
+/* Adaptive smoothing length (Eqs. 5-6), given a pilot grid:
+ *   pden_j = trilinear(pilot, r_j)                     (Section 3.1)
+ *   aveDen = (1/N_B) sum_j pden_j                      (Eq. 5, read as a mean)
+ *   l_kj   = min(l_k (aveDen / pden_j)^{1/3}, 5 s_k)   (Eq. 6)
+ * pden_j <= 0 gives the cap. ell_j: n_b x 3 floats (rounded once). */
+void orc_mbe_asl(const float* pts_b, int64_t n_b, const double* pilot,
+                 const double* lo, const double* hi, const int* res,
+                 const float* ell0, double* pden, double* aveden, float* ell_j) {
+  double sum = 0.0;
+  for (int64_t j = 0; j < n_b; ++j) {
+    pden[j] = orc_trilinear(pilot, lo, hi, res, pts_b + 3 * j);
+    sum += pden[j];
+  }
+  double ave = n_b > 0 ? sum / (double)n_b : 0.0;
+  *aveden = ave;
+  for (int64_t j = 0; j < n_b; ++j) {
+    for (int k = 0; k < 3; ++k) {
+      double cap = 5.0 * orc_spacing(lo[k], hi[k], res[k]);
+      double l;
+      if (pden[j] > 0.0) {
+        l = (double)ell0[k] * cbrt(ave / pden[j]);
+        if (l > cap) l = cap;
+      } else {
+        l = cap;
+      }
+      ell_j[3 * j + k] = (float)l;
+    }
+  }
+}
+
+/* Per-point parameters of an anisotropic per-particle smoothing length:
+ * ih_k = (float)(1/l_k), w = 1/(l_x l_y l_z) in double. */
+void orc_params_from_ell(const float* ell, int64_t n, float* ih3, double* w) {
+  for (int64_t j = 0; j < n; ++j) {
+    double lx = ell[3 * j], ly = ell[3 * j + 1], lz = ell[3 * j + 2];
+    ih3[3 * j] = (float)(1.0 / lx);
+    ih3[3 * j + 1] = (float)(1.0 / ly);
+    ih3[3 * j + 2] = (float)(1.0 / lz);
+    w[j] = 1.0 / (lx * ly * lz);
+  }
+}
