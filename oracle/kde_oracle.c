@@ -220,37 +220,40 @@ float orc_d2_f32(const float* a, const float* b) {
   return s;
 }
 
-static int cmp_float(const void* a, const void* b) {
-  float x = *(const float*)a, y = *(const float*)b;
-  return (x > y) - (x < y);
-}
-
-/* Returns 0 on success, -1 if n - 1 < k. */
+/* Returns 0 on success, -1 if n - 1 < k. Keeps the k smallest distances in
+ * an ascending array (insertion), so the answer is its last entry. */
 int orc_knn_h2(const float* pts, int64_t n, int k, const int64_t* queries,
                int64_t n_queries, float* out) {
   if (k < 1 || n - 1 < k) return -1;
 #pragma omp parallel
   {
-    float* d = (float*)malloc(sizeof(float) * (size_t)(n - 1));
+    float* a = (float*)malloc(sizeof(float) * (size_t)k);
 #pragma omp for schedule(dynamic, 1)
     for (int64_t q = 0; q < n_queries; ++q) {
       int64_t j = queries[q];
-      int64_t m = 0;
-      for (int64_t i = 0; i < n; ++i)
-        if (i != j) d[m++] = orc_d2_f32(pts + 3 * j, pts + 3 * i);
-      /* full sort: plainest correct selection of the k-th smallest */
-      qsort(d, (size_t)m, sizeof(float), cmp_float);
-      out[q] = d[k - 1];
+      int m = 0; /* entries held, <= k */
+      for (int64_t i = 0; i < n; ++i) {
+        if (i == j) continue;
+        float d = orc_d2_f32(pts + 3 * j, pts + 3 * i);
+        if (m == k && !(d < a[k - 1])) continue;
+        int p = m < k ? m++ : k - 1; /* slot freed at the end */
+        while (p > 0 && a[p - 1] > d) {
+          a[p] = a[p - 1];
+          --p;
+        }
+        a[p] = d;
+      }
+      out[q] = a[k - 1];
     }
-    free(d);
+    free(a);
   }
   return 0;
 }
 
 /* Per-point parameters of a per-particle isotropic bandwidth h_j = sqrt(h2_j):
  * ih_j = (float)(1/h_j) on every axis and w_j = 1/h_j^3. A zero bandwidth
- * (>= k+1 coincident particles) gives ih = FLT_MAX-like large value and
- * w = 0, so the particle contributes nothing. */
+ * (>= k+1 coincident particles) has an empty support: ih = +inf makes every
+ * scaled distance infinite or NaN, so the particle is never a member. */
 void orc_point_params_from_h2(const float* h2, int64_t n, float* ih3, double* w) {
   for (int64_t j = 0; j < n; ++j) {
     double h = sqrt((double)h2[j]);
@@ -259,7 +262,7 @@ void orc_point_params_from_h2(const float* h2, int64_t n, float* ih3, double* w)
       ih3[3 * j] = ih3[3 * j + 1] = ih3[3 * j + 2] = ih;
       w[j] = 1.0 / (h * h * h);
     } else {
-      ih3[3 * j] = ih3[3 * j + 1] = ih3[3 * j + 2] = 3.4028234663852886e38f;
+      ih3[3 * j] = ih3[3 * j + 1] = ih3[3 * j + 2] = INFINITY;
       w[j] = 0.0;
     }
   }

@@ -433,3 +433,19 @@ def test_c1_oracle_full_grid_runs():
     # boundary loss of the uniform half is a few percent; clusters are inside
     mass = rho.sum() / 31.0 ** 3
     assert 0.97 < mass < 1.01
+
+
+def test_zero_bandwidth_has_empty_support():
+    # 40 coincident particles: their 32nd-neighbour distance is 0, so their
+    # bandwidth is zero and they belong to no support, not even a node at
+    # their exact position; the other particles are unaffected
+    pts = np.concatenate([np.full((40, 3), 0.5, np.float32), synth.uniform_cloud(200, 1)])
+    h2 = oracle.knn_h2(pts, 32)
+    assert np.all(h2[:40] == 0.0) and np.all(h2[40:] > 0.0)
+    roi = Roi((0, 0, 0), (1, 1, 1), (5, 5, 5), kernel="gauss_trunc3", bw="per_point",
+              norm="count")
+    centre = np.array([2 + 5 * (2 + 5 * 2)])  # (0.5, 0.5, 0.5)
+    offs, idx = oracle.candidates(pts, roi, centre, h2=h2)
+    assert not np.any(idx < 40)
+    assert len(idx) > 0
+    assert np.isfinite(oracle.density(pts, roi, nodes=centre, h2=h2)[0])
