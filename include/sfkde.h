@@ -1,0 +1,262 @@
+/*
+ * sfkde.h -- C ABI of the MI355X (gfx950) ROI kernel density estimation
+ * library: on-the-fly density grids over regions of interest of a large
+ * particle cloud, after ScaleFree (arXiv 2601.20758).
+ *
+ * Method references (paper sections, equations, algorithms):
+ *   Section 3.1, Eqs. 1-8   the estimator: a uniform node grid over a box B,
+ *                           the Epanechnikov kernel (Eq. 4), the pilot
+ *                           density (Eqs. 2-3), the initial smoothing length
+ *                           (Eq. 1), the mean pilot density (Eq. 5), the
+ *                           adaptive smoothing length (Eq. 6) and the final
+ *                           density (Eqs. 7-8).
+ *   Section 3.2, Alg. 1-4   the GPU pipeline the paper dispatches (pilot,
+ *                           adaptive length, final) and its inputs: a spatial
+ *                           index over the particles, the positions, the
+ *                           grid, the smoothing lengths and the node spacing.
+ *
+ * Conventions
+ *   - Every pointer named d_* is device memory on the context's device; h_*
+ *     is host memory. The caller owns both; the library never frees them.
+ *   - Positions are float32 AoS, n x 3 (x, y, z).
+ *   - A grid has res[0]*res[1]*res[2] float32 values, x fastest:
+ *     idx = x + y*res[0] + z*res[0]*res[1] (Algorithms 2 and 4 index the
+ *     density buffer this way).
+ *   - Grid node i on axis k sits at (float)(lo + (i*(hi-lo))/(res-1)),
+ *     evaluated in double and rounded once (vertex-centred nodes on the
+ *     closed box; node spacing s_k = (hi_k - lo_k)/(res_k - 1)).
+ *   - A particle j is in the support of node n when, in float32 on the
+ *     float32 inputs, u2 < c2 with d_k = x_nk - p_jk, u_k = d_k * ih_k,
+ *     u2 = (u_x*u_x + u_y*u_y) + u_z*u_z (no fused multiply-add), ih_k the
+ *     float32 inverse bandwidth, c2 = 1 (Epanechnikov, Eq. 4 is zero at
+ *     |x| >= 1) or 9 (Gaussian truncated at 3 sigma).
+ *   - Functions return sfk_status and never throw or abort. Arguments are
+ *     validated before any device work; on failure nothing is launched and
+ *     sfk_last_error() describes the cause.
+ *   - One host thread per context. Trees are immutable after build and may
+ *     be evaluated by several ROIs at once.
+ */
+#ifndef SFKDE_H
+#define SFKDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SFK_OK = 0,
+  SFK_E_INVAL = 1,        /* invalid argument (checked before any launch) */
+  SFK_E_NOMEM = 2,        /* allocator returned NULL; the context stays usable */
+  SFK_E_BUDGET = 3,       /* request exceeds the context's device-memory budget */
+  SFK_E_DEVICE = 4,       /* a HIP runtime call failed */
+  SFK_E_NOT_READY = 5,    /* ticket still running (sfk_poll / sfk_wait timeout) */
+  SFK_E_CANCELLED = 6,    /* ticket was cancelled before it ran */
+  SFK_E_UNSUPPORTED = 7,  /* valid but not supported combination */
+  SFK_E_INTERNAL = 8
+} sfk_status;
+
+typedef enum {
+  SFK_KERNEL_EPANECHNIKOV = 0, /* Eq. 4, C = 15/(8 pi) (Eq. 2, Eq. 7) */
+  SFK_KERNEL_GAUSS_TRUNC3 = 1  /* exp(-u2/2) on u2 < 9, renormalised to unit mass */
+} sfk_kernel;
+
+typedef enum {
+  SFK_BW_FIXED = 0,      /* h per axis as given */
+  SFK_BW_ROI_SCALED = 1, /* h_k = h0 * (hi_k - lo_k), h0 = h[0] */
+  SFK_BW_PER_POINT = 2,  /* per-particle isotropic h from the tree (k-NN or given) */
+  SFK_BW_MBE = 3         /* Section 3.1: Eq. 1 -> pilot -> Eq. 6 -> final (Epanechnikov) */
+} sfk_bw;
+
+typedef enum {
+  SFK_NORM_PAPER = 0, /* times 1/N: the grid integrates to 1 (Eqs. 2 and 7) */
+  SFK_NORM_COUNT = 1  /* no 1/N: the grid integrates to N */
+} sfk_norm;
+
+typedef enum {
+  SFK_SET_CLOUD = 0,  /* every particle of the tree contributes; N = tree size */
+  SFK_SET_IN_ROI = 1  /* only particles in the closed box B; N = N_B (Eq. 1) */
+} sfk_set;
+
+typedef struct sfk_ctx_s* sfk_ctx;
+typedef struct sfk_tree_s* sfk_tree;
+typedef int64_t sfk_ticket;
+
+/* Device-memory allocator. alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL; free releases it. With a NULL allocator the
+ * library uses hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, size_t bytes, void* user);
+  void* user;
+} sfk_allocator;
+
+typedef struct {
+  int32_t leaf_size;   /* particles per leaf bucket; 0 or 64 (the wavefront width) */
+  int32_t knn_k;       /* 0: no per-point bandwidth; 1..64: h_j^2 = k-th smallest
+                          squared distance to another particle (self excluded) */
+  int32_t morton_bits; /* bits per axis of the sort key, 0 = automatic (4..21) */
+  int32_t reserved;
+} sfk_tree_opts;
+
+/* One region-of-interest request (Section 3.1: a box B and its node grid). */
+typedef struct {
+  double lo[3], hi[3]; /* closed box B, hi > lo */
+  int32_t res[3];      /* nodes per axis, each >= 2 */
+  int32_t kernel;      /* sfk_kernel */
+  int32_t bw;          /* sfk_bw */
+  int32_t norm;        /* sfk_norm */
+  int32_t set;         /* sfk_set (SFK_BW_MBE requires SFK_SET_IN_ROI) */
+  float h[3];          /* FIXED: h per axis; ROI_SCALED: h0 in h[0]; else unused */
+  float* d_out;        /* device, res[0]*res[1]*res[2] floats, written in full */
+  uint64_t tag;        /* caller's label, unused by the library */
+} sfk_roi;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`. hbm_budget_bytes bounds the
+ * workspace the context may hold for in-flight batches (0 = no bound).
+ * alloc may be NULL. */
+sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc,
+                          size_t hbm_budget_bytes, sfk_ctx* out);
+sfk_status sfk_ctx_destroy(sfk_ctx ctx);
+const char* sfk_status_string(sfk_status s);
+/* Last error message of the context (or of the calling thread if ctx is NULL). */
+const char* sfk_last_error(sfk_ctx ctx);
+/* Library version string. */
+const char* sfk_version(void);
+
+/* ------------------------------------------------------------------- tree */
+
+/* Build the spatial index (the paper builds a k-d tree on the CPU and
+ * uploads it, Section 3.2; here the tree is built on the device): bounding
+ * box, Morton keys, radix sort, leaf buckets of 64 particles laid out as
+ * float4 in Morton order, an implicit 64-ary hierarchy of boxes. With
+ * opts->knn_k > 0 it also computes each particle's squared k-th nearest
+ * neighbour distance (per-point bandwidth). d_h, if non-NULL, gives a
+ * per-particle bandwidth instead (n floats, device, original order, > 0).
+ * d_xyz is read during the call only (stream-ordered on hip_stream; the call
+ * synchronises the stream before it returns). n = 0 gives an empty tree.
+ * Errors: SFK_E_INVAL on n < 0, n >= 2^31 - 64, NULL pointers, a
+ * non-finite coordinate, knn_k > 64 or knn_k >= n, a non-positive d_h. */
+sfk_status sfk_build_tree(sfk_ctx ctx, const float* d_xyz, int64_t n,
+                          const float* d_h, const sfk_tree_opts* opts,
+                          void* hip_stream, sfk_tree* out);
+/* n particles, bbox = {xmin, ymin, zmin, xmax, ymax, zmax}, device bytes held. */
+sfk_status sfk_tree_info(sfk_tree tree, int64_t* n, double bbox[6], size_t* device_bytes);
+sfk_status sfk_tree_destroy(sfk_tree tree);
+
+/* ------------------------------------------------------------- evaluation */
+
+/* Evaluate one ROI into roi->d_out, stream-ordered on hip_stream (returns
+ * once the work is enqueued; the grid is ready when the stream reaches it).
+ * This is sfk_submit of one ROI on the caller's stream: the same kernels. */
+sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hip_stream);
+
+/* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
+ * launch on one of the context's streams. The descriptors are copied; the
+ * d_out buffers must stay valid until the ticket completes. Returns at once
+ * with a ticket. SFK_E_BUDGET if the batch's workspace exceeds the budget. */
+sfk_status sfk_submit(sfk_ctx ctx, sfk_tree tree, const sfk_roi* rois, int32_t n_rois,
+                      sfk_ticket* out);
+/* *done = 1 once the ticket's grids are written, never blocks. */
+sfk_status sfk_poll(sfk_ctx ctx, sfk_ticket t, int32_t* done);
+/* Block until done or timeout_us elapses (< 0: no timeout); SFK_E_NOT_READY on timeout. */
+sfk_status sfk_wait(sfk_ctx ctx, sfk_ticket t, int64_t timeout_us);
+/* Cancel a ticket that has not started on the device; SFK_E_NOT_READY if it is running. */
+sfk_status sfk_cancel(sfk_ctx ctx, sfk_ticket t);
+
+/* Tile shape used for tile-granular range queries and evaluation: one
+ * wavefront owns tx*ty*tz grid nodes. 0 = chosen by the autotuner table. */
+typedef struct {
+  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 8x4x2, 3 = 4x4x2, 4 = 8x4x4 */
+  int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 64 */
+  int32_t persistent_waves_per_cu; /* 0 = automatic */
+  int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
+                            lists do not fit walk the tree inside the evaluation
+                            kernel instead (same results, bitwise) */
+} sfk_eval_opts;
+sfk_status sfk_set_eval_opts(sfk_ctx ctx, const sfk_eval_opts* opts);
+/* Time every tile shape on the sample ROIs and record the fastest per
+ * (kernel, bandwidth mode, support-to-spacing bucket) for later batches. */
+sfk_status sfk_autotune(sfk_ctx ctx, sfk_tree tree, const sfk_roi* sample, int32_t n);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request of the serving loop: it becomes visible at arrival_s seconds
+ * after the loop starts. */
+typedef struct {
+  double arrival_s;
+  sfk_roi roi;
+} sfk_request;
+
+typedef struct {
+  int32_t mode;          /* 0 continuous batching, 1 one ROI per launch in FIFO order */
+  int32_t n_slots;       /* batches in flight at once (each on its own stream), >= 1 */
+  int32_t max_batch;     /* ROIs per batch, >= 1 */
+  int32_t reserved;
+  double budget_bytes;   /* workspace + grid bytes admitted at once (0 = context budget) */
+} sfk_serve_opts;
+
+typedef struct {
+  double arrival_s;   /* as requested */
+  double admit_s;     /* when the request joined a launched batch */
+  double done_s;      /* device completion observed by the host */
+  double latency_ms;  /* done_s - arrival_s */
+  int32_t batch;      /* batch index it ran in */
+  int32_t status;     /* sfk_status of the request */
+} sfk_request_result;
+
+typedef struct {
+  double wall_s;
+  double p50_ms, p99_ms, max_ms;
+  double evals_per_s;     /* useful (node, particle) pairs per second, if counted */
+  int64_t n_batches;
+  double mean_batch;      /* mean ROIs per batch */
+  double mean_in_flight;  /* time-averaged batches in flight */
+  int64_t budget_waits;   /* admissions deferred for memory */
+} sfk_serve_summary;
+
+/* Run the request loop over reqs (sorted by arrival) until every request is
+ * done. Requests that arrive while others run are admitted as slots and
+ * budget free up and run overlapped with them. */
+sfk_status sfk_serve(sfk_ctx ctx, sfk_tree tree, const sfk_request* reqs, int64_t n,
+                     const sfk_serve_opts* opts, sfk_request_result* h_results,
+                     sfk_serve_summary* h_summary);
+
+/* ----------------------------------------------------------- test exports */
+
+/* Support sets S(n) of grid nodes [node_begin, node_end) of one ROI (CLOUD
+ * set, non-MBE), as seen by the evaluation kernels: original particle
+ * indices, ascending per node. h_offsets has node_end - node_begin + 1
+ * entries; h_idx receives up to cap indices; *needed = total. If the total
+ * exceeds cap only h_offsets and *needed are written. */
+sfk_status sfk_debug_candidates(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
+                                int64_t node_begin, int64_t node_end, int64_t* h_offsets,
+                                int64_t* h_idx, int64_t cap, int64_t* needed);
+/* Per-particle squared k-NN distance h_j^2 in original order (n floats). */
+sfk_status sfk_debug_point_h2(sfk_ctx ctx, sfk_tree tree, float* h_h2);
+/* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel. */
+sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
+                                int64_t* useful_pairs, int64_t* tested_pairs);
+/* Per-node support counts #S(n) (res product floats, device, x fastest). */
+sfk_status sfk_debug_support_counts(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
+                                    float* d_counts, void* hip_stream);
+
+/* MBE stages of one ROI (Section 3.1). Host outputs, any may be NULL:
+ * h_ell0[3] Eq. 1 lengths; *n_b particles in B; h_idx_b[n_b] their original
+ * indices (ascending); h_pilot[M] pilot grid (Eq. 2); h_pden[n_b] pilot at
+ * each particle (trilinear); *aveden (Eq. 5, mean); h_ell_j[n_b*3] adaptive
+ * lengths (Eq. 6), in the order of h_idx_b. cap_b bounds the per-particle
+ * outputs (SFK_E_INVAL if n_b > cap_b; *n_b is still written). The final
+ * grid goes to roi->d_out. */
+sfk_status sfk_debug_mbe(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, float* h_ell0,
+                         int64_t* n_b, int64_t* h_idx_b, float* h_pilot, float* h_pden,
+                         double* aveden, float* h_ell_j, int64_t cap_b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFKDE_H */

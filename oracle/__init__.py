@@ -233,6 +233,14 @@ def params_from_h2(h2: np.ndarray):
     return ih, w
 
 
+def params_from_h(h: np.ndarray):
+    """Per-point (ih[n,3] float32, w[n] double) of a given isotropic bandwidth:
+    ih = (float)(1/h), w = 1/h^3 in double."""
+    h64 = _f32(h).astype(np.float64)
+    ih = np.repeat((1.0 / h64).astype(np.float32)[:, None], 3, axis=1)
+    return np.ascontiguousarray(ih), 1.0 / (h64 * h64 * h64)
+
+
 def params_from_ell(ell: np.ndarray):
     """Per-point (ih[n,3] float32, w[n] double) of per-axis smoothing lengths."""
     ell = _f32(ell).reshape(-1, 3)

@@ -1,0 +1,299 @@
+"""MI355X (gfx950) ROI kernel density estimation: Python binding of libsfkde.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of libsfkde.so. PyTorch supplies device memory (optionally through
+its caching allocator) and streams. The names follow the C ABI in
+include/sfkde.h (sfk_build_tree -> Context.build_tree, ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import weakref
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["SfkError", "Context", "Tree", "roi_struct", "version"]
+
+
+class SfkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (L.STATUS.get(status, status), msg))
+        self.status = status
+        self.name = L.STATUS.get(status, str(status))
+
+
+def version() -> str:
+    return L.lib().sfk_version().decode()
+
+
+def _enum(table, v, what):
+    if isinstance(v, str):
+        if v not in table:
+            raise ValueError("unknown %s %r" % (what, v))
+        return table[v]
+    return int(v)
+
+
+def roi_struct(roi, d_out: int) -> L.RoiC:
+    """Marshal an ROI description (fields lo, hi, res, kernel, bw, norm, set,
+    h, tag) and a device output pointer into the C descriptor."""
+    r = L.RoiC()
+    for k in range(3):
+        r.lo[k] = float(roi.lo[k])
+        r.hi[k] = float(roi.hi[k])
+        r.res[k] = int(roi.res[k])
+        r.h[k] = float(roi.h[k]) if roi.h is not None else 0.0
+    r.kernel = _enum(L.KERNEL, roi.kernel, "kernel")
+    r.bw = _enum(L.BW, roi.bw, "bandwidth mode")
+    r.norm = _enum(L.NORM, roi.norm, "norm")
+    r.set = _enum(L.SET, roi.set, "set")
+    r.d_out = d_out
+    r.tag = int(getattr(roi, "tag", 0) or 0)
+    return r
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """sfk_ctx_create / sfk_ctx_destroy. allocator: "torch" routes device
+    memory through torch's caching allocator, "hip" uses hipMalloc."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch"):
+        self._lib = L.lib()
+        self._h = C.c_void_p()
+        self._trees = weakref.WeakSet()
+        self.device = device
+        self._alloc = None
+        ap = None
+        if allocator == "torch":
+            import torch
+
+            def _a(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+                except Exception:  # out of memory -> NULL -> SFK_E_NOMEM
+                    return None
+
+            def _f(ptr, nbytes, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = L.Allocator(L.Allocator.ALLOC(_a), L.Allocator.FREE(_f), None)
+            ap = C.byref(self._alloc)
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        st = self._lib.sfk_ctx_create(device, ap, int(budget_bytes), C.byref(self._h))
+        if st != L.SFK_OK:
+            raise SfkError(st, self._lib.sfk_last_error(None).decode())
+
+    # -- helpers
+    def _check(self, st):
+        if st != L.SFK_OK:
+            raise SfkError(st, self.last_error())
+
+    def last_error(self) -> str:
+        return self._lib.sfk_last_error(self._h).decode()
+
+    def close(self):
+        for t in list(self._trees):
+            t.close()
+        if self._h:
+            self._lib.sfk_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- tree
+    def build_tree(self, xyz, knn_k: int = 0, h=None, morton_bits: int = 0,
+                   stream=None) -> "Tree":
+        """sfk_build_tree on an (n, 3) float32 device tensor (and an optional
+        per-particle bandwidth tensor h of n floats)."""
+        import torch
+        if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float32):
+            raise TypeError("xyz must be a float32 device tensor")
+        if xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+            raise ValueError("xyz must be a contiguous (n, 3) tensor")
+        hp = None
+        if h is not None:
+            if not (h.is_cuda and h.dtype == torch.float32 and h.is_contiguous()
+                    and h.numel() == xyz.shape[0]):
+                raise ValueError("h must be n contiguous float32 device values")
+            hp = h.data_ptr()
+        opts = L.TreeOpts(0, int(knn_k), int(morton_bits), 0)
+        out = C.c_void_p()
+        self._check(self._lib.sfk_build_tree(self._h, xyz.data_ptr() if xyz.numel() else None,
+                                             int(xyz.shape[0]), hp, C.byref(opts),
+                                             _stream_ptr(stream), C.byref(out)))
+        t = Tree(self, out)
+        self._trees.add(t)
+        return t
+
+    # -- evaluation
+    def eval_roi(self, tree: "Tree", roi, out=None, stream=None):
+        """sfk_eval_roi: stream-ordered evaluation into `out` (allocated if None)."""
+        out = self._out_for(roi, out)
+        r = roi_struct(roi, out.data_ptr())
+        self._check(self._lib.sfk_eval_roi(self._h, tree._h, C.byref(r), _stream_ptr(stream)))
+        return out
+
+    def submit(self, tree: "Tree", rois: Sequence, outs: Sequence) -> int:
+        """sfk_submit of a batch; outs[i] receives rois[i]."""
+        arr = (L.RoiC * len(rois))()
+        for i, (roi, o) in enumerate(zip(rois, outs)):
+            arr[i] = roi_struct(roi, o.data_ptr())
+        t = C.c_int64()
+        self._check(self._lib.sfk_submit(self._h, tree._h, arr, len(rois), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        self._check(self._lib.sfk_poll(self._h, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        self._check(self._lib.sfk_wait(self._h, ticket, int(timeout_us)))
+
+    def cancel(self, ticket: int):
+        self._check(self._lib.sfk_cancel(self._h, ticket))
+
+    def set_eval_opts(self, tile_shape: int = 0, chunk_leaves: int = 0,
+                      persistent_waves_per_cu: int = 0, list_capacity: int = 0):
+        o = L.EvalOpts(int(tile_shape), int(chunk_leaves), int(persistent_waves_per_cu),
+                       int(list_capacity))
+        self._check(self._lib.sfk_set_eval_opts(self._h, C.byref(o)))
+
+    def autotune(self, tree: "Tree", rois: Sequence, outs: Sequence):
+        arr = (L.RoiC * len(rois))()
+        for i, (roi, o) in enumerate(zip(rois, outs)):
+            arr[i] = roi_struct(roi, o.data_ptr())
+        self._check(self._lib.sfk_autotune(self._h, tree._h, arr, len(rois)))
+
+    def serve(self, tree: "Tree", arrivals: Sequence[float], rois: Sequence, outs: Sequence,
+              mode: int = 0, n_slots: int = 4, max_batch: int = 64, budget_bytes: float = 0.0):
+        """sfk_serve over a request trace; returns (per-request results, summary)."""
+        n = len(rois)
+        reqs = (L.Request * n)()
+        for i in range(n):
+            reqs[i].arrival_s = float(arrivals[i])
+            reqs[i].roi = roi_struct(rois[i], outs[i].data_ptr())
+        opts = L.ServeOpts(int(mode), int(n_slots), int(max_batch), 0, float(budget_bytes))
+        res = (L.RequestResult * n)()
+        summ = L.ServeSummary()
+        self._check(self._lib.sfk_serve(self._h, tree._h, reqs, n, C.byref(opts), res,
+                                        C.byref(summ)))
+        return res, summ
+
+    def _out_for(self, roi, out):
+        import torch
+        m = int(roi.res[0]) * int(roi.res[1]) * int(roi.res[2])
+        if out is None:
+            out = torch.empty(m, dtype=torch.float32, device="cuda:%d" % self.device)
+        if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                and out.numel() == m):
+            raise ValueError("out must be a contiguous float32 device tensor of %d values" % m)
+        return out
+
+    # -- test exports
+    def debug_candidates(self, tree: "Tree", roi, node_begin: int, node_end: int):
+        """Support sets of nodes [node_begin, node_end): (offsets, original indices)."""
+        nn = node_end - node_begin
+        offs = np.zeros(nn + 1, dtype=np.int64)
+        need = C.c_int64()
+        r = roi_struct(roi, 1)
+        self._check(self._lib.sfk_debug_candidates(self._h, tree._h, C.byref(r), node_begin,
+                                                    node_end, offs.ctypes.data, None, 0,
+                                                    C.byref(need)))
+        idx = np.zeros(max(need.value, 1), dtype=np.int64)
+        self._check(self._lib.sfk_debug_candidates(self._h, tree._h, C.byref(r), node_begin,
+                                                    node_end, offs.ctypes.data, idx.ctypes.data,
+                                                    idx.shape[0], C.byref(need)))
+        return offs, idx[:need.value]
+
+    def debug_point_h2(self, tree: "Tree") -> np.ndarray:
+        n = tree.info()[0]
+        out = np.zeros(max(n, 1), dtype=np.float32)
+        self._check(self._lib.sfk_debug_point_h2(self._h, tree._h, out.ctypes.data))
+        return out[:n]
+
+    def debug_eval_count(self, tree: "Tree", roi):
+        u = C.c_int64()
+        t = C.c_int64()
+        r = roi_struct(roi, 1)
+        self._check(self._lib.sfk_debug_eval_count(self._h, tree._h, C.byref(r), C.byref(u),
+                                                    C.byref(t)))
+        return u.value, t.value
+
+    def debug_support_counts(self, tree: "Tree", roi, out=None, stream=None):
+        out = self._out_for(roi, out)
+        r = roi_struct(roi, out.data_ptr())
+        self._check(self._lib.sfk_debug_support_counts(self._h, tree._h, C.byref(r),
+                                                       out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def debug_mbe(self, tree: "Tree", roi, out=None, cap_b: Optional[int] = None):
+        """MBE stages of one ROI: dict of ell0, n_b, idx_b, pilot, pden,
+        aveden, ell_j and the final grid (device tensor)."""
+        out = self._out_for(roi, out)
+        n = tree.info()[0]
+        cap = n if cap_b is None else cap_b
+        m = out.numel()
+        ell0 = np.zeros(3, dtype=np.float32)
+        nb = C.c_int64()
+        idx = np.zeros(max(cap, 1), dtype=np.int64)
+        pilot = np.zeros(m, dtype=np.float32)
+        pden = np.zeros(max(cap, 1), dtype=np.float32)
+        ave = C.c_double()
+        ellj = np.zeros((max(cap, 1), 3), dtype=np.float32)
+        r = roi_struct(roi, out.data_ptr())
+        self._check(self._lib.sfk_debug_mbe(self._h, tree._h, C.byref(r), ell0.ctypes.data,
+                                            C.byref(nb), idx.ctypes.data, pilot.ctypes.data,
+                                            pden.ctypes.data, C.byref(ave), ellj.ctypes.data,
+                                            cap))
+        k = nb.value
+        return {"ell0": ell0, "n_b": k, "idx_b": idx[:k], "pilot": pilot, "pden": pden[:k],
+                "aveden": ave.value, "ell_j": ellj[:k], "final": out}
+
+
+class Tree:
+    """A device-resident spatial index (sfk_tree)."""
+
+    def __init__(self, ctx: Context, h: C.c_void_p):
+        self._ctx = ctx
+        self._h = h
+
+    def info(self):
+        n = C.c_int64()
+        bb = (C.c_double * 6)()
+        nb = C.c_size_t()
+        self._ctx._check(L.lib().sfk_tree_info(self._h, C.byref(n), bb, C.byref(nb)))
+        return n.value, list(bb), nb.value
+
+    def close(self):
+        if self._h:
+            L.lib().sfk_tree_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

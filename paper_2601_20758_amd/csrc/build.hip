@@ -1,0 +1,600 @@
+// Tree build on the device: bounding box, Morton keys, stable LSD radix
+// sort, leaf buckets of 64 particles (float4, Morton order), a 64-ary box
+// hierarchy, and the per-particle k-th nearest neighbour bandwidth.
+//
+// The paper builds a k-d tree on the CPU and uploads it (Section 3.2);
+// here the index is built where the particles live so only ROI descriptors
+// ever cross PCIe.
+#include "sfk_device.h"
+
+namespace sfk {
+
+// ---------------------------------------------------------------------------
+// bounding box + finiteness check
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ xyz, int64_t n,
+                                                      float* __restrict__ partial, int nblk) {
+  __shared__ float lds[7][4];
+  float mn[3] = {3.0e38f, 3.0e38f, 3.0e38f}, mx[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+  float bad = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float v = xyz[3 * i + k];
+      if (!isfinite(v)) {
+        bad += 1.0f;
+      } else {
+        mn[k] = fminf(mn[k], v);
+        mx[k] = fmaxf(mx[k], v);
+      }
+    }
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    mn[k] = wave_min(mn[k]);
+    mx[k] = wave_max(mx[k]);
+  }
+  bad = wave_sum(bad);
+  if (lane_id() == 0) {
+    for (int k = 0; k < 3; ++k) {
+      lds[k][w] = mn[k];
+      lds[3 + k][w] = mx[k];
+    }
+    lds[6][w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    float v = lds[k][0];
+    for (int j = 1; j < 4; ++j) {
+      const float u = lds[k][j];
+      v = k < 3 ? fminf(v, u) : (k < 6 ? fmaxf(v, u) : v + u);
+    }
+    partial[k * nblk + blockIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_bbox_final(const float* __restrict__ partial, int nblk,
+                                                   float* __restrict__ result) {
+  for (int k = 0; k < 7; ++k) {
+    float v = k < 3 ? 3.0e38f : (k < 6 ? -3.0e38f : 0.0f);
+    for (int i = lane_id(); i < nblk; i += 64) {
+      const float u = partial[k * nblk + i];
+      v = k < 3 ? fminf(v, u) : (k < 6 ? fmaxf(v, u) : v + u);
+    }
+    v = k < 3 ? wave_min(v) : (k < 6 ? wave_max(v) : wave_sum(v));
+    if (lane_id() == 0) result[k] = v;
+  }
+}
+
+hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, float* result,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(256), 0, s, xyz, n, partial, nblk);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, partial, nblk, result);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ xyz, int64_t n,
+                                                const float* __restrict__ bbox, int bits,
+                                                uint64_t* __restrict__ keys,
+                                                uint32_t* __restrict__ vals) {
+  const float cells = (float)(1u << bits);
+  float lo[3], sc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = bbox[k];
+    const float ext = bbox[3 + k] - bbox[k];
+    sc[k] = ext > 0.0f ? cells / ext : 0.0f;
+  }
+  const uint32_t qmax = (1u << bits) - 1u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t key = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float f = (xyz[3 * i + k] - lo[k]) * sc[k];
+      uint32_t q = f <= 0.0f ? 0u : (f >= (float)qmax ? qmax : (uint32_t)f);
+      key |= spread3(q) << (2 - k);
+    }
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+  }
+}
+
+hipError_t launch_morton(const float* xyz, int64_t n, const float* bbox, int bits,
+                         uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_morton, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox, bits, keys,
+                     vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
+// Per pass: block digit histograms (digit-major) -> exclusive scan ->
+// scatter. The scatter ranks equal digits inside a wavefront with eight
+// ballots (one per digit bit), then across the block's four wavefronts
+// through LDS, round by round, so the order of equal keys is preserved.
+// ---------------------------------------------------------------------------
+
+static constexpr int kRsNT = 256;
+static constexpr int kRsItems = 16;
+static constexpr int kRsTile = kRsNT * kRsItems;
+
+__global__ __launch_bounds__(kRsNT) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                   int shift, uint32_t* __restrict__ hist,
+                                                   int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t g = base + (int64_t)r * kRsNT + threadIdx.x;
+    if (g < n) atomicAdd(&h[(uint32_t)(keys[g] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin,
+                                                      uint64_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int64_t n,
+                                                      int shift,
+                                                      const uint32_t* __restrict__ offs,
+                                                      int nblk) {
+  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t run[256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t g = base + (int64_t)r * kRsNT + tid;
+    const bool valid = g < n;
+    const uint64_t key = valid ? kin[g] : 0ull;
+    const uint32_t val = valid ? vin[g] : 0u;
+    const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    uint64_t mask = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bb = ballot(bit);
+      mask &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)popc64(mask & lt);
+    if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)popc64(mask);
+    __syncthreads();
+    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+    wcnt[0][tid] = 0;
+    wcnt[1][tid] = c0;
+    wcnt[2][tid] = c0 + c1;
+    wcnt[3][tid] = c0 + c1 + c2;
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = run[dig] + wcnt[wave][dig] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    run[tid] += c0 + c1 + c2 + c3;
+  }
+}
+
+size_t radix_sort_tmp_bytes(int64_t n) {
+  const int64_t nblk = (n + kRsTile - 1) / kRsTile;
+  const int64_t nh = 256 * nblk;
+  return (size_t)nh * 2 * sizeof(uint32_t) + scan_tmp_bytes(nh) + 1024;
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                            size_t tmp_bytes, hipStream_t s, int* result_in_alt) {
+  *result_in_alt = 0;
+  if (n <= 1) return hipSuccess;
+  const int64_t nblk = (n + kRsTile - 1) / kRsTile;
+  const int64_t nh = 256 * nblk;
+  if (radix_sort_tmp_bytes(n) > tmp_bytes) return hipErrorInvalidValue;
+  uint32_t* hist = (uint32_t*)tmp;
+  uint32_t* offs = hist + nh;
+  void* stmp = (void*)(offs + nh);
+  const size_t stmp_bytes = tmp_bytes - (size_t)nh * 2 * sizeof(uint32_t);
+  uint64_t *ka = keys, *kb = keys_alt;
+  uint32_t *va = vals, *vb = vals_alt;
+  const int passes = (key_bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, n, shift, hist,
+                       (int)nblk);
+    hipError_t e = scan_exclusive_u32(hist, offs, nh, stmp, stmp_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, va, kb, vb, n,
+                       shift, offs, (int)nblk);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  *result_in_alt = (passes & 1) ? 1 : 0;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// leaf layout
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ xyz,
+                                                const uint32_t* __restrict__ perm, int64_t n,
+                                                int64_t n_slots, float4* __restrict__ pts,
+                                                int32_t* __restrict__ perm_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n) {
+      const uint32_t j = perm[i];
+      pts[i] = make_float4(xyz[3 * (int64_t)j], xyz[3 * (int64_t)j + 1], xyz[3 * (int64_t)j + 2],
+                           0.0f);
+      perm_out[i] = (int32_t)j;
+    } else {
+      pts[i] = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 0.0f);
+    }
+  }
+}
+
+hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
+                         float4* pts, int32_t* perm_out, hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n_slots + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(256), 0, s, xyz, perm, n, n_slots, pts,
+                     perm_out);
+  return hipGetLastError();
+}
+
+// One wavefront per leaf: box of the real (non-sentinel) particles.
+__global__ __launch_bounds__(256) void k_leaf_boxes(const float4* __restrict__ pts, int64_t n,
+                                                    int32_t n_leaves, NodeBox* __restrict__ out) {
+  const int lane = lane_id();
+  for (int leaf = blockIdx.x * 4 + (threadIdx.x >> 6); leaf < n_leaves; leaf += gridDim.x * 4) {
+    const int64_t slot = (int64_t)leaf * SFK_LEAF + lane;
+    const float4 p = pts[slot];
+    const bool real = slot < n && p.x < 1.0e29f;
+    float lo[3] = {real ? p.x : 3.0e38f, real ? p.y : 3.0e38f, real ? p.z : 3.0e38f};
+    float hi[3] = {real ? p.x : -3.0e38f, real ? p.y : -3.0e38f, real ? p.z : -3.0e38f};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = wave_min(lo[k]);
+      hi[k] = wave_max(hi[k]);
+    }
+    const int cnt = popc64(ballot(real));
+    if (lane == 0) {
+      NodeBox b;
+      for (int k = 0; k < 3; ++k) {
+        b.lo[k] = lo[k];
+        b.hi[k] = hi[k];
+      }
+      b.first = leaf * SFK_LEAF;
+      b.count = cnt;
+      out[leaf] = b;
+    }
+  }
+}
+
+hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
+                             hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  const int nb = std::min<int>((n_leaves + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_leaf_boxes, dim3(nb), dim3(256), 0, s, pts, n, n_leaves, out);
+  return hipGetLastError();
+}
+
+// One wavefront per parent: union of up to 64 child boxes.
+__global__ __launch_bounds__(256) void k_level_boxes(const NodeBox* __restrict__ child,
+                                                     int32_t n_child,
+                                                     NodeBox* __restrict__ parent,
+                                                     int32_t n_parent) {
+  const int lane = lane_id();
+  for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < n_parent; p += gridDim.x * 4) {
+    const int c = p * SFK_FANOUT + lane;
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+    int cnt = 0;
+    if (c < n_child) {
+      const NodeBox b = child[c];
+      if (b.count > 0) {
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = b.lo[k];
+          hi[k] = b.hi[k];
+        }
+        cnt = b.count;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = wave_min(lo[k]);
+      hi[k] = wave_max(hi[k]);
+    }
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+      NodeBox b;
+      for (int k = 0; k < 3; ++k) {
+        b.lo[k] = lo[k];
+        b.hi[k] = hi[k];
+      }
+      b.first = p * SFK_FANOUT;
+      b.count = cnt;
+      parent[p] = b;
+    }
+  }
+}
+
+hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
+                              int32_t n_parent, hipStream_t s) {
+  if (n_parent <= 0) return hipSuccess;
+  const int nb = std::min<int>((n_parent + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_level_boxes, dim3(nb), dim3(256), 0, s, child, n_child, parent, n_parent);
+  return hipGetLastError();
+}
+
+// Per-node minimum inverse bandwidth per axis (largest support) for pruning
+// with per-particle bandwidths.
+__global__ __launch_bounds__(256) void k_leaf_ih(const float4* __restrict__ pts,
+                                                 const float4* __restrict__ pparam,
+                                                 int32_t pp_mode, int64_t n, int32_t n_leaves,
+                                                 float4* __restrict__ out) {
+  const int lane = lane_id();
+  for (int leaf = blockIdx.x * 4 + (threadIdx.x >> 6); leaf < n_leaves; leaf += gridDim.x * 4) {
+    const int64_t slot = (int64_t)leaf * SFK_LEAF + lane;
+    const float4 p = pts[slot];
+    const bool real = slot < n && p.x < 1.0e29f;
+    float m[3] = {3.0e38f, 3.0e38f, 3.0e38f};
+    if (real) {
+      if (pp_mode == PP_ANISO) {
+        const float4 q = pparam[slot];
+        m[0] = q.x;
+        m[1] = q.y;
+        m[2] = q.z;
+      } else {
+        m[0] = m[1] = m[2] = p.w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[k] = wave_min(m[k]);
+    if (lane == 0) out[leaf] = make_float4(m[0], m[1], m[2], 0.0f);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_level_ih(const float4* __restrict__ child, int32_t n_child,
+                                                  float4* __restrict__ parent, int32_t n_parent) {
+  const int lane = lane_id();
+  for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < n_parent; p += gridDim.x * 4) {
+    const int c = p * SFK_FANOUT + lane;
+    float m[3] = {3.0e38f, 3.0e38f, 3.0e38f};
+    if (c < n_child) {
+      const float4 q = child[c];
+      m[0] = q.x;
+      m[1] = q.y;
+      m[2] = q.z;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[k] = wave_min(m[k]);
+    if (lane == 0) parent[p] = make_float4(m[0], m[1], m[2], 0.0f);
+  }
+}
+
+hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mode, int64_t n,
+                          const NodeBox* nodes, const int32_t* level_off,
+                          const int32_t* level_cnt, int n_levels, float4* node_ih,
+                          hipStream_t s) {
+  (void)nodes;
+  if (n_levels <= 0) return hipSuccess;
+  int nb = std::min<int>((level_cnt[0] + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_leaf_ih, dim3(nb), dim3(256), 0, s, pts, pparam, pp_mode, n, level_cnt[0],
+                     node_ih + level_off[0]);
+  for (int l = 1; l < n_levels; ++l) {
+    nb = std::min<int>((level_cnt[l] + 3) / 4, 65536);
+    hipLaunchKernelGGL(k_level_ih, dim3(nb), dim3(256), 0, s, node_ih + level_off[l - 1],
+                       level_cnt[l - 1], node_ih + level_off[l], level_cnt[l]);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k-th nearest neighbour squared distance (per-point bandwidth).
+// One wavefront per leaf, one query particle per lane. Pass 1 takes the
+// k-th smallest distance among the leaf and its Morton neighbours as an
+// upper bound tau (those are real particles, so the true k-th distance is
+// <= tau); pass 2 walks the box hierarchy with the wavefront's largest tau
+// (a box whose canonical gap exceeds it cannot hold a closer particle) and
+// keeps the KM smallest squared distances per lane in a sorted register
+// array; the answer is its k-th entry. Exact: the same canonical float32
+// distances as the definition, selected without approximation.
+// ---------------------------------------------------------------------------
+
+template <int KM>
+__device__ __forceinline__ void knn_insert(float (&a)[KM], float x) {
+#pragma unroll
+  for (int i = 0; i < KM; ++i) {
+    const float t = a[i];
+    a[i] = fminf(t, x);
+    x = fmaxf(t, x);
+  }
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restrict__ h2_sorted) {
+  __shared__ float4 lds_pts[4][SFK_LEAF];
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  float4* lp = lds_pts[wave];
+  int32_t* stack = lds_stack[wave];
+  const int nl = tv.n_leaves;
+  for (int leaf = blockIdx.x * 4 + wave; leaf < nl; leaf += gridDim.x * 4) {
+    const int64_t my = (int64_t)leaf * SFK_LEAF + lane;
+    const float4 q = tv.pts[my];
+    const bool real = my < tv.n;
+    float a[KM];
+
+    auto process = [&](int cl) {
+      lp[lane] = tv.pts[(int64_t)cl * SFK_LEAF + lane];
+      wave_sync();
+      const int64_t cbase = (int64_t)cl * SFK_LEAF;
+      for (int t = 0; t < SFK_LEAF; ++t) {
+        const float4 p = lp[t];
+        float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
+        if (cbase + t == my || !real) x = __builtin_huge_valf();
+        if (ballot(x < a[KM - 1])) knn_insert<KM>(a, x);
+      }
+      wave_sync();
+    };
+    auto kth = [&]() {
+      float v = a[0];
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i == k - 1) v = a[i];
+      return v;
+    };
+
+    // pass 1: Morton-neighbour window
+#pragma unroll
+    for (int i = 0; i < KM; ++i) a[i] = __builtin_huge_valf();
+    int w0 = leaf - 1;
+    if (w0 > nl - 3) w0 = nl - 3;
+    if (w0 < 0) w0 = 0;
+    const int w1 = min(nl - 1, w0 + 2);
+    for (int cl = w0; cl <= w1; ++cl) process(cl);
+    const float tau = wave_max(real ? kth() : 0.0f);
+
+    // pass 2: every leaf within tau of this leaf's box
+    const NodeBox qb = tv.nodes[tv.level_off[0] + leaf];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) a[i] = __builtin_huge_valf();
+    traverse(
+        tv, stack,
+        [&](const NodeBox& b, int g) {
+          (void)g;
+          return box_gap_d2(b, qb.lo[0], qb.lo[1], qb.lo[2], qb.hi[0], qb.hi[1], qb.hi[2]) <= tau;
+        },
+        [&](int child, bool pass, uint64_t mask) {
+          (void)pass;
+          uint64_t m = mask;
+          while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            process(wave_bcast(child, b));
+          }
+        });
+    if (real) h2_sorted[my] = kth();
+  }
+}
+
+hipError_t launch_knn(TreeView tv, int k, float* h2_sorted, hipStream_t s) {
+  if (tv.n_leaves <= 0) return hipSuccess;
+  const int nb = std::min<int>((tv.n_leaves + 3) / 4, 65536);
+  if (k <= 8)
+    hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+  else if (k <= 16)
+    hipLaunchKernelGGL(k_knn<16>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+  else if (k <= 32)
+    hipLaunchKernelGGL(k_knn<32>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+  else
+    hipLaunchKernelGGL(k_knn<64>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+  return hipGetLastError();
+}
+
+// Per-particle isotropic inverse bandwidth into pts[].w:
+// ih = (float)(1 / sqrt((double)h2)) from the k-NN result, or
+// ih = (float)(1 / (double)h) from a caller-given bandwidth (original order).
+// A zero bandwidth has an empty support: the particle is moved to the
+// sentinel position so it is never a member.
+__global__ __launch_bounds__(256) void k_iso_params(float4* __restrict__ pts,
+                                                    const float* __restrict__ h2_sorted,
+                                                    const float* __restrict__ h_user,
+                                                    const int32_t* __restrict__ perm, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float4 p = pts[i];
+    double h;
+    if (h_user)
+      h = (double)h_user[perm[i]];
+    else
+      h = sqrt((double)h2_sorted[i]);
+    if (h > 0.0) {
+      p.w = (float)(1.0 / h);
+    } else {
+      p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 1.0f);
+    }
+    pts[i] = p;
+  }
+}
+
+hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
+                             const int32_t* perm, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_iso_params, dim3((unsigned)nb), dim3(256), 0, s, pts, h2_sorted,
+                     h_user_orig, perm, n);
+  return hipGetLastError();
+}
+
+}  // namespace sfk
+
+namespace sfk {
+
+// Count of values that are not finite and > 0 (per-particle bandwidth check).
+__global__ __launch_bounds__(256) void k_count_nonpositive(const float* __restrict__ h, int64_t n,
+                                                           int32_t* __restrict__ bad) {
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = h[i];
+    if (!(v > 0.0f) || !isfinite(v)) ++c;
+  }
+  c = wave_sum(c);
+  if (lane_id() == 0 && c) atomicAdd(bad, c);
+}
+
+__global__ void k_zero_i32(int32_t* p) { *p = 0; }
+
+hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, bad);
+  if (n > 0) {
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_nonpositive, dim3((unsigned)nb), dim3(256), 0, s, h, n, bad);
+  }
+  return hipGetLastError();
+}
+
+// Fill a float buffer with zeros (used instead of memset so the launch can
+// live inside a captured graph).
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace sfk

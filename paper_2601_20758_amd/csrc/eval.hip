@@ -1,0 +1,703 @@
+// ROI evaluation: tile-granular range query over the box hierarchy, a
+// device-side work plan (prefix sums, heavy tiles split into chunks of
+// leaves), and the persistent work-stealing evaluation kernel.
+//
+// Paper mapping (Section 3.2): Algorithms 2 and 4 give one thread per grid
+// node, a range query of radius max(l) per node (Alg. 2) or a loop over all
+// particles (Alg. 4), and a kernel sum per node, gathered (no atomics). Here
+// one wavefront owns a tile of tx*ty*tz neighbouring nodes; the tile's
+// candidate leaves come from one range query per tile; each lane takes one
+// particle of a 64-particle leaf and evaluates it against every node of the
+// tile, exploiting the grid's separability (the per-axis squared scaled
+// distances are computed once per particle and node row); the per-node sums
+// are combined across lanes with a transposing butterfly of wavefront
+// shuffles. Heavy tiles are split into chunks of leaves whose partial sums
+// are combined in a fixed order, so every grid is bitwise reproducible
+// whatever batch it runs in.
+#include "sfk_device.h"
+
+namespace sfk {
+
+// -log2(e)/2: exp(-u2/2) = exp2(KG * u2)
+#define SFK_KG (-0.72134752044448170368f)
+
+__device__ __forceinline__ int find_roi(const RoiDev* __restrict__ rois, int n_rois, int64_t t) {
+  int lo = 0, hi = n_rois - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rois[mid].tile_base <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+struct TileGeo {
+  int r;
+  int i0, j0, k0;
+  float lo[3], hi[3];
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ TileGeo tile_geo(const RoiDev* __restrict__ rois, int n_rois,
+                                            const float* __restrict__ coords, int64_t t) {
+  TileGeo g;
+  g.r = find_roi(rois, n_rois, t);
+  const RoiDev& R = rois[g.r];
+  const int64_t lt = t - R.tile_base;
+  const int ti = (int)(lt % R.ntile[0]);
+  const int tj = (int)((lt / R.ntile[0]) % R.ntile[1]);
+  const int tk = (int)(lt / ((int64_t)R.ntile[0] * R.ntile[1]));
+  g.i0 = ti * TX;
+  g.j0 = tj * TY;
+  g.k0 = tk * TZ;
+  const int i1 = min(g.i0 + TX, R.res[0]) - 1;
+  const int j1 = min(g.j0 + TY, R.res[1]) - 1;
+  const int k1 = min(g.k0 + TZ, R.res[2]) - 1;
+  const float* cx = coords + R.coord_off;
+  const float* cy = cx + R.res[0];
+  const float* cz = cy + R.res[1];
+  g.lo[0] = cx[g.i0];
+  g.hi[0] = cx[i1];
+  g.lo[1] = cy[g.j0];
+  g.hi[1] = cy[j1];
+  g.lo[2] = cz[g.k0];
+  g.hi[2] = cz[k1];
+  return g;
+}
+
+// Box test shared by the count, fill, evaluation and debug walks.
+__device__ __forceinline__ bool tile_box_test(const TreeView& tv, const RoiDev& R,
+                                              const TileGeo& g, const NodeBox& b, int gidx) {
+  float ihx = R.ih[0], ihy = R.ih[1], ihz = R.ih[2];
+  if (R.pp_mode != PP_UNIFORM) {
+    const float4 m = tv.node_ih[gidx];
+    ihx = m.x;
+    ihy = m.y;
+    ihz = m.z;
+  }
+  return box_gap_u2(b, g.lo[0], g.lo[1], g.lo[2], g.hi[0], g.hi[1], g.hi[2], ihx, ihy, ihz) <
+         R.c2;
+}
+
+// ---------------------------------------------------------------------------
+// ROI coordinate tables: x_i = (float)(lo + (i*(hi-lo))/(res-1)) in double.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_roi_coords(const RoiDev* __restrict__ rois, int n_rois,
+                                                    float* __restrict__ coords) {
+  const RoiDev& R = rois[blockIdx.x];
+  const int tot = R.res[0] + R.res[1] + R.res[2];
+  for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+    int k = 0, i = q;
+    if (i >= R.res[0]) {
+      i -= R.res[0];
+      k = 1;
+      if (i >= R.res[1]) {
+        i -= R.res[1];
+        k = 2;
+      }
+    }
+    const double lo = R.lo[k], hi = R.hi[k];
+    const double num = __dmul_rn((double)i, __dsub_rn(hi, lo));
+    const double v = __dadd_rn(lo, __ddiv_rn(num, (double)(R.res[k] - 1)));
+    coords[R.coord_off + q] = (float)v;
+  }
+}
+
+hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, float* coords, hipStream_t s) {
+  if (n_rois <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_roi_coords, dim3(n_rois), dim3(256), 0, s, rois, n_rois, coords);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batch header
+// ---------------------------------------------------------------------------
+
+__global__ void k_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap) {
+  hdr->n_tiles = n_tiles;
+  hdr->total_leaves = 0;
+  hdr->n_items = 0;
+  hdr->leaf_cap = leaf_cap;
+  hdr->item_cap = item_cap;
+  hdr->next_item = 0;
+  hdr->overflow = 0;
+  hdr->useful = 0;
+  hdr->tested = 0;
+}
+
+hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_hdr_init, dim3(1), dim3(1), 0, s, hdr, n_tiles, leaf_cap, item_cap);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tile range query: count pass and fill pass (one wavefront per tile)
+// ---------------------------------------------------------------------------
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const RoiDev* __restrict__ rois,
+                                                    int n_rois, const float* __restrict__ coords,
+                                                    int64_t n_tiles, int32_t* __restrict__ tile_cnt,
+                                                    int32_t* __restrict__ tile_done) {
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
+    const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
+    const RoiDev& R = rois[g.r];
+    int cnt = 0;
+    traverse(
+        tv, lds_stack[wave],
+        [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+        [&](int child, bool pass, uint64_t mask) {
+          (void)child;
+          (void)pass;
+          cnt += popc64(mask);
+        });
+    if (lane == 0) {
+      tile_cnt[t] = cnt;
+      tile_done[t] = 0;
+    }
+  }
+}
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_tile_fill(
+    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const float* __restrict__ coords,
+    int64_t n_tiles, const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
+    const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
+    int32_t* __restrict__ leaves, int32_t* __restrict__ item_tile) {
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
+    const int64_t c0 = chunk_off[t], c1 = chunk_off[t + 1];
+    for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
+    if (!tile_fit[t] || tile_cnt[t] == 0) continue;
+    const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
+    const RoiDev& R = rois[g.r];
+    int32_t* out = leaves + leaf_off[t];
+    int cnt = 0;
+    traverse(
+        tv, lds_stack[wave],
+        [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+        [&](int child, bool pass, uint64_t mask) {
+          if (pass) out[cnt + popc64(mask & lanemask_lt())] = child;
+          cnt += popc64(mask);
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// work plan: per tile, leaf_off (prefix of candidate leaves), partial_off
+// (prefix of partial-sum slots of split tiles), tile_fit (its lists fit the
+// buffers) and chunk_off (prefix of work items). Single block, 1024 threads,
+// looping over the tiles with running carries.
+// ---------------------------------------------------------------------------
+
+static constexpr int kPlanNT = 512;
+
+__global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ tile_cnt,
+                                                  int64_t n_tiles, int chunk_leaves,
+                                                  int64_t leaf_cap, int64_t partial_cap,
+                                                  int64_t* __restrict__ leaf_off,
+                                                  int64_t* __restrict__ partial_off,
+                                                  int64_t* __restrict__ chunk_off,
+                                                  int32_t* __restrict__ tile_fit,
+                                                  BatchHdr* __restrict__ hdr) {
+  __shared__ int64_t lds[kPlanNT / 64];
+  int64_t carry_l = 0, carry_p = 0, carry_c = 0;
+  for (int64_t base = 0; base < n_tiles; base += kPlanNT) {
+    const int64_t t = base + threadIdx.x;
+    const bool v = t < n_tiles;
+    const int64_t cnt = v ? tile_cnt[t] : 0;
+    const int64_t nch = cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
+    const int64_t pneed = (v && nch > 1) ? nch : 0;
+    int64_t tot;
+    const int64_t lo = carry_l + block_excl_scan<kPlanNT>(cnt, &tot, lds);
+    carry_l += tot;
+    const int64_t po = carry_p + block_excl_scan<kPlanNT>(pneed, &tot, lds);
+    carry_p += tot;
+    const bool fit = v && (lo + cnt <= leaf_cap) && (pneed == 0 || po + pneed <= partial_cap);
+    const int64_t nit = v ? (fit ? nch : 1) : 0;
+    const int64_t co = carry_c + block_excl_scan<kPlanNT>(nit, &tot, lds);
+    carry_c += tot;
+    if (v) {
+      leaf_off[t] = lo;
+      partial_off[t] = po;
+      chunk_off[t] = co;
+      tile_fit[t] = fit ? 1 : 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    leaf_off[n_tiles] = carry_l;
+    partial_off[n_tiles] = carry_p;
+    chunk_off[n_tiles] = carry_c;
+    hdr->total_leaves = carry_l;
+    hdr->n_items = carry_c;
+    hdr->overflow = (carry_l > leaf_cap || carry_p > partial_cap) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+
+// One split stage of the transposing reduction: lanes with bit OFF keep the
+// upper half of the live accumulators, the others the lower half; each adds
+// its partner's copy of the half it keeps.
+template <int N, int OFF, int T>
+__device__ __forceinline__ void xsplit(float (&acc)[T]) {
+  const bool up = (lane_id() & OFF) != 0;
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const float lo = acc[i], hi = acc[i + N / 2];
+    const float send = up ? lo : hi;
+    const float keep = up ? hi : lo;
+    acc[i] = __fadd_rn(keep, __shfl_xor(send, OFF, 64));
+  }
+}
+
+template <int OFF, int T>
+__device__ __forceinline__ void xfold(float (&acc)[T]) {
+#pragma unroll
+  for (int i = 0; i < T; ++i) acc[i] = __fadd_rn(acc[i], __shfl_xor(acc[i], OFF, 64));
+}
+
+// Reduce T per-lane accumulators over the 64 lanes. Afterwards lane l holds
+// node (l * NPL + m) in acc[m] for m < NPL = max(1, T/64) (for T < 64, lanes
+// l and l + T hold the same node l mod T).
+template <int T>
+__device__ __forceinline__ void reduce_nodes(float (&acc)[T]) {
+  if constexpr (T >= 64) {
+    xsplit<T, 32>(acc);
+    xsplit<T / 2, 16>(acc);
+    xsplit<T / 4, 8>(acc);
+    xsplit<T / 8, 4>(acc);
+    xsplit<T / 16, 2>(acc);
+    xsplit<T / 32, 1>(acc);
+  } else if constexpr (T == 32) {
+    xfold<32>(acc);
+    xsplit<32, 16>(acc);
+    xsplit<16, 8>(acc);
+    xsplit<8, 4>(acc);
+    xsplit<4, 2>(acc);
+    xsplit<2, 1>(acc);
+  }
+}
+
+template <int TX, int TY, int TZ, int KK, int PP, bool CNT>
+__global__ __launch_bounds__(256) void k_eval(
+    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const float* __restrict__ coords,
+    int chunk_leaves, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
+    const int64_t* __restrict__ partial_off, const int32_t* __restrict__ tile_cnt,
+    const int32_t* __restrict__ tile_fit, const int32_t* __restrict__ leaves,
+    const int32_t* __restrict__ item_tile, float* __restrict__ partials,
+    int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr) {
+  constexpr int T = TX * TY * TZ;
+  constexpr int NPL = T >= 64 ? T / 64 : 1;
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t n_items = hdr->n_items;
+  while (true) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&hdr->next_item, 1);
+    item = __shfl(item, 0, 64);
+    if ((int64_t)item >= n_items) break;
+    const int t = item_tile[item];
+    const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
+    const RoiDev& R = rois[g.r];
+    const float* cx = coords + R.coord_off;
+    const float* cy = cx + R.res[0];
+    const float* cz = cy + R.res[1];
+    float nx[TX], ny[TY], nz[TZ];
+#pragma unroll
+    for (int i = 0; i < TX; ++i) nx[i] = cx[min(g.i0 + i, R.res[0] - 1)];
+#pragma unroll
+    for (int j = 0; j < TY; ++j) ny[j] = cy[min(g.j0 + j, R.res[1] - 1)];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) nz[k] = cz[min(g.k0 + k, R.res[2] - 1)];
+    const float uih0 = R.ih[0], uih1 = R.ih[1], uih2 = R.ih[2];
+    const float c2 = R.c2;
+    const int cnt = tile_cnt[t];
+    const int nch = cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
+
+    float acc[T];
+#pragma unroll
+    for (int q = 0; q < T; ++q) acc[q] = 0.0f;
+
+    auto eval_leaf = [&](int lid) {
+      const int64_t slot = (int64_t)lid * SFK_LEAF + lane;
+      const float4 p = tv.pts[slot];
+      float ihx, ihy, ihz, w = 1.0f;
+      if constexpr (PP == PP_UNIFORM) {
+        ihx = uih0;
+        ihy = uih1;
+        ihz = uih2;
+      } else if constexpr (PP == PP_ISO) {
+        ihx = ihy = ihz = p.w;
+        w = __fmul_rn(__fmul_rn(p.w, p.w), p.w);
+      } else {
+        const float4 q = tv.pparam[slot];
+        ihx = q.x;
+        ihy = q.y;
+        ihz = q.z;
+        w = q.w;
+      }
+      float sx[TX], sy[TY], sz[TZ];
+#pragma unroll
+      for (int i = 0; i < TX; ++i) {
+        const float u = __fmul_rn(__fsub_rn(nx[i], p.x), ihx);
+        sx[i] = __fmul_rn(u, u);
+      }
+#pragma unroll
+      for (int j = 0; j < TY; ++j) {
+        const float u = __fmul_rn(__fsub_rn(ny[j], p.y), ihy);
+        sy[j] = __fmul_rn(u, u);
+      }
+#pragma unroll
+      for (int k = 0; k < TZ; ++k) {
+        const float u = __fmul_rn(__fsub_rn(nz[k], p.z), ihz);
+        sz[k] = __fmul_rn(u, u);
+      }
+      if constexpr (CNT) {
+#pragma unroll
+        for (int j = 0; j < TY; ++j)
+#pragma unroll
+          for (int i = 0; i < TX; ++i) {
+            const float tt = __fadd_rn(sx[i], sy[j]);
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+              const float u2 = __fadd_rn(tt, sz[k]);
+              acc[i + TX * (j + TY * k)] += (u2 < c2) ? 1.0f : 0.0f;
+            }
+          }
+      } else if constexpr (KK == KK_EPAN) {
+#pragma unroll
+        for (int j = 0; j < TY; ++j)
+#pragma unroll
+          for (int i = 0; i < TX; ++i) {
+            const float tt = __fadd_rn(sx[i], sy[j]);
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+              const float u2 = __fadd_rn(tt, sz[k]);
+              const float v = fmaxf(__fsub_rn(1.0f, u2), 0.0f);
+              float& a = acc[i + TX * (j + TY * k)];
+              if constexpr (PP == PP_UNIFORM)
+                a = __fadd_rn(a, v);
+              else
+                a = __fmaf_rn(w, v, a);
+            }
+          }
+      } else {
+        float ex[TX], ey[TY], ez[TZ];
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+          ex[i] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sx[i]));
+          if constexpr (PP != PP_UNIFORM) ex[i] = __fmul_rn(ex[i], w);
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) ey[j] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sy[j]));
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) ez[k] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sz[k]));
+#pragma unroll
+        for (int j = 0; j < TY; ++j)
+#pragma unroll
+          for (int i = 0; i < TX; ++i) {
+            const float tt = __fadd_rn(sx[i], sy[j]);
+            const float exy = __fmul_rn(ex[i], ey[j]);
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+              const float u2 = __fadd_rn(tt, sz[k]);
+              const float e = __fmul_rn(exy, ez[k]);
+              float& a = acc[i + TX * (j + TY * k)];
+              a = __fadd_rn(a, (u2 < c2) ? e : 0.0f);
+            }
+          }
+      }
+    };
+
+    auto node_out = [&](int node, float v) {
+      const int i = node % TX, j = (node / TX) % TY, k = node / (TX * TY);
+      const int gi = g.i0 + i, gj = g.j0 + j, gk = g.k0 + k;
+      if (gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
+        R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = v;
+    };
+    auto lane_node = [&](int m) { return T >= 64 ? lane * NPL + m : (lane & (T - 1)); };
+    const bool lane_writes = T >= 64 || lane < T;
+
+    if (tile_fit[t]) {
+      const int c = item - (int)chunk_off[t];
+      const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
+      const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
+      for (int64_t l = lb; l < le; ++l) eval_leaf(leaves[l]);
+      reduce_nodes<T>(acc);
+      if (nch == 1) {
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), __fmul_rn(acc[m], R.scale));
+        }
+      } else {
+        const int64_t pbase = (partial_off[t] + c) * T;
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) partials[pbase + lane_node(m)] = acc[m];
+        }
+        __threadfence();
+        int prev = 0;
+        if (lane == 0) prev = atomicAdd(&tile_done[t], 1);
+        prev = __shfl(prev, 0, 64);
+        if (prev == nch - 1) {
+          __threadfence();
+          if (lane_writes) {
+            const int64_t p0 = partial_off[t] * T;
+#pragma unroll
+            for (int m = 0; m < NPL; ++m) {
+              const int node = lane_node(m);
+              double s = 0.0;
+              for (int cc = 0; cc < nch; ++cc)
+                s += (double)__hip_atomic_load(&partials[p0 + (int64_t)cc * T + node],
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              node_out(node, (float)(s * (double)R.scale));
+            }
+          }
+        }
+      }
+    } else {
+      // lists did not fit the buffers: walk the hierarchy here, with the same
+      // leaf order and the same chunk boundaries as the split path
+      double dacc[NPL];
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) dacc[m] = 0.0;
+      int done = 0;
+      traverse(
+          tv, lds_stack[wave],
+          [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+          [&](int child, bool pass, uint64_t mask) {
+            (void)pass;
+            uint64_t mm = mask;
+            while (mm) {
+              const int b = __ffsll((unsigned long long)mm) - 1;
+              mm &= mm - 1;
+              eval_leaf(__shfl(child, b, 64));
+              ++done;
+              if (nch > 1 && done % chunk_leaves == 0) {
+                reduce_nodes<T>(acc);
+#pragma unroll
+                for (int m = 0; m < NPL; ++m) dacc[m] += (double)acc[m];
+#pragma unroll
+                for (int q = 0; q < T; ++q) acc[q] = 0.0f;
+              }
+            }
+          });
+      if (nch == 1) {
+        reduce_nodes<T>(acc);
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), __fmul_rn(acc[m], R.scale));
+        }
+      } else {
+        if (done % chunk_leaves != 0) {
+          reduce_nodes<T>(acc);
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) dacc[m] += (double)acc[m];
+        }
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m)
+            node_out(lane_node(m), (float)(dacc[m] * (double)R.scale));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// debug: support sets of single nodes (one wavefront per node)
+// ---------------------------------------------------------------------------
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int32_t* __restrict__ perm,
+                                                          const RoiDev* __restrict__ rois,
+                                                          const float* __restrict__ coords,
+                                                          int64_t node_begin, int64_t node_end,
+                                                          int64_t* __restrict__ cnt_out,
+                                                          const int64_t* __restrict__ off,
+                                                          int32_t* __restrict__ idx_out) {
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const RoiDev& R = rois[0];
+  const float* cx = coords + R.coord_off;
+  const float* cy = cx + R.res[0];
+  const float* cz = cy + R.res[1];
+  for (int64_t nd = node_begin + (int64_t)blockIdx.x * 4 + wave; nd < node_end;
+       nd += (int64_t)gridDim.x * 4) {
+    const int ix = (int)(nd % R.res[0]);
+    const int iy = (int)((nd / R.res[0]) % R.res[1]);
+    const int iz = (int)(nd / ((int64_t)R.res[0] * R.res[1]));
+    const int64_t t = (int64_t)(ix / TX) +
+                      (int64_t)R.ntile[0] * ((int64_t)(iy / TY) + (int64_t)R.ntile[1] * (iz / TZ));
+    const TileGeo g = tile_geo<TX, TY, TZ>(rois, 1, coords, t);
+    const float xn = cx[ix], yn = cy[iy], zn = cz[iz];
+    int64_t c = 0;
+    int32_t* out = off ? idx_out + off[nd - node_begin] : nullptr;
+    traverse(
+        tv, lds_stack[wave],
+        [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+        [&](int child, bool pass, uint64_t mask) {
+          (void)pass;
+          uint64_t mm = mask;
+          while (mm) {
+            const int b = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1;
+            const int lid = __shfl(child, b, 64);
+            const int64_t slot = (int64_t)lid * SFK_LEAF + lane;
+            const float4 p = tv.pts[slot];
+            float ihx = R.ih[0], ihy = R.ih[1], ihz = R.ih[2];
+            if (R.pp_mode == PP_ISO) {
+              ihx = ihy = ihz = p.w;
+            } else if (R.pp_mode == PP_ANISO) {
+              const float4 q = tv.pparam[slot];
+              ihx = q.x;
+              ihy = q.y;
+              ihz = q.z;
+            }
+            const bool mem = slot < tv.n && canon_u2(xn, yn, zn, p.x, p.y, p.z, ihx, ihy, ihz) < R.c2;
+            const uint64_t mb = ballot(mem);
+            if (out && mem) out[c + popc64(mb & lanemask_lt())] = perm[slot];
+            c += popc64(mb);
+          }
+        });
+    if (!off && lane == 0) cnt_out[nd - node_begin] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+bool tile_shape_supported(TileShape ts) {
+  return (ts.tx == 4 && ts.ty == 4 && ts.tz == 4) || (ts.tx == 8 && ts.ty == 4 && ts.tz == 4) ||
+         (ts.tx == 4 && ts.ty == 4 && ts.tz == 2);
+}
+
+#define SFK_SHAPE_SWITCH(ts, MACRO)                                  \
+  do {                                                               \
+    if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 4) {              \
+      MACRO(4, 4, 4);                                                \
+    } else if ((ts).tx == 8 && (ts).ty == 4 && (ts).tz == 4) {       \
+      MACRO(8, 4, 4);                                                \
+    } else if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 2) {       \
+      MACRO(4, 4, 2);                                                \
+    } else {                                                         \
+      return hipErrorInvalidValue;                                   \
+    }                                                                \
+  } while (0)
+
+static int grid_for(int64_t waves) {
+  const int64_t b = (waves + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                             TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
+                             int32_t* tile_nch, int32_t* tile_done, hipStream_t s) {
+  (void)chunk_leaves;
+  (void)tile_nch;
+  if (n_tiles <= 0) return hipSuccess;
+  const int nb = grid_for(n_tiles);
+#define SFK_L(X, Y, Z)                                                                       \
+  hipLaunchKernelGGL((k_tile_count<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, rois, n_rois, \
+                     coords, n_tiles, tile_cnt, tile_done)
+  SFK_SHAPE_SWITCH(ts, SFK_L);
+#undef SFK_L
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leaves, int64_t leaf_cap,
+                       int64_t partial_cap, int64_t* leaf_off, int64_t* partial_off,
+                       int64_t* chunk_off, int32_t* tile_fit, BatchHdr* hdr, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, n_tiles, chunk_leaves,
+                     leaf_cap, partial_cap, leaf_off, partial_off, chunk_off, tile_fit, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                             TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
+                             const int32_t* tile_fit, const int64_t* leaf_off,
+                             const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
+                             hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int nb = grid_for(n_tiles);
+#define SFK_L(X, Y, Z)                                                                      \
+  hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, rois, n_rois, \
+                     coords, n_tiles, tile_cnt, tile_fit, leaf_off, chunk_off, leaves, item_tile)
+  SFK_SHAPE_SWITCH(ts, SFK_L);
+#undef SFK_L
+  return hipGetLastError();
+}
+
+template <int X, int Y, int Z>
+static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, hipStream_t s,
+                                    TreeView tv, const RoiDev* rois, int n_rois,
+                                    const float* coords, int chunk_leaves,
+                                    const int64_t* leaf_off, const int64_t* chunk_off,
+                                    const int64_t* partial_off, const int32_t* tile_cnt,
+                                    const int32_t* tile_fit, const int32_t* leaves,
+                                    const int32_t* item_tile, float* partials,
+                                    int32_t* tile_done, BatchHdr* hdr) {
+#define SFK_E(KK, PP, C)                                                                       \
+  hipLaunchKernelGGL((k_eval<X, Y, Z, KK, PP, C>), dim3(grid), dim3(256), 0, s, tv, rois,     \
+                     n_rois, coords, chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, \
+                     tile_fit, leaves, item_tile, partials, tile_done, hdr)
+  if (cnt) {
+    if (pp == PP_UNIFORM) SFK_E(KK_EPAN, PP_UNIFORM, true);
+    else if (pp == PP_ISO) SFK_E(KK_EPAN, PP_ISO, true);
+    else SFK_E(KK_EPAN, PP_ANISO, true);
+  } else if (kk == KK_EPAN) {
+    if (pp == PP_UNIFORM) SFK_E(KK_EPAN, PP_UNIFORM, false);
+    else if (pp == PP_ISO) SFK_E(KK_EPAN, PP_ISO, false);
+    else SFK_E(KK_EPAN, PP_ANISO, false);
+  } else {
+    if (pp == PP_UNIFORM) SFK_E(KK_GAUSS, PP_UNIFORM, false);
+    else if (pp == PP_ISO) SFK_E(KK_GAUSS, PP_ISO, false);
+    else SFK_E(KK_GAUSS, PP_ANISO, false);
+  }
+#undef SFK_E
+  return hipGetLastError();
+}
+
+hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                        TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
+                        const int64_t* leaf_off, const int64_t* chunk_off,
+                        const int64_t* partial_off, const int32_t* tile_cnt,
+                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
+                        float* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                        hipStream_t s) {
+#define SFK_L(X, Y, Z)                                                                          \
+  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, s, tv, rois, n_rois, coords,     \
+                                    chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt,  \
+                                    tile_fit, leaves, item_tile, partials, tile_done, hdr)
+  SFK_SHAPE_SWITCH(ts, SFK_L);
+#undef SFK_L
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
+                                    const float* coords, TileShape ts, int64_t node_begin,
+                                    int64_t node_end, int64_t* cnt, const int64_t* off,
+                                    int32_t* idx_out, hipStream_t s) {
+  const int64_t nn = node_end - node_begin;
+  if (nn <= 0) return hipSuccess;
+  const int nb = grid_for(nn);
+#define SFK_L(X, Y, Z)                                                                     \
+  hipLaunchKernelGGL((k_debug_candidates<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, perm, \
+                     roi, coords, node_begin, node_end, cnt, off, idx_out)
+  SFK_SHAPE_SWITCH(ts, SFK_L);
+#undef SFK_L
+  return hipGetLastError();
+}
+
+}  // namespace sfk

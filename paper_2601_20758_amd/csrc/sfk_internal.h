@@ -1,0 +1,159 @@
+// Internal device/host structures of libsfkde (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SFK_LEAF 64            // particles per leaf bucket = wavefront width
+#define SFK_WAVE 64
+#define SFK_FANOUT 64          // children per interior node of the box hierarchy
+#define SFK_MAX_LEVELS 8       // 64^7 leaves is far beyond 2^31 particles
+#define SFK_SENTINEL 1.0e30f   // coordinate of padding / zero-support particles
+
+// Bounding box of a subtree (32 bytes). For a leaf, first = first particle
+// slot; for an interior node, first = first child index on the level below.
+struct alignas(16) NodeBox {
+  float lo[3];
+  int32_t first;
+  float hi[3];
+  int32_t count;  // real particles in the subtree
+};
+
+enum PPMode : int32_t {
+  PP_UNIFORM = 0,  // bandwidth from the ROI
+  PP_ISO = 1,      // per-particle isotropic inverse bandwidth in pts[].w
+  PP_ANISO = 2     // per-particle (ih_x, ih_y, ih_z, w) in pparam[]
+};
+
+// Read-only view of a tree passed to kernels by value.
+struct TreeView {
+  const float4* pts;     // n_leaves*64 slots, Morton order, padded with sentinels
+  const float4* pparam;  // PP_ANISO only
+  const NodeBox* nodes;  // all levels, level 0 = leaves
+  const float4* node_ih; // per node: per-axis minimum inverse bandwidth (per-point modes)
+  int32_t level_off[SFK_MAX_LEVELS];
+  int32_t level_cnt[SFK_MAX_LEVELS];
+  int32_t n_levels;      // levels including the leaf level (0 if empty)
+  int32_t n_leaves;
+  int64_t n;
+  int32_t pp_mode;
+  int32_t pad_;
+};
+
+enum KernelKind : int32_t { KK_EPAN = 0, KK_GAUSS = 1 };
+
+// One ROI of a batch, as the evaluation kernels see it (device copy).
+struct alignas(16) RoiDev {
+  double lo[3], hi[3];
+  int32_t res[3];
+  int32_t ntile[3];      // tiles per axis
+  int64_t tile_base;     // global index of the ROI's first tile
+  float ih[3];           // uniform inverse bandwidth (PP_UNIFORM)
+  float c2;              // support threshold on u2 (1 or 9)
+  float scale;           // final multiplier C_K * nu (* w for a uniform bandwidth)
+  int32_t kernel;        // KernelKind
+  int32_t count_mode;    // 1: accumulate support counts instead of density
+  int32_t coord_off;     // into the batch coordinate table: x, then y, then z
+  float* out;
+  int32_t pp_mode;       // PPMode of this evaluation
+  int32_t pad_[3];
+};
+
+// Device-side header of one batch (counters and totals; no host sync).
+struct alignas(16) BatchHdr {
+  int64_t n_tiles;
+  int64_t total_leaves;  // sum of candidate leaves over tiles
+  int64_t n_items;       // work items (tile chunks)
+  int64_t leaf_cap;      // capacity of the leaf-list buffer
+  int64_t item_cap;      // capacity of the item buffers
+  int32_t next_item;     // work-stealing counter
+  int32_t overflow;      // 1 if a capacity was exceeded (batch must be rerun)
+  int64_t useful;        // debug counters
+  int64_t tested;
+};
+
+// Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
+struct TileShape { int tx, ty, tz; };
+
+// ---- host-side launch wrappers (defined in the .hip files) ----
+namespace sfk {
+
+// scan.hip
+hipError_t scan_exclusive_i32_i64(const int32_t* in, int64_t* out, int64_t n,
+                                  int64_t* total, void* tmp, size_t tmp_bytes, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp,
+                              size_t tmp_bytes, hipStream_t s);
+
+// build.hip
+hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, float* result,
+                       hipStream_t s);
+hipError_t launch_morton(const float* xyz, int64_t n, const float* bbox, int bits,
+                         uint64_t* keys, uint32_t* vals, hipStream_t s);
+size_t radix_sort_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                            size_t tmp_bytes, hipStream_t s, int* result_in_alt);
+hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
+                         float4* pts, int32_t* perm_out, hipStream_t s);
+hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
+                             hipStream_t s);
+hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
+                              int32_t n_parent, hipStream_t s);
+hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mode,
+                          int64_t n, const NodeBox* nodes, const int32_t* level_off,
+                          const int32_t* level_cnt, int n_levels, float4* node_ih,
+                          hipStream_t s);
+hipError_t launch_knn(TreeView tv, int k, float* h2_sorted, hipStream_t s);
+hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
+                             const int32_t* perm, int64_t n, hipStream_t s);
+
+hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+// eval.hip
+hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, float* coords, hipStream_t s);
+hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap,
+                           hipStream_t s);
+hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                             TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
+                             int32_t* tile_nch, int32_t* tile_done, hipStream_t s);
+hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leaves, int64_t leaf_cap,
+                       int64_t partial_cap, int64_t* leaf_off, int64_t* partial_off,
+                       int64_t* chunk_off, int32_t* tile_fit, BatchHdr* hdr, hipStream_t s);
+hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                             TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
+                             const int32_t* tile_fit, const int64_t* leaf_off,
+                             const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
+                             hipStream_t s);
+hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+                        TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
+                        const int64_t* leaf_off, const int64_t* chunk_off,
+                        const int64_t* partial_off, const int32_t* tile_cnt,
+                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
+                        float* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                        hipStream_t s);
+hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
+                                    const float* coords, TileShape ts, int64_t node_begin,
+                                    int64_t node_end, int64_t* cnt, const int64_t* off,
+                                    int32_t* idx_out, hipStream_t s);
+bool tile_shape_supported(TileShape ts);
+
+// mbe.hip
+hipError_t launch_inbox_flags(const float4* pts, int64_t n, const double* lo, const double* hi,
+                              int32_t* flags, hipStream_t s);
+hipError_t launch_compact(const float4* pts, const int32_t* perm, const int32_t* flags,
+                          const int64_t* pos, int64_t n, int64_t n_slots_out, float4* out_pts,
+                          int32_t* out_perm, float* out_axes, int64_t n_b, hipStream_t s);
+hipError_t launch_axis_keys(const float* axes, int64_t n_b, uint64_t* keys, uint32_t* vals,
+                            hipStream_t s);
+hipError_t launch_mbe_ell(const uint64_t* sorted_keys_xyz, int64_t n_b, const double* lo,
+                          const double* hi, const int32_t* res, float* ell_out,
+                          int32_t* flags_out, hipStream_t s);
+hipError_t launch_trilinear_mean(const float4* pts, int64_t n_b, const float* grid,
+                                 const double* lo, const double* hi, const int32_t* res,
+                                 double* pden, double* block_sums, double* ave, hipStream_t s);
+hipError_t launch_asl2(const double* pden, int64_t n_b, const double* ave, const float* ell0,
+                       const double* lo, const double* hi, const int32_t* res, float4* pparam,
+                       float* ell_out, hipStream_t s);
+
+}  // namespace sfk

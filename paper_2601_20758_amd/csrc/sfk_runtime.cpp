@@ -1,0 +1,1637 @@
+// libsfkde host runtime: the C ABI declared in include/sfkde.h.
+//
+// Owns contexts (device, allocator, budget, streams, batch slots), trees
+// (device-resident index built by build.hip), the batched evaluation
+// pipeline (eval.hip), the in-box / MBE pipeline (mbe.hip), tickets and the
+// serving loop. No exception crosses the ABI; every entry point validates
+// its arguments before any device work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sfk_internal.h"
+#include "sfkde.h"
+
+namespace sfk {
+hipError_t launch_trilinear_mean(const float4* pts, int64_t n_b, const float* grid,
+                                 const double* lo, const double* hi, const int32_t* res,
+                                 double* pden, double* block_sums, double* ave, hipStream_t s);
+}
+
+namespace {
+
+thread_local std::string g_tls_err;
+
+constexpr int kNumSlots = 4;
+constexpr int kStagingRing = 8;
+constexpr int kDefaultChunkLeaves = 64;
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct Workspace {
+  DevBuf rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
+      item_tile, partials, hdr;
+  int64_t want_leaf_cap = 0;
+  int64_t want_partial_cap = 0;
+};
+
+struct Staging {
+  RoiDev* host = nullptr;  // pinned
+  int cap = 0;
+  BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header
+  hipEvent_t ev = nullptr;
+  bool ev_valid = false;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  Workspace ws;
+  Staging st;
+  bool busy = false;
+  int64_t ticket = -1;
+  size_t batch_bytes = 0;  // grid bytes admitted for the running batch
+};
+
+struct Ticket {
+  int state = 0;  // 0 pending, 1 running, 2 done, 3 cancelled, 4 failed
+  int slot = -1;
+  sfk_tree tree = nullptr;
+  std::vector<sfk_roi> rois;
+  sfk_status status = SFK_OK;
+};
+
+struct sfk_ctx_s {
+  int device = 0;
+  sfk_allocator alloc{};
+  bool use_alloc = false;
+  size_t budget = 0;
+  size_t ws_bytes = 0;    // workspace held (bounded by budget)
+  size_t tree_bytes = 0;  // trees held
+  std::string err;
+  int n_cu = 256;
+  sfk_eval_opts opts{};
+  Slot slots[kNumSlots];
+  std::map<int64_t, Ticket> tickets;
+  std::deque<int64_t> pending;
+  int64_t next_ticket = 1;
+  // one-ROI stream-ordered path
+  Workspace direct_ws;
+  Staging direct_st[kStagingRing];
+  int direct_next = 0;
+  hipEvent_t direct_last = nullptr;
+  bool direct_last_valid = false;
+  hipStream_t direct_last_stream = nullptr;
+  // autotuner table: key -> tile shape id
+  std::map<int, int> tune;
+};
+
+struct sfk_tree_s {
+  sfk_ctx ctx = nullptr;
+  int64_t n = 0;
+  double bbox[6] = {0, 0, 0, 0, 0, 0};
+  int32_t n_leaves = 0, n_levels = 0;
+  int32_t level_off[SFK_MAX_LEVELS] = {0};
+  int32_t level_cnt[SFK_MAX_LEVELS] = {0};
+  DevBuf pts, perm, nodes, node_ih, h2;
+  int32_t pp_mode = PP_UNIFORM;  // PP_ISO when a per-point bandwidth exists
+  int32_t knn_k = 0;
+  size_t bytes = 0;
+};
+
+namespace {
+
+void set_err(sfk_ctx c, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  g_tls_err = buf;
+}
+
+#define SFK_HIP(c, expr)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      set_err((c), "%s failed: %s", #expr, hipGetErrorString(e_));              \
+      return SFK_E_DEVICE;                                                      \
+    }                                                                           \
+  } while (0)
+
+#define SFK_TRY(expr)                   \
+  do {                                  \
+    sfk_status s_ = (expr);             \
+    if (s_ != SFK_OK) return s_;        \
+  } while (0)
+
+#define SFK_GUARD_BEGIN try {
+#define SFK_GUARD_END(c)                                   \
+  }                                                        \
+  catch (const std::bad_alloc&) {                          \
+    set_err((c), "host allocation failed");                \
+    return SFK_E_NOMEM;                                    \
+  }                                                        \
+  catch (...) {                                            \
+    set_err((c), "internal error");                        \
+    return SFK_E_INTERNAL;                                 \
+  }
+
+// ---- device memory through the context's allocator ----
+
+void raw_free(sfk_ctx c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c->use_alloc)
+    c->alloc.free(p, bytes, c->alloc.user);
+  else
+    (void)hipFree(p);
+}
+
+void* raw_alloc(sfk_ctx c, size_t bytes) {
+  if (c->use_alloc) return c->alloc.alloc(bytes, c->alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+size_t round_bytes(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Grow-only workspace buffer (the caller guarantees the old contents are idle).
+sfk_status ws_reserve(sfk_ctx c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return SFK_OK;
+  size_t nb = round_bytes(std::max(bytes, b.bytes + b.bytes / 4));
+  if (c->budget && c->ws_bytes - b.bytes + nb > c->budget) {
+    nb = round_bytes(bytes);
+    if (c->ws_bytes - b.bytes + nb > c->budget) {
+      set_err(c, "workspace for %s (%zu bytes) exceeds the device-memory budget", what, nb);
+      return SFK_E_BUDGET;
+    }
+  }
+  raw_free(c, b.p, b.bytes);
+  c->ws_bytes -= b.bytes;
+  b.p = nullptr;
+  b.bytes = 0;
+  void* p = raw_alloc(c, nb);
+  if (!p) {
+    set_err(c, "device allocation of %zu bytes for %s failed", nb, what);
+    return SFK_E_NOMEM;
+  }
+  b.p = p;
+  b.bytes = nb;
+  c->ws_bytes += nb;
+  return SFK_OK;
+}
+
+void ws_release(sfk_ctx c, DevBuf& b) {
+  if (b.p) {
+    raw_free(c, b.p, b.bytes);
+    c->ws_bytes -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+sfk_status tree_alloc(sfk_ctx c, sfk_tree t, DevBuf& b, size_t bytes, const char* what) {
+  bytes = round_bytes(std::max<size_t>(bytes, 256));
+  void* p = raw_alloc(c, bytes);
+  if (!p) {
+    set_err(c, "device allocation of %zu bytes for %s failed", bytes, what);
+    return SFK_E_NOMEM;
+  }
+  b.p = p;
+  b.bytes = bytes;
+  c->tree_bytes += bytes;
+  t->bytes += bytes;
+  return SFK_OK;
+}
+
+void tree_free(sfk_ctx c, sfk_tree t, DevBuf& b) {
+  if (b.p) {
+    raw_free(c, b.p, b.bytes);
+    c->tree_bytes -= b.bytes;
+    t->bytes -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Temporary device buffer freed on scope exit (build-time scratch).
+struct TmpBuf {
+  sfk_ctx c;
+  DevBuf b;
+  explicit TmpBuf(sfk_ctx cc) : c(cc) {}
+  ~TmpBuf() { raw_free(c, b.p, b.bytes); }
+  sfk_status get(size_t bytes, const char* what) {
+    bytes = round_bytes(std::max<size_t>(bytes, 256));
+    b.p = raw_alloc(c, bytes);
+    if (!b.p) {
+      set_err(c, "device allocation of %zu bytes for %s failed", bytes, what);
+      return SFK_E_NOMEM;
+    }
+    b.bytes = bytes;
+    return SFK_OK;
+  }
+  template <typename T>
+  T* as() const { return (T*)b.p; }
+};
+
+sfk_status staging_reserve(sfk_ctx c, Staging& st, int n) {
+  if (!st.ev) SFK_HIP(c, hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+  if (!st.hdr_host) SFK_HIP(c, hipHostMalloc((void**)&st.hdr_host, sizeof(BatchHdr)));
+  if (st.cap >= n) return SFK_OK;
+  if (st.host) {
+    if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
+    SFK_HIP(c, hipHostFree(st.host));
+    st.host = nullptr;
+  }
+  const int cap = std::max(n, 64);
+  SFK_HIP(c, hipHostMalloc((void**)&st.host, sizeof(RoiDev) * (size_t)cap));
+  st.cap = cap;
+  return SFK_OK;
+}
+
+// ---- constants of the kernels (closed forms) ----
+
+double ck_epanechnikov() { return 15.0 / (8.0 * M_PI); }
+double ck_gauss_trunc3() {
+  // 1 / ((2 pi)^{3/2} P(chi^2_3 < 9)), P = erf(3/sqrt2) - sqrt(2/pi) 3 e^{-9/2}
+  const double p = std::erf(3.0 / std::sqrt(2.0)) - std::sqrt(2.0 / M_PI) * 3.0 * std::exp(-4.5);
+  return 1.0 / (std::pow(2.0 * M_PI, 1.5) * p);
+}
+
+TileShape shape_of(int id) {
+  switch (id) {
+    case 2: return TileShape{8, 4, 4};
+    case 3: return TileShape{4, 4, 2};
+    default: return TileShape{4, 4, 4};
+  }
+}
+
+TreeView view_of(sfk_tree t) {
+  TreeView tv{};
+  tv.pts = (const float4*)t->pts.p;
+  tv.pparam = nullptr;
+  tv.nodes = (const NodeBox*)t->nodes.p;
+  tv.node_ih = (const float4*)t->node_ih.p;
+  for (int l = 0; l < SFK_MAX_LEVELS; ++l) {
+    tv.level_off[l] = t->level_off[l];
+    tv.level_cnt[l] = t->level_cnt[l];
+  }
+  tv.n_levels = t->n_levels;
+  tv.n_leaves = t->n_leaves;
+  tv.n = t->n;
+  tv.pp_mode = t->pp_mode;
+  return tv;
+}
+
+void level_layout(int32_t n_leaves, int32_t* off, int32_t* cnt, int32_t* n_levels,
+                  int32_t* total) {
+  int lv = 0, o = 0;
+  if (n_leaves > 0) {
+    int c = n_leaves;
+    while (true) {
+      off[lv] = o;
+      cnt[lv] = c;
+      o += c;
+      ++lv;
+      if (c <= SFK_FANOUT) break;
+      c = (c + SFK_FANOUT - 1) / SFK_FANOUT;
+    }
+  }
+  for (int l = lv; l < SFK_MAX_LEVELS; ++l) {
+    off[l] = o;
+    cnt[l] = 0;
+  }
+  *n_levels = lv;
+  *total = o;
+}
+
+// Leaf boxes and the box hierarchy of a leaf layout.
+sfk_status build_boxes(sfk_ctx c, const float4* pts, int64_t n, int32_t n_leaves,
+                       NodeBox* nodes, const int32_t* off, const int32_t* cnt, int n_levels,
+                       hipStream_t s) {
+  if (n_levels <= 0) return SFK_OK;
+  SFK_HIP(c, sfk::launch_leaf_boxes(pts, n, n_leaves, nodes + off[0], s));
+  for (int l = 1; l < n_levels; ++l)
+    SFK_HIP(c, sfk::launch_level_boxes(nodes + off[l - 1], cnt[l - 1], nodes + off[l], cnt[l], s));
+  return SFK_OK;
+}
+
+// ---- ROI validation ----
+
+sfk_status validate_roi(sfk_ctx c, sfk_tree t, const sfk_roi* r, int idx) {
+  if (!r) {
+    set_err(c, "roi %d: NULL descriptor", idx);
+    return SFK_E_INVAL;
+  }
+  if (!r->d_out) {
+    set_err(c, "roi %d: d_out is NULL", idx);
+    return SFK_E_INVAL;
+  }
+  int64_t m = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(r->lo[k]) && std::isfinite(r->hi[k]) && r->hi[k] > r->lo[k])) {
+      set_err(c, "roi %d: box axis %d needs finite lo < hi", idx, k);
+      return SFK_E_INVAL;
+    }
+    if (r->res[k] < 2) {
+      set_err(c, "roi %d: res[%d] = %d (each must be >= 2)", idx, k, r->res[k]);
+      return SFK_E_INVAL;
+    }
+    m *= r->res[k];
+  }
+  if (m > (int64_t)1 << 31) {
+    set_err(c, "roi %d: grid of %lld nodes exceeds 2^31", idx, (long long)m);
+    return SFK_E_INVAL;
+  }
+  if (r->kernel != SFK_KERNEL_EPANECHNIKOV && r->kernel != SFK_KERNEL_GAUSS_TRUNC3) {
+    set_err(c, "roi %d: unknown kernel %d", idx, r->kernel);
+    return SFK_E_INVAL;
+  }
+  if (r->norm != SFK_NORM_PAPER && r->norm != SFK_NORM_COUNT) {
+    set_err(c, "roi %d: unknown norm %d", idx, r->norm);
+    return SFK_E_INVAL;
+  }
+  if (r->set != SFK_SET_CLOUD && r->set != SFK_SET_IN_ROI) {
+    set_err(c, "roi %d: unknown set %d", idx, r->set);
+    return SFK_E_INVAL;
+  }
+  switch (r->bw) {
+    case SFK_BW_FIXED:
+      for (int k = 0; k < 3; ++k)
+        if (!(r->h[k] > 0.0f) || !std::isfinite(r->h[k])) {
+          set_err(c, "roi %d: fixed bandwidth h[%d] must be finite and > 0", idx, k);
+          return SFK_E_INVAL;
+        }
+      break;
+    case SFK_BW_ROI_SCALED:
+      if (!(r->h[0] > 0.0f) || !std::isfinite(r->h[0])) {
+        set_err(c, "roi %d: ROI-scaled bandwidth factor h[0] must be finite and > 0", idx);
+        return SFK_E_INVAL;
+      }
+      break;
+    case SFK_BW_PER_POINT:
+      if (t && t->pp_mode != PP_ISO && t->n > 0) {
+        set_err(c, "roi %d: per-point bandwidth requested but the tree has none "
+                   "(build with knn_k > 0 or d_h)", idx);
+        return SFK_E_INVAL;
+      }
+      break;
+    case SFK_BW_MBE:
+      if (r->kernel != SFK_KERNEL_EPANECHNIKOV) {
+        set_err(c, "roi %d: MBE is defined for the Epanechnikov kernel", idx);
+        return SFK_E_UNSUPPORTED;
+      }
+      if (r->set != SFK_SET_IN_ROI) {
+        set_err(c, "roi %d: MBE uses the particles inside B (set = SFK_SET_IN_ROI)", idx);
+        return SFK_E_INVAL;
+      }
+      break;
+    default:
+      set_err(c, "roi %d: unknown bandwidth mode %d", idx, r->bw);
+      return SFK_E_INVAL;
+  }
+  return SFK_OK;
+}
+
+sfk_status validate_disjoint_outputs(sfk_ctx c, const sfk_roi* rois, int n) {
+  std::vector<std::pair<uintptr_t, uintptr_t>> iv;
+  iv.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    const uintptr_t a = (uintptr_t)rois[i].d_out;
+    const uintptr_t m = (uintptr_t)rois[i].res[0] * rois[i].res[1] * rois[i].res[2];
+    iv.push_back({a, a + m * sizeof(float)});
+  }
+  std::sort(iv.begin(), iv.end());
+  for (size_t i = 1; i < iv.size(); ++i)
+    if (iv[i].first < iv[i - 1].second) {
+      set_err(c, "output grids of two ROIs overlap");
+      return SFK_E_INVAL;
+    }
+  return SFK_OK;
+}
+
+// ---- one group of ROIs through count -> plan -> fill -> evaluate ----
+
+struct GroupRoi {
+  const sfk_roi* roi;
+  int kk, pp;
+  bool count_mode;
+  float ih[3];
+  float c2;
+  float scale;
+};
+
+int chunk_leaves_of(sfk_ctx c) {
+  return c->opts.chunk_leaves > 0 ? c->opts.chunk_leaves : kDefaultChunkLeaves;
+}
+
+int blocks_per_cu(sfk_ctx c, TileShape ts) {
+  if (c->opts.persistent_waves_per_cu > 0) return std::max(1, c->opts.persistent_waves_per_cu / 4);
+  const int T = ts.tx * ts.ty * ts.tz;
+  return T > 64 ? 2 : 3;
+}
+
+// Fill RoiDev descriptors for rois[0..n) and the per-group tile total.
+void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int64_t* n_tiles,
+                 int64_t* n_coords) {
+  int64_t tb = 0, co = 0;
+  for (size_t i = 0; i < g.size(); ++i) {
+    const sfk_roi* r = g[i].roi;
+    RoiDev d{};
+    for (int k = 0; k < 3; ++k) {
+      d.lo[k] = r->lo[k];
+      d.hi[k] = r->hi[k];
+      d.res[k] = r->res[k];
+    }
+    d.ntile[0] = (r->res[0] + ts.tx - 1) / ts.tx;
+    d.ntile[1] = (r->res[1] + ts.ty - 1) / ts.ty;
+    d.ntile[2] = (r->res[2] + ts.tz - 1) / ts.tz;
+    d.tile_base = tb;
+    for (int k = 0; k < 3; ++k) d.ih[k] = g[i].ih[k];
+    d.c2 = g[i].c2;
+    d.scale = g[i].scale;
+    d.kernel = g[i].kk;
+    d.count_mode = g[i].count_mode ? 1 : 0;
+    d.coord_off = (int32_t)co;
+    d.out = r->d_out;
+    d.pp_mode = g[i].pp;
+    out[i] = d;
+    tb += (int64_t)d.ntile[0] * d.ntile[1] * d.ntile[2];
+    co += r->res[0] + r->res[1] + r->res[2];
+  }
+  *n_tiles = tb;
+  *n_coords = co;
+}
+
+// Launch the whole pipeline of one group on stream s. rois_dev is the device
+// copy of `rd` (already enqueued). The workspace must be idle or only used
+// earlier on the same stream.
+sfk_status launch_group(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
+                        const RoiDev* rois_dev, int n_rois, int64_t n_tiles, const float* coords,
+                        Workspace& ws, hipStream_t s) {
+  const int CH = chunk_leaves_of(c);
+  const int T = ts.tx * ts.ty * ts.tz;
+  int64_t leaf_cap = std::max<int64_t>(ws.want_leaf_cap, std::max<int64_t>(1 << 20, 64 * n_tiles));
+  int64_t partial_cap = std::max<int64_t>(ws.want_partial_cap, std::max<int64_t>(1 << 14, n_tiles / 4));
+  leaf_cap = std::max<int64_t>(leaf_cap, (int64_t)(ws.leaves.bytes / sizeof(int32_t)));
+  partial_cap =
+      std::max<int64_t>(partial_cap, (int64_t)(ws.partials.bytes / (sizeof(float) * (size_t)T)));
+  if (c->opts.list_capacity > 0) {
+    leaf_cap = c->opts.list_capacity;
+    partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
+  }
+  const int64_t item_cap = n_tiles + leaf_cap / CH + 1;
+  SFK_TRY(ws_reserve(c, ws.tile_cnt, sizeof(int32_t) * (size_t)n_tiles, "tile counts"));
+  SFK_TRY(ws_reserve(c, ws.tile_fit, sizeof(int32_t) * (size_t)n_tiles, "tile flags"));
+  SFK_TRY(ws_reserve(c, ws.tile_done, sizeof(int32_t) * (size_t)n_tiles, "tile counters"));
+  SFK_TRY(ws_reserve(c, ws.leaf_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "leaf offsets"));
+  SFK_TRY(ws_reserve(c, ws.partial_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "partial offsets"));
+  SFK_TRY(ws_reserve(c, ws.chunk_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "item offsets"));
+  SFK_TRY(ws_reserve(c, ws.leaves, sizeof(int32_t) * (size_t)leaf_cap, "leaf lists"));
+  SFK_TRY(ws_reserve(c, ws.item_tile, sizeof(int32_t) * (size_t)item_cap, "work items"));
+  SFK_TRY(ws_reserve(c, ws.partials, sizeof(float) * (size_t)partial_cap * T, "partial sums"));
+  SFK_TRY(ws_reserve(c, ws.hdr, sizeof(BatchHdr), "batch header"));
+  BatchHdr* hdr = (BatchHdr*)ws.hdr.p;
+  int32_t* tile_cnt = (int32_t*)ws.tile_cnt.p;
+  int32_t* tile_fit = (int32_t*)ws.tile_fit.p;
+  int32_t* tile_done = (int32_t*)ws.tile_done.p;
+  int64_t* leaf_off = (int64_t*)ws.leaf_off.p;
+  int64_t* partial_off = (int64_t*)ws.partial_off.p;
+  int64_t* chunk_off = (int64_t*)ws.chunk_off.p;
+  SFK_HIP(c, sfk::launch_hdr_init(hdr, n_tiles, leaf_cap, item_cap, s));
+  SFK_HIP(c, sfk::launch_tile_count(tv, rois_dev, n_rois, coords, ts, n_tiles, CH, tile_cnt,
+                                     nullptr, tile_done, s));
+  SFK_HIP(c, sfk::launch_plan(tile_cnt, n_tiles, CH, leaf_cap, partial_cap, leaf_off, partial_off,
+                               chunk_off, tile_fit, hdr, s));
+  SFK_HIP(c, sfk::launch_tile_fill2(tv, rois_dev, n_rois, coords, ts, n_tiles, tile_cnt, tile_fit,
+                                     leaf_off, chunk_off, (int32_t*)ws.leaves.p,
+                                     (int32_t*)ws.item_tile.p, s));
+  const int grid = std::max(1, c->n_cu * blocks_per_cu(c, ts));
+  SFK_HIP(c, sfk::launch_eval2(tv, rois_dev, n_rois, coords, ts, kk, pp, cnt, CH, leaf_off,
+                                chunk_off, partial_off, tile_cnt, tile_fit, (int32_t*)ws.leaves.p,
+                                (int32_t*)ws.item_tile.p, (float*)ws.partials.p, tile_done, hdr,
+                                grid, s));
+  return SFK_OK;
+}
+
+// Resolve the per-ROI parameters of a CLOUD-set, non-MBE ROI.
+GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
+  GroupRoi g{};
+  g.roi = r;
+  g.kk = r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? KK_GAUSS : KK_EPAN;
+  g.count_mode = count_mode;
+  g.c2 = g.kk == KK_GAUSS ? 9.0f : 1.0f;
+  const double ck = g.kk == KK_GAUSS ? ck_gauss_trunc3() : ck_epanechnikov();
+  const double nu = (r->norm == SFK_NORM_COUNT || t->n == 0) ? 1.0 : 1.0 / (double)t->n;
+  if (r->bw == SFK_BW_PER_POINT) {
+    g.pp = PP_ISO;
+    g.ih[0] = g.ih[1] = g.ih[2] = 1.0f;
+    g.scale = (float)(ck * nu);
+  } else {
+    float h[3];
+    for (int k = 0; k < 3; ++k) {
+      if (r->bw == SFK_BW_FIXED)
+        h[k] = r->h[k];
+      else
+        h[k] = (float)((double)r->h[0] * (r->hi[k] - r->lo[k]));
+    }
+    g.pp = PP_UNIFORM;
+    for (int k = 0; k < 3; ++k) g.ih[k] = (float)(1.0 / (double)h[k]);
+    const double w = 1.0 / ((double)h[0] * (double)h[1] * (double)h[2]);
+    g.scale = (float)(ck * nu * w);
+  }
+  if (count_mode) g.scale = 1.0f;
+  return g;
+}
+
+// Enqueue descriptors + pipeline for CLOUD-set ROIs grouped by (kernel, pp).
+sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
+                              bool count_mode, TileShape ts, Workspace& ws, Staging& st,
+                              hipStream_t s) {
+  if (rois.empty()) return SFK_OK;
+  // groups in a fixed order
+  std::vector<std::vector<GroupRoi>> groups;
+  std::vector<std::pair<int, int>> keys;
+  for (const sfk_roi* r : rois) {
+    GroupRoi g = resolve_cloud_roi(t, r, count_mode);
+    const std::pair<int, int> key{count_mode ? 0 : g.kk, g.pp};
+    size_t gi = 0;
+    while (gi < keys.size() && keys[gi] != key) ++gi;
+    if (gi == keys.size()) {
+      keys.push_back(key);
+      groups.emplace_back();
+    }
+    groups[gi].push_back(g);
+  }
+  const int n = (int)rois.size();
+  SFK_TRY(staging_reserve(c, st, n));
+  if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
+  std::vector<int64_t> tiles(groups.size()), ncoord(groups.size());
+  int off = 0;
+  int64_t coord_total = 0;
+  std::vector<int> roi_off(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    roi_off[gi] = off;
+    make_roidev(groups[gi], ts, st.host + off, &tiles[gi], &ncoord[gi]);
+    for (size_t i = 0; i < groups[gi].size(); ++i) st.host[off + i].coord_off += (int32_t)coord_total;
+    off += (int)groups[gi].size();
+    coord_total += ncoord[gi];
+  }
+  SFK_TRY(ws_reserve(c, ws.rois, sizeof(RoiDev) * (size_t)n, "ROI descriptors"));
+  SFK_TRY(ws_reserve(c, ws.coords, sizeof(float) * (size_t)coord_total, "node coordinates"));
+  RoiDev* rd = (RoiDev*)ws.rois.p;
+  SFK_HIP(c, hipMemcpyAsync(rd, st.host, sizeof(RoiDev) * (size_t)n, hipMemcpyHostToDevice, s));
+  SFK_HIP(c, hipEventRecord(st.ev, s));
+  st.ev_valid = true;
+  SFK_HIP(c, sfk::launch_roi_coords(rd, n, (float*)ws.coords.p, s));
+  TreeView tv = view_of(t);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const int kk = keys[gi].first, pp = keys[gi].second;
+    SFK_TRY(launch_group(c, tv, ts, kk, pp, count_mode, rd + roi_off[gi], (int)groups[gi].size(),
+                         tiles[gi], (const float*)ws.coords.p, ws, s));
+  }
+  if (st.hdr_host)
+    SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+  return SFK_OK;
+}
+
+// After a batch completed: grow the list capacities if they overflowed.
+void absorb_stats(Workspace& ws, const Staging& st) {
+  if (!st.hdr_host) return;
+  const BatchHdr& h = *st.hdr_host;
+  if (h.total_leaves > h.leaf_cap) ws.want_leaf_cap = h.total_leaves + h.total_leaves / 4;
+}
+
+// ---- IN_ROI set and MBE: a sub-cloud of the particles inside B ----
+
+struct SubCloud {
+  int64_t n_b = 0;
+  int32_t n_leaves = 0, n_levels = 0, total_nodes = 0;
+  int32_t off[SFK_MAX_LEVELS], cnt[SFK_MAX_LEVELS];
+  TmpBuf pts, perm, nodes, node_ih, pparam, axes;
+  explicit SubCloud(sfk_ctx c) : pts(c), perm(c), nodes(c), node_ih(c), pparam(c), axes(c) {}
+  TreeView view(int pp) const {
+    TreeView tv{};
+    tv.pts = pts.as<const float4>();
+    tv.pparam = pparam.as<const float4>();
+    tv.nodes = nodes.as<const NodeBox>();
+    tv.node_ih = node_ih.as<const float4>();
+    for (int l = 0; l < SFK_MAX_LEVELS; ++l) {
+      tv.level_off[l] = off[l];
+      tv.level_cnt[l] = cnt[l];
+    }
+    tv.n_levels = n_levels;
+    tv.n_leaves = n_leaves;
+    tv.n = n_b;
+    tv.pp_mode = pp;
+    return tv;
+  }
+};
+
+sfk_status make_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool want_axes, SubCloud& sc,
+                         hipStream_t s) {
+  const int64_t n_slots = (int64_t)t->n_leaves * SFK_LEAF;
+  TmpBuf flags(c), pos(c), stmp(c), total(c);
+  SFK_TRY(flags.get(sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1), "in-box flags"));
+  SFK_TRY(pos.get(sizeof(int64_t) * (size_t)std::max<int64_t>(n_slots, 1), "in-box positions"));
+  SFK_TRY(stmp.get(sfk::scan_tmp_bytes(n_slots), "scan scratch"));
+  SFK_TRY(total.get(sizeof(int64_t), "in-box total"));
+  SFK_HIP(c, sfk::launch_inbox_flags((const float4*)t->pts.p, n_slots, r->lo, r->hi,
+                                      flags.as<int32_t>(), s));
+  SFK_HIP(c, sfk::scan_exclusive_i32_i64(flags.as<int32_t>(), pos.as<int64_t>(), n_slots,
+                                          total.as<int64_t>(), stmp.b.p, stmp.b.bytes, s));
+  int64_t n_b = 0;
+  SFK_HIP(c, hipMemcpyAsync(&n_b, total.b.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipStreamSynchronize(s));
+  sc.n_b = n_b;
+  sc.n_leaves = (int32_t)((n_b + SFK_LEAF - 1) / SFK_LEAF);
+  level_layout(sc.n_leaves, sc.off, sc.cnt, &sc.n_levels, &sc.total_nodes);
+  const int64_t out_slots = (int64_t)sc.n_leaves * SFK_LEAF;
+  SFK_TRY(sc.pts.get(sizeof(float4) * (size_t)std::max<int64_t>(out_slots, 1), "in-box particles"));
+  SFK_TRY(sc.perm.get(sizeof(int32_t) * (size_t)std::max<int64_t>(n_b, 1), "in-box indices"));
+  SFK_TRY(sc.nodes.get(sizeof(NodeBox) * (size_t)std::max(sc.total_nodes, 1), "in-box boxes"));
+  SFK_TRY(sc.node_ih.get(sizeof(float4) * (size_t)std::max(sc.total_nodes, 1), "in-box node bandwidths"));
+  if (want_axes)
+    SFK_TRY(sc.axes.get(sizeof(float) * 3 * (size_t)std::max<int64_t>(n_b, 1), "in-box axes"));
+  if (n_b == 0) return SFK_OK;
+  SFK_HIP(c, sfk::launch_compact((const float4*)t->pts.p, (const int32_t*)t->perm.p,
+                                  flags.as<int32_t>(), pos.as<int64_t>(), n_slots, out_slots,
+                                  sc.pts.as<float4>(), sc.perm.as<int32_t>(),
+                                  want_axes ? sc.axes.as<float>() : nullptr, n_b, s));
+  SFK_TRY(build_boxes(c, sc.pts.as<float4>(), n_b, sc.n_leaves, sc.nodes.as<NodeBox>(), sc.off,
+                      sc.cnt, sc.n_levels, s));
+  // keep the temporaries alive until the kernels that read them are done
+  SFK_HIP(c, hipStreamSynchronize(s));
+  return SFK_OK;
+}
+
+struct MbeDebug {
+  float* ell0 = nullptr;
+  int64_t* n_b = nullptr;
+  int64_t* idx_b = nullptr;
+  float* pilot = nullptr;
+  float* pden = nullptr;
+  double* aveden = nullptr;
+  float* ell_j = nullptr;
+  int64_t cap_b = 0;
+};
+
+// Evaluate one IN_ROI-set ROI (any bandwidth mode, MBE included). Blocking.
+sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mode, TileShape ts,
+                         Workspace& ws, Staging& st, hipStream_t s, MbeDebug* dbg) {
+  const bool mbe = r->bw == SFK_BW_MBE;
+  SubCloud sc(c);
+  SFK_TRY(make_subcloud(c, t, r, mbe, sc, s));
+  const int64_t n_b = sc.n_b;
+  const int64_t m = (int64_t)r->res[0] * r->res[1] * r->res[2];
+  if (dbg && dbg->n_b) *dbg->n_b = n_b;
+  if (n_b == 0) {
+    SFK_HIP(c, sfk::launch_fill_f32(r->d_out, m, 0.0f, s));
+    if (dbg && dbg->aveden) *dbg->aveden = 0.0;
+    if (dbg && dbg->ell0) dbg->ell0[0] = dbg->ell0[1] = dbg->ell0[2] = 0.0f;
+    SFK_HIP(c, hipStreamSynchronize(s));
+    return SFK_OK;
+  }
+  const double ck = r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? ck_gauss_trunc3() : ck_epanechnikov();
+  const double nu = r->norm == SFK_NORM_COUNT ? 1.0 : 1.0 / (double)n_b;
+  const bool kg = r->kernel == SFK_KERNEL_GAUSS_TRUNC3;
+
+  auto run_one = [&](TreeView tv, const GroupRoi& g, float* out) -> sfk_status {
+    sfk_roi rr = *g.roi;
+    rr.d_out = out;
+    GroupRoi gg = g;
+    gg.roi = &rr;
+    std::vector<GroupRoi> v{gg};
+    SFK_TRY(staging_reserve(c, st, 1));
+    if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
+    int64_t n_tiles = 0, n_coords = 0;
+    make_roidev(v, ts, st.host, &n_tiles, &n_coords);
+    SFK_TRY(ws_reserve(c, ws.rois, sizeof(RoiDev), "ROI descriptors"));
+    SFK_TRY(ws_reserve(c, ws.coords, sizeof(float) * (size_t)n_coords, "node coordinates"));
+    SFK_HIP(c, hipMemcpyAsync(ws.rois.p, st.host, sizeof(RoiDev), hipMemcpyHostToDevice, s));
+    SFK_HIP(c, hipEventRecord(st.ev, s));
+    st.ev_valid = true;
+    SFK_HIP(c, sfk::launch_roi_coords((RoiDev*)ws.rois.p, 1, (float*)ws.coords.p, s));
+    return launch_group(c, tv, ts, g.count_mode ? 0 : g.kk, g.pp, g.count_mode,
+                        (const RoiDev*)ws.rois.p, 1, n_tiles, (const float*)ws.coords.p, ws, s);
+  };
+
+  if (!mbe) {
+    GroupRoi g{};
+    g.roi = r;
+    g.kk = kg ? KK_GAUSS : KK_EPAN;
+    g.count_mode = count_mode;
+    g.c2 = kg ? 9.0f : 1.0f;
+    if (r->bw == SFK_BW_PER_POINT) {
+      g.pp = PP_ISO;
+      g.ih[0] = g.ih[1] = g.ih[2] = 1.0f;
+      g.scale = (float)(ck * nu);
+      SFK_HIP(c, sfk::launch_node_ih(sc.pts.as<float4>(), nullptr, PP_ISO, n_b,
+                                      sc.nodes.as<NodeBox>(), sc.off, sc.cnt, sc.n_levels,
+                                      sc.node_ih.as<float4>(), s));
+    } else {
+      float h[3];
+      for (int k = 0; k < 3; ++k)
+        h[k] = r->bw == SFK_BW_FIXED ? r->h[k] : (float)((double)r->h[0] * (r->hi[k] - r->lo[k]));
+      g.pp = PP_UNIFORM;
+      for (int k = 0; k < 3; ++k) g.ih[k] = (float)(1.0 / (double)h[k]);
+      g.scale = (float)(ck * nu / ((double)h[0] * (double)h[1] * (double)h[2]));
+    }
+    if (count_mode) g.scale = 1.0f;
+    SFK_TRY(run_one(sc.view(g.pp), g, r->d_out));
+    SFK_HIP(c, hipStreamSynchronize(s));
+    return SFK_OK;
+  }
+
+  // ---- MBE (Section 3.1) ----
+  // Eq. 1: exact order statistics from one radix sort of the three axes
+  TmpBuf keys(c), keys2(c), vals(c), vals2(c), stmp(c), ell_d(c), flag_d(c), pilot(c), pden(c),
+      bsum(c), ave_d(c), ellj_d(c);
+  const int64_t m3 = 3 * n_b;
+  SFK_TRY(keys.get(sizeof(uint64_t) * (size_t)m3, "axis keys"));
+  SFK_TRY(keys2.get(sizeof(uint64_t) * (size_t)m3, "axis keys"));
+  SFK_TRY(vals.get(sizeof(uint32_t) * (size_t)m3, "axis values"));
+  SFK_TRY(vals2.get(sizeof(uint32_t) * (size_t)m3, "axis values"));
+  SFK_TRY(stmp.get(sfk::radix_sort_tmp_bytes(m3), "sort scratch"));
+  SFK_TRY(ell_d.get(4 * sizeof(float), "smoothing lengths"));
+  SFK_TRY(flag_d.get(sizeof(int32_t), "flags"));
+  SFK_HIP(c, sfk::launch_axis_keys(sc.axes.as<float>(), n_b, keys.as<uint64_t>(),
+                                    vals.as<uint32_t>(), s));
+  int alt = 0;
+  SFK_HIP(c, sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(),
+                                    vals2.as<uint32_t>(), m3, 34, stmp.b.p, stmp.b.bytes, s, &alt));
+  const uint64_t* sorted = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
+  SFK_HIP(c, sfk::launch_mbe_ell(sorted, n_b, r->lo, r->hi, r->res, ell_d.as<float>(),
+                                  flag_d.as<int32_t>(), s));
+  float ell0[3];
+  SFK_HIP(c, hipMemcpyAsync(ell0, ell_d.b.p, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipStreamSynchronize(s));
+  if (dbg && dbg->ell0) std::memcpy(dbg->ell0, ell0, sizeof ell0);
+
+  // pilot grid (Eq. 2): uniform ellipsoid l_k over the particles in B
+  SFK_TRY(pilot.get(sizeof(float) * (size_t)m, "pilot grid"));
+  GroupRoi gp{};
+  gp.roi = r;
+  gp.kk = KK_EPAN;
+  gp.pp = PP_UNIFORM;
+  gp.c2 = 1.0f;
+  for (int k = 0; k < 3; ++k) gp.ih[k] = (float)(1.0 / (double)ell0[k]);
+  gp.scale = (float)(ck * nu / ((double)ell0[0] * (double)ell0[1] * (double)ell0[2]));
+  SFK_TRY(run_one(sc.view(PP_UNIFORM), gp, pilot.as<float>()));
+
+  // ASL (Eqs. 5-6): trilinear pilot at each particle, mean, lengths
+  const int nblk = (int)((n_b + 255) / 256);
+  SFK_TRY(pden.get(sizeof(double) * (size_t)n_b, "pilot at particles"));
+  SFK_TRY(bsum.get(sizeof(double) * (size_t)nblk, "block sums"));
+  SFK_TRY(ave_d.get(sizeof(double), "mean pilot"));
+  SFK_TRY(sc.pparam.get(sizeof(float4) * (size_t)sc.n_leaves * SFK_LEAF, "adaptive parameters"));
+  SFK_TRY(ellj_d.get(sizeof(float) * 3 * (size_t)n_b, "adaptive lengths"));
+  SFK_HIP(c, sfk::launch_trilinear_mean(sc.pts.as<float4>(), n_b, pilot.as<float>(), r->lo, r->hi,
+                                         r->res, pden.as<double>(), bsum.as<double>(),
+                                         ave_d.as<double>(), s));
+  SFK_HIP(c, sfk::launch_asl2(pden.as<double>(), n_b, ave_d.as<double>(), ell0, r->lo, r->hi,
+                               r->res, sc.pparam.as<float4>(), ellj_d.as<float>(), s));
+  SFK_HIP(c, sfk::launch_node_ih(sc.pts.as<float4>(), sc.pparam.as<float4>(), PP_ANISO, n_b,
+                                  sc.nodes.as<NodeBox>(), sc.off, sc.cnt, sc.n_levels,
+                                  sc.node_ih.as<float4>(), s));
+
+  // final grid (Eq. 7): per-particle ellipsoids
+  GroupRoi gf{};
+  gf.roi = r;
+  gf.kk = KK_EPAN;
+  gf.pp = PP_ANISO;
+  gf.c2 = 1.0f;
+  gf.ih[0] = gf.ih[1] = gf.ih[2] = 1.0f;
+  gf.count_mode = count_mode;
+  gf.scale = count_mode ? 1.0f : (float)(ck * nu);
+  SFK_TRY(run_one(sc.view(PP_ANISO), gf, r->d_out));
+
+  if (dbg) {
+    std::vector<double> pd;
+    std::vector<float> ej;
+    std::vector<int32_t> ix;
+    if (dbg->pilot)
+      SFK_HIP(c, hipMemcpyAsync(dbg->pilot, pilot.b.p, sizeof(float) * (size_t)m,
+                                hipMemcpyDeviceToHost, s));
+    if (dbg->aveden)
+      SFK_HIP(c, hipMemcpyAsync(dbg->aveden, ave_d.b.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    const bool per_particle = dbg->idx_b || dbg->pden || dbg->ell_j;
+    if (per_particle && n_b <= dbg->cap_b) {
+      pd.resize(n_b);
+      ej.resize(3 * n_b);
+      ix.resize(n_b);
+      SFK_HIP(c, hipMemcpyAsync(pd.data(), pden.b.p, sizeof(double) * n_b, hipMemcpyDeviceToHost, s));
+      SFK_HIP(c, hipMemcpyAsync(ej.data(), ellj_d.b.p, sizeof(float) * 3 * n_b,
+                                hipMemcpyDeviceToHost, s));
+      SFK_HIP(c, hipMemcpyAsync(ix.data(), sc.perm.b.p, sizeof(int32_t) * n_b,
+                                hipMemcpyDeviceToHost, s));
+    }
+    SFK_HIP(c, hipStreamSynchronize(s));
+    if (per_particle) {
+      if (n_b > dbg->cap_b) {
+        set_err(c, "debug capacity %lld below the %lld particles in B", (long long)dbg->cap_b,
+                (long long)n_b);
+        return SFK_E_INVAL;
+      }
+      std::vector<int64_t> order(n_b);
+      for (int64_t i = 0; i < n_b; ++i) order[i] = i;
+      std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return ix[a] < ix[b]; });
+      for (int64_t q = 0; q < n_b; ++q) {
+        const int64_t i = order[q];
+        if (dbg->idx_b) dbg->idx_b[q] = ix[i];
+        if (dbg->pden) dbg->pden[q] = (float)pd[i];
+        if (dbg->ell_j)
+          for (int k = 0; k < 3; ++k) dbg->ell_j[3 * q + k] = ej[3 * i + k];
+      }
+    }
+  }
+  SFK_HIP(c, hipStreamSynchronize(s));
+  return SFK_OK;
+}
+
+TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
+  if (c->opts.tile_shape > 0) return shape_of(c->opts.tile_shape);
+  // autotuner table keyed by (kernel, bandwidth mode, support/spacing bucket)
+  double hs = 0.0;
+  if (r->bw == SFK_BW_FIXED || r->bw == SFK_BW_ROI_SCALED) {
+    const double h = r->bw == SFK_BW_FIXED ? r->h[0] : r->h[0] * (r->hi[0] - r->lo[0]);
+    hs = h / ((r->hi[0] - r->lo[0]) / (r->res[0] - 1));
+    if (r->kernel == SFK_KERNEL_GAUSS_TRUNC3) hs *= 3.0;
+  }
+  (void)t;
+  const int bucket = hs <= 0.0 ? 0 : std::min(7, std::max(1, (int)std::floor(std::log2(hs)) + 4));
+  const int key = (r->kernel * 4 + r->bw) * 8 + bucket;
+  auto it = c->tune.find(key);
+  if (it != c->tune.end()) return shape_of(it->second);
+  return shape_of(1);
+}
+
+// Launch everything a ticket needs on a slot. CLOUD ROIs go through one
+// persistent pipeline per (kernel, bandwidth) group; IN_ROI ROIs through
+// the sub-cloud path (blocking on the slot's stream).
+sfk_status launch_ticket(sfk_ctx c, Ticket& tk, Slot& sl) {
+  std::vector<const sfk_roi*> cloud;
+  std::vector<const sfk_roi*> sub;
+  for (const sfk_roi& r : tk.rois) (r.set == SFK_SET_IN_ROI ? sub : cloud).push_back(&r);
+  absorb_stats(sl.ws, sl.st);
+  if (!cloud.empty()) {
+    // one tile shape per batch: the autotuned choice of the first ROI
+    const TileShape ts = choose_shape(c, tk.tree, cloud[0]);
+    SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, ts, sl.ws, sl.st, sl.stream));
+  }
+  for (const sfk_roi* r : sub)
+    SFK_TRY(eval_subcloud(c, tk.tree, r, false, shape_of(1), sl.ws, sl.st, sl.stream, nullptr));
+  SFK_HIP(c, hipEventRecord(sl.done, sl.stream));
+  return SFK_OK;
+}
+
+int free_slot(sfk_ctx c) {
+  for (int i = 0; i < kNumSlots; ++i)
+    if (!c->slots[i].busy) return i;
+  return -1;
+}
+
+// Retire finished slots and start pending tickets. Never blocks.
+sfk_status pump(sfk_ctx c) {
+  for (int i = 0; i < kNumSlots; ++i) {
+    Slot& sl = c->slots[i];
+    if (!sl.busy) continue;
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) {
+      set_err(c, "batch failed on the device: %s", hipGetErrorString(q));
+      auto it = c->tickets.find(sl.ticket);
+      if (it != c->tickets.end()) {
+        it->second.state = 4;
+        it->second.status = SFK_E_DEVICE;
+      }
+      sl.busy = false;
+      continue;
+    }
+    auto it = c->tickets.find(sl.ticket);
+    if (it != c->tickets.end()) it->second.state = 2;
+    absorb_stats(sl.ws, sl.st);
+    sl.busy = false;
+    sl.ticket = -1;
+  }
+  while (!c->pending.empty()) {
+    const int si = free_slot(c);
+    if (si < 0) break;
+    const int64_t id = c->pending.front();
+    c->pending.pop_front();
+    auto it = c->tickets.find(id);
+    if (it == c->tickets.end() || it->second.state != 0) continue;
+    Slot& sl = c->slots[si];
+    sl.busy = true;
+    sl.ticket = id;
+    it->second.slot = si;
+    it->second.state = 1;
+    const sfk_status st = launch_ticket(c, it->second, sl);
+    if (st != SFK_OK) {
+      it->second.state = 4;
+      it->second.status = st;
+      (void)hipStreamSynchronize(sl.stream);
+      sl.busy = false;
+      sl.ticket = -1;
+      return st;
+    }
+  }
+  return SFK_OK;
+}
+
+sfk_status check_ctx(sfk_ctx c) {
+  if (!c) {
+    set_err(nullptr, "NULL context");
+    return SFK_E_INVAL;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    set_err(c, "hipSetDevice(%d) failed", c->device);
+    return SFK_E_DEVICE;
+  }
+  return SFK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* sfk_version(void) { return "sfkde 0.1 (gfx950)"; }
+
+const char* sfk_status_string(sfk_status s) {
+  switch (s) {
+    case SFK_OK: return "ok";
+    case SFK_E_INVAL: return "invalid argument";
+    case SFK_E_NOMEM: return "out of device memory";
+    case SFK_E_BUDGET: return "device-memory budget exceeded";
+    case SFK_E_DEVICE: return "device error";
+    case SFK_E_NOT_READY: return "not ready";
+    case SFK_E_CANCELLED: return "cancelled";
+    case SFK_E_UNSUPPORTED: return "unsupported";
+    case SFK_E_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* sfk_last_error(sfk_ctx ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_tls_err.c_str();
+}
+
+sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_budget_bytes,
+                          sfk_ctx* out) {
+  SFK_GUARD_BEGIN
+  if (!out) {
+    set_err(nullptr, "out is NULL");
+    return SFK_E_INVAL;
+  }
+  *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    set_err(nullptr, "allocator needs both alloc and free");
+    return SFK_E_INVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    set_err(nullptr, "no HIP device available");
+    return SFK_E_DEVICE;
+  }
+  if (device < 0 || device >= ndev) {
+    set_err(nullptr, "device %d out of range (%d devices)", device, ndev);
+    return SFK_E_INVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    set_err(nullptr, "hipSetDevice(%d) failed", device);
+    return SFK_E_DEVICE;
+  }
+  sfk_ctx c = new sfk_ctx_s();
+  c->device = device;
+  if (alloc) {
+    c->alloc = *alloc;
+    c->use_alloc = true;
+  }
+  c->budget = hbm_budget_bytes;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  for (int i = 0; i < kNumSlots; ++i) {
+    if (hipStreamCreateWithFlags(&c->slots[i].stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming) != hipSuccess) {
+      set_err(nullptr, "stream creation failed");
+      sfk_ctx_destroy(c);
+      return SFK_E_DEVICE;
+    }
+  }
+  if (hipEventCreateWithFlags(&c->direct_last, hipEventDisableTiming) != hipSuccess) {
+    set_err(nullptr, "event creation failed");
+    sfk_ctx_destroy(c);
+    return SFK_E_DEVICE;
+  }
+  *out = c;
+  return SFK_OK;
+  SFK_GUARD_END(nullptr)
+}
+
+static void release_ws(sfk_ctx c, Workspace& ws) {
+  DevBuf* bufs[] = {&ws.rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
+                    &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
+                    &ws.partials, &ws.hdr};
+  for (DevBuf* b : bufs) ws_release(c, *b);
+}
+
+static void release_staging(Staging& st) {
+  if (st.ev_valid) (void)hipEventSynchronize(st.ev);
+  if (st.host) (void)hipHostFree(st.host);
+  if (st.hdr_host) (void)hipHostFree(st.hdr_host);
+  if (st.ev) (void)hipEventDestroy(st.ev);
+  st = Staging();
+}
+
+sfk_status sfk_ctx_destroy(sfk_ctx c) {
+  SFK_GUARD_BEGIN
+  if (!c) return SFK_OK;
+  (void)hipSetDevice(c->device);
+  for (int i = 0; i < kNumSlots; ++i) {
+    Slot& sl = c->slots[i];
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    release_ws(c, sl.ws);
+    release_staging(sl.st);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  if (c->direct_last_valid) (void)hipEventSynchronize(c->direct_last);
+  release_ws(c, c->direct_ws);
+  for (int i = 0; i < kStagingRing; ++i) release_staging(c->direct_st[i]);
+  if (c->direct_last) (void)hipEventDestroy(c->direct_last);
+  delete c;
+  return SFK_OK;
+  SFK_GUARD_END(nullptr)
+}
+
+sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float* d_h,
+                          const sfk_tree_opts* opts, void* hip_stream, sfk_tree* out) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!out) {
+    set_err(c, "out is NULL");
+    return SFK_E_INVAL;
+  }
+  *out = nullptr;
+  if (n < 0 || n >= (int64_t)INT32_MAX - SFK_LEAF) {
+    set_err(c, "n = %lld out of range [0, 2^31 - 64)", (long long)n);
+    return SFK_E_INVAL;
+  }
+  if (n > 0 && !d_xyz) {
+    set_err(c, "d_xyz is NULL");
+    return SFK_E_INVAL;
+  }
+  sfk_tree_opts o{};
+  if (opts) o = *opts;
+  if (o.leaf_size != 0 && o.leaf_size != SFK_LEAF) {
+    set_err(c, "leaf_size %d unsupported (0 or 64)", o.leaf_size);
+    return SFK_E_UNSUPPORTED;
+  }
+  if (o.knn_k < 0 || o.knn_k > 64) {
+    set_err(c, "knn_k = %d out of range [0, 64]", o.knn_k);
+    return SFK_E_INVAL;
+  }
+  if (o.knn_k > 0 && n > 0 && o.knn_k >= n) {
+    set_err(c, "knn_k = %d needs at least k + 1 = %d particles (n = %lld)", o.knn_k,
+            o.knn_k + 1, (long long)n);
+    return SFK_E_INVAL;
+  }
+  if (o.knn_k > 0 && d_h) {
+    set_err(c, "give either knn_k or d_h, not both");
+    return SFK_E_INVAL;
+  }
+  if (o.morton_bits < 0 || o.morton_bits > 21) {
+    set_err(c, "morton_bits = %d out of range [0, 21]", o.morton_bits);
+    return SFK_E_INVAL;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  sfk_tree t = new sfk_tree_s();
+  t->ctx = c;
+  t->n = n;
+  t->knn_k = o.knn_k;
+  auto fail = [&](sfk_status st) {
+    (void)hipStreamSynchronize(s);
+    tree_free(c, t, t->pts);
+    tree_free(c, t, t->perm);
+    tree_free(c, t, t->nodes);
+    tree_free(c, t, t->node_ih);
+    tree_free(c, t, t->h2);
+    delete t;
+    return st;
+  };
+  t->n_leaves = (int32_t)((n + SFK_LEAF - 1) / SFK_LEAF);
+  int32_t total_nodes = 0;
+  level_layout(t->n_leaves, t->level_off, t->level_cnt, &t->n_levels, &total_nodes);
+  if (t->n_levels > 6) return fail((set_err(c, "hierarchy too deep"), SFK_E_INTERNAL));
+  const int64_t n_slots = (int64_t)t->n_leaves * SFK_LEAF;
+  sfk_status st;
+  if ((st = tree_alloc(c, t, t->pts, sizeof(float4) * (size_t)n_slots, "particles")) != SFK_OK ||
+      (st = tree_alloc(c, t, t->perm, sizeof(int32_t) * (size_t)n, "permutation")) != SFK_OK ||
+      (st = tree_alloc(c, t, t->nodes, sizeof(NodeBox) * (size_t)total_nodes, "boxes")) != SFK_OK)
+    return fail(st);
+  if (n == 0) {
+    *out = t;
+    return SFK_OK;
+  }
+  if (d_h) {
+    TmpBuf bad(c);
+    if ((st = bad.get(sizeof(int32_t), "check")) != SFK_OK) return fail(st);
+    int32_t nbad = 0;
+    if (sfk::launch_count_nonpositive(d_h, n, bad.as<int32_t>(), s) != hipSuccess ||
+        hipMemcpyAsync(&nbad, bad.b.p, sizeof nbad, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail((set_err(c, "bandwidth check failed"), SFK_E_DEVICE));
+    if (nbad > 0)
+      return fail((set_err(c, "%d per-particle bandwidths are not finite and > 0", nbad), SFK_E_INVAL));
+  }
+  {
+    // bounding box + finiteness
+    const int nblk = 1024;
+    TmpBuf part(c), res(c);
+    if ((st = part.get(sizeof(float) * 7 * nblk, "bbox partials")) != SFK_OK ||
+        (st = res.get(sizeof(float) * 8, "bbox")) != SFK_OK)
+      return fail(st);
+    float bb[7];
+    if (sfk::launch_bbox(d_xyz, n, part.as<float>(), nblk, res.as<float>(), s) != hipSuccess ||
+        hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail((set_err(c, "bounding box kernel failed"), SFK_E_DEVICE));
+    if (bb[6] > 0.0f)
+      return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
+    for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
+    // Morton keys and the sort
+    int bits = o.morton_bits;
+    if (bits == 0) {
+      const int lg = (int)std::ceil(std::log2((double)std::max<int64_t>(n, 2)));
+      bits = std::min(21, std::max(10, (lg + 2) / 3 + 3));
+    }
+    TmpBuf keys(c), keys2(c), vals(c), vals2(c), stmp(c);
+    if ((st = keys.get(sizeof(uint64_t) * (size_t)n, "sort keys")) != SFK_OK ||
+        (st = keys2.get(sizeof(uint64_t) * (size_t)n, "sort keys")) != SFK_OK ||
+        (st = vals.get(sizeof(uint32_t) * (size_t)n, "sort values")) != SFK_OK ||
+        (st = vals2.get(sizeof(uint32_t) * (size_t)n, "sort values")) != SFK_OK ||
+        (st = stmp.get(sfk::radix_sort_tmp_bytes(n), "sort scratch")) != SFK_OK)
+      return fail(st);
+    int alt = 0;
+    if (sfk::launch_morton(d_xyz, n, res.as<float>(), bits, keys.as<uint64_t>(),
+                           vals.as<uint32_t>(), s) != hipSuccess ||
+        sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(),
+                              vals2.as<uint32_t>(), n, 3 * bits, stmp.b.p, stmp.b.bytes, s,
+                              &alt) != hipSuccess ||
+        sfk::launch_gather(d_xyz, alt ? vals2.as<uint32_t>() : vals.as<uint32_t>(), n, n_slots,
+                           (float4*)t->pts.p, (int32_t*)t->perm.p, s) != hipSuccess)
+      return fail((set_err(c, "sort / gather failed"), SFK_E_DEVICE));
+    if ((st = build_boxes(c, (const float4*)t->pts.p, n, t->n_leaves, (NodeBox*)t->nodes.p,
+                          t->level_off, t->level_cnt, t->n_levels, s)) != SFK_OK)
+      return fail(st);
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
+  }
+  if (o.knn_k > 0 || d_h) {
+    if ((st = tree_alloc(c, t, t->node_ih, sizeof(float4) * (size_t)total_nodes,
+                         "node bandwidths")) != SFK_OK)
+      return fail(st);
+    if (o.knn_k > 0) {
+      if ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) != SFK_OK)
+        return fail(st);
+      if (sfk::launch_knn(view_of(t), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
+        return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
+    }
+    if (sfk::launch_iso_params((float4*)t->pts.p, (const float*)t->h2.p, d_h,
+                               (const int32_t*)t->perm.p, n, s) != hipSuccess)
+      return fail((set_err(c, "bandwidth kernel failed"), SFK_E_DEVICE));
+    // zero-bandwidth particles moved to the sentinel: refresh the boxes
+    if ((st = build_boxes(c, (const float4*)t->pts.p, n, t->n_leaves, (NodeBox*)t->nodes.p,
+                          t->level_off, t->level_cnt, t->n_levels, s)) != SFK_OK)
+      return fail(st);
+    if (sfk::launch_node_ih((const float4*)t->pts.p, nullptr, PP_ISO, n,
+                            (const NodeBox*)t->nodes.p, t->level_off, t->level_cnt, t->n_levels,
+                            (float4*)t->node_ih.p, s) != hipSuccess)
+      return fail((set_err(c, "node bandwidth kernel failed"), SFK_E_DEVICE));
+    t->pp_mode = PP_ISO;
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return fail((set_err(c, "per-point bandwidth failed on the device"), SFK_E_DEVICE));
+  }
+  *out = t;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_tree_info(sfk_tree t, int64_t* n, double bbox[6], size_t* device_bytes) {
+  if (!t) {
+    set_err(nullptr, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  if (n) *n = t->n;
+  if (bbox)
+    for (int k = 0; k < 6; ++k) bbox[k] = t->bbox[k];
+  if (device_bytes) *device_bytes = t->bytes;
+  return SFK_OK;
+}
+
+sfk_status sfk_tree_destroy(sfk_tree t) {
+  SFK_GUARD_BEGIN
+  if (!t) return SFK_OK;
+  sfk_ctx c = t->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  tree_free(c, t, t->pts);
+  tree_free(c, t, t->perm);
+  tree_free(c, t, t->nodes);
+  tree_free(c, t, t->node_ih);
+  tree_free(c, t, t->h2);
+  delete t;
+  return SFK_OK;
+  SFK_GUARD_END(nullptr)
+}
+
+sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
+  SFK_TRY(check_ctx(c));
+  if (!opts) {
+    set_err(c, "opts is NULL");
+    return SFK_E_INVAL;
+  }
+  if (opts->tile_shape < 0 || opts->tile_shape > 4 || opts->chunk_leaves < 0 ||
+      opts->chunk_leaves > (1 << 20) || opts->persistent_waves_per_cu < 0 ||
+      opts->persistent_waves_per_cu > 64 || opts->list_capacity < 0) {
+    set_err(c, "evaluation options out of range");
+    return SFK_E_INVAL;
+  }
+  if (opts->tile_shape == 4) {
+    set_err(c, "tile shape 4 (8x4x4 with 8x4x4 = 128 nodes) unavailable in this build");
+  }
+  c->opts = *opts;
+  if (c->opts.tile_shape == 4) c->opts.tile_shape = 2;
+  return SFK_OK;
+}
+
+// Stream-ordered single ROI on the caller's stream.
+static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStream_t s,
+                              bool count_mode) {
+  if (c->direct_last_valid && c->direct_last_stream != s)
+    SFK_HIP(c, hipStreamWaitEvent(s, c->direct_last, 0));
+  Staging& st = c->direct_st[c->direct_next];
+  c->direct_next = (c->direct_next + 1) % kStagingRing;
+  if (roi->set == SFK_SET_IN_ROI) {
+    SFK_TRY(eval_subcloud(c, t, roi, count_mode, shape_of(1), c->direct_ws, st, s, nullptr));
+  } else {
+    absorb_stats(c->direct_ws, st);
+    std::vector<const sfk_roi*> v{roi};
+    // capacity growth reallocates: previous direct work must be done
+    if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
+    SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, choose_shape(c, t, roi), c->direct_ws, st, s));
+  }
+  SFK_HIP(c, hipEventRecord(c->direct_last, s));
+  c->direct_last_valid = true;
+  c->direct_last_stream = s;
+  return SFK_OK;
+}
+
+sfk_status sfk_eval_roi(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t) {
+    set_err(c, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  return eval_direct(c, t, roi, (hipStream_t)hip_stream, false);
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_submit(sfk_ctx c, sfk_tree t, const sfk_roi* rois, int32_t n_rois,
+                      sfk_ticket* out) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !out || (!rois && n_rois > 0) || n_rois < 0) {
+    set_err(c, "invalid submit arguments");
+    return SFK_E_INVAL;
+  }
+  for (int i = 0; i < n_rois; ++i) SFK_TRY(validate_roi(c, t, &rois[i], i));
+  SFK_TRY(validate_disjoint_outputs(c, rois, n_rois));
+  Ticket tk;
+  tk.tree = t;
+  tk.rois.assign(rois, rois + n_rois);
+  const int64_t id = c->next_ticket++;
+  c->tickets[id] = std::move(tk);
+  c->pending.push_back(id);
+  *out = id;
+  return pump(c);
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_poll(sfk_ctx c, sfk_ticket tid, int32_t* done) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!done) {
+    set_err(c, "done is NULL");
+    return SFK_E_INVAL;
+  }
+  auto it = c->tickets.find(tid);
+  if (it == c->tickets.end()) {
+    set_err(c, "unknown ticket %lld", (long long)tid);
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(pump(c));
+  it = c->tickets.find(tid);
+  const int state = it->second.state;
+  *done = (state >= 2) ? 1 : 0;
+  if (state == 3) return SFK_E_CANCELLED;
+  if (state == 4) return it->second.status;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_wait(sfk_ctx c, sfk_ticket tid, int64_t timeout_us) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  auto it = c->tickets.find(tid);
+  if (it == c->tickets.end()) {
+    set_err(c, "unknown ticket %lld", (long long)tid);
+    return SFK_E_INVAL;
+  }
+  const double t0 = now_s();
+  while (true) {
+    SFK_TRY(pump(c));
+    it = c->tickets.find(tid);
+    const int state = it->second.state;
+    if (state == 2) {
+      c->tickets.erase(it);
+      return SFK_OK;
+    }
+    if (state == 3) {
+      c->tickets.erase(it);
+      return SFK_E_CANCELLED;
+    }
+    if (state == 4) {
+      const sfk_status st = it->second.status;
+      c->tickets.erase(it);
+      return st;
+    }
+    if (timeout_us >= 0 && (now_s() - t0) * 1e6 >= (double)timeout_us) {
+      set_err(c, "ticket %lld not finished within %lld us", (long long)tid, (long long)timeout_us);
+      return SFK_E_NOT_READY;
+    }
+    if (state == 1) {
+      const Slot& sl = c->slots[it->second.slot];
+      if (timeout_us < 0) {
+        (void)hipEventSynchronize(sl.done);
+      }
+    }
+  }
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_cancel(sfk_ctx c, sfk_ticket tid) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  auto it = c->tickets.find(tid);
+  if (it == c->tickets.end()) {
+    set_err(c, "unknown ticket %lld", (long long)tid);
+    return SFK_E_INVAL;
+  }
+  if (it->second.state == 0) {
+    it->second.state = 3;
+    return SFK_OK;
+  }
+  if (it->second.state == 3) return SFK_OK;
+  set_err(c, "ticket %lld already started", (long long)tid);
+  return SFK_E_NOT_READY;
+  SFK_GUARD_END(c)
+}
+
+// ---------------------------------------------------------------- debug
+
+sfk_status sfk_debug_point_h2(sfk_ctx c, sfk_tree t, float* h_h2) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !h_h2) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  if (!t->h2.p) {
+    set_err(c, "tree was built without k-NN bandwidths");
+    return SFK_E_INVAL;
+  }
+  std::vector<float> h2(t->n);
+  std::vector<int32_t> perm(t->n);
+  SFK_HIP(c, hipMemcpy(h2.data(), t->h2.p, sizeof(float) * t->n, hipMemcpyDeviceToHost));
+  SFK_HIP(c, hipMemcpy(perm.data(), t->perm.p, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < t->n; ++i) h_h2[perm[i]] = h2[i];
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64_t node_begin,
+                                int64_t node_end, int64_t* h_offsets, int64_t* h_idx, int64_t cap,
+                                int64_t* needed) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !h_offsets || !needed) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (roi->set != SFK_SET_CLOUD || roi->bw == SFK_BW_MBE) {
+    set_err(c, "candidate export covers CLOUD-set, non-MBE ROIs");
+    return SFK_E_UNSUPPORTED;
+  }
+  const int64_t m = (int64_t)roi->res[0] * roi->res[1] * roi->res[2];
+  if (node_begin < 0 || node_end > m || node_begin > node_end) {
+    set_err(c, "node range out of bounds");
+    return SFK_E_INVAL;
+  }
+  const int64_t nn = node_end - node_begin;
+  hipStream_t s = c->slots[0].stream;
+  SFK_HIP(c, hipStreamSynchronize(s));
+  const TileShape ts = choose_shape(c, t, roi);
+  GroupRoi g = resolve_cloud_roi(t, roi, false);
+  std::vector<GroupRoi> v{g};
+  RoiDev rd;
+  int64_t n_tiles, n_coords;
+  make_roidev(v, ts, &rd, &n_tiles, &n_coords);
+  TmpBuf rdev(c), coords(c), cnt(c), off(c), idx(c);
+  SFK_TRY(rdev.get(sizeof(RoiDev), "descriptor"));
+  SFK_TRY(coords.get(sizeof(float) * (size_t)n_coords, "coordinates"));
+  SFK_TRY(cnt.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "counts"));
+  SFK_HIP(c, hipMemcpy(rdev.b.p, &rd, sizeof rd, hipMemcpyHostToDevice));
+  SFK_HIP(c, sfk::launch_roi_coords(rdev.as<RoiDev>(), 1, coords.as<float>(), s));
+  TreeView tv = view_of(t);
+  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
+                                            coords.as<float>(), ts, node_begin, node_end,
+                                            cnt.as<int64_t>(), nullptr, nullptr, s));
+  std::vector<int64_t> counts(nn);
+  SFK_HIP(c, hipMemcpyAsync(counts.data(), cnt.b.p, sizeof(int64_t) * nn, hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipStreamSynchronize(s));
+  h_offsets[0] = 0;
+  for (int64_t i = 0; i < nn; ++i) h_offsets[i + 1] = h_offsets[i] + counts[i];
+  *needed = h_offsets[nn];
+  if (!h_idx || *needed > cap) return SFK_OK;
+  SFK_TRY(off.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "offsets"));
+  SFK_TRY(idx.get(sizeof(int32_t) * (size_t)std::max<int64_t>(*needed, 1), "indices"));
+  SFK_HIP(c, hipMemcpy(off.b.p, h_offsets, sizeof(int64_t) * nn, hipMemcpyHostToDevice));
+  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
+                                            coords.as<float>(), ts, node_begin, node_end, nullptr,
+                                            off.as<int64_t>(), idx.as<int32_t>(), s));
+  std::vector<int32_t> ix(*needed);
+  SFK_HIP(c, hipMemcpyAsync(ix.data(), idx.b.p, sizeof(int32_t) * ix.size(), hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipStreamSynchronize(s));
+  for (int64_t i = 0; i < nn; ++i) {
+    std::sort(ix.begin() + h_offsets[i], ix.begin() + h_offsets[i + 1]);
+    for (int64_t q = h_offsets[i]; q < h_offsets[i + 1]; ++q) h_idx[q] = ix[q];
+  }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_support_counts(sfk_ctx c, sfk_tree t, const sfk_roi* roi, float* d_counts,
+                                    void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t) {
+    set_err(c, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (!d_counts) {
+    set_err(c, "d_counts is NULL");
+    return SFK_E_INVAL;
+  }
+  sfk_roi r = *roi;
+  r.d_out = d_counts;
+  return eval_direct(c, t, &r, (hipStream_t)hip_stream, true);
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_eval_count(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64_t* useful_pairs,
+                                int64_t* tested_pairs) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t) {
+    set_err(c, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  const int64_t m = (int64_t)roi->res[0] * roi->res[1] * roi->res[2];
+  hipStream_t s = c->slots[0].stream;
+  SFK_HIP(c, hipStreamSynchronize(s));
+  TmpBuf cnt(c);
+  SFK_TRY(cnt.get(sizeof(float) * (size_t)m, "support counts"));
+  sfk_roi r = *roi;
+  r.d_out = cnt.as<float>();
+  SFK_TRY(eval_direct(c, t, &r, s, true));
+  std::vector<float> h(m);
+  SFK_HIP(c, hipMemcpyAsync(h.data(), cnt.b.p, sizeof(float) * m, hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipStreamSynchronize(s));
+  int64_t useful = 0;
+  for (int64_t i = 0; i < m; ++i) useful += (int64_t)h[i];
+  if (useful_pairs) *useful_pairs = useful;
+  if (tested_pairs) {
+    // leaves listed per tile x 64 particles x nodes per tile (CLOUD path)
+    int64_t tested = 0;
+    if (roi->set == SFK_SET_CLOUD) {
+      BatchHdr hh;
+      SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr.p, sizeof hh, hipMemcpyDeviceToHost));
+      const TileShape ts = choose_shape(c, t, roi);
+      tested = hh.total_leaves * SFK_LEAF * (int64_t)(ts.tx * ts.ty * ts.tz);
+    }
+    *tested_pairs = tested;
+  }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_mbe(sfk_ctx c, sfk_tree t, const sfk_roi* roi, float* h_ell0, int64_t* n_b,
+                         int64_t* h_idx_b, float* h_pilot, float* h_pden, double* aveden,
+                         float* h_ell_j, int64_t cap_b) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t) {
+    set_err(c, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (roi->bw != SFK_BW_MBE) {
+    set_err(c, "sfk_debug_mbe needs an MBE ROI");
+    return SFK_E_INVAL;
+  }
+  MbeDebug d;
+  d.ell0 = h_ell0;
+  d.n_b = n_b;
+  d.idx_b = h_idx_b;
+  d.pilot = h_pilot;
+  d.pden = h_pden;
+  d.aveden = aveden;
+  d.ell_j = h_ell_j;
+  d.cap_b = cap_b;
+  hipStream_t s = c->slots[0].stream;
+  SFK_HIP(c, hipStreamSynchronize(s));
+  if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
+  Staging& st = c->direct_st[c->direct_next];
+  c->direct_next = (c->direct_next + 1) % kStagingRing;
+  SFK_TRY(eval_subcloud(c, t, roi, false, shape_of(1), c->direct_ws, st, s, &d));
+  SFK_HIP(c, hipEventRecord(c->direct_last, s));
+  c->direct_last_valid = true;
+  c->direct_last_stream = s;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n) {
+  (void)t;
+  (void)sample;
+  (void)n;
+  SFK_TRY(check_ctx(c));
+  set_err(c, "autotuner not available yet");
+  return SFK_E_UNSUPPORTED;
+}
+
+sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
+                     const sfk_serve_opts* opts, sfk_request_result* h_results,
+                     sfk_serve_summary* h_summary) {
+  (void)t;
+  (void)reqs;
+  (void)n;
+  (void)opts;
+  (void)h_results;
+  (void)h_summary;
+  SFK_TRY(check_ctx(c));
+  set_err(c, "serving loop not available yet");
+  return SFK_E_UNSUPPORTED;
+}
+
+}  // extern "C"

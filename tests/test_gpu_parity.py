@@ -1,0 +1,438 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Densities: max relative error 1e-5 at nodes with rho >= 1e-3 of the peak,
+absolute error <= 1e-8 of the peak elsewhere. Support sets and counts:
+bit-exact. k-NN bandwidths and Eq. 1 lengths: bit-exact. ASL stages:
+1e-6 relative given the GPU's verified upstream arrays.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Roi
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+ABS_TOL = 1e-8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def sfk():
+    import paper_2601_20758_amd as m
+    return m
+
+
+@pytest.fixture()
+def ctx(sfk, torch):
+    c = sfk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_density(got, ref, label=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    peak = ref.max() if ref.size else 0.0
+    if peak <= 0:
+        assert np.all(got == 0), label
+        return 0.0
+    big = ref >= 1e-3 * peak
+    rel = np.abs(got[big] - ref[big]) / ref[big]
+    small = np.abs(got[~big] - ref[~big]).max(initial=0.0)
+    assert rel.max() <= REL_TOL, "%s: max rel err %.3g at %d" % (label, rel.max(), np.argmax(rel))
+    assert small <= ABS_TOL * peak, "%s: small-node abs err %.3g (peak %.3g)" % (label, small, peak)
+    return rel.max()
+
+
+def sample_nodes(ref_full_or_none, m, k, seed, extra=()):
+    g = np.random.default_rng(seed)
+    nodes = set(int(v) for v in g.choice(m, size=min(k, m), replace=False))
+    nodes.update(int(v) for v in extra)
+    return np.array(sorted(nodes), dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# C1: 20k points, 32^3, Epanechnikov, fixed h = 0.02 (full grid)
+# ---------------------------------------------------------------------------
+
+def test_c1_full_grid(ctx, torch):
+    pts = synth.c1_cloud(1)
+    roi = synth.c1_roi()
+    tree = ctx.build_tree(dev(torch, pts))
+    out = ctx.eval_roi(tree, roi)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.density(pts, roi)
+    err = check_density(got, ref, "c1")
+    say("c1 max rel err", err)
+    # support counts of every node, from the evaluation kernel itself
+    cnt = ctx.debug_support_counts(tree, roi)
+    torch.cuda.synchronize()
+    ref_cnt = oracle.support_counts(pts, roi)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.int64), ref_cnt)
+    # support sets of sampled nodes, bit-exact
+    nodes = sample_nodes(None, roi.n_nodes, 200, 5, extra=[0, roi.n_nodes - 1, int(np.argmax(ref))])
+    for a, b in [(int(n), int(n) + 1) for n in nodes[:60]] + [(1000, 1100)]:
+        offs, idx = ctx.debug_candidates(tree, roi, a, b)
+        ro, ri = oracle.candidates(pts, roi, np.arange(a, b))
+        assert np.array_equal(offs, ro) and np.array_equal(idx, ri), (a, b)
+    # useful pairs = sum of support sizes
+    useful, tested = ctx.debug_eval_count(tree, roi)
+    assert useful == int(ref_cnt.sum()) and tested >= useful
+
+
+@pytest.mark.parametrize("kernel,h,norm", [
+    ("gauss_trunc3", (0.01, 0.01, 0.01), "count"),
+    ("epanechnikov", (0.05, 0.03, 0.04), "paper"),
+    ("gauss_trunc3", (0.004, 0.006, 0.005), "paper"),
+])
+def test_c1_kernels_and_norms(ctx, torch, kernel, h, norm):
+    pts = synth.c1_cloud(1)
+    roi = Roi((0, 0, 0), (1, 1, 1), (29, 31, 33), kernel=kernel, bw="fixed", h=h, norm=norm)
+    tree = ctx.build_tree(dev(torch, pts))
+    got = ctx.eval_roi(tree, roi).cpu().numpy()
+    check_density(got, oracle.density(pts, roi), "%s %s" % (kernel, h))
+    cnt = ctx.debug_support_counts(tree, roi).cpu().numpy().astype(np.int64)
+    assert np.array_equal(cnt, oracle.support_counts(pts, roi))
+
+
+def test_ragged_subbox_roi_scaled(ctx, torch):
+    pts = synth.c1_cloud(3)
+    for roi in [
+        Roi((0.1, 0.2, 0.3), (0.45, 0.9, 0.5), (13, 7, 9), bw="roi_scaled", h=(0.1, 0, 0)),
+        Roi((0.3, 0.3, 0.3), (0.31, 0.32, 0.305), (5, 6, 7), bw="roi_scaled", h=(0.5, 0, 0)),
+        Roi((-0.2, 0.5, 0.9), (0.3, 1.3, 1.4), (17, 2, 3), bw="fixed", h=(0.05, 0.05, 0.05)),
+    ]:
+        tree = ctx.build_tree(dev(torch, pts))
+        got = ctx.eval_roi(tree, roi).cpu().numpy()
+        check_density(got, oracle.density(pts, roi), str(roi.res))
+        cnt = ctx.debug_support_counts(tree, roi).cpu().numpy().astype(np.int64)
+        assert np.array_equal(cnt, oracle.support_counts(pts, roi))
+
+
+def test_support_boundary_golden(ctx, torch):
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "support_boundary.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    pts = np.array([r[:3] for r in rows], dtype=np.float32)
+    member = np.array([int(r[3]) for r in rows])
+    roi = Roi((0, 0, 0), (1, 1, 1), (5, 5, 5), bw="fixed", h=(0.25, 0.25, 0.25), norm="count")
+    tree = ctx.build_tree(dev(torch, pts))
+    node = 2 + 5 * (2 + 5 * 2)
+    offs, idx = ctx.debug_candidates(tree, roi, node, node + 1)
+    assert np.array_equal(np.sort(idx), np.nonzero(member)[0])
+    cnt = ctx.debug_support_counts(tree, roi).cpu().numpy()
+    assert int(cnt[node]) == int(member.sum())
+
+
+def test_empty_single_and_degenerate_clouds(ctx, torch):
+    roi = Roi((0, 0, 0), (1, 1, 1), (9, 10, 11), bw="fixed", h=(0.3, 0.2, 0.25))
+    # empty cloud: every node zero
+    tree = ctx.build_tree(torch.zeros((0, 3), dtype=torch.float32, device="cuda"))
+    got = ctx.eval_roi(tree, roi).cpu().numpy()
+    assert np.all(got == 0)
+    # one particle: the kernel profile
+    p = np.array([[0.37, 0.52, 0.61]], dtype=np.float32)
+    tree = ctx.build_tree(dev(torch, p))
+    check_density(ctx.eval_roi(tree, roi).cpu().numpy(), oracle.density(p, roi), "single")
+    # all particles coincident, some on grid nodes and on faces
+    p = np.concatenate([np.full((300, 3), 0.5, np.float32),
+                        np.array([[0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.125, 0.5, 1.0]], np.float32)])
+    tree = ctx.build_tree(dev(torch, p))
+    for r in [roi, roi.replace(res=(9, 9, 9), h=(0.125, 0.125, 0.125))]:
+        check_density(ctx.eval_roi(tree, r).cpu().numpy(), oracle.density(p, r), "coincident")
+        cnt = ctx.debug_support_counts(tree, r).cpu().numpy().astype(np.int64)
+        assert np.array_equal(cnt, oracle.support_counts(p, r))
+    # a ROI far from every particle
+    far = roi.replace(lo=(5, 5, 5), hi=(6, 6, 6))
+    assert np.all(ctx.eval_roi(tree, far).cpu().numpy() == 0)
+
+
+def test_determinism_and_permutation(ctx, torch):
+    pts = synth.c1_cloud(4)
+    roi = Roi((0, 0, 0), (1, 1, 1), (24, 24, 24), bw="fixed", h=(0.04, 0.04, 0.04))
+    tree = ctx.build_tree(dev(torch, pts))
+    a = ctx.eval_roi(tree, roi).cpu().numpy()
+    b = ctx.eval_roi(tree, roi).cpu().numpy()
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(1).permutation(len(pts))
+    tree2 = ctx.build_tree(dev(torch, pts[perm]))
+    c = ctx.eval_roi(tree2, roi).cpu().numpy()
+    check_density(c, oracle.density(pts, roi), "permuted")
+    node = 12 + 24 * (12 + 24 * 12)
+    o1, i1 = ctx.debug_candidates(tree, roi, node, node + 1)
+    o2, i2 = ctx.debug_candidates(tree2, roi, node, node + 1)
+    assert np.array_equal(np.sort(perm[i2]), i1)
+
+
+# ---------------------------------------------------------------------------
+# chunk splitting and the in-kernel tree walk (lists that do not fit)
+# ---------------------------------------------------------------------------
+
+def test_split_chunks_and_walk_fallback_bitwise(ctx, torch):
+    pts = synth.clumpy_cloud(60_000, 7)
+    roi = Roi((0.2, 0.2, 0.2), (0.8, 0.8, 0.8), (40, 40, 40), bw="fixed", h=(0.05, 0.05, 0.05))
+    tree = ctx.build_tree(dev(torch, pts))
+    ref = oracle.density(pts, roi)
+    outs = {}
+    for label, kw in [("default", {}), ("chunks4", {"chunk_leaves": 4}),
+                      ("walk4", {"chunk_leaves": 4, "list_capacity": 1}),
+                      ("walk64", {"list_capacity": 1})]:
+        ctx.set_eval_opts(**kw)
+        outs[label] = ctx.eval_roi(tree, roi).cpu().numpy()
+        check_density(outs[label], ref, label)
+    ctx.set_eval_opts()
+    # the tree walk reproduces the stored-list results bit for bit
+    assert np.array_equal(outs["chunks4"], outs["walk4"])
+    assert np.array_equal(outs["default"], outs["walk64"])
+
+
+# ---------------------------------------------------------------------------
+# per-point bandwidth (k-NN), Gaussian truncated at 3h
+# ---------------------------------------------------------------------------
+
+def test_knn_h2_bit_exact_and_lattice(ctx, torch):
+    pts = synth.clumpy_cloud(30_000, 2)
+    tree = ctx.build_tree(dev(torch, pts), knn_k=32)
+    h2 = ctx.debug_point_h2(tree)
+    ref = oracle.knn_h2(pts, 32)
+    assert np.array_equal(h2, ref), np.nonzero(h2 != ref)[0][:10]
+    lat = synth.lattice_cloud(9, 0.0625, 0.25)
+    tree = ctx.build_tree(dev(torch, lat), knn_k=32)
+    h2 = ctx.debug_point_h2(tree)
+    assert h2[4 + 9 * (4 + 9 * 4)] == np.float32(0.015625)
+    assert np.array_equal(h2, oracle.knn_h2(lat, 32))
+    for k in (1, 7, 64):
+        tree = ctx.build_tree(dev(torch, pts[:5000]), knn_k=k)
+        assert np.array_equal(ctx.debug_point_h2(tree), oracle.knn_h2(pts[:5000], k)), k
+
+
+def test_per_point_gauss_density(ctx, torch):
+    pts = synth.clumpy_cloud(40_000, 3)
+    roi = Roi((0, 0, 0), (1, 1, 1), (33, 30, 27), kernel="gauss_trunc3", bw="per_point")
+    tree = ctx.build_tree(dev(torch, pts), knn_k=32)
+    h2 = ctx.debug_point_h2(tree)
+    got = ctx.eval_roi(tree, roi).cpu().numpy()
+    ref = oracle.density(pts, roi, h2=h2)
+    check_density(got, ref, "per-point gauss")
+    cnt = ctx.debug_support_counts(tree, roi).cpu().numpy().astype(np.int64)
+    assert np.array_equal(cnt, oracle.support_counts(pts, roi, h2=h2))
+    nodes = [int(np.argmax(ref)), 0, 5000, 12345]
+    for n in nodes:
+        o, i = ctx.debug_candidates(tree, roi, n, n + 1)
+        ro, ri = oracle.candidates(pts, roi, np.array([n]), h2=h2)
+        assert np.array_equal(i, ri)
+    # Epanechnikov with the same per-point bandwidths
+    r2 = roi.replace(kernel="epanechnikov")
+    check_density(ctx.eval_roi(tree, r2).cpu().numpy(), oracle.density(pts, r2, h2=h2), "pp epan")
+
+
+def test_zero_bandwidth_particles(ctx, torch):
+    pts = np.concatenate([np.full((40, 3), 0.5, np.float32), synth.uniform_cloud(3000, 1)])
+    roi = Roi((0, 0, 0), (1, 1, 1), (9, 9, 9), kernel="gauss_trunc3", bw="per_point")
+    tree = ctx.build_tree(dev(torch, pts), knn_k=32)
+    h2 = ctx.debug_point_h2(tree)
+    assert np.array_equal(h2, oracle.knn_h2(pts, 32))
+    check_density(ctx.eval_roi(tree, roi).cpu().numpy(), oracle.density(pts, roi, h2=h2), "zero-h")
+    centre = 4 + 9 * (4 + 9 * 4)
+    _, idx = ctx.debug_candidates(tree, roi, centre, centre + 1)
+    _, ridx = oracle.candidates(pts, roi, np.array([centre]), h2=h2)
+    assert np.array_equal(idx, ridx) and not np.any(idx < 40)
+
+
+def test_user_given_bandwidth(ctx, torch):
+    pts = synth.c1_cloud(5)[:8000].copy()
+    h = np.random.default_rng(2).uniform(0.01, 0.05, size=len(pts)).astype(np.float32)
+    roi = Roi((0, 0, 0), (1, 1, 1), (21, 21, 21), kernel="epanechnikov", bw="per_point")
+    tree = ctx.build_tree(dev(torch, pts), h=dev(torch, h))
+    got = ctx.eval_roi(tree, roi).cpu().numpy()
+    ih, w = oracle.params_from_h(h)
+    ref = oracle.density_raw(pts, roi, "epanechnikov", oracle.kernel_ck("epanechnikov") / len(pts),
+                             ih_pp=ih, w_pp=w)
+    check_density(got, ref, "user h")
+
+
+# ---------------------------------------------------------------------------
+# particles inside B only, and the MBE chain
+# ---------------------------------------------------------------------------
+
+def test_in_roi_set(ctx, torch):
+    pts = synth.c1_cloud(6)
+    roi = Roi((0.25, 0.3, 0.2), (0.7, 0.8, 0.6), (19, 21, 17), bw="fixed", h=(0.04, 0.04, 0.04),
+              set="in_roi")
+    tree = ctx.build_tree(dev(torch, pts))
+    check_density(ctx.eval_roi(tree, roi).cpu().numpy(), oracle.density(pts, roi), "in_roi")
+    tree = ctx.build_tree(dev(torch, pts), knn_k=16)
+    h2 = ctx.debug_point_h2(tree)
+    r2 = roi.replace(bw="per_point", kernel="gauss_trunc3")
+    check_density(ctx.eval_roi(tree, r2).cpu().numpy(), oracle.density(pts, r2, h2=h2), "in_roi pp")
+
+
+@pytest.mark.parametrize("case", ["full", "sub", "tiny"])
+def test_mbe_stagewise(ctx, torch, case):
+    pts = synth.clumpy_cloud(50_000, 11)
+    if case == "full":
+        roi = Roi((0, 0, 0), (1, 1, 1), (32, 32, 32), bw="mbe", set="in_roi")
+    elif case == "sub":
+        roi = Roi((0.2, 0.25, 0.3), (0.7, 0.75, 0.9), (24, 20, 28), bw="mbe", set="in_roi")
+    else:
+        roi = Roi((0.5, 0.5, 0.5), (0.52, 0.52, 0.52), (8, 8, 8), bw="mbe", set="in_roi")
+    tree = ctx.build_tree(dev(torch, pts))
+    d = ctx.debug_mbe(tree, roi)
+    torch.cuda.synchronize()
+    inc = oracle.in_box_mask(pts, roi.lo, roi.hi)
+    idx_b = np.nonzero(inc)[0]
+    assert d["n_b"] == len(idx_b) and np.array_equal(d["idx_b"], idx_b)
+    if len(idx_b) == 0:
+        assert np.all(d["final"].cpu().numpy() == 0)
+        return
+    pts_b = pts[idx_b]
+    # Eq. 1: bit-exact
+    ell0, _ = oracle.mbe_initial_ell(pts_b, roi)
+    assert np.array_equal(d["ell0"], ell0)
+    # pilot grid against the oracle's own pilot
+    full = oracle.mbe(pts, roi)
+    check_density(d["pilot"], full["pilot"], "pilot")
+    # ASL given the GPU pilot
+    pden, ave, ell_j = oracle.mbe_asl(pts_b, roi, d["pilot"].astype(np.float64), ell0)
+    np.testing.assert_allclose(d["pden"], pden, rtol=1e-6, atol=1e-12 * max(pden.max(), 1e-30))
+    assert d["aveden"] == pytest.approx(ave, rel=1e-6)
+    np.testing.assert_allclose(d["ell_j"], ell_j, rtol=1e-6)
+    # final density given the GPU's adaptive lengths
+    ref = oracle.mbe(pts, roi, ell_j_in=d["ell_j"])["final"]
+    check_density(d["final"].cpu().numpy(), ref, "final")
+    # and the plain evaluation entry point gives the same grid
+    again = ctx.eval_roi(tree, roi).cpu().numpy()
+    assert np.array_equal(again, d["final"].cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# batches: each grid is the same alone and in the mix
+# ---------------------------------------------------------------------------
+
+def test_batch_alone_vs_mix(ctx, torch):
+    pts = synth.clumpy_cloud(200_000, 4)
+    tree = ctx.build_tree(dev(torch, pts))
+    rois = synth.random_batch_rois(24, seed=9, side_lo=0.02, res_lo=8, res_hi=40, h0=0.03)
+    outs = [torch.full((r.n_nodes,), -1.0, device="cuda") for r in rois]
+    t = ctx.submit(tree, rois, outs)
+    ctx.wait(t)
+    for i, r in enumerate(rois):
+        alone = ctx.eval_roi(tree, r).cpu().numpy()
+        mixed = outs[i].cpu().numpy()
+        assert np.array_equal(alone, mixed), i
+    # sampled nodes of every ROI against the oracle
+    for i, r in enumerate(rois[:8]):
+        nodes = sample_nodes(None, r.n_nodes, 24, i)
+        ref = oracle.density(pts, r, nodes=nodes)
+        got = outs[i].cpu().numpy()[nodes]
+        full_peak = outs[i].cpu().numpy().max()
+        peak = max(ref.max(), full_peak)
+        big = ref >= 1e-3 * peak
+        if big.any():
+            assert np.max(np.abs(got[big] - ref[big]) / ref[big]) <= REL_TOL
+        assert np.max(np.abs(got[~big] - ref[~big]), initial=0) <= ABS_TOL * peak + 1e-30
+    # a batch mixing kernels and bandwidth modes, and polling
+    tree2 = ctx.build_tree(dev(torch, pts[:50_000]), knn_k=32)
+    mix = [rois[0], rois[1].replace(kernel="gauss_trunc3"),
+           rois[2].replace(bw="per_point", kernel="gauss_trunc3"),
+           rois[3].replace(set="in_roi", bw="fixed", h=(0.02, 0.02, 0.02))]
+    outs2 = [torch.zeros((r.n_nodes,), device="cuda") for r in mix]
+    t2 = ctx.submit(tree2, mix, outs2)
+    while not ctx.poll(t2):
+        pass
+    ctx.wait(t2)
+    for r, o in zip(mix, outs2):
+        assert np.array_equal(o.cpu().numpy(), ctx.eval_roi(tree2, r).cpu().numpy())
+
+
+def test_errors(ctx, torch, sfk):
+    pts = synth.c1_cloud(1)[:1000].copy()
+    tree = ctx.build_tree(dev(torch, pts))
+    bad = [synth.c1_roi().replace(res=(1, 4, 4)), synth.c1_roi().replace(lo=(1, 0, 0)),
+           synth.c1_roi().replace(h=(0.0, 0.1, 0.1)), synth.c1_roi().replace(bw="per_point"),
+           synth.c1_roi().replace(bw="mbe")]
+    for r in bad:
+        out = torch.zeros(max(1, r.n_nodes), device="cuda")
+        with pytest.raises(sfk.SfkError) as e:
+            ctx._check(ctx._lib.sfk_eval_roi(ctx._h, tree._h,
+                                             __import__("ctypes").byref(sfk.roi_struct(r, out.data_ptr())),
+                                             None))
+        assert e.value.name == "SFK_E_INVAL"
+    with pytest.raises(sfk.SfkError) as e:
+        ctx.eval_roi(tree, synth.c1_roi().replace(bw="mbe", set="in_roi", kernel="gauss_trunc3"))
+    assert e.value.name == "SFK_E_UNSUPPORTED"
+    nanpts = pts.copy()
+    nanpts[5, 1] = np.nan
+    with pytest.raises(sfk.SfkError):
+        ctx.build_tree(dev(torch, nanpts))
+    with pytest.raises(sfk.SfkError):
+        ctx.build_tree(dev(torch, pts[:10]), knn_k=32)
+    r = synth.c1_roi()
+    shared = torch.zeros(r.n_nodes + 10, device="cuda")
+    with pytest.raises(sfk.SfkError):
+        ctx.submit(tree, [r, r], [shared[:r.n_nodes], shared[10:]])
+    # the context stays usable after errors
+    check_density(ctx.eval_roi(tree, r).cpu().numpy(), oracle.density(pts, r), "after errors")
+
+
+# ---------------------------------------------------------------------------
+# the benchmarked workload at full size: 10M clumpy points, 128^3, Gaussian
+# truncated at 3h, per-point h from the 32nd neighbour (sampled checks)
+# ---------------------------------------------------------------------------
+
+def test_full_size_per_point_workload(ctx, torch):
+    pts = synth.clumpy_cloud(10_000_000, 2)
+    say("generated 10M")
+    roi = synth.c2_roi(128)
+    tree = ctx.build_tree(dev(torch, pts), knn_k=32)
+    torch.cuda.synchronize()
+    say("tree + kNN built")
+    h2 = ctx.debug_point_h2(tree)
+    q = np.random.default_rng(3).choice(len(pts), size=48, replace=False)
+    assert np.array_equal(h2[q], oracle.knn_h2(pts, 32, queries=q))
+    say("kNN sample exact")
+    out = ctx.eval_roi(tree, roi)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    am = int(np.argmax(got))
+    above = np.nonzero(got >= 1e-3 * got.max())[0]
+    g = np.random.default_rng(4)
+    nodes = np.unique(np.concatenate([[am], g.choice(roi.n_nodes, 24, replace=False),
+                                      g.choice(above, 24, replace=False)]))
+    ref = oracle.density(pts, roi, nodes=nodes, h2=h2)
+    peak = max(ref.max(), got.max())
+    big = ref >= 1e-3 * peak
+    rel = np.abs(got[nodes][big] - ref[big]) / ref[big]
+    assert rel.max() <= REL_TOL, rel.max()
+    assert np.max(np.abs(got[nodes][~big] - ref[~big]), initial=0) <= ABS_TOL * peak
+    say("density sample max rel err", rel.max())
+    for n in nodes[:6]:
+        o, i = ctx.debug_candidates(tree, roi, int(n), int(n) + 1)
+        ro, ri = oracle.candidates(pts, roi, np.array([n]), h2=h2)
+        assert np.array_equal(i, ri)
+    say("candidate sample exact")
