@@ -57,9 +57,9 @@ def _lib():
         lib.orc_percentile.argtypes = [vp, C.c_int64, C.c_int, C.c_double]
         lib.orc_percentile.restype = C.c_double
         lib.orc_node_coord.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
-        lib.orc_node_coord.restype = C.c_float
-        lib.orc_u2_f32.argtypes = [C.c_float] * 9
-        lib.orc_u2_f32.restype = C.c_float
+        lib.orc_node_coord.restype = C.c_double
+        lib.orc_u2.argtypes = [C.c_double] * 3 + [C.c_float] * 6
+        lib.orc_u2.restype = C.c_double
         lib.orc_d2_f32.argtypes = [vp, vp]
         lib.orc_d2_f32.restype = C.c_float
         for name in ("orc_ck_epanechnikov", "orc_ck_gauss_trunc3", "orc_p_chi2_3_below_9"):
@@ -102,7 +102,7 @@ def node_coord(lo: float, hi: float, res: int, i: int) -> float:
 
 
 def axis_coords(lo: float, hi: float, res: int) -> np.ndarray:
-    return np.array([node_coord(lo, hi, res, i) for i in range(res)], dtype=np.float32)
+    return np.array([node_coord(lo, hi, res, i) for i in range(res)], dtype=np.float64)
 
 
 def node_positions(roi, nodes: np.ndarray) -> np.ndarray:
@@ -114,11 +114,12 @@ def node_positions(roi, nodes: np.ndarray) -> np.ndarray:
     return np.stack([ax[0][ix], ax[1][iy], ax[2][iz]], axis=1)
 
 
-def u2_f32(node, p, ih) -> float:
-    """Canonical float32 squared scaled distance (membership quantity)."""
-    return _lib().orc_u2_f32(float(node[0]), float(node[1]), float(node[2]),
-                             float(p[0]), float(p[1]), float(p[2]),
-                             float(ih[0]), float(ih[1]), float(ih[2]))
+def u2(node, p, ih) -> float:
+    """Canonical squared scaled distance (double, on float32 particle and
+    inverse-bandwidth inputs): the membership and kernel-value quantity."""
+    return _lib().orc_u2(float(node[0]), float(node[1]), float(node[2]),
+                         float(p[0]), float(p[1]), float(p[2]),
+                         float(ih[0]), float(ih[1]), float(ih[2]))
 
 
 def roi_h(roi) -> np.ndarray:

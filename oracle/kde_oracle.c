@@ -9,21 +9,22 @@
  *
  * Conventions (the readings of the paper that every function below follows):
  *  - Grid nodes are vertex-centred on the closed box B: along axis k,
- *    x_i = (float)(lo + (i * (hi - lo)) / (res - 1)) evaluated in double and
- *    rounded once (Section 3.1 places nodes on a uniform grid over B and calls
- *    their distance the node spacing s_k = (hi - lo) / (res - 1)).
+ *    x_i = lo + (i * (hi - lo)) / (res - 1) in double (Section 3.1 places
+ *    nodes on a uniform grid over B and calls their distance the node
+ *    spacing s_k = (hi - lo) / (res - 1)).
  *  - Linear node index x fastest: idx = x + y*res_x + z*res_x*res_y
  *    (Algorithm 2 and Algorithm 4 index the density buffer this way).
- *  - Support membership is decided in float32 on the float32 inputs by one
- *    fixed operation sequence (the "canonical predicate"):
- *        d_k = fl(x_nk - p_k);  u_k = fl(d_k * ih_k);
- *        u2  = fl(fl(fl(u_x*u_x) + fl(u_y*u_y)) + fl(u_z*u_z));
+ *  - Support membership is decided in double on the float32 inputs by one
+ *    fixed operation sequence (the "canonical predicate"), every operation
+ *    rounded to double, no fused multiply-add:
+ *        d_k = x_nk - p_k;  u_k = d_k * ih_k;
+ *        u2  = (u_x*u_x + u_y*u_y) + u_z*u_z;
  *        member  <=>  u2 < c2
- *    with ih_k = (float)(1 / h_k) the inverse bandwidth and c2 = 1 for the
- *    Epanechnikov kernel (Eq. 4: zero for |x| >= 1, so the support boundary
- *    is excluded) and c2 = 9 for the Gaussian truncated at 3h.
+ *    with ih_k = (float)(1 / h_k) the float32 inverse bandwidth and c2 = 1
+ *    for the Epanechnikov kernel (Eq. 4: zero for |x| >= 1, so the support
+ *    boundary is excluded) and c2 = 9 for the Gaussian truncated at 3h.
  *    This is the per-axis scaled distance of Eq. 3 and Algorithm 2.
- *  - Kernel values are computed in double from the same float inputs.
+ *  - Kernel values are functions of that same u2.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared.
  * Every loop over particles runs in index order inside one thread, so results
@@ -64,8 +65,8 @@ double orc_kernel_ck(int kernel) {
   return 1.0;
 }
 
-float orc_kernel_c2(int kernel) {
-  return kernel == ORC_GAUSS_TRUNC3 ? 9.0f : 1.0f;
+double orc_kernel_c2(int kernel) {
+  return kernel == ORC_GAUSS_TRUNC3 ? 9.0 : 1.0;
 }
 
 /* Kernel profile of the squared scaled distance u2 (double). Eq. 4 for the
@@ -83,42 +84,32 @@ double orc_kernel_value(int kernel, double u2) {
 /* Grid geometry.                                                           */
 /* ------------------------------------------------------------------------ */
 
-float orc_node_coord(double lo, double hi, int res, int i) {
-  return (float)(lo + ((double)i * (hi - lo)) / (double)(res - 1));
+double orc_node_coord(double lo, double hi, int res, int i) {
+  return lo + ((double)i * (hi - lo)) / (double)(res - 1);
 }
 
-void orc_axis_coords(double lo, double hi, int res, float* out) {
+void orc_axis_coords(double lo, double hi, int res, double* out) {
   for (int i = 0; i < res; ++i) out[i] = orc_node_coord(lo, hi, res, i);
 }
 
 /* ------------------------------------------------------------------------ */
-/* Canonical float32 membership predicate.                                  */
+/* Canonical membership quantity: squared scaled distance in double.        */
 /* ------------------------------------------------------------------------ */
 
-float orc_u2_f32(float xn, float yn, float zn, float px, float py, float pz,
-                 float ihx, float ihy, float ihz) {
-  volatile float dx = xn - px, dy = yn - py, dz = zn - pz;
-  volatile float ux = dx * ihx, uy = dy * ihy, uz = dz * ihz;
-  volatile float sx = ux * ux, sy = uy * uy, sz = uz * uz;
-  volatile float sxy = sx + sy;
-  volatile float s = sxy + sz;
-  return s;
-}
-
-/* Squared scaled distance in double from the same float inputs. */
-double orc_u2_f64(float xn, float yn, float zn, float px, float py, float pz,
-                  float ihx, float ihy, float ihz) {
-  double ux = ((double)xn - (double)px) * (double)ihx;
-  double uy = ((double)yn - (double)py) * (double)ihy;
-  double uz = ((double)zn - (double)pz) * (double)ihz;
-  return ux * ux + uy * uy + uz * uz;
+double orc_u2(double xn, double yn, double zn, float px, float py, float pz,
+              float ihx, float ihy, float ihz) {
+  double ux = (xn - (double)px) * (double)ihx;
+  double uy = (yn - (double)py) * (double)ihy;
+  double uz = (zn - (double)pz) * (double)ihz;
+  double sxy = ux * ux + uy * uy;
+  return sxy + uz * uz;
 }
 
 /* ------------------------------------------------------------------------ */
 /* Density at grid nodes (Eq. 2 with a uniform bandwidth, Eq. 7 with a      */
 /* per-particle bandwidth).                                                 */
 /*                                                                          */
-/*  rho(n) = scale * sum_j [u2_f32(n, j) < c2] * w_j * K(u2_f64(n, j))      */
+/*  rho(n) = scale * sum_j [u2(n, j) < c2] * w_j * K(u2(n, j))              */
 /*                                                                          */
 /* pts      n x 3 float positions                                           */
 /* ih_pp    n x 3 per-particle inverse bandwidths, or NULL -> ih_u          */
@@ -132,16 +123,16 @@ void orc_density_nodes(const float* pts, int64_t n, const float* ih_pp,
                        const uint8_t* include, int kernel, const double* lo,
                        const double* hi, const int* res, double scale,
                        const int64_t* nodes, int64_t n_nodes, double* out) {
-  const float c2 = orc_kernel_c2(kernel);
+  const double c2 = orc_kernel_c2(kernel);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < n_nodes; ++q) {
     int64_t idx = nodes[q];
     int ix = (int)(idx % res[0]);
     int iy = (int)((idx / res[0]) % res[1]);
     int iz = (int)(idx / ((int64_t)res[0] * res[1]));
-    float xn = orc_node_coord(lo[0], hi[0], res[0], ix);
-    float yn = orc_node_coord(lo[1], hi[1], res[1], iy);
-    float zn = orc_node_coord(lo[2], hi[2], res[2], iz);
+    double xn = orc_node_coord(lo[0], hi[0], res[0], ix);
+    double yn = orc_node_coord(lo[1], hi[1], res[1], iy);
+    double zn = orc_node_coord(lo[2], hi[2], res[2], iz);
     double sum = 0.0;
     for (int64_t j = 0; j < n; ++j) {
       if (include && !include[j]) continue;
@@ -154,14 +145,12 @@ void orc_density_nodes(const float* pts, int64_t n, const float* ih_pp,
         ihx = ih_u[0]; ihy = ih_u[1]; ihz = ih_u[2];
       }
       w = w_pp ? w_pp[j] : w_u;
-      float u2 = orc_u2_f32(xn, yn, zn, p[0], p[1], p[2], ihx, ihy, ihz);
+      double u2 = orc_u2(xn, yn, zn, p[0], p[1], p[2], ihx, ihy, ihz);
       if (!(u2 < c2)) continue;
-      if (kernel == ORC_COUNT) {
+      if (kernel == ORC_COUNT)
         sum += 1.0;
-      } else {
-        double u2d = orc_u2_f64(xn, yn, zn, p[0], p[1], p[2], ihx, ihy, ihz);
-        sum += w * orc_kernel_value(kernel, u2d);
-      }
+      else
+        sum += w * orc_kernel_value(kernel, u2);
     }
     out[q] = kernel == ORC_COUNT ? sum : scale * sum;
   }
@@ -175,7 +164,7 @@ void orc_candidates(const float* pts, int64_t n, const float* ih_pp,
                     const double* lo, const double* hi, const int* res,
                     const int64_t* nodes, int64_t n_nodes, int64_t* offsets,
                     int64_t* idx_out) {
-  const float c2 = orc_kernel_c2(kernel);
+  const double c2 = orc_kernel_c2(kernel);
   if (!idx_out) offsets[0] = 0;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t q = 0; q < n_nodes; ++q) {
@@ -183,16 +172,16 @@ void orc_candidates(const float* pts, int64_t n, const float* ih_pp,
     int ix = (int)(idx % res[0]);
     int iy = (int)((idx / res[0]) % res[1]);
     int iz = (int)(idx / ((int64_t)res[0] * res[1]));
-    float xn = orc_node_coord(lo[0], hi[0], res[0], ix);
-    float yn = orc_node_coord(lo[1], hi[1], res[1], iy);
-    float zn = orc_node_coord(lo[2], hi[2], res[2], iz);
+    double xn = orc_node_coord(lo[0], hi[0], res[0], ix);
+    double yn = orc_node_coord(lo[1], hi[1], res[1], iy);
+    double zn = orc_node_coord(lo[2], hi[2], res[2], iz);
     int64_t c = 0;
     int64_t base = idx_out ? offsets[q] : 0;
     for (int64_t j = 0; j < n; ++j) {
       if (include && !include[j]) continue;
       const float* p = pts + 3 * j;
       const float* ih = ih_pp ? ih_pp + 3 * j : ih_u;
-      float u2 = orc_u2_f32(xn, yn, zn, p[0], p[1], p[2], ih[0], ih[1], ih[2]);
+      double u2 = orc_u2(xn, yn, zn, p[0], p[1], p[2], ih[0], ih[1], ih[2]);
       if (u2 < c2) {
         if (idx_out) idx_out[base + c] = j;
         ++c;

@@ -59,10 +59,11 @@ def test_gauss_trunc3_constant_unit_mass():
 
 def test_node_coords_dyadic_and_endpoints():
     ax = oracle.axis_coords(0.0, 1.0, 33)
-    assert np.array_equal(ax, (np.arange(33) / 32.0).astype(np.float32))
+    assert np.array_equal(ax, np.arange(33) / 32.0)
     ax = oracle.axis_coords(0.1, 0.7, 17)
-    assert ax[0] == np.float32(0.1) and ax[-1] == np.float32(0.7)
+    assert ax[0] == 0.1 and ax[-1] == 0.7
     assert np.all(np.diff(ax) > 0)
+    np.testing.assert_allclose(np.diff(ax), 0.6 / 16, rtol=1e-13)
 
 
 # ---------------------------------------------------------------------------
@@ -113,7 +114,7 @@ def test_support_boundary_golden():
     ih = np.float32(4.0)
     for px, py, pz, member, u2 in rows:
         p = np.array([[px, py, pz]], dtype=np.float32)
-        assert oracle.u2_f32((0.5, 0.5, 0.5), p[0], (ih, ih, ih)) == np.float32(u2)
+        assert oracle.u2((0.5, 0.5, 0.5), p[0], (ih, ih, ih)) == u2
         cnt = oracle.support_counts(p, roi, nodes=np.array([node]))
         assert int(cnt[0]) == int(member), (px, py, pz)
         # density is zero exactly on the boundary
@@ -217,11 +218,11 @@ def test_uniform_interior_constant():
 # ---------------------------------------------------------------------------
 
 def _np_members(pts, node, ih, c2):
-    d = (np.float32(node) - pts).astype(np.float32)
-    u = (d * ih.astype(np.float32)).astype(np.float32)
-    s = (u * u).astype(np.float32)
-    u2 = ((s[:, 0] + s[:, 1]).astype(np.float32) + s[:, 2]).astype(np.float32)
-    return np.nonzero(u2 < np.float32(c2))[0]
+    d = np.asarray(node, dtype=np.float64) - pts.astype(np.float64)
+    u = d * ih.astype(np.float64)
+    s = u * u
+    u2 = (s[:, 0] + s[:, 1]) + s[:, 2]
+    return np.nonzero(u2 < c2)[0]
 
 
 @pytest.mark.parametrize("kernel", ["epanechnikov", "gauss_trunc3"])
@@ -260,7 +261,7 @@ def test_permutation_invariance():
 
 def test_in_roi_set_excludes_outside_particles():
     # a particle outside the box contributes to CLOUD but not to IN_ROI
-    pts = np.array([[0.5, 0.5, 0.5], [0.52, 0.5, 0.5], [0.61, 0.5, 0.5]], dtype=np.float32)
+    pts = np.array([[0.45, 0.5, 0.5], [0.52, 0.5, 0.5], [0.61, 0.5, 0.5]], dtype=np.float32)
     roi = Roi((0.4, 0.4, 0.4), (0.6, 0.6, 0.6), (3, 3, 3), kernel="epanechnikov",
               bw="fixed", h=(0.1, 0.1, 0.1), norm="count")
     node = np.array([2 + 3 * (1 + 3 * 1)])  # (0.6, 0.5, 0.5)
