@@ -1,0 +1,248 @@
+"""Benchmark of the ROI kernel density estimation hot path on one MI355X.
+
+Default workload (the configuration the headline metric is quoted on):
+10M clustered float32 points (2,000 anisotropic Gaussian clumps with
+power-law masses plus 20% uniform background), ROI = unit box, 128^3 grid,
+Gaussian kernel truncated at 3h, per-point h from the 32nd nearest
+neighbour. One step = the whole hot path from points resident in HBM to the
+density grid: tree build (bounding box, Morton sort, leaves, box hierarchy),
+k-NN bandwidths, tile range query and evaluation.
+
+Prints one JSON line (rank 0): value = useful kernel evaluations (node,
+particle pairs inside the support) per second of step time.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("kernel evals/s + ROI grid latency p50/p99 (ms), batched vs "
+          "one-ROI-per-launch")
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published fp32 vector peak
+HBM_PEAK_GBS = 8000.0
+# algorithmic float operations per useful evaluation, counted from the
+# definition (per axis: difference, scaling, square; two adds for u2; the
+# kernel value; the weight; the accumulation)
+FLOPS_PER_EVAL = {"gauss_trunc3": 15, "epanechnikov": 13}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="per_point_10m",
+                   choices=["per_point_10m", "small"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-nodes", type=int, default=600)
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the batched vs one-ROI-per-launch comparison")
+    p.add_argument("--n-batch", type=int, default=256)
+    p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--no-serve", action="store_true")
+    return p.parse_args()
+
+
+def workload(name):
+    import synth
+    if name == "small":
+        pts = synth.c1_cloud(1)
+        roi = synth.c1_roi()
+        return pts, roi, 0, {"workload": "20k points (half uniform, half in 8 clusters), unit box, "
+                                         "32^3, Epanechnikov, fixed h=0.02",
+                             "n_points": len(pts), "grid": [32, 32, 32]}
+    pts = synth.clumpy_cloud(10_000_000, 2)
+    roi = synth.c2_roi(128)
+    return pts, roi, 32, {
+        "workload": "10M clustered points (2,000 power-law clumps + 20% uniform), unit-box ROI, "
+                    "128^3 grid, Gaussian truncated at 3h, per-point h from the 32nd nearest "
+                    "neighbour; step = tree build + k-NN + range query + evaluation",
+        "n_points": len(pts), "grid": [128, 128, 128], "kernel": "gauss_trunc3",
+        "bandwidth": "per_point_knn32", "seed": 2}
+
+
+def cpu_baseline(pts, roi, h2, n_nodes, seed=7):
+    """The FP64 oracle (brute force over every particle) timed on a random
+    sample of grid nodes, reported as useful evaluations per second."""
+    import oracle
+    g = np.random.default_rng(seed)
+    nodes = np.sort(g.choice(roi.n_nodes, size=min(n_nodes, roi.n_nodes), replace=False))
+    t0 = time.perf_counter()
+    oracle.density(pts, roi, nodes=nodes, h2=h2)
+    dt = time.perf_counter() - t0
+    useful = int(oracle.support_counts(pts, roi, nodes=nodes, h2=h2).sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": useful / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random nodes of the grid, each brute-forced over all %d particles "
+                      "(FP64 values, per-point h given); %.1f s, %d useful evals"
+                      % (len(nodes), len(pts), dt, useful)}
+
+
+def batch_vs_single(ctx, tree, torch, n_rois):
+    """Many uneven ROIs in one persistent launch vs one launch per ROI, on
+    the resident tree (same kernels, same results)."""
+    import synth
+    rois = synth.random_batch_rois(n_rois, seed=4)
+    outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    # warm both paths
+    ctx.wait(ctx.submit(tree, rois, outs))
+    for r, o in zip(rois, outs):
+        ctx.eval_roi(tree, r, out=o)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    # one launch per ROI: per-ROI completion events
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_rois + 1)]
+    evs[0].record(stream)
+    for i, (r, o) in enumerate(zip(rois, outs)):
+        ctx.eval_roi(tree, r, out=o, stream=stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    single_ms = evs[0].elapsed_time(evs[-1])
+    lat_single = np.array([evs[0].elapsed_time(e) for e in evs[1:]])
+    ref = [o.clone() for o in outs]
+    # batched: one submit
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = ctx.submit(tree, rois, outs)
+    ctx.wait(t)
+    batch_ms = (time.perf_counter() - t0) * 1e3
+    same = all(torch.equal(a, b) for a, b in zip(ref, outs))
+    useful = 0
+    for r in rois:
+        useful += ctx.debug_eval_count(tree, r)[0]
+    return {
+        "workload": "%d ROIs, sides log-uniform in [1e-3, 1], grids 16^3-128^3, Epanechnikov, "
+                    "h = 0.01 x side, on the resident 10M-point tree" % n_rois,
+        "nodes": int(sum(r.n_nodes for r in rois)), "useful_evals": int(useful),
+        "batched_ms": batch_ms, "single_launch_ms": single_ms,
+        "batched_evals_per_s": useful / (batch_ms * 1e-3),
+        "single_launch_evals_per_s": useful / (single_ms * 1e-3),
+        "speedup": single_ms / batch_ms,
+        "single_launch_latency_p50_ms": float(np.percentile(lat_single, 50)),
+        "single_launch_latency_p99_ms": float(np.percentile(lat_single, 99)),
+        "batched_latency_ms": batch_ms,
+        "bitwise_equal": bool(same),
+    }
+
+
+def serving(ctx, tree, torch, duration_s):
+    """VR-like request loop on the resident tree: 8 streams of Poisson
+    arrivals at 90 Hz each (sides log-uniform in [1e-4, 1], panning centres,
+    grids 32^3-128^3, Epanechnikov, h = 0.01 x side). Continuous batching
+    over 4 streams vs one ROI per launch in FIFO order."""
+    import synth
+    arr, _, rois = synth.serving_trace(seed=5, duration_s=duration_s)
+    outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    rec = {"workload": "%d requests over %.1f s from 8 streams at 90 Hz, sides log-uniform "
+                       "in [1e-4, 1], grids 32^3-128^3, Epanechnikov, h = 0.01 x side, "
+                       "on the resident 10M-point tree" % (len(rois), duration_s),
+           "frame_budget_ms": 1000.0 / 90.0}
+    useful = 0
+    for r in rois:
+        useful += ctx.debug_eval_count(tree, r)[0]
+    rec["useful_evals"] = int(useful)
+    for name, mode in (("continuous_batching", 0), ("one_roi_per_launch", 1)):
+        res, s = ctx.serve(tree, arr, rois, outs, mode=mode, n_slots=4, max_batch=64,
+                           budget_bytes=float(8 << 30))
+        lat = np.array([res[i].latency_ms for i in range(len(rois))])
+        rec[name] = {"p50_ms": s.p50_ms, "p99_ms": s.p99_ms, "max_ms": s.max_ms,
+                     "deadline_miss_rate": float(np.mean(lat > 1000.0 / 90.0)),
+                     "evals_per_s": useful / s.wall_s, "wall_s": s.wall_s,
+                     "batches": s.n_batches, "mean_batch": s.mean_batch,
+                     "mean_in_flight": s.mean_in_flight, "budget_waits": s.budget_waits}
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2601_20758_amd as sfk
+
+    pts, roi, knn_k, config = workload(args.workload)
+    log("workload ready:", config["workload"])
+    xyz = torch.from_numpy(pts).cuda()
+    ctx = sfk.Context(0)
+    ctx.profile_enable(True)
+    out = torch.empty(roi.n_nodes, device="cuda")
+
+    def step():
+        tree = ctx.build_tree(xyz, knn_k=knn_k)
+        ctx.eval_roi(tree, roi, out=out)
+        return tree
+
+    for i in range(args.warmup):
+        step().close()
+        torch.cuda.synchronize()
+        log("warmup step", i + 1)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tree = step()
+        if i + 1 < args.steps:
+            tree.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    log("timed %d steps in %.3f s" % (args.steps, dt))
+
+    # untimed: useful pairs of one evaluation and tested pairs
+    useful, tested = ctx.debug_eval_count(tree, roi)
+    ms_per_step = dt * 1e3 / args.steps
+    value = useful * args.steps / dt
+    eval_ms = prof["eval_ms"] / max(1, prof["eval_launches"])
+    flops = FLOPS_PER_EVAL[roi.kernel] * useful
+    achieved = flops / (eval_ms * 1e-3) / 1e12
+    result = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": config,
+        "roofline": {"bound": "alu", "kernel": "k_eval", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_eval": FLOPS_PER_EVAL[roi.kernel], "evals_per_launch": useful,
+                     "avg_launch_ms": eval_ms},
+        "phases_ms": {k: prof[k] / args.steps for k in
+                      ("build_ms", "knn_ms", "tile_count_ms", "plan_ms", "tile_fill_ms",
+                       "eval_ms")},
+        "eval_only_evals_per_s": useful / (eval_ms * 1e-3),
+        "useful_evals": useful, "tested_pairs": tested,
+        "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
+    }
+    if args.workload == "per_point_10m" and not args.no_batch:
+        try:
+            result["batch_vs_single"] = batch_vs_single(ctx, tree, torch, args.n_batch)
+        except Exception as e:  # report, never hide
+            result["batch_vs_single"] = {"error": repr(e)}
+    if args.workload == "per_point_10m" and not args.no_serve:
+        try:
+            result["serving"] = serving(ctx, tree, torch, args.serve_seconds)
+        except Exception as e:  # report, never hide
+            result["serving"] = {"error": repr(e)}
+    if not args.no_cpu_baseline:
+        h2 = ctx.debug_point_h2(tree) if knn_k else None
+        log("timing the oracle on a node sample")
+        result["cpu_baseline"] = cpu_baseline(pts, roi, h2, args.cpu_sample_nodes)
+    tree.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,7 +171,7 @@ sfk_status sfk_cancel(sfk_ctx ctx, sfk_ticket t);
 /* Tile shape used for tile-granular range queries and evaluation: one
  * wavefront owns tx*ty*tz grid nodes. 0 = chosen by the autotuner table. */
 typedef struct {
-  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 8x4x2, 3 = 4x4x2, 4 = 8x4x4 */
+  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2 */
   int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 64 */
   int32_t persistent_waves_per_cu; /* 0 = automatic */
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
@@ -182,6 +182,32 @@ sfk_status sfk_set_eval_opts(sfk_ctx ctx, const sfk_eval_opts* opts);
 /* Time every tile shape on the sample ROIs and record the fastest per
  * (kernel, bandwidth mode, support-to-spacing bucket) for later batches. */
 sfk_status sfk_autotune(sfk_ctx ctx, sfk_tree tree, const sfk_roi* sample, int32_t n);
+/* The autotuner's table: up to cap (key, tile shape) pairs, *n_out = entries.
+ * key = (kernel * 4 + bandwidth mode) * 8 + support-in-spacings bucket. */
+sfk_status sfk_autotune_table(sfk_ctx ctx, int32_t* keys, int32_t* shapes, int32_t cap,
+                              int32_t* n_out);
+
+/* -------------------------------------------------------------- profiling */
+
+/* Device time of each pipeline phase, measured with HIP events recorded on
+ * the stream each kernel is launched on (only while profiling is enabled). */
+typedef struct {
+  double tile_count_ms;  /* tile range query, count pass */
+  double plan_ms;        /* work plan (prefix sums) */
+  double tile_fill_ms;   /* tile range query, fill pass */
+  double eval_ms;        /* evaluation kernel (the hot loop) */
+  double build_ms;       /* tree build: bbox, keys, sort, leaves, boxes */
+  double knn_ms;         /* k-NN bandwidth kernel */
+  int64_t eval_launches;
+  int64_t builds;
+  int64_t last_total_leaves; /* candidate leaves of the last evaluated batch */
+  int64_t last_items;        /* work items of the last evaluated batch */
+} sfk_profile;
+
+sfk_status sfk_profile_enable(sfk_ctx ctx, int32_t on);
+/* Wait for the recorded events, add their durations into *out (totals since
+ * the last reset) and optionally reset. */
+sfk_status sfk_profile_read(sfk_ctx ctx, sfk_profile* out, int32_t reset);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -187,6 +187,14 @@ class Context:
             arr[i] = roi_struct(roi, o.data_ptr())
         self._check(self._lib.sfk_autotune(self._h, tree._h, arr, len(rois)))
 
+    def autotune_table(self) -> dict:
+        n = C.c_int32()
+        self._check(self._lib.sfk_autotune_table(self._h, None, None, 0, C.byref(n)))
+        keys = (C.c_int32 * max(1, n.value))()
+        shapes = (C.c_int32 * max(1, n.value))()
+        self._check(self._lib.sfk_autotune_table(self._h, keys, shapes, n.value, C.byref(n)))
+        return {keys[i]: shapes[i] for i in range(n.value)}
+
     def serve(self, tree: "Tree", arrivals: Sequence[float], rois: Sequence, outs: Sequence,
               mode: int = 0, n_slots: int = 4, max_batch: int = 64, budget_bytes: float = 0.0):
         """sfk_serve over a request trace; returns (per-request results, summary)."""
@@ -211,6 +219,15 @@ class Context:
                 and out.numel() == m):
             raise ValueError("out must be a contiguous float32 device tensor of %d values" % m)
         return out
+
+    # -- profiling
+    def profile_enable(self, on: bool = True):
+        self._check(self._lib.sfk_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = False) -> dict:
+        pr = L.Profile()
+        self._check(self._lib.sfk_profile_read(self._h, C.byref(pr), 1 if reset else 0))
+        return {name: getattr(pr, name) for name, _ in L.Profile._fields_}
 
     # -- test exports
     def debug_candidates(self, tree: "Tree", roi, node_begin: int, node_end: int):

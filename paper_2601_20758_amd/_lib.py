@@ -60,6 +60,13 @@ class ServeSummary(C.Structure):
                 ("budget_waits", C.c_int64)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("tile_count_ms", C.c_double), ("plan_ms", C.c_double),
+                ("tile_fill_ms", C.c_double), ("eval_ms", C.c_double), ("build_ms", C.c_double),
+                ("knn_ms", C.c_double), ("eval_launches", C.c_int64), ("builds", C.c_int64),
+                ("last_total_leaves", C.c_int64), ("last_items", C.c_int64)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "sfk_version": (C.c_char_p, []),
@@ -80,9 +87,13 @@ EXPORTS = {
     "sfk_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "sfk_set_eval_opts": (C.c_int, [C.c_void_p, C.POINTER(EvalOpts)]),
     "sfk_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_int32]),
+    "sfk_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.c_int32, C.POINTER(C.c_int32)]),
     "sfk_serve": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Request), C.c_int64,
                             C.POINTER(ServeOpts), C.POINTER(RequestResult),
                             C.POINTER(ServeSummary)]),
+    "sfk_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sfk_profile_read": (C.c_int, [C.c_void_p, C.POINTER(Profile), C.c_int32]),
     "sfk_debug_candidates": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_int64,
                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                        C.POINTER(C.c_int64)]),

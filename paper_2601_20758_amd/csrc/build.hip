@@ -418,14 +418,15 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 
 // ---------------------------------------------------------------------------
 // k-th nearest neighbour squared distance (per-point bandwidth).
-// One wavefront per leaf, one query particle per lane. Pass 1 takes the
-// k-th smallest distance among the leaf and its Morton neighbours as an
-// upper bound tau (those are real particles, so the true k-th distance is
-// <= tau); pass 2 walks the box hierarchy with the wavefront's largest tau
-// (a box whose canonical gap exceeds it cannot hold a closer particle) and
-// keeps the KM smallest squared distances per lane in a sorted register
-// array; the answer is its k-th entry. Exact: the same canonical float32
-// distances as the definition, selected without approximation.
+// One wavefront per leaf, one query particle per lane; each lane keeps its
+// KM smallest squared distances in a sorted register array and its current
+// k-th smallest as a threshold. Pass 1 scans the leaf and its Morton
+// neighbours, which bounds every lane's answer from above by real
+// distances. Pass 2 walks the box hierarchy with the wavefront's largest
+// threshold (a box farther than that cannot hold a closer particle) and,
+// per leaf, skips it unless some lane's own threshold exceeds that lane's
+// distance to the leaf box. Exact: the same canonical float32 distances as
+// the definition, selected without approximation.
 // ---------------------------------------------------------------------------
 
 template <int KM>
@@ -442,50 +443,74 @@ template <int KM>
 __global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restrict__ h2_sorted) {
   __shared__ float4 lds_pts[4][SFK_LEAF];
   __shared__ int32_t lds_stack[4][SFK_STACK];
+  __shared__ float lds_d2[4][16 * 64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   float4* lp = lds_pts[wave];
+  float* ld2 = lds_d2[wave];
   int32_t* stack = lds_stack[wave];
   const int nl = tv.n_leaves;
   for (int leaf = blockIdx.x * 4 + wave; leaf < nl; leaf += gridDim.x * 4) {
     const int64_t my = (int64_t)leaf * SFK_LEAF + lane;
     const float4 q = tv.pts[my];
     const bool real = my < tv.n;
+    // The first KM - k slots hold -inf and never move, so the last slot is
+    // always the k-th smallest distance seen (no runtime index into a).
     float a[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) a[i] = i < KM - k ? -__builtin_huge_valf() : __builtin_huge_valf();
+    float thr = __builtin_huge_valf();
 
+    auto kth = [&]() { return a[KM - 1]; };
+    // One candidate leaf: per sub-block of 16 candidates each lane marks the
+    // ones below its own threshold; the insertion network then runs once per
+    // round, a round inserting every lane's next marked candidate, so the
+    // wavefront pays max-over-lanes(marked) networks instead of one per
+    // candidate that any lane wants.
     auto process = [&](int cl) {
       lp[lane] = tv.pts[(int64_t)cl * SFK_LEAF + lane];
       wave_sync();
       const int64_t cbase = (int64_t)cl * SFK_LEAF;
-      for (int t = 0; t < SFK_LEAF; ++t) {
-        const float4 p = lp[t];
-        float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
-        if (cbase + t == my || !real) x = __builtin_huge_valf();
-        if (ballot(x < a[KM - 1])) knn_insert<KM>(a, x);
+      for (int t0 = 0; t0 < SFK_LEAF; t0 += 16) {
+        uint32_t mark = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const float4 p = lp[t0 + u];
+          float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
+          if (cbase + t0 + u == my || !real) x = __builtin_huge_valf();
+          ld2[u * 64 + lane] = x;
+          if (x < thr) mark |= 1u << u;
+        }
+        int rounds = __popc(mark);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off, 64));
+        if (rounds == 0) continue;
+        wave_sync();
+        for (int r = 0; r < rounds; ++r) {
+          float x = __builtin_huge_valf();
+          if (mark) {
+            const int u = __ffs(mark) - 1;
+            mark &= mark - 1;
+            x = ld2[u * 64 + lane];
+          }
+          // lanes with x >= thr only touch entries past the k-th: harmless
+          knn_insert<KM>(a, x);
+          thr = kth();
+        }
+        wave_sync();
       }
       wave_sync();
     };
-    auto kth = [&]() {
-      float v = a[0];
-#pragma unroll
-      for (int i = 0; i < KM; ++i)
-        if (i == k - 1) v = a[i];
-      return v;
-    };
 
-    // pass 1: Morton-neighbour window
-#pragma unroll
-    for (int i = 0; i < KM; ++i) a[i] = __builtin_huge_valf();
+    // pass 1: the leaf and its Morton neighbours
     int w0 = leaf - 1;
     if (w0 > nl - 3) w0 = nl - 3;
     if (w0 < 0) w0 = 0;
     const int w1 = min(nl - 1, w0 + 2);
     for (int cl = w0; cl <= w1; ++cl) process(cl);
-    const float tau = wave_max(real ? kth() : 0.0f);
+    const float tau = wave_max(real ? thr : 0.0f);
 
-    // pass 2: every leaf within tau of this leaf's box
+    // pass 2: the other leaves within tau of this leaf's box
     const NodeBox qb = tv.nodes[tv.level_off[0] + leaf];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) a[i] = __builtin_huge_valf();
     traverse(
         tv, stack,
         [&](const NodeBox& b, int g) {
@@ -496,12 +521,17 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restri
           (void)pass;
           uint64_t m = mask;
           while (m) {
-            const int b = __ffsll((unsigned long long)m) - 1;
+            const int bit = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            process(wave_bcast(child, b));
+            const int cl = wave_bcast(child, bit);
+            if (cl >= w0 && cl <= w1) continue;
+            const NodeBox lb = tv.nodes[tv.level_off[0] + cl];
+            const float gap = box_gap_d2(lb, q.x, q.y, q.z, q.x, q.y, q.z);
+            if (!ballot(real && gap < thr)) continue;
+            process(cl);
           }
         });
-    if (real) h2_sorted[my] = kth();
+    if (real) h2_sorted[my] = thr;
   }
 }
 

@@ -14,12 +14,11 @@
 // shuffles. Heavy tiles are split into chunks of leaves whose partial sums
 // are combined in a fixed order, so every grid is bitwise reproducible
 // whatever batch it runs in.
+#include <type_traits>
+
 #include "sfk_device.h"
 
 namespace sfk {
-
-// -log2(e)/2: exp(-u2/2) = exp2(KG * u2)
-#define SFK_KG (-0.72134752044448170368f)
 
 __device__ __forceinline__ int find_roi(const RoiDev* __restrict__ rois, int n_rois, int64_t t) {
   int lo = 0, hi = n_rois - 1;
@@ -36,12 +35,12 @@ __device__ __forceinline__ int find_roi(const RoiDev* __restrict__ rois, int n_r
 struct TileGeo {
   int r;
   int i0, j0, k0;
-  float lo[3], hi[3];
+  double lo[3], hi[3];
 };
 
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ TileGeo tile_geo(const RoiDev* __restrict__ rois, int n_rois,
-                                            const float* __restrict__ coords, int64_t t) {
+                                            const double* __restrict__ coords, int64_t t) {
   TileGeo g;
   g.r = find_roi(rois, n_rois, t);
   const RoiDev& R = rois[g.r];
@@ -55,9 +54,9 @@ __device__ __forceinline__ TileGeo tile_geo(const RoiDev* __restrict__ rois, int
   const int i1 = min(g.i0 + TX, R.res[0]) - 1;
   const int j1 = min(g.j0 + TY, R.res[1]) - 1;
   const int k1 = min(g.k0 + TZ, R.res[2]) - 1;
-  const float* cx = coords + R.coord_off;
-  const float* cy = cx + R.res[0];
-  const float* cz = cy + R.res[1];
+  const double* cx = coords + R.coord_off;
+  const double* cy = cx + R.res[0];
+  const double* cz = cy + R.res[1];
   g.lo[0] = cx[g.i0];
   g.hi[0] = cx[i1];
   g.lo[1] = cy[g.j0];
@@ -78,15 +77,15 @@ __device__ __forceinline__ bool tile_box_test(const TreeView& tv, const RoiDev& 
     ihz = m.z;
   }
   return box_gap_u2(b, g.lo[0], g.lo[1], g.lo[2], g.hi[0], g.hi[1], g.hi[2], ihx, ihy, ihz) <
-         R.c2;
+         (double)R.c2;
 }
 
 // ---------------------------------------------------------------------------
-// ROI coordinate tables: x_i = (float)(lo + (i*(hi-lo))/(res-1)) in double.
+// ROI coordinate tables: x_i = lo + (i*(hi-lo))/(res-1) in double.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_roi_coords(const RoiDev* __restrict__ rois, int n_rois,
-                                                    float* __restrict__ coords) {
+                                                    double* __restrict__ coords) {
   const RoiDev& R = rois[blockIdx.x];
   const int tot = R.res[0] + R.res[1] + R.res[2];
   for (int q = threadIdx.x; q < tot; q += blockDim.x) {
@@ -102,11 +101,11 @@ __global__ __launch_bounds__(256) void k_roi_coords(const RoiDev* __restrict__ r
     const double lo = R.lo[k], hi = R.hi[k];
     const double num = __dmul_rn((double)i, __dsub_rn(hi, lo));
     const double v = __dadd_rn(lo, __ddiv_rn(num, (double)(R.res[k] - 1)));
-    coords[R.coord_off + q] = (float)v;
+    coords[R.coord_off + q] = v;
   }
 }
 
-hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, float* coords, hipStream_t s) {
+hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, double* coords, hipStream_t s) {
   if (n_rois <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_roi_coords, dim3(n_rois), dim3(256), 0, s, rois, n_rois, coords);
   return hipGetLastError();
@@ -140,7 +139,7 @@ hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int
 
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const RoiDev* __restrict__ rois,
-                                                    int n_rois, const float* __restrict__ coords,
+                                                    int n_rois, const double* __restrict__ coords,
                                                     int64_t n_tiles, int32_t* __restrict__ tile_cnt,
                                                     int32_t* __restrict__ tile_done) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
@@ -166,7 +165,7 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const RoiDev* _
 
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_fill(
-    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const float* __restrict__ coords,
+    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const double* __restrict__ coords,
     int64_t n_tiles, const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
     const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
     int32_t* __restrict__ leaves, int32_t* __restrict__ item_tile) {
@@ -248,29 +247,46 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ ti
 // One split stage of the transposing reduction: lanes with bit OFF keep the
 // upper half of the live accumulators, the others the lower half; each adds
 // its partner's copy of the half it keeps.
-template <int N, int OFF, int T>
-__device__ __forceinline__ void xsplit(float (&acc)[T]) {
+template <int N, int OFF, typename A, int T>
+__device__ __forceinline__ void xsplit(A (&acc)[T]) {
   const bool up = (lane_id() & OFF) != 0;
 #pragma unroll
   for (int i = 0; i < N / 2; ++i) {
-    const float lo = acc[i], hi = acc[i + N / 2];
-    const float send = up ? lo : hi;
-    const float keep = up ? hi : lo;
-    acc[i] = __fadd_rn(keep, __shfl_xor(send, OFF, 64));
+    const A lo = acc[i], hi = acc[i + N / 2];
+    const A send = up ? lo : hi;
+    const A keep = up ? hi : lo;
+    acc[i] = keep + __shfl_xor(send, OFF, 64);
   }
 }
 
-template <int OFF, int T>
-__device__ __forceinline__ void xfold(float (&acc)[T]) {
+template <int OFF, typename A, int T>
+__device__ __forceinline__ void xfold(A (&acc)[T]) {
 #pragma unroll
-  for (int i = 0; i < T; ++i) acc[i] = __fadd_rn(acc[i], __shfl_xor(acc[i], OFF, 64));
+  for (int i = 0; i < T; ++i) acc[i] = acc[i] + __shfl_xor(acc[i], OFF, 64);
+}
+
+template <int OFF, typename A, int T>
+__device__ __forceinline__ void fold_down(A (&acc)[T]) {
+  if constexpr (OFF >= T && OFF >= 1) {
+    xfold<OFF>(acc);
+    fold_down<OFF / 2>(acc);
+  }
+}
+
+template <int N, typename A, int T>
+__device__ __forceinline__ void split_down(A (&acc)[T]) {
+  if constexpr (N >= 2) {
+    xsplit<N, N / 2>(acc);
+    split_down<N / 2>(acc);
+  }
 }
 
 // Reduce T per-lane accumulators over the 64 lanes. Afterwards lane l holds
-// node (l * NPL + m) in acc[m] for m < NPL = max(1, T/64) (for T < 64, lanes
-// l and l + T hold the same node l mod T).
-template <int T>
-__device__ __forceinline__ void reduce_nodes(float (&acc)[T]) {
+// node (l * NPL + m) in acc[m] for m < NPL = max(1, T/64); for T < 64 the
+// lanes first fold in halves down to T lanes' worth, so lane l holds node
+// l mod T. Fixed order: deterministic.
+template <typename A, int T>
+__device__ __forceinline__ void reduce_nodes(A (&acc)[T]) {
   if constexpr (T >= 64) {
     xsplit<T, 32>(acc);
     xsplit<T / 2, 16>(acc);
@@ -278,27 +294,34 @@ __device__ __forceinline__ void reduce_nodes(float (&acc)[T]) {
     xsplit<T / 8, 4>(acc);
     xsplit<T / 16, 2>(acc);
     xsplit<T / 32, 1>(acc);
-  } else if constexpr (T == 32) {
-    xfold<32>(acc);
-    xsplit<32, 16>(acc);
-    xsplit<16, 8>(acc);
-    xsplit<8, 4>(acc);
-    xsplit<4, 2>(acc);
-    xsplit<2, 1>(acc);
+  } else {
+    fold_down<32>(acc);
+    split_down<T>(acc);
   }
 }
 
+// -log2(e)/2 in double: exp(-u2/2) = exp2(KG * u2)
+#define SFK_KG64 (-0.72134752044448170368)
+
+// The evaluation kernel. Template parameters: tile shape (TX, TY, TZ), kernel
+// (Epanechnikov / truncated Gaussian), bandwidth source (uniform, per-particle
+// isotropic, per-particle anisotropic) and counting mode. Membership and the
+// Epanechnikov value are double (same rate as unpacked float32 on gfx950);
+// the Gaussian factors are float32 exp2 of the double exponents.
 template <int TX, int TY, int TZ, int KK, int PP, bool CNT>
 __global__ __launch_bounds__(256) void k_eval(
-    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const float* __restrict__ coords,
+    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const double* __restrict__ coords,
     int chunk_leaves, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
     const int64_t* __restrict__ partial_off, const int32_t* __restrict__ tile_cnt,
     const int32_t* __restrict__ tile_fit, const int32_t* __restrict__ leaves,
-    const int32_t* __restrict__ item_tile, float* __restrict__ partials,
+    const int32_t* __restrict__ item_tile, double* __restrict__ partials,
     int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr) {
   constexpr int T = TX * TY * TZ;
   constexpr int NPL = T >= 64 ? T / 64 : 1;
+  using Acc = typename std::conditional<(KK == KK_EPAN && !CNT), double, float>::type;
   __shared__ int32_t lds_stack[4][SFK_STACK];
+  __shared__ float4 lds_qpts[4][128];
+  __shared__ float4 lds_qprm[4][PP == PP_ANISO ? 128 : 1];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_items = hdr->n_items;
   while (true) {
@@ -309,10 +332,10 @@ __global__ __launch_bounds__(256) void k_eval(
     const int t = item_tile[item];
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
-    const float* cx = coords + R.coord_off;
-    const float* cy = cx + R.res[0];
-    const float* cz = cy + R.res[1];
-    float nx[TX], ny[TY], nz[TZ];
+    const double* cx = coords + R.coord_off;
+    const double* cy = cx + R.res[0];
+    const double* cz = cy + R.res[1];
+    double nx[TX], ny[TY], nz[TZ];
 #pragma unroll
     for (int i = 0; i < TX; ++i) nx[i] = cx[min(g.i0 + i, R.res[0] - 1)];
 #pragma unroll
@@ -320,57 +343,67 @@ __global__ __launch_bounds__(256) void k_eval(
 #pragma unroll
     for (int k = 0; k < TZ; ++k) nz[k] = cz[min(g.k0 + k, R.res[2] - 1)];
     const float uih0 = R.ih[0], uih1 = R.ih[1], uih2 = R.ih[2];
-    const float c2 = R.c2;
+    const double c2 = R.c2;
     const int cnt = tile_cnt[t];
     const int nch = cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
 
-    float acc[T];
+    Acc acc[T];
 #pragma unroll
-    for (int q = 0; q < T; ++q) acc[q] = 0.0f;
+    for (int q = 0; q < T; ++q) acc[q] = (Acc)0;
 
-    auto eval_leaf = [&](int lid) {
-      const int64_t slot = (int64_t)lid * SFK_LEAF + lane;
-      const float4 p = tv.pts[slot];
-      float ihx, ihy, ihz, w = 1.0f;
+    // Per-wave queue of particles whose support reaches the tile box. Each
+    // leaf is loaded one particle per lane and culled against the tile with
+    // the same monotone-rounding bound as the tree walk (a culled particle
+    // would only add exact zeros); survivors are appended in leaf-then-lane
+    // order and evaluated 64 at a time, so lanes stay busy with particles
+    // that can matter. The order is fixed, hence so are the sums.
+    float4* qp = lds_qpts[wave];
+    float4* qa = lds_qprm[wave];
+    int qn = 0;
+
+    auto eval_point = [&](const float4 p, const float4 prm) {
+      float ihx, ihy, ihz;
+      double w = 1.0;
       if constexpr (PP == PP_UNIFORM) {
         ihx = uih0;
         ihy = uih1;
         ihz = uih2;
       } else if constexpr (PP == PP_ISO) {
         ihx = ihy = ihz = p.w;
-        w = __fmul_rn(__fmul_rn(p.w, p.w), p.w);
+        const double ih = (double)p.w;
+        w = (ih * ih) * ih;
       } else {
-        const float4 q = tv.pparam[slot];
-        ihx = q.x;
-        ihy = q.y;
-        ihz = q.z;
-        w = q.w;
+        ihx = prm.x;
+        ihy = prm.y;
+        ihz = prm.z;
+        w = (double)prm.w;
       }
-      float sx[TX], sy[TY], sz[TZ];
+      const double px = p.x, py = p.y, pz = p.z;
+      double sx[TX], sy[TY], sz[TZ];
 #pragma unroll
       for (int i = 0; i < TX; ++i) {
-        const float u = __fmul_rn(__fsub_rn(nx[i], p.x), ihx);
-        sx[i] = __fmul_rn(u, u);
+        const double u = (nx[i] - px) * (double)ihx;
+        sx[i] = u * u;
       }
 #pragma unroll
       for (int j = 0; j < TY; ++j) {
-        const float u = __fmul_rn(__fsub_rn(ny[j], p.y), ihy);
-        sy[j] = __fmul_rn(u, u);
+        const double u = (ny[j] - py) * (double)ihy;
+        sy[j] = u * u;
       }
 #pragma unroll
       for (int k = 0; k < TZ; ++k) {
-        const float u = __fmul_rn(__fsub_rn(nz[k], p.z), ihz);
-        sz[k] = __fmul_rn(u, u);
+        const double u = (nz[k] - pz) * (double)ihz;
+        sz[k] = u * u;
       }
       if constexpr (CNT) {
 #pragma unroll
         for (int j = 0; j < TY; ++j)
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
-            const float tt = __fadd_rn(sx[i], sy[j]);
+            const double tt = sx[i] + sy[j];
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
-              const float u2 = __fadd_rn(tt, sz[k]);
+              const double u2 = tt + sz[k];
               acc[i + TX * (j + TY * k)] += (u2 < c2) ? 1.0f : 0.0f;
             }
           }
@@ -379,51 +412,113 @@ __global__ __launch_bounds__(256) void k_eval(
         for (int j = 0; j < TY; ++j)
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
-            const float tt = __fadd_rn(sx[i], sy[j]);
+            const double tt = sx[i] + sy[j];
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
-              const float u2 = __fadd_rn(tt, sz[k]);
-              const float v = fmaxf(__fsub_rn(1.0f, u2), 0.0f);
-              float& a = acc[i + TX * (j + TY * k)];
+              const double u2 = tt + sz[k];
+              const double v = fmax(1.0 - u2, 0.0);
+              Acc& a = acc[i + TX * (j + TY * k)];
               if constexpr (PP == PP_UNIFORM)
-                a = __fadd_rn(a, v);
+                a = a + v;
               else
-                a = __fmaf_rn(w, v, a);
+                a = fma(w, v, a);
             }
           }
       } else {
         float ex[TX], ey[TY], ez[TZ];
+        const float wf = (float)w;
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
-          ex[i] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sx[i]));
-          if constexpr (PP != PP_UNIFORM) ex[i] = __fmul_rn(ex[i], w);
+          ex[i] = __builtin_amdgcn_exp2f((float)(SFK_KG64 * sx[i]));
+          if constexpr (PP != PP_UNIFORM) ex[i] = ex[i] * wf;
         }
 #pragma unroll
-        for (int j = 0; j < TY; ++j) ey[j] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sy[j]));
+        for (int j = 0; j < TY; ++j) ey[j] = __builtin_amdgcn_exp2f((float)(SFK_KG64 * sy[j]));
 #pragma unroll
-        for (int k = 0; k < TZ; ++k) ez[k] = __builtin_amdgcn_exp2f(__fmul_rn(SFK_KG, sz[k]));
+        for (int k = 0; k < TZ; ++k) ez[k] = __builtin_amdgcn_exp2f((float)(SFK_KG64 * sz[k]));
 #pragma unroll
         for (int j = 0; j < TY; ++j)
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
-            const float tt = __fadd_rn(sx[i], sy[j]);
-            const float exy = __fmul_rn(ex[i], ey[j]);
+            const double tt = sx[i] + sy[j];
+            const float exy = ex[i] * ey[j];
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
-              const float u2 = __fadd_rn(tt, sz[k]);
-              const float e = __fmul_rn(exy, ez[k]);
-              float& a = acc[i + TX * (j + TY * k)];
-              a = __fadd_rn(a, (u2 < c2) ? e : 0.0f);
+              const double u2 = tt + sz[k];
+              const float e = exy * ez[k];
+              Acc& a = acc[i + TX * (j + TY * k)];
+              a = a + ((u2 < c2) ? e : 0.0f);
             }
           }
       }
     };
 
-    auto node_out = [&](int node, float v) {
+    // evaluate queue entries [0, 64) and move the rest to the front
+    auto drain64 = [&]() {
+      const float4 p = qp[lane];
+      float4 prm = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (PP == PP_ANISO) prm = qa[lane];
+      if (lane + 64 < qn) {
+        qp[lane] = qp[lane + 64];
+        if constexpr (PP == PP_ANISO) qa[lane] = qa[lane + 64];
+      }
+      qn -= 64;
+      wave_sync();
+      eval_point(p, prm);
+    };
+    // evaluate what is left (lanes past the end take a far dummy particle)
+    auto drain_rest = [&]() {
+      if (qn == 0) return;
+      float4 p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 1.0f);
+      float4 prm = make_float4(1.f, 1.f, 1.f, 0.f);
+      if (lane < qn) {
+        p = qp[lane];
+        if constexpr (PP == PP_ANISO) prm = qa[lane];
+      }
+      qn = 0;
+      wave_sync();
+      eval_point(p, prm);
+    };
+
+    auto eval_leaf = [&](int lid) {
+      const int64_t slot = (int64_t)lid * SFK_LEAF + lane;
+      const float4 p = tv.pts[slot];
+      float4 prm = make_float4(0.f, 0.f, 0.f, 0.f);
+      float ihx = uih0, ihy = uih1, ihz = uih2;
+      if constexpr (PP == PP_ISO) {
+        ihx = ihy = ihz = p.w;
+      } else if constexpr (PP == PP_ANISO) {
+        prm = tv.pparam[slot];
+        ihx = prm.x;
+        ihy = prm.y;
+        ihz = prm.z;
+      }
+      const double px = p.x, py = p.y, pz = p.z;
+      const double gx = fmax(fmax(g.lo[0] - px, px - g.hi[0]), 0.0);
+      const double gy = fmax(fmax(g.lo[1] - py, py - g.hi[1]), 0.0);
+      const double gz = fmax(fmax(g.lo[2] - pz, pz - g.hi[2]), 0.0);
+      const double ux = gx * (double)ihx, uy = gy * (double)ihy, uz = gz * (double)ihz;
+      const bool keep = ((ux * ux + uy * uy) + uz * uz) < c2;
+      const uint64_t m = ballot(keep);
+      if (keep) {
+        const int pos = qn + popc64(m & lanemask_lt());
+        qp[pos] = p;
+        if constexpr (PP == PP_ANISO) qa[pos] = prm;
+      }
+      qn += popc64(m);
+      wave_sync();
+      if (qn >= 64) drain64();
+    };
+    auto end_chunk = [&]() {
+      drain_rest();
+      reduce_nodes(acc);
+    };
+
+    auto node_out = [&](int node, double v) {
       const int i = node % TX, j = (node / TX) % TY, k = node / (TX * TY);
       const int gi = g.i0 + i, gj = g.j0 + j, gk = g.k0 + k;
       if (gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
-        R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = v;
+        R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = (float)v;
     };
     auto lane_node = [&](int m) { return T >= 64 ? lane * NPL + m : (lane & (T - 1)); };
     const bool lane_writes = T >= 64 || lane < T;
@@ -433,17 +528,17 @@ __global__ __launch_bounds__(256) void k_eval(
       const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
       const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
       for (int64_t l = lb; l < le; ++l) eval_leaf(leaves[l]);
-      reduce_nodes<T>(acc);
+      end_chunk();
       if (nch == 1) {
         if (lane_writes) {
 #pragma unroll
-          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), __fmul_rn(acc[m], R.scale));
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), (double)acc[m] * R.scale);
         }
       } else {
         const int64_t pbase = (partial_off[t] + c) * T;
         if (lane_writes) {
 #pragma unroll
-          for (int m = 0; m < NPL; ++m) partials[pbase + lane_node(m)] = acc[m];
+          for (int m = 0; m < NPL; ++m) partials[pbase + lane_node(m)] = (double)acc[m];
         }
         __threadfence();
         int prev = 0;
@@ -458,9 +553,9 @@ __global__ __launch_bounds__(256) void k_eval(
               const int node = lane_node(m);
               double s = 0.0;
               for (int cc = 0; cc < nch; ++cc)
-                s += (double)__hip_atomic_load(&partials[p0 + (int64_t)cc * T + node],
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              node_out(node, (float)(s * (double)R.scale));
+                s += __hip_atomic_load(&partials[p0 + (int64_t)cc * T + node], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+              node_out(node, s * R.scale);
             }
           }
         }
@@ -484,30 +579,29 @@ __global__ __launch_bounds__(256) void k_eval(
               eval_leaf(__shfl(child, b, 64));
               ++done;
               if (nch > 1 && done % chunk_leaves == 0) {
-                reduce_nodes<T>(acc);
+                end_chunk();
 #pragma unroll
                 for (int m = 0; m < NPL; ++m) dacc[m] += (double)acc[m];
 #pragma unroll
-                for (int q = 0; q < T; ++q) acc[q] = 0.0f;
+                for (int q = 0; q < T; ++q) acc[q] = (Acc)0;
               }
             }
           });
       if (nch == 1) {
-        reduce_nodes<T>(acc);
+        end_chunk();
         if (lane_writes) {
 #pragma unroll
-          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), __fmul_rn(acc[m], R.scale));
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), (double)acc[m] * R.scale);
         }
       } else {
         if (done % chunk_leaves != 0) {
-          reduce_nodes<T>(acc);
+          end_chunk();
 #pragma unroll
           for (int m = 0; m < NPL; ++m) dacc[m] += (double)acc[m];
         }
         if (lane_writes) {
 #pragma unroll
-          for (int m = 0; m < NPL; ++m)
-            node_out(lane_node(m), (float)(dacc[m] * (double)R.scale));
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), dacc[m] * R.scale);
         }
       }
     }
@@ -521,7 +615,7 @@ __global__ __launch_bounds__(256) void k_eval(
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int32_t* __restrict__ perm,
                                                           const RoiDev* __restrict__ rois,
-                                                          const float* __restrict__ coords,
+                                                          const double* __restrict__ coords,
                                                           int64_t node_begin, int64_t node_end,
                                                           int64_t* __restrict__ cnt_out,
                                                           const int64_t* __restrict__ off,
@@ -529,9 +623,9 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const RoiDev& R = rois[0];
-  const float* cx = coords + R.coord_off;
-  const float* cy = cx + R.res[0];
-  const float* cz = cy + R.res[1];
+  const double* cx = coords + R.coord_off;
+  const double* cy = cx + R.res[0];
+  const double* cz = cy + R.res[1];
   for (int64_t nd = node_begin + (int64_t)blockIdx.x * 4 + wave; nd < node_end;
        nd += (int64_t)gridDim.x * 4) {
     const int ix = (int)(nd % R.res[0]);
@@ -540,7 +634,7 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
     const int64_t t = (int64_t)(ix / TX) +
                       (int64_t)R.ntile[0] * ((int64_t)(iy / TY) + (int64_t)R.ntile[1] * (iz / TZ));
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, 1, coords, t);
-    const float xn = cx[ix], yn = cy[iy], zn = cz[iz];
+    const double xn = cx[ix], yn = cy[iy], zn = cz[iz];
     int64_t c = 0;
     int32_t* out = off ? idx_out + off[nd - node_begin] : nullptr;
     traverse(
@@ -564,7 +658,8 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
               ihy = q.y;
               ihz = q.z;
             }
-            const bool mem = slot < tv.n && canon_u2(xn, yn, zn, p.x, p.y, p.z, ihx, ihy, ihz) < R.c2;
+            const bool mem =
+                slot < tv.n && canon_u2(xn, yn, zn, p.x, p.y, p.z, ihx, ihy, ihz) < (double)R.c2;
             const uint64_t mb = ballot(mem);
             if (out && mem) out[c + popc64(mb & lanemask_lt())] = perm[slot];
             c += popc64(mb);
@@ -579,18 +674,20 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
 // ---------------------------------------------------------------------------
 
 bool tile_shape_supported(TileShape ts) {
-  return (ts.tx == 4 && ts.ty == 4 && ts.tz == 4) || (ts.tx == 8 && ts.ty == 4 && ts.tz == 4) ||
-         (ts.tx == 4 && ts.ty == 4 && ts.tz == 2);
+  return (ts.tx == 4 && ts.ty == 4 && (ts.tz == 4 || ts.tz == 2)) ||
+         (ts.tx == 4 && ts.ty == 2 && ts.tz == 2) || (ts.tx == 2 && ts.ty == 2 && ts.tz == 2);
 }
 
 #define SFK_SHAPE_SWITCH(ts, MACRO)                                  \
   do {                                                               \
     if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 4) {              \
       MACRO(4, 4, 4);                                                \
-    } else if ((ts).tx == 8 && (ts).ty == 4 && (ts).tz == 4) {       \
-      MACRO(8, 4, 4);                                                \
     } else if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 2) {       \
       MACRO(4, 4, 2);                                                \
+    } else if ((ts).tx == 4 && (ts).ty == 2 && (ts).tz == 2) {       \
+      MACRO(4, 2, 2);                                                \
+    } else if ((ts).tx == 2 && (ts).ty == 2 && (ts).tz == 2) {       \
+      MACRO(2, 2, 2);                                                \
     } else {                                                         \
       return hipErrorInvalidValue;                                   \
     }                                                                \
@@ -601,7 +698,7 @@ static int grid_for(int64_t waves) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
 }
 
-hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                              TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
                              int32_t* tile_nch, int32_t* tile_done, hipStream_t s) {
   (void)chunk_leaves;
@@ -624,7 +721,7 @@ hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leave
   return hipGetLastError();
 }
 
-hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                              TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
                              const int32_t* tile_fit, const int64_t* leaf_off,
                              const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
@@ -640,18 +737,29 @@ hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const 
 }
 
 template <int X, int Y, int Z>
-static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, hipStream_t s,
+static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu, hipStream_t s,
                                     TreeView tv, const RoiDev* rois, int n_rois,
-                                    const float* coords, int chunk_leaves,
+                                    const double* coords, int chunk_leaves,
                                     const int64_t* leaf_off, const int64_t* chunk_off,
                                     const int64_t* partial_off, const int32_t* tile_cnt,
                                     const int32_t* tile_fit, const int32_t* leaves,
-                                    const int32_t* item_tile, float* partials,
+                                    const int32_t* item_tile, double* partials,
                                     int32_t* tile_done, BatchHdr* hdr) {
 #define SFK_E(KK, PP, C)                                                                       \
-  hipLaunchKernelGGL((k_eval<X, Y, Z, KK, PP, C>), dim3(grid), dim3(256), 0, s, tv, rois,     \
-                     n_rois, coords, chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, \
-                     tile_fit, leaves, item_tile, partials, tile_done, hdr)
+  do {                                                                                         \
+    static int occ_ = 0;                                                                       \
+    if (occ_ == 0) {                                                                           \
+      int b_ = 0;                                                                              \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b_, k_eval<X, Y, Z, KK, PP, C>, 256,   \
+                                                       0) != hipSuccess || b_ < 1)             \
+        b_ = 1;                                                                                \
+      occ_ = b_;                                                                               \
+    }                                                                                          \
+    const int g_ = grid > 0 ? grid : n_cu * occ_;                                              \
+    hipLaunchKernelGGL((k_eval<X, Y, Z, KK, PP, C>), dim3(g_), dim3(256), 0, s, tv, rois,      \
+                       n_rois, coords, chunk_leaves, leaf_off, chunk_off, partial_off,         \
+                       tile_cnt, tile_fit, leaves, item_tile, partials, tile_done, hdr);       \
+  } while (0)
   if (cnt) {
     if (pp == PP_UNIFORM) SFK_E(KK_EPAN, PP_UNIFORM, true);
     else if (pp == PP_ISO) SFK_E(KK_EPAN, PP_ISO, true);
@@ -669,15 +777,16 @@ static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                         TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
                         const int64_t* leaf_off, const int64_t* chunk_off,
                         const int64_t* partial_off, const int32_t* tile_cnt,
                         const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                        float* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                        hipStream_t s) {
+                        double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                        int n_cu, hipStream_t s) {
 #define SFK_L(X, Y, Z)                                                                          \
-  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, s, tv, rois, n_rois, coords,     \
+  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, s, tv, rois, n_rois,      \
+                                    coords,                                                     \
                                     chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt,  \
                                     tile_fit, leaves, item_tile, partials, tile_done, hdr)
   SFK_SHAPE_SWITCH(ts, SFK_L);
@@ -686,7 +795,7 @@ hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const float
 }
 
 hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
-                                    const float* coords, TileShape ts, int64_t node_begin,
+                                    const double* coords, TileShape ts, int64_t node_begin,
                                     int64_t node_end, int64_t* cnt, const int64_t* off,
                                     int32_t* idx_out, hipStream_t s) {
   const int64_t nn = node_end - node_begin;

@@ -87,29 +87,33 @@ __device__ __forceinline__ float canon_d2(float ax, float ay, float az, float bx
   return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
-// Canonical float32 squared scaled distance of a node to a particle.
-__device__ __forceinline__ float canon_u2(float nx, float ny, float nz, float px, float py,
-                                          float pz, float ihx, float ihy, float ihz) {
-  float ux = __fmul_rn(__fsub_rn(nx, px), ihx);
-  float uy = __fmul_rn(__fsub_rn(ny, py), ihy);
-  float uz = __fmul_rn(__fsub_rn(nz, pz), ihz);
-  return __fadd_rn(__fadd_rn(__fmul_rn(ux, ux), __fmul_rn(uy, uy)), __fmul_rn(uz, uz));
+// Canonical squared scaled distance of a node to a particle: double
+// operations on the float32 particle and inverse-bandwidth values, every
+// operation rounded, no contraction (the library is built with
+// -ffp-contract=off): u_k = (x_nk - p_k) * ih_k, u2 = (ux^2 + uy^2) + uz^2.
+__device__ __forceinline__ double canon_u2(double nx, double ny, double nz, float px, float py,
+                                           float pz, float ihx, float ihy, float ihz) {
+  const double ux = (nx - (double)px) * (double)ihx;
+  const double uy = (ny - (double)py) * (double)ihy;
+  const double uz = (nz - (double)pz) * (double)ihz;
+  return (ux * ux + uy * uy) + uz * uz;
 }
 
 // Lower bound of the canonical scaled distance between any node of box
 // [tlo, thi] and any particle of box b with inverse bandwidths >= ih: the
 // per-axis gap, rounded the same way as the per-pair arithmetic, so by
 // monotonicity of rounding no member can lie in a box that fails this test.
-__device__ __forceinline__ float box_gap_u2(const NodeBox& b, float tlx, float tly, float tlz,
-                                            float thx, float thy, float thz, float ihx,
-                                            float ihy, float ihz) {
-  float gx = fmaxf(fmaxf(__fsub_rn(b.lo[0], thx), __fsub_rn(tlx, b.hi[0])), 0.0f);
-  float gy = fmaxf(fmaxf(__fsub_rn(b.lo[1], thy), __fsub_rn(tly, b.hi[1])), 0.0f);
-  float gz = fmaxf(fmaxf(__fsub_rn(b.lo[2], thz), __fsub_rn(tlz, b.hi[2])), 0.0f);
-  float ux = __fmul_rn(gx, ihx), uy = __fmul_rn(gy, ihy), uz = __fmul_rn(gz, ihz);
-  return __fadd_rn(__fadd_rn(__fmul_rn(ux, ux), __fmul_rn(uy, uy)), __fmul_rn(uz, uz));
+__device__ __forceinline__ double box_gap_u2(const NodeBox& b, double tlx, double tly,
+                                             double tlz, double thx, double thy, double thz,
+                                             float ihx, float ihy, float ihz) {
+  const double gx = fmax(fmax((double)b.lo[0] - thx, tlx - (double)b.hi[0]), 0.0);
+  const double gy = fmax(fmax((double)b.lo[1] - thy, tly - (double)b.hi[1]), 0.0);
+  const double gz = fmax(fmax((double)b.lo[2] - thz, tlz - (double)b.hi[2]), 0.0);
+  const double ux = gx * (double)ihx, uy = gy * (double)ihy, uz = gz * (double)ihz;
+  return (ux * ux + uy * uy) + uz * uz;
 }
 
+// float32 canonical squared distance lower bound (k-NN selection).
 __device__ __forceinline__ float box_gap_d2(const NodeBox& b, float tlx, float tly, float tlz,
                                             float thx, float thy, float thz) {
   float gx = fmaxf(fmaxf(__fsub_rn(b.lo[0], thx), __fsub_rn(tlx, b.hi[0])), 0.0f);

@@ -49,7 +49,7 @@ struct alignas(16) RoiDev {
   int64_t tile_base;     // global index of the ROI's first tile
   float ih[3];           // uniform inverse bandwidth (PP_UNIFORM)
   float c2;              // support threshold on u2 (1 or 9)
-  float scale;           // final multiplier C_K * nu (* w for a uniform bandwidth)
+  double scale;          // final multiplier C_K * nu (* w for a uniform bandwidth)
   int32_t kernel;        // KernelKind
   int32_t count_mode;    // 1: accumulate support counts instead of density
   int32_t coord_off;     // into the batch coordinate table: x, then y, then z
@@ -111,29 +111,29 @@ hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hip
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
 // eval.hip
-hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, float* coords, hipStream_t s);
+hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, double* coords, hipStream_t s);
 hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap,
                            hipStream_t s);
-hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                              TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
                              int32_t* tile_nch, int32_t* tile_done, hipStream_t s);
 hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leaves, int64_t leaf_cap,
                        int64_t partial_cap, int64_t* leaf_off, int64_t* partial_off,
                        int64_t* chunk_off, int32_t* tile_fit, BatchHdr* hdr, hipStream_t s);
-hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                              TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
                              const int32_t* tile_fit, const int64_t* leaf_off,
                              const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
                              hipStream_t s);
-hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const float* coords,
+hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
                         TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
                         const int64_t* leaf_off, const int64_t* chunk_off,
                         const int64_t* partial_off, const int32_t* tile_cnt,
                         const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                        float* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                        hipStream_t s);
+                        double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                        int n_cu, hipStream_t s);
 hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
-                                    const float* coords, TileShape ts, int64_t node_begin,
+                                    const double* coords, TileShape ts, int64_t node_begin,
                                     int64_t node_end, int64_t* cnt, const int64_t* off,
                                     int32_t* idx_out, hipStream_t s);
 bool tile_shape_supported(TileShape ts);

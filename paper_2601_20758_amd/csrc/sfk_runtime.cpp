@@ -18,6 +18,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sfk_internal.h"
@@ -54,6 +55,9 @@ struct Workspace {
       item_tile, partials, hdr;
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
+  // last enqueued use of the buffers: a buffer that must grow waits for it
+  hipEvent_t last_use = nullptr;
+  bool last_use_valid = false;
 };
 
 struct Staging {
@@ -82,8 +86,21 @@ struct Ticket {
   sfk_status status = SFK_OK;
 };
 
+enum ProfKind { PK_TILE_COUNT = 0, PK_PLAN, PK_TILE_FILL, PK_EVAL, PK_BUILD, PK_KNN, PK_N };
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  BatchHdr* hdr_dev;  // eval records: header to read totals from (may be null)
+};
+
 struct sfk_ctx_s {
   int device = 0;
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[PK_N] = {0};
+  int64_t prof_evals = 0, prof_builds = 0, prof_last_leaves = 0, prof_last_items = 0;
   sfk_allocator alloc{};
   bool use_alloc = false;
   size_t budget = 0;
@@ -159,6 +176,41 @@ void set_err(sfk_ctx c, const char* fmt, ...) {
     return SFK_E_INTERNAL;                                 \
   }
 
+// ---- profiling events ----
+
+hipEvent_t prof_event(sfk_ctx c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a phase (no-op unless profiling).
+struct ProfScope {
+  sfk_ctx c;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  BatchHdr* hdr;
+  ProfScope(sfk_ctx cc, int k, hipStream_t ss, BatchHdr* h = nullptr) : c(cc), kind(k), s(ss), hdr(h) {
+    if (c->prof_on) {
+      a = prof_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_pending.push_back(ProfRec{kind, a, b, hdr});
+  }
+};
+
 // ---- device memory through the context's allocator ----
 
 void raw_free(sfk_ctx c, void* p, size_t bytes) {
@@ -181,10 +233,12 @@ void* raw_alloc(sfk_ctx c, size_t bytes) {
 
 size_t round_bytes(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Grow-only workspace buffer (the caller guarantees the old contents are idle).
-sfk_status ws_reserve(sfk_ctx c, DevBuf& b, size_t bytes, const char* what) {
+// Grow-only workspace buffer; before replacing a buffer it waits for the
+// workspace's last enqueued use.
+sfk_status ws_reserve(sfk_ctx c, Workspace& ws, DevBuf& b, size_t bytes, const char* what) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return SFK_OK;
+  if (ws.last_use_valid) SFK_HIP(c, hipEventSynchronize(ws.last_use));
   size_t nb = round_bytes(std::max(bytes, b.bytes + b.bytes / 4));
   if (c->budget && c->ws_bytes - b.bytes + nb > c->budget) {
     nb = round_bytes(bytes);
@@ -287,8 +341,9 @@ double ck_gauss_trunc3() {
 
 TileShape shape_of(int id) {
   switch (id) {
-    case 2: return TileShape{8, 4, 4};
-    case 3: return TileShape{4, 4, 2};
+    case 2: return TileShape{4, 4, 2};
+    case 3: return TileShape{4, 2, 2};
+    case 4: return TileShape{2, 2, 2};
     default: return TileShape{4, 4, 4};
   }
 }
@@ -445,17 +500,11 @@ struct GroupRoi {
   bool count_mode;
   float ih[3];
   float c2;
-  float scale;
+  double scale;
 };
 
 int chunk_leaves_of(sfk_ctx c) {
   return c->opts.chunk_leaves > 0 ? c->opts.chunk_leaves : kDefaultChunkLeaves;
-}
-
-int blocks_per_cu(sfk_ctx c, TileShape ts) {
-  if (c->opts.persistent_waves_per_cu > 0) return std::max(1, c->opts.persistent_waves_per_cu / 4);
-  const int T = ts.tx * ts.ty * ts.tz;
-  return T > 64 ? 2 : 3;
 }
 
 // Fill RoiDev descriptors for rois[0..n) and the per-group tile total.
@@ -494,7 +543,7 @@ void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int6
 // copy of `rd` (already enqueued). The workspace must be idle or only used
 // earlier on the same stream.
 sfk_status launch_group(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
-                        const RoiDev* rois_dev, int n_rois, int64_t n_tiles, const float* coords,
+                        const RoiDev* rois_dev, int n_rois, int64_t n_tiles, const double* coords,
                         Workspace& ws, hipStream_t s) {
   const int CH = chunk_leaves_of(c);
   const int T = ts.tx * ts.ty * ts.tz;
@@ -502,22 +551,22 @@ sfk_status launch_group(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int
   int64_t partial_cap = std::max<int64_t>(ws.want_partial_cap, std::max<int64_t>(1 << 14, n_tiles / 4));
   leaf_cap = std::max<int64_t>(leaf_cap, (int64_t)(ws.leaves.bytes / sizeof(int32_t)));
   partial_cap =
-      std::max<int64_t>(partial_cap, (int64_t)(ws.partials.bytes / (sizeof(float) * (size_t)T)));
+      std::max<int64_t>(partial_cap, (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T)));
   if (c->opts.list_capacity > 0) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
   }
   const int64_t item_cap = n_tiles + leaf_cap / CH + 1;
-  SFK_TRY(ws_reserve(c, ws.tile_cnt, sizeof(int32_t) * (size_t)n_tiles, "tile counts"));
-  SFK_TRY(ws_reserve(c, ws.tile_fit, sizeof(int32_t) * (size_t)n_tiles, "tile flags"));
-  SFK_TRY(ws_reserve(c, ws.tile_done, sizeof(int32_t) * (size_t)n_tiles, "tile counters"));
-  SFK_TRY(ws_reserve(c, ws.leaf_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "leaf offsets"));
-  SFK_TRY(ws_reserve(c, ws.partial_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "partial offsets"));
-  SFK_TRY(ws_reserve(c, ws.chunk_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "item offsets"));
-  SFK_TRY(ws_reserve(c, ws.leaves, sizeof(int32_t) * (size_t)leaf_cap, "leaf lists"));
-  SFK_TRY(ws_reserve(c, ws.item_tile, sizeof(int32_t) * (size_t)item_cap, "work items"));
-  SFK_TRY(ws_reserve(c, ws.partials, sizeof(float) * (size_t)partial_cap * T, "partial sums"));
-  SFK_TRY(ws_reserve(c, ws.hdr, sizeof(BatchHdr), "batch header"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)n_tiles, "tile counts"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)n_tiles, "tile flags"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)n_tiles, "tile counters"));
+  SFK_TRY(ws_reserve(c, ws, ws.leaf_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "leaf offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.partial_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "partial offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.chunk_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "item offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.leaves, sizeof(int32_t) * (size_t)leaf_cap, "leaf lists"));
+  SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)item_cap, "work items"));
+  SFK_TRY(ws_reserve(c, ws, ws.partials, sizeof(double) * (size_t)partial_cap * T, "partial sums"));
+  SFK_TRY(ws_reserve(c, ws, ws.hdr, sizeof(BatchHdr), "batch header"));
   BatchHdr* hdr = (BatchHdr*)ws.hdr.p;
   int32_t* tile_cnt = (int32_t*)ws.tile_cnt.p;
   int32_t* tile_fit = (int32_t*)ws.tile_fit.p;
@@ -526,18 +575,32 @@ sfk_status launch_group(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int
   int64_t* partial_off = (int64_t*)ws.partial_off.p;
   int64_t* chunk_off = (int64_t*)ws.chunk_off.p;
   SFK_HIP(c, sfk::launch_hdr_init(hdr, n_tiles, leaf_cap, item_cap, s));
-  SFK_HIP(c, sfk::launch_tile_count(tv, rois_dev, n_rois, coords, ts, n_tiles, CH, tile_cnt,
-                                     nullptr, tile_done, s));
-  SFK_HIP(c, sfk::launch_plan(tile_cnt, n_tiles, CH, leaf_cap, partial_cap, leaf_off, partial_off,
-                               chunk_off, tile_fit, hdr, s));
-  SFK_HIP(c, sfk::launch_tile_fill2(tv, rois_dev, n_rois, coords, ts, n_tiles, tile_cnt, tile_fit,
-                                     leaf_off, chunk_off, (int32_t*)ws.leaves.p,
-                                     (int32_t*)ws.item_tile.p, s));
-  const int grid = std::max(1, c->n_cu * blocks_per_cu(c, ts));
-  SFK_HIP(c, sfk::launch_eval2(tv, rois_dev, n_rois, coords, ts, kk, pp, cnt, CH, leaf_off,
-                                chunk_off, partial_off, tile_cnt, tile_fit, (int32_t*)ws.leaves.p,
-                                (int32_t*)ws.item_tile.p, (float*)ws.partials.p, tile_done, hdr,
-                                grid, s));
+  {
+    ProfScope p(c, PK_TILE_COUNT, s);
+    SFK_HIP(c, sfk::launch_tile_count(tv, rois_dev, n_rois, coords, ts, n_tiles, CH, tile_cnt,
+                                       nullptr, tile_done, s));
+  }
+  {
+    ProfScope p(c, PK_PLAN, s);
+    SFK_HIP(c, sfk::launch_plan(tile_cnt, n_tiles, CH, leaf_cap, partial_cap, leaf_off,
+                                 partial_off, chunk_off, tile_fit, hdr, s));
+  }
+  {
+    ProfScope p(c, PK_TILE_FILL, s);
+    SFK_HIP(c, sfk::launch_tile_fill2(tv, rois_dev, n_rois, coords, ts, n_tiles, tile_cnt,
+                                       tile_fit, leaf_off, chunk_off, (int32_t*)ws.leaves.p,
+                                       (int32_t*)ws.item_tile.p, s));
+  }
+  const int grid = c->opts.persistent_waves_per_cu > 0
+                       ? c->n_cu * std::max(1, c->opts.persistent_waves_per_cu / 4)
+                       : 0;  // 0: resident blocks per CU from the occupancy query
+  {
+    ProfScope p(c, PK_EVAL, s, hdr);
+    SFK_HIP(c, sfk::launch_eval2(tv, rois_dev, n_rois, coords, ts, kk, pp, cnt, CH, leaf_off,
+                                  chunk_off, partial_off, tile_cnt, tile_fit,
+                                  (int32_t*)ws.leaves.p, (int32_t*)ws.item_tile.p,
+                                  (double*)ws.partials.p, tile_done, hdr, grid, c->n_cu, s));
+  }
   return SFK_OK;
 }
 
@@ -553,7 +616,7 @@ GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
   if (r->bw == SFK_BW_PER_POINT) {
     g.pp = PP_ISO;
     g.ih[0] = g.ih[1] = g.ih[2] = 1.0f;
-    g.scale = (float)(ck * nu);
+    g.scale = ck * nu;
   } else {
     float h[3];
     for (int k = 0; k < 3; ++k) {
@@ -565,9 +628,9 @@ GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
     g.pp = PP_UNIFORM;
     for (int k = 0; k < 3; ++k) g.ih[k] = (float)(1.0 / (double)h[k]);
     const double w = 1.0 / ((double)h[0] * (double)h[1] * (double)h[2]);
-    g.scale = (float)(ck * nu * w);
+    g.scale = ck * nu * w;
   }
-  if (count_mode) g.scale = 1.0f;
+  if (count_mode) g.scale = 1.0;
   return g;
 }
 
@@ -604,18 +667,18 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
     off += (int)groups[gi].size();
     coord_total += ncoord[gi];
   }
-  SFK_TRY(ws_reserve(c, ws.rois, sizeof(RoiDev) * (size_t)n, "ROI descriptors"));
-  SFK_TRY(ws_reserve(c, ws.coords, sizeof(float) * (size_t)coord_total, "node coordinates"));
+  SFK_TRY(ws_reserve(c, ws, ws.rois, sizeof(RoiDev) * (size_t)n, "ROI descriptors"));
+  SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)coord_total, "node coordinates"));
   RoiDev* rd = (RoiDev*)ws.rois.p;
   SFK_HIP(c, hipMemcpyAsync(rd, st.host, sizeof(RoiDev) * (size_t)n, hipMemcpyHostToDevice, s));
   SFK_HIP(c, hipEventRecord(st.ev, s));
   st.ev_valid = true;
-  SFK_HIP(c, sfk::launch_roi_coords(rd, n, (float*)ws.coords.p, s));
+  SFK_HIP(c, sfk::launch_roi_coords(rd, n, (double*)ws.coords.p, s));
   TreeView tv = view_of(t);
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const int kk = keys[gi].first, pp = keys[gi].second;
     SFK_TRY(launch_group(c, tv, ts, kk, pp, count_mode, rd + roi_off[gi], (int)groups[gi].size(),
-                         tiles[gi], (const float*)ws.coords.p, ws, s));
+                         tiles[gi], (const double*)ws.coords.p, ws, s));
   }
   if (st.hdr_host)
     SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
@@ -733,14 +796,14 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
     int64_t n_tiles = 0, n_coords = 0;
     make_roidev(v, ts, st.host, &n_tiles, &n_coords);
-    SFK_TRY(ws_reserve(c, ws.rois, sizeof(RoiDev), "ROI descriptors"));
-    SFK_TRY(ws_reserve(c, ws.coords, sizeof(float) * (size_t)n_coords, "node coordinates"));
+    SFK_TRY(ws_reserve(c, ws, ws.rois, sizeof(RoiDev), "ROI descriptors"));
+    SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)n_coords, "node coordinates"));
     SFK_HIP(c, hipMemcpyAsync(ws.rois.p, st.host, sizeof(RoiDev), hipMemcpyHostToDevice, s));
     SFK_HIP(c, hipEventRecord(st.ev, s));
     st.ev_valid = true;
-    SFK_HIP(c, sfk::launch_roi_coords((RoiDev*)ws.rois.p, 1, (float*)ws.coords.p, s));
+    SFK_HIP(c, sfk::launch_roi_coords((RoiDev*)ws.rois.p, 1, (double*)ws.coords.p, s));
     return launch_group(c, tv, ts, g.count_mode ? 0 : g.kk, g.pp, g.count_mode,
-                        (const RoiDev*)ws.rois.p, 1, n_tiles, (const float*)ws.coords.p, ws, s);
+                        (const RoiDev*)ws.rois.p, 1, n_tiles, (const double*)ws.coords.p, ws, s);
   };
 
   if (!mbe) {
@@ -752,7 +815,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     if (r->bw == SFK_BW_PER_POINT) {
       g.pp = PP_ISO;
       g.ih[0] = g.ih[1] = g.ih[2] = 1.0f;
-      g.scale = (float)(ck * nu);
+      g.scale = ck * nu;
       SFK_HIP(c, sfk::launch_node_ih(sc.pts.as<float4>(), nullptr, PP_ISO, n_b,
                                       sc.nodes.as<NodeBox>(), sc.off, sc.cnt, sc.n_levels,
                                       sc.node_ih.as<float4>(), s));
@@ -762,9 +825,9 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
         h[k] = r->bw == SFK_BW_FIXED ? r->h[k] : (float)((double)r->h[0] * (r->hi[k] - r->lo[k]));
       g.pp = PP_UNIFORM;
       for (int k = 0; k < 3; ++k) g.ih[k] = (float)(1.0 / (double)h[k]);
-      g.scale = (float)(ck * nu / ((double)h[0] * (double)h[1] * (double)h[2]));
+      g.scale = ck * nu / ((double)h[0] * (double)h[1] * (double)h[2]);
     }
-    if (count_mode) g.scale = 1.0f;
+    if (count_mode) g.scale = 1.0;
     SFK_TRY(run_one(sc.view(g.pp), g, r->d_out));
     SFK_HIP(c, hipStreamSynchronize(s));
     return SFK_OK;
@@ -803,7 +866,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
   gp.pp = PP_UNIFORM;
   gp.c2 = 1.0f;
   for (int k = 0; k < 3; ++k) gp.ih[k] = (float)(1.0 / (double)ell0[k]);
-  gp.scale = (float)(ck * nu / ((double)ell0[0] * (double)ell0[1] * (double)ell0[2]));
+  gp.scale = ck * nu / ((double)ell0[0] * (double)ell0[1] * (double)ell0[2]);
   SFK_TRY(run_one(sc.view(PP_UNIFORM), gp, pilot.as<float>()));
 
   // ASL (Eqs. 5-6): trilinear pilot at each particle, mean, lengths
@@ -830,7 +893,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
   gf.c2 = 1.0f;
   gf.ih[0] = gf.ih[1] = gf.ih[2] = 1.0f;
   gf.count_mode = count_mode;
-  gf.scale = count_mode ? 1.0f : (float)(ck * nu);
+  gf.scale = count_mode ? 1.0 : ck * nu;
   SFK_TRY(run_one(sc.view(PP_ANISO), gf, r->d_out));
 
   if (dbg) {
@@ -876,21 +939,30 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
   return SFK_OK;
 }
 
-TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
-  if (c->opts.tile_shape > 0) return shape_of(c->opts.tile_shape);
-  // autotuner table keyed by (kernel, bandwidth mode, support/spacing bucket)
+// Autotuner key: kernel, bandwidth mode and the support radius measured in
+// node spacings (log2 bucket; per-point bandwidths share one bucket).
+int tune_key(const sfk_roi* r) {
   double hs = 0.0;
   if (r->bw == SFK_BW_FIXED || r->bw == SFK_BW_ROI_SCALED) {
-    const double h = r->bw == SFK_BW_FIXED ? r->h[0] : r->h[0] * (r->hi[0] - r->lo[0]);
-    hs = h / ((r->hi[0] - r->lo[0]) / (r->res[0] - 1));
-    if (r->kernel == SFK_KERNEL_GAUSS_TRUNC3) hs *= 3.0;
+    double rs = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double h = r->bw == SFK_BW_FIXED ? (double)r->h[k] : (double)r->h[0] * (r->hi[k] - r->lo[k]);
+      rs = std::max(rs, h / ((r->hi[k] - r->lo[k]) / (r->res[k] - 1)));
+    }
+    hs = r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 * rs : rs;
   }
-  (void)t;
   const int bucket = hs <= 0.0 ? 0 : std::min(7, std::max(1, (int)std::floor(std::log2(hs)) + 4));
-  const int key = (r->kernel * 4 + r->bw) * 8 + bucket;
-  auto it = c->tune.find(key);
+  return (r->kernel * 4 + r->bw) * 8 + bucket;
+}
+
+constexpr int kDefaultShape = 1;
+
+TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
+  (void)t;
+  if (c->opts.tile_shape > 0) return shape_of(c->opts.tile_shape);
+  auto it = c->tune.find(tune_key(r));
   if (it != c->tune.end()) return shape_of(it->second);
-  return shape_of(1);
+  return shape_of(kDefaultShape);
 }
 
 // Launch everything a ticket needs on a slot. CLOUD ROIs go through one
@@ -1093,6 +1165,12 @@ sfk_status sfk_ctx_destroy(sfk_ctx c) {
   release_ws(c, c->direct_ws);
   for (int i = 0; i < kStagingRing; ++i) release_staging(c->direct_st[i]);
   if (c->direct_last) (void)hipEventDestroy(c->direct_last);
+  for (const ProfRec& r : c->prof_pending) {
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   delete c;
   return SFK_OK;
   SFK_GUARD_END(nullptr)
@@ -1207,6 +1285,7 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
         (st = stmp.get(sfk::radix_sort_tmp_bytes(n), "sort scratch")) != SFK_OK)
       return fail(st);
     int alt = 0;
+    ProfScope prof(c, PK_BUILD, s);
     if (sfk::launch_morton(d_xyz, n, res.as<float>(), bits, keys.as<uint64_t>(),
                            vals.as<uint32_t>(), s) != hipSuccess ||
         sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(),
@@ -1228,6 +1307,7 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if (o.knn_k > 0) {
       if ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) != SFK_OK)
         return fail(st);
+      ProfScope prof(c, PK_KNN, s);
       if (sfk::launch_knn(view_of(t), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
     }
@@ -1246,7 +1326,56 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if (hipStreamSynchronize(s) != hipSuccess)
       return fail((set_err(c, "per-point bandwidth failed on the device"), SFK_E_DEVICE));
   }
+  if (c->prof_on) ++c->prof_builds;
   *out = t;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_profile_enable(sfk_ctx c, int32_t on) {
+  SFK_TRY(check_ctx(c));
+  c->prof_on = on != 0;
+  return SFK_OK;
+}
+
+sfk_status sfk_profile_read(sfk_ctx c, sfk_profile* out, int32_t reset) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  for (const ProfRec& r : c->prof_pending) {
+    SFK_HIP(c, hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    SFK_HIP(c, hipEventElapsedTime(&ms, r.a, r.b));
+    c->prof_ms[r.kind] += ms;
+    if (r.kind == PK_EVAL) {
+      ++c->prof_evals;
+      if (r.hdr_dev) {
+        BatchHdr h;
+        if (hipMemcpy(&h, r.hdr_dev, sizeof h, hipMemcpyDeviceToHost) == hipSuccess) {
+          c->prof_last_leaves = h.total_leaves;
+          c->prof_last_items = h.n_items;
+        }
+      }
+    }
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+  if (out) {
+    out->tile_count_ms = c->prof_ms[PK_TILE_COUNT];
+    out->plan_ms = c->prof_ms[PK_PLAN];
+    out->tile_fill_ms = c->prof_ms[PK_TILE_FILL];
+    out->eval_ms = c->prof_ms[PK_EVAL];
+    out->build_ms = c->prof_ms[PK_BUILD];
+    out->knn_ms = c->prof_ms[PK_KNN];
+    out->eval_launches = c->prof_evals;
+    out->builds = c->prof_builds;
+    out->last_total_leaves = c->prof_last_leaves;
+    out->last_items = c->prof_last_items;
+  }
+  if (reset) {
+    for (int k = 0; k < PK_N; ++k) c->prof_ms[k] = 0.0;
+    c->prof_evals = c->prof_builds = 0;
+  }
   return SFK_OK;
   SFK_GUARD_END(c)
 }
@@ -1291,11 +1420,7 @@ sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
     set_err(c, "evaluation options out of range");
     return SFK_E_INVAL;
   }
-  if (opts->tile_shape == 4) {
-    set_err(c, "tile shape 4 (8x4x4 with 8x4x4 = 128 nodes) unavailable in this build");
-  }
   c->opts = *opts;
-  if (c->opts.tile_shape == 4) c->opts.tile_shape = 2;
   return SFK_OK;
 }
 
@@ -1311,13 +1436,13 @@ static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStre
   } else {
     absorb_stats(c->direct_ws, st);
     std::vector<const sfk_roi*> v{roi};
-    // capacity growth reallocates: previous direct work must be done
-    if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
     SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, choose_shape(c, t, roi), c->direct_ws, st, s));
   }
   SFK_HIP(c, hipEventRecord(c->direct_last, s));
   c->direct_last_valid = true;
   c->direct_last_stream = s;
+  c->direct_ws.last_use = c->direct_last;
+  c->direct_ws.last_use_valid = true;
   return SFK_OK;
 }
 
@@ -1486,13 +1611,13 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   make_roidev(v, ts, &rd, &n_tiles, &n_coords);
   TmpBuf rdev(c), coords(c), cnt(c), off(c), idx(c);
   SFK_TRY(rdev.get(sizeof(RoiDev), "descriptor"));
-  SFK_TRY(coords.get(sizeof(float) * (size_t)n_coords, "coordinates"));
+  SFK_TRY(coords.get(sizeof(double) * (size_t)n_coords, "coordinates"));
   SFK_TRY(cnt.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "counts"));
   SFK_HIP(c, hipMemcpy(rdev.b.p, &rd, sizeof rd, hipMemcpyHostToDevice));
-  SFK_HIP(c, sfk::launch_roi_coords(rdev.as<RoiDev>(), 1, coords.as<float>(), s));
+  SFK_HIP(c, sfk::launch_roi_coords(rdev.as<RoiDev>(), 1, coords.as<double>(), s));
   TreeView tv = view_of(t);
   SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
-                                            coords.as<float>(), ts, node_begin, node_end,
+                                            coords.as<double>(), ts, node_begin, node_end,
                                             cnt.as<int64_t>(), nullptr, nullptr, s));
   std::vector<int64_t> counts(nn);
   SFK_HIP(c, hipMemcpyAsync(counts.data(), cnt.b.p, sizeof(int64_t) * nn, hipMemcpyDeviceToHost, s));
@@ -1505,7 +1630,7 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   SFK_TRY(idx.get(sizeof(int32_t) * (size_t)std::max<int64_t>(*needed, 1), "indices"));
   SFK_HIP(c, hipMemcpy(off.b.p, h_offsets, sizeof(int64_t) * nn, hipMemcpyHostToDevice));
   SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
-                                            coords.as<float>(), ts, node_begin, node_end, nullptr,
+                                            coords.as<double>(), ts, node_begin, node_end, nullptr,
                                             off.as<int64_t>(), idx.as<int32_t>(), s));
   std::vector<int32_t> ix(*needed);
   SFK_HIP(c, hipMemcpyAsync(ix.data(), idx.b.p, sizeof(int32_t) * ix.size(), hipMemcpyDeviceToHost, s));
@@ -1612,26 +1737,288 @@ sfk_status sfk_debug_mbe(sfk_ctx c, sfk_tree t, const sfk_roi* roi, float* h_ell
 }
 
 sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n) {
-  (void)t;
-  (void)sample;
-  (void)n;
+  SFK_GUARD_BEGIN
   SFK_TRY(check_ctx(c));
-  set_err(c, "autotuner not available yet");
-  return SFK_E_UNSUPPORTED;
+  if (!t || (!sample && n > 0) || n < 0) {
+    set_err(c, "invalid autotune arguments");
+    return SFK_E_INVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    SFK_TRY(validate_roi(c, t, &sample[i], i));
+    if (sample[i].set != SFK_SET_CLOUD || sample[i].bw == SFK_BW_MBE) {
+      set_err(c, "autotune samples must be CLOUD-set, non-MBE ROIs");
+      return SFK_E_UNSUPPORTED;
+    }
+  }
+  hipStream_t s = c->slots[0].stream;
+  SFK_HIP(c, hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  SFK_HIP(c, hipEventCreate(&e0));
+  SFK_HIP(c, hipEventCreate(&e1));
+  const sfk_eval_opts saved = c->opts;
+  // per key: summed time of each shape over that key's samples
+  std::map<int, std::vector<double>> cost;
+  sfk_status st = SFK_OK;
+  for (int i = 0; i < n && st == SFK_OK; ++i) {
+    const int key = tune_key(&sample[i]);
+    auto& v = cost[key];
+    if (v.empty()) v.assign(5, 0.0);
+    for (int shape = 1; shape <= 4 && st == SFK_OK; ++shape) {
+      c->opts.tile_shape = shape;
+      float best = 1e30f;
+      for (int rep = 0; rep < 3 && st == SFK_OK; ++rep) {
+        (void)hipEventRecord(e0, s);
+        st = eval_direct(c, t, &sample[i], s, false);
+        (void)hipEventRecord(e1, s);
+        if (st == SFK_OK && hipEventSynchronize(e1) == hipSuccess) {
+          float ms = 0.0f;
+          if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0) best = std::min(best, ms);
+        }
+      }
+      v[shape] += best;
+    }
+  }
+  c->opts = saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SFK_OK) return st;
+  for (auto& kv : cost) {
+    int best = kDefaultShape;
+    for (int shape = 1; shape <= 4; ++shape)
+      if (kv.second[shape] < kv.second[best]) best = shape;
+    c->tune[kv.first] = best;
+  }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+/* Autotuner table: (key, tile shape) pairs. */
+sfk_status sfk_autotune_table(sfk_ctx c, int32_t* keys, int32_t* shapes, int32_t cap,
+                              int32_t* n_out) {
+  SFK_TRY(check_ctx(c));
+  if (!n_out) {
+    set_err(c, "n_out is NULL");
+    return SFK_E_INVAL;
+  }
+  int32_t i = 0;
+  for (auto& kv : c->tune) {
+    if (keys && shapes && i < cap) {
+      keys[i] = kv.first;
+      shapes[i] = kv.second;
+    }
+    ++i;
+  }
+  *n_out = i;
+  return SFK_OK;
+}
+
+// Device bytes one request holds while in flight: its grid plus an estimate
+// of its share of the batch workspace (per-tile arrays and leaf lists).
+static double request_bytes(const sfk_roi& r, TileShape ts) {
+  const double m = (double)r.res[0] * r.res[1] * r.res[2];
+  const double tiles = std::ceil((double)r.res[0] / ts.tx) * std::ceil((double)r.res[1] / ts.ty) *
+                       std::ceil((double)r.res[2] / ts.tz);
+  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4);
 }
 
 sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
-                     const sfk_serve_opts* opts, sfk_request_result* h_results,
-                     sfk_serve_summary* h_summary) {
-  (void)t;
-  (void)reqs;
-  (void)n;
-  (void)opts;
-  (void)h_results;
-  (void)h_summary;
+                     const sfk_serve_opts* opts, sfk_request_result* res,
+                     sfk_serve_summary* summ) {
+  SFK_GUARD_BEGIN
   SFK_TRY(check_ctx(c));
-  set_err(c, "serving loop not available yet");
-  return SFK_E_UNSUPPORTED;
+  if (!t || (!reqs && n > 0) || n < 0 || !opts || (!res && n > 0)) {
+    set_err(c, "invalid serve arguments");
+    return SFK_E_INVAL;
+  }
+  if (opts->mode < 0 || opts->mode > 1 || opts->n_slots < 1 || opts->n_slots > kNumSlots ||
+      opts->max_batch < 1 || !(opts->budget_bytes >= 0.0)) {
+    set_err(c, "serve options out of range (mode 0|1, 1 <= n_slots <= %d, max_batch >= 1)",
+            kNumSlots);
+    return SFK_E_INVAL;
+  }
+  std::vector<sfk_roi> rois((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    SFK_TRY(validate_roi(c, t, &reqs[i].roi, (int)i));
+    if (reqs[i].roi.set != SFK_SET_CLOUD || reqs[i].roi.bw == SFK_BW_MBE) {
+      set_err(c, "request %lld: the serving loop takes CLOUD-set, non-MBE requests", (long long)i);
+      return SFK_E_UNSUPPORTED;
+    }
+    if (i > 0 && reqs[i].arrival_s < reqs[i - 1].arrival_s) {
+      set_err(c, "requests must be sorted by arrival time");
+      return SFK_E_INVAL;
+    }
+    rois[i] = reqs[i].roi;
+  }
+  SFK_TRY(validate_disjoint_outputs(c, rois.data(), (int)n));
+  // drain anything the context still runs
+  for (int i = 0; i < kNumSlots; ++i)
+    if (c->slots[i].busy) SFK_HIP(c, hipEventSynchronize(c->slots[i].done));
+  SFK_TRY(pump(c));
+  if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
+
+  const double budget = opts->budget_bytes > 0 ? opts->budget_bytes : (double)c->budget;
+  for (int64_t i = 0; i < n; ++i) {
+    res[i] = sfk_request_result{};
+    res[i].arrival_s = reqs[i].arrival_s;
+    res[i].batch = -1;
+  }
+  int64_t n_batches = 0, budget_waits = 0, batched_reqs = 0;
+  double in_flight_area = 0.0;  // integral of batches in flight over time
+  const double t0 = now_s();
+  double last_t = 0.0;
+  int64_t next = 0, done_cnt = 0;
+
+  if (opts->mode == 1) {
+    // one ROI per launch, in arrival order, on one stream
+    hipStream_t s = c->slots[0].stream;
+    std::vector<hipEvent_t> evs((size_t)n, nullptr);
+    for (auto& e : evs) SFK_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int64_t retire = 0;
+    sfk_status st = SFK_OK;
+    while (done_cnt < n) {
+      const double now = now_s() - t0;
+      bool acted = false;
+      if (next < n && reqs[next].arrival_s <= now) {
+        res[next].admit_s = now;
+        res[next].batch = (int32_t)n_batches++;
+        st = eval_direct(c, t, &rois[next], s, false);
+        if (st != SFK_OK) break;
+        SFK_HIP(c, hipEventRecord(evs[next], s));
+        ++next;
+        acted = true;
+      }
+      while (retire < next) {
+        const hipError_t q = hipEventQuery(evs[retire]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          set_err(c, "request %lld failed on the device", (long long)retire);
+          st = SFK_E_DEVICE;
+          break;
+        }
+        const double tnow = now_s() - t0;
+        res[retire].done_s = tnow;
+        res[retire].latency_ms = (tnow - reqs[retire].arrival_s) * 1e3;
+        res[retire].status = SFK_OK;
+        ++retire;
+        ++done_cnt;
+        acted = true;
+      }
+      if (st != SFK_OK) break;
+      const double tnow = now_s() - t0;
+      in_flight_area += (double)(next - retire) * (tnow - last_t);
+      last_t = tnow;
+      if (!acted) std::this_thread::yield();
+    }
+    (void)hipStreamSynchronize(s);
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    if (st != SFK_OK) return st;
+    batched_reqs = n;
+  } else {
+    const int ns = opts->n_slots;
+    std::vector<std::vector<int64_t>> in_slot((size_t)ns);
+    std::vector<double> slot_bytes((size_t)ns, 0.0);
+    std::deque<int64_t> pending;
+    double in_flight = 0.0;
+    std::vector<const sfk_roi*> batch;
+    while (done_cnt < n) {
+      const double now = now_s() - t0;
+      bool acted = false;
+      while (next < n && reqs[next].arrival_s <= now) pending.push_back(next++);
+      // retire finished batches
+      int busy = 0;
+      for (int si = 0; si < ns; ++si) {
+        Slot& sl = c->slots[si];
+        if (!sl.busy) continue;
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) {
+          ++busy;
+          continue;
+        }
+        if (q != hipSuccess) {
+          set_err(c, "a batch failed on the device: %s", hipGetErrorString(q));
+          return SFK_E_DEVICE;
+        }
+        const double tnow = now_s() - t0;
+        for (int64_t i : in_slot[si]) {
+          res[i].done_s = tnow;
+          res[i].latency_ms = (tnow - reqs[i].arrival_s) * 1e3;
+          res[i].status = SFK_OK;
+          ++done_cnt;
+        }
+        in_flight -= slot_bytes[si];
+        slot_bytes[si] = 0.0;
+        in_slot[si].clear();
+        absorb_stats(sl.ws, sl.st);
+        sl.busy = false;
+        acted = true;
+      }
+      // admit: every free slot takes the waiting requests that fit
+      for (int si = 0; si < ns && !pending.empty(); ++si) {
+        Slot& sl = c->slots[si];
+        if (sl.busy) continue;
+        batch.clear();
+        double bytes = 0.0;
+        const TileShape ts = choose_shape(c, t, &rois[pending.front()]);
+        while (!pending.empty() && (int)batch.size() < opts->max_batch) {
+          const int64_t i = pending.front();
+          const double rb = request_bytes(rois[i], ts);
+          const bool fits = budget <= 0.0 || in_flight + bytes + rb <= budget;
+          if (!fits && !(batch.empty() && in_flight == 0.0)) break;
+          batch.push_back(&rois[i]);
+          in_slot[si].push_back(i);
+          bytes += rb;
+          pending.pop_front();
+        }
+        if (batch.empty()) {
+          ++budget_waits;
+          break;
+        }
+        const double tnow = now_s() - t0;
+        for (int64_t i : in_slot[si]) {
+          res[i].admit_s = tnow;
+          res[i].batch = (int32_t)n_batches;
+        }
+        ++n_batches;
+        batched_reqs += (int64_t)batch.size();
+        sl.busy = true;
+        sl.ticket = -1;
+        SFK_TRY(enqueue_cloud_rois(c, t, batch, false, ts, sl.ws, sl.st, sl.stream));
+        SFK_HIP(c, hipEventRecord(sl.done, sl.stream));
+        slot_bytes[si] = bytes;
+        in_flight += bytes;
+        ++busy;
+        acted = true;
+      }
+      const double tnow = now_s() - t0;
+      in_flight_area += (double)busy * (tnow - last_t);
+      last_t = tnow;
+      if (!acted) std::this_thread::yield();
+    }
+  }
+  const double wall = now_s() - t0;
+  if (summ) {
+    std::vector<double> lat((size_t)n);
+    for (int64_t i = 0; i < n; ++i) lat[i] = res[i].latency_ms;
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double q) {
+      if (lat.empty()) return 0.0;
+      const double pos = q * (double)(lat.size() - 1);
+      const size_t i = (size_t)pos;
+      const double f = pos - (double)i;
+      return i + 1 < lat.size() ? lat[i] + f * (lat[i + 1] - lat[i]) : lat[i];
+    };
+    summ->wall_s = wall;
+    summ->p50_ms = pct(0.50);
+    summ->p99_ms = pct(0.99);
+    summ->max_ms = lat.empty() ? 0.0 : lat.back();
+    summ->evals_per_s = 0.0;
+    summ->n_batches = n_batches;
+    summ->mean_batch = n_batches ? (double)batched_reqs / (double)n_batches : 0.0;
+    summ->mean_in_flight = wall > 0 ? in_flight_area / wall : 0.0;
+    summ->budget_waits = budget_waits;
+  }
+  return SFK_OK;
+  SFK_GUARD_END(c)
 }
 
 }  // extern "C"

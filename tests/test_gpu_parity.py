@@ -436,3 +436,79 @@ def test_full_size_per_point_workload(ctx, torch):
         ro, ri = oracle.candidates(pts, roi, np.array([n]), h2=h2)
         assert np.array_equal(i, ri)
     say("candidate sample exact")
+
+
+# ---------------------------------------------------------------------------
+# serving: continuous batching over streams; every result equals its alone run
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_serve_alone_vs_mix(ctx, torch, mode):
+    pts = synth.clumpy_cloud(300_000, 5)
+    tree = ctx.build_tree(dev(torch, pts))
+    arr, streams, rois = synth.serving_trace(seed=3, duration_s=0.25, res_choices=(16, 24, 32, 48))
+    outs = [torch.full((r.n_nodes,), -1.0, device="cuda") for r in rois]
+    res, summ = ctx.serve(tree, arr, rois, outs, mode=mode, n_slots=4, max_batch=32,
+                          budget_bytes=64 << 20)
+    torch.cuda.synchronize()
+    say("serve mode", mode, "requests", len(rois), "batches", summ.n_batches, "p50",
+        summ.p50_ms, "p99", summ.p99_ms, "mean batch", summ.mean_batch)
+    assert summ.n_batches >= 1 and summ.p99_ms >= summ.p50_ms > 0
+    for i in range(len(rois)):
+        assert res[i].status == 0 and res[i].done_s >= res[i].admit_s >= res[i].arrival_s - 1e-9
+    for i, r in enumerate(rois):
+        alone = ctx.eval_roi(tree, r).cpu().numpy()
+        assert np.array_equal(alone, outs[i].cpu().numpy()), i
+    # a few requests against the oracle on sampled nodes
+    for i in range(0, len(rois), max(1, len(rois) // 5)):
+        r = rois[i]
+        nodes = sample_nodes(None, r.n_nodes, 16, i)
+        ref = oracle.density(pts, r, nodes=nodes)
+        got = outs[i].cpu().numpy()
+        peak = max(ref.max(), got.max())
+        big = ref >= 1e-3 * peak
+        if big.any():
+            assert np.max(np.abs(got[nodes][big] - ref[big]) / ref[big]) <= REL_TOL
+        assert np.max(np.abs(got[nodes][~big] - ref[~big]), initial=0) <= ABS_TOL * peak + 1e-30
+
+
+# ---------------------------------------------------------------------------
+# every tile shape, and the autotuner that picks among them
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
+def test_every_tile_shape(ctx, torch, shape):
+    pts = synth.clumpy_cloud(80_000, 8)
+    ctx.set_eval_opts(tile_shape=shape)
+    tree = ctx.build_tree(dev(torch, pts), knn_k=16)
+    h2 = ctx.debug_point_h2(tree)
+    for roi in [Roi((0, 0, 0), (1, 1, 1), (23, 19, 17), bw="fixed", h=(0.05, 0.04, 0.06)),
+                Roi((0.1, 0.1, 0.1), (0.9, 0.8, 0.7), (21, 22, 13), kernel="gauss_trunc3",
+                    bw="per_point")]:
+        got = ctx.eval_roi(tree, roi).cpu().numpy()
+        check_density(got, oracle.density(pts, roi, h2=h2), "shape %d" % shape)
+        cnt = ctx.debug_support_counts(tree, roi).cpu().numpy().astype(np.int64)
+        assert np.array_equal(cnt, oracle.support_counts(pts, roi, h2=h2))
+        n = roi.n_nodes // 2
+        _, idx = ctx.debug_candidates(tree, roi, n, n + 1)
+        _, ridx = oracle.candidates(pts, roi, np.array([n]), h2=h2)
+        assert np.array_equal(idx, ridx)
+    ctx.set_eval_opts()
+
+
+def test_autotune(ctx, torch):
+    pts = synth.clumpy_cloud(200_000, 9)
+    tree = ctx.build_tree(dev(torch, pts))
+    rois = synth.random_batch_rois(6, seed=2, res_lo=16, res_hi=40)
+    outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    ctx.autotune(tree, rois, outs)
+    table = ctx.autotune_table()
+    assert len(table) >= 1 and all(1 <= s <= 4 for s in table.values())
+    for r in rois:
+        nodes = sample_nodes(None, r.n_nodes, 16, 1)
+        got = ctx.eval_roi(tree, r).cpu().numpy()[nodes]
+        ref = oracle.density(pts, r, nodes=nodes)
+        peak = max(ref.max(), got.max())
+        big = ref >= 1e-3 * peak
+        if big.any():
+            assert np.max(np.abs(got[big] - ref[big]) / ref[big]) <= REL_TOL
