@@ -50,6 +50,9 @@ def parse():
                    help="skip the batched vs one-ROI-per-launch comparison")
     p.add_argument("--n-batch", type=int, default=256)
     p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run one 1 GiB device-to-device copy first (reference for "
+                        "hardware byte counters)")
     p.add_argument("--no-serve", action="store_true")
     return p.parse_args()
 
@@ -173,6 +176,12 @@ def main():
     import torch
     import paper_2601_20758_amd as sfk
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     pts, roi, knn_k, config = workload(args.workload)
     log("workload ready:", config["workload"])
     xyz = torch.from_numpy(pts).cuda()

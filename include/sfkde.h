@@ -158,7 +158,11 @@ sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hi
 /* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
  * launch on one of the context's streams. The descriptors are copied; the
  * d_out buffers must stay valid until the ticket completes. Returns at once
- * with a ticket. SFK_E_BUDGET if the batch's workspace exceeds the budget. */
+ * with a ticket. SFK_E_BUDGET if the batch's workspace exceeds the budget.
+ * A batch of one (kernel, bandwidth) group replays the slot's captured
+ * hipGraph (descriptor copy -> node coordinates -> tile range query -> work
+ * plan -> leaf lists -> evaluation -> header readback), recaptured only when
+ * the batch outgrows the graph's buffers. */
 sfk_status sfk_submit(sfk_ctx ctx, sfk_tree tree, const sfk_roi* rois, int32_t n_rois,
                       sfk_ticket* out);
 /* *done = 1 once the ticket's grids are written, never blocks. */
@@ -177,6 +181,9 @@ typedef struct {
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
                             lists do not fit walk the tree inside the evaluation
                             kernel instead (same results, bitwise) */
+  int32_t disable_graphs; /* 1: batches on context streams use direct launches
+                             instead of each slot's captured hipGraph */
+  int32_t reserved;
 } sfk_eval_opts;
 sfk_status sfk_set_eval_opts(sfk_ctx ctx, const sfk_eval_opts* opts);
 /* Time every tile shape on the sample ROIs and record the fastest per

@@ -84,8 +84,10 @@ __device__ __forceinline__ bool tile_box_test(const TreeView& tv, const RoiDev& 
 // ROI coordinate tables: x_i = lo + (i*(hi-lo))/(res-1) in double.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_roi_coords(const RoiDev* __restrict__ rois, int n_rois,
+__global__ __launch_bounds__(256) void k_roi_coords(const BatchHdr* __restrict__ hdr,
+                                                    const RoiDev* __restrict__ rois,
                                                     double* __restrict__ coords) {
+  if ((int)blockIdx.x >= hdr->n_rois) return;
   const RoiDev& R = rois[blockIdx.x];
   const int tot = R.res[0] + R.res[1] + R.res[2];
   for (int q = threadIdx.x; q < tot; q += blockDim.x) {
@@ -105,31 +107,10 @@ __global__ __launch_bounds__(256) void k_roi_coords(const RoiDev* __restrict__ r
   }
 }
 
-hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, double* coords, hipStream_t s) {
-  if (n_rois <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_roi_coords, dim3(n_rois), dim3(256), 0, s, rois, n_rois, coords);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// batch header
-// ---------------------------------------------------------------------------
-
-__global__ void k_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap) {
-  hdr->n_tiles = n_tiles;
-  hdr->total_leaves = 0;
-  hdr->n_items = 0;
-  hdr->leaf_cap = leaf_cap;
-  hdr->item_cap = item_cap;
-  hdr->next_item = 0;
-  hdr->overflow = 0;
-  hdr->useful = 0;
-  hdr->tested = 0;
-}
-
-hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_hdr_init, dim3(1), dim3(1), 0, s, hdr, n_tiles, leaf_cap, item_cap);
+hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
+                             double* coords, hipStream_t s) {
+  if (grid_rois <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_roi_coords, dim3(grid_rois), dim3(256), 0, s, hdr, rois, coords);
   return hipGetLastError();
 }
 
@@ -138,12 +119,15 @@ hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int
 // ---------------------------------------------------------------------------
 
 template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const RoiDev* __restrict__ rois,
-                                                    int n_rois, const double* __restrict__ coords,
-                                                    int64_t n_tiles, int32_t* __restrict__ tile_cnt,
+__global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr* __restrict__ hdr,
+                                                    const RoiDev* __restrict__ rois,
+                                                    const double* __restrict__ coords,
+                                                    int32_t* __restrict__ tile_cnt,
                                                     int32_t* __restrict__ tile_done) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t n_tiles = hdr->n_tiles;
+  const int n_rois = hdr->n_rois;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
@@ -165,12 +149,15 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const RoiDev* _
 
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_fill(
-    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const double* __restrict__ coords,
-    int64_t n_tiles, const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
-    const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
-    int32_t* __restrict__ leaves, int32_t* __restrict__ item_tile) {
+    TreeView tv, const BatchHdr* __restrict__ hdr, const RoiDev* __restrict__ rois,
+    const double* __restrict__ coords, const int32_t* __restrict__ tile_cnt,
+    const int32_t* __restrict__ tile_fit, const int64_t* __restrict__ leaf_off,
+    const int64_t* __restrict__ chunk_off, int32_t* __restrict__ leaves,
+    int32_t* __restrict__ item_tile) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t n_tiles = hdr->n_tiles;
+  const int n_rois = hdr->n_rois;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
     const int64_t c0 = chunk_off[t], c1 = chunk_off[t + 1];
     for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
@@ -199,14 +186,15 @@ __global__ __launch_bounds__(256) void k_tile_fill(
 static constexpr int kPlanNT = 512;
 
 __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ tile_cnt,
-                                                  int64_t n_tiles, int chunk_leaves,
-                                                  int64_t leaf_cap, int64_t partial_cap,
+                                                  BatchHdr* __restrict__ hdr, int chunk_leaves,
                                                   int64_t* __restrict__ leaf_off,
                                                   int64_t* __restrict__ partial_off,
                                                   int64_t* __restrict__ chunk_off,
-                                                  int32_t* __restrict__ tile_fit,
-                                                  BatchHdr* __restrict__ hdr) {
+                                                  int32_t* __restrict__ tile_fit) {
   __shared__ int64_t lds[kPlanNT / 64];
+  const int64_t n_tiles = hdr->n_tiles;
+  const int64_t leaf_cap = hdr->leaf_cap;
+  const int64_t partial_cap = hdr->partial_cap;
   int64_t carry_l = 0, carry_p = 0, carry_c = 0;
   for (int64_t base = 0; base < n_tiles; base += kPlanNT) {
     const int64_t t = base + threadIdx.x;
@@ -230,6 +218,8 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ ti
       tile_fit[t] = fit ? 1 : 0;
     }
   }
+  // every thread has read the header above before thread 0 writes it
+  __syncthreads();
   if (threadIdx.x == 0) {
     leaf_off[n_tiles] = carry_l;
     partial_off[n_tiles] = carry_p;
@@ -310,7 +300,7 @@ __device__ __forceinline__ void reduce_nodes(A (&acc)[T]) {
 // the Gaussian factors are float32 exp2 of the double exponents.
 template <int TX, int TY, int TZ, int KK, int PP, bool CNT>
 __global__ __launch_bounds__(256) void k_eval(
-    TreeView tv, const RoiDev* __restrict__ rois, int n_rois, const double* __restrict__ coords,
+    TreeView tv, const RoiDev* __restrict__ rois, const double* __restrict__ coords,
     int chunk_leaves, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
     const int64_t* __restrict__ partial_off, const int32_t* __restrict__ tile_cnt,
     const int32_t* __restrict__ tile_fit, const int32_t* __restrict__ leaves,
@@ -324,6 +314,7 @@ __global__ __launch_bounds__(256) void k_eval(
   __shared__ float4 lds_qprm[4][PP == PP_ANISO ? 128 : 1];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_items = hdr->n_items;
+  const int n_rois = hdr->n_rois;
   while (true) {
     int item = 0;
     if (lane == 0) item = atomicAdd(&hdr->next_item, 1);
@@ -698,39 +689,37 @@ static int grid_for(int64_t waves) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
 }
 
-hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                             TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
-                             int32_t* tile_nch, int32_t* tile_done, hipStream_t s) {
-  (void)chunk_leaves;
-  (void)tile_nch;
-  if (n_tiles <= 0) return hipSuccess;
-  const int nb = grid_for(n_tiles);
-#define SFK_L(X, Y, Z)                                                                       \
-  hipLaunchKernelGGL((k_tile_count<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, rois, n_rois, \
-                     coords, n_tiles, tile_cnt, tile_done)
+int tile_grid_blocks(int64_t n_tiles) { return grid_for(n_tiles); }
+
+hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, TileShape ts, int grid_blocks,
+                             int32_t* tile_cnt, int32_t* tile_done, hipStream_t s) {
+  const int nb = std::max(1, grid_blocks);
+#define SFK_L(X, Y, Z)                                                                      \
+  hipLaunchKernelGGL((k_tile_count<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
+                     coords, tile_cnt, tile_done)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leaves, int64_t leaf_cap,
-                       int64_t partial_cap, int64_t* leaf_off, int64_t* partial_off,
-                       int64_t* chunk_off, int32_t* tile_fit, BatchHdr* hdr, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, n_tiles, chunk_leaves,
-                     leaf_cap, partial_cap, leaf_off, partial_off, chunk_off, tile_fit, hdr);
+hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int chunk_leaves,
+                       int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
+                       int32_t* tile_fit, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, hdr, chunk_leaves, leaf_off,
+                     partial_off, chunk_off, tile_fit);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                             TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
-                             const int32_t* tile_fit, const int64_t* leaf_off,
-                             const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
-                             hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  const int nb = grid_for(n_tiles);
-#define SFK_L(X, Y, Z)                                                                      \
-  hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, rois, n_rois, \
-                     coords, n_tiles, tile_cnt, tile_fit, leaf_off, chunk_off, leaves, item_tile)
+hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                            const double* coords, TileShape ts, int grid_blocks,
+                            const int32_t* tile_cnt, const int32_t* tile_fit,
+                            const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
+                            int32_t* item_tile, hipStream_t s) {
+  const int nb = std::max(1, grid_blocks);
+#define SFK_L(X, Y, Z)                                                                     \
+  hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
+                     coords, tile_cnt, tile_fit, leaf_off, chunk_off, leaves, item_tile)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();
@@ -738,13 +727,12 @@ hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const 
 
 template <int X, int Y, int Z>
 static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu, hipStream_t s,
-                                    TreeView tv, const RoiDev* rois, int n_rois,
-                                    const double* coords, int chunk_leaves,
-                                    const int64_t* leaf_off, const int64_t* chunk_off,
-                                    const int64_t* partial_off, const int32_t* tile_cnt,
-                                    const int32_t* tile_fit, const int32_t* leaves,
-                                    const int32_t* item_tile, double* partials,
-                                    int32_t* tile_done, BatchHdr* hdr) {
+                                    TreeView tv, const RoiDev* rois, const double* coords,
+                                    int chunk_leaves, const int64_t* leaf_off,
+                                    const int64_t* chunk_off, const int64_t* partial_off,
+                                    const int32_t* tile_cnt, const int32_t* tile_fit,
+                                    const int32_t* leaves, const int32_t* item_tile,
+                                    double* partials, int32_t* tile_done, BatchHdr* hdr) {
 #define SFK_E(KK, PP, C)                                                                       \
   do {                                                                                         \
     static int occ_ = 0;                                                                       \
@@ -757,8 +745,8 @@ static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu
     }                                                                                          \
     const int g_ = grid > 0 ? grid : n_cu * occ_;                                              \
     hipLaunchKernelGGL((k_eval<X, Y, Z, KK, PP, C>), dim3(g_), dim3(256), 0, s, tv, rois,      \
-                       n_rois, coords, chunk_leaves, leaf_off, chunk_off, partial_off,         \
-                       tile_cnt, tile_fit, leaves, item_tile, partials, tile_done, hdr);       \
+                       coords, chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt,       \
+                       tile_fit, leaves, item_tile, partials, tile_done, hdr);                 \
   } while (0)
   if (cnt) {
     if (pp == PP_UNIFORM) SFK_E(KK_EPAN, PP_UNIFORM, true);
@@ -777,17 +765,17 @@ static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu
   return hipGetLastError();
 }
 
-hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                        TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
-                        const int64_t* leaf_off, const int64_t* chunk_off,
-                        const int64_t* partial_off, const int32_t* tile_cnt,
-                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                        double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                        int n_cu, hipStream_t s) {
-#define SFK_L(X, Y, Z)                                                                          \
-  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, s, tv, rois, n_rois,      \
-                                    coords,                                                     \
-                                    chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt,  \
+hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
+                       const double* coords, TileShape ts, int kk, int pp, bool cnt,
+                       int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,
+                       const int64_t* partial_off, const int32_t* tile_cnt,
+                       const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
+                       double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                       int n_cu, hipStream_t s) {
+  (void)hdr_c;
+#define SFK_L(X, Y, Z)                                                                        \
+  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, s, tv, rois, coords,     \
+                                    chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, \
                                     tile_fit, leaves, item_tile, partials, tile_done, hdr)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L

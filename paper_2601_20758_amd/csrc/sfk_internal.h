@@ -58,17 +58,20 @@ struct alignas(16) RoiDev {
   int32_t pad_[3];
 };
 
-// Device-side header of one batch (counters and totals; no host sync).
+// Device-side header of one batch, staged by the host together with the ROI
+// descriptors (so a captured graph can be replayed for any batch that fits
+// its buffers); the plan kernel fills in the totals. No host sync.
 struct alignas(16) BatchHdr {
-  int64_t n_tiles;
-  int64_t total_leaves;  // sum of candidate leaves over tiles
-  int64_t n_items;       // work items (tile chunks)
-  int64_t leaf_cap;      // capacity of the leaf-list buffer
-  int64_t item_cap;      // capacity of the item buffers
-  int32_t next_item;     // work-stealing counter
-  int32_t overflow;      // 1 if a capacity was exceeded (batch must be rerun)
-  int64_t useful;        // debug counters
-  int64_t tested;
+  int64_t n_tiles;       // host: tiles of the batch
+  int64_t leaf_cap;      // host: capacity of the leaf-list buffer
+  int64_t partial_cap;   // host: capacity of the split-tile partial slots
+  int64_t item_cap;      // host: capacity of the item buffers
+  int32_t n_rois;        // host: descriptors that follow the header
+  int32_t next_item;     // host stages 0; work-stealing counter
+  int64_t total_leaves;  // plan: candidate leaves over all tiles
+  int64_t n_items;       // plan: work items (tile chunks)
+  int32_t overflow;      // plan: 1 if some tile's lists did not fit (it walks the tree)
+  int32_t pad_;
 };
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
@@ -110,33 +113,33 @@ hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h
 hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
-// eval.hip
-hipError_t launch_roi_coords(const RoiDev* rois, int n_rois, double* coords, hipStream_t s);
-hipError_t launch_hdr_init(BatchHdr* hdr, int64_t n_tiles, int64_t leaf_cap, int64_t item_cap,
-                           hipStream_t s);
-hipError_t launch_tile_count(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                             TileShape ts, int64_t n_tiles, int chunk_leaves, int32_t* tile_cnt,
-                             int32_t* tile_nch, int32_t* tile_done, hipStream_t s);
-hipError_t launch_plan(const int32_t* tile_cnt, int64_t n_tiles, int chunk_leaves, int64_t leaf_cap,
-                       int64_t partial_cap, int64_t* leaf_off, int64_t* partial_off,
-                       int64_t* chunk_off, int32_t* tile_fit, BatchHdr* hdr, hipStream_t s);
-hipError_t launch_tile_fill2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                             TileShape ts, int64_t n_tiles, const int32_t* tile_cnt,
-                             const int32_t* tile_fit, const int64_t* leaf_off,
-                             const int64_t* chunk_off, int32_t* leaves, int32_t* item_tile,
-                             hipStream_t s);
-hipError_t launch_eval2(TreeView tv, const RoiDev* rois, int n_rois, const double* coords,
-                        TileShape ts, int kk, int pp, bool cnt, int chunk_leaves,
-                        const int64_t* leaf_off, const int64_t* chunk_off,
-                        const int64_t* partial_off, const int32_t* tile_cnt,
-                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                        double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                        int n_cu, hipStream_t s);
+// eval.hip (every kernel reads the batch sizes from the device header)
+hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
+                             double* coords, hipStream_t s);
+hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, TileShape ts, int grid_blocks,
+                             int32_t* tile_cnt, int32_t* tile_done, hipStream_t s);
+hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int chunk_leaves,
+                       int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
+                       int32_t* tile_fit, hipStream_t s);
+hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                            const double* coords, TileShape ts, int grid_blocks,
+                            const int32_t* tile_cnt, const int32_t* tile_fit,
+                            const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
+                            int32_t* item_tile, hipStream_t s);
+hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
+                       const double* coords, TileShape ts, int kk, int pp, bool cnt,
+                       int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,
+                       const int64_t* partial_off, const int32_t* tile_cnt,
+                       const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
+                       double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
+                       int n_cu, hipStream_t s);
 hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
                                     const double* coords, TileShape ts, int64_t node_begin,
                                     int64_t node_end, int64_t* cnt, const int64_t* off,
                                     int32_t* idx_out, hipStream_t s);
 bool tile_shape_supported(TileShape ts);
+int tile_grid_blocks(int64_t n_tiles);
 
 // mbe.hip
 hipError_t launch_inbox_flags(const float4* pts, int64_t n, const double* lo, const double* hi,

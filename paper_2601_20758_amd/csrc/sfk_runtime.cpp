@@ -51,8 +51,10 @@ struct DevBuf {
 }  // namespace
 
 struct Workspace {
-  DevBuf rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
-      item_tile, partials, hdr;
+  // hdr_rois = [BatchHdr][RoiDev x capacity]: staged by one host-to-device copy
+  DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
+      item_tile, partials;
+  uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
   // last enqueued use of the buffers: a buffer that must grow waits for it
@@ -61,14 +63,29 @@ struct Workspace {
 };
 
 struct Staging {
-  RoiDev* host = nullptr;  // pinned
-  int cap = 0;
+  char* host = nullptr;  // pinned: per group [BatchHdr][RoiDev...]
+  size_t cap = 0;        // bytes
   BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header
   hipEvent_t ev = nullptr;
   bool ev_valid = false;
 };
 
+// A captured batch pipeline of one slot, replayed while its key and the
+// workspace generation are unchanged and the batch fits its capacities.
+struct GraphCache {
+  bool valid = false;
+  TileShape ts{0, 0, 0};
+  int kk = 0, pp = 0, ch = 0;
+  bool cnt = false;
+  sfk_tree tree = nullptr;
+  uint64_t gen = 0;
+  int64_t tiles_cap = 0, rois_cap = 0, coords_cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Slot {
+  GraphCache gc;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   Workspace ws;
@@ -251,6 +268,7 @@ sfk_status ws_reserve(sfk_ctx c, Workspace& ws, DevBuf& b, size_t bytes, const c
   c->ws_bytes -= b.bytes;
   b.p = nullptr;
   b.bytes = 0;
+  ++ws.gen;
   void* p = raw_alloc(c, nb);
   if (!p) {
     set_err(c, "device allocation of %zu bytes for %s failed", nb, what);
@@ -315,17 +333,17 @@ struct TmpBuf {
   T* as() const { return (T*)b.p; }
 };
 
-sfk_status staging_reserve(sfk_ctx c, Staging& st, int n) {
+sfk_status staging_reserve(sfk_ctx c, Staging& st, size_t bytes) {
   if (!st.ev) SFK_HIP(c, hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
   if (!st.hdr_host) SFK_HIP(c, hipHostMalloc((void**)&st.hdr_host, sizeof(BatchHdr)));
-  if (st.cap >= n) return SFK_OK;
+  if (st.cap >= bytes) return SFK_OK;
   if (st.host) {
     if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
     SFK_HIP(c, hipHostFree(st.host));
     st.host = nullptr;
   }
-  const int cap = std::max(n, 64);
-  SFK_HIP(c, hipHostMalloc((void**)&st.host, sizeof(RoiDev) * (size_t)cap));
+  const size_t cap = std::max<size_t>(bytes, sizeof(BatchHdr) + 64 * sizeof(RoiDev));
+  SFK_HIP(c, hipHostMalloc((void**)&st.host, cap));
   st.cap = cap;
   return SFK_OK;
 }
@@ -539,67 +557,108 @@ void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int6
   *n_coords = co;
 }
 
-// Launch the whole pipeline of one group on stream s. rois_dev is the device
-// copy of `rd` (already enqueued). The workspace must be idle or only used
-// earlier on the same stream.
-sfk_status launch_group(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
-                        const RoiDev* rois_dev, int n_rois, int64_t n_tiles, const double* coords,
-                        Workspace& ws, hipStream_t s) {
+struct Caps {
+  int64_t leaf_cap, partial_cap, item_cap, tiles_cap, rois_cap, coords_cap;
+};
+
+// Reserve every buffer of a group (n_rois descriptors, n_tiles tiles,
+// n_coords coordinates; `headroom` > 1 over-allocates so later batches fit a
+// captured graph) and report the capacities the buffers actually have.
+sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois, int64_t n_tiles,
+                         int64_t n_coords, double headroom, Caps* caps) {
   const int CH = chunk_leaves_of(c);
   const int T = ts.tx * ts.ty * ts.tz;
-  int64_t leaf_cap = std::max<int64_t>(ws.want_leaf_cap, std::max<int64_t>(1 << 20, 64 * n_tiles));
-  int64_t partial_cap = std::max<int64_t>(ws.want_partial_cap, std::max<int64_t>(1 << 14, n_tiles / 4));
-  leaf_cap = std::max<int64_t>(leaf_cap, (int64_t)(ws.leaves.bytes / sizeof(int32_t)));
-  partial_cap =
-      std::max<int64_t>(partial_cap, (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T)));
+  const int64_t tiles = (int64_t)std::ceil((double)n_tiles * headroom);
+  const int64_t nr = std::max<int64_t>(64, (int64_t)std::ceil((double)n_rois * headroom));
+  const int64_t nc = std::max<int64_t>(1024, (int64_t)std::ceil((double)n_coords * headroom));
+  int64_t leaf_cap = std::max<int64_t>(ws.want_leaf_cap, std::max<int64_t>(1 << 20, 64 * tiles));
+  int64_t partial_cap = std::max<int64_t>(ws.want_partial_cap, std::max<int64_t>(1 << 14, tiles / 4));
   if (c->opts.list_capacity > 0) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
   }
-  const int64_t item_cap = n_tiles + leaf_cap / CH + 1;
-  SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)n_tiles, "tile counts"));
-  SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)n_tiles, "tile flags"));
-  SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)n_tiles, "tile counters"));
-  SFK_TRY(ws_reserve(c, ws, ws.leaf_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "leaf offsets"));
-  SFK_TRY(ws_reserve(c, ws, ws.partial_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "partial offsets"));
-  SFK_TRY(ws_reserve(c, ws, ws.chunk_off, sizeof(int64_t) * (size_t)(n_tiles + 1), "item offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)tiles, "tile counts"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)tiles, "tile flags"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)tiles, "tile counters"));
+  SFK_TRY(ws_reserve(c, ws, ws.leaf_off, sizeof(int64_t) * (size_t)(tiles + 1), "leaf offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.partial_off, sizeof(int64_t) * (size_t)(tiles + 1), "partial offsets"));
+  SFK_TRY(ws_reserve(c, ws, ws.chunk_off, sizeof(int64_t) * (size_t)(tiles + 1), "item offsets"));
   SFK_TRY(ws_reserve(c, ws, ws.leaves, sizeof(int32_t) * (size_t)leaf_cap, "leaf lists"));
-  SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)item_cap, "work items"));
   SFK_TRY(ws_reserve(c, ws, ws.partials, sizeof(double) * (size_t)partial_cap * T, "partial sums"));
-  SFK_TRY(ws_reserve(c, ws, ws.hdr, sizeof(BatchHdr), "batch header"));
-  BatchHdr* hdr = (BatchHdr*)ws.hdr.p;
+  SFK_TRY(ws_reserve(c, ws, ws.hdr_rois, sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)nr,
+                     "ROI descriptors"));
+  SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)nc, "node coordinates"));
+  Caps k;
+  k.tiles_cap = std::min<int64_t>({(int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
+                                   (int64_t)(ws.tile_fit.bytes / sizeof(int32_t)),
+                                   (int64_t)(ws.tile_done.bytes / sizeof(int32_t)),
+                                   (int64_t)(ws.leaf_off.bytes / sizeof(int64_t)) - 1,
+                                   (int64_t)(ws.partial_off.bytes / sizeof(int64_t)) - 1,
+                                   (int64_t)(ws.chunk_off.bytes / sizeof(int64_t)) - 1});
+  k.leaf_cap = c->opts.list_capacity > 0 ? leaf_cap : (int64_t)(ws.leaves.bytes / sizeof(int32_t));
+  k.partial_cap = c->opts.list_capacity > 0
+                      ? partial_cap
+                      : (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T));
+  k.rois_cap = (int64_t)((ws.hdr_rois.bytes - sizeof(BatchHdr)) / sizeof(RoiDev));
+  k.coords_cap = (int64_t)(ws.coords.bytes / sizeof(double));
+  k.item_cap = k.tiles_cap + k.leaf_cap / CH + 1;
+  SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)k.item_cap, "work items"));
+  *caps = k;
+  return SFK_OK;
+}
+
+// The batch header a group stages in front of its descriptors.
+BatchHdr make_hdr(const Caps& k, int64_t n_rois, int64_t n_tiles) {
+  BatchHdr h{};
+  h.n_tiles = n_tiles;
+  h.leaf_cap = k.leaf_cap;
+  h.partial_cap = k.partial_cap;
+  h.item_cap = k.item_cap;
+  h.n_rois = (int32_t)n_rois;
+  h.next_item = 0;
+  return h;
+}
+
+// Enqueue the kernels of one group whose header + descriptors are already
+// (being) copied into ws.hdr_rois. roi_grid / tile_grid: blocks of the
+// coordinate and tile kernels (exact for direct launches, capacities for a
+// captured graph).
+sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
+                          Workspace& ws, int roi_grid, int tile_grid, hipStream_t s) {
+  const int CH = chunk_leaves_of(c);
+  BatchHdr* hdr = (BatchHdr*)ws.hdr_rois.p;
+  const RoiDev* rois = (const RoiDev*)((char*)ws.hdr_rois.p + sizeof(BatchHdr));
+  double* coords = (double*)ws.coords.p;
   int32_t* tile_cnt = (int32_t*)ws.tile_cnt.p;
   int32_t* tile_fit = (int32_t*)ws.tile_fit.p;
   int32_t* tile_done = (int32_t*)ws.tile_done.p;
   int64_t* leaf_off = (int64_t*)ws.leaf_off.p;
   int64_t* partial_off = (int64_t*)ws.partial_off.p;
   int64_t* chunk_off = (int64_t*)ws.chunk_off.p;
-  SFK_HIP(c, sfk::launch_hdr_init(hdr, n_tiles, leaf_cap, item_cap, s));
+  SFK_HIP(c, sfk::launch_roi_coords(hdr, rois, roi_grid, coords, s));
   {
     ProfScope p(c, PK_TILE_COUNT, s);
-    SFK_HIP(c, sfk::launch_tile_count(tv, rois_dev, n_rois, coords, ts, n_tiles, CH, tile_cnt,
-                                       nullptr, tile_done, s));
+    SFK_HIP(c, sfk::launch_tile_count(tv, hdr, rois, coords, ts, tile_grid, tile_cnt, tile_done, s));
   }
   {
     ProfScope p(c, PK_PLAN, s);
-    SFK_HIP(c, sfk::launch_plan(tile_cnt, n_tiles, CH, leaf_cap, partial_cap, leaf_off,
-                                 partial_off, chunk_off, tile_fit, hdr, s));
+    SFK_HIP(c, sfk::launch_plan(tile_cnt, hdr, CH, leaf_off, partial_off, chunk_off, tile_fit, s));
   }
   {
     ProfScope p(c, PK_TILE_FILL, s);
-    SFK_HIP(c, sfk::launch_tile_fill2(tv, rois_dev, n_rois, coords, ts, n_tiles, tile_cnt,
-                                       tile_fit, leaf_off, chunk_off, (int32_t*)ws.leaves.p,
-                                       (int32_t*)ws.item_tile.p, s));
+    SFK_HIP(c, sfk::launch_tile_fill(tv, hdr, rois, coords, ts, tile_grid, tile_cnt, tile_fit,
+                                      leaf_off, chunk_off, (int32_t*)ws.leaves.p,
+                                      (int32_t*)ws.item_tile.p, s));
   }
   const int grid = c->opts.persistent_waves_per_cu > 0
                        ? c->n_cu * std::max(1, c->opts.persistent_waves_per_cu / 4)
                        : 0;  // 0: resident blocks per CU from the occupancy query
   {
     ProfScope p(c, PK_EVAL, s, hdr);
-    SFK_HIP(c, sfk::launch_eval2(tv, rois_dev, n_rois, coords, ts, kk, pp, cnt, CH, leaf_off,
-                                  chunk_off, partial_off, tile_cnt, tile_fit,
-                                  (int32_t*)ws.leaves.p, (int32_t*)ws.item_tile.p,
-                                  (double*)ws.partials.p, tile_done, hdr, grid, c->n_cu, s));
+    SFK_HIP(c, sfk::launch_eval(tv, hdr, rois, coords, ts, kk, pp, cnt, CH, leaf_off, chunk_off,
+                                 partial_off, tile_cnt, tile_fit, (int32_t*)ws.leaves.p,
+                                 (int32_t*)ws.item_tile.p, (double*)ws.partials.p, tile_done,
+                                 hdr, grid, c->n_cu, s));
   }
   return SFK_OK;
 }
@@ -634,54 +693,144 @@ GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
   return g;
 }
 
-// Enqueue descriptors + pipeline for CLOUD-set ROIs grouped by (kernel, pp).
-sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
-                              bool count_mode, TileShape ts, Workspace& ws, Staging& st,
-                              hipStream_t s) {
-  if (rois.empty()) return SFK_OK;
-  // groups in a fixed order
-  std::vector<std::vector<GroupRoi>> groups;
-  std::vector<std::pair<int, int>> keys;
+// Group CLOUD-set ROIs by (kernel, bandwidth source), in a fixed order.
+void group_rois(sfk_tree t, const std::vector<const sfk_roi*>& rois, bool count_mode,
+                std::vector<std::vector<GroupRoi>>* groups, std::vector<std::pair<int, int>>* keys) {
   for (const sfk_roi* r : rois) {
     GroupRoi g = resolve_cloud_roi(t, r, count_mode);
     const std::pair<int, int> key{count_mode ? 0 : g.kk, g.pp};
     size_t gi = 0;
-    while (gi < keys.size() && keys[gi] != key) ++gi;
-    if (gi == keys.size()) {
-      keys.push_back(key);
-      groups.emplace_back();
+    while (gi < keys->size() && (*keys)[gi] != key) ++gi;
+    if (gi == keys->size()) {
+      keys->push_back(key);
+      groups->emplace_back();
     }
-    groups[gi].push_back(g);
+    (*groups)[gi].push_back(g);
   }
-  const int n = (int)rois.size();
-  SFK_TRY(staging_reserve(c, st, n));
+}
+
+// Enqueue CLOUD-set ROIs, one pipeline per (kernel, bandwidth) group, with
+// direct launches sized to the batch.
+sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
+                              bool count_mode, TileShape ts, Workspace& ws, Staging& st,
+                              hipStream_t s) {
+  if (rois.empty()) return SFK_OK;
+  std::vector<std::vector<GroupRoi>> groups;
+  std::vector<std::pair<int, int>> keys;
+  group_rois(t, rois, count_mode, &groups, &keys);
+  size_t bytes = 0;
+  for (auto& g : groups) bytes += sizeof(BatchHdr) + sizeof(RoiDev) * g.size();
+  SFK_TRY(staging_reserve(c, st, bytes));
   if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
-  std::vector<int64_t> tiles(groups.size()), ncoord(groups.size());
-  int off = 0;
-  int64_t coord_total = 0;
-  std::vector<int> roi_off(groups.size());
+  TreeView tv = view_of(t);
+  size_t off = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
-    roi_off[gi] = off;
-    make_roidev(groups[gi], ts, st.host + off, &tiles[gi], &ncoord[gi]);
-    for (size_t i = 0; i < groups[gi].size(); ++i) st.host[off + i].coord_off += (int32_t)coord_total;
-    off += (int)groups[gi].size();
-    coord_total += ncoord[gi];
+    const int64_t n = (int64_t)groups[gi].size();
+    BatchHdr* h = (BatchHdr*)(st.host + off);
+    RoiDev* rd = (RoiDev*)(st.host + off + sizeof(BatchHdr));
+    int64_t n_tiles = 0, n_coords = 0;
+    make_roidev(groups[gi], ts, rd, &n_tiles, &n_coords);
+    Caps k;
+    SFK_TRY(reserve_group(c, ws, ts, n, n_tiles, n_coords, 1.0, &k));
+    *h = make_hdr(k, n, n_tiles);
+    const size_t gb = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
+    SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host + off, gb, hipMemcpyHostToDevice, s));
+    SFK_TRY(launch_kernels(c, tv, ts, keys[gi].first, keys[gi].second, count_mode, ws, (int)n,
+                           sfk::tile_grid_blocks(n_tiles), s));
+    off += gb;
   }
-  SFK_TRY(ws_reserve(c, ws, ws.rois, sizeof(RoiDev) * (size_t)n, "ROI descriptors"));
-  SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)coord_total, "node coordinates"));
-  RoiDev* rd = (RoiDev*)ws.rois.p;
-  SFK_HIP(c, hipMemcpyAsync(rd, st.host, sizeof(RoiDev) * (size_t)n, hipMemcpyHostToDevice, s));
   SFK_HIP(c, hipEventRecord(st.ev, s));
   st.ev_valid = true;
-  SFK_HIP(c, sfk::launch_roi_coords(rd, n, (double*)ws.coords.p, s));
-  TreeView tv = view_of(t);
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const int kk = keys[gi].first, pp = keys[gi].second;
-    SFK_TRY(launch_group(c, tv, ts, kk, pp, count_mode, rd + roi_off[gi], (int)groups[gi].size(),
-                         tiles[gi], (const double*)ws.coords.p, ws, s));
+  SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+  return SFK_OK;
+}
+
+void drop_graph(GraphCache& gc) {
+  if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  if (gc.graph) (void)hipGraphDestroy(gc.graph);
+  gc = GraphCache();
+}
+
+// Enqueue a single-group batch on an idle slot through its captured graph,
+// capturing (again) when the key, the workspace or the capacities changed.
+sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
+                                    const std::vector<const sfk_roi*>& rois, TileShape ts,
+                                    Slot& sl) {
+  std::vector<std::vector<GroupRoi>> groups;
+  std::vector<std::pair<int, int>> keys;
+  group_rois(t, rois, false, &groups, &keys);
+  if (groups.size() != 1)
+    return enqueue_cloud_rois(c, t, rois, false, ts, sl.ws, sl.st, sl.stream);
+  const int64_t n = (int64_t)groups[0].size();
+  const int kk = keys[0].first, pp = keys[0].second, ch = chunk_leaves_of(c);
+  std::vector<RoiDev> rd((size_t)n);
+  int64_t n_tiles = 0, n_coords = 0;
+  make_roidev(groups[0], ts, rd.data(), &n_tiles, &n_coords);
+  GraphCache& gc = sl.gc;
+  const bool fits = gc.valid && gc.gen == sl.ws.gen && gc.tree == t && gc.kk == kk &&
+                    gc.pp == pp && gc.ch == ch && !gc.cnt && gc.ts.tx == ts.tx &&
+                    gc.ts.ty == ts.ty && gc.ts.tz == ts.tz && n <= gc.rois_cap &&
+                    n_tiles <= gc.tiles_cap && n_coords <= gc.coords_cap;
+  Caps k;
+  if (!fits) {
+    drop_graph(gc);
+    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, &k));
+  } else {
+    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 1.0, &k));
+    if (sl.ws.gen != gc.gen) {  // a buffer moved after all
+      drop_graph(gc);
+      SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, &k));
+    }
   }
-  if (st.hdr_host)
-    SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+  const size_t full = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)k.rois_cap;
+  SFK_TRY(staging_reserve(c, sl.st, full));
+  BatchHdr* h = (BatchHdr*)sl.st.host;
+  *h = make_hdr(k, n, n_tiles);
+  std::memcpy(sl.st.host + sizeof(BatchHdr), rd.data(), sizeof(RoiDev) * (size_t)n);
+  if (!gc.valid) {
+    // profiling events cannot be recorded inside a capture
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    const hipStream_t s = sl.stream;
+    SFK_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    sfk_status st = SFK_OK;
+    if (hipMemcpyAsync(sl.ws.hdr_rois.p, sl.st.host, full, hipMemcpyHostToDevice, s) != hipSuccess)
+      st = SFK_E_DEVICE;
+    if (st == SFK_OK)
+      st = launch_kernels(c, view_of(t), ts, kk, pp, false, sl.ws, (int)k.rois_cap,
+                          c->n_cu * 4, s);
+    if (st == SFK_OK && hipMemcpyAsync(sl.st.hdr_host, sl.ws.hdr_rois.p, sizeof(BatchHdr),
+                                       hipMemcpyDeviceToHost, s) != hipSuccess)
+      st = SFK_E_DEVICE;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    c->prof_on = prof;
+    if (st != SFK_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      set_err(c, "capturing the batch graph failed");
+      return st != SFK_OK ? st : SFK_E_DEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      set_err(c, "instantiating the batch graph failed");
+      return SFK_E_DEVICE;
+    }
+    gc.valid = true;
+    gc.ts = ts;
+    gc.kk = kk;
+    gc.pp = pp;
+    gc.ch = ch;
+    gc.cnt = false;
+    gc.tree = t;
+    gc.gen = sl.ws.gen;
+    gc.tiles_cap = k.tiles_cap;
+    gc.rois_cap = k.rois_cap;
+    gc.coords_cap = k.coords_cap;
+    gc.graph = graph;
+    gc.exec = exec;
+  }
+  SFK_HIP(c, hipGraphLaunch(gc.exec, sl.stream));
   return SFK_OK;
 }
 
@@ -792,18 +941,19 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     GroupRoi gg = g;
     gg.roi = &rr;
     std::vector<GroupRoi> v{gg};
-    SFK_TRY(staging_reserve(c, st, 1));
+    const size_t gb = sizeof(BatchHdr) + sizeof(RoiDev);
+    SFK_TRY(staging_reserve(c, st, gb));
     if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
     int64_t n_tiles = 0, n_coords = 0;
-    make_roidev(v, ts, st.host, &n_tiles, &n_coords);
-    SFK_TRY(ws_reserve(c, ws, ws.rois, sizeof(RoiDev), "ROI descriptors"));
-    SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)n_coords, "node coordinates"));
-    SFK_HIP(c, hipMemcpyAsync(ws.rois.p, st.host, sizeof(RoiDev), hipMemcpyHostToDevice, s));
+    make_roidev(v, ts, (RoiDev*)(st.host + sizeof(BatchHdr)), &n_tiles, &n_coords);
+    Caps k;
+    SFK_TRY(reserve_group(c, ws, ts, 1, n_tiles, n_coords, 1.0, &k));
+    *(BatchHdr*)st.host = make_hdr(k, 1, n_tiles);
+    SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host, gb, hipMemcpyHostToDevice, s));
     SFK_HIP(c, hipEventRecord(st.ev, s));
     st.ev_valid = true;
-    SFK_HIP(c, sfk::launch_roi_coords((RoiDev*)ws.rois.p, 1, (double*)ws.coords.p, s));
-    return launch_group(c, tv, ts, g.count_mode ? 0 : g.kk, g.pp, g.count_mode,
-                        (const RoiDev*)ws.rois.p, 1, n_tiles, (const double*)ws.coords.p, ws, s);
+    return launch_kernels(c, tv, ts, g.count_mode ? 0 : g.kk, g.pp, g.count_mode, ws, 1,
+                          sfk::tile_grid_blocks(n_tiles), s);
   };
 
   if (!mbe) {
@@ -976,7 +1126,10 @@ sfk_status launch_ticket(sfk_ctx c, Ticket& tk, Slot& sl) {
   if (!cloud.empty()) {
     // one tile shape per batch: the autotuned choice of the first ROI
     const TileShape ts = choose_shape(c, tk.tree, cloud[0]);
-    SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, ts, sl.ws, sl.st, sl.stream));
+    if (c->opts.disable_graphs)
+      SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, ts, sl.ws, sl.st, sl.stream));
+    else
+      SFK_TRY(enqueue_cloud_rois_graph(c, tk.tree, cloud, ts, sl));
   }
   for (const sfk_roi* r : sub)
     SFK_TRY(eval_subcloud(c, tk.tree, r, false, shape_of(1), sl.ws, sl.st, sl.stream, nullptr));
@@ -1135,9 +1288,9 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
 }
 
 static void release_ws(sfk_ctx c, Workspace& ws) {
-  DevBuf* bufs[] = {&ws.rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
+  DevBuf* bufs[] = {&ws.hdr_rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
                     &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
-                    &ws.partials, &ws.hdr};
+                    &ws.partials};
   for (DevBuf* b : bufs) ws_release(c, *b);
 }
 
@@ -1156,6 +1309,7 @@ sfk_status sfk_ctx_destroy(sfk_ctx c) {
   for (int i = 0; i < kNumSlots; ++i) {
     Slot& sl = c->slots[i];
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    drop_graph(sl.gc);
     release_ws(c, sl.ws);
     release_staging(sl.st);
     if (sl.done) (void)hipEventDestroy(sl.done);
@@ -1416,7 +1570,8 @@ sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
   }
   if (opts->tile_shape < 0 || opts->tile_shape > 4 || opts->chunk_leaves < 0 ||
       opts->chunk_leaves > (1 << 20) || opts->persistent_waves_per_cu < 0 ||
-      opts->persistent_waves_per_cu > 64 || opts->list_capacity < 0) {
+      opts->persistent_waves_per_cu > 64 || opts->list_capacity < 0 ||
+      opts->disable_graphs < 0 || opts->disable_graphs > 1) {
     set_err(c, "evaluation options out of range");
     return SFK_E_INVAL;
   }
@@ -1609,14 +1764,21 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   RoiDev rd;
   int64_t n_tiles, n_coords;
   make_roidev(v, ts, &rd, &n_tiles, &n_coords);
-  TmpBuf rdev(c), coords(c), cnt(c), off(c), idx(c);
-  SFK_TRY(rdev.get(sizeof(RoiDev), "descriptor"));
+  TmpBuf hdev(c), coords(c), cnt(c), off(c), idx(c);
+  SFK_TRY(hdev.get(sizeof(BatchHdr) + sizeof(RoiDev), "descriptor"));
   SFK_TRY(coords.get(sizeof(double) * (size_t)n_coords, "coordinates"));
   SFK_TRY(cnt.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "counts"));
-  SFK_HIP(c, hipMemcpy(rdev.b.p, &rd, sizeof rd, hipMemcpyHostToDevice));
-  SFK_HIP(c, sfk::launch_roi_coords(rdev.as<RoiDev>(), 1, coords.as<double>(), s));
+  {
+    BatchHdr h{};
+    h.n_rois = 1;
+    h.n_tiles = n_tiles;
+    SFK_HIP(c, hipMemcpy(hdev.b.p, &h, sizeof h, hipMemcpyHostToDevice));
+    SFK_HIP(c, hipMemcpy((char*)hdev.b.p + sizeof(BatchHdr), &rd, sizeof rd, hipMemcpyHostToDevice));
+  }
+  const RoiDev* rdev_p = (const RoiDev*)((char*)hdev.b.p + sizeof(BatchHdr));
+  SFK_HIP(c, sfk::launch_roi_coords(hdev.as<BatchHdr>(), rdev_p, 1, coords.as<double>(), s));
   TreeView tv = view_of(t);
-  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
+  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev_p,
                                             coords.as<double>(), ts, node_begin, node_end,
                                             cnt.as<int64_t>(), nullptr, nullptr, s));
   std::vector<int64_t> counts(nn);
@@ -1629,7 +1791,7 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   SFK_TRY(off.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "offsets"));
   SFK_TRY(idx.get(sizeof(int32_t) * (size_t)std::max<int64_t>(*needed, 1), "indices"));
   SFK_HIP(c, hipMemcpy(off.b.p, h_offsets, sizeof(int64_t) * nn, hipMemcpyHostToDevice));
-  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev.as<RoiDev>(),
+  SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev_p,
                                             coords.as<double>(), ts, node_begin, node_end, nullptr,
                                             off.as<int64_t>(), idx.as<int32_t>(), s));
   std::vector<int32_t> ix(*needed);
@@ -1690,7 +1852,7 @@ sfk_status sfk_debug_eval_count(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
     int64_t tested = 0;
     if (roi->set == SFK_SET_CLOUD) {
       BatchHdr hh;
-      SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr.p, sizeof hh, hipMemcpyDeviceToHost));
+      SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr_rois.p, sizeof hh, hipMemcpyDeviceToHost));
       const TileShape ts = choose_shape(c, t, roi);
       tested = hh.total_leaves * SFK_LEAF * (int64_t)(ts.tx * ts.ty * ts.tz);
     }
@@ -1982,7 +2144,10 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
         batched_reqs += (int64_t)batch.size();
         sl.busy = true;
         sl.ticket = -1;
-        SFK_TRY(enqueue_cloud_rois(c, t, batch, false, ts, sl.ws, sl.st, sl.stream));
+        if (c->opts.disable_graphs)
+          SFK_TRY(enqueue_cloud_rois(c, t, batch, false, ts, sl.ws, sl.st, sl.stream));
+        else
+          SFK_TRY(enqueue_cloud_rois_graph(c, t, batch, ts, sl));
         SFK_HIP(c, hipEventRecord(sl.done, sl.stream));
         slot_bytes[si] = bytes;
         in_flight += bytes;

@@ -10,6 +10,7 @@ from .clouds import (  # noqa: F401
     Roi,
     c1_cloud,
     clumpy_cloud,
+    clumpy_cloud_device,
     lattice_cloud,
     uniform_cloud,
     blob_cloud,

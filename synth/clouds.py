@@ -19,7 +19,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 __all__ = [
-    "Roi", "c1_cloud", "clumpy_cloud", "lattice_cloud", "uniform_cloud",
+    "Roi", "c1_cloud", "clumpy_cloud", "clumpy_cloud_device", "lattice_cloud", "uniform_cloud",
     "blob_cloud", "paperlike_cloud", "c1_roi", "c2_roi", "nested_zoom_rois",
     "random_batch_rois", "serving_trace",
 ]
@@ -296,3 +296,66 @@ def serving_trace(seed: int, duration_s: float, n_streams: int = 8,
     for k, r in enumerate(rs):
         r.tag = k
     return arr, st, rs
+
+
+def clumpy_cloud_device(n: int, seed: int, device="cuda", n_clumps: int = 2000,
+                        bg_frac: float = 0.2, m_lo: float = 1.0, m_hi: float = 1e3,
+                        index: float = -1.8, chunk: int = 1 << 25):
+    """The `clumpy_cloud` recipe drawn on the GPU with torch's seeded Philox
+    generator, for clouds too large to draw on the host (1e8-1e9 points).
+    Same distribution, different random stream: the points differ from
+    `clumpy_cloud(n, seed)`. Returns an (n, 3) float32 device tensor; the
+    clump metadata is drawn on the host with numpy (seeded) and returned.
+    Out-of-box samples are redrawn."""
+    import torch
+    g = _rng(seed)
+    a = index + 1.0
+    u = g.random(n_clumps)
+    masses = (m_lo ** a + u * (m_hi ** a - m_lo ** a)) ** (1.0 / a)
+    centres = g.uniform(0.05, 0.95, size=(n_clumps, 3))
+    s1 = 0.02 * (masses / m_hi) ** (1.0 / 3.0)
+    q = g.uniform(0.3, 1.0, size=(n_clumps, 2))
+    sig = np.stack([s1, s1 * q[:, 0], s1 * q[:, 1]], axis=1)
+    quat = g.standard_normal((n_clumps, 4))
+    quat /= np.linalg.norm(quat, axis=1, keepdims=True)
+    rot = _quat_rot(quat)
+    n_bg = int(round(bg_frac * n))
+    counts = g.multinomial(n - n_bg, masses / masses.sum())
+    tg = torch.Generator(device=device)
+    tg.manual_seed(int(seed))
+    out = torch.empty((n, 3), dtype=torch.float32, device=device)
+    pos = 0
+    while pos < n_bg:
+        k = min(chunk, n_bg - pos)
+        out[pos:pos + k] = torch.rand((k, 3), generator=tg, device=device, dtype=torch.float32)
+        pos += k
+    c_t = torch.as_tensor(centres, dtype=torch.float64, device=device)
+    s_t = torch.as_tensor(sig, dtype=torch.float64, device=device)
+    r_t = torch.as_tensor(rot, dtype=torch.float64, device=device)
+    cum = np.concatenate([[0], np.cumsum(counts)])
+    cid = 0
+    while cid < n_clumps:
+        stop = cid
+        while stop < n_clumps and (stop == cid or cum[stop + 1] - cum[cid] <= chunk):
+            stop += 1
+        tot = int(cum[stop] - cum[cid])
+        ids = torch.repeat_interleave(torch.arange(cid, stop, device=device),
+                                      torch.as_tensor(counts[cid:stop], device=device))
+
+        def draw(sel):
+            z = torch.randn((sel.shape[0], 3), generator=tg, device=device,
+                            dtype=torch.float64) * s_t[sel]
+            r = r_t[sel]
+            rz = r[:, :, 0] * z[:, 0:1] + r[:, :, 1] * z[:, 1:2] + r[:, :, 2] * z[:, 2:3]
+            return c_t[sel] + rz
+
+        pts = draw(ids)
+        bad = ~((pts >= 0) & (pts <= 1)).all(dim=1)
+        while bool(bad.any()):
+            pts[bad] = draw(ids[bad])
+            bad = ~((pts >= 0) & (pts <= 1)).all(dim=1)
+        out[pos:pos + tot] = pts.to(torch.float32)
+        pos += tot
+        cid = stop
+    assert pos == n
+    return out, ClumpInfo(centres, masses, s1, counts)

@@ -512,3 +512,32 @@ def test_autotune(ctx, torch):
         big = ref >= 1e-3 * peak
         if big.any():
             assert np.max(np.abs(got[big] - ref[big]) / ref[big]) <= REL_TOL
+
+
+# ---------------------------------------------------------------------------
+# captured-graph submit path: replays (and recaptures as batches grow) give
+# the same grids as direct launches and as one-ROI evaluation
+# ---------------------------------------------------------------------------
+
+def test_graph_replays_match_direct(ctx, torch):
+    pts = synth.clumpy_cloud(150_000, 12)
+    tree = ctx.build_tree(dev(torch, pts))
+    batches = [synth.random_batch_rois(k, seed=20 + i, side_lo=0.05, res_lo=8, res_hi=36, h0=0.02)
+               for i, k in enumerate([5, 5, 9, 3, 17, 5])]
+    for rep in range(2):  # the second pass replays graphs captured in the first
+        for rois in batches:
+            outs = [torch.full((r.n_nodes,), -1.0, device="cuda") for r in rois]
+            ctx.wait(ctx.submit(tree, rois, outs))
+            # eager work between replays
+            alone = [ctx.eval_roi(tree, r).cpu().numpy() for r in rois]
+            for a, o in zip(alone, outs):
+                assert np.array_equal(a, o.cpu().numpy())
+    ctx.set_eval_opts(disable_graphs=True)
+    rois = batches[4]
+    outs = [torch.zeros((r.n_nodes,), device="cuda") for r in rois]
+    ctx.wait(ctx.submit(tree, rois, outs))
+    ctx.set_eval_opts()
+    outs2 = [torch.zeros((r.n_nodes,), device="cuda") for r in rois]
+    ctx.wait(ctx.submit(tree, rois, outs2))
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
