@@ -65,6 +65,7 @@ struct Workspace {
 struct Staging {
   char* host = nullptr;  // pinned: per group [BatchHdr][RoiDev...]
   size_t cap = 0;        // bytes
+  uint64_t gen = 0;      // bumped when `host` is replaced (captured copies go stale)
   BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header
   hipEvent_t ev = nullptr;
   bool ev_valid = false;
@@ -78,7 +79,7 @@ struct GraphCache {
   int kk = 0, pp = 0, ch = 0;
   bool cnt = false;
   sfk_tree tree = nullptr;
-  uint64_t gen = 0;
+  uint64_t gen = 0, st_gen = 0;
   int64_t tiles_cap = 0, rois_cap = 0, coords_cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -345,6 +346,7 @@ sfk_status staging_reserve(sfk_ctx c, Staging& st, size_t bytes) {
   const size_t cap = std::max<size_t>(bytes, sizeof(BatchHdr) + 64 * sizeof(RoiDev));
   SFK_HIP(c, hipHostMalloc((void**)&st.host, cap));
   st.cap = cap;
+  ++st.gen;
   return SFK_OK;
 }
 
@@ -767,7 +769,8 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   int64_t n_tiles = 0, n_coords = 0;
   make_roidev(groups[0], ts, rd.data(), &n_tiles, &n_coords);
   GraphCache& gc = sl.gc;
-  const bool fits = gc.valid && gc.gen == sl.ws.gen && gc.tree == t && gc.kk == kk &&
+  const bool fits = gc.valid && gc.gen == sl.ws.gen && gc.st_gen == sl.st.gen && gc.tree == t &&
+                    gc.kk == kk &&
                     gc.pp == pp && gc.ch == ch && !gc.cnt && gc.ts.tx == ts.tx &&
                     gc.ts.ty == ts.ty && gc.ts.tz == ts.tz && n <= gc.rois_cap &&
                     n_tiles <= gc.tiles_cap && n_coords <= gc.coords_cap;
@@ -784,6 +787,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   }
   const size_t full = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)k.rois_cap;
   SFK_TRY(staging_reserve(c, sl.st, full));
+  if (gc.valid && gc.st_gen != sl.st.gen) drop_graph(gc);
   BatchHdr* h = (BatchHdr*)sl.st.host;
   *h = make_hdr(k, n, n_tiles);
   std::memcpy(sl.st.host + sizeof(BatchHdr), rd.data(), sizeof(RoiDev) * (size_t)n);
@@ -824,6 +828,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
     gc.cnt = false;
     gc.tree = t;
     gc.gen = sl.ws.gen;
+    gc.st_gen = sl.st.gen;
     gc.tiles_cap = k.tiles_cap;
     gc.rois_cap = k.rois_cap;
     gc.coords_cap = k.coords_cap;
@@ -1552,6 +1557,9 @@ sfk_status sfk_tree_destroy(sfk_tree t) {
   sfk_ctx c = t->ctx;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  // graphs captured against this tree hold its device pointers
+  for (int i = 0; i < kNumSlots; ++i)
+    if (c->slots[i].gc.tree == t) drop_graph(c->slots[i].gc);
   tree_free(c, t, t->pts);
   tree_free(c, t, t->perm);
   tree_free(c, t, t->nodes);

@@ -541,3 +541,23 @@ def test_graph_replays_match_direct(ctx, torch):
     ctx.wait(ctx.submit(tree, rois, outs2))
     for a, b in zip(outs, outs2):
         assert torch.equal(a, b)
+
+
+def test_graph_cache_survives_tree_replacement(ctx, torch):
+    # a new tree (possibly at a recycled address) must not replay a graph
+    # captured for a destroyed one
+    rois = synth.random_batch_rois(4, seed=31, side_lo=0.1, res_lo=8, res_hi=20, h0=0.03)
+    for seed in (1, 2, 3):
+        pts = synth.clumpy_cloud(40_000, seed)
+        tree = ctx.build_tree(dev(torch, pts))
+        outs = [torch.zeros((r.n_nodes,), device="cuda") for r in rois]
+        ctx.wait(ctx.submit(tree, rois, outs))
+        for r, o in zip(rois, outs):
+            assert np.array_equal(o.cpu().numpy(), ctx.eval_roi(tree, r).cpu().numpy())
+        nodes = sample_nodes(None, rois[0].n_nodes, 12, seed)
+        ref = oracle.density(pts, rois[0], nodes=nodes)
+        got = outs[0].cpu().numpy()[nodes]
+        big = ref >= 1e-3 * max(ref.max(), 1e-300)
+        if big.any():
+            assert np.max(np.abs(got[big] - ref[big]) / ref[big]) <= REL_TOL
+        tree.close()
