@@ -7,6 +7,7 @@ include/sfkde.h (sfk_build_tree -> Context.build_tree, ...).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import weakref
 from typing import Optional, Sequence
@@ -78,14 +79,20 @@ class Context:
         if allocator == "torch":
             import torch
 
+            alloc_fn = torch.cuda.caching_allocator_alloc
+            free_fn = torch.cuda.caching_allocator_delete
+
             def _a(nbytes, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+                    return alloc_fn(int(nbytes), device)
                 except Exception:  # out of memory -> NULL -> SFK_E_NOMEM
                     return None
 
             def _f(ptr, nbytes, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    free_fn(ptr)
+                except Exception:  # interpreter shutdown: the process frees it
+                    pass
 
             self._alloc = L.Allocator(L.Allocator.ALLOC(_a), L.Allocator.FREE(_f), None)
             ap = C.byref(self._alloc)
@@ -94,6 +101,8 @@ class Context:
         st = self._lib.sfk_ctx_create(device, ap, int(budget_bytes), C.byref(self._h))
         if st != L.SFK_OK:
             raise SfkError(st, self._lib.sfk_last_error(None).decode())
+        # release device memory while torch is still alive
+        atexit.register(self.close)
 
     # -- helpers
     def _check(self, st):

@@ -36,7 +36,7 @@ thread_local std::string g_tls_err;
 
 constexpr int kNumSlots = 4;
 constexpr int kStagingRing = 8;
-constexpr int kDefaultChunkLeaves = 64;
+constexpr int kDefaultChunkLeaves = 256;
 
 double now_s() {
   using namespace std::chrono;
