@@ -419,36 +419,86 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // ---------------------------------------------------------------------------
 // k-th nearest neighbour squared distance (per-point bandwidth).
 // One wavefront per leaf, one query particle per lane; each lane keeps its
-// KM smallest squared distances in a sorted register array and its current
-// k-th smallest as a threshold. Pass 1 scans the leaf and its Morton
-// neighbours, which bounds every lane's answer from above by real
-// distances. Pass 2 walks the box hierarchy with the wavefront's largest
-// threshold (a box farther than that cannot hold a closer particle) and,
-// per leaf, skips it unless some lane's own threshold exceeds that lane's
-// distance to the leaf box. Exact: the same canonical float32 distances as
-// the definition, selected without approximation.
+// KM smallest squared distances in a sorted register array whose last slot
+// is its current k-th smallest (the threshold). The lane's own leaf and its
+// two Morton neighbours come first and bound every answer from above by
+// real distances. The box hierarchy is then walked with the wavefront's
+// largest threshold (a box farther than that cannot hold a closer
+// particle); the leaves it yields are kept in a per-wave list and visited
+// nearest-first in three distance bands, so thresholds shrink early. Per
+// visited leaf a lane takes part only if its own threshold exceeds its
+// distance to the leaf box, and per group of 8 particles only if it exceeds
+// its distance to that group's box. Exact: the canonical float32 distances
+// of the definition, selected without approximation; every pruning bound
+// uses the same rounded operations, so by monotonicity of rounding it never
+// exceeds a distance it stands for.
 // ---------------------------------------------------------------------------
 
-template <int KM>
-__device__ __forceinline__ void knn_insert(float (&a)[KM], float x) {
+constexpr int kKnnSub = 8;                          // particles per sub-block
+constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
+constexpr int kKnnList = 256;                       // leaves held for ordering
+
+// Boxes of the sub-blocks of 8 consecutive particles: 6 floats (lo, hi) per
+// sub-block. A sub-block without real particles gets an empty box, whose
+// distance to any point is infinite.
+__global__ __launch_bounds__(256) void k_sub_boxes(const float4* __restrict__ pts, int64_t n,
+                                                   int64_t n_slots, float* __restrict__ out) {
+  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < n_slots;
+       slot += (int64_t)gridDim.x * blockDim.x) {
+    const float4 p = pts[slot];
+    const bool real = slot < n && p.x < 1.0e29f;
+    float v[6] = {real ? p.x : 3.0e38f,  real ? p.y : 3.0e38f,  real ? p.z : 3.0e38f,
+                  real ? p.x : -3.0e38f, real ? p.y : -3.0e38f, real ? p.z : -3.0e38f};
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    const float t = a[i];
-    a[i] = fminf(t, x);
-    x = fmaxf(t, x);
+    for (int off = 1; off < kKnnSub; off <<= 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[c] = fminf(v[c], __shfl_xor(v[c], off, 64));
+        v[c + 3] = fmaxf(v[c + 3], __shfl_xor(v[c + 3], off, 64));
+      }
+    }
+    if ((slot & (kKnnSub - 1)) == 0) {
+      float* o = out + (slot / kKnnSub) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = v[c];
+    }
   }
 }
 
+// Insert x into the ascending array a, dropping the largest entry. Each new
+// entry is the median of (old left neighbour, x, old entry), so the updates
+// are independent of each other.
 template <int KM>
-__global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restrict__ h2_sorted) {
+__device__ __forceinline__ void knn_insert(float (&a)[KM], float x) {
+#pragma unroll
+  for (int i = KM - 1; i >= 1; --i) a[i] = __builtin_amdgcn_fmed3f(a[i - 1], x, a[i]);
+  a[0] = fminf(a[0], x);
+}
+
+// float32 squared distance from a point to a box, rounded like canon_d2
+__device__ __forceinline__ float pt_box_d2(const float* b, float x, float y, float z) {
+  const float gx = fmaxf(fmaxf(__fsub_rn(b[0], x), __fsub_rn(x, b[3])), 0.0f);
+  const float gy = fmaxf(fmaxf(__fsub_rn(b[1], y), __fsub_rn(y, b[4])), 0.0f);
+  const float gz = fmaxf(fmaxf(__fsub_rn(b[2], z), __fsub_rn(z, b[5])), 0.0f);
+  return __fadd_rn(__fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy)), __fmul_rn(gz, gz));
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
+                                             float* __restrict__ h2_sorted) {
   __shared__ float4 lds_pts[4][SFK_LEAF];
   __shared__ int32_t lds_stack[4][SFK_STACK];
-  __shared__ float lds_d2[4][16 * 64];
+  __shared__ float lds_d2[4][kKnnSub * 64];
+  __shared__ int32_t lds_lid[4][kKnnList];
+  __shared__ float lds_lkey[4][kKnnList];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   float4* lp = lds_pts[wave];
   float* ld2 = lds_d2[wave];
   int32_t* stack = lds_stack[wave];
+  int32_t* lid = lds_lid[wave];
+  float* lkey = lds_lkey[wave];
   const int nl = tv.n_leaves;
+  const NodeBox* leaf_box = tv.nodes + tv.level_off[0];
   for (int leaf = blockIdx.x * 4 + wave; leaf < nl; leaf += gridDim.x * 4) {
     const int64_t my = (int64_t)leaf * SFK_LEAF + lane;
     const float4 q = tv.pts[my];
@@ -460,31 +510,36 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restri
     for (int i = 0; i < KM; ++i) a[i] = i < KM - k ? -__builtin_huge_valf() : __builtin_huge_valf();
     float thr = __builtin_huge_valf();
 
-    auto kth = [&]() { return a[KM - 1]; };
-    // One candidate leaf: per sub-block of 16 candidates each lane marks the
-    // ones below its own threshold; the insertion network then runs once per
-    // round, a round inserting every lane's next marked candidate, so the
-    // wavefront pays max-over-lanes(marked) networks instead of one per
-    // candidate that any lane wants.
+    // One candidate leaf. Per needed sub-block each lane marks the
+    // particles below its threshold; the insertion then runs in rounds, a
+    // round inserting every lane's next marked particle.
     auto process = [&](int cl) {
-      lp[lane] = tv.pts[(int64_t)cl * SFK_LEAF + lane];
-      wave_sync();
+      const float lgap = box_gap_d2(leaf_box[cl], q.x, q.y, q.z, q.x, q.y, q.z);
+      if (!ballot(real && lgap < thr)) return;
+      const float* sb = sub_box + (int64_t)cl * (kKnnSubPerLeaf * 6);
+      uint32_t need = 0;
+#pragma unroll
+      for (int j = 0; j < kKnnSubPerLeaf; ++j)
+        if (ballot(real && pt_box_d2(sb + 6 * j, q.x, q.y, q.z) < thr)) need |= 1u << j;
+      if (!need) return;
       const int64_t cbase = (int64_t)cl * SFK_LEAF;
-      for (int t0 = 0; t0 < SFK_LEAF; t0 += 16) {
+      lp[lane] = tv.pts[cbase + lane];
+      wave_sync();
+      while (need) {
+        const int j = __ffs(need) - 1;
+        need &= need - 1;
         uint32_t mark = 0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const float4 p = lp[t0 + u];
+        for (int u = 0; u < kKnnSub; ++u) {
+          const float4 p = lp[j * kKnnSub + u];
           float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
-          if (cbase + t0 + u == my || !real) x = __builtin_huge_valf();
-          ld2[u * 64 + lane] = x;
+          if (cbase + j * kKnnSub + u == my || !real) x = __builtin_huge_valf();
+          ld2[u * 64 + lane] = x;  // own column: no other lane reads it
           if (x < thr) mark |= 1u << u;
         }
         int rounds = __popc(mark);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off, 64));
-        if (rounds == 0) continue;
-        wave_sync();
         for (int r = 0; r < rounds; ++r) {
           float x = __builtin_huge_valf();
           if (mark) {
@@ -494,59 +549,91 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, int k, float* __restri
           }
           // lanes with x >= thr only touch entries past the k-th: harmless
           knn_insert<KM>(a, x);
-          thr = kth();
+          thr = a[KM - 1];
         }
-        wave_sync();
       }
       wave_sync();
     };
 
-    // pass 1: the leaf and its Morton neighbours
-    int w0 = leaf - 1;
-    if (w0 > nl - 3) w0 = nl - 3;
-    if (w0 < 0) w0 = 0;
-    const int w1 = min(nl - 1, w0 + 2);
-    for (int cl = w0; cl <= w1; ++cl) process(cl);
+    // pass 1: the leaf itself, then its Morton neighbours
+    process(leaf);
+    if (leaf > 0) process(leaf - 1);
+    if (leaf + 1 < nl) process(leaf + 1);
     const float tau = wave_max(real ? thr : 0.0f);
 
-    // pass 2: the other leaves within tau of this leaf's box
-    const NodeBox qb = tv.nodes[tv.level_off[0] + leaf];
+    // pass 2: every other leaf within tau of this leaf's box, nearest first
+    const NodeBox qb = leaf_box[leaf];
+    int ln = 0;
+    auto flush = [&]() {
+      float lo_lim = -1.0f;
+#pragma unroll 1
+      for (int band = 0; band < 3; ++band) {
+        const float hi_lim = band == 0 ? tau * 0.0625f : band == 1 ? tau * 0.25f
+                                                                   : __builtin_huge_valf();
+        for (int i0 = 0; i0 < ln; i0 += 64) {
+          const int i = i0 + lane;
+          const float key = i < ln ? lkey[i] : -2.0f;
+          uint64_t m = ballot(key > lo_lim && key <= hi_lim);
+          const int id = i < ln ? lid[i] : 0;
+          while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            process(wave_bcast(id, b));
+          }
+        }
+        lo_lim = hi_lim;
+      }
+      ln = 0;
+      wave_sync();
+    };
+    float tkey = 0.0f;
     traverse(
         tv, stack,
         [&](const NodeBox& b, int g) {
           (void)g;
-          return box_gap_d2(b, qb.lo[0], qb.lo[1], qb.lo[2], qb.hi[0], qb.hi[1], qb.hi[2]) <= tau;
+          tkey = box_gap_d2(b, qb.lo[0], qb.lo[1], qb.lo[2], qb.hi[0], qb.hi[1], qb.hi[2]);
+          return tkey <= tau;
         },
         [&](int child, bool pass, uint64_t mask) {
-          (void)pass;
-          uint64_t m = mask;
-          while (m) {
-            const int bit = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int cl = wave_bcast(child, bit);
-            if (cl >= w0 && cl <= w1) continue;
-            const NodeBox lb = tv.nodes[tv.level_off[0] + cl];
-            const float gap = box_gap_d2(lb, q.x, q.y, q.z, q.x, q.y, q.z);
-            if (!ballot(real && gap < thr)) continue;
-            process(cl);
+          const bool take = pass && (child < leaf - 1 || child > leaf + 1);
+          const uint64_t tm = ballot(take);
+          const int nt = popc64(tm);
+          if (nt == 0) return;
+          if (ln + nt > kKnnList) flush();
+          if (take) {
+            const int pos = ln + popc64(tm & lanemask_lt());
+            lid[pos] = child;
+            lkey[pos] = tkey;
           }
+          ln += nt;
+          wave_sync();
+          (void)mask;
         });
+    if (ln > 0) flush();
     if (real) h2_sorted[my] = thr;
   }
 }
 
-hipError_t launch_knn(TreeView tv, int k, float* h2_sorted, hipStream_t s) {
+hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s) {
   if (tv.n_leaves <= 0) return hipSuccess;
+  const int64_t n_slots = (int64_t)tv.n_leaves * SFK_LEAF;
+  const int64_t nbs = std::min<int64_t>((n_slots + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_sub_boxes, dim3((unsigned)nbs), dim3(256), 0, s, tv.pts, tv.n, n_slots,
+                     sub_box);
   const int nb = std::min<int>((tv.n_leaves + 3) / 4, 65536);
   if (k <= 8)
-    hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
   else if (k <= 16)
-    hipLaunchKernelGGL(k_knn<16>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<16>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
   else if (k <= 32)
-    hipLaunchKernelGGL(k_knn<32>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<32>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
   else
-    hipLaunchKernelGGL(k_knn<64>, dim3(nb), dim3(256), 0, s, tv, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<64>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
   return hipGetLastError();
+}
+
+size_t knn_sub_box_bytes(int32_t n_leaves) {
+  return sizeof(float) * 6 * (size_t)n_leaves * kKnnSubPerLeaf;
 }
 
 // Per-particle isotropic inverse bandwidth into pts[].w:

@@ -106,7 +106,9 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
                           int64_t n, const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
                           hipStream_t s);
-hipError_t launch_knn(TreeView tv, int k, float* h2_sorted, hipStream_t s);
+// sub_box: knn_sub_box_bytes(n_leaves) of scratch for the sub-block boxes
+hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s);
+size_t knn_sub_box_bytes(int32_t n_leaves);
 hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
                              const int32_t* perm, int64_t n, hipStream_t s);
 

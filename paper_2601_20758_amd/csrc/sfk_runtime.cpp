@@ -1460,14 +1460,17 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
   }
   if (o.knn_k > 0 || d_h) {
+    TmpBuf sub(c);  // k-NN scratch; released after the synchronize below
     if ((st = tree_alloc(c, t, t->node_ih, sizeof(float4) * (size_t)total_nodes,
                          "node bandwidths")) != SFK_OK)
       return fail(st);
     if (o.knn_k > 0) {
       if ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) != SFK_OK)
         return fail(st);
+      if ((st = sub.get(sfk::knn_sub_box_bytes(t->n_leaves), "k-NN sub-block boxes")) != SFK_OK)
+        return fail(st);
       ProfScope prof(c, PK_KNN, s);
-      if (sfk::launch_knn(view_of(t), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
+      if (sfk::launch_knn(view_of(t), sub.as<float>(), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
     }
     if (sfk::launch_iso_params((float4*)t->pts.p, (const float*)t->h2.p, d_h,
