@@ -51,8 +51,8 @@ def parse():
     p.add_argument("--n-batch", type=int, default=256)
     p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--copy-calibration", action="store_true",
-                   help="run one 1 GiB device-to-device copy first (reference for "
-                        "hardware byte counters)")
+                   help="run a 1 GiB fill and a 1 GiB elementwise scale first "
+                        "(references for the hardware byte counters)")
     p.add_argument("--no-serve", action="store_true")
     return p.parse_args()
 
@@ -177,9 +177,12 @@ def main():
     import paper_2601_20758_amd as sfk
 
     if args.copy_calibration:
+        # reference kernels of known traffic for the byte counters: a fill
+        # writes 1 GiB; an elementwise scale reads 1 GiB and writes 1 GiB
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         src.fill_(1.0)
-        dst = src.clone()
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     pts, roi, knn_k, config = workload(args.workload)

@@ -484,19 +484,21 @@ __device__ __forceinline__ float pt_box_d2(const float* b, float x, float y, flo
 }
 
 template <int KM>
-__global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 4 : 2))) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
                                              float* __restrict__ h2_sorted) {
   __shared__ float4 lds_pts[4][SFK_LEAF];
   __shared__ int32_t lds_stack[4][SFK_STACK];
   __shared__ float lds_d2[4][kKnnSub * 64];
   __shared__ int32_t lds_lid[4][kKnnList];
   __shared__ float lds_lkey[4][kKnnList];
+  __shared__ int32_t lds_ord[4][kKnnList];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   float4* lp = lds_pts[wave];
   float* ld2 = lds_d2[wave];
   int32_t* stack = lds_stack[wave];
   int32_t* lid = lds_lid[wave];
   float* lkey = lds_lkey[wave];
+  int32_t* ord = lds_ord[wave];
   const int nl = tv.n_leaves;
   const NodeBox* leaf_box = tv.nodes + tv.level_off[0];
   for (int leaf = blockIdx.x * 4 + wave; leaf < nl; leaf += gridDim.x * 4) {
@@ -510,20 +512,26 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restric
     for (int i = 0; i < KM; ++i) a[i] = i < KM - k ? -__builtin_huge_valf() : __builtin_huge_valf();
     float thr = __builtin_huge_valf();
 
-    // One candidate leaf. Per needed sub-block each lane marks the
-    // particles below its threshold; the insertion then runs in rounds, a
-    // round inserting every lane's next marked particle.
-    auto process = [&](int cl) {
-      const float lgap = box_gap_d2(leaf_box[cl], q.x, q.y, q.z, q.x, q.y, q.z);
-      if (!ballot(real && lgap < thr)) return;
-      const float* sb = sub_box + (int64_t)cl * (kKnnSubPerLeaf * 6);
+    // One candidate leaf, its particle for this lane in pc and its
+    // sub-block boxes spread over lanes 0..47 of sbv. Per needed sub-block
+    // each lane marks the particles below its threshold; the insertion then
+    // runs in rounds, a round inserting every lane's next marked particle.
+    auto process = [&](int cl, const float4 pc, const float sbv) {
       uint32_t need = 0;
 #pragma unroll
-      for (int j = 0; j < kKnnSubPerLeaf; ++j)
-        if (ballot(real && pt_box_d2(sb + 6 * j, q.x, q.y, q.z) < thr)) need |= 1u << j;
+      for (int j = 0; j < kKnnSubPerLeaf; ++j) {
+        const float bx[6] = {readlane_f(sbv, 6 * j + 0),
+                             readlane_f(sbv, 6 * j + 1),
+                             readlane_f(sbv, 6 * j + 2),
+                             readlane_f(sbv, 6 * j + 3),
+                             readlane_f(sbv, 6 * j + 4),
+                             readlane_f(sbv, 6 * j + 5)};
+        if (ballot(real && pt_box_d2(bx, q.x, q.y, q.z) < thr)) need |= 1u << j;
+      }
       if (!need) return;
       const int64_t cbase = (int64_t)cl * SFK_LEAF;
-      lp[lane] = tv.pts[cbase + lane];
+      const int self = cl == leaf ? lane : -1;
+      lp[lane] = pc;
       wave_sync();
       while (need) {
         const int j = __ffs(need) - 1;
@@ -533,7 +541,7 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restric
         for (int u = 0; u < kKnnSub; ++u) {
           const float4 p = lp[j * kKnnSub + u];
           float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
-          if (cbase + j * kKnnSub + u == my || !real) x = __builtin_huge_valf();
+          if (j * kKnnSub + u == self || !real) x = __builtin_huge_valf();
           ld2[u * 64 + lane] = x;  // own column: no other lane reads it
           if (x < thr) mark |= 1u << u;
         }
@@ -552,19 +560,80 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restric
           thr = a[KM - 1];
         }
       }
+      (void)cbase;
       wave_sync();
     };
+    // process() over the leaves ord[0..count), with the next leaf's
+    // particles and sub-block boxes in flight
+    auto run = [&](int count) {
+      if (count <= 0) return;
+      int cl = __builtin_amdgcn_readfirstlane(ord[0]);
+      float4 pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
+      float sn = lane < 6 * kKnnSubPerLeaf ? sub_box[(int64_t)cl * (6 * kKnnSubPerLeaf) + lane] : 0.f;
+      for (int i = 0; i < count; ++i) {
+        const int cur = cl;
+        const float4 pc = pn;
+        const float sc = sn;
+        if (i + 1 < count) {
+          cl = __builtin_amdgcn_readfirstlane(ord[i + 1]);
+          pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
+          sn = lane < 6 * kKnnSubPerLeaf ? sub_box[(int64_t)cl * (6 * kKnnSubPerLeaf) + lane] : 0.f;
+        }
+        process(cur, pc, sc);
+      }
+    };
 
-    // pass 1: the leaf itself, then its Morton neighbours
-    process(leaf);
-    if (leaf > 0) process(leaf - 1);
-    if (leaf + 1 < nl) process(leaf + 1);
-    const float tau = wave_max(real ? thr : 0.0f);
-
-    // pass 2: every other leaf within tau of this leaf's box, nearest first
+    // Depth-first walk of the box hierarchy that stops whenever the held
+    // list may not take another group of 64 leaves and resumes where it
+    // stopped (its stack stays in LDS). It keeps the leaves, other than the
+    // first pass's, whose box is within tau of this leaf's box.
     const NodeBox qb = leaf_box[leaf];
-    int ln = 0;
-    auto flush = [&]() {
+    float tau = 0.0f;
+    int ln = 0, sp = 0, level = 0, first = 0, cnt = 0;
+    bool walk_done = false;
+    auto collect = [&]() {
+      while (!walk_done && ln <= kKnnList - SFK_FANOUT) {
+        const int child = first + lane;
+        bool pass = false;
+        float key = 0.0f;
+        if (lane < cnt) {
+          key = box_gap_d2(tv.nodes[tv.level_off[level] + child], qb.lo[0], qb.lo[1], qb.lo[2],
+                           qb.hi[0], qb.hi[1], qb.hi[2]);
+          pass = key <= tau;
+        }
+        if (level == 0) {
+          const bool take = pass && (child < leaf - 1 || child > leaf + 1);
+          const uint64_t tm = ballot(take);
+          if (take) {
+            const int pos = ln + popc64(tm & lanemask_lt());
+            lid[pos] = child;
+            lkey[pos] = key;
+          }
+          ln += popc64(tm);
+        } else {
+          const uint64_t mask = ballot(pass);
+          const int np = popc64(mask);
+          if (pass) stack[sp + np - 1 - popc64(mask & lanemask_lt())] = ((level - 1) << 27) | child;
+          sp += np;
+        }
+        wave_sync();
+        if (sp == 0) {
+          walk_done = true;
+          break;
+        }
+        --sp;
+        const int e = stack[sp];
+        level = e >> 27;
+        first = (e & ((1 << 27) - 1)) * SFK_FANOUT;
+        cnt = min(SFK_FANOUT, tv.level_cnt[level] - first);
+        wave_sync();
+      }
+    };
+    // Order the held leaves by distance band into ord[], dropping those no
+    // lane needs (thresholds only shrink, so a leaf no lane needs now is
+    // never needed); leaf boxes come in 64 at a time, one per lane.
+    auto order = [&]() {
+      int no = 0;
       float lo_lim = -1.0f;
 #pragma unroll 1
       for (int band = 0; band < 3; ++band) {
@@ -573,43 +642,61 @@ __global__ __launch_bounds__(256) void k_knn(TreeView tv, const float* __restric
         for (int i0 = 0; i0 < ln; i0 += 64) {
           const int i = i0 + lane;
           const float key = i < ln ? lkey[i] : -2.0f;
-          uint64_t m = ballot(key > lo_lim && key <= hi_lim);
+          const bool inb = key > lo_lim && key <= hi_lim;
+          uint64_t m = ballot(inb);
+          if (!m) continue;
           const int id = i < ln ? lid[i] : 0;
+          NodeBox bb = {};
+          if (inb) bb = leaf_box[id];
           while (m) {
             const int b = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            process(wave_bcast(id, b));
+            const float bx[6] = {readlane_f(bb.lo[0], b), readlane_f(bb.lo[1], b),
+                                 readlane_f(bb.lo[2], b), readlane_f(bb.hi[0], b),
+                                 readlane_f(bb.hi[1], b), readlane_f(bb.hi[2], b)};
+            if (ballot(real && pt_box_d2(bx, q.x, q.y, q.z) < thr)) {
+              if (lane == 0) ord[no] = __builtin_amdgcn_readlane(id, b);
+              ++no;
+            }
           }
         }
         lo_lim = hi_lim;
       }
       ln = 0;
       wave_sync();
+      return no;
     };
-    float tkey = 0.0f;
-    traverse(
-        tv, stack,
-        [&](const NodeBox& b, int g) {
-          (void)g;
-          tkey = box_gap_d2(b, qb.lo[0], qb.lo[1], qb.lo[2], qb.hi[0], qb.hi[1], qb.hi[2]);
-          return tkey <= tau;
-        },
-        [&](int child, bool pass, uint64_t mask) {
-          const bool take = pass && (child < leaf - 1 || child > leaf + 1);
-          const uint64_t tm = ballot(take);
-          const int nt = popc64(tm);
-          if (nt == 0) return;
-          if (ln + nt > kKnnList) flush();
-          if (take) {
-            const int pos = ln + popc64(tm & lanemask_lt());
-            lid[pos] = child;
-            lkey[pos] = tkey;
-          }
-          ln += nt;
-          wave_sync();
-          (void)mask;
-        });
-    if (ln > 0) flush();
+
+    // Phase 0 visits the leaf itself and its Morton neighbours, which bound
+    // every lane's answer from above; tau is then the wavefront's largest
+    // bound. Each later phase visits one collected chunk of the walk. One
+    // visiting site keeps a single copy of the insertion code.
+    for (int phase = 0;; ++phase) {
+      int no;
+      if (phase == 0) {
+        no = 1 + (leaf > 0 ? 1 : 0) + (leaf + 1 < nl ? 1 : 0);
+        if (lane == 0) {
+          ord[0] = leaf;
+          if (leaf > 0) ord[1] = leaf - 1;
+          if (leaf + 1 < nl) ord[no - 1] = leaf + 1;
+        }
+        wave_sync();
+      } else {
+        collect();
+        no = order();
+      }
+      run(no);
+      wave_sync();
+      if (phase == 0) {
+        tau = wave_max(real ? thr : 0.0f);
+        level = tv.n_levels - 1;
+        first = 0;
+        cnt = tv.level_cnt[level];
+        walk_done = tv.n_levels <= 0;
+      } else if (walk_done) {
+        break;
+      }
+    }
     if (real) h2_sorted[my] = thr;
   }
 }

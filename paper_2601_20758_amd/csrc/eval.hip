@@ -290,6 +290,9 @@ __device__ __forceinline__ void reduce_nodes(A (&acc)[T]) {
   }
 }
 
+// leaf ids of a work item staged in LDS at a time
+constexpr int kIdBlock = 256;
+
 // -log2(e)/2 in double: exp(-u2/2) = exp2(KG * u2)
 #define SFK_KG64 (-0.72134752044448170368)
 
@@ -309,17 +312,40 @@ __global__ __launch_bounds__(256) void k_eval(
   constexpr int T = TX * TY * TZ;
   constexpr int NPL = T >= 64 ? T / 64 : 1;
   using Acc = typename std::conditional<(KK == KK_EPAN && !CNT), double, float>::type;
+  // particle buffers of the leaf pipeline (fewer where double accumulators
+  // leave fewer registers); each pipeline round appends up to NB leaves to
+  // the queue before draining it, hence its capacity
+  constexpr int NB = sizeof(Acc) == 8 ? 2 : 3;
+  constexpr int QCAP = 64 * (NB + 1);
   __shared__ int32_t lds_stack[4][SFK_STACK];
-  __shared__ float4 lds_qpts[4][128];
-  __shared__ float4 lds_qprm[4][PP == PP_ANISO ? 128 : 1];
+  __shared__ float4 lds_qpts[4][QCAP];
+  __shared__ float4 lds_qprm[4][PP == PP_ANISO ? QCAP : 1];
+  __shared__ int32_t lds_ids[4][kIdBlock];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_items = hdr->n_items;
   const int n_rois = hdr->n_rois;
+  // XCD-aware work stealing. Workgroups are dispatched round-robin over the
+  // 8 XCDs, each with its own L2; the item list is cut into 8 contiguous
+  // (hence spatially coherent) slices and a workgroup takes items from its
+  // own XCD's slice first, then from the others in turn. Which workgroup
+  // takes an item never changes what the item computes.
+  const int xcd = blockIdx.x & 7;
+  int scan = 0;  // slices this wave has found empty, in its order
   while (true) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(&hdr->next_item, 1);
-    item = __shfl(item, 0, 64);
-    if ((int64_t)item >= n_items) break;
+    int64_t item = -1;
+    while (scan < 8) {
+      const int x = (xcd + scan) & 7;
+      const int64_t b = n_items * x / 8, e = n_items * (x + 1) / 8;
+      int idx = 0;
+      if (b < e && lane == 0) idx = atomicAdd(&hdr->next_xcd[x], 1);
+      idx = __shfl(idx, 0, 64);
+      if (b < e && b + idx < e) {
+        item = b + idx;
+        break;
+      }
+      ++scan;
+    }
+    if (item < 0) break;
     const int t = item_tile[item];
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
@@ -350,6 +376,7 @@ __global__ __launch_bounds__(256) void k_eval(
     // that can matter. The order is fixed, hence so are the sums.
     float4* qp = lds_qpts[wave];
     float4* qa = lds_qprm[wave];
+    int32_t* ids = lds_ids[wave];
     int qn = 0;
 
     auto eval_point = [&](const float4 p, const float4 prm) {
@@ -449,9 +476,10 @@ __global__ __launch_bounds__(256) void k_eval(
       const float4 p = qp[lane];
       float4 prm = make_float4(0.f, 0.f, 0.f, 0.f);
       if constexpr (PP == PP_ANISO) prm = qa[lane];
-      if (lane + 64 < qn) {
-        qp[lane] = qp[lane + 64];
-        if constexpr (PP == PP_ANISO) qa[lane] = qa[lane + 64];
+      // move entries [64, qn) to the front, 64 at a time in ascending order
+      for (int e = lane; e + 64 < qn; e += 64) {
+        qp[e] = qp[e + 64];
+        if constexpr (PP == PP_ANISO) qa[e] = qa[e + 64];
       }
       qn -= 64;
       wave_sync();
@@ -471,15 +499,17 @@ __global__ __launch_bounds__(256) void k_eval(
       eval_point(p, prm);
     };
 
-    auto eval_leaf = [&](int lid) {
+    // particle (and, anisotropic, its parameters) of lane `lane` of leaf lid
+    auto fetch = [&](int lid, float4& p, float4& prm) {
       const int64_t slot = (int64_t)lid * SFK_LEAF + lane;
-      const float4 p = tv.pts[slot];
-      float4 prm = make_float4(0.f, 0.f, 0.f, 0.f);
+      p = tv.pts[slot];
+      if constexpr (PP == PP_ANISO) prm = tv.pparam[slot];
+    };
+    auto cull = [&](const float4 p, const float4 prm, bool live) {
       float ihx = uih0, ihy = uih1, ihz = uih2;
       if constexpr (PP == PP_ISO) {
         ihx = ihy = ihz = p.w;
       } else if constexpr (PP == PP_ANISO) {
-        prm = tv.pparam[slot];
         ihx = prm.x;
         ihy = prm.y;
         ihz = prm.z;
@@ -489,7 +519,7 @@ __global__ __launch_bounds__(256) void k_eval(
       const double gy = fmax(fmax(g.lo[1] - py, py - g.hi[1]), 0.0);
       const double gz = fmax(fmax(g.lo[2] - pz, pz - g.hi[2]), 0.0);
       const double ux = gx * (double)ihx, uy = gy * (double)ihy, uz = gz * (double)ihz;
-      const bool keep = ((ux * ux + uy * uy) + uz * uz) < c2;
+      const bool keep = live && ((ux * ux + uy * uy) + uz * uz) < c2;
       const uint64_t m = ballot(keep);
       if (keep) {
         const int pos = qn + popc64(m & lanemask_lt());
@@ -498,7 +528,15 @@ __global__ __launch_bounds__(256) void k_eval(
       }
       qn += popc64(m);
       wave_sync();
+    };
+    auto cull_push = [&](const float4 p, const float4 prm) {
+      cull(p, prm, true);
       if (qn >= 64) drain64();
+    };
+    auto eval_leaf = [&](int lid) {
+      float4 p, prm = make_float4(0.f, 0.f, 0.f, 0.f);
+      fetch(lid, p, prm);
+      cull_push(p, prm);
     };
     auto end_chunk = [&]() {
       drain_rest();
@@ -515,10 +553,40 @@ __global__ __launch_bounds__(256) void k_eval(
     const bool lane_writes = T >= 64 || lane < T;
 
     if (tile_fit[t]) {
-      const int c = item - (int)chunk_off[t];
+      const int c = (int)(item - chunk_off[t]);
       const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
       const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
-      for (int64_t l = lb; l < le; ++l) eval_leaf(leaves[l]);
+      // Software pipeline over NB particle buffers: a buffer is refilled
+      // with the leaf NB places ahead as soon as it has been culled, so
+      // NB - 1 leaves are in flight during each cull; the loop is unrolled
+      // over the buffers so that no register is copied while its load is
+      // pending. The leaf ids of a block of the chunk are staged in LDS
+      // first, so reading them never waits on the particle loads.
+      for (int64_t b0 = lb; b0 < le; b0 += kIdBlock) {
+        const int n = (int)min((int64_t)kIdBlock, le - b0);
+        for (int i = lane; i < n; i += 64) ids[i] = leaves[b0 + i];
+        wave_sync();
+        // Every buffer is refilled unconditionally (past the end with the
+        // block's last leaf, culled as empty), which keeps the count of
+        // loads in flight the same on every path through the loop.
+        float4 pb[NB], ab[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          pb[u] = ab[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          fetch(__builtin_amdgcn_readfirstlane(ids[min(u, n - 1)]), pb[u], ab[u]);
+          // keep buffer order = issue order (the oldest load is consumed first)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int i = 0; i < n; i += NB) {
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            cull(pb[u], ab[u], i + u < n);
+            fetch(__builtin_amdgcn_readfirstlane(ids[min(i + u + NB, n - 1)]), pb[u], ab[u]);
+          }
+          while (qn >= 64) drain64();
+        }
+        wave_sync();
+      }
       end_chunk();
       if (nch == 1) {
         if (lane_writes) {

@@ -29,6 +29,11 @@ __device__ __forceinline__ T wave_bcast(T v, int src) { return __shfl(v, src, 64
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Lane l's value of a float (l uniform), bit for bit.
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -67,11 +67,12 @@ struct alignas(16) BatchHdr {
   int64_t partial_cap;   // host: capacity of the split-tile partial slots
   int64_t item_cap;      // host: capacity of the item buffers
   int32_t n_rois;        // host: descriptors that follow the header
-  int32_t next_item;     // host stages 0; work-stealing counter
+  int32_t pad0_;
   int64_t total_leaves;  // plan: candidate leaves over all tiles
   int64_t n_items;       // plan: work items (tile chunks)
   int32_t overflow;      // plan: 1 if some tile's lists did not fit (it walks the tree)
   int32_t pad_;
+  int32_t next_xcd[8];   // host stages 0; per-XCD work counters of the evaluation
 };
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).

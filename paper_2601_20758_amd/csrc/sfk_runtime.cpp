@@ -617,7 +617,6 @@ BatchHdr make_hdr(const Caps& k, int64_t n_rois, int64_t n_tiles) {
   h.partial_cap = k.partial_cap;
   h.item_cap = k.item_cap;
   h.n_rois = (int32_t)n_rois;
-  h.next_item = 0;
   return h;
 }
 
