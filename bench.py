@@ -25,12 +25,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("kernel evals/s + ROI grid latency p50/p99 (ms), batched vs "
           "one-ROI-per-launch")
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published fp32 vector peak
 HBM_PEAK_GBS = 8000.0
-# algorithmic float operations per useful evaluation, counted from the
-# definition (per axis: difference, scaling, square; two adds for u2; the
-# kernel value; the weight; the accumulation)
-FLOPS_PER_EVAL = {"gauss_trunc3": 15, "epanechnikov": 13}
+# VALU issue ceiling of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# operations per second. Unpacked float32 and float64 add / mul / fma /
+# compare each take one slot (the 78.6 TFLOP/s fp64 and unpacked fp32 vector
+# peaks are this rate with an FMA counted as 2 flops); a transcendental
+# (exp2) issues at quarter rate and takes 4 slots.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU slots per useful evaluation, counted from the definition
+# of one (node, particle) term: per axis a difference and a scaling (6), the
+# squares and their sum (5), the support test (1), the kernel value
+# (Gaussian: scale + exp2 = 1 + 4; Epanechnikov: 1 - u2 = 1), the
+# per-particle weight (1) and the accumulation (1).
+SLOTS_PER_EVAL = {"gauss_trunc3": 19, "epanechnikov": 15}
+# kernel sources whose counter readings a traffic summary is valid for
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_gauss_per_point_10m_128_traffic.md")
+KERNEL_SOURCES = ("paper_2601_20758_amd/csrc/eval.hip", "paper_2601_20758_amd/csrc/sfk_device.h",
+                  "paper_2601_20758_amd/csrc/sfk_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the evaluation kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of
+    a reference kernel of known size), or None when the summary is missing or
+    was taken on other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -218,17 +257,18 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = useful * args.steps / dt
     eval_ms = prof["eval_ms"] / max(1, prof["eval_launches"])
-    flops = FLOPS_PER_EVAL[roi.kernel] * useful
-    achieved = flops / (eval_ms * 1e-3) / 1e12
+    slots = SLOTS_PER_EVAL[roi.kernel] * useful
+    achieved = slots / (eval_ms * 1e-3) / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
     result = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "config": config,
-        "roofline": {"bound": "alu", "kernel": "k_eval", "achieved": achieved,
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_eval": FLOPS_PER_EVAL[roi.kernel], "evals_per_launch": useful,
+        "roofline": {"bound": "alu", "kernel": "k_eval", "achieved": achieved, "peak": peak,
+                     "unit": "T VALU-slot/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(),
+                     "slots_per_eval": SLOTS_PER_EVAL[roi.kernel], "evals_per_launch": useful,
                      "avg_launch_ms": eval_ms},
         "phases_ms": {k: prof[k] / args.steps for k in
                       ("build_ms", "knn_ms", "tile_count_ms", "plan_ms", "tile_fill_ms",
