@@ -175,7 +175,7 @@ sfk_status sfk_cancel(sfk_ctx ctx, sfk_ticket t);
 /* Tile shape used for tile-granular range queries and evaluation: one
  * wavefront owns tx*ty*tz grid nodes. 0 = chosen by the autotuner table. */
 typedef struct {
-  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2 */
+  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2, 5 = 1x1x1 */
   int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 256 */
   int32_t persistent_waves_per_cu; /* 0 = automatic */
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose

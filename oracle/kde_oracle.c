@@ -124,7 +124,7 @@ void orc_density_nodes(const float* pts, int64_t n, const float* ih_pp,
                        const double* hi, const int* res, double scale,
                        const int64_t* nodes, int64_t n_nodes, double* out) {
   const double c2 = orc_kernel_c2(kernel);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < n_nodes; ++q) {
     int64_t idx = nodes[q];
     int ix = (int)(idx % res[0]);

@@ -226,6 +226,7 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ ti
     chunk_off[n_tiles] = carry_c;
     hdr->total_leaves = carry_l;
     hdr->n_items = carry_c;
+    hdr->total_partials = carry_p;
     hdr->overflow = (carry_l > leaf_cap || carry_p > partial_cap) ? 1 : 0;
   }
 }
@@ -734,7 +735,8 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
 
 bool tile_shape_supported(TileShape ts) {
   return (ts.tx == 4 && ts.ty == 4 && (ts.tz == 4 || ts.tz == 2)) ||
-         (ts.tx == 4 && ts.ty == 2 && ts.tz == 2) || (ts.tx == 2 && ts.ty == 2 && ts.tz == 2);
+         (ts.tx == 4 && ts.ty == 2 && ts.tz == 2) || (ts.tx == 2 && ts.ty == 2 && ts.tz == 2) ||
+         (ts.tx == 1 && ts.ty == 1 && ts.tz == 1);
 }
 
 #define SFK_SHAPE_SWITCH(ts, MACRO)                                  \
@@ -747,6 +749,8 @@ bool tile_shape_supported(TileShape ts) {
       MACRO(4, 2, 2);                                                \
     } else if ((ts).tx == 2 && (ts).ty == 2 && (ts).tz == 2) {       \
       MACRO(2, 2, 2);                                                \
+    } else if ((ts).tx == 1 && (ts).ty == 1 && (ts).tz == 1) {       \
+      MACRO(1, 1, 1);                                                \
     } else {                                                         \
       return hipErrorInvalidValue;                                   \
     }                                                                \

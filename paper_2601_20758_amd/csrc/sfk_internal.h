@@ -70,6 +70,7 @@ struct alignas(16) BatchHdr {
   int32_t pad0_;
   int64_t total_leaves;  // plan: candidate leaves over all tiles
   int64_t n_items;       // plan: work items (tile chunks)
+  int64_t total_partials;  // plan: partial-sum slots the split tiles need
   int32_t overflow;      // plan: 1 if some tile's lists did not fit (it walks the tree)
   int32_t pad_;
   int32_t next_xcd[8];   // host stages 0; per-XCD work counters of the evaluation

@@ -69,6 +69,7 @@ struct Staging {
   BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header
   hipEvent_t ev = nullptr;
   bool ev_valid = false;
+  bool stats_pending = false;  // ev follows a header readback not yet absorbed
 };
 
 // A captured batch pipeline of one slot, replayed while its key and the
@@ -359,11 +360,14 @@ double ck_gauss_trunc3() {
   return 1.0 / (std::pow(2.0 * M_PI, 1.5) * p);
 }
 
+constexpr int kNumShapes = 5;  // tile shapes 1..5 of sfk_eval_opts.tile_shape
+
 TileShape shape_of(int id) {
   switch (id) {
     case 2: return TileShape{4, 4, 2};
     case 3: return TileShape{4, 2, 2};
     case 4: return TileShape{2, 2, 2};
+    case 5: return TileShape{1, 1, 1};
     default: return TileShape{4, 4, 4};
   }
 }
@@ -566,15 +570,21 @@ struct Caps {
 // Reserve every buffer of a group (n_rois descriptors, n_tiles tiles,
 // n_coords coordinates; `headroom` > 1 over-allocates so later batches fit a
 // captured graph) and report the capacities the buffers actually have.
+// The default leaf-list capacity is 4 entries per leaf of the tree (and at
+// least 64 per tile), so ROIs of any size over the cloud usually fit at the
+// first call; overflowing batches still complete (walk fallback) and grow
+// the capacities for the next one.
 sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois, int64_t n_tiles,
-                         int64_t n_coords, double headroom, Caps* caps) {
+                         int64_t n_coords, double headroom, int64_t tree_leaves, Caps* caps) {
   const int CH = chunk_leaves_of(c);
   const int T = ts.tx * ts.ty * ts.tz;
   const int64_t tiles = (int64_t)std::ceil((double)n_tiles * headroom);
   const int64_t nr = std::max<int64_t>(64, (int64_t)std::ceil((double)n_rois * headroom));
   const int64_t nc = std::max<int64_t>(1024, (int64_t)std::ceil((double)n_coords * headroom));
-  int64_t leaf_cap = std::max<int64_t>(ws.want_leaf_cap, std::max<int64_t>(1 << 20, 64 * tiles));
-  int64_t partial_cap = std::max<int64_t>(ws.want_partial_cap, std::max<int64_t>(1 << 14, tiles / 4));
+  int64_t leaf_cap = std::max<int64_t>({ws.want_leaf_cap, (int64_t)1 << 20, 64 * tiles,
+                                        4 * tree_leaves});
+  int64_t partial_cap = std::max<int64_t>({ws.want_partial_cap, (int64_t)1 << 14, tiles / 4,
+                                           leaf_cap / CH});
   if (c->opts.list_capacity > 0) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
@@ -695,13 +705,26 @@ GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
 }
 
 // Group CLOUD-set ROIs by (kernel, bandwidth source), in a fixed order.
-void group_rois(sfk_tree t, const std::vector<const sfk_roi*>& rois, bool count_mode,
-                std::vector<std::vector<GroupRoi>>* groups, std::vector<std::pair<int, int>>* keys) {
+// One evaluation pipeline per (kernel, bandwidth source, tile shape). The
+// shape of a ROI depends on that ROI alone (the autotuned or default choice
+// for its key), so a ROI is evaluated the same way alone and in any batch.
+struct GroupKey {
+  int kk, pp;
+  TileShape ts;
+  bool operator==(const GroupKey& o) const {
+    return kk == o.kk && pp == o.pp && ts.tx == o.ts.tx && ts.ty == o.ts.ty && ts.tz == o.ts.tz;
+  }
+};
+
+TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r);
+
+void group_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois, bool count_mode,
+                std::vector<std::vector<GroupRoi>>* groups, std::vector<GroupKey>* keys) {
   for (const sfk_roi* r : rois) {
     GroupRoi g = resolve_cloud_roi(t, r, count_mode);
-    const std::pair<int, int> key{count_mode ? 0 : g.kk, g.pp};
+    const GroupKey key{count_mode ? 0 : g.kk, g.pp, choose_shape(c, t, r)};
     size_t gi = 0;
-    while (gi < keys->size() && (*keys)[gi] != key) ++gi;
+    while (gi < keys->size() && !((*keys)[gi] == key)) ++gi;
     if (gi == keys->size()) {
       keys->push_back(key);
       groups->emplace_back();
@@ -710,39 +733,46 @@ void group_rois(sfk_tree t, const std::vector<const sfk_roi*>& rois, bool count_
   }
 }
 
-// Enqueue CLOUD-set ROIs, one pipeline per (kernel, bandwidth) group, with
-// direct launches sized to the batch.
+// Enqueue CLOUD-set ROIs, one pipeline per group, with direct launches sized
+// to the batch. Every group's buffers are reserved before the first launch:
+// the groups run one after another on the same workspace, and growing a
+// buffer frees the old one.
 sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
-                              bool count_mode, TileShape ts, Workspace& ws, Staging& st,
-                              hipStream_t s) {
+                              bool count_mode, Workspace& ws, Staging& st, hipStream_t s) {
   if (rois.empty()) return SFK_OK;
   std::vector<std::vector<GroupRoi>> groups;
-  std::vector<std::pair<int, int>> keys;
-  group_rois(t, rois, count_mode, &groups, &keys);
+  std::vector<GroupKey> keys;
+  group_rois(c, t, rois, count_mode, &groups, &keys);
   size_t bytes = 0;
   for (auto& g : groups) bytes += sizeof(BatchHdr) + sizeof(RoiDev) * g.size();
   SFK_TRY(staging_reserve(c, st, bytes));
   if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
   TreeView tv = view_of(t);
+  std::vector<int64_t> tiles(groups.size());
   size_t off = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const int64_t n = (int64_t)groups[gi].size();
-    BatchHdr* h = (BatchHdr*)(st.host + off);
     RoiDev* rd = (RoiDev*)(st.host + off + sizeof(BatchHdr));
-    int64_t n_tiles = 0, n_coords = 0;
-    make_roidev(groups[gi], ts, rd, &n_tiles, &n_coords);
+    int64_t n_coords = 0;
+    make_roidev(groups[gi], keys[gi].ts, rd, &tiles[gi], &n_coords);
     Caps k;
-    SFK_TRY(reserve_group(c, ws, ts, n, n_tiles, n_coords, 1.0, &k));
-    *h = make_hdr(k, n, n_tiles);
+    SFK_TRY(reserve_group(c, ws, keys[gi].ts, n, tiles[gi], n_coords, 1.0, t->n_leaves, &k));
+    *(BatchHdr*)(st.host + off) = make_hdr(k, n, tiles[gi]);
+    off += sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
+  }
+  off = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const int64_t n = (int64_t)groups[gi].size();
     const size_t gb = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
     SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host + off, gb, hipMemcpyHostToDevice, s));
-    SFK_TRY(launch_kernels(c, tv, ts, keys[gi].first, keys[gi].second, count_mode, ws, (int)n,
-                           sfk::tile_grid_blocks(n_tiles), s));
+    SFK_TRY(launch_kernels(c, tv, keys[gi].ts, keys[gi].kk, keys[gi].pp, count_mode, ws, (int)n,
+                           sfk::tile_grid_blocks(tiles[gi]), s));
     off += gb;
   }
+  SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
   SFK_HIP(c, hipEventRecord(st.ev, s));
   st.ev_valid = true;
-  SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+  st.stats_pending = true;
   return SFK_OK;
 }
 
@@ -755,15 +785,14 @@ void drop_graph(GraphCache& gc) {
 // Enqueue a single-group batch on an idle slot through its captured graph,
 // capturing (again) when the key, the workspace or the capacities changed.
 sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
-                                    const std::vector<const sfk_roi*>& rois, TileShape ts,
-                                    Slot& sl) {
+                                    const std::vector<const sfk_roi*>& rois, Slot& sl) {
   std::vector<std::vector<GroupRoi>> groups;
-  std::vector<std::pair<int, int>> keys;
-  group_rois(t, rois, false, &groups, &keys);
-  if (groups.size() != 1)
-    return enqueue_cloud_rois(c, t, rois, false, ts, sl.ws, sl.st, sl.stream);
+  std::vector<GroupKey> keys;
+  group_rois(c, t, rois, false, &groups, &keys);
+  if (groups.size() != 1) return enqueue_cloud_rois(c, t, rois, false, sl.ws, sl.st, sl.stream);
   const int64_t n = (int64_t)groups[0].size();
-  const int kk = keys[0].first, pp = keys[0].second, ch = chunk_leaves_of(c);
+  const TileShape ts = keys[0].ts;
+  const int kk = keys[0].kk, pp = keys[0].pp, ch = chunk_leaves_of(c);
   std::vector<RoiDev> rd((size_t)n);
   int64_t n_tiles = 0, n_coords = 0;
   make_roidev(groups[0], ts, rd.data(), &n_tiles, &n_coords);
@@ -776,12 +805,12 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   Caps k;
   if (!fits) {
     drop_graph(gc);
-    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, &k));
+    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, t->n_leaves, &k));
   } else {
-    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 1.0, &k));
+    SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 1.0, t->n_leaves, &k));
     if (sl.ws.gen != gc.gen) {  // a buffer moved after all
       drop_graph(gc);
-      SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, &k));
+      SFK_TRY(reserve_group(c, sl.ws, ts, n, n_tiles, n_coords, 2.0, t->n_leaves, &k));
     }
   }
   const size_t full = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)k.rois_cap;
@@ -838,11 +867,26 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   return SFK_OK;
 }
 
+// Grow the list capacities from every direct-path batch whose header
+// readback has completed (never blocks).
+void absorb_stats(Workspace& ws, const Staging& st);
+void absorb_ready(Workspace& ws, Staging* ring, int n) {
+  for (int i = 0; i < n; ++i) {
+    Staging& st = ring[i];
+    if (st.stats_pending && st.ev_valid && hipEventQuery(st.ev) == hipSuccess) {
+      absorb_stats(ws, st);
+      st.stats_pending = false;
+    }
+  }
+}
+
 // After a batch completed: grow the list capacities if they overflowed.
 void absorb_stats(Workspace& ws, const Staging& st) {
   if (!st.hdr_host) return;
   const BatchHdr& h = *st.hdr_host;
   if (h.total_leaves > h.leaf_cap) ws.want_leaf_cap = h.total_leaves + h.total_leaves / 4;
+  if (h.total_partials > h.partial_cap)
+    ws.want_partial_cap = h.total_partials + h.total_partials / 4;
 }
 
 // ---- IN_ROI set and MBE: a sub-cloud of the particles inside B ----
@@ -951,7 +995,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     int64_t n_tiles = 0, n_coords = 0;
     make_roidev(v, ts, (RoiDev*)(st.host + sizeof(BatchHdr)), &n_tiles, &n_coords);
     Caps k;
-    SFK_TRY(reserve_group(c, ws, ts, 1, n_tiles, n_coords, 1.0, &k));
+    SFK_TRY(reserve_group(c, ws, ts, 1, n_tiles, n_coords, 1.0, tv.n_leaves, &k));
     *(BatchHdr*)st.host = make_hdr(k, 1, n_tiles);
     SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host, gb, hipMemcpyHostToDevice, s));
     SFK_HIP(c, hipEventRecord(st.ev, s));
@@ -1109,14 +1153,37 @@ int tune_key(const sfk_roi* r) {
   return (r->kernel * 4 + r->bw) * 8 + bucket;
 }
 
-constexpr int kDefaultShape = 1;
+// Untuned default per support/spacing bucket (measured on 1e8-1e9 point
+// clumpy clouds): a support below half the node spacing reaches at most one
+// node per particle, so one node per wavefront reads only the particles near
+// nodes; larger supports share each particle among more nodes of a tile.
+int default_shape(int key) {
+  const int bucket = key & 7;
+  if (bucket == 0) return 1;  // per-particle bandwidths
+  if (bucket <= 2) return 5;  // support < 0.5 spacing
+  if (bucket == 3) return 4;  // [0.5, 1)
+  if (bucket == 4) return 3;  // [1, 2)
+  return 1;
+}
 
 TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
-  (void)t;
   if (c->opts.tile_shape > 0) return shape_of(c->opts.tile_shape);
-  auto it = c->tune.find(tune_key(r));
+  const int key = tune_key(r);
+  auto it = c->tune.find(key);
   if (it != c->tune.end()) return shape_of(it->second);
-  return shape_of(kDefaultShape);
+  int shape = default_shape(key);
+  if (shape == 5 && t) {
+    // one node per wavefront pays off only when a node's support holds a few
+    // leaves' worth of particles (estimate: the cloud's mean density)
+    double vol = 1.0, sup = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      vol *= std::max(1e-30, (double)t->bbox[3 + k] - (double)t->bbox[k]);
+      const double h = r->bw == SFK_BW_FIXED ? (double)r->h[k] : (double)r->h[0] * (r->hi[k] - r->lo[k]);
+      sup *= 2.0 * h * (r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 : 1.0);
+    }
+    if ((double)t->n * sup / vol < 2048.0) shape = 4;
+  }
+  return shape_of(shape);
 }
 
 // Launch everything a ticket needs on a slot. CLOUD ROIs go through one
@@ -1128,12 +1195,10 @@ sfk_status launch_ticket(sfk_ctx c, Ticket& tk, Slot& sl) {
   for (const sfk_roi& r : tk.rois) (r.set == SFK_SET_IN_ROI ? sub : cloud).push_back(&r);
   absorb_stats(sl.ws, sl.st);
   if (!cloud.empty()) {
-    // one tile shape per batch: the autotuned choice of the first ROI
-    const TileShape ts = choose_shape(c, tk.tree, cloud[0]);
     if (c->opts.disable_graphs)
-      SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, ts, sl.ws, sl.st, sl.stream));
+      SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, sl.ws, sl.st, sl.stream));
     else
-      SFK_TRY(enqueue_cloud_rois_graph(c, tk.tree, cloud, ts, sl));
+      SFK_TRY(enqueue_cloud_rois_graph(c, tk.tree, cloud, sl));
   }
   for (const sfk_roi* r : sub)
     SFK_TRY(eval_subcloud(c, tk.tree, r, false, shape_of(1), sl.ws, sl.st, sl.stream, nullptr));
@@ -1578,7 +1643,7 @@ sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
     set_err(c, "opts is NULL");
     return SFK_E_INVAL;
   }
-  if (opts->tile_shape < 0 || opts->tile_shape > 4 || opts->chunk_leaves < 0 ||
+  if (opts->tile_shape < 0 || opts->tile_shape > kNumShapes || opts->chunk_leaves < 0 ||
       opts->chunk_leaves > (1 << 20) || opts->persistent_waves_per_cu < 0 ||
       opts->persistent_waves_per_cu > 64 || opts->list_capacity < 0 ||
       opts->disable_graphs < 0 || opts->disable_graphs > 1) {
@@ -1599,9 +1664,9 @@ static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStre
   if (roi->set == SFK_SET_IN_ROI) {
     SFK_TRY(eval_subcloud(c, t, roi, count_mode, shape_of(1), c->direct_ws, st, s, nullptr));
   } else {
-    absorb_stats(c->direct_ws, st);
+    absorb_ready(c->direct_ws, c->direct_st, kStagingRing);
     std::vector<const sfk_roi*> v{roi};
-    SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, choose_shape(c, t, roi), c->direct_ws, st, s));
+    SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, c->direct_ws, st, s));
   }
   SFK_HIP(c, hipEventRecord(c->direct_last, s));
   c->direct_last_valid = true;
@@ -1934,8 +1999,8 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
   for (int i = 0; i < n && st == SFK_OK; ++i) {
     const int key = tune_key(&sample[i]);
     auto& v = cost[key];
-    if (v.empty()) v.assign(5, 0.0);
-    for (int shape = 1; shape <= 4 && st == SFK_OK; ++shape) {
+    if (v.empty()) v.assign(kNumShapes + 1, 0.0);
+    for (int shape = 1; shape <= kNumShapes && st == SFK_OK; ++shape) {
       c->opts.tile_shape = shape;
       float best = 1e30f;
       for (int rep = 0; rep < 3 && st == SFK_OK; ++rep) {
@@ -1955,8 +2020,8 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
   (void)hipEventDestroy(e1);
   if (st != SFK_OK) return st;
   for (auto& kv : cost) {
-    int best = kDefaultShape;
-    for (int shape = 1; shape <= 4; ++shape)
+    int best = default_shape(kv.first);
+    for (int shape = 1; shape <= kNumShapes; ++shape)
       if (kv.second[shape] < kv.second[best]) best = shape;
     c->tune[kv.first] = best;
   }
@@ -2130,10 +2195,9 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
         if (sl.busy) continue;
         batch.clear();
         double bytes = 0.0;
-        const TileShape ts = choose_shape(c, t, &rois[pending.front()]);
         while (!pending.empty() && (int)batch.size() < opts->max_batch) {
           const int64_t i = pending.front();
-          const double rb = request_bytes(rois[i], ts);
+          const double rb = request_bytes(rois[i], choose_shape(c, t, &rois[i]));
           const bool fits = budget <= 0.0 || in_flight + bytes + rb <= budget;
           if (!fits && !(batch.empty() && in_flight == 0.0)) break;
           batch.push_back(&rois[i]);
@@ -2155,9 +2219,9 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
         sl.busy = true;
         sl.ticket = -1;
         if (c->opts.disable_graphs)
-          SFK_TRY(enqueue_cloud_rois(c, t, batch, false, ts, sl.ws, sl.st, sl.stream));
+          SFK_TRY(enqueue_cloud_rois(c, t, batch, false, sl.ws, sl.st, sl.stream));
         else
-          SFK_TRY(enqueue_cloud_rois_graph(c, t, batch, ts, sl));
+          SFK_TRY(enqueue_cloud_rois_graph(c, t, batch, sl));
         SFK_HIP(c, hipEventRecord(sl.done, sl.stream));
         slot_bytes[si] = bytes;
         in_flight += bytes;
