@@ -300,8 +300,9 @@ constexpr int kIdBlock = 256;
 // The evaluation kernel. Template parameters: tile shape (TX, TY, TZ), kernel
 // (Epanechnikov / truncated Gaussian), bandwidth source (uniform, per-particle
 // isotropic, per-particle anisotropic) and counting mode. Membership and the
-// Epanechnikov value are double (same rate as unpacked float32 on gfx950);
-// the Gaussian factors are float32 exp2 of the double exponents.
+// Epanechnikov value 1 - u2 are double (same rate as unpacked float32 on
+// gfx950), each term then rounded once to float32; the Gaussian factors are
+// float32 exp2 of the double exponents.
 template <int TX, int TY, int TZ, int KK, int PP, bool CNT>
 __global__ __launch_bounds__(256) void k_eval(
     TreeView tv, const RoiDev* __restrict__ rois, const double* __restrict__ coords,
@@ -312,11 +313,13 @@ __global__ __launch_bounds__(256) void k_eval(
     int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr) {
   constexpr int T = TX * TY * TZ;
   constexpr int NPL = T >= 64 ? T / 64 : 1;
-  using Acc = typename std::conditional<(KK == KK_EPAN && !CNT), double, float>::type;
-  // particle buffers of the leaf pipeline (fewer where double accumulators
-  // leave fewer registers); each pipeline round appends up to NB leaves to
-  // the queue before draining it, hence its capacity
-  constexpr int NB = sizeof(Acc) == 8 ? 2 : 3;
+  // Per-lane node accumulators are float32: a lane adds one term per drained
+  // batch of 64 particles (at most chunk_leaves terms per work item), the 64
+  // lanes are combined by a 6-level tree and the chunks of a tile in double.
+  using Acc = float;
+  // particle buffers of the leaf pipeline; each pipeline round appends up to
+  // NB leaves to the queue before draining it, hence its capacity
+  constexpr int NB = 3;
   constexpr int QCAP = 64 * (NB + 1);
   __shared__ int32_t lds_stack[4][SFK_STACK];
   __shared__ float4 lds_qpts[4][QCAP];
@@ -427,6 +430,7 @@ __global__ __launch_bounds__(256) void k_eval(
             }
           }
       } else if constexpr (KK == KK_EPAN) {
+        const float wf = (float)w;
 #pragma unroll
         for (int j = 0; j < TY; ++j)
 #pragma unroll
@@ -435,12 +439,12 @@ __global__ __launch_bounds__(256) void k_eval(
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
               const double u2 = tt + sz[k];
-              const double v = fmax(1.0 - u2, 0.0);
+              const float v = (float)fmax(1.0 - u2, 0.0);
               Acc& a = acc[i + TX * (j + TY * k)];
               if constexpr (PP == PP_UNIFORM)
                 a = a + v;
               else
-                a = fma(w, v, a);
+                a = fmaf(wf, v, a);
             }
           }
       } else {
@@ -506,7 +510,9 @@ __global__ __launch_bounds__(256) void k_eval(
       p = tv.pts[slot];
       if constexpr (PP == PP_ANISO) prm = tv.pparam[slot];
     };
-    auto cull = [&](const float4 p, const float4 prm, bool live) {
+    // does the particle's support reach the tile box? (same monotone bound
+    // as the tree walk)
+    auto keep_of = [&](const float4 p, const float4 prm) {
       float ihx = uih0, ihy = uih1, ihz = uih2;
       if constexpr (PP == PP_ISO) {
         ihx = ihy = ihz = p.w;
@@ -520,7 +526,11 @@ __global__ __launch_bounds__(256) void k_eval(
       const double gy = fmax(fmax(g.lo[1] - py, py - g.hi[1]), 0.0);
       const double gz = fmax(fmax(g.lo[2] - pz, pz - g.hi[2]), 0.0);
       const double ux = gx * (double)ihx, uy = gy * (double)ihy, uz = gz * (double)ihz;
-      const bool keep = live && ((ux * ux + uy * uy) + uz * uz) < c2;
+      return ((ux * ux + uy * uy) + uz * uz) < c2;
+    };
+    // append the kept particles of one leaf (lane order) to the queue; the
+    // caller makes the writes visible (wave_sync) before the queue is read
+    auto push = [&](const float4 p, const float4 prm, bool keep) {
       const uint64_t m = ballot(keep);
       if (keep) {
         const int pos = qn + popc64(m & lanemask_lt());
@@ -528,6 +538,9 @@ __global__ __launch_bounds__(256) void k_eval(
         if constexpr (PP == PP_ANISO) qa[pos] = prm;
       }
       qn += popc64(m);
+    };
+    auto cull = [&](const float4 p, const float4 prm, bool live) {
+      push(p, prm, live && keep_of(p, prm));
       wave_sync();
     };
     auto cull_push = [&](const float4 p, const float4 prm) {
@@ -579,11 +592,14 @@ __global__ __launch_bounds__(256) void k_eval(
           __builtin_amdgcn_sched_barrier(0);
         }
         for (int i = 0; i < n; i += NB) {
+          // appends only need to be visible to the drain: one visibility
+          // point per round lets the compiler overlap consecutive culls
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
-            cull(pb[u], ab[u], i + u < n);
+            push(pb[u], ab[u], i + u < n && keep_of(pb[u], ab[u]));
             fetch(__builtin_amdgcn_readfirstlane(ids[min(i + u + NB, n - 1)]), pb[u], ab[u]);
           }
+          wave_sync();
           while (qn >= 64) drain64();
         }
         wave_sync();

@@ -867,16 +867,17 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   return SFK_OK;
 }
 
-// Grow the list capacities from every direct-path batch whose header
-// readback has completed (never blocks).
+// Grow the list capacities from the direct-path batches whose header
+// readback has completed, oldest first, stopping at the first one still in
+// flight (never blocks; about one event query per call in steady state).
 void absorb_stats(Workspace& ws, const Staging& st);
-void absorb_ready(Workspace& ws, Staging* ring, int n) {
+void absorb_ready(Workspace& ws, Staging* ring, int n, int oldest) {
   for (int i = 0; i < n; ++i) {
-    Staging& st = ring[i];
-    if (st.stats_pending && st.ev_valid && hipEventQuery(st.ev) == hipSuccess) {
-      absorb_stats(ws, st);
-      st.stats_pending = false;
-    }
+    Staging& st = ring[(oldest + i) % n];
+    if (!st.stats_pending || !st.ev_valid) continue;
+    if (hipEventQuery(st.ev) != hipSuccess) break;
+    absorb_stats(ws, st);
+    st.stats_pending = false;
   }
 }
 
@@ -1153,17 +1154,33 @@ int tune_key(const sfk_roi* r) {
   return (r->kernel * 4 + r->bw) * 8 + bucket;
 }
 
-// Untuned default per support/spacing bucket (measured on 1e8-1e9 point
-// clumpy clouds): a support below half the node spacing reaches at most one
-// node per particle, so one node per wavefront reads only the particles near
-// nodes; larger supports share each particle among more nodes of a tile.
-int default_shape(int key) {
+// Untuned default tile shape. Smaller tiles pay off only where a node's
+// support holds many particles (measured on clumpy clouds of 1e7-1e9 points:
+// below about 2048 expected particles per node support the per-tile work
+// dominates and 4x4x4 wins at every support/spacing ratio). Above that, per
+// support/spacing bucket: a support below half the node spacing reaches at
+// most one node per particle, so one node per wavefront reads only the
+// particles near nodes; larger supports share each particle among more nodes.
+int default_shape(int key, double particles_per_support) {
   const int bucket = key & 7;
-  if (bucket == 0) return 1;  // per-particle bandwidths
+  if (bucket == 0 || particles_per_support < 2048.0) return 1;
   if (bucket <= 2) return 5;  // support < 0.5 spacing
   if (bucket == 3) return 4;  // [0.5, 1)
   if (bucket == 4) return 3;  // [1, 2)
   return 1;
+}
+
+// Expected particles in the support box of one node at the cloud's mean
+// density (0 for per-particle bandwidths).
+double particles_per_support(sfk_tree t, const sfk_roi* r) {
+  if (!t || (r->bw != SFK_BW_FIXED && r->bw != SFK_BW_ROI_SCALED)) return 0.0;
+  double vol = 1.0, sup = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    vol *= std::max(1e-30, (double)t->bbox[3 + k] - (double)t->bbox[k]);
+    const double h = r->bw == SFK_BW_FIXED ? (double)r->h[k] : (double)r->h[0] * (r->hi[k] - r->lo[k]);
+    sup *= 2.0 * h * (r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 : 1.0);
+  }
+  return (double)t->n * sup / vol;
 }
 
 TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
@@ -1171,19 +1188,7 @@ TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
   const int key = tune_key(r);
   auto it = c->tune.find(key);
   if (it != c->tune.end()) return shape_of(it->second);
-  int shape = default_shape(key);
-  if (shape == 5 && t) {
-    // one node per wavefront pays off only when a node's support holds a few
-    // leaves' worth of particles (estimate: the cloud's mean density)
-    double vol = 1.0, sup = 1.0;
-    for (int k = 0; k < 3; ++k) {
-      vol *= std::max(1e-30, (double)t->bbox[3 + k] - (double)t->bbox[k]);
-      const double h = r->bw == SFK_BW_FIXED ? (double)r->h[k] : (double)r->h[0] * (r->hi[k] - r->lo[k]);
-      sup *= 2.0 * h * (r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 : 1.0);
-    }
-    if ((double)t->n * sup / vol < 2048.0) shape = 4;
-  }
-  return shape_of(shape);
+  return shape_of(default_shape(key, particles_per_support(t, r)));
 }
 
 // Launch everything a ticket needs on a slot. CLOUD ROIs go through one
@@ -1659,12 +1664,13 @@ static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStre
                               bool count_mode) {
   if (c->direct_last_valid && c->direct_last_stream != s)
     SFK_HIP(c, hipStreamWaitEvent(s, c->direct_last, 0));
+  const int oldest = c->direct_next;
   Staging& st = c->direct_st[c->direct_next];
   c->direct_next = (c->direct_next + 1) % kStagingRing;
   if (roi->set == SFK_SET_IN_ROI) {
     SFK_TRY(eval_subcloud(c, t, roi, count_mode, shape_of(1), c->direct_ws, st, s, nullptr));
   } else {
-    absorb_ready(c->direct_ws, c->direct_st, kStagingRing);
+    absorb_ready(c->direct_ws, c->direct_st, kStagingRing, oldest);
     std::vector<const sfk_roi*> v{roi};
     SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, c->direct_ws, st, s));
   }
@@ -2020,7 +2026,7 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
   (void)hipEventDestroy(e1);
   if (st != SFK_OK) return st;
   for (auto& kv : cost) {
-    int best = default_shape(kv.first);
+    int best = 1;
     for (int shape = 1; shape <= kNumShapes; ++shape)
       if (kv.second[shape] < kv.second[best]) best = shape;
     c->tune[kv.first] = best;
