@@ -425,7 +425,7 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // real distances. The box hierarchy is then walked with the wavefront's
 // largest threshold (a box farther than that cannot hold a closer
 // particle); the leaves it yields are kept in a per-wave list and visited
-// nearest-first in three distance bands, so thresholds shrink early. Per
+// nearest-first in five distance bands, so thresholds shrink early. Per
 // visited leaf a lane takes part only if its own threshold exceeds its
 // distance to the leaf box, and per group of 8 particles only if it exceeds
 // its distance to that group's box. Exact: the canonical float32 distances
@@ -437,6 +437,7 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 constexpr int kKnnSub = 8;                          // particles per sub-block
 constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
 constexpr int kKnnList = 256;                       // leaves held for ordering
+constexpr int kKnnBands = 5;                        // distance bands of the visiting order
 
 // Boxes of the sub-blocks of 8 consecutive particles: 6 floats (lo, hi) per
 // sub-block. A sub-block without real particles gets an empty box, whose
@@ -540,11 +541,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
 #pragma unroll
         for (int u = 0; u < kKnnSub; ++u) {
           const float4 p = lp[j * kKnnSub + u];
-          float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
-          if (j * kKnnSub + u == self || !real) x = __builtin_huge_valf();
+          const float x = canon_d2(q.x, q.y, q.z, p.x, p.y, p.z);
           ld2[u * 64 + lane] = x;  // own column: no other lane reads it
           if (x < thr) mark |= 1u << u;
         }
+        // the query itself and padding lanes never insert
+        const int rel = self - j * kKnnSub;
+        if ((unsigned)rel < (unsigned)kKnnSub) mark &= ~(1u << rel);
+        if (!real) mark = 0;
         int rounds = __popc(mark);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off, 64));
@@ -629,16 +633,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
         wave_sync();
       }
     };
-    // Order the held leaves by distance band into ord[], dropping those no
+    // Order the held leaves by distance band (limits tau/256, tau/64, tau/16,
+    // tau/4, open) into ord[], dropping those no
     // lane needs (thresholds only shrink, so a leaf no lane needs now is
     // never needed); leaf boxes come in 64 at a time, one per lane.
     auto order = [&]() {
       int no = 0;
       float lo_lim = -1.0f;
 #pragma unroll 1
-      for (int band = 0; band < 3; ++band) {
-        const float hi_lim = band == 0 ? tau * 0.0625f : band == 1 ? tau * 0.25f
-                                                                   : __builtin_huge_valf();
+      for (int band = 0; band < kKnnBands; ++band) {
+        // band limits tau / 4^(kKnnBands - 1 - band); the last one is open
+        const float hi_lim = band == kKnnBands - 1
+                                 ? __builtin_huge_valf()
+                                 : tau * __builtin_ldexpf(1.0f, -2 * (kKnnBands - 1 - band));
         for (int i0 = 0; i0 < ln; i0 += 64) {
           const int i = i0 + lane;
           const float key = i < ln ? lkey[i] : -2.0f;
