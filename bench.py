@@ -9,7 +9,11 @@ density grid: tree build (bounding box, Morton sort, leaves, box hierarchy),
 k-NN bandwidths, tile range query and evaluation.
 
 Prints one JSON line (rank 0): value = useful kernel evaluations (node,
-particle pairs inside the support) per second of step time.
+particle pairs inside the support) per second of step time. The line also
+carries, outside the timed steps, the batched vs one-ROI-per-launch
+comparison (256 uneven ROIs on a 100M-point cloud) and the served request
+trace (8 streams at 90 Hz on a 1B-point cloud, continuous batching vs one ROI
+per launch in FIFO order), both on clouds drawn on the device.
 """
 import argparse
 import json
@@ -88,6 +92,10 @@ def parse():
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batched vs one-ROI-per-launch comparison")
     p.add_argument("--n-batch", type=int, default=256)
+    p.add_argument("--batch-points", type=int, default=100_000_000,
+                   help="cloud size of the batched vs one-per-launch comparison")
+    p.add_argument("--serve-points", type=int, default=1_000_000_000,
+                   help="cloud size of the served request trace")
     p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB fill and a 1 GiB elementwise scale first "
@@ -131,12 +139,13 @@ def cpu_baseline(pts, roi, h2, n_nodes, seed=7):
                       % (len(nodes), len(pts), dt, useful)}
 
 
-def batch_vs_single(ctx, tree, torch, n_rois):
+def batch_vs_single(ctx, tree, torch, n_rois, label):
     """Many uneven ROIs in one persistent launch vs one launch per ROI, on
     the resident tree (same kernels, same results)."""
     import synth
     rois = synth.random_batch_rois(n_rois, seed=4)
     outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    log("batch vs one launch per ROI:", n_rois, "ROIs")
     # warm both paths
     ctx.wait(ctx.submit(tree, rois, outs))
     for r, o in zip(rois, outs):
@@ -165,7 +174,7 @@ def batch_vs_single(ctx, tree, torch, n_rois):
         useful += ctx.debug_eval_count(tree, r)[0]
     return {
         "workload": "%d ROIs, sides log-uniform in [1e-3, 1], grids 16^3-128^3, Epanechnikov, "
-                    "h = 0.01 x side, on the resident 10M-point tree" % n_rois,
+                    "h = 0.01 x side, on the resident %s tree" % (n_rois, label),
         "nodes": int(sum(r.n_nodes for r in rois)), "useful_evals": int(useful),
         "batched_ms": batch_ms, "single_launch_ms": single_ms,
         "batched_evals_per_s": useful / (batch_ms * 1e-3),
@@ -178,7 +187,7 @@ def batch_vs_single(ctx, tree, torch, n_rois):
     }
 
 
-def serving(ctx, tree, torch, duration_s):
+def serving(ctx, tree, torch, duration_s, label):
     """VR-like request loop on the resident tree: 8 streams of Poisson
     arrivals at 90 Hz each (sides log-uniform in [1e-4, 1], panning centres,
     grids 32^3-128^3, Epanechnikov, h = 0.01 x side). Continuous batching
@@ -188,13 +197,15 @@ def serving(ctx, tree, torch, duration_s):
     outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
     rec = {"workload": "%d requests over %.1f s from 8 streams at 90 Hz, sides log-uniform "
                        "in [1e-4, 1], grids 32^3-128^3, Epanechnikov, h = 0.01 x side, "
-                       "on the resident 10M-point tree" % (len(rois), duration_s),
+                       "on the resident %s tree" % (len(rois), duration_s, label),
            "frame_budget_ms": 1000.0 / 90.0}
+    log("counting useful pairs of %d requests" % len(rois))
     useful = 0
     for r in rois:
         useful += ctx.debug_eval_count(tree, r)[0]
     rec["useful_evals"] = int(useful)
     for name, mode in (("continuous_batching", 0), ("one_roi_per_launch", 1)):
+        log("serving:", name)
         res, s = ctx.serve(tree, arr, rois, outs, mode=mode, n_slots=4, max_batch=64,
                            budget_bytes=float(8 << 30))
         lat = np.array([res[i].latency_ms for i in range(len(rois))])
@@ -277,23 +288,42 @@ def main():
         "useful_evals": useful, "tested_pairs": tested,
         "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
     }
-    if args.workload == "per_point_10m" and not args.no_batch:
-        try:
-            result["batch_vs_single"] = batch_vs_single(ctx, tree, torch, args.n_batch)
-        except Exception as e:  # report, never hide
-            result["batch_vs_single"] = {"error": repr(e)}
-    if args.workload == "per_point_10m" and not args.no_serve:
-        try:
-            result["serving"] = serving(ctx, tree, torch, args.serve_seconds)
-        except Exception as e:  # report, never hide
-            result["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         h2 = ctx.debug_point_h2(tree) if knn_k else None
         log("timing the oracle on a node sample")
         result["cpu_baseline"] = cpu_baseline(pts, roi, h2, args.cpu_sample_nodes)
     tree.close()
+    del xyz, out
+    torch.cuda.empty_cache()
+    if args.workload == "per_point_10m" and not args.no_batch:
+        result["batch_vs_single"] = large_section(
+            ctx, torch, args.batch_points, 3,
+            lambda t, lab: batch_vs_single(ctx, t, torch, args.n_batch, lab))
+    if args.workload == "per_point_10m" and not args.no_serve:
+        result["serving"] = large_section(
+            ctx, torch, args.serve_points, 5,
+            lambda t, lab: serving(ctx, t, torch, args.serve_seconds, lab))
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def large_section(ctx, torch, n, seed, fn):
+    """Run fn(tree, label) on a clumpy cloud of n points drawn on the device
+    (tree built outside any timed region); errors are reported, not hidden."""
+    import synth
+    try:
+        log("drawing %d clumpy points on the device" % n)
+        xyz, _ = synth.clumpy_cloud_device(n, seed)
+        tree = ctx.build_tree(xyz)
+        del xyz
+        torch.cuda.empty_cache()
+        label = "%s-point" % ("%dB" % (n // 10**9) if n % 10**9 == 0 else "%dM" % (n // 10**6))
+        rec = fn(tree, label)
+        tree.close()
+        torch.cuda.empty_cache()
+        return rec
+    except Exception as e:  # report, never hide
+        return {"error": repr(e)}
 
 
 if __name__ == "__main__":
