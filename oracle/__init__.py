@@ -67,6 +67,12 @@ def _lib():
             getattr(lib, name).restype = C.c_double
         lib.orc_kernel_ck.argtypes = [C.c_int]
         lib.orc_kernel_ck.restype = C.c_double
+        lib.orc_sample_points.argtypes = [vp, vp, vp, vp, vp, C.c_int64, vp]
+        lib.orc_sample_points.restype = None
+        lib.orc_select_points.argtypes = [vp, vp, vp, vp, C.c_double, vp, C.c_int64, vp]
+        lib.orc_select_points.restype = C.c_int64
+        lib.orc_iso_cells.argtypes = [vp, vp, C.c_double, vp, vp]
+        lib.orc_iso_cells.restype = C.c_int64
         _LIB = lib
     return _LIB
 
@@ -398,3 +404,40 @@ def candidates(pts, roi, nodes, h2=None):
     kernel, _, ih_u, _, ih_pp, _, include = _setup(pts, roi, h2)
     return candidates_raw(pts, roi, kernel, ih_u=ih_u, ih_pp=ih_pp, include=include,
                           nodes=nodes)
+
+
+# ---------------------------------------------------------------------------
+# consumers of a density grid (Section 3.1 after Eq. 8; selection section)
+# ---------------------------------------------------------------------------
+
+def sample_density(grid: np.ndarray, roi, pts: np.ndarray) -> np.ndarray:
+    """Trilinear density of the node grid at each point; 0 outside the closed box."""
+    grid = _f64(grid).ravel()
+    lo, hi, res = _geom(roi)
+    pts = _f32(pts).reshape(-1, 3)
+    out = np.zeros(pts.shape[0], dtype=np.float64)
+    _lib().orc_sample_points(_ptr(grid), _ptr(lo), _ptr(hi), _ptr(res), _ptr(pts),
+                             pts.shape[0], _ptr(out))
+    return out
+
+
+def select_points(grid: np.ndarray, roi, iso: float, pts: np.ndarray) -> np.ndarray:
+    """Ascending indices of the points in the closed box whose density is >= iso."""
+    grid = _f64(grid).ravel()
+    lo, hi, res = _geom(roi)
+    pts = _f32(pts).reshape(-1, 3)
+    idx = np.zeros(max(1, pts.shape[0]), dtype=np.int64)
+    m = _lib().orc_select_points(_ptr(grid), _ptr(lo), _ptr(hi), _ptr(res), float(iso),
+                                 _ptr(pts), pts.shape[0], _ptr(idx))
+    return idx[:m].copy()
+
+
+def iso_cells(grid: np.ndarray, roi, iso: float):
+    """Active Marching Cubes cells (ascending) and their 8-bit cases."""
+    grid = _f64(grid).ravel()
+    _, _, res = _geom(roi)
+    n_cells = int(np.prod(np.asarray(roi.res, dtype=np.int64) - 1))
+    cells = np.zeros(max(1, n_cells), dtype=np.int64)
+    cases = np.zeros(max(1, n_cells), dtype=np.uint8)
+    m = _lib().orc_iso_cells(_ptr(grid), _ptr(res), float(iso), _ptr(cells), _ptr(cases))
+    return cells[:m].copy(), cases[:m].copy()

@@ -385,3 +385,69 @@ void orc_params_from_ell(const float* ell, int64_t n, float* ih3, double* w) {
     w[j] = 1.0 / (lx * ly * lz);
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Consumers of a density grid (Section 3.1, after Eq. 8: the density at any
+ * position is the trilinear interpolation of the surrounding grid nodes;
+ * Section 4.2 / selection: a density threshold, the Marching Cubes
+ * iso-surface as selection volume, and the points inside it). Readings:
+ * a position outside the closed box B has no surrounding nodes and density
+ * 0; a point is selected when it lies in B and its interpolated density is
+ * >= the threshold (the region the iso-surface bounds); the Marching Cubes
+ * case of a cell has bit (dx + 2 dy + 4 dz) set when that corner's value is
+ * >= the threshold, and a cell is active unless its case is 0 or 255. */
+
+static int orc_in_closed_box(const double* lo, const double* hi, const float* p) {
+  for (int k = 0; k < 3; ++k) {
+    const double v = (double)p[k];
+    if (!(v >= lo[k] && v <= hi[k])) return 0;
+  }
+  return 1;
+}
+
+/* out[j] = density at pts[j] (n x 3 floats), grid values in double. */
+void orc_sample_points(const double* grid, const double* lo, const double* hi, const int* res,
+                       const float* pts, int64_t n, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j)
+    out[j] = orc_in_closed_box(lo, hi, pts + 3 * j)
+                 ? orc_trilinear(grid, lo, hi, res, pts + 3 * j)
+                 : 0.0;
+}
+
+/* Ascending indices of the selected points; returns their count. */
+int64_t orc_select_points(const double* grid, const double* lo, const double* hi,
+                          const int* res, double iso, const float* pts, int64_t n,
+                          int64_t* idx_out) {
+  int64_t m = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!orc_in_closed_box(lo, hi, pts + 3 * j)) continue;
+    if (orc_trilinear(grid, lo, hi, res, pts + 3 * j) >= iso) idx_out[m++] = j;
+  }
+  return m;
+}
+
+/* Active Marching Cubes cells in ascending linear cell index (x fastest over
+ * (res - 1) cells per axis) and their cases; returns the count. */
+int64_t orc_iso_cells(const double* grid, const int* res, double iso, int64_t* cells,
+                      uint8_t* cases) {
+  const int64_t cx = res[0] - 1, cy = res[1] - 1, cz = res[2] - 1;
+  int64_t m = 0;
+  for (int64_t k = 0; k < cz; ++k)
+    for (int64_t j = 0; j < cy; ++j)
+      for (int64_t i = 0; i < cx; ++i) {
+        int c = 0;
+        for (int b = 0; b < 8; ++b) {
+          const int dx = b & 1, dy = (b >> 1) & 1, dz = (b >> 2) & 1;
+          const double v =
+              grid[(i + dx) + (int64_t)res[0] * ((j + dy) + (int64_t)res[1] * (k + dz))];
+          if (v >= iso) c |= 1 << b;
+        }
+        if (c != 0 && c != 255) {
+          cells[m] = i + cx * (j + cy * k);
+          cases[m] = (uint8_t)c;
+          ++m;
+        }
+      }
+  return m;
+}

@@ -450,3 +450,103 @@ def test_zero_bandwidth_has_empty_support():
     assert not np.any(idx < 40)
     assert len(idx) > 0
     assert np.isfinite(oracle.density(pts, roi, nodes=centre, h2=h2)[0])
+
+
+# ---------------------------------------------------------------------------
+# consumers of a density grid: trilinear density at points, selection by a
+# density threshold, Marching Cubes cell classification
+# ---------------------------------------------------------------------------
+
+def _field(res, seed):
+    g = np.random.default_rng(seed)
+    return g.random(int(np.prod(res))).astype(np.float32) * 3.0
+
+
+def test_sample_matches_scipy_trilinear():
+    from scipy.interpolate import RegularGridInterpolator
+    res = (7, 5, 6)
+    roi = Roi((0.1, -0.3, 0.2), (0.9, 0.5, 1.4), res)
+    grid = _field(res, 11)
+    g = np.random.default_rng(12)
+    pts = np.column_stack([g.uniform(roi.lo[k], roi.hi[k], 500) for k in range(3)]).astype(np.float32)
+    pts = np.vstack([pts, np.array([roi.hi, roi.lo], np.float32)])
+    axes = [np.linspace(roi.lo[k], roi.hi[k], res[k]) for k in range(3)]
+    # grid is x fastest: index [z, y, x]
+    f = RegularGridInterpolator(axes[::-1], grid.reshape(res[2], res[1], res[0]).astype(np.float64),
+                                method="linear")
+    inside = np.all((pts.astype(np.float64) >= roi.lo) & (pts.astype(np.float64) <= roi.hi), axis=1)
+    ref = np.zeros(len(pts))
+    ref[inside] = f(pts[inside][:, ::-1].astype(np.float64))
+    got = oracle.sample_density(grid, roi, pts)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_sample_exact_at_nodes_outside_zero():
+    res = (4, 3, 5)
+    roi = Roi((0.0, 0.0, 0.0), (3.0, 2.0, 4.0), res)  # spacing 1: node coordinates are integers
+    grid = _field(res, 13)
+    nodes = np.array([[i, j, k] for k in range(5) for j in range(3) for i in range(4)], np.float32)
+    assert np.array_equal(oracle.sample_density(grid, roi, nodes), grid.astype(np.float64))
+    out = np.array([[-1e-3, 1, 1], [3.001, 1, 1], [1, 2.5, 1], [1, 1, -0.5]], np.float32)
+    assert np.array_equal(oracle.sample_density(grid, roi, out), np.zeros(4))
+    # midpoint of an edge: the mean of its two nodes
+    v = oracle.sample_density(grid, roi, np.array([[1.5, 1, 2]], np.float32))[0]
+    assert v == pytest.approx(0.5 * (float(grid[1 + 4 * (1 + 3 * 2)]) + float(grid[2 + 4 * (1 + 3 * 2)])), rel=1e-15)
+
+
+def test_select_matches_scipy_mask_and_is_inclusive():
+    from scipy.interpolate import RegularGridInterpolator
+    res = (9, 8, 7)
+    roi = Roi((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), res)
+    grid = _field(res, 14)
+    g = np.random.default_rng(15)
+    pts = g.uniform(-0.1, 1.1, size=(4000, 3)).astype(np.float32)
+    axes = [np.linspace(0, 1, r) for r in res]
+    f = RegularGridInterpolator(axes[::-1], grid.reshape(res[2], res[1], res[0]).astype(np.float64))
+    inside = np.all((pts >= 0) & (pts <= 1), axis=1)
+    vals = np.full(len(pts), -1.0)
+    vals[inside] = f(pts[inside][:, ::-1].astype(np.float64))
+    iso = float(np.median(vals[inside]))
+    clear = np.abs(vals - iso) > 1e-9
+    got = oracle.select_points(grid, roi, iso, pts)
+    assert np.all(np.diff(got) > 0)
+    want = np.nonzero(inside & (vals >= iso))[0]
+    assert np.array_equal(np.intersect1d(got, np.nonzero(clear)[0]), np.intersect1d(want, np.nonzero(clear)[0]))
+    # a point exactly at a node whose value equals the threshold is selected (>=)
+    roi1 = Roi((0.0, 0.0, 0.0), (8.0, 7.0, 6.0), res)
+    node = np.array([[3, 4, 2]], np.float32)
+    v = float(grid[3 + 9 * (4 + 8 * 2)])
+    assert list(oracle.select_points(grid, roi1, v, node)) == [0]
+    assert list(oracle.select_points(grid, roi1, np.nextafter(v, 10.0), node)) == []
+
+
+def test_iso_cells_closed_forms():
+    res = (6, 5, 4)
+    roi = Roi((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), res)
+    n = int(np.prod(res))
+    # one node above the threshold: the (up to) 8 cells around it, each with
+    # the bit of the corner that node is
+    hot = (2, 3, 1)
+    grid = np.zeros(n, np.float32)
+    grid[hot[0] + 6 * (hot[1] + 5 * hot[2])] = 1.0
+    cells, cases = oracle.iso_cells(grid, roi, 0.5)
+    want = {}
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                ci, cj, ck = hot[0] - dx, hot[1] - dy, hot[2] - dz
+                if 0 <= ci < 5 and 0 <= cj < 4 and 0 <= ck < 3:
+                    want[ci + 5 * (cj + 4 * ck)] = 1 << (dx + 2 * dy + 4 * dz)
+    assert list(cells) == sorted(want) and [want[c] for c in cells] == list(cases)
+    # a ramp along x: only the cells whose x-edge straddles the threshold,
+    # with the four dx = 1 corners set
+    ramp = np.tile(np.arange(6, dtype=np.float32), 5 * 4)
+    cells, cases = oracle.iso_cells(ramp, roi, 2.5)
+    assert len(cells) == 4 * 3 and np.all(cells % 5 == 2) and np.all(cases == 0b10101010)
+    # a constant field, and thresholds outside the range: nothing active
+    assert len(oracle.iso_cells(np.full(n, 2.0, np.float32), roi, 1.0)[0]) == 0
+    assert len(oracle.iso_cells(grid, roi, -1.0)[0]) == 0
+    assert len(oracle.iso_cells(grid, roi, 2.0)[0]) == 0
+    # the threshold itself counts as inside (>=)
+    cells, cases = oracle.iso_cells(grid, roi, 1.0)
+    assert len(cells) == len(want)
