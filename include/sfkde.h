@@ -259,6 +259,42 @@ sfk_status sfk_serve(sfk_ctx ctx, sfk_tree tree, const sfk_request* reqs, int64_
                      const sfk_serve_opts* opts, sfk_request_result* h_results,
                      sfk_serve_summary* h_summary);
 
+/* ------------------------------------------------- consumers of a grid */
+/* These take a node grid in the layout sfk_eval_roi writes (res[0] * res[1]
+ * * res[2] floats, x fastest) and the ROI whose nodes it holds; only
+ * roi->lo, roi->hi and roi->res are read. Points are n x 3 float32 (AoS) on
+ * the device. Interpolation is in double with a fixed operation order
+ * (per axis f = ((p - lo)(res - 1)) / (hi - lo), cell floor(f) clamped to
+ * [0, res - 2], t = f - cell clamped to [0, 1]; corner terms
+ * ((wx wy) wz) value summed z-major, then y, then x), so threshold decisions
+ * are reproducible. SFK_E_INVAL for a NULL pointer (unless n = 0), n < 0 or
+ * invalid geometry (res < 2, lo >= hi, non-finite). */
+
+/* Density at each point: trilinear interpolation of the surrounding grid
+ * nodes (Section 3.1, after Eq. 8), rounded once to float; 0 for a point
+ * outside the closed box. Stream-ordered, asynchronous. */
+sfk_status sfk_sample_density(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid,
+                              const float* d_xyz, int64_t n, float* d_out, void* hip_stream);
+
+/* Selection (selection section: a density threshold, the region bounded by
+ * the grid's iso-surface at that threshold, the points inside it): the
+ * ascending indices of the points inside the closed box whose interpolated
+ * density is >= iso. Writes the first min(count, cap) indices to d_idx
+ * (int64, device) and the full count to *h_count; blocks on the stream. */
+sfk_status sfk_select_points(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid, double iso,
+                             const float* d_xyz, int64_t n, int64_t* d_idx, int64_t cap,
+                             int64_t* h_count, void* hip_stream);
+
+/* Marching Cubes classification of the grid's (res - 1)^3 cells against iso
+ * (selection section): the case of a cell has bit dx + 2 dy + 4 dz set when
+ * that corner's value is >= iso; a cell is active unless its case is 0 or
+ * 255. Writes the first min(count, cap) active cells in ascending linear
+ * cell index (x fastest over res - 1 cells per axis) to d_cells (int64) and
+ * their cases to d_cases (uint8), the full count to *h_count; blocks. */
+sfk_status sfk_iso_cells(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid, double iso,
+                         int64_t* d_cells, uint8_t* d_cases, int64_t cap, int64_t* h_count,
+                         void* hip_stream);
+
 /* ----------------------------------------------------------- test exports */
 
 /* Support sets S(n) of grid nodes [node_begin, node_end) of one ROI (CLOUD

@@ -255,6 +255,60 @@ class Context:
                                                     idx.shape[0], C.byref(need)))
         return offs, idx[:need.value]
 
+    # ---- consumers of a density grid (all on the device) ----
+
+    @staticmethod
+    def _grid_args(roi, grid, xyz=None):
+        import torch
+        if not (isinstance(grid, torch.Tensor) and grid.is_cuda and grid.dtype == torch.float32
+                and grid.is_contiguous() and grid.numel() == roi.n_nodes):
+            raise ValueError("grid must be a contiguous float32 device tensor of the ROI's nodes")
+        if xyz is not None and not (isinstance(xyz, torch.Tensor) and xyz.is_cuda
+                                    and xyz.dtype == torch.float32 and xyz.is_contiguous()
+                                    and xyz.dim() == 2 and xyz.shape[1] == 3):
+            raise ValueError("points must be a contiguous (n, 3) float32 device tensor")
+
+    def sample_density(self, roi, grid, xyz, out=None, stream=None):
+        """sfk_sample_density: trilinear density of `grid` (the nodes of `roi`) at each point."""
+        import torch
+        self._grid_args(roi, grid, xyz)
+        n = xyz.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+        r = roi_struct(roi, 0)
+        self._check(self._lib.sfk_sample_density(self._h, C.byref(r), grid.data_ptr(),
+                                                 xyz.data_ptr(), n, out.data_ptr(),
+                                                 _stream_ptr(stream)))
+        return out
+
+    def select_points(self, roi, grid, iso: float, xyz, stream=None):
+        """sfk_select_points: ascending int64 indices of the points in the box with density >= iso."""
+        import torch
+        self._grid_args(roi, grid, xyz)
+        n = xyz.shape[0]
+        cap = n
+        idx = torch.empty(max(1, cap), dtype=torch.int64, device=xyz.device)
+        cnt = C.c_int64()
+        r = roi_struct(roi, 0)
+        self._check(self._lib.sfk_select_points(self._h, C.byref(r), grid.data_ptr(), float(iso),
+                                                xyz.data_ptr(), n, idx.data_ptr(), cap,
+                                                C.byref(cnt), _stream_ptr(stream)))
+        return idx[:cnt.value]
+
+    def iso_cells(self, roi, grid, iso: float, stream=None):
+        """sfk_iso_cells: (active cells ascending, their Marching Cubes cases) as device tensors."""
+        import torch
+        self._grid_args(roi, grid)
+        nc = (roi.res[0] - 1) * (roi.res[1] - 1) * (roi.res[2] - 1)
+        cells = torch.empty(max(1, nc), dtype=torch.int64, device=grid.device)
+        cases = torch.empty(max(1, nc), dtype=torch.uint8, device=grid.device)
+        cnt = C.c_int64()
+        r = roi_struct(roi, 0)
+        self._check(self._lib.sfk_iso_cells(self._h, C.byref(r), grid.data_ptr(), float(iso),
+                                            cells.data_ptr(), cases.data_ptr(), nc, C.byref(cnt),
+                                            _stream_ptr(stream)))
+        return cells[:cnt.value], cases[:cnt.value]
+
     def debug_point_h2(self, tree: "Tree") -> np.ndarray:
         n = tree.info()[0]
         out = np.zeros(max(n, 1), dtype=np.float32)

@@ -98,6 +98,13 @@ EXPORTS = {
     "sfk_debug_candidates": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_int64,
                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                        C.POINTER(C.c_int64)]),
+    "sfk_sample_density": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_void_p]),
+    "sfk_select_points": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_double,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                    C.POINTER(C.c_int64), C.c_void_p]),
+    "sfk_iso_cells": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_double, C.c_void_p,
+                                C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
     "sfk_debug_point_h2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

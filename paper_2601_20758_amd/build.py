@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfkde.so")
-SOURCES = ["scan.hip", "build.hip", "eval.hip", "mbe.hip", "sfk_runtime.cpp"]
+SOURCES = ["scan.hip", "build.hip", "eval.hip", "mbe.hip", "consumers.hip", "sfk_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -1,0 +1,189 @@
+// Consumers of a density grid on the device, so a grid never has to cross
+// PCIe for them: the density at arbitrary positions (trilinear interpolation
+// of the surrounding grid nodes, Section 3.1 after Eq. 8), the selection of
+// the points whose density reaches a threshold (the region a Marching Cubes
+// iso-surface of the grid bounds, selection section), and the Marching Cubes
+// classification of the grid's cells against that threshold.
+//
+// Arithmetic: double, every operation rounded, no contraction (the library
+// is built with -ffp-contract=off), in this fixed order per axis
+//   f = ((p - lo) * (res - 1)) / (hi - lo), cell c = floor(f) clamped to
+//   [0, res - 2], t = f - c clamped to [0, 1],
+// and the eight corner terms ((wx * wy) * wz) * value accumulated z-major,
+// then y, then x, so a threshold decision is the same as the definition's.
+#include <algorithm>
+
+#include "sfk_device.h"
+
+namespace sfk {
+
+struct GridGeom {
+  double lo[3], hi[3];
+  int32_t res[3];
+  int32_t pad_;
+};
+
+__device__ __forceinline__ bool in_closed_box(const GridGeom& g, float x, float y, float z) {
+  const double p[3] = {(double)x, (double)y, (double)z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!(p[k] >= g.lo[k] && p[k] <= g.hi[k])) return false;
+  return true;
+}
+
+__device__ __forceinline__ double trilinear_at(const float* __restrict__ grid, const GridGeom& g,
+                                               float x, float y, float z) {
+  const double p[3] = {(double)x, (double)y, (double)z};
+  int c[3];
+  double t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double f = ((p[k] - g.lo[k]) * (double)(g.res[k] - 1)) / (g.hi[k] - g.lo[k]);
+    int ci = (int)floor(f);
+    ci = max(0, min(ci, g.res[k] - 2));
+    double tt = f - (double)ci;
+    tt = fmin(fmax(tt, 0.0), 1.0);
+    c[k] = ci;
+    t[k] = tt;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const double w = ((dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1])) *
+                         (dz ? t[2] : 1.0 - t[2]);
+        const int64_t idx =
+            (int64_t)(c[0] + dx) +
+            (int64_t)g.res[0] * ((int64_t)(c[1] + dy) + (int64_t)g.res[1] * (int64_t)(c[2] + dz));
+        acc += w * (double)grid[idx];
+      }
+  return acc;
+}
+
+// density at each point (0 outside the closed box), rounded once to float
+__global__ __launch_bounds__(256) void k_sample(const float* __restrict__ grid, GridGeom g,
+                                                const float* __restrict__ xyz, int64_t n,
+                                                float* __restrict__ out) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const float x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+    out[j] = in_closed_box(g, x, y, z) ? (float)trilinear_at(grid, g, x, y, z) : 0.0f;
+  }
+}
+
+// 1 where the point lies in the closed box and its density is >= iso
+__global__ __launch_bounds__(256) void k_select_flags(const float* __restrict__ grid, GridGeom g,
+                                                      double iso, const float* __restrict__ xyz,
+                                                      int64_t n, int32_t* __restrict__ flags) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const float x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+    flags[j] = (in_closed_box(g, x, y, z) && trilinear_at(grid, g, x, y, z) >= iso) ? 1 : 0;
+  }
+}
+
+// ascending indices of the flagged entries (the first `cap` of them)
+__global__ __launch_bounds__(256) void k_compact_index(const int32_t* __restrict__ flags,
+                                                       const int64_t* __restrict__ pos, int64_t n,
+                                                       int64_t* __restrict__ idx, int64_t cap) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    if (flags[j] && pos[j] < cap) idx[pos[j]] = j;
+}
+
+// Marching Cubes case of every cell (bit dx + 2 dy + 4 dz set when that
+// corner's value is >= iso); flag = case not in {0, 255}
+__global__ __launch_bounds__(256) void k_iso_flags(const float* __restrict__ grid, GridGeom g,
+                                                   double iso, int64_t n_cells,
+                                                   int32_t* __restrict__ flags,
+                                                   uint8_t* __restrict__ case_all) {
+  const int64_t cx = g.res[0] - 1, cy = g.res[1] - 1;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_cells;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q % cx, j = (q / cx) % cy, k = q / (cx * cy);
+    int cs = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int dx = b & 1, dy = (b >> 1) & 1, dz = (b >> 2) & 1;
+      const double v = (double)grid[(i + dx) + (int64_t)g.res[0] * ((j + dy) + (int64_t)g.res[1] * (k + dz))];
+      if (v >= iso) cs |= 1 << b;
+    }
+    case_all[q] = (uint8_t)cs;
+    flags[q] = (cs != 0 && cs != 255) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_cells(const int32_t* __restrict__ flags,
+                                                       const int64_t* __restrict__ pos,
+                                                       const uint8_t* __restrict__ case_all,
+                                                       int64_t n, int64_t* __restrict__ cells,
+                                                       uint8_t* __restrict__ cases, int64_t cap) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    if (flags[q] && pos[q] < cap) {
+      cells[pos[q]] = q;
+      cases[pos[q]] = case_all[q];
+    }
+}
+
+static GridGeom geom_of(const double lo[3], const double hi[3], const int32_t res[3]) {
+  GridGeom g{};
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = lo[k];
+    g.hi[k] = hi[k];
+    g.res[k] = res[k];
+  }
+  return g;
+}
+
+static unsigned grid_of(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+}
+
+hipError_t launch_sample(const float* grid, const double lo[3], const double hi[3],
+                         const int32_t res[3], const float* xyz, int64_t n, float* out,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample, dim3(grid_of(n)), dim3(256), 0, s, grid, geom_of(lo, hi, res), xyz,
+                     n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_flags(const float* grid, const double lo[3], const double hi[3],
+                               const int32_t res[3], double iso, const float* xyz, int64_t n,
+                               int32_t* flags, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select_flags, dim3(grid_of(n)), dim3(256), 0, s, grid,
+                     geom_of(lo, hi, res), iso, xyz, n, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_index(const int32_t* flags, const int64_t* pos, int64_t n, int64_t* idx,
+                                int64_t cap, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_index, dim3(grid_of(n)), dim3(256), 0, s, flags, pos, n, idx, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_flags(const float* grid, const int32_t res[3], double iso, int64_t n_cells,
+                            int32_t* flags, uint8_t* case_all, hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  const double z[3] = {0.0, 0.0, 0.0};
+  hipLaunchKernelGGL(k_iso_flags, dim3(grid_of(n_cells)), dim3(256), 0, s, grid,
+                     geom_of(z, z, res), iso, n_cells, flags, case_all);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const uint8_t* case_all,
+                                int64_t n, int64_t* cells, uint8_t* cases, int64_t cap,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_cells, dim3(grid_of(n)), dim3(256), 0, s, flags, pos, case_all, n,
+                     cells, cases, cap);
+  return hipGetLastError();
+}
+
+}  // namespace sfk

@@ -82,6 +82,21 @@ struct TileShape { int tx, ty, tz; };
 // ---- host-side launch wrappers (defined in the .hip files) ----
 namespace sfk {
 
+// consumers.hip
+hipError_t launch_sample(const float* grid, const double lo[3], const double hi[3],
+                         const int32_t res[3], const float* xyz, int64_t n, float* out,
+                         hipStream_t s);
+hipError_t launch_select_flags(const float* grid, const double lo[3], const double hi[3],
+                               const int32_t res[3], double iso, const float* xyz, int64_t n,
+                               int32_t* flags, hipStream_t s);
+hipError_t launch_compact_index(const int32_t* flags, const int64_t* pos, int64_t n, int64_t* idx,
+                                int64_t cap, hipStream_t s);
+hipError_t launch_iso_flags(const float* grid, const int32_t res[3], double iso, int64_t n_cells,
+                            int32_t* flags, uint8_t* case_all, hipStream_t s);
+hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const uint8_t* case_all,
+                                int64_t n, int64_t* cells, uint8_t* cases, int64_t cap,
+                                hipStream_t s);
+
 // scan.hip
 hipError_t scan_exclusive_i32_i64(const int32_t* in, int64_t* out, int64_t n,
                                   int64_t* total, void* tmp, size_t tmp_bytes, hipStream_t s);

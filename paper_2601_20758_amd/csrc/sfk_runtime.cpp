@@ -1797,6 +1797,123 @@ sfk_status sfk_cancel(sfk_ctx c, sfk_ticket tid) {
 
 // ---------------------------------------------------------------- debug
 
+// ---- consumers of a grid: density at points, selection, Marching Cubes cells ----
+
+namespace {
+sfk_status validate_grid_args(sfk_ctx c, const sfk_roi* roi, const float* grid, int64_t n,
+                              const void* a, const void* b) {
+  if (!roi || !grid) {
+    set_err(c, "NULL ROI or grid");
+    return SFK_E_INVAL;
+  }
+  if (n < 0 || (n > 0 && (!a || !b))) {
+    set_err(c, "invalid point arguments (n = %lld)", (long long)n);
+    return SFK_E_INVAL;
+  }
+  int64_t m = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(roi->lo[k]) && std::isfinite(roi->hi[k]) && roi->hi[k] > roi->lo[k]) ||
+        roi->res[k] < 2) {
+      set_err(c, "grid axis %d needs finite lo < hi and res >= 2", k);
+      return SFK_E_INVAL;
+    }
+    m *= roi->res[k];
+  }
+  if (m > (int64_t)1 << 31) {
+    set_err(c, "grid of %lld nodes exceeds 2^31", (long long)m);
+    return SFK_E_INVAL;
+  }
+  return SFK_OK;
+}
+}  // namespace
+
+sfk_status sfk_sample_density(sfk_ctx c, const sfk_roi* roi, const float* d_grid,
+                              const float* d_xyz, int64_t n, float* d_out, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  SFK_TRY(validate_grid_args(c, roi, d_grid, n, d_xyz, d_out));
+  SFK_HIP(c, sfk::launch_sample(d_grid, roi->lo, roi->hi, roi->res, d_xyz, n, d_out,
+                                (hipStream_t)hip_stream));
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_select_points(sfk_ctx c, const sfk_roi* roi, const float* d_grid, double iso,
+                             const float* d_xyz, int64_t n, int64_t* d_idx, int64_t cap,
+                             int64_t* h_count, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  SFK_TRY(validate_grid_args(c, roi, d_grid, n, d_xyz, d_idx));
+  if (!h_count || cap < 0 || !std::isfinite(iso)) {
+    set_err(c, "invalid selection arguments");
+    return SFK_E_INVAL;
+  }
+  *h_count = 0;
+  if (n == 0) return SFK_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  TmpBuf flags(c), pos(c), tmp(c), total(c);
+  sfk_status st;
+  if ((st = flags.get(sizeof(int32_t) * (size_t)n, "selection flags")) != SFK_OK ||
+      (st = pos.get(sizeof(int64_t) * (size_t)n, "selection offsets")) != SFK_OK ||
+      (st = tmp.get(sfk::scan_tmp_bytes(n), "scan scratch")) != SFK_OK ||
+      (st = total.get(sizeof(int64_t), "selection count")) != SFK_OK)
+    return st;
+  int64_t cnt = 0;
+  if (sfk::launch_select_flags(d_grid, roi->lo, roi->hi, roi->res, iso, d_xyz, n,
+                               flags.as<int32_t>(), s) != hipSuccess ||
+      sfk::scan_exclusive_i32_i64(flags.as<int32_t>(), pos.as<int64_t>(), n, total.as<int64_t>(),
+                                  tmp.b.p, tmp.b.bytes, s) != hipSuccess ||
+      sfk::launch_compact_index(flags.as<int32_t>(), pos.as<int64_t>(), n, d_idx, cap, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(&cnt, total.b.p, sizeof cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    set_err(c, "selection kernels failed");
+    return SFK_E_DEVICE;
+  }
+  *h_count = cnt;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_iso_cells(sfk_ctx c, const sfk_roi* roi, const float* d_grid, double iso,
+                         int64_t* d_cells, uint8_t* d_cases, int64_t cap, int64_t* h_count,
+                         void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  SFK_TRY(validate_grid_args(c, roi, d_grid, 0, nullptr, nullptr));
+  if (!h_count || cap < 0 || (cap > 0 && (!d_cells || !d_cases)) || !std::isfinite(iso)) {
+    set_err(c, "invalid iso-cell arguments");
+    return SFK_E_INVAL;
+  }
+  const int64_t nc = (int64_t)(roi->res[0] - 1) * (roi->res[1] - 1) * (roi->res[2] - 1);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TmpBuf flags(c), pos(c), cases(c), tmp(c), total(c);
+  sfk_status st;
+  if ((st = flags.get(sizeof(int32_t) * (size_t)nc, "cell flags")) != SFK_OK ||
+      (st = pos.get(sizeof(int64_t) * (size_t)nc, "cell offsets")) != SFK_OK ||
+      (st = cases.get((size_t)nc, "cell cases")) != SFK_OK ||
+      (st = tmp.get(sfk::scan_tmp_bytes(nc), "scan scratch")) != SFK_OK ||
+      (st = total.get(sizeof(int64_t), "cell count")) != SFK_OK)
+    return st;
+  int64_t cnt = 0;
+  if (sfk::launch_iso_flags(d_grid, roi->res, iso, nc, flags.as<int32_t>(), cases.as<uint8_t>(),
+                            s) != hipSuccess ||
+      sfk::scan_exclusive_i32_i64(flags.as<int32_t>(), pos.as<int64_t>(), nc, total.as<int64_t>(),
+                                  tmp.b.p, tmp.b.bytes, s) != hipSuccess ||
+      sfk::launch_compact_cells(flags.as<int32_t>(), pos.as<int64_t>(), cases.as<uint8_t>(), nc,
+                                d_cells, d_cases, cap, s) != hipSuccess ||
+      hipMemcpyAsync(&cnt, total.b.p, sizeof cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    set_err(c, "iso-cell kernels failed");
+    return SFK_E_DEVICE;
+  }
+  *h_count = cnt;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
 sfk_status sfk_debug_point_h2(sfk_ctx c, sfk_tree t, float* h_h2) {
   SFK_GUARD_BEGIN
   SFK_TRY(check_ctx(c));

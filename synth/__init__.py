@@ -20,4 +20,6 @@ from .clouds import (  # noqa: F401
     nested_zoom_rois,
     random_batch_rois,
     serving_trace,
+    random_grid,
+    probe_points,
 )

@@ -359,3 +359,27 @@ def clumpy_cloud_device(n: int, seed: int, device="cuda", n_clumps: int = 2000,
         cid = stop
     assert pos == n
     return out, ClumpInfo(centres, masses, s1, counts)
+
+
+def random_grid(res: Sequence[int], seed: int, scale: float = 3.0) -> np.ndarray:
+    """A seeded float32 node field of res[0] * res[1] * res[2] values (x
+    fastest), uniform in [0, scale): an input for the grid consumers."""
+    g = _rng(seed)
+    return (g.random(int(np.prod(res))) * scale).astype(np.float32)
+
+
+def probe_points(roi: Roi, n: int, seed: int, margin: float = 0.1) -> np.ndarray:
+    """n float32 points uniform in the ROI box grown by `margin` of its side
+    on every face, plus the box corners and one row of node x-positions on
+    the box's middle y and z planes (points on faces, near nodes, outside)."""
+    g = _rng(seed)
+    lo = np.asarray(roi.lo, np.float64)
+    hi = np.asarray(roi.hi, np.float64)
+    side = hi - lo
+    p = g.uniform(lo - margin * side, hi + margin * side, size=(n, 3))
+    corners = np.array([[lo[0] if b & 1 == 0 else hi[0], lo[1] if b & 2 == 0 else hi[1],
+                         lo[2] if b & 4 == 0 else hi[2]] for b in range(8)])
+    row = np.column_stack([np.linspace(lo[0], hi[0], roi.res[0]),
+                           np.full(roi.res[0], 0.5 * (lo[1] + hi[1])),
+                           np.full(roi.res[0], 0.5 * (lo[2] + hi[2]))])
+    return np.vstack([p, corners, row]).astype(np.float32)
