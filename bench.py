@@ -139,6 +139,41 @@ def cpu_baseline(pts, roi, h2, n_nodes, seed=7):
                       % (len(nodes), len(pts), dt, useful)}
 
 
+def consumers(ctx, torch, roi, grid, xyz, reps=5):
+    """The grid consumers on the step's grid and cloud: density at every
+    particle, the selection at the median density and the Marching Cubes
+    cells at that threshold (device time per call from events on the
+    current stream). Algorithmic bytes of sampling: 12 B read + 4 B written
+    per point plus one read of the grid."""
+    n = xyz.shape[0]
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            r = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    dens = torch.empty(n, dtype=torch.float32, device="cuda")
+    t_s, _ = timed(lambda: ctx.sample_density(roi, grid, xyz, out=dens))
+    iso = float(torch.median(dens[dens > 0]).item())
+    t_sel, sel = timed(lambda: ctx.select_points(roi, grid, iso, xyz))
+    t_iso, cells = timed(lambda: ctx.iso_cells(roi, grid, iso))
+    sample_bytes = 16.0 * n + 4.0 * roi.n_nodes
+    return {"workload": "%d particles on the %s grid of the step; threshold = median particle "
+                        "density" % (n, "x".join(str(r) for r in roi.res)),
+            "sample_ms": t_s, "sample_points_per_s": n / (t_s * 1e-3),
+            "sample_gb_per_s": sample_bytes / (t_s * 1e-3) / 1e9,
+            "sample_frac_of_hbm": sample_bytes / (t_s * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "select_ms": t_sel, "selected": int(sel.numel()),
+            "iso_cells_ms": t_iso, "active_cells": int(cells[0].numel())}
+
+
 def batch_vs_single(ctx, tree, torch, n_rois, label):
     """Many uneven ROIs in one persistent launch vs one launch per ROI, on
     the resident tree (same kernels, same results)."""
@@ -288,6 +323,8 @@ def main():
         "useful_evals": useful, "tested_pairs": tested,
         "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
     }
+    if args.workload == "per_point_10m":
+        result["consumers"] = consumers(ctx, torch, roi, out, xyz)
     if not args.no_cpu_baseline:
         h2 = ctx.debug_point_h2(tree) if knn_k else None
         log("timing the oracle on a node sample")
