@@ -180,10 +180,13 @@ typedef struct {
   int32_t persistent_waves_per_cu; /* 0 = automatic */
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
                             lists do not fit walk the tree inside the evaluation
-                            kernel instead (same results, bitwise) */
+                            kernel instead (same results, bitwise): one work item
+                            per chunk while partial slots remain, else one per tile */
   int32_t disable_graphs; /* 1: batches on context streams use direct launches
                              instead of each slot's captured hipGraph */
-  int32_t reserved;
+  int32_t partial_capacity; /* partial-sum slots (chunks of split tiles) per batch,
+                               0 = automatic (list_capacity / chunk_leaves when
+                               list_capacity is set) */
 } sfk_eval_opts;
 sfk_status sfk_set_eval_opts(sfk_ctx ctx, const sfk_eval_opts* opts);
 /* Time every tile shape on the sample ROIs and record the fastest per

@@ -186,9 +186,9 @@ class Context:
 
     def set_eval_opts(self, tile_shape: int = 0, chunk_leaves: int = 0,
                       persistent_waves_per_cu: int = 0, list_capacity: int = 0,
-                      disable_graphs: bool = False):
+                      disable_graphs: bool = False, partial_capacity: int = 0):
         o = L.EvalOpts(int(tile_shape), int(chunk_leaves), int(persistent_waves_per_cu),
-                       int(list_capacity), 1 if disable_graphs else 0, 0)
+                       int(list_capacity), 1 if disable_graphs else 0, int(partial_capacity))
         self._check(self._lib.sfk_set_eval_opts(self._h, C.byref(o)))
 
     def autotune(self, tree: "Tree", rois: Sequence, outs: Sequence):

@@ -37,7 +37,7 @@ class RoiC(C.Structure):
 class EvalOpts(C.Structure):
     _fields_ = [("tile_shape", C.c_int32), ("chunk_leaves", C.c_int32),
                 ("persistent_waves_per_cu", C.c_int32), ("list_capacity", C.c_int32),
-                ("disable_graphs", C.c_int32), ("reserved", C.c_int32)]
+                ("disable_graphs", C.c_int32), ("partial_capacity", C.c_int32)]
 
 
 class Request(C.Structure):

@@ -147,6 +147,16 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
   }
 }
 
+// How a tile is evaluated. Lists: its leaf list and partial slots fit the
+// buffers, one work item per chunk of its list. Walk per chunk: only the
+// partial slots fit; one work item per chunk, each walking the hierarchy and
+// evaluating the leaves of its chunk. Walk whole tile: one work item walks
+// and evaluates every chunk in order. All three visit the same leaves in the
+// same order with the same chunk boundaries, so the sums are bitwise equal.
+static constexpr int kModeWalkTile = 0;
+static constexpr int kModeLists = 1;
+static constexpr int kModeWalkChunk = 2;
+
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_fill(
     TreeView tv, const BatchHdr* __restrict__ hdr, const RoiDev* __restrict__ rois,
@@ -159,9 +169,9 @@ __global__ __launch_bounds__(256) void k_tile_fill(
   const int64_t n_tiles = hdr->n_tiles;
   const int n_rois = hdr->n_rois;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
-    const int64_t c0 = chunk_off[t], c1 = chunk_off[t + 1];
+    const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], hdr->item_cap);
     for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
-    if (!tile_fit[t] || tile_cnt[t] == 0) continue;
+    if (tile_fit[t] != kModeLists || tile_cnt[t] == 0) continue;
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
     int32_t* out = leaves + leaf_off[t];
@@ -178,12 +188,13 @@ __global__ __launch_bounds__(256) void k_tile_fill(
 
 // ---------------------------------------------------------------------------
 // work plan: per tile, leaf_off (prefix of candidate leaves), partial_off
-// (prefix of partial-sum slots of split tiles), tile_fit (its lists fit the
-// buffers) and chunk_off (prefix of work items). Single block, 1024 threads,
+// (prefix of partial-sum slots of split tiles), tile_fit (how the tile is
+// evaluated, below) and chunk_off (prefix of work items). Single block,
 // looping over the tiles with running carries.
 // ---------------------------------------------------------------------------
 
 static constexpr int kPlanNT = 512;
+
 
 __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ tile_cnt,
                                                   BatchHdr* __restrict__ hdr, int chunk_leaves,
@@ -207,15 +218,19 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ ti
     carry_l += tot;
     const int64_t po = carry_p + block_excl_scan<kPlanNT>(pneed, &tot, lds);
     carry_p += tot;
-    const bool fit = v && (lo + cnt <= leaf_cap) && (pneed == 0 || po + pneed <= partial_cap);
-    const int64_t nit = v ? (fit ? nch : 1) : 0;
+    const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
+    const int mode = !v ? kModeWalkTile
+                        : (lo + cnt <= leaf_cap && fit_p) ? kModeLists
+                                                           : (fit_p && nch > 1) ? kModeWalkChunk
+                                                                                : kModeWalkTile;
+    const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
     const int64_t co = carry_c + block_excl_scan<kPlanNT>(nit, &tot, lds);
     carry_c += tot;
     if (v) {
       leaf_off[t] = lo;
       partial_off[t] = po;
       chunk_off[t] = co;
-      tile_fit[t] = fit ? 1 : 0;
+      tile_fit[t] = mode;
     }
   }
   // every thread has read the header above before thread 0 writes it
@@ -326,7 +341,7 @@ __global__ __launch_bounds__(256) void k_eval(
   __shared__ float4 lds_qprm[4][PP == PP_ANISO ? QCAP : 1];
   __shared__ int32_t lds_ids[4][kIdBlock];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t n_items = hdr->n_items;
+  const int64_t n_items = min(hdr->n_items, hdr->item_cap);  // equal by construction
   const int n_rois = hdr->n_rois;
   // XCD-aware work stealing. Workgroups are dispatched round-robin over the
   // 8 XCDs, each with its own L2; the item list is cut into 8 contiguous
@@ -566,8 +581,45 @@ __global__ __launch_bounds__(256) void k_eval(
     auto lane_node = [&](int m) { return T >= 64 ? lane * NPL + m : (lane & (T - 1)); };
     const bool lane_writes = T >= 64 || lane < T;
 
-    if (tile_fit[t]) {
-      const int c = (int)(item - chunk_off[t]);
+    const int mode = tile_fit[t];
+    const int c = (int)(item - chunk_off[t]);
+    // the chunk's per-node sums: the grid values when the tile has one
+    // chunk, else a partial slot, the last chunk to finish combining all
+    // of them in chunk order (in double)
+    auto finish_chunk = [&]() {
+      if (nch == 1) {
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), (double)acc[m] * R.scale);
+        }
+      } else {
+        const int64_t pbase = (partial_off[t] + c) * T;
+        if (lane_writes) {
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) partials[pbase + lane_node(m)] = (double)acc[m];
+        }
+        __threadfence();
+        int prev = 0;
+        if (lane == 0) prev = atomicAdd(&tile_done[t], 1);
+        prev = __shfl(prev, 0, 64);
+        if (prev == nch - 1) {
+          __threadfence();
+          if (lane_writes) {
+            const int64_t p0 = partial_off[t] * T;
+#pragma unroll
+            for (int m = 0; m < NPL; ++m) {
+              const int node = lane_node(m);
+              double s = 0.0;
+              for (int cc = 0; cc < nch; ++cc)
+                s += __hip_atomic_load(&partials[p0 + (int64_t)cc * T + node], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+              node_out(node, s * R.scale);
+            }
+          }
+        }
+      }
+    };
+    if (mode == kModeLists) {
       const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
       const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
       // Software pipeline over NB particle buffers: a buffer is refilled
@@ -605,40 +657,36 @@ __global__ __launch_bounds__(256) void k_eval(
         wave_sync();
       }
       end_chunk();
-      if (nch == 1) {
-        if (lane_writes) {
-#pragma unroll
-          for (int m = 0; m < NPL; ++m) node_out(lane_node(m), (double)acc[m] * R.scale);
-        }
-      } else {
-        const int64_t pbase = (partial_off[t] + c) * T;
-        if (lane_writes) {
-#pragma unroll
-          for (int m = 0; m < NPL; ++m) partials[pbase + lane_node(m)] = (double)acc[m];
-        }
-        __threadfence();
-        int prev = 0;
-        if (lane == 0) prev = atomicAdd(&tile_done[t], 1);
-        prev = __shfl(prev, 0, 64);
-        if (prev == nch - 1) {
-          __threadfence();
-          if (lane_writes) {
-            const int64_t p0 = partial_off[t] * T;
-#pragma unroll
-            for (int m = 0; m < NPL; ++m) {
-              const int node = lane_node(m);
-              double s = 0.0;
-              for (int cc = 0; cc < nch; ++cc)
-                s += __hip_atomic_load(&partials[p0 + (int64_t)cc * T + node], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-              node_out(node, s * R.scale);
+      finish_chunk();
+    } else if (mode == kModeWalkChunk) {
+      // the list did not fit: walk the hierarchy and evaluate the leaves of
+      // this chunk (walk order = list order), stopping after its last one
+      const int start = c * chunk_leaves, stop = min(start + chunk_leaves, cnt);
+      int done = 0;
+      traverse_until(
+          tv, lds_stack[wave],
+          [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+          [&](int child, bool pass, uint64_t mask) {
+            (void)pass;
+            const int np = popc64(mask);
+            if (done + np <= start) {
+              done += np;
+              return true;
             }
-          }
-        }
-      }
+            uint64_t mm = mask;
+            while (mm && done < stop) {
+              const int b = __ffsll((unsigned long long)mm) - 1;
+              mm &= mm - 1;
+              if (done >= start) eval_leaf(__shfl(child, b, 64));
+              ++done;
+            }
+            return done < stop;
+          });
+      end_chunk();
+      finish_chunk();
     } else {
-      // lists did not fit the buffers: walk the hierarchy here, with the same
-      // leaf order and the same chunk boundaries as the split path
+      // neither list nor partial slots fit: one work item walks the
+      // hierarchy with the same leaf order and the same chunk boundaries
       double dacc[NPL];
 #pragma unroll
       for (int m = 0; m < NPL; ++m) dacc[m] = 0.0;

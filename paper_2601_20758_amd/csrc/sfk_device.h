@@ -174,4 +174,46 @@ __device__ __forceinline__ void traverse(const TreeView& tv, int32_t* stack, Tes
   }
 }
 
+// traverse() whose leaf callback returns false to end the walk early.
+template <class TestF, class LeafF>
+__device__ __forceinline__ void traverse_until(const TreeView& tv, int32_t* stack, TestF test,
+                                               LeafF leaves) {
+  if (tv.n_levels <= 0) return;
+  const int lane = lane_id();
+  int sp = 0;
+  int level = tv.n_levels - 1;
+  int first = 0;
+  int cnt = tv.level_cnt[level];
+  while (true) {
+    const int child = first + lane;
+    const bool valid = lane < cnt;
+    bool pass = false;
+    if (valid) {
+      const int g = tv.level_off[level] + child;
+      pass = test(tv.nodes[g], g);
+    }
+    const uint64_t mask = ballot(pass);
+    if (level == 0) {
+      if (!leaves(child, pass, mask)) return;
+    } else if (mask) {
+      const int np = popc64(mask);
+      if (pass) {
+        const int r = popc64(mask & lanemask_lt());
+        stack[sp + np - 1 - r] = ((level - 1) << 27) | child;
+      }
+      sp += np;
+      wave_sync();
+    }
+    if (sp == 0) break;
+    --sp;
+    const int e = stack[sp];
+    const int pl = e >> 27;
+    const int pn = e & ((1 << 27) - 1);
+    level = pl;
+    first = pn * SFK_FANOUT;
+    cnt = min(SFK_FANOUT, tv.level_cnt[pl] - first);
+    wave_sync();
+  }
+}
+
 }  // namespace sfk

@@ -583,12 +583,16 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   const int64_t nc = std::max<int64_t>(1024, (int64_t)std::ceil((double)n_coords * headroom));
   int64_t leaf_cap = std::max<int64_t>({ws.want_leaf_cap, (int64_t)1 << 20, 64 * tiles,
                                         4 * tree_leaves});
+  // partial slots are small (T doubles per chunk): room for twice the
+  // chunks the leaf lists hold, so a batch whose lists overflow still splits
+  // its heavy tiles over work items (walking per chunk)
   int64_t partial_cap = std::max<int64_t>({ws.want_partial_cap, (int64_t)1 << 14, tiles / 4,
-                                           leaf_cap / CH});
+                                           2 * leaf_cap / CH});
   if (c->opts.list_capacity > 0) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
   }
+  if (c->opts.partial_capacity > 0) partial_cap = c->opts.partial_capacity;
   SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)tiles, "tile counts"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)tiles, "tile flags"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)tiles, "tile counters"));
@@ -613,7 +617,10 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                       : (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T));
   k.rois_cap = (int64_t)((ws.hdr_rois.bytes - sizeof(BatchHdr)) / sizeof(RoiDev));
   k.coords_cap = (int64_t)(ws.coords.bytes / sizeof(double));
-  k.item_cap = k.tiles_cap + k.leaf_cap / CH + 1;
+  // work items: one per tile plus one per partial slot (a split tile has one
+  // item per chunk and one partial slot per chunk, whether it evaluates its
+  // list or walks per chunk), so the plan can never exceed this
+  k.item_cap = k.tiles_cap + k.partial_cap + 1;
   SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)k.item_cap, "work items"));
   *caps = k;
   return SFK_OK;
@@ -1651,6 +1658,7 @@ sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
   if (opts->tile_shape < 0 || opts->tile_shape > kNumShapes || opts->chunk_leaves < 0 ||
       opts->chunk_leaves > (1 << 20) || opts->persistent_waves_per_cu < 0 ||
       opts->persistent_waves_per_cu > 64 || opts->list_capacity < 0 ||
+      opts->partial_capacity < 0 ||
       opts->disable_graphs < 0 || opts->disable_graphs > 1) {
     set_err(c, "evaluation options out of range");
     return SFK_E_INVAL;

@@ -149,13 +149,20 @@ def test_split_chunks_and_walk_fallback_bitwise(ctx, torch):
     outs = {}
     for label, kw in [("default", {}), ("chunks4", {"chunk_leaves": 4}),
                       ("walk4", {"chunk_leaves": 4, "list_capacity": 1}),
-                      ("walk64", {"list_capacity": 1})]:
+                      ("walk64", {"list_capacity": 1}),
+                      ("chunkwalk4", {"chunk_leaves": 4, "list_capacity": 1,
+                                      "partial_capacity": 1 << 20}),
+                      ("mixed4", {"chunk_leaves": 4, "list_capacity": 3000,
+                                  "partial_capacity": 1500})]:
         ctx.set_eval_opts(**kw)
         outs[label] = ctx.eval_roi(tree, roi).cpu().numpy()
         check_density(outs[label], ref, label)
     ctx.set_eval_opts()
-    # the tree walk reproduces the stored-list results bit for bit
+    # the tree walks (per tile, per chunk, and a mix of lists and both
+    # walks) reproduce the stored-list results bit for bit
     assert np.array_equal(outs["chunks4"], outs["walk4"])
+    assert np.array_equal(outs["chunks4"], outs["chunkwalk4"])
+    assert np.array_equal(outs["chunks4"], outs["mixed4"])
     assert np.array_equal(outs["default"], outs["walk64"])
 
 
