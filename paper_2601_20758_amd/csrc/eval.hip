@@ -197,7 +197,8 @@ static constexpr int kPlanNT = 512;
 
 
 __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ tile_cnt,
-                                                  BatchHdr* __restrict__ hdr, int chunk_leaves,
+                                                  BatchHdr* __restrict__ hdr,
+                                                  int32_t* __restrict__ claims, int chunk_leaves,
                                                   int64_t* __restrict__ leaf_off,
                                                   int64_t* __restrict__ partial_off,
                                                   int64_t* __restrict__ chunk_off,
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ ti
   }
   // every thread has read the header above before thread 0 writes it
   __syncthreads();
+  if (threadIdx.x < kClaimSlices) claims[threadIdx.x * kClaimStride] = 0;
   if (threadIdx.x == 0) {
     leaf_off[n_tiles] = carry_l;
     partial_off[n_tiles] = carry_p;
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void k_eval(
     const int64_t* __restrict__ partial_off, const int32_t* __restrict__ tile_cnt,
     const int32_t* __restrict__ tile_fit, const int32_t* __restrict__ leaves,
     const int32_t* __restrict__ item_tile, double* __restrict__ partials,
-    int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr) {
+    int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr, int32_t* __restrict__ claims) {
   constexpr int T = TX * TY * TZ;
   constexpr int NPL = T >= 64 ? T / 64 : 1;
   // Per-lane node accumulators are float32: a lane adds one term per drained
@@ -344,25 +346,38 @@ __global__ __launch_bounds__(256) void k_eval(
   const int64_t n_items = min(hdr->n_items, hdr->item_cap);  // equal by construction
   const int n_rois = hdr->n_rois;
   // XCD-aware work stealing. Workgroups are dispatched round-robin over the
-  // 8 XCDs, each with its own L2; the item list is cut into 8 contiguous
-  // (hence spatially coherent) slices and a workgroup takes items from its
-  // own XCD's slice first, then from the others in turn. Which workgroup
-  // takes an item never changes what the item computes.
+  // 8 XCDs, each with its own L2. The item list is cut into kClaimSlices
+  // contiguous (hence spatially coherent) slices, 8 per XCD, each with its own
+  // counter on its own cache line: device-scope atomics serialize per line,
+  // so spreading them is what lets many light items be claimed quickly. A
+  // wave claims single items from its home slice (one of its XCD's eight);
+  // when that slice is exhausted, the 64 lanes read all 64 counters at once
+  // (plain loads) and the wave moves to the first slice with items left in
+  // its order: its XCD's other slices, then the other XCDs'. Which wave takes
+  // an item never changes what the item computes.
   const int xcd = blockIdx.x & 7;
-  int scan = 0;  // slices this wave has found empty, in its order
+  const int sub = (int)(((blockIdx.x >> 3) * 4 + wave) & 7);
+  auto slice_at = [&](int pos) { return ((xcd + (pos >> 3)) & 7) * 8 + ((sub + pos) & 7); };
+  auto slice_begin = [&](int sl) { return n_items * sl / kClaimSlices; };
+  int cur = slice_at(0);
   while (true) {
     int64_t item = -1;
-    while (scan < 8) {
-      const int x = (xcd + scan) & 7;
-      const int64_t b = n_items * x / 8, e = n_items * (x + 1) / 8;
+    while (true) {
+      const int64_t b = slice_begin(cur), e = slice_begin(cur + 1);
       int idx = 0;
-      if (b < e && lane == 0) idx = atomicAdd(&hdr->next_xcd[x], 1);
+      if (b < e && lane == 0) idx = atomicAdd(&claims[cur * kClaimStride], 1);
       idx = __shfl(idx, 0, 64);
-      if (b < e && b + idx < e) {
+      if (b + idx < e) {
         item = b + idx;
         break;
       }
-      ++scan;
+      const int my = slice_at(lane);
+      const int64_t mb = slice_begin(my), me = slice_begin(my + 1);
+      const int seen =
+          __hip_atomic_load(&claims[my * kClaimStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t open = __ballot(mb + seen < me);
+      if (open == 0) break;
+      cur = slice_at(__ffsll((unsigned long long)open) - 1);
     }
     if (item < 0) break;
     const int t = item_tile[item];
@@ -839,11 +854,11 @@ hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* roi
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int chunk_leaves,
+hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, int chunk_leaves,
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
                        int32_t* tile_fit, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, hdr, chunk_leaves, leaf_off,
-                     partial_off, chunk_off, tile_fit);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, hdr, claims, chunk_leaves,
+                     leaf_off, partial_off, chunk_off, tile_fit);
   return hipGetLastError();
 }
 
@@ -862,13 +877,15 @@ hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois
 }
 
 template <int X, int Y, int Z>
-static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu, hipStream_t s,
+static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu, int max_blocks,
+                                    hipStream_t s,
                                     TreeView tv, const RoiDev* rois, const double* coords,
                                     int chunk_leaves, const int64_t* leaf_off,
                                     const int64_t* chunk_off, const int64_t* partial_off,
                                     const int32_t* tile_cnt, const int32_t* tile_fit,
                                     const int32_t* leaves, const int32_t* item_tile,
-                                    double* partials, int32_t* tile_done, BatchHdr* hdr) {
+                                    double* partials, int32_t* tile_done, BatchHdr* hdr,
+                                    int32_t* claims) {
 #define SFK_E(KK, PP, C)                                                                       \
   do {                                                                                         \
     static int occ_ = 0;                                                                       \
@@ -879,10 +896,10 @@ static hipError_t launch_eval_shape(int kk, int pp, bool cnt, int grid, int n_cu
         b_ = 1;                                                                                \
       occ_ = b_;                                                                               \
     }                                                                                          \
-    const int g_ = grid > 0 ? grid : n_cu * occ_;                                              \
+    const int g_ = grid > 0 ? grid : std::max(1, std::min(n_cu * occ_, max_blocks));          \
     hipLaunchKernelGGL((k_eval<X, Y, Z, KK, PP, C>), dim3(g_), dim3(256), 0, s, tv, rois,      \
                        coords, chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt,       \
-                       tile_fit, leaves, item_tile, partials, tile_done, hdr);                 \
+                       tile_fit, leaves, item_tile, partials, tile_done, hdr, claims);         \
   } while (0)
   if (cnt) {
     if (pp == PP_UNIFORM) SFK_E(KK_EPAN, PP_UNIFORM, true);
@@ -906,13 +923,15 @@ hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
                        int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,
                        const int64_t* partial_off, const int32_t* tile_cnt,
                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                       double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                       int n_cu, hipStream_t s) {
+                       double* partials, int32_t* tile_done, BatchHdr* hdr, int32_t* claims,
+                       int grid_blocks, int n_cu, int max_blocks, hipStream_t s) {
   (void)hdr_c;
 #define SFK_L(X, Y, Z)                                                                        \
-  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, s, tv, rois, coords,     \
+  return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, max_blocks, s, tv, rois, \
+                                    coords,                                                   \
                                     chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, \
-                                    tile_fit, leaves, item_tile, partials, tile_done, hdr)
+                                    tile_fit, leaves, item_tile, partials, tile_done, hdr,    \
+                                    claims)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipErrorInvalidValue;

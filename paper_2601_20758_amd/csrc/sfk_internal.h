@@ -73,8 +73,14 @@ struct alignas(16) BatchHdr {
   int64_t total_partials;  // plan: partial-sum slots the split tiles need
   int32_t overflow;      // plan: 1 if some tile's lists did not fit (it walks the tree)
   int32_t pad_;
-  int32_t next_xcd[8];   // host stages 0; per-XCD work counters of the evaluation
 };
+
+// Work-claim counters of the evaluation: kClaimSlices counters, one per
+// 128-byte line (kClaimStride int32 apart) so claims on different slices do
+// not contend; zeroed by the plan kernel of each batch.
+constexpr int kClaimSlices = 64;
+constexpr int kClaimStride = 32;
+constexpr size_t kClaimBytes = sizeof(int32_t) * kClaimSlices * kClaimStride;
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
 struct TileShape { int tx, ty, tz; };
@@ -138,7 +144,7 @@ hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_r
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                              const double* coords, TileShape ts, int grid_blocks,
                              int32_t* tile_cnt, int32_t* tile_done, hipStream_t s);
-hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int chunk_leaves,
+hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, int chunk_leaves,
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
                        int32_t* tile_fit, hipStream_t s);
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
@@ -151,8 +157,8 @@ hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
                        int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,
                        const int64_t* partial_off, const int32_t* tile_cnt,
                        const int32_t* tile_fit, const int32_t* leaves, const int32_t* item_tile,
-                       double* partials, int32_t* tile_done, BatchHdr* hdr, int grid_blocks,
-                       int n_cu, hipStream_t s);
+                       double* partials, int32_t* tile_done, BatchHdr* hdr, int32_t* claims,
+                       int grid_blocks, int n_cu, int max_blocks, hipStream_t s);
 hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiDev* roi,
                                     const double* coords, TileShape ts, int64_t node_begin,
                                     int64_t node_end, int64_t* cnt, const int64_t* off,

@@ -53,7 +53,7 @@ struct DevBuf {
 struct Workspace {
   // hdr_rois = [BatchHdr][RoiDev x capacity]: staged by one host-to-device copy
   DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
-      item_tile, partials;
+      item_tile, partials, claims;
   uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
@@ -604,6 +604,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   SFK_TRY(ws_reserve(c, ws, ws.hdr_rois, sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)nr,
                      "ROI descriptors"));
   SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)nc, "node coordinates"));
+  SFK_TRY(ws_reserve(c, ws, ws.claims, kClaimBytes, "work-claim counters"));
   Caps k;
   k.tiles_cap = std::min<int64_t>({(int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_fit.bytes / sizeof(int32_t)),
@@ -660,7 +661,8 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   }
   {
     ProfScope p(c, PK_PLAN, s);
-    SFK_HIP(c, sfk::launch_plan(tile_cnt, hdr, CH, leaf_off, partial_off, chunk_off, tile_fit, s));
+    SFK_HIP(c, sfk::launch_plan(tile_cnt, hdr, (int32_t*)ws.claims.p, CH, leaf_off, partial_off,
+                                chunk_off, tile_fit, s));
   }
   {
     ProfScope p(c, PK_TILE_FILL, s);
@@ -668,15 +670,19 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
                                       leaf_off, chunk_off, (int32_t*)ws.leaves.p,
                                       (int32_t*)ws.item_tile.p, s));
   }
+  // 0: resident blocks per CU from the occupancy query, capped at one wave
+  // per tile (the tile kernels' grid) but at least one block per CU, so a
+  // small batch does not launch (and drain) a full-device persistent grid
   const int grid = c->opts.persistent_waves_per_cu > 0
                        ? c->n_cu * std::max(1, c->opts.persistent_waves_per_cu / 4)
-                       : 0;  // 0: resident blocks per CU from the occupancy query
+                       : 0;
   {
     ProfScope p(c, PK_EVAL, s, hdr);
     SFK_HIP(c, sfk::launch_eval(tv, hdr, rois, coords, ts, kk, pp, cnt, CH, leaf_off, chunk_off,
                                  partial_off, tile_cnt, tile_fit, (int32_t*)ws.leaves.p,
                                  (int32_t*)ws.item_tile.p, (double*)ws.partials.p, tile_done,
-                                 hdr, grid, c->n_cu, s));
+                                 hdr, (int32_t*)ws.claims.p, grid, c->n_cu,
+                                 std::max(c->n_cu, tile_grid), s));
   }
   return SFK_OK;
 }
@@ -837,7 +843,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
       st = SFK_E_DEVICE;
     if (st == SFK_OK)
       st = launch_kernels(c, view_of(t), ts, kk, pp, false, sl.ws, (int)k.rois_cap,
-                          c->n_cu * 4, s);
+                          sfk::tile_grid_blocks(k.tiles_cap), s);
     if (st == SFK_OK && hipMemcpyAsync(sl.st.hdr_host, sl.ws.hdr_rois.p, sizeof(BatchHdr),
                                        hipMemcpyDeviceToHost, s) != hipSuccess)
       st = SFK_E_DEVICE;
@@ -1371,7 +1377,7 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
 static void release_ws(sfk_ctx c, Workspace& ws) {
   DevBuf* bufs[] = {&ws.hdr_rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
                     &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
-                    &ws.partials};
+                    &ws.partials, &ws.claims};
   for (DevBuf* b : bufs) ws_release(c, *b);
 }
 
