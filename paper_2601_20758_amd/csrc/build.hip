@@ -439,11 +439,12 @@ constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
 constexpr int kKnnList = 256;                       // leaves held for ordering
 constexpr int kKnnBands = 5;                        // distance bands of the visiting order
 
-// Boxes of the sub-blocks of 8 consecutive particles: 6 floats (lo, hi) per
-// sub-block. A sub-block without real particles gets an empty box, whose
-// distance to any point is infinite.
+// Boxes of the sub-blocks of 8 consecutive particles, 8 floats per box
+// (lo.xyz, 0, hi.xyz, 0) so one 256-byte line holds a leaf's eight boxes. A
+// sub-block without real particles gets an empty box, whose distance to any
+// point is infinite.
 __global__ __launch_bounds__(256) void k_sub_boxes(const float4* __restrict__ pts, int64_t n,
-                                                   int64_t n_slots, float* __restrict__ out) {
+                                                   int64_t n_slots, float4* __restrict__ out) {
   for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < n_slots;
        slot += (int64_t)gridDim.x * blockDim.x) {
     const float4 p = pts[slot];
@@ -459,9 +460,9 @@ __global__ __launch_bounds__(256) void k_sub_boxes(const float4* __restrict__ pt
       }
     }
     if ((slot & (kKnnSub - 1)) == 0) {
-      float* o = out + (slot / kKnnSub) * 6;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) o[c] = v[c];
+      float4* o = out + (slot / kKnnSub) * 2;
+      o[0] = make_float4(v[0], v[1], v[2], 0.0f);
+      o[1] = make_float4(v[3], v[4], v[5], 0.0f);
     }
   }
 }
@@ -473,7 +474,33 @@ template <int KM>
 __device__ __forceinline__ void knn_insert(float (&a)[KM], float x) {
 #pragma unroll
   for (int i = KM - 1; i >= 1; --i) a[i] = __builtin_amdgcn_fmed3f(a[i - 1], x, a[i]);
-  a[0] = fminf(a[0], x);
+  // min(a[0], x) as one operation: the bound -FLT_MAX lies below every
+  // distance, and a -inf entry (only ever read as a left neighbour of
+  // another -inf entry or of this one) may become -FLT_MAX harmlessly
+  a[0] = __builtin_amdgcn_fmed3f(a[0], x, -3.402823466e38f);
+}
+
+// Largest unsigned value over the wavefront (uniform result): DPP row
+// shifts and row broadcasts, with 0 (the identity of max) for lanes without
+// a source, leave the total in lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned b) {
+#define SFK_DPP_MAX(CTRL, ROWS) \
+  b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false))
+  SFK_DPP_MAX(0x111, 0xf);  // row_shr:1
+  SFK_DPP_MAX(0x112, 0xf);  // row_shr:2
+  SFK_DPP_MAX(0x114, 0xf);  // row_shr:4
+  SFK_DPP_MAX(0x118, 0xf);  // row_shr:8: lane 15 of each row holds the row's max
+  SFK_DPP_MAX(0x142, 0xa);  // row_bcast:15
+  SFK_DPP_MAX(0x143, 0xc);  // row_bcast:31: lane 63 holds the total
+#undef SFK_DPP_MAX
+  return (unsigned)__builtin_amdgcn_readlane((int)b, 63);
+}
+
+// Largest of the non-negative floats v (+inf allowed) over the wavefront: on
+// such values the order of the bit patterns as unsigned integers is the
+// order of the floats.
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  return __uint_as_float(wave_max_u32(__float_as_uint(v)));
 }
 
 // float32 squared distance from a point to a box, rounded like canon_d2
@@ -493,8 +520,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
   __shared__ int32_t lds_lid[4][kKnnList];
   __shared__ float lds_lkey[4][kKnnList];
   __shared__ int32_t lds_ord[4][kKnnList];
+  __shared__ float4 lds_sb[4][2 * kKnnSubPerLeaf];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   float4* lp = lds_pts[wave];
+  float4* lsb = lds_sb[wave];
   float* ld2 = lds_d2[wave];
   int32_t* stack = lds_stack[wave];
   int32_t* lid = lds_lid[wave];
@@ -512,28 +541,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
 #pragma unroll
     for (int i = 0; i < KM; ++i) a[i] = i < KM - k ? -__builtin_huge_valf() : __builtin_huge_valf();
     float thr = __builtin_huge_valf();
+    const NodeBox qb = leaf_box[leaf];
 
-    // One candidate leaf, its particle for this lane in pc and its
-    // sub-block boxes spread over lanes 0..47 of sbv. Per needed sub-block
-    // each lane marks the particles below its threshold; the insertion then
-    // runs in rounds, a round inserting every lane's next marked particle.
+    // One candidate leaf, its particle for this lane in pc and its eight
+    // sub-block boxes over the lanes of sbv (8 floats per box). Lanes 0..7
+    // first test one box each against the query leaf's box and the
+    // wavefront's largest threshold (a box that fails cannot hold a particle
+    // closer to any lane than its threshold); the boxes that pass are tested
+    // per lane. Per needed sub-block each lane marks the particles below its
+    // threshold; the insertion then runs in rounds, a round inserting every
+    // lane's next marked particle, until no lane has one left.
     auto process = [&](int cl, const float4 pc, const float sbv) {
+      lp[lane] = pc;
+      reinterpret_cast<float*>(lsb)[lane] = sbv;
+      wave_sync();
+      const float tnow = wave_max_nonneg(real ? thr : 0.0f);
+      bool cpass = false;
+      if (lane < kKnnSubPerLeaf) {
+        const float4 blo = lsb[2 * lane], bhi = lsb[2 * lane + 1];
+        const NodeBox b = {{blo.x, blo.y, blo.z}, 0, {bhi.x, bhi.y, bhi.z}, 0};
+        cpass = box_gap_d2(b, qb.lo[0], qb.lo[1], qb.lo[2], qb.hi[0], qb.hi[1], qb.hi[2]) < tnow;
+      }
+      const uint32_t cand = (uint32_t)ballot(cpass);
       uint32_t need = 0;
 #pragma unroll
       for (int j = 0; j < kKnnSubPerLeaf; ++j) {
-        const float bx[6] = {readlane_f(sbv, 6 * j + 0),
-                             readlane_f(sbv, 6 * j + 1),
-                             readlane_f(sbv, 6 * j + 2),
-                             readlane_f(sbv, 6 * j + 3),
-                             readlane_f(sbv, 6 * j + 4),
-                             readlane_f(sbv, 6 * j + 5)};
-        if (ballot(real && pt_box_d2(bx, q.x, q.y, q.z) < thr)) need |= 1u << j;
+        if (cand & (1u << j)) {
+          const float4 blo = lsb[2 * j], bhi = lsb[2 * j + 1];
+          const float bx[6] = {blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z};
+          if (ballot(real && pt_box_d2(bx, q.x, q.y, q.z) < thr)) need |= 1u << j;
+        }
       }
-      if (!need) return;
-      const int64_t cbase = (int64_t)cl * SFK_LEAF;
       const int self = cl == leaf ? lane : -1;
-      lp[lane] = pc;
-      wave_sync();
       while (need) {
         const int j = __ffs(need) - 1;
         need &= need - 1;
@@ -549,22 +588,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
         const int rel = self - j * kKnnSub;
         if ((unsigned)rel < (unsigned)kKnnSub) mark &= ~(1u << rel);
         if (!real) mark = 0;
-        int rounds = __popc(mark);
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off, 64));
+        const int rounds = (int)wave_max_u32((unsigned)__popc(mark));
         for (int r = 0; r < rounds; ++r) {
-          float x = __builtin_huge_valf();
-          if (mark) {
-            const int u = __ffs(mark) - 1;
-            mark &= mark - 1;
-            x = ld2[u * 64 + lane];
-          }
+          // a lane without a mark reads any slot of its column and inserts +inf
+          const int u = (__ffs(mark) - 1) & (kKnnSub - 1);
+          const float x = mark ? ld2[u * 64 + lane] : __builtin_huge_valf();
+          mark &= mark - 1;
           // lanes with x >= thr only touch entries past the k-th: harmless
           knn_insert<KM>(a, x);
           thr = a[KM - 1];
         }
       }
-      (void)cbase;
       wave_sync();
     };
     // process() over the leaves ord[0..count), with the next leaf's
@@ -573,7 +607,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
       if (count <= 0) return;
       int cl = __builtin_amdgcn_readfirstlane(ord[0]);
       float4 pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
-      float sn = lane < 6 * kKnnSubPerLeaf ? sub_box[(int64_t)cl * (6 * kKnnSubPerLeaf) + lane] : 0.f;
+      float sn = sub_box[(int64_t)cl * (8 * kKnnSubPerLeaf) + lane];
       for (int i = 0; i < count; ++i) {
         const int cur = cl;
         const float4 pc = pn;
@@ -581,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
         if (i + 1 < count) {
           cl = __builtin_amdgcn_readfirstlane(ord[i + 1]);
           pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
-          sn = lane < 6 * kKnnSubPerLeaf ? sub_box[(int64_t)cl * (6 * kKnnSubPerLeaf) + lane] : 0.f;
+          sn = sub_box[(int64_t)cl * (8 * kKnnSubPerLeaf) + lane];
         }
         process(cur, pc, sc);
       }
@@ -591,7 +625,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
     // list may not take another group of 64 leaves and resumes where it
     // stopped (its stack stays in LDS). It keeps the leaves, other than the
     // first pass's, whose box is within tau of this leaf's box.
-    const NodeBox qb = leaf_box[leaf];
     float tau = 0.0f;
     int ln = 0, sp = 0, level = 0, first = 0, cnt = 0;
     bool walk_done = false;
@@ -713,7 +746,7 @@ hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipS
   const int64_t n_slots = (int64_t)tv.n_leaves * SFK_LEAF;
   const int64_t nbs = std::min<int64_t>((n_slots + 255) / 256, 65536);
   hipLaunchKernelGGL(k_sub_boxes, dim3((unsigned)nbs), dim3(256), 0, s, tv.pts, tv.n, n_slots,
-                     sub_box);
+                     reinterpret_cast<float4*>(sub_box));
   const int nb = std::min<int>((tv.n_leaves + 3) / 4, 65536);
   if (k <= 8)
     hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
@@ -727,7 +760,7 @@ hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipS
 }
 
 size_t knn_sub_box_bytes(int32_t n_leaves) {
-  return sizeof(float) * 6 * (size_t)n_leaves * kKnnSubPerLeaf;
+  return sizeof(float) * 8 * (size_t)n_leaves * kKnnSubPerLeaf;
 }
 
 // Per-particle isotropic inverse bandwidth into pts[].w:
