@@ -22,14 +22,15 @@
  *   - A grid has res[0]*res[1]*res[2] float32 values, x fastest:
  *     idx = x + y*res[0] + z*res[0]*res[1] (Algorithms 2 and 4 index the
  *     density buffer this way).
- *   - Grid node i on axis k sits at (float)(lo + (i*(hi-lo))/(res-1)),
- *     evaluated in double and rounded once (vertex-centred nodes on the
- *     closed box; node spacing s_k = (hi_k - lo_k)/(res_k - 1)).
- *   - A particle j is in the support of node n when, in float32 on the
- *     float32 inputs, u2 < c2 with d_k = x_nk - p_jk, u_k = d_k * ih_k,
- *     u2 = (u_x*u_x + u_y*u_y) + u_z*u_z (no fused multiply-add), ih_k the
- *     float32 inverse bandwidth, c2 = 1 (Epanechnikov, Eq. 4 is zero at
- *     |x| >= 1) or 9 (Gaussian truncated at 3 sigma).
+ *   - Grid node i on axis k sits at lo + (i*(hi-lo))/(res-1), evaluated in
+ *     double (vertex-centred nodes on the closed box; node spacing
+ *     s_k = (hi_k - lo_k)/(res_k - 1)).
+ *   - A particle j is in the support of node n when, in double on the
+ *     float32 particle and inverse-bandwidth values, u2 < c2 with
+ *     u_k = (x_nk - p_jk) * ih_k, u2 = (u_x*u_x + u_y*u_y) + u_z*u_z, every
+ *     operation rounded (no fused multiply-add), ih_k the float32 inverse
+ *     bandwidth, c2 = 1 (Epanechnikov, Eq. 4 is zero at |x| >= 1) or 9
+ *     (Gaussian truncated at 3 sigma).
  *   - Functions return sfk_status and never throw or abort. Arguments are
  *     validated before any device work; on failure nothing is launched and
  *     sfk_last_error() describes the cause.
@@ -297,6 +298,76 @@ sfk_status sfk_select_points(sfk_ctx ctx, const sfk_roi* roi, const float* d_gri
 sfk_status sfk_iso_cells(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid, double iso,
                          int64_t* d_cells, uint8_t* d_cases, int64_t cap, int64_t* h_count,
                          void* hip_stream);
+
+/* ------------------------------------------------- view cache (reuse) */
+/* Recomputation policy of an interactive view (Section 6.3, limitations and
+ * future work: recompute only when the scale changes by more than a
+ * threshold, and evaluate the viewport plus a margin so that panning inside
+ * it needs no new evaluation; Section 6.2: recompute once the user has moved
+ * to a new scale).
+ *
+ * A view evaluates density on lattices of nodes o + g*s per axis (o = the
+ * tree's bounding-box minimum, g an integer, s the spacing of the lattice),
+ * cut into blocks of block^3 nodes. Block (bx, by, bz) of a lattice is the
+ * ROI with lo_k = o_k + (b_k*block)*s, hi_k = o_k + (b_k*block + block - 1)*s
+ * (double), res = block, CLOUD set, evaluated with the kernels of
+ * sfk_eval_roi and one tile shape per lattice, so a cached block is bitwise
+ * equal to a fresh sfk_eval_roi of that ROI. Blocks live in a device cache
+ * of max_blocks blocks, evicted least recently used. A frame (a view box):
+ *   1. wanted spacing s_w = (longest side of the box) / (res - 1); the cached
+ *      lattice with the spacing closest to s_w in ratio is used if that ratio
+ *      is within scale_threshold, else a lattice with s = s_w is created;
+ *   2. every block holding a node within margin * (longest side) of the box
+ *      is made present (only missing blocks are evaluated, in one batch);
+ *   3. the lattice nodes g_lo..g_hi covering the box (g_lo = the largest
+ *      node index at or below lo, g_hi = the smallest at or above hi) are
+ *      copied into the caller's grid (x fastest).
+ * The tree must outlive the view; frames of one view run in call order. */
+typedef struct sfk_view_s* sfk_view;
+
+typedef struct {
+  int32_t kernel;          /* sfk_kernel */
+  int32_t bw;              /* SFK_BW_FIXED, SFK_BW_PER_POINT, or SFK_BW_ROI_SCALED:
+                              h_k = h0 * (res - 1) * s, fixed per lattice */
+  int32_t norm;            /* sfk_norm */
+  int32_t res;             /* wanted nodes across the box's longest side, >= 2 */
+  float h[3];              /* FIXED: h per axis; ROI_SCALED: h0 in h[0] */
+  int32_t block;           /* nodes per block edge: 8, 16, 32 or 64 (0 = 32) */
+  double scale_threshold;  /* >= 1 (1: a new lattice whenever the spacing changes) */
+  double margin;           /* >= 0, fraction of the box's longest side */
+  int64_t max_blocks;      /* cache capacity in blocks, >= 1 */
+} sfk_view_opts;
+
+typedef struct {
+  double lo[3], hi[3];       /* coordinates of the grid's first and last node */
+  int64_t g0[3];             /* lattice index of the grid's first node */
+  int32_t res[3];            /* nodes per axis of the grid */
+  int32_t new_lattice;       /* 1 if the frame creates (created) a lattice */
+  double spacing;            /* spacing s of the lattice */
+  int64_t lattice_id;        /* lattices are numbered from 0 in creation order */
+  int64_t blocks_needed;     /* blocks covering the box plus margin */
+  int64_t blocks_evaluated;  /* of those, evaluated by this frame */
+} sfk_view_frame_info;
+
+/* Create a view of tree. The cache (max_blocks * block^3 floats) comes from
+ * the context's allocator and counts against its budget (SFK_E_BUDGET).
+ * SFK_E_INVAL: NULL pointers, kernel/norm out of range, bw MBE or out of
+ * range, PER_POINT without a per-point bandwidth in the tree, non-positive
+ * or non-finite h, res < 2, block not in {0, 8, 16, 32, 64},
+ * scale_threshold < 1, margin < 0, max_blocks < 1, or a tree with no
+ * particles. */
+sfk_status sfk_view_create(sfk_ctx ctx, sfk_tree tree, const sfk_view_opts* opts,
+                           sfk_view* out);
+/* Waits for the view's last frame, then frees its cache. */
+sfk_status sfk_view_destroy(sfk_view view);
+/* One frame for the box [lo, hi] (hi > lo, finite). With d_out NULL only
+ * *info is filled (what the frame would do; no device work, no state
+ * change). Otherwise d_out (device, cap floats) receives the grid,
+ * stream-ordered on hip_stream (asynchronous). SFK_E_INVAL if the grid needs
+ * more than cap floats or more than 2^31 nodes; SFK_E_BUDGET if the box plus
+ * margin needs more than max_blocks blocks. */
+sfk_status sfk_view_frame(sfk_view view, const double lo[3], const double hi[3], float* d_out,
+                          int64_t cap, sfk_view_frame_info* info, void* hip_stream);
 
 /* ----------------------------------------------------------- test exports */
 

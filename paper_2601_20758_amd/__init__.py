@@ -73,6 +73,7 @@ class Context:
         self._lib = L.lib()
         self._h = C.c_void_p()
         self._trees = weakref.WeakSet()
+        self._views = weakref.WeakSet()
         self.device = device
         self._alloc = None
         ap = None
@@ -113,6 +114,8 @@ class Context:
         return self._lib.sfk_last_error(self._h).decode()
 
     def close(self):
+        for v in list(self._views):
+            v.close()
         for t in list(self._trees):
             t.close()
         if self._h:
@@ -255,6 +258,23 @@ class Context:
                                                     idx.shape[0], C.byref(need)))
         return offs, idx[:need.value]
 
+    # ---- view cache (recomputation policy, reuse across frames) ----
+
+    def view(self, tree: "Tree", kernel: str = "epanechnikov", bw: str = "fixed", h=(0.01,) * 3,
+             res: int = 64, block: int = 32, scale_threshold: float = 1.0, margin: float = 0.0,
+             max_blocks: int = 512, norm: str = "paper") -> "View":
+        """sfk_view_create: a device-resident block cache over lattices of nodes."""
+        hh = tuple(float(x) for x in h) if h is not None else (1.0, 1.0, 1.0)
+        if len(hh) == 1:
+            hh = hh * 3
+        o = L.ViewOpts(L.KERNEL[kernel], L.BW[bw], L.NORM[norm], int(res), (C.c_float * 3)(*hh),
+                       int(block), float(scale_threshold), float(margin), int(max_blocks))
+        out = C.c_void_p()
+        self._check(self._lib.sfk_view_create(self._h, tree._h, C.byref(o), C.byref(out)))
+        v = View(self, tree, out, int(block) or 32)
+        self._views.add(v)
+        return v
+
     # ---- consumers of a density grid (all on the device) ----
 
     @staticmethod
@@ -354,6 +374,57 @@ class Context:
                 "aveden": ave.value, "ell_j": ellj[:k], "final": out}
 
 
+class View:
+    """An interactive view's block cache (sfk_view). frame(lo, hi) returns the
+    grid of lattice nodes covering the box and what the frame did."""
+
+    def __init__(self, ctx: Context, tree: "Tree", h: C.c_void_p, block: int):
+        self._ctx = ctx
+        self._tree = tree  # the tree must outlive the view
+        self._h = h
+        self.block = block
+
+    @staticmethod
+    def _info(inf) -> dict:
+        return {"lo": tuple(inf.lo), "hi": tuple(inf.hi), "g0": tuple(inf.g0),
+                "res": tuple(inf.res), "new_lattice": bool(inf.new_lattice),
+                "spacing": inf.spacing, "lattice_id": inf.lattice_id,
+                "blocks_needed": inf.blocks_needed, "blocks_evaluated": inf.blocks_evaluated}
+
+    def plan(self, lo, hi) -> dict:
+        """What frame(lo, hi) would do (no device work, no state change)."""
+        a, b = (C.c_double * 3)(*lo), (C.c_double * 3)(*hi)
+        inf = L.ViewFrameInfo()
+        self._ctx._check(L.lib().sfk_view_frame(self._h, a, b, None, 0, C.byref(inf), None))
+        return self._info(inf)
+
+    def frame(self, lo, hi, out=None, stream=None):
+        """sfk_view_frame: (grid tensor (x fastest, nodes of info['res']), info)."""
+        import torch
+        need = self.plan(lo, hi)
+        n = need["res"][0] * need["res"][1] * need["res"][2]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device="cuda:%d" % self._ctx.device)
+        if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float32 device tensor")
+        a, b = (C.c_double * 3)(*lo), (C.c_double * 3)(*hi)
+        inf = L.ViewFrameInfo()
+        self._ctx._check(L.lib().sfk_view_frame(self._h, a, b, out.data_ptr(), out.numel(),
+                                                C.byref(inf), _stream_ptr(stream)))
+        return out[:n], self._info(inf)
+
+    def close(self):
+        if self._h:
+            L.lib().sfk_view_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Tree:
     """A device-resident spatial index (sfk_tree)."""
 
@@ -370,6 +441,9 @@ class Tree:
 
     def close(self):
         if self._h:
+            for v in list(self._ctx._views):  # views of this tree go first
+                if v._tree is self:
+                    v.close()
             L.lib().sfk_tree_destroy(self._h)
             self._h = C.c_void_p()
 

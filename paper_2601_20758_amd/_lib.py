@@ -68,6 +68,19 @@ class Profile(C.Structure):
                 ("last_total_leaves", C.c_int64), ("last_items", C.c_int64)]
 
 
+class ViewOpts(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("bw", C.c_int32), ("norm", C.c_int32), ("res", C.c_int32),
+                ("h", C.c_float * 3), ("block", C.c_int32), ("scale_threshold", C.c_double),
+                ("margin", C.c_double), ("max_blocks", C.c_int64)]
+
+
+class ViewFrameInfo(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("g0", C.c_int64 * 3),
+                ("res", C.c_int32 * 3), ("new_lattice", C.c_int32), ("spacing", C.c_double),
+                ("lattice_id", C.c_int64), ("blocks_needed", C.c_int64),
+                ("blocks_evaluated", C.c_int64)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "sfk_version": (C.c_char_p, []),
@@ -105,6 +118,11 @@ EXPORTS = {
                                     C.POINTER(C.c_int64), C.c_void_p]),
     "sfk_iso_cells": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_double, C.c_void_p,
                                 C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
+    "sfk_view_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ViewOpts),
+                                  C.POINTER(C.c_void_p)]),
+    "sfk_view_destroy": (C.c_int, [C.c_void_p]),
+    "sfk_view_frame": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.c_void_p, C.c_int64, C.POINTER(ViewFrameInfo), C.c_void_p]),
     "sfk_debug_point_h2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

@@ -129,6 +129,50 @@ __global__ __launch_bounds__(256) void k_compact_cells(const int32_t* __restrict
     }
 }
 
+// Lattice nodes g0 + (i, j, k) of a view, copied out of cached blocks of B^3
+// nodes (x fastest inside a block). table[] holds the cache slot of each
+// block of the range b0 .. b0 + nb - 1 (x fastest); every node of the grid
+// falls in that range by construction, and a node that did not would be
+// written as 0 rather than read out of bounds.
+struct GatherGeom {
+  int64_t g0[3], b0[3];
+  int32_t res[3], nb[3];
+  int32_t B;
+  int32_t pad_;
+  int64_t n_slots;
+};
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+__global__ __launch_bounds__(256) void k_view_gather(const float* __restrict__ cache,
+                                                     const int32_t* __restrict__ table,
+                                                     GatherGeom G, float* __restrict__ out) {
+  const int64_t n = (int64_t)G.res[0] * G.res[1] * G.res[2];
+  const int64_t B = G.B;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q % G.res[0], j = (q / G.res[0]) % G.res[1], k = q / ((int64_t)G.res[0] * G.res[1]);
+    const int64_t g[3] = {G.g0[0] + i, G.g0[1] + j, G.g0[2] + k};
+    int64_t b[3], l[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t bb = floor_div(g[a], B);
+      l[a] = g[a] - bb * B;
+      b[a] = bb - G.b0[a];
+      ok = ok && b[a] >= 0 && b[a] < G.nb[a];
+    }
+    float v = 0.0f;
+    if (ok) {
+      const int32_t slot = table[b[0] + (int64_t)G.nb[0] * (b[1] + (int64_t)G.nb[1] * b[2])];
+      if (slot >= 0 && slot < G.n_slots) v = cache[(int64_t)slot * B * B * B + l[0] + B * (l[1] + B * l[2])];
+    }
+    out[q] = v;
+  }
+}
+
 static GridGeom geom_of(const double lo[3], const double hi[3], const int32_t res[3]) {
   GridGeom g{};
   for (int k = 0; k < 3; ++k) {
@@ -183,6 +227,24 @@ hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_compact_cells, dim3(grid_of(n)), dim3(256), 0, s, flags, pos, case_all, n,
                      cells, cases, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_view_gather(const float* cache, int64_t n_slots, int block, const int32_t* table,
+                              const int64_t b0[3], const int32_t nb[3], const int64_t g0[3],
+                              const int32_t res[3], float* out, hipStream_t s) {
+  GatherGeom G{};
+  for (int k = 0; k < 3; ++k) {
+    G.g0[k] = g0[k];
+    G.b0[k] = b0[k];
+    G.res[k] = res[k];
+    G.nb[k] = nb[k];
+  }
+  G.B = block;
+  G.n_slots = n_slots;
+  const int64_t n = (int64_t)res[0] * res[1] * res[2];
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_view_gather, dim3(grid_of(n)), dim3(256), 0, s, cache, table, G, out);
   return hipGetLastError();
 }
 

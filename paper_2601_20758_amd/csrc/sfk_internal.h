@@ -89,6 +89,9 @@ struct TileShape { int tx, ty, tz; };
 namespace sfk {
 
 // consumers.hip
+hipError_t launch_view_gather(const float* cache, int64_t n_slots, int block, const int32_t* table,
+                              const int64_t b0[3], const int32_t nb[3], const int64_t g0[3],
+                              const int32_t res[3], float* out, hipStream_t s);
 hipError_t launch_sample(const float* grid, const double lo[3], const double hi[3],
                          const int32_t res[3], const float* xyz, int64_t n, float* out,
                          hipStream_t s);

@@ -16,9 +16,11 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "sfk_internal.h"
@@ -732,10 +734,11 @@ struct GroupKey {
 TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r);
 
 void group_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois, bool count_mode,
-                std::vector<std::vector<GroupRoi>>* groups, std::vector<GroupKey>* keys) {
+                std::vector<std::vector<GroupRoi>>* groups, std::vector<GroupKey>* keys,
+                const TileShape* force_ts = nullptr) {
   for (const sfk_roi* r : rois) {
     GroupRoi g = resolve_cloud_roi(t, r, count_mode);
-    const GroupKey key{count_mode ? 0 : g.kk, g.pp, choose_shape(c, t, r)};
+    const GroupKey key{count_mode ? 0 : g.kk, g.pp, force_ts ? *force_ts : choose_shape(c, t, r)};
     size_t gi = 0;
     while (gi < keys->size() && !((*keys)[gi] == key)) ++gi;
     if (gi == keys->size()) {
@@ -751,11 +754,12 @@ void group_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois, 
 // the groups run one after another on the same workspace, and growing a
 // buffer frees the old one.
 sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
-                              bool count_mode, Workspace& ws, Staging& st, hipStream_t s) {
+                              bool count_mode, Workspace& ws, Staging& st, hipStream_t s,
+                              const TileShape* force_ts = nullptr) {
   if (rois.empty()) return SFK_OK;
   std::vector<std::vector<GroupRoi>> groups;
   std::vector<GroupKey> keys;
-  group_rois(c, t, rois, count_mode, &groups, &keys);
+  group_rois(c, t, rois, count_mode, &groups, &keys, force_ts);
   size_t bytes = 0;
   for (auto& g : groups) bytes += sizeof(BatchHdr) + sizeof(RoiDev) * g.size();
   SFK_TRY(staging_reserve(c, st, bytes));
@@ -1674,20 +1678,36 @@ sfk_status sfk_set_eval_opts(sfk_ctx c, const sfk_eval_opts* opts) {
 }
 
 // Stream-ordered single ROI on the caller's stream.
-static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStream_t s,
-                              bool count_mode) {
+// CLOUD-set ROIs in one batch on the caller's stream (the direct path's
+// workspace and staging ring), optionally all with one tile shape.
+static sfk_status eval_direct_cloud(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& v,
+                                    hipStream_t s, bool count_mode, const TileShape* force_ts) {
   if (c->direct_last_valid && c->direct_last_stream != s)
     SFK_HIP(c, hipStreamWaitEvent(s, c->direct_last, 0));
   const int oldest = c->direct_next;
   Staging& st = c->direct_st[c->direct_next];
   c->direct_next = (c->direct_next + 1) % kStagingRing;
-  if (roi->set == SFK_SET_IN_ROI) {
-    SFK_TRY(eval_subcloud(c, t, roi, count_mode, shape_of(1), c->direct_ws, st, s, nullptr));
-  } else {
-    absorb_ready(c->direct_ws, c->direct_st, kStagingRing, oldest);
+  absorb_ready(c->direct_ws, c->direct_st, kStagingRing, oldest);
+  SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, c->direct_ws, st, s, force_ts));
+  SFK_HIP(c, hipEventRecord(c->direct_last, s));
+  c->direct_last_valid = true;
+  c->direct_last_stream = s;
+  c->direct_ws.last_use = c->direct_last;
+  c->direct_ws.last_use_valid = true;
+  return SFK_OK;
+}
+
+static sfk_status eval_direct(sfk_ctx c, sfk_tree t, const sfk_roi* roi, hipStream_t s,
+                              bool count_mode) {
+  if (roi->set != SFK_SET_IN_ROI) {
     std::vector<const sfk_roi*> v{roi};
-    SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, c->direct_ws, st, s));
+    return eval_direct_cloud(c, t, v, s, count_mode, nullptr);
   }
+  if (c->direct_last_valid && c->direct_last_stream != s)
+    SFK_HIP(c, hipStreamWaitEvent(s, c->direct_last, 0));
+  Staging& st = c->direct_st[c->direct_next];
+  c->direct_next = (c->direct_next + 1) % kStagingRing;
+  SFK_TRY(eval_subcloud(c, t, roi, count_mode, shape_of(1), c->direct_ws, st, s, nullptr));
   SFK_HIP(c, hipEventRecord(c->direct_last, s));
   c->direct_last_valid = true;
   c->direct_last_stream = s;
@@ -2393,6 +2413,448 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
     summ->mean_in_flight = wall > 0 ? in_flight_area / wall : 0.0;
     summ->budget_waits = budget_waits;
   }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// View cache: lattices of nodes o + g*s cut into blocks of B^3 nodes, each
+// block an ordinary ROI evaluated by the batch path with one tile shape per
+// lattice, kept in a device-resident LRU cache across frames.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct ViewLattice {
+  int64_t id;
+  double s;        // spacing
+  float h[3];      // FIXED / ROI_SCALED bandwidth of the lattice
+  TileShape ts;    // tile shape every block of the lattice is evaluated with
+};
+
+struct BlockKey {
+  int64_t lat, b[3];
+  bool operator==(const BlockKey& o) const {
+    return lat == o.lat && b[0] == o.b[0] && b[1] == o.b[1] && b[2] == o.b[2];
+  }
+};
+struct BlockKeyHash {
+  size_t operator()(const BlockKey& k) const {
+    uint64_t h = (uint64_t)k.lat * 0x9E3779B97F4A7C15ull;
+    for (int a = 0; a < 3; ++a) h = (h ^ (uint64_t)k.b[a]) * 0xBF58476D1CE4E5B9ull + 0x94D049BB133111EBull;
+    return (size_t)(h ^ (h >> 31));
+  }
+};
+struct BlockEntry {
+  int32_t slot;
+  int64_t stamp;  // frame that last needed the block
+};
+
+int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// What a frame does, from the box and the view's state (pure host logic).
+struct FramePlan {
+  int lat = -1;            // index into the view's lattices, -1 = a new lattice
+  double s = 0.0;
+  int64_t g_lo[3], g_hi[3];  // lattice nodes of the returned grid
+  int64_t m_lo[3], m_hi[3];  // blocks covering the box plus margin
+  int64_t v_lo[3], v_hi[3];  // blocks covering the grid
+  int64_t nodes = 0, blocks = 0;
+};
+
+}  // namespace
+
+struct sfk_view_s {
+  sfk_ctx ctx = nullptr;
+  sfk_tree tree = nullptr;
+  sfk_view_opts o{};
+  int B = 32;
+  double origin[3] = {0, 0, 0};
+  int chunk_leaves = 0;  // chunking the cached blocks were evaluated with
+  DevBuf cache;
+  int64_t n_slots = 0;
+  std::vector<ViewLattice> lattices;
+  int64_t next_lattice = 0;
+  std::unordered_map<BlockKey, BlockEntry, BlockKeyHash> map;
+  std::vector<int32_t> free_slots;
+  int64_t stamp = 0;
+  DevBuf table;  // per-frame block -> slot table of the returned grid
+  hipEvent_t last = nullptr;
+  bool last_valid = false;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+sfk_status view_plan(sfk_view v, const double lo[3], const double hi[3], FramePlan* p) {
+  sfk_ctx c = v->ctx;
+  double side = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(lo[k]) && std::isfinite(hi[k]) && hi[k] > lo[k])) {
+      set_err(c, "view box axis %d needs finite lo < hi", k);
+      return SFK_E_INVAL;
+    }
+    side = std::max(side, hi[k] - lo[k]);
+  }
+  const double sw = side / (double)(v->o.res - 1);
+  // the cached lattice closest in ratio, if within the threshold
+  const double lim = std::log(v->o.scale_threshold);
+  double best = 0.0;
+  p->lat = -1;
+  for (size_t i = 0; i < v->lattices.size(); ++i) {
+    const double d = std::fabs(std::log(v->lattices[i].s / sw));
+    if (d <= lim && (p->lat < 0 || d < best)) {
+      p->lat = (int)i;
+      best = d;
+    }
+  }
+  const double s = p->lat >= 0 ? v->lattices[p->lat].s : sw;
+  p->s = s;
+  const int64_t B = v->B;
+  const double lim_g = 1099511627776.0;  // 2^40: keeps o + g*s exact enough and products in range
+  p->nodes = 1;
+  p->blocks = 1;
+  for (int k = 0; k < 3; ++k) {
+    const double o = v->origin[k];
+    const double ql = std::floor((lo[k] - o) / s), qh = std::ceil((hi[k] - o) / s);
+    const double mg = v->o.margin * side;
+    const double ml = std::floor((lo[k] - mg - o) / s), mh = std::ceil((hi[k] + mg - o) / s);
+    if (!(std::fabs(ql) < lim_g && std::fabs(qh) < lim_g && std::fabs(ml) < lim_g &&
+          std::fabs(mh) < lim_g)) {
+      set_err(c, "view box axis %d lies too far from the tree at this spacing", k);
+      return SFK_E_INVAL;
+    }
+    int64_t gl = (int64_t)ql, gh = (int64_t)qh;
+    // the largest node at or below lo, the smallest at or above hi
+    while (o + (double)(gl + 1) * s <= lo[k]) ++gl;
+    while (o + (double)gl * s > lo[k]) --gl;
+    while (o + (double)(gh - 1) * s >= hi[k]) --gh;
+    while (o + (double)gh * s < hi[k]) ++gh;
+    p->g_lo[k] = gl;
+    p->g_hi[k] = gh;
+    const int64_t mlo = std::min<int64_t>((int64_t)ml, gl), mhi = std::max<int64_t>((int64_t)mh, gh);
+    p->m_lo[k] = floor_div64(mlo, B);
+    p->m_hi[k] = floor_div64(mhi, B);
+    p->v_lo[k] = floor_div64(gl, B);
+    p->v_hi[k] = floor_div64(gh, B);
+    const int64_t nn = gh - gl + 1, nb = p->m_hi[k] - p->m_lo[k] + 1;
+    if (nn > ((int64_t)1 << 31) || nb > ((int64_t)1 << 21)) {
+      set_err(c, "view grid axis %d: %lld nodes / %lld blocks is too many", k, (long long)nn,
+              (long long)nb);
+      return SFK_E_INVAL;
+    }
+    p->nodes = std::min<int64_t>(p->nodes * nn, (int64_t)1 << 62);
+    p->blocks = std::min<int64_t>(p->blocks * nb, (int64_t)1 << 62);
+  }
+  if (p->nodes > ((int64_t)1 << 31)) {
+    set_err(c, "view grid of %lld nodes exceeds 2^31", (long long)p->nodes);
+    return SFK_E_INVAL;
+  }
+  return SFK_OK;
+}
+
+void view_fill_info(sfk_view v, const FramePlan& p, int64_t evaluated, sfk_view_frame_info* info) {
+  if (!info) return;
+  *info = sfk_view_frame_info{};
+  for (int k = 0; k < 3; ++k) {
+    info->g0[k] = p.g_lo[k];
+    info->res[k] = (int32_t)(p.g_hi[k] - p.g_lo[k] + 1);
+    info->lo[k] = v->origin[k] + (double)p.g_lo[k] * p.s;
+    info->hi[k] = v->origin[k] + (double)p.g_hi[k] * p.s;
+  }
+  info->new_lattice = p.lat < 0 ? 1 : 0;
+  info->spacing = p.s;
+  info->lattice_id = p.lat >= 0 ? v->lattices[p.lat].id : v->next_lattice;
+  info->blocks_needed = p.blocks;
+  info->blocks_evaluated = evaluated;
+}
+
+// The ROI of block b of lattice L.
+sfk_roi block_roi(sfk_view v, const ViewLattice& L, const int64_t b[3], float* out) {
+  sfk_roi r{};
+  for (int k = 0; k < 3; ++k) {
+    r.lo[k] = v->origin[k] + (double)(b[k] * v->B) * L.s;
+    r.hi[k] = v->origin[k] + (double)(b[k] * v->B + v->B - 1) * L.s;
+    r.res[k] = v->B;
+    r.h[k] = L.h[k];
+  }
+  r.kernel = v->o.kernel;
+  r.bw = v->o.bw == SFK_BW_PER_POINT ? SFK_BW_PER_POINT : SFK_BW_FIXED;
+  r.norm = v->o.norm;
+  r.set = SFK_SET_CLOUD;
+  r.d_out = out;
+  return r;
+}
+
+void view_flush(sfk_view v) {
+  v->map.clear();
+  v->lattices.clear();
+  v->free_slots.clear();
+  for (int64_t i = v->n_slots - 1; i >= 0; --i) v->free_slots.push_back((int32_t)i);
+}
+
+}  // namespace
+
+extern "C" {
+
+sfk_status sfk_view_create(sfk_ctx c, sfk_tree t, const sfk_view_opts* o, sfk_view* out) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !o || !out) {
+    set_err(c, "NULL view argument");
+    return SFK_E_INVAL;
+  }
+  *out = nullptr;
+  if (t->n <= 0) {
+    set_err(c, "view of an empty tree");
+    return SFK_E_INVAL;
+  }
+  if (o->kernel != SFK_KERNEL_EPANECHNIKOV && o->kernel != SFK_KERNEL_GAUSS_TRUNC3) {
+    set_err(c, "view: unknown kernel %d", o->kernel);
+    return SFK_E_INVAL;
+  }
+  if (o->norm != SFK_NORM_PAPER && o->norm != SFK_NORM_COUNT) {
+    set_err(c, "view: unknown norm %d", o->norm);
+    return SFK_E_INVAL;
+  }
+  if (o->bw == SFK_BW_FIXED) {
+    for (int k = 0; k < 3; ++k)
+      if (!(o->h[k] > 0.0f) || !std::isfinite(o->h[k])) {
+        set_err(c, "view: fixed bandwidth h[%d] must be finite and > 0", k);
+        return SFK_E_INVAL;
+      }
+  } else if (o->bw == SFK_BW_ROI_SCALED) {
+    if (!(o->h[0] > 0.0f) || !std::isfinite(o->h[0])) {
+      set_err(c, "view: bandwidth factor h[0] must be finite and > 0");
+      return SFK_E_INVAL;
+    }
+  } else if (o->bw == SFK_BW_PER_POINT) {
+    if (t->pp_mode != PP_ISO) {
+      set_err(c, "view: per-point bandwidth requested but the tree has none");
+      return SFK_E_INVAL;
+    }
+  } else {
+    set_err(c, "view: bandwidth mode %d is not supported (FIXED, ROI_SCALED, PER_POINT)", o->bw);
+    return SFK_E_INVAL;
+  }
+  const int B = o->block == 0 ? 32 : o->block;
+  if (o->res < 2 || !(B == 8 || B == 16 || B == 32 || B == 64) ||
+      !(o->scale_threshold >= 1.0) || !std::isfinite(o->scale_threshold) ||
+      !(o->margin >= 0.0) || !std::isfinite(o->margin) || o->max_blocks < 1 ||
+      o->max_blocks > ((int64_t)1 << 31) - 1) {
+    set_err(c, "view: need res >= 2, block in {8, 16, 32, 64}, finite scale_threshold >= 1, "
+               "finite margin >= 0, 1 <= max_blocks < 2^31");
+    return SFK_E_INVAL;
+  }
+  const size_t bytes = round_bytes(sizeof(float) * (size_t)B * B * B * (size_t)o->max_blocks);
+  if (c->budget && c->ws_bytes + bytes > c->budget) {
+    set_err(c, "view cache of %zu bytes exceeds the device-memory budget", bytes);
+    return SFK_E_BUDGET;
+  }
+  std::unique_ptr<sfk_view_s> v(new sfk_view_s());
+  v->ctx = c;
+  v->tree = t;
+  v->o = *o;
+  v->B = B;
+  for (int k = 0; k < 3; ++k) v->origin[k] = t->bbox[k];
+  v->cache.p = raw_alloc(c, bytes);
+  if (!v->cache.p) {
+    set_err(c, "device allocation of %zu bytes for the view cache failed", bytes);
+    return SFK_E_NOMEM;
+  }
+  v->cache.bytes = bytes;
+  c->ws_bytes += bytes;
+  v->n_slots = o->max_blocks;
+  if (hipEventCreateWithFlags(&v->last, hipEventDisableTiming) != hipSuccess) {
+    raw_free(c, v->cache.p, v->cache.bytes);
+    c->ws_bytes -= bytes;
+    set_err(c, "event creation failed");
+    return SFK_E_DEVICE;
+  }
+  view_flush(v.get());
+  *out = v.release();
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_view_destroy(sfk_view v) {
+  SFK_GUARD_BEGIN
+  if (!v) return SFK_OK;
+  sfk_ctx c = v->ctx;
+  if (v->last_valid) (void)hipEventSynchronize(v->last);
+  if (v->last) (void)hipEventDestroy(v->last);
+  raw_free(c, v->cache.p, v->cache.bytes);
+  c->ws_bytes -= v->cache.bytes;
+  raw_free(c, v->table.p, v->table.bytes);
+  delete v;
+  return SFK_OK;
+  SFK_GUARD_END(nullptr)
+}
+
+sfk_status sfk_view_frame(sfk_view v, const double lo[3], const double hi[3], float* d_out,
+                          int64_t cap, sfk_view_frame_info* info, void* hip_stream) {
+  if (!v) return SFK_E_INVAL;
+  sfk_ctx c = v->ctx;
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!lo || !hi) {
+    set_err(c, "view frame: NULL box");
+    return SFK_E_INVAL;
+  }
+  // blocks evaluated with another chunking would not be bitwise reproducible
+  if (chunk_leaves_of(c) != v->chunk_leaves) {
+    view_flush(v);
+    v->chunk_leaves = chunk_leaves_of(c);
+  }
+  FramePlan p;
+  SFK_TRY(view_plan(v, lo, hi, &p));
+  if (!d_out) {
+    int64_t missing = 0;
+    if (p.lat < 0) {
+      missing = p.blocks;
+    } else {
+      const int64_t id = v->lattices[p.lat].id;
+      for (int64_t bz = p.m_lo[2]; bz <= p.m_hi[2]; ++bz)
+        for (int64_t by = p.m_lo[1]; by <= p.m_hi[1]; ++by)
+          for (int64_t bx = p.m_lo[0]; bx <= p.m_hi[0]; ++bx)
+            if (!v->map.count(BlockKey{id, {bx, by, bz}})) ++missing;
+    }
+    view_fill_info(v, p, missing, info);
+    return SFK_OK;
+  }
+  if (cap < p.nodes) {
+    view_fill_info(v, p, 0, info);
+    set_err(c, "view frame: the grid needs %lld floats, cap is %lld", (long long)p.nodes,
+            (long long)cap);
+    return SFK_E_INVAL;
+  }
+  if (p.blocks > v->n_slots) {
+    view_fill_info(v, p, 0, info);
+    set_err(c, "view frame: box plus margin needs %lld blocks, the cache holds %lld",
+            (long long)p.blocks, (long long)v->n_slots);
+    return SFK_E_BUDGET;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (v->last_valid && v->last_stream != s) SFK_HIP(c, hipStreamWaitEvent(s, v->last, 0));
+  const bool created = p.lat < 0;
+  if (created) {
+    ViewLattice L{};
+    L.id = v->next_lattice++;
+    L.s = p.s;
+    for (int k = 0; k < 3; ++k)
+      L.h[k] = v->o.bw == SFK_BW_FIXED ? v->o.h[k]
+               : v->o.bw == SFK_BW_ROI_SCALED
+                   ? (float)((double)v->o.h[0] * (double)(v->o.res - 1) * p.s)
+                   : 1.0f;
+    const int64_t b0[3] = {p.m_lo[0], p.m_lo[1], p.m_lo[2]};
+    const sfk_roi r = block_roi(v, L, b0, (float*)v->cache.p);
+    L.ts = choose_shape(c, v->tree, &r);
+    v->lattices.push_back(L);
+    p.lat = (int)v->lattices.size() - 1;
+  }
+  const ViewLattice& L = v->lattices[p.lat];
+  const int64_t cur = ++v->stamp;
+  std::vector<BlockKey> missing;
+  for (int64_t bz = p.m_lo[2]; bz <= p.m_hi[2]; ++bz)
+    for (int64_t by = p.m_lo[1]; by <= p.m_hi[1]; ++by)
+      for (int64_t bx = p.m_lo[0]; bx <= p.m_hi[0]; ++bx) {
+        const BlockKey key{L.id, {bx, by, bz}};
+        auto it = v->map.find(key);
+        if (it != v->map.end())
+          it->second.stamp = cur;
+        else
+          missing.push_back(key);
+      }
+  // slots: free ones first, then the least recently used blocks this frame
+  // does not need (earlier frames' reads of them are ordered before this
+  // frame's writes on the stream)
+  if ((int64_t)missing.size() > (int64_t)v->free_slots.size()) {
+    std::vector<std::pair<int64_t, BlockKey>> old;
+    for (const auto& kv : v->map)
+      if (kv.second.stamp < cur) old.push_back({kv.second.stamp, kv.first});
+    std::sort(old.begin(), old.end(), [](const std::pair<int64_t, BlockKey>& a,
+                                         const std::pair<int64_t, BlockKey>& b) {
+      if (a.first != b.first) return a.first < b.first;
+      for (int k = 2; k >= 0; --k)
+        if (a.second.b[k] != b.second.b[k]) return a.second.b[k] < b.second.b[k];
+      return a.second.lat < b.second.lat;
+    });
+    size_t i = 0;
+    while ((int64_t)missing.size() > (int64_t)v->free_slots.size() && i < old.size()) {
+      auto it = v->map.find(old[i++].second);
+      v->free_slots.push_back(it->second.slot);
+      v->map.erase(it);
+    }
+    if ((int64_t)missing.size() > (int64_t)v->free_slots.size()) {
+      set_err(c, "view cache: no slot left");
+      return SFK_E_INTERNAL;
+    }
+  }
+  std::vector<sfk_roi> rois;
+  rois.reserve(missing.size());
+  const size_t per_block = (size_t)v->B * v->B * v->B;
+  for (const BlockKey& key : missing) {
+    const int32_t slot = v->free_slots.back();
+    v->free_slots.pop_back();
+    v->map[key] = BlockEntry{slot, cur};
+    rois.push_back(block_roi(v, L, key.b, (float*)v->cache.p + per_block * (size_t)slot));
+  }
+  if (!rois.empty()) {
+    std::vector<const sfk_roi*> ptrs;
+    for (const sfk_roi& r : rois) ptrs.push_back(&r);
+    const sfk_status st = eval_direct_cloud(c, v->tree, ptrs, s, false, &L.ts);
+    if (st != SFK_OK) {
+      // the blocks may be partly written: forget them
+      for (const BlockKey& key : missing) {
+        auto it = v->map.find(key);
+        if (it != v->map.end()) {
+          v->free_slots.push_back(it->second.slot);
+          v->map.erase(it);
+        }
+      }
+      return st;
+    }
+  }
+  // block -> slot table of the returned grid's blocks
+  int32_t nb[3];
+  int64_t nt = 1;
+  for (int k = 0; k < 3; ++k) {
+    nb[k] = (int32_t)(p.v_hi[k] - p.v_lo[k] + 1);
+    nt *= nb[k];
+  }
+  std::vector<int32_t> tab((size_t)nt);
+  for (int64_t bz = 0; bz < nb[2]; ++bz)
+    for (int64_t by = 0; by < nb[1]; ++by)
+      for (int64_t bx = 0; bx < nb[0]; ++bx) {
+        auto it = v->map.find(BlockKey{L.id, {p.v_lo[0] + bx, p.v_lo[1] + by, p.v_lo[2] + bz}});
+        tab[(size_t)(bx + nb[0] * (by + nb[1] * bz))] = it != v->map.end() ? it->second.slot : -1;
+      }
+  const size_t tb = sizeof(int32_t) * (size_t)nt;
+  if (v->table.bytes < tb) {
+    if (v->last_valid) SFK_HIP(c, hipEventSynchronize(v->last));
+    raw_free(c, v->table.p, v->table.bytes);
+    v->table = DevBuf();
+    const size_t nbytes = round_bytes(std::max<size_t>(tb, 4096));
+    v->table.p = raw_alloc(c, nbytes);
+    if (!v->table.p) {
+      set_err(c, "device allocation of %zu bytes for the view table failed", nbytes);
+      return SFK_E_NOMEM;
+    }
+    v->table.bytes = nbytes;
+  }
+  // pageable source: the copy has read it when the call returns
+  SFK_HIP(c, hipMemcpyAsync(v->table.p, tab.data(), tb, hipMemcpyHostToDevice, s));
+  int32_t res[3];
+  for (int k = 0; k < 3; ++k) res[k] = (int32_t)(p.g_hi[k] - p.g_lo[k] + 1);
+  SFK_HIP(c, sfk::launch_view_gather((const float*)v->cache.p, v->n_slots, v->B,
+                                     (const int32_t*)v->table.p, p.v_lo, nb, p.g_lo, res, d_out, s));
+  SFK_HIP(c, hipEventRecord(v->last, s));
+  v->last_valid = true;
+  v->last_stream = s;
+  view_fill_info(v, p, (int64_t)missing.size(), info);
+  if (info) info->new_lattice = created ? 1 : 0;
   return SFK_OK;
   SFK_GUARD_END(c)
 }
