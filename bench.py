@@ -101,6 +101,8 @@ def parse():
                    help="run a 1 GiB fill and a 1 GiB elementwise scale first "
                         "(references for the hardware byte counters)")
     p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--no-view", action="store_true",
+                   help="skip the view-cache comparison on the 100M cloud")
     return p.parse_args()
 
 
@@ -252,6 +254,65 @@ def serving(ctx, tree, torch, duration_s, label):
     return rec
 
 
+def view_cache(ctx, tree, torch, label, info, n_frames=180):
+    """Recomputation policy (view cache) vs recomputing every frame: a smooth
+    90 Hz camera path around a massive clump (pan plus a zoom breathing over
+    three octaves). Every frame: Epanechnikov, h = 0.01 x the side of the
+    wanted grid (64 nodes across the longest side). Recompute: one ROI per
+    frame at 64^3. View cache: blocks of 16^3 on lattices reused within a
+    spacing ratio of 1.5, a margin of 0.25 x side prefetched."""
+    import synth
+    boxes = synth.view_path(info, seed=7, n_frames=n_frames)
+    res, h0 = 64, 0.01
+    budget = 1000.0 / 90.0
+    log("view path: %d frames, recompute every frame" % n_frames)
+    out = torch.empty(res ** 3, device="cuda")
+    lat_re, nodes_re = [], 0
+    # warm-up frame (first-use growth of the workspace)
+    ctx.eval_roi(tree, synth.Roi(boxes[0][0], boxes[0][1], (res,) * 3, kernel="epanechnikov",
+                                 bw="roi_scaled", h=(h0,) * 3), out=out)
+    torch.cuda.synchronize()
+    for lo, hi in boxes:
+        r = synth.Roi(lo, hi, (res,) * 3, kernel="epanechnikov", bw="roi_scaled", h=(h0,) * 3)
+        t0 = time.perf_counter()
+        ctx.eval_roi(tree, r, out=out)
+        torch.cuda.synchronize()
+        lat_re.append((time.perf_counter() - t0) * 1e3)
+        nodes_re += r.n_nodes
+    log("view path: view cache")
+    view = ctx.view(tree, kernel="epanechnikov", bw="roi_scaled", h=(h0,), res=res, block=16,
+                    scale_threshold=1.5, margin=0.25, max_blocks=16384)
+    lat_v, blocks_ev, lattices, grid_nodes = [], 0, 0, 0
+    gout = torch.empty(1 << 22, device="cuda")
+    for lo, hi in boxes:
+        t0 = time.perf_counter()
+        g, inf = view.frame(lo, hi, out=gout)
+        torch.cuda.synchronize()
+        lat_v.append((time.perf_counter() - t0) * 1e3)
+        blocks_ev += inf["blocks_evaluated"]
+        lattices += 1 if inf["new_lattice"] else 0
+        grid_nodes += g.numel()
+    view.close()
+    lat_re, lat_v = np.array(lat_re), np.array(lat_v)
+    ev_nodes = blocks_ev * 16 ** 3
+    return {
+        "workload": "%d frames at 90 Hz around a massive clump of the resident %s tree: pan "
+                    "radius 0.15, side 0.2 x 2^(+-1.5) over 2 s; Epanechnikov, h = 0.01 x "
+                    "side at 64 nodes across" % (n_frames, label),
+        "recompute_every_frame": {
+            "p50_ms": float(np.percentile(lat_re, 50)), "p99_ms": float(np.percentile(lat_re, 99)),
+            "deadline_miss_rate": float(np.mean(lat_re > budget)),
+            "evaluated_nodes_per_frame": nodes_re / n_frames},
+        "view_cache": {
+            "p50_ms": float(np.percentile(lat_v, 50)), "p99_ms": float(np.percentile(lat_v, 99)),
+            "deadline_miss_rate": float(np.mean(lat_v > budget)),
+            "evaluated_nodes_per_frame": ev_nodes / n_frames,
+            "returned_nodes_per_frame": grid_nodes / n_frames,
+            "lattices_created": lattices, "block": 16, "scale_threshold": 1.5, "margin": 0.25},
+        "evaluated_nodes_ratio": (ev_nodes / n_frames) / (nodes_re / n_frames),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -332,30 +393,40 @@ def main():
     tree.close()
     del xyz, out
     torch.cuda.empty_cache()
-    if args.workload == "per_point_10m" and not args.no_batch:
-        result["batch_vs_single"] = large_section(
-            ctx, torch, args.batch_points, 3,
-            lambda t, lab: batch_vs_single(ctx, t, torch, args.n_batch, lab))
+    if args.workload == "per_point_10m" and not (args.no_batch and args.no_view):
+        def on_100m(t, lab, info):
+            rec = {}
+            if not args.no_batch:
+                rec["batch_vs_single"] = batch_vs_single(ctx, t, torch, args.n_batch, lab)
+            if not args.no_view:
+                rec["view_cache"] = view_cache(ctx, t, torch, lab, info)
+            return rec
+        rec = large_section(ctx, torch, args.batch_points, 3, on_100m)
+        if "error" in rec:
+            result["batch_vs_single"] = rec
+        else:
+            result.update(rec)
     if args.workload == "per_point_10m" and not args.no_serve:
         result["serving"] = large_section(
             ctx, torch, args.serve_points, 5,
-            lambda t, lab: serving(ctx, t, torch, args.serve_seconds, lab))
+            lambda t, lab, info: serving(ctx, t, torch, args.serve_seconds, lab))
     ctx.close()
     print(json.dumps(result), flush=True)
 
 
 def large_section(ctx, torch, n, seed, fn):
-    """Run fn(tree, label) on a clumpy cloud of n points drawn on the device
-    (tree built outside any timed region); errors are reported, not hidden."""
+    """Run fn(tree, label, clump_info) on a clumpy cloud of n points drawn on
+    the device (tree built outside any timed region); errors are reported,
+    not hidden."""
     import synth
     try:
         log("drawing %d clumpy points on the device" % n)
-        xyz, _ = synth.clumpy_cloud_device(n, seed)
+        xyz, info = synth.clumpy_cloud_device(n, seed)
         tree = ctx.build_tree(xyz)
         del xyz
         torch.cuda.empty_cache()
         label = "%s-point" % ("%dB" % (n // 10**9) if n % 10**9 == 0 else "%dM" % (n // 10**6))
-        rec = fn(tree, label)
+        rec = fn(tree, label, info)
         tree.close()
         torch.cuda.empty_cache()
         return rec

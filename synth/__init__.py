@@ -20,6 +20,7 @@ from .clouds import (  # noqa: F401
     nested_zoom_rois,
     random_batch_rois,
     serving_trace,
+    view_path,
     random_grid,
     probe_points,
 )

@@ -298,6 +298,28 @@ def serving_trace(seed: int, duration_s: float, n_streams: int = 8,
     return arr, st, rs
 
 
+def view_path(info: ClumpInfo, seed: int, n_frames: int = 180, fps: float = 90.0,
+              side0: float = 0.2, zoom_octaves: float = 1.5, zoom_period_s: float = 2.0,
+              pan_radius: float = 0.15):
+    """A smooth camera path of an interactive view (one box per frame at fps):
+    the centre circles a massive clump (three incommensurate sinusoids of
+    amplitude pan_radius), the side breathes between side0 * 2^-zoom_octaves
+    and side0 * 2^zoom_octaves over zoom_period_s. Returns [(lo, hi), ...]."""
+    g = _rng(seed)
+    top = np.argsort(-np.asarray(info.masses))[:10]
+    c0 = np.asarray(info.centres[int(top[int(g.integers(0, len(top)))])], dtype=np.float64)
+    ph = g.uniform(0.0, 2.0 * math.pi, size=4)
+    boxes = []
+    for i in range(n_frames):
+        t = i / fps
+        side = side0 * 2.0 ** (zoom_octaves * math.sin(2.0 * math.pi * t / zoom_period_s + ph[3]))
+        c = c0 + pan_radius * np.array([math.sin(2.0 * math.pi * t / 2.7 + ph[0]),
+                                        math.sin(2.0 * math.pi * t / 3.1 + ph[1]),
+                                        math.sin(2.0 * math.pi * t / 3.7 + ph[2])])
+        boxes.append((tuple(float(v) for v in c - side / 2), tuple(float(v) for v in c + side / 2)))
+    return boxes
+
+
 def clumpy_cloud_device(n: int, seed: int, device="cuda", n_clumps: int = 2000,
                         bg_frac: float = 0.2, m_lo: float = 1.0, m_hi: float = 1e3,
                         index: float = -1.8, chunk: int = 1 << 25):
