@@ -369,6 +369,58 @@ sfk_status sfk_view_destroy(sfk_view view);
 sfk_status sfk_view_frame(sfk_view view, const double lo[3], const double hi[3], float* d_out,
                           int64_t cap, sfk_view_frame_info* info, void* hip_stream);
 
+/* ------------------------------------------- adaptive resolution (f4) */
+/* Feature-aware refinement of a ROI grid (Section 6.3: a resolution that
+ * adapts to the distribution so that fine structures in the region are not
+ * missed at a fixed grid size).
+ *
+ * The base grid is evaluated into roi->d_out like sfk_eval_roi. Its cells
+ * are grouped into bricks of `brick` cells per axis (the last brick of an
+ * axis takes the cells that remain). A brick is refined when, over its
+ * nodes, max - min > threshold * peak, both sides rounded to float32
+ * (peak = the largest value of the base grid). A refined brick is the ROI
+ * whose box spans the brick's corner nodes (their double coordinates as the
+ * parent grid defines them) with 2*cells + 1 nodes per axis (half the
+ * spacing), the same kernel, normalisation and bandwidth as the base (a
+ * ROI-scaled bandwidth keeps the base ROI's h), evaluated like sfk_eval_roi
+ * (bitwise the same as sfk_eval_roi of that ROI) into d_bricks. Refinement
+ * repeats inside refined bricks, each split into bricks of `brick` of its
+ * own cells, up to max_level levels. The list holds the bricks level by
+ * level; within a level, by parent, then z, y, x. If a level's bricks do not
+ * fit in the remaining capacity, refinement stops before that level
+ * (complete = 0). Blocks on hip_stream between levels. */
+typedef struct {
+  int32_t level;       /* 1..max_level */
+  int32_t parent;      /* index of the parent brick in the list, -1 = the base grid */
+  int32_t cell0[3];    /* first cell of the brick in the parent grid */
+  int32_t res[3];      /* nodes per axis of the brick's grid */
+  double lo[3], hi[3]; /* box of the brick's grid */
+  int64_t offset;      /* first float of the brick's grid in d_bricks */
+} sfk_brick;
+
+typedef struct {
+  int32_t brick;       /* cells per brick edge, 2..64 */
+  int32_t max_level;   /* 1..4 */
+  float threshold;     /* > 0, relative to the base grid's peak */
+  int32_t reserved;
+} sfk_adaptive_opts;
+
+typedef struct {
+  int32_t n_bricks;    /* bricks listed in h_bricks */
+  int32_t levels;      /* refinement levels evaluated */
+  int32_t complete;    /* 0 if refinement stopped for lack of capacity */
+  float peak;          /* largest value of the base grid */
+  int64_t floats_used; /* of d_bricks */
+} sfk_adaptive_result;
+
+/* SFK_E_INVAL: NULL pointers, an invalid ROI, brick outside 2..64,
+ * max_level outside 1..4, threshold not finite and > 0, cap_floats or
+ * cap_bricks < 0. SFK_E_UNSUPPORTED: MBE or set = IN_ROI. */
+sfk_status sfk_eval_adaptive(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
+                             const sfk_adaptive_opts* opts, float* d_bricks, int64_t cap_floats,
+                             sfk_brick* h_bricks, int32_t cap_bricks,
+                             sfk_adaptive_result* h_result, void* hip_stream);
+
 /* ----------------------------------------------------------- test exports */
 
 /* Support sets S(n) of grid nodes [node_begin, node_end) of one ROI (CLOUD

@@ -258,6 +258,31 @@ class Context:
                                                     idx.shape[0], C.byref(need)))
         return offs, idx[:need.value]
 
+    # ---- adaptive resolution ----
+
+    def eval_adaptive(self, tree: "Tree", roi, brick: int = 8, max_level: int = 2,
+                      threshold: float = 0.1, cap_floats: int = 1 << 24, cap_bricks: int = 1 << 16,
+                      out=None, stream=None):
+        """sfk_eval_adaptive: (base grid, brick values, [brick dicts], result dict). Brick i's
+        grid is bricks[b['offset'] : b['offset'] + prod(b['res'])], x fastest."""
+        import torch
+        out = self._out_for(roi, out)
+        r = roi_struct(roi, out.data_ptr())
+        o = L.AdaptiveOpts(int(brick), int(max_level), float(threshold), 0)
+        vals = torch.empty(max(1, int(cap_floats)), dtype=torch.float32, device=out.device)
+        hb = (L.Brick * max(1, int(cap_bricks)))()
+        res = L.AdaptiveResult()
+        self._check(self._lib.sfk_eval_adaptive(self._h, tree._h, C.byref(r), C.byref(o),
+                                                vals.data_ptr(), int(cap_floats), hb,
+                                                int(cap_bricks), C.byref(res),
+                                                _stream_ptr(stream)))
+        bricks = [{"level": hb[i].level, "parent": hb[i].parent, "cell0": tuple(hb[i].cell0),
+                   "res": tuple(hb[i].res), "lo": tuple(hb[i].lo), "hi": tuple(hb[i].hi),
+                   "offset": hb[i].offset} for i in range(res.n_bricks)]
+        info = {"n_bricks": res.n_bricks, "levels": res.levels, "complete": bool(res.complete),
+                "peak": res.peak, "floats_used": res.floats_used}
+        return out, vals[:res.floats_used], bricks, info
+
     # ---- view cache (recomputation policy, reuse across frames) ----
 
     def view(self, tree: "Tree", kernel: str = "epanechnikov", bw: str = "fixed", h=(0.01,) * 3,

@@ -81,6 +81,22 @@ class ViewFrameInfo(C.Structure):
                 ("blocks_evaluated", C.c_int64)]
 
 
+class Brick(C.Structure):
+    _fields_ = [("level", C.c_int32), ("parent", C.c_int32), ("cell0", C.c_int32 * 3),
+                ("res", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("offset", C.c_int64)]
+
+
+class AdaptiveOpts(C.Structure):
+    _fields_ = [("brick", C.c_int32), ("max_level", C.c_int32), ("threshold", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class AdaptiveResult(C.Structure):
+    _fields_ = [("n_bricks", C.c_int32), ("levels", C.c_int32), ("complete", C.c_int32),
+                ("peak", C.c_float), ("floats_used", C.c_int64)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "sfk_version": (C.c_char_p, []),
@@ -123,6 +139,10 @@ EXPORTS = {
     "sfk_view_destroy": (C.c_int, [C.c_void_p]),
     "sfk_view_frame": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.c_void_p, C.c_int64, C.POINTER(ViewFrameInfo), C.c_void_p]),
+    "sfk_eval_adaptive": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
+                                    C.POINTER(AdaptiveOpts), C.c_void_p, C.c_int64,
+                                    C.POINTER(Brick), C.c_int32, C.POINTER(AdaptiveResult),
+                                    C.c_void_p]),
     "sfk_debug_point_h2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

@@ -2,8 +2,10 @@
 // PCIe for them: the density at arbitrary positions (trilinear interpolation
 // of the surrounding grid nodes, Section 3.1 after Eq. 8), the selection of
 // the points whose density reaches a threshold (the region a Marching Cubes
-// iso-surface of the grid bounds, selection section), and the Marching Cubes
-// classification of the grid's cells against that threshold.
+// iso-surface of the grid bounds, Section 4.1), the Marching Cubes
+// classification of the grid's cells against that threshold, the per-brick
+// value range that drives adaptive refinement, and the copy of a view's
+// lattice nodes out of cached blocks.
 //
 // Arithmetic: double, every operation rounded, no contraction (the library
 // is built with -ffp-contract=off), in this fixed order per axis
@@ -173,6 +175,40 @@ __global__ __launch_bounds__(256) void k_view_gather(const float* __restrict__ c
   }
 }
 
+// Smallest and largest node value of each brick (one workgroup per brick).
+__global__ __launch_bounds__(256) void k_brick_minmax(const BrickDesc* __restrict__ d, int32_t n,
+                                                      float* __restrict__ mn,
+                                                      float* __restrict__ mx) {
+  __shared__ float s_lo[256], s_hi[256];
+  for (int32_t b = blockIdx.x; b < n; b += gridDim.x) {
+    const BrickDesc D = d[b];
+    const int64_t nx = D.cells[0] + 1, ny = D.cells[1] + 1, nz = D.cells[2] + 1;
+    float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+    for (int64_t q = threadIdx.x; q < nx * ny * nz; q += blockDim.x) {
+      const int64_t i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+      const float v = D.grid[(D.n0[0] + i) +
+                             (int64_t)D.res[0] * ((D.n0[1] + j) + (int64_t)D.res[1] * (D.n0[2] + k))];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + off]);
+        s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + off]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      mn[b] = s_lo[0];
+      mx[b] = s_hi[0];
+    }
+    __syncthreads();
+  }
+}
+
 static GridGeom geom_of(const double lo[3], const double hi[3], const int32_t res[3]) {
   GridGeom g{};
   for (int k = 0; k < 3; ++k) {
@@ -227,6 +263,14 @@ hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_compact_cells, dim3(grid_of(n)), dim3(256), 0, s, flags, pos, case_all, n,
                      cells, cases, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_brick_minmax(const BrickDesc* d_descs, int32_t n, float* d_min, float* d_max,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_brick_minmax, dim3((unsigned)std::min<int32_t>(n, 65536)), dim3(256), 0, s,
+                     d_descs, n, d_min, d_max);
   return hipGetLastError();
 }
 

@@ -88,7 +88,19 @@ struct TileShape { int tx, ty, tz; };
 // ---- host-side launch wrappers (defined in the .hip files) ----
 namespace sfk {
 
+// A brick of a node grid for the refinement test: nodes n0 .. n0 + cells of
+// `grid` (res nodes per axis, x fastest).
+struct BrickDesc {
+  const float* grid;
+  int32_t res[3];
+  int32_t n0[3];
+  int32_t cells[3];
+  int32_t pad_;
+};
+
 // consumers.hip
+hipError_t launch_brick_minmax(const BrickDesc* d_descs, int32_t n, float* d_min, float* d_max,
+                               hipStream_t s);
 hipError_t launch_view_gather(const float* cache, int64_t n_slots, int block, const int32_t* table,
                               const int64_t b0[3], const int32_t nb[3], const int64_t g0[3],
                               const int32_t res[3], float* out, hipStream_t s);

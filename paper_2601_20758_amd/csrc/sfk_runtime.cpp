@@ -2860,3 +2860,199 @@ sfk_status sfk_view_frame(sfk_view v, const double lo[3], const double hi[3], fl
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adaptive resolution: bricks of a grid whose value range is large relative
+// to the base grid's peak are re-evaluated at half the spacing, level by
+// level.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+using sfk::BrickDesc;
+
+// A grid whose cells may be refined: its device values and geometry.
+struct AdaptiveGrid {
+  const float* grid;
+  double lo[3], hi[3];
+  int32_t res[3];
+  int32_t index;  // in the brick list, -1 = the base grid
+};
+
+// Node i of a grid axis, as the evaluation kernels place it.
+double node_coord(double lo, double hi, int32_t res, int32_t i) {
+  return lo + ((double)i * (hi - lo)) / (double)(res - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+sfk_status sfk_eval_adaptive(sfk_ctx c, sfk_tree t, const sfk_roi* roi,
+                             const sfk_adaptive_opts* o, float* d_bricks, int64_t cap_floats,
+                             sfk_brick* h_bricks, int32_t cap_bricks,
+                             sfk_adaptive_result* res_out, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !o || !res_out || (cap_floats > 0 && !d_bricks) || (cap_bricks > 0 && !h_bricks) ||
+      cap_floats < 0 || cap_bricks < 0) {
+    set_err(c, "invalid adaptive-evaluation arguments");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (roi->bw == SFK_BW_MBE || roi->set != SFK_SET_CLOUD) {
+    set_err(c, "adaptive evaluation takes CLOUD-set ROIs with fixed, ROI-scaled or per-point "
+               "bandwidths");
+    return SFK_E_UNSUPPORTED;
+  }
+  if (o->brick < 2 || o->brick > 64 || o->max_level < 1 || o->max_level > 4 ||
+      !(o->threshold > 0.0f) || !std::isfinite(o->threshold)) {
+    set_err(c, "adaptive options: brick in 2..64, max_level in 1..4, finite threshold > 0");
+    return SFK_E_INVAL;
+  }
+  *res_out = sfk_adaptive_result{};
+  res_out->complete = 1;
+  hipStream_t s = (hipStream_t)hip_stream;
+  SFK_TRY(eval_direct(c, t, roi, s, false));
+  // the bricks' ROI template: same kernel and normalisation; a ROI-scaled
+  // bandwidth becomes the base ROI's fixed h
+  sfk_roi tmpl = *roi;
+  if (roi->bw == SFK_BW_ROI_SCALED) {
+    tmpl.bw = SFK_BW_FIXED;
+    for (int k = 0; k < 3; ++k) tmpl.h[k] = (float)((double)roi->h[0] * (roi->hi[k] - roi->lo[k]));
+  }
+  std::vector<AdaptiveGrid> parents(1);
+  for (int k = 0; k < 3; ++k) {
+    parents[0].lo[k] = roi->lo[k];
+    parents[0].hi[k] = roi->hi[k];
+    parents[0].res[k] = roi->res[k];
+  }
+  parents[0].grid = roi->d_out;
+  parents[0].index = -1;
+  const int B = o->brick;
+  float thr = 0.0f;
+  int64_t used = 0;
+  int32_t n_listed = 0;
+  TmpBuf d_desc(c), d_mm(c);
+  for (int level = 1; level <= o->max_level && !parents.empty(); ++level) {
+    // bricks of every parent grid, in (parent, z, y, x) order
+    std::vector<BrickDesc> descs;
+    std::vector<int32_t> owner;
+    for (size_t pi = 0; pi < parents.size(); ++pi) {
+      const AdaptiveGrid& P = parents[pi];
+      int32_t nb[3];
+      for (int k = 0; k < 3; ++k) nb[k] = (P.res[k] - 1 + B - 1) / B;
+      for (int32_t bz = 0; bz < nb[2]; ++bz)
+        for (int32_t by = 0; by < nb[1]; ++by)
+          for (int32_t bx = 0; bx < nb[0]; ++bx) {
+            BrickDesc d{};
+            d.grid = P.grid;
+            const int32_t bb[3] = {bx, by, bz};
+            for (int k = 0; k < 3; ++k) {
+              d.res[k] = P.res[k];
+              d.n0[k] = bb[k] * B;
+              d.cells[k] = std::min(B, P.res[k] - 1 - bb[k] * B);
+            }
+            descs.push_back(d);
+            owner.push_back((int32_t)pi);
+          }
+    }
+    const int32_t nd = (int32_t)descs.size();
+    if (nd == 0) break;
+    if (d_desc.b.bytes < sizeof(BrickDesc) * (size_t)nd) {
+      raw_free(c, d_desc.b.p, d_desc.b.bytes);
+      d_desc.b = DevBuf();
+      SFK_TRY(d_desc.get(sizeof(BrickDesc) * (size_t)nd, "brick descriptors"));
+    }
+    if (d_mm.b.bytes < 2 * sizeof(float) * (size_t)nd) {
+      raw_free(c, d_mm.b.p, d_mm.b.bytes);
+      d_mm.b = DevBuf();
+      SFK_TRY(d_mm.get(2 * sizeof(float) * (size_t)nd, "brick ranges"));
+    }
+    std::vector<float> mm(2 * (size_t)nd);
+    SFK_HIP(c, hipMemcpyAsync(d_desc.b.p, descs.data(), sizeof(BrickDesc) * (size_t)nd,
+                              hipMemcpyHostToDevice, s));
+    SFK_HIP(c, sfk::launch_brick_minmax(d_desc.as<BrickDesc>(), nd, d_mm.as<float>(),
+                                        d_mm.as<float>() + nd, s));
+    SFK_HIP(c, hipMemcpyAsync(mm.data(), d_mm.b.p, 2 * sizeof(float) * (size_t)nd,
+                              hipMemcpyDeviceToHost, s));
+    SFK_HIP(c, hipStreamSynchronize(s));
+    if (level == 1) {
+      float peak = -__builtin_huge_valf();
+      for (int32_t i = 0; i < nd; ++i) peak = std::max(peak, mm[(size_t)nd + i]);
+      res_out->peak = peak;
+      thr = (float)((double)o->threshold * (double)peak);
+      if (!(peak > 0.0f)) break;  // an empty field has nothing to refine
+    }
+    // the refined bricks of this level
+    std::vector<sfk_brick> lvl;
+    std::vector<AdaptiveGrid> next;
+    int64_t lvl_floats = 0;
+    for (int32_t i = 0; i < nd; ++i) {
+      const float range = mm[(size_t)nd + i] - mm[i];
+      if (!(range > thr)) continue;
+      const BrickDesc& d = descs[i];
+      const AdaptiveGrid& P = parents[owner[i]];
+      sfk_brick b{};
+      b.level = level;
+      b.parent = P.index;
+      int64_t nodes = 1;
+      for (int k = 0; k < 3; ++k) {
+        b.cell0[k] = d.n0[k];
+        b.res[k] = 2 * d.cells[k] + 1;
+        b.lo[k] = node_coord(P.lo[k], P.hi[k], P.res[k], d.n0[k]);
+        b.hi[k] = node_coord(P.lo[k], P.hi[k], P.res[k], d.n0[k] + d.cells[k]);
+        nodes *= b.res[k];
+      }
+      b.offset = used + lvl_floats;
+      lvl_floats += nodes;
+      lvl.push_back(b);
+    }
+    if (lvl.empty()) break;
+    if (used + lvl_floats > cap_floats || (int64_t)n_listed + (int64_t)lvl.size() > cap_bricks) {
+      res_out->complete = 0;
+      break;
+    }
+    std::vector<sfk_roi> rois(lvl.size());
+    std::vector<const sfk_roi*> ptrs(lvl.size());
+    for (size_t i = 0; i < lvl.size(); ++i) {
+      sfk_roi r = tmpl;
+      for (int k = 0; k < 3; ++k) {
+        r.lo[k] = lvl[i].lo[k];
+        r.hi[k] = lvl[i].hi[k];
+        r.res[k] = lvl[i].res[k];
+      }
+      r.d_out = d_bricks + lvl[i].offset;
+      r.tag = 0;
+      rois[i] = r;
+      ptrs[i] = &rois[i];
+    }
+    for (size_t i = 0; i < lvl.size(); ++i) SFK_TRY(validate_roi(c, t, &rois[i], (int)i));
+    SFK_TRY(eval_direct_cloud(c, t, ptrs, s, false, nullptr));
+    for (size_t i = 0; i < lvl.size(); ++i) {
+      h_bricks[n_listed + (int32_t)i] = lvl[i];
+      AdaptiveGrid g{};
+      g.grid = rois[i].d_out;
+      for (int k = 0; k < 3; ++k) {
+        g.lo[k] = lvl[i].lo[k];
+        g.hi[k] = lvl[i].hi[k];
+        g.res[k] = lvl[i].res[k];
+      }
+      g.index = n_listed + (int32_t)i;
+      next.push_back(g);
+    }
+    n_listed += (int32_t)lvl.size();
+    used += lvl_floats;
+    res_out->levels = level;
+    parents.swap(next);
+  }
+  // the descriptor and range buffers are freed on return: let the last
+  // kernels that read them finish first
+  SFK_HIP(c, hipStreamSynchronize(s));
+  res_out->n_bricks = n_listed;
+  res_out->floats_used = used;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+}  // extern "C"
