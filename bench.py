@@ -313,6 +313,66 @@ def view_cache(ctx, tree, torch, label, info, n_frames=180):
     }
 
 
+def adaptive(ctx, tree, torch, label):
+    """Adaptive resolution vs a uniform fine grid over the whole cloud: a 64^3
+    base grid refined twice (bricks of 8 cells, threshold 0.2 of the peak)
+    reaches the spacing of a uniform 253^3 grid inside the refined bricks.
+    Epanechnikov, h = 0.01 (fixed, the ROI-scaled value of the unit box)."""
+    import synth
+    base_res, brick, levels, thr = 64, 8, 2, 0.2
+    fine_res = (base_res - 1) * 2 ** levels + 1
+    roi = synth.Roi((0, 0, 0), (1, 1, 1), (base_res,) * 3, kernel="epanechnikov", bw="fixed",
+                    h=(0.01,) * 3)
+    fine = roi.replace(res=(fine_res,) * 3)
+    log("adaptive resolution: %d^3 base, %d levels vs uniform %d^3" % (base_res, levels, fine_res))
+    fout = torch.empty(fine.n_nodes, device="cuda")
+    ctx.eval_roi(tree, fine, out=fout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.eval_roi(tree, fine, out=fout)
+    torch.cuda.synchronize()
+    fine_ms = (time.perf_counter() - t0) * 1e3
+    ctx.eval_adaptive(tree, roi, brick=brick, max_level=levels, threshold=thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base, vals, bricks, info = ctx.eval_adaptive(tree, roi, brick=brick, max_level=levels,
+                                                 threshold=thr)
+    torch.cuda.synchronize()
+    ad_ms = (time.perf_counter() - t0) * 1e3
+    nodes = base.numel() + vals.numel()
+    # which fine-grid nodes the deepest bricks cover (cell index ranges)
+    cover = torch.zeros((fine_res - 1,) * 3, dtype=torch.bool, device="cuda")
+    for i, b in enumerate(bricks):
+        # the brick's first cell in the fine grid: walk up the parents
+        c0 = list(b["cell0"])
+        p, lev = b["parent"], b["level"]
+        cells = [(r - 1) // 2 for r in b["res"]]
+        f0 = [c * 2 ** (levels - lev + 1) for c in c0]
+        while p >= 0:
+            pb = bricks[p]
+            f0 = [f0[k] + pb["cell0"][k] * 2 ** (levels - pb["level"] + 1) for k in range(3)]
+            p = pb["parent"]
+        if lev == levels:
+            span = [cells[k] * 2 ** (levels - lev + 1) for k in range(3)]
+            cover[f0[2]:f0[2] + span[2], f0[1]:f0[1] + span[1], f0[0]:f0[0] + span[0]] = True
+    fg = fout.view(fine_res, fine_res, fine_res)[:-1, :-1, :-1]
+    hot = fg >= 0.1 * float(fout.max())
+    coverage = float((hot & cover).sum()) / max(1.0, float(hot.sum()))
+    del fout, cover, fg, hot
+    torch.cuda.empty_cache()
+    per_level = [sum(1 for b in bricks if b["level"] == l) for l in range(1, levels + 1)]
+    return {
+        "workload": "unit box of the resident %s tree, Epanechnikov, h = 0.01; base %d^3, bricks "
+                    "of %d cells, %d levels, threshold %.2f of the peak vs a uniform %d^3 grid"
+                    % (label, base_res, brick, levels, thr, fine_res),
+        "uniform_fine": {"nodes": fine.n_nodes, "ms": fine_ms},
+        "adaptive": {"nodes": int(nodes), "ms": ad_ms, "bricks_per_level": per_level,
+                     "complete": info["complete"]},
+        "nodes_ratio": nodes / fine.n_nodes, "time_ratio": ad_ms / fine_ms,
+        "hot_fine_nodes_in_deepest_bricks": coverage,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -400,6 +460,7 @@ def main():
                 rec["batch_vs_single"] = batch_vs_single(ctx, t, torch, args.n_batch, lab)
             if not args.no_view:
                 rec["view_cache"] = view_cache(ctx, t, torch, lab, info)
+                rec["adaptive_resolution"] = adaptive(ctx, t, torch, lab)
             return rec
         rec = large_section(ctx, torch, args.batch_points, 3, on_100m)
         if "error" in rec:

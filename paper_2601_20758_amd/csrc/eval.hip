@@ -189,63 +189,129 @@ __global__ __launch_bounds__(256) void k_tile_fill(
 // ---------------------------------------------------------------------------
 // work plan: per tile, leaf_off (prefix of candidate leaves), partial_off
 // (prefix of partial-sum slots of split tiles), tile_fit (how the tile is
-// evaluated, below) and chunk_off (prefix of work items). Single block,
-// looping over the tiles with running carries.
+// evaluated, below) and chunk_off (prefix of work items). Three launches over
+// blocks of kPlanNT consecutive tiles (coalesced; no block waits for
+// another): per-block sums of leaves and partial slots; then each block adds
+// the sums of the blocks before it, scans its tiles, decides each tile's mode
+// from the prefixes and sums its work items; then the same for the items.
+// Block 0 of the last launch writes the totals. A batch of at most kPlanNT
+// tiles takes one launch of one block instead.
 // ---------------------------------------------------------------------------
 
-static constexpr int kPlanNT = 512;
+static constexpr int kPlanNT = 1024;
 
+__device__ __forceinline__ int64_t plan_chunks(int64_t cnt, int chunk_leaves) {
+  return cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
+}
 
-__global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ tile_cnt,
-                                                  BatchHdr* __restrict__ hdr,
-                                                  int32_t* __restrict__ claims, int chunk_leaves,
-                                                  int64_t* __restrict__ leaf_off,
-                                                  int64_t* __restrict__ partial_off,
-                                                  int64_t* __restrict__ chunk_off,
-                                                  int32_t* __restrict__ tile_fit) {
+// sum of v over the block (every thread gets it)
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
+  int64_t tot;
+  (void)block_excl_scan<kPlanNT>(v, &tot, lds);
+  return tot;
+}
+
+// sum of bs[stride * i + k] over the blocks i < nb
+__device__ __forceinline__ int64_t sum_before(const int64_t* __restrict__ bs, int stride, int k,
+                                              int64_t nb, int64_t* lds) {
+  int64_t v = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kPlanNT) v += bs[stride * i + k];
+  return block_sum(v, lds);
+}
+
+__global__ __launch_bounds__(kPlanNT) void k_plan_sums(const int32_t* __restrict__ tile_cnt,
+                                                       const BatchHdr* __restrict__ hdr,
+                                                       int chunk_leaves,
+                                                       int64_t* __restrict__ bs) {
+  __shared__ int64_t lds[kPlanNT / 64];
+  const int64_t n_tiles = hdr->n_tiles;
+  const int64_t t = (int64_t)blockIdx.x * kPlanNT + threadIdx.x;
+  if ((int64_t)blockIdx.x * kPlanNT >= n_tiles) return;  // whole block past the end
+  const int64_t cnt = t < n_tiles ? tile_cnt[t] : 0;
+  const int64_t nch = plan_chunks(cnt, chunk_leaves);
+  const int64_t sl = block_sum(cnt, lds);
+  const int64_t sp = block_sum(t < n_tiles && nch > 1 ? nch : 0, lds);
+  if (threadIdx.x == 0) {
+    bs[3 * blockIdx.x] = sl;
+    bs[3 * blockIdx.x + 1] = sp;
+  }
+}
+
+__global__ __launch_bounds__(kPlanNT) void k_plan_modes(const int32_t* __restrict__ tile_cnt,
+                                                        const BatchHdr* __restrict__ hdr,
+                                                        int chunk_leaves, int64_t* __restrict__ bs,
+                                                        int64_t* __restrict__ leaf_off,
+                                                        int64_t* __restrict__ partial_off,
+                                                        int32_t* __restrict__ tile_fit) {
   __shared__ int64_t lds[kPlanNT / 64];
   const int64_t n_tiles = hdr->n_tiles;
   const int64_t leaf_cap = hdr->leaf_cap;
   const int64_t partial_cap = hdr->partial_cap;
-  int64_t carry_l = 0, carry_p = 0, carry_c = 0;
-  for (int64_t base = 0; base < n_tiles; base += kPlanNT) {
-    const int64_t t = base + threadIdx.x;
-    const bool v = t < n_tiles;
-    const int64_t cnt = v ? tile_cnt[t] : 0;
-    const int64_t nch = cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
-    const int64_t pneed = (v && nch > 1) ? nch : 0;
-    int64_t tot;
-    const int64_t lo = carry_l + block_excl_scan<kPlanNT>(cnt, &tot, lds);
-    carry_l += tot;
-    const int64_t po = carry_p + block_excl_scan<kPlanNT>(pneed, &tot, lds);
-    carry_p += tot;
-    const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
-    const int mode = !v ? kModeWalkTile
-                        : (lo + cnt <= leaf_cap && fit_p) ? kModeLists
-                                                           : (fit_p && nch > 1) ? kModeWalkChunk
-                                                                                : kModeWalkTile;
-    const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
-    const int64_t co = carry_c + block_excl_scan<kPlanNT>(nit, &tot, lds);
-    carry_c += tot;
-    if (v) {
-      leaf_off[t] = lo;
-      partial_off[t] = po;
-      chunk_off[t] = co;
-      tile_fit[t] = mode;
+  if ((int64_t)blockIdx.x * kPlanNT >= n_tiles) return;
+  const int64_t base_l = sum_before(bs, 3, 0, blockIdx.x, lds);
+  const int64_t base_p = sum_before(bs, 3, 1, blockIdx.x, lds);
+  const int64_t t = (int64_t)blockIdx.x * kPlanNT + threadIdx.x;
+  const bool v = t < n_tiles;
+  const int64_t cnt = v ? tile_cnt[t] : 0;
+  const int64_t nch = plan_chunks(cnt, chunk_leaves);
+  const int64_t pneed = v && nch > 1 ? nch : 0;
+  int64_t tot;
+  const int64_t lo = base_l + block_excl_scan<kPlanNT>(cnt, &tot, lds);
+  const int64_t po = base_p + block_excl_scan<kPlanNT>(pneed, &tot, lds);
+  const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
+  const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
+                   : (fit_p && nch > 1)            ? kModeWalkChunk
+                                                   : kModeWalkTile;
+  const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
+  if (v) {
+    leaf_off[t] = lo;
+    partial_off[t] = po;
+    tile_fit[t] = mode;
+  }
+  const int64_t si = block_sum(nit, lds);
+  if (threadIdx.x == 0) bs[3 * blockIdx.x + 2] = si;
+}
+
+__global__ __launch_bounds__(kPlanNT) void k_plan_items(const int32_t* __restrict__ tile_cnt,
+                                                        BatchHdr* __restrict__ hdr,
+                                                        int32_t* __restrict__ claims,
+                                                        int chunk_leaves,
+                                                        const int64_t* __restrict__ bs,
+                                                        int64_t* __restrict__ leaf_off,
+                                                        int64_t* __restrict__ partial_off,
+                                                        int64_t* __restrict__ chunk_off,
+                                                        const int32_t* __restrict__ tile_fit) {
+  __shared__ int64_t lds[kPlanNT / 64];
+  const int64_t n_tiles = hdr->n_tiles;
+  const int64_t nb = (n_tiles + kPlanNT - 1) / kPlanNT;
+  if (blockIdx.x == 0) {
+    // totals (block 0 runs even for an empty batch)
+    const int64_t tl = sum_before(bs, 3, 0, nb, lds);
+    const int64_t tp = sum_before(bs, 3, 1, nb, lds);
+    const int64_t tc = sum_before(bs, 3, 2, nb, lds);
+    const int64_t leaf_cap = hdr->leaf_cap, partial_cap = hdr->partial_cap;
+    // every thread of this block has read the header before thread 0 writes it
+    __syncthreads();
+    if (threadIdx.x < kClaimSlices) claims[threadIdx.x * kClaimStride] = 0;
+    if (threadIdx.x == 0) {
+      leaf_off[n_tiles] = tl;
+      partial_off[n_tiles] = tp;
+      chunk_off[n_tiles] = tc;
+      hdr->total_leaves = tl;
+      hdr->n_items = tc;
+      hdr->total_partials = tp;
+      hdr->overflow = (tl > leaf_cap || tp > partial_cap) ? 1 : 0;
     }
   }
-  // every thread has read the header above before thread 0 writes it
-  __syncthreads();
-  if (threadIdx.x < kClaimSlices) claims[threadIdx.x * kClaimStride] = 0;
-  if (threadIdx.x == 0) {
-    leaf_off[n_tiles] = carry_l;
-    partial_off[n_tiles] = carry_p;
-    chunk_off[n_tiles] = carry_c;
-    hdr->total_leaves = carry_l;
-    hdr->n_items = carry_c;
-    hdr->total_partials = carry_p;
-    hdr->overflow = (carry_l > leaf_cap || carry_p > partial_cap) ? 1 : 0;
-  }
+  if ((int64_t)blockIdx.x >= nb) return;
+  const int64_t base_c = sum_before(bs, 3, 2, blockIdx.x, lds);
+  const int64_t t = (int64_t)blockIdx.x * kPlanNT + threadIdx.x;
+  const bool v = t < n_tiles;
+  int64_t nit = 0;
+  if (v) nit = tile_fit[t] == kModeWalkTile ? 1 : plan_chunks(tile_cnt[t], chunk_leaves);
+  int64_t tot;
+  const int64_t co = base_c + block_excl_scan<kPlanNT>(nit, &tot, lds);
+  if (v) chunk_off[t] = co;
 }
 
 // ---------------------------------------------------------------------------
@@ -854,11 +920,71 @@ hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* roi
   return hipGetLastError();
 }
 
+// The whole plan in one block, for batches of at most kPlanNT tiles.
+__global__ __launch_bounds__(kPlanNT) void k_plan_one(const int32_t* __restrict__ tile_cnt,
+                                                      BatchHdr* __restrict__ hdr,
+                                                      int32_t* __restrict__ claims,
+                                                      int chunk_leaves,
+                                                      int64_t* __restrict__ leaf_off,
+                                                      int64_t* __restrict__ partial_off,
+                                                      int64_t* __restrict__ chunk_off,
+                                                      int32_t* __restrict__ tile_fit) {
+  __shared__ int64_t lds[kPlanNT / 64];
+  const int64_t n_tiles = hdr->n_tiles;
+  const int64_t leaf_cap = hdr->leaf_cap, partial_cap = hdr->partial_cap;
+  const int64_t t = threadIdx.x;
+  const bool v = t < n_tiles;
+  const int64_t cnt = v ? tile_cnt[t] : 0;
+  const int64_t nch = plan_chunks(cnt, chunk_leaves);
+  const int64_t pneed = v && nch > 1 ? nch : 0;
+  int64_t tl, tp, tc;
+  const int64_t lo = block_excl_scan<kPlanNT>(cnt, &tl, lds);
+  const int64_t po = block_excl_scan<kPlanNT>(pneed, &tp, lds);
+  const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
+  const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
+                   : (fit_p && nch > 1)            ? kModeWalkChunk
+                                                   : kModeWalkTile;
+  const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
+  const int64_t co = block_excl_scan<kPlanNT>(nit, &tc, lds);
+  if (v) {
+    leaf_off[t] = lo;
+    partial_off[t] = po;
+    chunk_off[t] = co;
+    tile_fit[t] = mode;
+  }
+  // every thread has read the header above before thread 0 writes it
+  __syncthreads();
+  if (threadIdx.x < kClaimSlices) claims[threadIdx.x * kClaimStride] = 0;
+  if (threadIdx.x == 0) {
+    leaf_off[n_tiles] = tl;
+    partial_off[n_tiles] = tp;
+    chunk_off[n_tiles] = tc;
+    hdr->total_leaves = tl;
+    hdr->n_items = tc;
+    hdr->total_partials = tp;
+    hdr->overflow = (tl > leaf_cap || tp > partial_cap) ? 1 : 0;
+  }
+}
+
+int plan_blocks(int64_t max_tiles) {
+  return (int)std::max<int64_t>(1, (max_tiles + kPlanNT - 1) / kPlanNT);
+}
+
 hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, int chunk_leaves,
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
-                       int32_t* tile_fit, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, hdr, claims, chunk_leaves,
-                     leaf_off, partial_off, chunk_off, tile_fit);
+                       int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s) {
+  const int nb = plan_blocks(max_tiles);
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_plan_one, dim3(1), dim3(kPlanNT), 0, s, tile_cnt, hdr, claims,
+                       chunk_leaves, leaf_off, partial_off, chunk_off, tile_fit);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_plan_sums, dim3(nb), dim3(kPlanNT), 0, s, tile_cnt, hdr, chunk_leaves,
+                     plan_tmp);
+  hipLaunchKernelGGL(k_plan_modes, dim3(nb), dim3(kPlanNT), 0, s, tile_cnt, hdr, chunk_leaves,
+                     plan_tmp, leaf_off, partial_off, tile_fit);
+  hipLaunchKernelGGL(k_plan_items, dim3(nb), dim3(kPlanNT), 0, s, tile_cnt, hdr, claims,
+                     chunk_leaves, plan_tmp, leaf_off, partial_off, chunk_off, tile_fit);
   return hipGetLastError();
 }
 

@@ -159,9 +159,12 @@ hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_r
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                              const double* coords, TileShape ts, int grid_blocks,
                              int32_t* tile_cnt, int32_t* tile_done, hipStream_t s);
+// plan_tmp: 3 int64 per block of plan_blocks(max_tiles); max_tiles bounds
+// the header's tile count (the grid of a captured graph uses the capacity)
+int plan_blocks(int64_t max_tiles);
 hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, int chunk_leaves,
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
-                       int32_t* tile_fit, hipStream_t s);
+                       int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s);
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                             const double* coords, TileShape ts, int grid_blocks,
                             const int32_t* tile_cnt, const int32_t* tile_fit,

@@ -55,7 +55,7 @@ struct DevBuf {
 struct Workspace {
   // hdr_rois = [BatchHdr][RoiDev x capacity]: staged by one host-to-device copy
   DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
-      item_tile, partials, claims;
+      item_tile, partials, claims, plan_tmp;
   uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
@@ -607,8 +607,11 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                      "ROI descriptors"));
   SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)nc, "node coordinates"));
   SFK_TRY(ws_reserve(c, ws, ws.claims, kClaimBytes, "work-claim counters"));
+  SFK_TRY(ws_reserve(c, ws, ws.plan_tmp, 3 * sizeof(int64_t) * (size_t)sfk::plan_blocks(tiles),
+                     "plan block sums"));
   Caps k;
-  k.tiles_cap = std::min<int64_t>({(int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
+  k.tiles_cap = std::min<int64_t>({(int64_t)(ws.plan_tmp.bytes / (3 * sizeof(int64_t))) * 1024,
+                                   (int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_fit.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_done.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.leaf_off.bytes / sizeof(int64_t)) - 1,
@@ -641,11 +644,13 @@ BatchHdr make_hdr(const Caps& k, int64_t n_rois, int64_t n_tiles) {
 }
 
 // Enqueue the kernels of one group whose header + descriptors are already
-// (being) copied into ws.hdr_rois. roi_grid / tile_grid: blocks of the
-// coordinate and tile kernels (exact for direct launches, capacities for a
+// (being) copied into ws.hdr_rois. roi_grid: blocks of the coordinate
+// kernel (one per ROI); max_tiles: a bound on the batch's tiles that sizes the
+// tile and plan grids (exact for direct launches, the capacities for a
 // captured graph).
 sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
-                          Workspace& ws, int roi_grid, int tile_grid, hipStream_t s) {
+                          Workspace& ws, int roi_grid, int64_t max_tiles, hipStream_t s) {
+  const int tile_grid = sfk::tile_grid_blocks(max_tiles);
   const int CH = chunk_leaves_of(c);
   BatchHdr* hdr = (BatchHdr*)ws.hdr_rois.p;
   const RoiDev* rois = (const RoiDev*)((char*)ws.hdr_rois.p + sizeof(BatchHdr));
@@ -664,7 +669,7 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   {
     ProfScope p(c, PK_PLAN, s);
     SFK_HIP(c, sfk::launch_plan(tile_cnt, hdr, (int32_t*)ws.claims.p, CH, leaf_off, partial_off,
-                                chunk_off, tile_fit, s));
+                                chunk_off, tile_fit, (int64_t*)ws.plan_tmp.p, max_tiles, s));
   }
   {
     ProfScope p(c, PK_TILE_FILL, s);
@@ -783,7 +788,7 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
     const size_t gb = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
     SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host + off, gb, hipMemcpyHostToDevice, s));
     SFK_TRY(launch_kernels(c, tv, keys[gi].ts, keys[gi].kk, keys[gi].pp, count_mode, ws, (int)n,
-                           sfk::tile_grid_blocks(tiles[gi]), s));
+                           tiles[gi], s));
     off += gb;
   }
   SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
@@ -846,8 +851,8 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
     if (hipMemcpyAsync(sl.ws.hdr_rois.p, sl.st.host, full, hipMemcpyHostToDevice, s) != hipSuccess)
       st = SFK_E_DEVICE;
     if (st == SFK_OK)
-      st = launch_kernels(c, view_of(t), ts, kk, pp, false, sl.ws, (int)k.rois_cap,
-                          sfk::tile_grid_blocks(k.tiles_cap), s);
+      st = launch_kernels(c, view_of(t), ts, kk, pp, false, sl.ws, (int)k.rois_cap, k.tiles_cap,
+                          s);
     if (st == SFK_OK && hipMemcpyAsync(sl.st.hdr_host, sl.ws.hdr_rois.p, sizeof(BatchHdr),
                                        hipMemcpyDeviceToHost, s) != hipSuccess)
       st = SFK_E_DEVICE;
@@ -1019,7 +1024,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     SFK_HIP(c, hipEventRecord(st.ev, s));
     st.ev_valid = true;
     return launch_kernels(c, tv, ts, g.count_mode ? 0 : g.kk, g.pp, g.count_mode, ws, 1,
-                          sfk::tile_grid_blocks(n_tiles), s);
+                          n_tiles, s);
   };
 
   if (!mbe) {
@@ -1381,7 +1386,7 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
 static void release_ws(sfk_ctx c, Workspace& ws) {
   DevBuf* bufs[] = {&ws.hdr_rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
                     &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
-                    &ws.partials, &ws.claims};
+                    &ws.partials, &ws.claims, &ws.plan_tmp};
   for (DevBuf* b : bufs) ws_release(c, *b);
 }
 
