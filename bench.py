@@ -48,6 +48,21 @@ KERNEL_SOURCES = ("paper_2601_20758_amd/csrc/eval.hip", "paper_2601_20758_amd/cs
                   "paper_2601_20758_amd/csrc/sfk_internal.h")
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "k_knn_k_eval_per_point_10m_valu.md")
+
+
+def profiled_valu_busy(kernel_prefix):
+    """VALU busy fraction of a kernel from the committed counter summary
+    (None if the summary or the kernel's row is missing)."""
+    try:
+        for line in open(VALU_FILE):
+            if line.startswith("| `" + kernel_prefix):
+                return float(line.split("|")[3].strip().rstrip("%")) / 100.0
+    except (OSError, ValueError, IndexError):
+        pass
+    return None
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -440,6 +455,15 @@ def main():
         "phases_ms": {k: prof[k] / args.steps for k in
                       ("build_ms", "knn_ms", "tile_count_ms", "plan_ms", "tile_fill_ms",
                        "eval_ms")},
+        "dominant_kernel": {
+            "kernel": "k_knn<32>" if knn_k else "k_eval",
+            "ms_per_step": (prof["knn_ms"] if knn_k else prof["eval_ms"]) / args.steps,
+            "share_of_step": (prof["knn_ms"] if knn_k else prof["eval_ms"]) / args.steps
+                             / ms_per_step,
+            "bound": "alu (VALU instruction issue)",
+            "valu_busy_profiled": profiled_valu_busy("k_knn<32>" if knn_k else "k_eval<4, 4, 4, 1, 1"),
+            "note": "roofline above is the per-ROI evaluation kernel (the hot loop the metric "
+                    "counts); the k-NN bandwidth kernel runs once per tree build"},
         "eval_only_evals_per_s": useful / (eval_ms * 1e-3),
         "useful_evals": useful, "tested_pairs": tested,
         "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
