@@ -131,8 +131,10 @@ hipError_t launch_morton(const float* xyz, int64_t n, const float* bbox, int bit
 // stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
 // Per pass: block digit histograms (digit-major) -> exclusive scan ->
 // scatter. The scatter ranks equal digits inside a wavefront with eight
-// ballots (one per digit bit), then across the block's four wavefronts
-// through LDS, round by round, so the order of equal keys is preserved.
+// ballots (one per digit bit); each wavefront owns a contiguous quarter of
+// the block's tile and starts each digit after the earlier wavefronts'
+// elements of that digit, so the order of equal keys is preserved; the
+// ranked tile is staged in LDS and written out in digit order.
 // ---------------------------------------------------------------------------
 
 static constexpr int kRsNT = 256;
@@ -160,23 +162,61 @@ __global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict
                                                       uint64_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int64_t n,
                                                       int shift,
+                                                      const uint32_t* __restrict__ hist,
                                                       const uint32_t* __restrict__ offs,
                                                       int nblk) {
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t run[256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+  // Each wavefront owns a contiguous quarter of the block's tile. Its digit
+  // counts give every (wavefront, digit) a first local slot (digits in
+  // order, wavefronts in order within a digit); each wavefront then ranks its
+  // elements in index order into an LDS copy of the tile (stable), and the
+  // tile is written out in that order, so the elements of one digit go to
+  // consecutive global positions.
+  constexpr int kPerWave = kRsTile / 4;
+  __shared__ uint64_t stage_k[kRsTile];
+  __shared__ uint32_t stage_v[kRsTile];
+  __shared__ uint32_t wslot[4][256];  // counts, then next local slot per (wavefront, digit)
+  __shared__ uint32_t lstart[256];    // first local slot of each digit
+  __shared__ uint32_t gbase[256];     // global position of the digit's first element
+  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
   const int64_t base = (int64_t)blockIdx.x * kRsTile;
-  const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRsItems; ++r) {
-    const int64_t g = base + (int64_t)r * kRsNT + tid;
-    const bool valid = g < n;
-    const uint64_t key = valid ? kin[g] : 0ull;
-    const uint32_t val = valid ? vin[g] : 0u;
-    const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+  const int tile_n = (int)min((int64_t)kRsTile, n - base);
+  const int w0 = wave * kPerWave;
+  for (int d = lane; d < 256; d += 64) wslot[wave][d] = 0;
+  wave_sync();
+  for (int r = 0; r < kPerWave / 64; ++r) {
+    const int li = w0 + r * 64 + lane;
+    if (li < tile_n) atomicAdd(&wslot[wave][(uint32_t)(kin[base + li] >> shift) & 255u], 1u);
+  }
+  // local digit starts: exclusive scan of this block's histogram
+  const uint32_t hc = hist[(int64_t)tid * nblk + blockIdx.x];
+  uint32_t inc = hc;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  __shared__ uint32_t wsum[4];
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t start = inc - hc;
+  for (int w = 0; w < wave; ++w) start += wsum[w];
+  lstart[tid] = start;
+  gbase[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+  {
+    const uint32_t c0 = wslot[0][tid], c1 = wslot[1][tid], c2 = wslot[2][tid];
+    wslot[0][tid] = start;
+    wslot[1][tid] = start + c0;
+    wslot[2][tid] = start + c0 + c1;
+    wslot[3][tid] = start + c0 + c1 + c2;
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kPerWave / 64; ++r) {
+    const int li = w0 + r * 64 + lane;
+    const bool valid = li < tile_n;
+    const uint64_t key = valid ? kin[base + li] : 0ull;
+    const uint32_t val = valid ? vin[base + li] : 0u;
+    const uint32_t dig = (uint32_t)(key >> shift) & 255u;
     uint64_t mask = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -185,21 +225,22 @@ __global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict
       mask &= bit ? bb : ~bb;
     }
     const uint32_t rank = (uint32_t)popc64(mask & lt);
-    if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)popc64(mask);
-    __syncthreads();
-    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-    wcnt[0][tid] = 0;
-    wcnt[1][tid] = c0;
-    wcnt[2][tid] = c0 + c1;
-    wcnt[3][tid] = c0 + c1 + c2;
-    __syncthreads();
+    uint32_t slot = 0;
+    if (valid) slot = wslot[wave][dig];
+    wave_sync();  // every lane has read its digit's slot before the leaders advance it
     if (valid) {
-      const uint32_t pos = run[dig] + wcnt[wave][dig] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      stage_k[slot + rank] = key;
+      stage_v[slot + rank] = val;
+      if (rank == 0) wslot[wave][dig] = slot + (uint32_t)popc64(mask);
     }
-    __syncthreads();
-    run[tid] += c0 + c1 + c2 + c3;
+    wave_sync();
+  }
+  __syncthreads();
+  for (int i = tid; i < tile_n; i += kRsNT) {
+    const uint64_t key = stage_k[i];
+    const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+    kout[gbase[dig] + ((uint32_t)i - lstart[dig])] = key;
+    vout[gbase[dig] + ((uint32_t)i - lstart[dig])] = stage_v[i];
   }
 }
 
@@ -231,7 +272,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     hipError_t e = scan_exclusive_u32(hist, offs, nh, stmp, stmp_bytes, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, va, kb, vb, n,
-                       shift, offs, (int)nblk);
+                       shift, hist, offs, (int)nblk);
     std::swap(ka, kb);
     std::swap(va, vb);
   }

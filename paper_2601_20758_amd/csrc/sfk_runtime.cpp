@@ -1522,10 +1522,12 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
     for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
     // Morton keys and the sort
+    // automatic: about 4x finer per axis than n^(1/3), at least 10 bits
+    // (10M points: 30-bit keys, four 8-bit sort passes)
     int bits = o.morton_bits;
     if (bits == 0) {
       const int lg = (int)std::ceil(std::log2((double)std::max<int64_t>(n, 2)));
-      bits = std::min(21, std::max(10, (lg + 2) / 3 + 3));
+      bits = std::min(21, std::max(10, (lg + 2) / 3 + 2));
     }
     TmpBuf keys(c), keys2(c), vals(c), vals2(c), stmp(c);
     if ((st = keys.get(sizeof(uint64_t) * (size_t)n, "sort keys")) != SFK_OK ||
