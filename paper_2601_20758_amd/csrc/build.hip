@@ -462,7 +462,7 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // One wavefront per leaf, one query particle per lane; each lane keeps its
 // KM smallest squared distances in a sorted register array whose last slot
 // is its current k-th smallest (the threshold). The lane's own leaf and its
-// two Morton neighbours come first and bound every answer from above by
+// nearest Morton neighbours come first and bound every answer from above by
 // real distances. The box hierarchy is then walked with the wavefront's
 // largest threshold (a box farther than that cannot hold a closer
 // particle); the leaves it yields are kept in a per-wave list and visited
@@ -479,6 +479,13 @@ constexpr int kKnnSub = 8;                          // particles per sub-block
 constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
 constexpr int kKnnList = 256;                       // leaves held for ordering
 constexpr int kKnnBands = 5;                        // distance bands of the visiting order
+// Morton neighbours of the query leaf visited first, on each side: more
+// seed candidates bound the answers of the leaf's edge lanes more tightly
+// before the walk (10M points, k = 32: 1 -> 4 per side cut the kernel by 5%)
+template <int KM>
+constexpr int knn_near() {
+  return KM >= 32 ? 4 : KM >= 16 ? 2 : 1;
+}
 
 // Boxes of the sub-blocks of 8 consecutive particles, 8 floats per box
 // (lo.xyz, 0, hi.xyz, 0) so one 256-byte line holds a leaf's eight boxes. A
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
           pass = key <= tau;
         }
         if (level == 0) {
-          const bool take = pass && (child < leaf - 1 || child > leaf + 1);
+          const bool take = pass && (child < leaf - knn_near<KM>() || child > leaf + knn_near<KM>());
           const uint64_t tm = ballot(take);
           if (take) {
             const int pos = ln + popc64(tm & lanemask_lt());
@@ -755,11 +762,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
     for (int phase = 0;; ++phase) {
       int no;
       if (phase == 0) {
-        no = 1 + (leaf > 0 ? 1 : 0) + (leaf + 1 < nl ? 1 : 0);
-        if (lane == 0) {
-          ord[0] = leaf;
-          if (leaf > 0) ord[1] = leaf - 1;
-          if (leaf + 1 < nl) ord[no - 1] = leaf + 1;
+        // the leaf, then its Morton neighbours at distance 1, 2, ... knn_near
+        no = 0;
+        if (lane == 0) ord[0] = leaf;
+        ++no;
+        for (int d = 1; d <= knn_near<KM>(); ++d) {
+          if (leaf - d >= 0) {
+            if (lane == 0) ord[no] = leaf - d;
+            ++no;
+          }
+          if (leaf + d < nl) {
+            if (lane == 0) ord[no] = leaf + d;
+            ++no;
+          }
         }
         wave_sync();
       } else {
