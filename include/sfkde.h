@@ -280,7 +280,7 @@ sfk_status sfk_serve(sfk_ctx ctx, sfk_tree tree, const sfk_request* reqs, int64_
 sfk_status sfk_sample_density(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid,
                               const float* d_xyz, int64_t n, float* d_out, void* hip_stream);
 
-/* Selection (selection section: a density threshold, the region bounded by
+/* Selection (Section 4.1: a density threshold, the region bounded by
  * the grid's iso-surface at that threshold, the points inside it): the
  * ascending indices of the points inside the closed box whose interpolated
  * density is >= iso. Writes the first min(count, cap) indices to d_idx
@@ -290,7 +290,7 @@ sfk_status sfk_select_points(sfk_ctx ctx, const sfk_roi* roi, const float* d_gri
                              int64_t* h_count, void* hip_stream);
 
 /* Marching Cubes classification of the grid's (res - 1)^3 cells against iso
- * (selection section): the case of a cell has bit dx + 2 dy + 4 dz set when
+ * (Section 4.1): the case of a cell has bit dx + 2 dy + 4 dz set when
  * that corner's value is >= iso; a cell is active unless its case is 0 or
  * 255. Writes the first min(count, cap) active cells in ascending linear
  * cell index (x fastest over res - 1 cells per axis) to d_cells (int64) and

@@ -407,7 +407,7 @@ def candidates(pts, roi, nodes, h2=None):
 
 
 # ---------------------------------------------------------------------------
-# consumers of a density grid (Section 3.1 after Eq. 8; selection section)
+# consumers of a density grid (Section 3.1 after Eq. 8; Section 4.1)
 # ---------------------------------------------------------------------------
 
 def sample_density(grid: np.ndarray, roi, pts: np.ndarray) -> np.ndarray:
