@@ -136,7 +136,7 @@ def workload(name):
                     "128^3 grid, Gaussian truncated at 3h, per-point h from the 32nd nearest "
                     "neighbour; step = tree build + k-NN + range query + evaluation",
         "n_points": len(pts), "grid": [128, 128, 128], "kernel": "gauss_trunc3",
-        "bandwidth": "per_point_knn32", "seed": 2}
+        "bandwidth": "per_point_knn32", "seed": 2, "particle_order": "hilbert"}
 
 
 def cpu_baseline(pts, roi, h2, n_nodes, seed=7):

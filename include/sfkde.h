@@ -81,6 +81,12 @@ typedef enum {
   SFK_SET_IN_ROI = 1  /* only particles in the closed box B; N = N_B (Eq. 1) */
 } sfk_set;
 
+typedef enum {
+  SFK_CURVE_HILBERT = 0, /* Hilbert order (default): consecutive cells are face
+                            neighbours, so leaf and group boxes are compact */
+  SFK_CURVE_MORTON = 1   /* Morton (Z) order: the coordinate bits interleaved */
+} sfk_curve;
+
 typedef struct sfk_ctx_s* sfk_ctx;
 typedef struct sfk_tree_s* sfk_tree;
 typedef int64_t sfk_ticket;
@@ -98,8 +104,9 @@ typedef struct {
   int32_t leaf_size;   /* particles per leaf bucket; 0 or 64 (the wavefront width) */
   int32_t knn_k;       /* 0: no per-point bandwidth; 1..64: h_j^2 = k-th smallest
                           squared distance to another particle (self excluded) */
-  int32_t morton_bits; /* bits per axis of the sort key, 0 = automatic (4..21) */
-  int32_t reserved;
+  int32_t key_bits;    /* bits per axis of the sort key, 1..21, 0 = automatic
+                          (10..21, about 4 cells per axis per n^(1/3)) */
+  int32_t curve;       /* sfk_curve: the order of particles in the leaves */
 } sfk_tree_opts;
 
 /* One region-of-interest request (Section 3.1: a box B and its node grid). */
@@ -133,15 +140,18 @@ const char* sfk_version(void);
 
 /* Build the spatial index (the paper builds a k-d tree on the CPU and
  * uploads it, Section 3.2; here the tree is built on the device): bounding
- * box, Morton keys, radix sort, leaf buckets of 64 particles laid out as
- * float4 in Morton order, an implicit 64-ary hierarchy of boxes. With
+ * box, space-filling curve keys (opts->curve), radix sort, leaf buckets of
+ * 64 particles laid out as float4 in curve order, an implicit 64-ary
+ * hierarchy of boxes over consecutive leaves. Results do not depend on the
+ * curve beyond float32 summation order. With
  * opts->knn_k > 0 it also computes each particle's squared k-th nearest
  * neighbour distance (per-point bandwidth). d_h, if non-NULL, gives a
  * per-particle bandwidth instead (n floats, device, original order, > 0).
  * d_xyz is read during the call only (stream-ordered on hip_stream; the call
  * synchronises the stream before it returns). n = 0 gives an empty tree.
  * Errors: SFK_E_INVAL on n < 0, n >= 2^31 - 64, NULL pointers, a
- * non-finite coordinate, knn_k > 64 or knn_k >= n, a non-positive d_h. */
+ * non-finite coordinate, knn_k > 64 or knn_k >= n, a non-positive d_h,
+ * key_bits outside 0..21, an unknown curve. */
 sfk_status sfk_build_tree(sfk_ctx ctx, const float* d_xyz, int64_t n,
                           const float* d_h, const sfk_tree_opts* opts,
                           void* hip_stream, sfk_tree* out);
@@ -433,6 +443,15 @@ sfk_status sfk_debug_candidates(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* h_idx, int64_t cap, int64_t* needed);
 /* Per-particle squared k-NN distance h_j^2 in original order (n floats). */
 sfk_status sfk_debug_point_h2(sfk_ctx ctx, sfk_tree tree, float* h_h2);
+/* The tree's particle order: h_perm[i] = original index of the i-th
+ * particle in leaf (curve) order, n int32. */
+sfk_status sfk_debug_tree_order(sfk_ctx ctx, sfk_tree tree, int32_t* h_perm);
+/* Host-only (no device work): the sort key the tree build gives the cell
+ * (x, y, z) of a 2^bits-per-axis lattice, for n cells given as uint32
+ * triples; 3*bits-bit keys to h_keys. SFK_E_INVAL on NULL pointers, n < 0,
+ * bits outside 1..21, an unknown curve or a coordinate >= 2^bits. */
+sfk_status sfk_debug_curve_keys(int32_t curve, int32_t bits, const uint32_t* h_cells, int64_t n,
+                                uint64_t* h_keys);
 /* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel. */
 sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* useful_pairs, int64_t* tested_pairs);

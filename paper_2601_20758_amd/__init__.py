@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["SfkError", "Context", "Tree", "roi_struct", "version"]
+__all__ = ["SfkError", "Context", "Tree", "curve_keys", "roi_struct", "version"]
 
 
 class SfkError(RuntimeError):
@@ -28,6 +28,18 @@ class SfkError(RuntimeError):
 
 def version() -> str:
     return L.lib().sfk_version().decode()
+
+
+def curve_keys(curve, bits: int, cells) -> np.ndarray:
+    """sfk_debug_curve_keys (host only): the tree build's sort key of each
+    (x, y, z) lattice cell of an (n, 3) integer array, 2^bits cells per axis."""
+    c = np.ascontiguousarray(cells, dtype=np.uint32).reshape(-1, 3)
+    out = np.zeros(max(len(c), 1), dtype=np.uint64)
+    st = L.lib().sfk_debug_curve_keys(_enum(L.CURVES, curve, "curve"), int(bits),
+                                      c.ctypes.data, len(c), out.ctypes.data)
+    if st != 0:
+        raise SfkError(st, L.lib().sfk_last_error(None).decode())
+    return out[:len(c)]
 
 
 def _enum(table, v, what):
@@ -135,10 +147,11 @@ class Context:
         self.close()
 
     # -- tree
-    def build_tree(self, xyz, knn_k: int = 0, h=None, morton_bits: int = 0,
-                   stream=None) -> "Tree":
+    def build_tree(self, xyz, knn_k: int = 0, h=None, key_bits: int = 0,
+                   curve: str = "hilbert", stream=None) -> "Tree":
         """sfk_build_tree on an (n, 3) float32 device tensor (and an optional
-        per-particle bandwidth tensor h of n floats)."""
+        per-particle bandwidth tensor h of n floats); curve is "hilbert" or
+        "morton"."""
         import torch
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float32):
             raise TypeError("xyz must be a float32 device tensor")
@@ -150,7 +163,7 @@ class Context:
                     and h.numel() == xyz.shape[0]):
                 raise ValueError("h must be n contiguous float32 device values")
             hp = h.data_ptr()
-        opts = L.TreeOpts(0, int(knn_k), int(morton_bits), 0)
+        opts = L.TreeOpts(0, int(knn_k), int(key_bits), _enum(L.CURVES, curve, "curve"))
         out = C.c_void_p()
         self._check(self._lib.sfk_build_tree(self._h, xyz.data_ptr() if xyz.numel() else None,
                                              int(xyz.shape[0]), hp, C.byref(opts),
@@ -358,6 +371,13 @@ class Context:
         n = tree.info()[0]
         out = np.zeros(max(n, 1), dtype=np.float32)
         self._check(self._lib.sfk_debug_point_h2(self._h, tree._h, out.ctypes.data))
+        return out[:n]
+
+    def debug_tree_order(self, tree: "Tree") -> np.ndarray:
+        """Original index of each particle in the tree's leaf order."""
+        n = tree.info()[0]
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        self._check(self._lib.sfk_debug_tree_order(self._h, tree._h, out.ctypes.data))
         return out[:n]
 
     def debug_eval_count(self, tree: "Tree", roi):

@@ -24,8 +24,11 @@ class Allocator(C.Structure):
 
 
 class TreeOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("knn_k", C.c_int32), ("morton_bits", C.c_int32),
-                ("reserved", C.c_int32)]
+    _fields_ = [("leaf_size", C.c_int32), ("knn_k", C.c_int32), ("key_bits", C.c_int32),
+                ("curve", C.c_int32)]
+
+
+CURVES = {"hilbert": 0, "morton": 1}
 
 
 class RoiC(C.Structure):
@@ -144,6 +147,8 @@ EXPORTS = {
                                     C.POINTER(Brick), C.c_int32, C.POINTER(AdaptiveResult),
                                     C.c_void_p]),
     "sfk_debug_point_h2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sfk_debug_tree_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sfk_debug_curve_keys": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sfk_debug_support_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_void_p,

@@ -1,6 +1,7 @@
-// Tree build on the device: bounding box, Morton keys, stable LSD radix
-// sort, leaf buckets of 64 particles (float4, Morton order), a 64-ary box
-// hierarchy, and the per-particle k-th nearest neighbour bandwidth.
+// Tree build on the device: bounding box, space-filling curve keys
+// (Hilbert or Morton), stable LSD radix sort, leaf buckets of 64 particles
+// (float4, curve order), a 64-ary box hierarchy, and the per-particle k-th
+// nearest neighbour bandwidth.
 //
 // The paper builds a k-d tree on the CPU and uploads it (Section 3.2);
 // here the index is built where the particles live so only ROI descriptors
@@ -78,10 +79,10 @@ hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, fl
 }
 
 // ---------------------------------------------------------------------------
-// Morton keys
+// space-filling curve keys
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+__host__ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   v &= 0x1fffffull;
   v = (v | (v << 32)) & 0x1f00000000ffffull;
   v = (v | (v << 16)) & 0x1f0000ff0000ffull;
@@ -91,10 +92,46 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ xyz, int64_t n,
-                                                const float* __restrict__ bbox, int bits,
-                                                uint64_t* __restrict__ keys,
-                                                uint32_t* __restrict__ vals) {
+// Key of the cell (x, y, z) of a 2^bits-per-axis lattice, 3*bits bits.
+// Morton: the coordinate bits interleaved, x the most significant of each
+// triple. Hilbert: J. Skilling's transpose method (Programming the Hilbert
+// curve, AIP Conf. Proc. 707, 2004): from the top bit down, each lower bit
+// field is inverted or exchanged with x's according to the current bit, a
+// Gray-code step then makes the three words the transposed index, whose
+// bits are interleaved like Morton's. Consecutive Hilbert keys are
+// face-adjacent cells, so 64 consecutive particles span a more compact box
+// than under Morton's jumps.
+__host__ __device__ __forceinline__ uint64_t curve_key(uint32_t x, uint32_t y, uint32_t z,
+                                                       int bits, int hilbert) {
+  if (hilbert) {
+    for (uint32_t q = 1u << (bits - 1); q > 1u; q >>= 1) {
+      const uint32_t p = q - 1u;
+      if (x & q) x ^= p;
+      uint32_t t = (x ^ y) & p;
+      if (y & q) { x ^= p; t = 0u; }
+      x ^= t;
+      y ^= t;
+      t = (x ^ z) & p;
+      if (z & q) { x ^= p; t = 0u; }
+      x ^= t;
+      z ^= t;
+    }
+    y ^= x;
+    z ^= y;
+    uint32_t t = 0u;
+    for (uint32_t q = 1u << (bits - 1); q > 1u; q >>= 1)
+      if (z & q) t ^= q - 1u;
+    x ^= t;
+    y ^= t;
+    z ^= t;
+  }
+  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+__global__ __launch_bounds__(256) void k_curve_keys(const float* __restrict__ xyz, int64_t n,
+                                                    const float* __restrict__ bbox, int bits,
+                                                    int hilbert, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
   const float cells = (float)(1u << bits);
   float lo[3], sc[3];
 #pragma unroll
@@ -106,25 +143,29 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ xyz, i
   const uint32_t qmax = (1u << bits) - 1u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t key = 0;
+    uint32_t q[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float f = (xyz[3 * i + k] - lo[k]) * sc[k];
-      uint32_t q = f <= 0.0f ? 0u : (f >= (float)qmax ? qmax : (uint32_t)f);
-      key |= spread3(q) << (2 - k);
+      const float f = (xyz[3 * i + k] - lo[k]) * sc[k];
+      q[k] = f <= 0.0f ? 0u : (f >= (float)qmax ? qmax : (uint32_t)f);
     }
-    keys[i] = key;
+    keys[i] = curve_key(q[0], q[1], q[2], bits, hilbert);
     vals[i] = (uint32_t)i;
   }
 }
 
-hipError_t launch_morton(const float* xyz, int64_t n, const float* bbox, int bits,
-                         uint64_t* keys, uint32_t* vals, hipStream_t s) {
+hipError_t launch_curve_keys(const float* xyz, int64_t n, const float* bbox, int bits,
+                             int hilbert, uint64_t* keys, uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_morton, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox, bits, keys,
-                     vals);
+  hipLaunchKernelGGL(k_curve_keys, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox, bits,
+                     hilbert, keys, vals);
   return hipGetLastError();
+}
+
+void curve_keys_host(const uint32_t* cells, int64_t n, int bits, int hilbert, uint64_t* keys) {
+  for (int64_t i = 0; i < n; ++i)
+    keys[i] = curve_key(cells[3 * i], cells[3 * i + 1], cells[3 * i + 2], bits, hilbert);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,7 +503,7 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // One wavefront per leaf, one query particle per lane; each lane keeps its
 // KM smallest squared distances in a sorted register array whose last slot
 // is its current k-th smallest (the threshold). The lane's own leaf and its
-// nearest Morton neighbours come first and bound every answer from above by
+// nearest neighbours along the curve come first and bound every answer from above by
 // real distances. The box hierarchy is then walked with the wavefront's
 // largest threshold (a box farther than that cannot hold a closer
 // particle); the leaves it yields are kept in a per-wave list and visited
@@ -479,9 +520,10 @@ constexpr int kKnnSub = 8;                          // particles per sub-block
 constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
 constexpr int kKnnList = 256;                       // leaves held for ordering
 constexpr int kKnnBands = 5;                        // distance bands of the visiting order
-// Morton neighbours of the query leaf visited first, on each side: more
+// Curve neighbours of the query leaf visited first, on each side: more
 // seed candidates bound the answers of the leaf's edge lanes more tightly
-// before the walk (10M points, k = 32: 1 -> 4 per side cut the kernel by 5%)
+// before the walk (10M points, k = 32, Morton order: 1 -> 4 per side cut the
+// kernel by 5%)
 template <int KM>
 constexpr int knn_near() {
   return KM >= 32 ? 4 : KM >= 16 ? 2 : 1;
@@ -755,14 +797,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
       return no;
     };
 
-    // Phase 0 visits the leaf itself and its Morton neighbours, which bound
+    // Phase 0 visits the leaf itself and its curve neighbours, which bound
     // every lane's answer from above; tau is then the wavefront's largest
     // bound. Each later phase visits one collected chunk of the walk. One
     // visiting site keeps a single copy of the insertion code.
     for (int phase = 0;; ++phase) {
       int no;
       if (phase == 0) {
-        // the leaf, then its Morton neighbours at distance 1, 2, ... knn_near
+        // the leaf, then its curve neighbours at distance 1, 2, ... knn_near
         no = 0;
         if (lane == 0) ord[0] = leaf;
         ++no;

@@ -1,5 +1,5 @@
 // Kernels of the in-box particle set and of the MBE stages (Section 3.1):
-// the particles inside a ROI's closed box B are compacted (keeping Morton
+// the particles inside a ROI's closed box B are compacted (keeping curve
 // order) into a sub-cloud with its own leaves; Eq. 1 takes exact order
 // statistics from a radix sort of each axis; the adaptive smoothing length
 // (Eqs. 5-6) interpolates the pilot grid at every particle, averages with a

@@ -131,7 +131,7 @@ __device__ __forceinline__ float box_gap_d2(const NodeBox& b, float tlx, float t
 // test(box, node_global_index) -> bool per lane (lane = one child);
 // leaves(child_leaf_index, pass, mask) is called for each group of up to 64
 // sibling leaves, in increasing leaf order. Children are pushed in reverse
-// so the walk emits leaves in ascending (Morton) order.
+// so the walk emits leaves in ascending (curve) order.
 #define SFK_STACK 384
 template <class TestF, class LeafF>
 __device__ __forceinline__ void traverse(const TreeView& tv, int32_t* stack, TestF test,

@@ -26,7 +26,7 @@ enum PPMode : int32_t {
 
 // Read-only view of a tree passed to kernels by value.
 struct TreeView {
-  const float4* pts;     // n_leaves*64 slots, Morton order, padded with sentinels
+  const float4* pts;     // n_leaves*64 slots, curve order, padded with sentinels
   const float4* pparam;  // PP_ANISO only
   const NodeBox* nodes;  // all levels, level 0 = leaves
   const float4* node_ih; // per node: per-axis minimum inverse bandwidth (per-point modes)
@@ -128,8 +128,10 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 // build.hip
 hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, float* result,
                        hipStream_t s);
-hipError_t launch_morton(const float* xyz, int64_t n, const float* bbox, int bits,
-                         uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_curve_keys(const float* xyz, int64_t n, const float* bbox, int bits,
+                             int hilbert, uint64_t* keys, uint32_t* vals, hipStream_t s);
+// the same key function on the host: cells = n (x, y, z) triples < 2^bits
+void curve_keys_host(const uint32_t* cells, int64_t n, int bits, int hilbert, uint64_t* keys);
 size_t radix_sort_tmp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,

@@ -1462,8 +1462,12 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     set_err(c, "give either knn_k or d_h, not both");
     return SFK_E_INVAL;
   }
-  if (o.morton_bits < 0 || o.morton_bits > 21) {
-    set_err(c, "morton_bits = %d out of range [0, 21]", o.morton_bits);
+  if (o.key_bits < 0 || o.key_bits > 21) {
+    set_err(c, "key_bits = %d out of range [0, 21]", o.key_bits);
+    return SFK_E_INVAL;
+  }
+  if (o.curve != SFK_CURVE_HILBERT && o.curve != SFK_CURVE_MORTON) {
+    set_err(c, "unknown curve %d", o.curve);
     return SFK_E_INVAL;
   }
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1521,10 +1525,10 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if (bb[6] > 0.0f)
       return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
     for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
-    // Morton keys and the sort
+    // curve keys and the sort
     // automatic: about 4x finer per axis than n^(1/3), at least 10 bits
     // (10M points: 30-bit keys, four 8-bit sort passes)
-    int bits = o.morton_bits;
+    int bits = o.key_bits;
     if (bits == 0) {
       const int lg = (int)std::ceil(std::log2((double)std::max<int64_t>(n, 2)));
       bits = std::min(21, std::max(10, (lg + 2) / 3 + 2));
@@ -1538,8 +1542,8 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       return fail(st);
     int alt = 0;
     ProfScope prof(c, PK_BUILD, s);
-    if (sfk::launch_morton(d_xyz, n, res.as<float>(), bits, keys.as<uint64_t>(),
-                           vals.as<uint32_t>(), s) != hipSuccess ||
+    if (sfk::launch_curve_keys(d_xyz, n, res.as<float>(), bits, o.curve == SFK_CURVE_HILBERT,
+                               keys.as<uint64_t>(), vals.as<uint32_t>(), s) != hipSuccess ||
         sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(),
                               vals2.as<uint32_t>(), n, 3 * bits, stmp.b.p, stmp.b.bytes, s,
                               &alt) != hipSuccess ||
@@ -1953,6 +1957,37 @@ sfk_status sfk_iso_cells(sfk_ctx c, const sfk_roi* roi, const float* d_grid, dou
   *h_count = cnt;
   return SFK_OK;
   SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_tree_order(sfk_ctx c, sfk_tree t, int32_t* h_perm) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || (!h_perm && t->n > 0)) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  if (t->n > 0)
+    SFK_HIP(c, hipMemcpy(h_perm, t->perm.p, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost));
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_curve_keys(int32_t curve, int32_t bits, const uint32_t* h_cells, int64_t n,
+                                uint64_t* h_keys) {
+  SFK_GUARD_BEGIN
+  if (n < 0 || (n > 0 && (!h_cells || !h_keys)) || bits < 1 || bits > 21 ||
+      (curve != SFK_CURVE_HILBERT && curve != SFK_CURVE_MORTON)) {
+    set_err(nullptr, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (h_cells[i] >> bits) {
+      set_err(nullptr, "cell coordinate %u >= 2^%d", h_cells[i], bits);
+      return SFK_E_INVAL;
+    }
+  sfk::curve_keys_host(h_cells, n, bits, curve == SFK_CURVE_HILBERT, h_keys);
+  return SFK_OK;
+  SFK_GUARD_END(nullptr)
 }
 
 sfk_status sfk_debug_point_h2(sfk_ctx c, sfk_tree t, float* h_h2) {

@@ -137,6 +137,45 @@ def test_determinism_and_permutation(ctx, torch):
     assert np.array_equal(np.sort(perm[i2]), i1)
 
 
+@pytest.mark.parametrize("curve", ["hilbert", "morton"])
+def test_tree_order_follows_curve_keys(ctx, sfk, torch, curve):
+    # one particle at the centre of each cell of a 16^3 lattice, shuffled:
+    # with 4 key bits every particle quantises to its own cell, so the
+    # device sort must give the order of the host-side keys
+    c = 16
+    g = np.stack(np.meshgrid(np.arange(c), np.arange(c), np.arange(c), indexing="ij"),
+                 -1).reshape(-1, 3)
+    perm = np.random.default_rng(5).permutation(len(g))
+    cells = g[perm]
+    pts = ((cells + 0.5) / c).astype(np.float32)
+    tree = ctx.build_tree(dev(torch, pts), key_bits=4, curve=curve)
+    order = ctx.debug_tree_order(tree)
+    keys = sfk.curve_keys(curve, 4, cells)
+    assert np.array_equal(order, np.argsort(keys))
+    if curve == "hilbert":
+        assert np.all(np.abs(np.diff(cells[order], axis=0)).sum(1) == 1)
+    tree.close()
+
+
+def test_morton_curve_parity(ctx, sfk, torch):
+    pts = synth.clumpy_cloud(30_000, 5)
+    tree = ctx.build_tree(dev(torch, pts), knn_k=16, curve="morton")
+    h2 = ctx.debug_point_h2(tree)
+    assert np.array_equal(h2, oracle.knn_h2(pts, 16))
+    roi = Roi((0.1, 0, 0.05), (0.9, 1, 0.95), (29, 31, 26), kernel="gauss_trunc3",
+              bw="per_point")
+    check_density(ctx.eval_roi(tree, roi).cpu().numpy(), oracle.density(pts, roi, h2=h2),
+                  "morton per-point")
+    fixed = Roi((0, 0, 0), (1, 1, 1), (30, 30, 30), bw="fixed", h=(0.04, 0.04, 0.04))
+    check_density(ctx.eval_roi(tree, fixed).cpu().numpy(), oracle.density(pts, fixed),
+                  "morton fixed")
+    tree.close()
+    for kw in (dict(curve=2), dict(key_bits=22), dict(key_bits=-1)):
+        with pytest.raises(sfk.SfkError) as e:
+            ctx.build_tree(dev(torch, pts[:1000]), **kw)
+        assert e.value.status == 1, kw
+
+
 # ---------------------------------------------------------------------------
 # chunk splitting and the in-kernel tree walk (lists that do not fit)
 # ---------------------------------------------------------------------------
