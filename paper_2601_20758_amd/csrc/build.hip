@@ -128,9 +128,10 @@ __host__ __device__ __forceinline__ uint64_t curve_key(uint32_t x, uint32_t y, u
   return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
 }
 
+template <typename K>
 __global__ __launch_bounds__(256) void k_curve_keys(const float* __restrict__ xyz, int64_t n,
                                                     const float* __restrict__ bbox, int bits,
-                                                    int hilbert, uint64_t* __restrict__ keys,
+                                                    int hilbert, K* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
   const float cells = (float)(1u << bits);
   float lo[3], sc[3];
@@ -149,17 +150,21 @@ __global__ __launch_bounds__(256) void k_curve_keys(const float* __restrict__ xy
       const float f = (xyz[3 * i + k] - lo[k]) * sc[k];
       q[k] = f <= 0.0f ? 0u : (f >= (float)qmax ? qmax : (uint32_t)f);
     }
-    keys[i] = curve_key(q[0], q[1], q[2], bits, hilbert);
+    keys[i] = (K)curve_key(q[0], q[1], q[2], bits, hilbert);
     vals[i] = (uint32_t)i;
   }
 }
 
 hipError_t launch_curve_keys(const float* xyz, int64_t n, const float* bbox, int bits,
-                             int hilbert, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+                             int hilbert, void* keys, uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_curve_keys, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox, bits,
-                     hilbert, keys, vals);
+  if (3 * bits <= 32)
+    hipLaunchKernelGGL(k_curve_keys<uint32_t>, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox,
+                       bits, hilbert, (uint32_t*)keys, vals);
+  else
+    hipLaunchKernelGGL(k_curve_keys<uint64_t>, dim3((unsigned)nb), dim3(256), 0, s, xyz, n, bbox,
+                       bits, hilbert, (uint64_t*)keys, vals);
   return hipGetLastError();
 }
 
@@ -169,7 +174,7 @@ void curve_keys_host(const uint32_t* cells, int64_t n, int bits, int hilbert, ui
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
+// stable LSD radix sort of (u32 or u64 key, u32 value) pairs, 8-bit digits.
 // Per pass: block digit histograms (digit-major) -> exclusive scan ->
 // scatter. The scatter ranks equal digits inside a wavefront with eight
 // ballots (one per digit bit); each wavefront owns a contiguous quarter of
@@ -182,7 +187,8 @@ static constexpr int kRsNT = 256;
 static constexpr int kRsItems = 16;
 static constexpr int kRsTile = kRsNT * kRsItems;
 
-__global__ __launch_bounds__(kRsNT) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
+template <typename K>
+__global__ __launch_bounds__(kRsNT) void k_rs_hist(const K* __restrict__ keys, int64_t n,
                                                    int shift, uint32_t* __restrict__ hist,
                                                    int nblk) {
   __shared__ uint32_t h[256];
@@ -198,9 +204,10 @@ __global__ __launch_bounds__(kRsNT) void k_rs_hist(const uint64_t* __restrict__ 
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict__ kin,
+template <typename K>
+__global__ __launch_bounds__(kRsNT) void k_rs_scatter(const K* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin,
-                                                      uint64_t* __restrict__ kout,
+                                                      K* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int64_t n,
                                                       int shift,
                                                       const uint32_t* __restrict__ hist,
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict
   // tile is written out in that order, so the elements of one digit go to
   // consecutive global positions.
   constexpr int kPerWave = kRsTile / 4;
-  __shared__ uint64_t stage_k[kRsTile];
+  __shared__ K stage_k[kRsTile];
   __shared__ uint32_t stage_v[kRsTile];
   __shared__ uint32_t wslot[4][256];  // counts, then next local slot per (wavefront, digit)
   __shared__ uint32_t lstart[256];    // first local slot of each digit
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict
   for (int r = 0; r < kPerWave / 64; ++r) {
     const int li = w0 + r * 64 + lane;
     const bool valid = li < tile_n;
-    const uint64_t key = valid ? kin[base + li] : 0ull;
+    const K key = valid ? kin[base + li] : (K)0;
     const uint32_t val = valid ? vin[base + li] : 0u;
     const uint32_t dig = (uint32_t)(key >> shift) & 255u;
     uint64_t mask = ballot(valid);
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(kRsNT) void k_rs_scatter(const uint64_t* __restrict
   }
   __syncthreads();
   for (int i = tid; i < tile_n; i += kRsNT) {
-    const uint64_t key = stage_k[i];
+    const K key = stage_k[i];
     const uint32_t dig = (uint32_t)(key >> shift) & 255u;
     kout[gbase[dig] + ((uint32_t)i - lstart[dig])] = key;
     vout[gbase[dig] + ((uint32_t)i - lstart[dig])] = stage_v[i];
@@ -291,9 +298,10 @@ size_t radix_sort_tmp_bytes(int64_t n) {
   return (size_t)nh * 2 * sizeof(uint32_t) + scan_tmp_bytes(nh) + 1024;
 }
 
-hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
-                            uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
-                            size_t tmp_bytes, hipStream_t s, int* result_in_alt) {
+template <typename K>
+static hipError_t radix_sort_impl(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt,
+                                  int64_t n, int key_bits, void* tmp, size_t tmp_bytes,
+                                  hipStream_t s, int* result_in_alt) {
   *result_in_alt = 0;
   if (n <= 1) return hipSuccess;
   const int64_t nblk = (n + kRsTile - 1) / kRsTile;
@@ -303,22 +311,37 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   uint32_t* offs = hist + nh;
   void* stmp = (void*)(offs + nh);
   const size_t stmp_bytes = tmp_bytes - (size_t)nh * 2 * sizeof(uint32_t);
-  uint64_t *ka = keys, *kb = keys_alt;
+  K *ka = keys, *kb = keys_alt;
   uint32_t *va = vals, *vb = vals_alt;
   const int passes = (key_bits + 7) / 8;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, n, shift, hist,
+    hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, n, shift, hist,
                        (int)nblk);
     hipError_t e = scan_exclusive_u32(hist, offs, nh, stmp, stmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, va, kb, vb, n,
-                       shift, hist, offs, (int)nblk);
+    hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(kRsNT), 0, s, ka, va, kb, vb,
+                       n, shift, hist, offs, (int)nblk);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   *result_in_alt = (passes & 1) ? 1 : 0;
   return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                            size_t tmp_bytes, hipStream_t s, int* result_in_alt) {
+  return radix_sort_impl(keys, vals, keys_alt, vals_alt, n, key_bits, tmp, tmp_bytes, s,
+                         result_in_alt);
+}
+
+hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                                uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                                size_t tmp_bytes, hipStream_t s, int* result_in_alt) {
+  if (key_bits > 32) return hipErrorInvalidValue;
+  return radix_sort_impl(keys, vals, keys_alt, vals_alt, n, key_bits, tmp, tmp_bytes, s,
+                         result_in_alt);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,6 +541,8 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 
 constexpr int kKnnSub = 8;                          // particles per sub-block
 constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
+constexpr int kKnnBoxFloats = 8 * kKnnSubPerLeaf;   // a leaf's sub-block boxes, <= 64
+static_assert(kKnnBoxFloats <= 64, "a leaf's sub-block boxes are loaded one float per lane");
 constexpr int kKnnList = 256;                       // leaves held for ordering
 constexpr int kKnnBands = 5;                        // distance bands of the visiting order
 // Curve neighbours of the query leaf visited first, on each side: more
@@ -643,7 +668,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
     // lane's next marked particle, until no lane has one left.
     auto process = [&](int cl, const float4 pc, const float sbv) {
       lp[lane] = pc;
-      reinterpret_cast<float*>(lsb)[lane] = sbv;
+      if (lane < kKnnBoxFloats) reinterpret_cast<float*>(lsb)[lane] = sbv;
       wave_sync();
       const float tnow = wave_max_nonneg(real ? thr : 0.0f);
       bool cpass = false;
@@ -697,7 +722,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
       if (count <= 0) return;
       int cl = __builtin_amdgcn_readfirstlane(ord[0]);
       float4 pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
-      float sn = sub_box[(int64_t)cl * (8 * kKnnSubPerLeaf) + lane];
+      float sn = lane < kKnnBoxFloats ? sub_box[(int64_t)cl * kKnnBoxFloats + lane] : 0.0f;
       for (int i = 0; i < count; ++i) {
         const int cur = cl;
         const float4 pc = pn;
@@ -705,7 +730,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
         if (i + 1 < count) {
           cl = __builtin_amdgcn_readfirstlane(ord[i + 1]);
           pn = tv.pts[(int64_t)cl * SFK_LEAF + lane];
-          sn = sub_box[(int64_t)cl * (8 * kKnnSubPerLeaf) + lane];
+          sn = lane < kKnnBoxFloats ? sub_box[(int64_t)cl * kKnnBoxFloats + lane] : 0.0f;
         }
         process(cur, pc, sc);
       }

@@ -128,14 +128,19 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 // build.hip
 hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, float* result,
                        hipStream_t s);
+// keys: uint32_t[n] when 3*bits <= 32, else uint64_t[n]
 hipError_t launch_curve_keys(const float* xyz, int64_t n, const float* bbox, int bits,
-                             int hilbert, uint64_t* keys, uint32_t* vals, hipStream_t s);
+                             int hilbert, void* keys, uint32_t* vals, hipStream_t s);
 // the same key function on the host: cells = n (x, y, z) triples < 2^bits
 void curve_keys_host(const uint32_t* cells, int64_t n, int bits, int hilbert, uint64_t* keys);
 size_t radix_sort_tmp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
                             size_t tmp_bytes, hipStream_t s, int* result_in_alt);
+// the same with 32-bit keys (key_bits <= 32)
+hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                                uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                                size_t tmp_bytes, hipStream_t s, int* result_in_alt);
 hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
                          float4* pts, int32_t* perm_out, hipStream_t s);
 hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,

@@ -1542,11 +1542,16 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       return fail(st);
     int alt = 0;
     ProfScope prof(c, PK_BUILD, s);
+    // keys of at most 32 bits are sorted as uint32 (a third less traffic per pass)
+    const bool narrow = 3 * bits <= 32;
     if (sfk::launch_curve_keys(d_xyz, n, res.as<float>(), bits, o.curve == SFK_CURVE_HILBERT,
-                               keys.as<uint64_t>(), vals.as<uint32_t>(), s) != hipSuccess ||
-        sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(),
-                              vals2.as<uint32_t>(), n, 3 * bits, stmp.b.p, stmp.b.bytes, s,
-                              &alt) != hipSuccess ||
+                               keys.b.p, vals.as<uint32_t>(), s) != hipSuccess ||
+        (narrow ? sfk::radix_sort_pairs_u32(keys.as<uint32_t>(), vals.as<uint32_t>(),
+                                            keys2.as<uint32_t>(), vals2.as<uint32_t>(), n,
+                                            3 * bits, stmp.b.p, stmp.b.bytes, s, &alt)
+                : sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(),
+                                        keys2.as<uint64_t>(), vals2.as<uint32_t>(), n, 3 * bits,
+                                        stmp.b.p, stmp.b.bytes, s, &alt)) != hipSuccess ||
         sfk::launch_gather(d_xyz, alt ? vals2.as<uint32_t>() : vals.as<uint32_t>(), n, n_slots,
                            (float4*)t->pts.p, (int32_t*)t->perm.p, s) != hipSuccess)
       return fail((set_err(c, "sort / gather failed"), SFK_E_DEVICE));
