@@ -220,7 +220,9 @@ def test_knn_h2_bit_exact_and_lattice(ctx, torch):
     h2 = ctx.debug_point_h2(tree)
     assert h2[4 + 9 * (4 + 9 * 4)] == np.float32(0.015625)
     assert np.array_equal(h2, oracle.knn_h2(lat, 32))
-    for k in (1, 7, 64):
+    # k = 8, 16 (below), 32 and 64 fill the query leaf by sorting networks,
+    # k = 1 and 7 by insertion
+    for k in (1, 7, 8, 64):
         tree = ctx.build_tree(dev(torch, pts[:5000]), knn_k=k)
         assert np.array_equal(ctx.debug_point_h2(tree), oracle.knn_h2(pts[:5000], k)), k
 
