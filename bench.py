@@ -5,7 +5,7 @@ Default workload (the configuration the headline metric is quoted on):
 power-law masses plus 20% uniform background), ROI = unit box, 128^3 grid,
 Gaussian kernel truncated at 3h, per-point h from the 32nd nearest
 neighbour. One step = the whole hot path from points resident in HBM to the
-density grid: tree build (bounding box, Morton sort, leaves, box hierarchy),
+density grid: tree build (bounding box, Hilbert-curve sort, leaves, box hierarchy),
 k-NN bandwidths, tile range query and evaluation.
 
 Prints one JSON line (rank 0): value = useful kernel evaluations (node,
