@@ -157,6 +157,37 @@ def test_tree_order_follows_curve_keys(ctx, sfk, torch, curve):
     tree.close()
 
 
+def quantise_like_device(pts, bbox, bits):
+    """The build's float32 cell of every particle: (x - lo) * (2^bits / extent),
+    each operation rounded to float32, truncated and clamped to the lattice."""
+    lo = np.array(bbox[:3], dtype=np.float32)
+    ext = np.array(bbox[3:], dtype=np.float32) - lo
+    cells = np.float32(1 << bits)
+    sc = np.where(ext > 0, cells / np.where(ext > 0, ext, np.float32(1)), np.float32(0))
+    f = (pts.astype(np.float32) - lo) * sc.astype(np.float32)
+    qmax = (1 << bits) - 1
+    q = np.where(f <= 0, 0, np.where(f >= np.float32(qmax), qmax,
+                                     np.floor(np.maximum(f, 0)).astype(np.int64)))
+    return q.astype(np.uint32)
+
+
+@pytest.mark.parametrize("curve", ["hilbert", "morton"])
+def test_tree_order_exact_at_every_key_width(ctx, sfk, torch, curve):
+    # ragged cloud (not a multiple of the sort tile); 1 bit per axis gives
+    # 8 cells and massive ties (stable: input order), 21 bits 63-bit keys
+    # (eight passes, the 64-bit path), the automatic width 10 bits (four
+    # passes, the 32-bit path)
+    pts = synth.clumpy_cloud(50_003, 31)
+    for bits in (1, 0, 21):
+        tree = ctx.build_tree(dev(torch, pts), key_bits=bits, curve=curve)
+        n, bbox, _ = tree.info()
+        b = bits or 10
+        keys = sfk.curve_keys(curve, b, quantise_like_device(pts, bbox, b))
+        order = ctx.debug_tree_order(tree)
+        assert np.array_equal(order, np.argsort(keys, kind="stable")), (curve, bits)
+        tree.close()
+
+
 def test_morton_curve_parity(ctx, sfk, torch):
     pts = synth.clumpy_cloud(30_000, 5)
     tree = ctx.build_tree(dev(torch, pts), knn_k=16, curve="morton")
