@@ -116,6 +116,8 @@ def parse():
                    help="run a 1 GiB fill and a 1 GiB elementwise scale first "
                         "(references for the hardware byte counters)")
     p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--no-zoom", action="store_true",
+                   help="skip the nested-zoom and MBE sections on the 100M cloud")
     p.add_argument("--no-view", action="store_true",
                    help="skip the view-cache comparison on the 100M cloud")
     return p.parse_args()
@@ -328,6 +330,95 @@ def view_cache(ctx, tree, torch, label, info, n_frames=180):
     }
 
 
+def nested_zoom(ctx, tree, torch, label, info):
+    """Nested zoom: boxes of side 2^-i (i = 0..10) around one of the ten most
+    massive clumps, each at 64^3, 128^3 and 256^3, Epanechnikov, h = 0.01 x
+    side, one ROI per launch on the resident tree. Per ROI: the launch's time
+    from HIP events on its stream and its useful evaluations (untimed count)."""
+    import synth
+    rois = synth.nested_zoom_rois(info, seed=3)
+    stream = torch.cuda.current_stream()
+    outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    for r, o in zip(rois, outs):
+        ctx.eval_roi(tree, r, out=o, stream=stream)
+    torch.cuda.synchronize()
+    ms = []
+    for r, o in zip(rois, outs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = None
+        for _ in range(3):
+            e0.record(stream)
+            ctx.eval_roi(tree, r, out=o, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        ms.append(best)
+    useful = [ctx.debug_eval_count(tree, r)[0] for r in rois]
+    per_res = {}
+    for res in (64, 128, 256):
+        idx = [i for i, r in enumerate(rois) if r.res[0] == res]
+        t = sum(ms[i] for i in idx)
+        u = sum(useful[i] for i in idx)
+        per_res["%d^3" % res] = {
+            "rois": len(idx), "total_ms": t, "useful_evals": u,
+            "evals_per_s": u / (t * 1e-3),
+            "frac_of_valu_ceiling": u / (t * 1e-3) * SLOTS_PER_EVAL["epanechnikov"]
+                                    / VALU_SLOTS_PER_S,
+            "ms_by_side": [round(ms[i], 4) for i in idx]}
+    return {"workload": "11 nested boxes (side 1 to 1/1024) around a top-10 clump of the "
+                        "resident %s cloud, each at 64^3, 128^3, 256^3; Epanechnikov, "
+                        "h = 0.01 x side; one ROI per launch" % label,
+            "per_resolution": per_res}
+
+
+def mbe_rois(ctx, tree, torch, label, info):
+    """The paper's adaptive estimator (Eqs. 1-8, particles inside the box
+    only) on boxes around the most massive clump of the resident cloud.
+    Wall time per ROI (the path reads back Eq. 1's lengths, so it
+    synchronises), the evaluation phases from the library's own events, and
+    the useful evaluations of the pilot (the Eq. 1 ellipsoid over the
+    particles in the box) and of the final grid, counted untimed."""
+    import synth
+    c = info.centres[int(np.argmax(info.masses))]
+    recs = []
+    for side in (0.02, 0.05, 0.1):
+        lo, hi = synth.clouds._clamped_box(c, side)
+        for res in (64, 128):
+            roi = synth.Roi(lo, hi, (res, res, res), kernel="epanechnikov", bw="mbe",
+                            set="in_roi")
+            out = torch.empty(roi.n_nodes, device="cuda")
+            ctx.eval_roi(tree, roi, out=out)
+            torch.cuda.synchronize()
+            ctx.profile_read(reset=True)
+            walls = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                ctx.eval_roi(tree, roi, out=out)
+                torch.cuda.synchronize()
+                walls.append((time.perf_counter() - t0) * 1e3)
+            prof = ctx.profile_read(reset=True)
+            d = ctx.debug_mbe(tree, roi, per_particle=False)
+            ell0 = [float(v) for v in d["ell0"]]
+            pilot_roi = synth.Roi(lo, hi, (res, res, res), kernel="epanechnikov", bw="fixed",
+                                  set="in_roi", h=tuple(ell0))
+            u_pilot = ctx.debug_eval_count(tree, pilot_roi)[0]
+            u_final = ctx.debug_eval_count(tree, roi)[0]
+            wall = float(np.median(walls))
+            n_ev = max(1, prof["eval_launches"])
+            recs.append({
+                "side": side, "res": res, "n_b": int(d["n_b"]), "wall_ms": wall,
+                "eval_kernels_ms": prof["eval_ms"] * 2 / n_ev,
+                "range_query_ms": (prof["tile_count_ms"] + prof["plan_ms"]
+                                   + prof["tile_fill_ms"]) * 2 / n_ev,
+                "useful_evals_pilot": u_pilot, "useful_evals_final": u_final,
+                "evals_per_s": (u_pilot + u_final) / (wall * 1e-3),
+                "particles_in_box_per_s": d["n_b"] / (wall * 1e-3)})
+    return {"workload": "MBE (Eqs. 1-8, set = particles in B) on boxes of side 0.02, 0.05, "
+                        "0.1 around the most massive clump of the resident %s cloud, 64^3 "
+                        "and 128^3" % label, "rois": recs}
+
+
 def adaptive(ctx, tree, torch, label):
     """Adaptive resolution vs a uniform fine grid over the whole cloud: a 64^3
     base grid refined twice (bricks of 8 cells, threshold 0.2 of the peak)
@@ -477,7 +568,8 @@ def main():
     tree.close()
     del xyz, out
     torch.cuda.empty_cache()
-    if args.workload == "per_point_10m" and not (args.no_batch and args.no_view):
+    if args.workload == "per_point_10m" and not (args.no_batch and args.no_view
+                                                 and args.no_zoom):
         def on_100m(t, lab, info):
             rec = {}
             if not args.no_batch:
@@ -485,6 +577,10 @@ def main():
             if not args.no_view:
                 rec["view_cache"] = view_cache(ctx, t, torch, lab, info)
                 rec["adaptive_resolution"] = adaptive(ctx, t, torch, lab)
+            if not args.no_zoom:
+                rec["nested_zoom"] = nested_zoom(ctx, t, torch, lab, info)
+                ctx.profile_enable(True)
+                rec["mbe"] = mbe_rois(ctx, t, torch, lab, info)
             return rec
         rec = large_section(ctx, torch, args.batch_points, 3, on_100m)
         if "error" in rec:

@@ -395,28 +395,36 @@ class Context:
                                                        out.data_ptr(), _stream_ptr(stream)))
         return out
 
-    def debug_mbe(self, tree: "Tree", roi, out=None, cap_b: Optional[int] = None):
+    def debug_mbe(self, tree: "Tree", roi, out=None, cap_b: Optional[int] = None,
+                  per_particle: bool = True):
         """MBE stages of one ROI: dict of ell0, n_b, idx_b, pilot, pden,
-        aveden, ell_j and the final grid (device tensor)."""
+        aveden, ell_j and the final grid (device tensor). per_particle=False
+        returns ell0, n_b, pilot, aveden and the grid only (no per-particle
+        host arrays)."""
         out = self._out_for(roi, out)
         n = tree.info()[0]
-        cap = n if cap_b is None else cap_b
+        cap = (n if cap_b is None else cap_b) if per_particle else 0
         m = out.numel()
         ell0 = np.zeros(3, dtype=np.float32)
         nb = C.c_int64()
-        idx = np.zeros(max(cap, 1), dtype=np.int64)
         pilot = np.zeros(m, dtype=np.float32)
-        pden = np.zeros(max(cap, 1), dtype=np.float32)
         ave = C.c_double()
-        ellj = np.zeros((max(cap, 1), 3), dtype=np.float32)
+        if per_particle:
+            idx = np.zeros(max(cap, 1), dtype=np.int64)
+            pden = np.zeros(max(cap, 1), dtype=np.float32)
+            ellj = np.zeros((max(cap, 1), 3), dtype=np.float32)
+            ptrs = (idx.ctypes.data, pden.ctypes.data, ellj.ctypes.data)
+        else:
+            ptrs = (None, None, None)
         r = roi_struct(roi, out.data_ptr())
         self._check(self._lib.sfk_debug_mbe(self._h, tree._h, C.byref(r), ell0.ctypes.data,
-                                            C.byref(nb), idx.ctypes.data, pilot.ctypes.data,
-                                            pden.ctypes.data, C.byref(ave), ellj.ctypes.data,
-                                            cap))
+                                            C.byref(nb), ptrs[0], pilot.ctypes.data, ptrs[1],
+                                            C.byref(ave), ptrs[2], cap))
         k = nb.value
-        return {"ell0": ell0, "n_b": k, "idx_b": idx[:k], "pilot": pilot, "pden": pden[:k],
-                "aveden": ave.value, "ell_j": ellj[:k], "final": out}
+        res = {"ell0": ell0, "n_b": k, "pilot": pilot, "aveden": ave.value, "final": out}
+        if per_particle:
+            res.update(idx_b=idx[:k], pden=pden[:k], ell_j=ellj[:k])
+        return res
 
 
 class View:
