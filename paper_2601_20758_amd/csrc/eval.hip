@@ -84,9 +84,23 @@ __device__ __forceinline__ bool tile_box_test(const TreeView& tv, const RoiDev& 
 // ROI coordinate tables: x_i = lo + (i*(hi-lo))/(res-1) in double.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_roi_coords(const BatchHdr* __restrict__ hdr,
+__device__ __forceinline__ double node_coord(const RoiDev& R, int k, int i) {
+  const double lo = R.lo[k], hi = R.hi[k];
+  const double num = __dmul_rn((double)i, __dsub_rn(hi, lo));
+  return __dadd_rn(lo, __ddiv_rn(num, (double)(R.res[k] - 1)));
+}
+
+__device__ void roi_list_walk(const TreeView& tv, int r, const RoiDev& R, int32_t* stack,
+                              int32_t* __restrict__ roi_leaves, int32_t* __restrict__ roi_nl);
+
+// One block per ROI: the coordinate table, then (first wavefront) the ROI's
+// leaf list, described below.
+__global__ __launch_bounds__(256) void k_roi_coords(TreeView tv, const BatchHdr* __restrict__ hdr,
                                                     const RoiDev* __restrict__ rois,
-                                                    double* __restrict__ coords) {
+                                                    double* __restrict__ coords,
+                                                    int32_t* __restrict__ roi_leaves,
+                                                    int32_t* __restrict__ roi_nl) {
+  __shared__ int32_t lds_stack[SFK_STACK];
   if ((int)blockIdx.x >= hdr->n_rois) return;
   const RoiDev& R = rois[blockIdx.x];
   const int tot = R.res[0] + R.res[1] + R.res[2];
@@ -100,18 +114,84 @@ __global__ __launch_bounds__(256) void k_roi_coords(const BatchHdr* __restrict__
         k = 2;
       }
     }
-    const double lo = R.lo[k], hi = R.hi[k];
-    const double num = __dmul_rn((double)i, __dsub_rn(hi, lo));
-    const double v = __dadd_rn(lo, __ddiv_rn(num, (double)(R.res[k] - 1)));
-    coords[R.coord_off + q] = v;
+    coords[R.coord_off + q] = node_coord(R, k, i);
   }
+  if (threadIdx.x < 64) roi_list_walk(tv, (int)blockIdx.x, R, lds_stack, roi_leaves, roi_nl);
 }
 
-hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
-                             double* coords, hipStream_t s) {
+hipError_t launch_roi_coords(TreeView tv, const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
+                             double* coords, int32_t* roi_leaves, int32_t* roi_nl,
+                             hipStream_t s) {
   if (grid_rois <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_roi_coords, dim3(grid_rois), dim3(256), 0, s, hdr, rois, coords);
+  hipLaunchKernelGGL(k_roi_coords, dim3(grid_rois), dim3(256), 0, s, tv, hdr, rois, coords,
+                     roi_leaves, roi_nl);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ROI leaf lists: one wavefront per ROI walks the hierarchy once with the
+// box of all the ROI's nodes and keeps the passing leaves, ascending, when
+// there are at most kRoiListCap of them (else the count is -1 and every tile
+// walks). A tile's box lies inside the ROI's and the test is monotone in the
+// box (rounded subtractions, products with non-negative inverse bandwidths
+// and sums are monotone), so every leaf a tile's walk yields is in the list;
+// a tile then tests the list's leaves directly and yields the same leaves in
+// the same order, without descending from the root.
+// ---------------------------------------------------------------------------
+
+// The box of the first and last nodes, computed as the coordinate table
+// computes them.
+__device__ void roi_list_walk(const TreeView& tv, int r, const RoiDev& R, int32_t* stack,
+                              int32_t* __restrict__ roi_leaves, int32_t* __restrict__ roi_nl) {
+  const int lane = lane_id();
+  TileGeo g;
+  g.r = r;
+  g.i0 = g.j0 = g.k0 = 0;
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = node_coord(R, k, 0);
+    g.hi[k] = node_coord(R, k, R.res[k] - 1);
+  }
+  int32_t* out = roi_leaves + (int64_t)r * kRoiListCap;
+  int cnt = 0;
+  traverse_until(
+      tv, stack,
+      [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+      [&](int child, bool pass, uint64_t mask) {
+        const int pos = cnt + popc64(mask & lanemask_lt());
+        if (pass && pos < kRoiListCap) out[pos] = child;
+        cnt += popc64(mask);
+        return cnt <= kRoiListCap;
+      });
+  if (lane == 0) roi_nl[r] = cnt <= kRoiListCap ? cnt : -1;
+}
+
+// A tile's candidate leaves: from its ROI's list when there is one, else by
+// a walk from the root. leaves(child, pass, mask) per group of up to 64, in
+// ascending leaf order either way.
+template <int TX, int TY, int TZ, class LeafF>
+__device__ __forceinline__ void tile_leaves(const TreeView& tv, int32_t* stack, const RoiDev& R,
+                                            const TileGeo& g,
+                                            const int32_t* __restrict__ roi_leaves,
+                                            const int32_t* __restrict__ roi_nl, LeafF leaves) {
+  const int nl = roi_nl[g.r];
+  if (nl >= 0) {
+    const int32_t* list = roi_leaves + (int64_t)g.r * kRoiListCap;
+    for (int i0 = 0; i0 < nl; i0 += 64) {
+      const int i = i0 + lane_id();
+      int child = 0;
+      bool pass = false;
+      if (i < nl) {
+        child = list[i];
+        const int gi = tv.level_off[0] + child;
+        pass = tile_box_test(tv, R, g, tv.nodes[gi], gi);
+      }
+      leaves(child, pass, ballot(pass));
+    }
+    return;
+  }
+  traverse(
+      tv, stack, [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+      leaves);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,6 +202,8 @@ template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr* __restrict__ hdr,
                                                     const RoiDev* __restrict__ rois,
                                                     const double* __restrict__ coords,
+                                                    const int32_t* __restrict__ roi_leaves,
+                                                    const int32_t* __restrict__ roi_nl,
                                                     int32_t* __restrict__ tile_cnt,
                                                     int32_t* __restrict__ tile_done) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
@@ -132,14 +214,12 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
     int cnt = 0;
-    traverse(
-        tv, lds_stack[wave],
-        [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
-        [&](int child, bool pass, uint64_t mask) {
-          (void)child;
-          (void)pass;
-          cnt += popc64(mask);
-        });
+    tile_leaves<TX, TY, TZ>(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
+                            [&](int child, bool pass, uint64_t mask) {
+                              (void)child;
+                              (void)pass;
+                              cnt += popc64(mask);
+                            });
     if (lane == 0) {
       tile_cnt[t] = cnt;
       tile_done[t] = 0;
@@ -160,7 +240,8 @@ static constexpr int kModeWalkChunk = 2;
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_fill(
     TreeView tv, const BatchHdr* __restrict__ hdr, const RoiDev* __restrict__ rois,
-    const double* __restrict__ coords, const int32_t* __restrict__ tile_cnt,
+    const double* __restrict__ coords, const int32_t* __restrict__ roi_leaves,
+    const int32_t* __restrict__ roi_nl, const int32_t* __restrict__ tile_cnt,
     const int32_t* __restrict__ tile_fit, const int64_t* __restrict__ leaf_off,
     const int64_t* __restrict__ chunk_off, int32_t* __restrict__ leaves,
     int32_t* __restrict__ item_tile) {
@@ -176,13 +257,11 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     const RoiDev& R = rois[g.r];
     int32_t* out = leaves + leaf_off[t];
     int cnt = 0;
-    traverse(
-        tv, lds_stack[wave],
-        [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
-        [&](int child, bool pass, uint64_t mask) {
-          if (pass) out[cnt + popc64(mask & lanemask_lt())] = child;
-          cnt += popc64(mask);
-        });
+    tile_leaves<TX, TY, TZ>(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
+                            [&](int child, bool pass, uint64_t mask) {
+                              if (pass) out[cnt + popc64(mask & lanemask_lt())] = child;
+                              cnt += popc64(mask);
+                            });
   }
 }
 
@@ -909,12 +988,13 @@ static int grid_for(int64_t waves) {
 int tile_grid_blocks(int64_t n_tiles) { return grid_for(n_tiles); }
 
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
-                             const double* coords, TileShape ts, int grid_blocks,
+                             const double* coords, const int32_t* roi_leaves,
+                             const int32_t* roi_nl, TileShape ts, int grid_blocks,
                              int32_t* tile_cnt, int32_t* tile_done, hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                      \
   hipLaunchKernelGGL((k_tile_count<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
-                     coords, tile_cnt, tile_done)
+                     coords, roi_leaves, roi_nl, tile_cnt, tile_done)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();
@@ -989,14 +1069,16 @@ hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, 
 }
 
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
-                            const double* coords, TileShape ts, int grid_blocks,
+                            const double* coords, const int32_t* roi_leaves,
+                            const int32_t* roi_nl, TileShape ts, int grid_blocks,
                             const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
                             int32_t* item_tile, hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                     \
   hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
-                     coords, tile_cnt, tile_fit, leaf_off, chunk_off, leaves, item_tile)
+                     coords, roi_leaves, roi_nl, tile_cnt, tile_fit, leaf_off, chunk_off,  \
+                     leaves, item_tile)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();

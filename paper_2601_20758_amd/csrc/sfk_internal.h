@@ -81,6 +81,9 @@ struct alignas(16) BatchHdr {
 constexpr int kClaimSlices = 64;
 constexpr int kClaimStride = 32;
 constexpr size_t kClaimBytes = sizeof(int32_t) * kClaimSlices * kClaimStride;
+// Leaves held per ROI list (the leaves that can reach any of the ROI's
+// nodes); a ROI with more walks the hierarchy per tile instead.
+constexpr int kRoiListCap = 256;
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
 struct TileShape { int tx, ty, tz; };
@@ -161,10 +164,15 @@ hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hip
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
 // eval.hip (every kernel reads the batch sizes from the device header)
-hipError_t launch_roi_coords(const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
-                             double* coords, hipStream_t s);
+// the coordinate tables and the ROI leaf lists (one block per ROI);
+// roi_leaves: kRoiListCap int32 per ROI; roi_nl: one int32 per ROI (list
+// length, or -1 when the ROI reaches more leaves than a list holds)
+hipError_t launch_roi_coords(TreeView tv, const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
+                             double* coords, int32_t* roi_leaves, int32_t* roi_nl,
+                             hipStream_t s);
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
-                             const double* coords, TileShape ts, int grid_blocks,
+                             const double* coords, const int32_t* roi_leaves,
+                             const int32_t* roi_nl, TileShape ts, int grid_blocks,
                              int32_t* tile_cnt, int32_t* tile_done, hipStream_t s);
 // plan_tmp: 3 int64 per block of plan_blocks(max_tiles); max_tiles bounds
 // the header's tile count (the grid of a captured graph uses the capacity)
@@ -173,7 +181,8 @@ hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, 
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
                        int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s);
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
-                            const double* coords, TileShape ts, int grid_blocks,
+                            const double* coords, const int32_t* roi_leaves,
+                            const int32_t* roi_nl, TileShape ts, int grid_blocks,
                             const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
                             int32_t* item_tile, hipStream_t s);

@@ -55,7 +55,7 @@ struct DevBuf {
 struct Workspace {
   // hdr_rois = [BatchHdr][RoiDev x capacity]: staged by one host-to-device copy
   DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
-      item_tile, partials, claims, plan_tmp;
+      item_tile, partials, claims, plan_tmp, roi_leaves, roi_nl;
   uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
@@ -607,6 +607,9 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                      "ROI descriptors"));
   SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)nc, "node coordinates"));
   SFK_TRY(ws_reserve(c, ws, ws.claims, kClaimBytes, "work-claim counters"));
+  SFK_TRY(ws_reserve(c, ws, ws.roi_leaves, sizeof(int32_t) * kRoiListCap * (size_t)nr,
+                     "ROI leaf lists"));
+  SFK_TRY(ws_reserve(c, ws, ws.roi_nl, sizeof(int32_t) * (size_t)nr, "ROI list lengths"));
   SFK_TRY(ws_reserve(c, ws, ws.plan_tmp, 3 * sizeof(int64_t) * (size_t)sfk::plan_blocks(tiles),
                      "plan block sums"));
   Caps k;
@@ -621,7 +624,9 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   k.partial_cap = c->opts.list_capacity > 0
                       ? partial_cap
                       : (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T));
-  k.rois_cap = (int64_t)((ws.hdr_rois.bytes - sizeof(BatchHdr)) / sizeof(RoiDev));
+  k.rois_cap = std::min<int64_t>({(int64_t)((ws.hdr_rois.bytes - sizeof(BatchHdr)) / sizeof(RoiDev)),
+                                  (int64_t)(ws.roi_leaves.bytes / (sizeof(int32_t) * kRoiListCap)),
+                                  (int64_t)(ws.roi_nl.bytes / sizeof(int32_t))});
   k.coords_cap = (int64_t)(ws.coords.bytes / sizeof(double));
   // work items: one per tile plus one per partial slot (a split tile has one
   // item per chunk and one partial slot per chunk, whether it evaluates its
@@ -661,10 +666,13 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   int64_t* leaf_off = (int64_t*)ws.leaf_off.p;
   int64_t* partial_off = (int64_t*)ws.partial_off.p;
   int64_t* chunk_off = (int64_t*)ws.chunk_off.p;
-  SFK_HIP(c, sfk::launch_roi_coords(hdr, rois, roi_grid, coords, s));
+  int32_t* roi_leaves = (int32_t*)ws.roi_leaves.p;
+  int32_t* roi_nl = (int32_t*)ws.roi_nl.p;
+  SFK_HIP(c, sfk::launch_roi_coords(tv, hdr, rois, roi_grid, coords, roi_leaves, roi_nl, s));
   {
     ProfScope p(c, PK_TILE_COUNT, s);
-    SFK_HIP(c, sfk::launch_tile_count(tv, hdr, rois, coords, ts, tile_grid, tile_cnt, tile_done, s));
+    SFK_HIP(c, sfk::launch_tile_count(tv, hdr, rois, coords, roi_leaves, roi_nl, ts, tile_grid,
+                                      tile_cnt, tile_done, s));
   }
   {
     ProfScope p(c, PK_PLAN, s);
@@ -673,7 +681,8 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   }
   {
     ProfScope p(c, PK_TILE_FILL, s);
-    SFK_HIP(c, sfk::launch_tile_fill(tv, hdr, rois, coords, ts, tile_grid, tile_cnt, tile_fit,
+    SFK_HIP(c, sfk::launch_tile_fill(tv, hdr, rois, coords, roi_leaves, roi_nl, ts, tile_grid,
+                                      tile_cnt, tile_fit,
                                       leaf_off, chunk_off, (int32_t*)ws.leaves.p,
                                       (int32_t*)ws.item_tile.p, s));
   }
@@ -1386,7 +1395,7 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
 static void release_ws(sfk_ctx c, Workspace& ws) {
   DevBuf* bufs[] = {&ws.hdr_rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
                     &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
-                    &ws.partials, &ws.claims, &ws.plan_tmp};
+                    &ws.partials, &ws.claims, &ws.plan_tmp, &ws.roi_leaves, &ws.roi_nl};
   for (DevBuf* b : bufs) ws_release(c, *b);
 }
 
@@ -2043,9 +2052,10 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   RoiDev rd;
   int64_t n_tiles, n_coords;
   make_roidev(v, ts, &rd, &n_tiles, &n_coords);
-  TmpBuf hdev(c), coords(c), cnt(c), off(c), idx(c);
+  TmpBuf hdev(c), coords(c), cnt(c), off(c), idx(c), rlist(c);
   SFK_TRY(hdev.get(sizeof(BatchHdr) + sizeof(RoiDev), "descriptor"));
   SFK_TRY(coords.get(sizeof(double) * (size_t)n_coords, "coordinates"));
+  SFK_TRY(rlist.get(sizeof(int32_t) * (kRoiListCap + 1), "ROI leaf list"));
   SFK_TRY(cnt.get(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1), "counts"));
   {
     BatchHdr h{};
@@ -2055,8 +2065,9 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
     SFK_HIP(c, hipMemcpy((char*)hdev.b.p + sizeof(BatchHdr), &rd, sizeof rd, hipMemcpyHostToDevice));
   }
   const RoiDev* rdev_p = (const RoiDev*)((char*)hdev.b.p + sizeof(BatchHdr));
-  SFK_HIP(c, sfk::launch_roi_coords(hdev.as<BatchHdr>(), rdev_p, 1, coords.as<double>(), s));
   TreeView tv = view_of(t);
+  SFK_HIP(c, sfk::launch_roi_coords(tv, hdev.as<BatchHdr>(), rdev_p, 1, coords.as<double>(),
+                                    rlist.as<int32_t>() + 1, rlist.as<int32_t>(), s));
   SFK_HIP(c, sfk::launch_debug_candidates2(tv, (const int32_t*)t->perm.p, rdev_p,
                                             coords.as<double>(), ts, node_begin, node_end,
                                             cnt.as<int64_t>(), nullptr, nullptr, s));
