@@ -1533,21 +1533,22 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if (nbad > 0)
       return fail((set_err(c, "%d per-particle bandwidths are not finite and > 0", nbad), SFK_E_INVAL));
   }
+  // Build scratch lives until the build's last synchronisation, and each
+  // stage's buffers are taken while the GPU runs the stage before, so no
+  // allocation (a host callback under a caller's allocator) or release sits
+  // between two launches.
+  TmpBuf part(c), res(c), keys(c), keys2(c), vals(c), vals2(c), stmp(c), sub(c);
+  const bool per_point = o.knn_k > 0 || d_h;
   {
     // bounding box + finiteness
     const int nblk = 1024;
-    TmpBuf part(c), res(c);
     if ((st = part.get(sizeof(float) * 7 * nblk, "bbox partials")) != SFK_OK ||
         (st = res.get(sizeof(float) * 8, "bbox")) != SFK_OK)
       return fail(st);
     float bb[7];
     if (sfk::launch_bbox(d_xyz, n, part.as<float>(), nblk, res.as<float>(), s) != hipSuccess ||
-        hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+        hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess)
       return fail((set_err(c, "bounding box kernel failed"), SFK_E_DEVICE));
-    if (bb[6] > 0.0f)
-      return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
-    for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
     // curve keys and the sort
     // automatic: about 4x finer per axis than n^(1/3), at least 10 bits
     // (10M points: 30-bit keys, four 8-bit sort passes)
@@ -1556,13 +1557,17 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       const int lg = (int)std::ceil(std::log2((double)std::max<int64_t>(n, 2)));
       bits = std::min(21, std::max(10, (lg + 2) / 3 + 2));
     }
-    TmpBuf keys(c), keys2(c), vals(c), vals2(c), stmp(c);
     if ((st = keys.get(sizeof(uint64_t) * (size_t)n, "sort keys")) != SFK_OK ||
         (st = keys2.get(sizeof(uint64_t) * (size_t)n, "sort keys")) != SFK_OK ||
         (st = vals.get(sizeof(uint32_t) * (size_t)n, "sort values")) != SFK_OK ||
         (st = vals2.get(sizeof(uint32_t) * (size_t)n, "sort values")) != SFK_OK ||
         (st = stmp.get(sfk::radix_sort_tmp_bytes(n), "sort scratch")) != SFK_OK)
       return fail(st);
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return fail((set_err(c, "bounding box kernel failed"), SFK_E_DEVICE));
+    if (bb[6] > 0.0f)
+      return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
+    for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
     int alt = 0;
     ProfScope prof(c, PK_BUILD, s);
     // keys of at most 32 bits are sorted as uint32 (a third less traffic per pass)
@@ -1581,19 +1586,22 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if ((st = build_boxes(c, (const float4*)t->pts.p, n, t->n_leaves, (NodeBox*)t->nodes.p,
                           t->level_off, t->level_cnt, t->n_levels, s)) != SFK_OK)
       return fail(st);
-    if (hipStreamSynchronize(s) != hipSuccess)
+    if (per_point) {
+      // the per-point stage's buffers, while the sort runs
+      if ((st = tree_alloc(c, t, t->node_ih, sizeof(float4) * (size_t)total_nodes,
+                           "node bandwidths")) != SFK_OK)
+        return fail(st);
+      if (o.knn_k > 0 &&
+          ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) !=
+               SFK_OK ||
+           (st = sub.get(sfk::knn_sub_box_bytes(t->n_leaves), "k-NN sub-block boxes")) != SFK_OK))
+        return fail(st);
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
       return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
+    }
   }
-  if (o.knn_k > 0 || d_h) {
-    TmpBuf sub(c);  // k-NN scratch; released after the synchronize below
-    if ((st = tree_alloc(c, t, t->node_ih, sizeof(float4) * (size_t)total_nodes,
-                         "node bandwidths")) != SFK_OK)
-      return fail(st);
+  if (per_point) {
     if (o.knn_k > 0) {
-      if ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) != SFK_OK)
-        return fail(st);
-      if ((st = sub.get(sfk::knn_sub_box_bytes(t->n_leaves), "k-NN sub-block boxes")) != SFK_OK)
-        return fail(st);
       ProfScope prof(c, PK_KNN, s);
       if (sfk::launch_knn(view_of(t), sub.as<float>(), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
