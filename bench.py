@@ -383,7 +383,7 @@ def mbe_rois(ctx, tree, torch, label, info):
     c = info.centres[int(np.argmax(info.masses))]
     recs = []
     for side in (0.02, 0.05, 0.1):
-        lo, hi = synth.clouds._clamped_box(c, side)
+        lo, hi = synth.box_around(c, side)
         for res in (64, 128):
             roi = synth.Roi(lo, hi, (res, res, res), kernel="epanechnikov", bw="mbe",
                             set="in_roi")

@@ -23,4 +23,5 @@ from .clouds import (  # noqa: F401
     view_path,
     random_grid,
     probe_points,
+    box_around,
 )

@@ -219,9 +219,14 @@ def c2_roi(res: int = 128) -> Roi:
                kernel="gauss_trunc3", bw="per_point", h=(0.0, 0.0, 0.0))
 
 
-def _clamped_box(centre, side):
+def box_around(centre, side):
+    """(lo, hi) of the cube of the given side centred on `centre`, moved
+    inside the unit box."""
     c = np.clip(np.asarray(centre, dtype=np.float64), side / 2, 1.0 - side / 2)
     return tuple(float(v) for v in c - side / 2), tuple(float(v) for v in c + side / 2)
+
+
+_clamped_box = box_around
 
 
 def nested_zoom_rois(info: ClumpInfo, seed: int, n_steps: int = 11,
