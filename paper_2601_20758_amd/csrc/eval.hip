@@ -168,7 +168,7 @@ __device__ void roi_list_walk(const TreeView& tv, int r, const RoiDev& R, int32_
 // A tile's candidate leaves: from its ROI's list when there is one, else by
 // a walk from the root. leaves(child, pass, mask) per group of up to 64, in
 // ascending leaf order either way.
-template <int TX, int TY, int TZ, class LeafF>
+template <class LeafF>
 __device__ __forceinline__ void tile_leaves(const TreeView& tv, int32_t* stack, const RoiDev& R,
                                             const TileGeo& g,
                                             const int32_t* __restrict__ roi_leaves,
@@ -214,12 +214,12 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
     int cnt = 0;
-    tile_leaves<TX, TY, TZ>(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
-                            [&](int child, bool pass, uint64_t mask) {
-                              (void)child;
-                              (void)pass;
-                              cnt += popc64(mask);
-                            });
+    tile_leaves(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
+                [&](int child, bool pass, uint64_t mask) {
+                  (void)child;
+                  (void)pass;
+                  cnt += popc64(mask);
+                });
     if (lane == 0) {
       tile_cnt[t] = cnt;
       tile_done[t] = 0;
@@ -257,11 +257,11 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     const RoiDev& R = rois[g.r];
     int32_t* out = leaves + leaf_off[t];
     int cnt = 0;
-    tile_leaves<TX, TY, TZ>(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
-                            [&](int child, bool pass, uint64_t mask) {
-                              if (pass) out[cnt + popc64(mask & lanemask_lt())] = child;
-                              cnt += popc64(mask);
-                            });
+    tile_leaves(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
+                [&](int child, bool pass, uint64_t mask) {
+                  if (pass) out[cnt + popc64(mask & lanemask_lt())] = child;
+                  cnt += popc64(mask);
+                });
   }
 }
 
