@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
                                                     const int32_t* __restrict__ roi_leaves,
                                                     const int32_t* __restrict__ roi_nl,
                                                     int32_t* __restrict__ tile_cnt,
-                                                    int32_t* __restrict__ tile_done) {
+                                                    int32_t* __restrict__ tile_done,
+                                                    int32_t* __restrict__ tile_slots) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_tiles = hdr->n_tiles;
@@ -214,10 +215,11 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
     int cnt = 0;
+    int32_t* slot = tile_slots + t * kTileSlotCap;
     tile_leaves(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
                 [&](int child, bool pass, uint64_t mask) {
-                  (void)child;
-                  (void)pass;
+                  const int pos = cnt + popc64(mask & lanemask_lt());
+                  if (pass && pos < kTileSlotCap) slot[pos] = child;
                   cnt += popc64(mask);
                 });
     if (lane == 0) {
@@ -241,8 +243,9 @@ template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_tile_fill(
     TreeView tv, const BatchHdr* __restrict__ hdr, const RoiDev* __restrict__ rois,
     const double* __restrict__ coords, const int32_t* __restrict__ roi_leaves,
-    const int32_t* __restrict__ roi_nl, const int32_t* __restrict__ tile_cnt,
-    const int32_t* __restrict__ tile_fit, const int64_t* __restrict__ leaf_off,
+    const int32_t* __restrict__ roi_nl, const int32_t* __restrict__ tile_slots,
+    const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
+    const int64_t* __restrict__ leaf_off,
     const int64_t* __restrict__ chunk_off, int32_t* __restrict__ leaves,
     int32_t* __restrict__ item_tile) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
@@ -252,10 +255,16 @@ __global__ __launch_bounds__(256) void k_tile_fill(
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
     const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], hdr->item_cap);
     for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
-    if (tile_fit[t] != kModeLists || tile_cnt[t] == 0) continue;
+    const int tc = tile_cnt[t];
+    if (tile_fit[t] != kModeLists || tc == 0) continue;
+    int32_t* out = leaves + leaf_off[t];
+    if (tc <= kTileSlotCap) {
+      // the count pass kept the whole list, in walk order
+      if (lane < tc) out[lane] = tile_slots[t * kTileSlotCap + lane];
+      continue;
+    }
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
-    int32_t* out = leaves + leaf_off[t];
     int cnt = 0;
     tile_leaves(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
                 [&](int child, bool pass, uint64_t mask) {
@@ -990,11 +999,12 @@ int tile_grid_blocks(int64_t n_tiles) { return grid_for(n_tiles); }
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                              const double* coords, const int32_t* roi_leaves,
                              const int32_t* roi_nl, TileShape ts, int grid_blocks,
-                             int32_t* tile_cnt, int32_t* tile_done, hipStream_t s) {
+                             int32_t* tile_cnt, int32_t* tile_done, int32_t* tile_slots,
+                             hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                      \
   hipLaunchKernelGGL((k_tile_count<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
-                     coords, roi_leaves, roi_nl, tile_cnt, tile_done)
+                     coords, roi_leaves, roi_nl, tile_cnt, tile_done, tile_slots)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();
@@ -1070,15 +1080,15 @@ hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, 
 
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                             const double* coords, const int32_t* roi_leaves,
-                            const int32_t* roi_nl, TileShape ts, int grid_blocks,
-                            const int32_t* tile_cnt, const int32_t* tile_fit,
+                            const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
+                            int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
                             int32_t* item_tile, hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                     \
   hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
-                     coords, roi_leaves, roi_nl, tile_cnt, tile_fit, leaf_off, chunk_off,  \
-                     leaves, item_tile)
+                     coords, roi_leaves, roi_nl, tile_slots, tile_cnt, tile_fit, leaf_off,  \
+                     chunk_off, leaves, item_tile)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();

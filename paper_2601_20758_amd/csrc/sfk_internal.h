@@ -84,6 +84,9 @@ constexpr size_t kClaimBytes = sizeof(int32_t) * kClaimSlices * kClaimStride;
 // Leaves held per ROI list (the leaves that can reach any of the ROI's
 // nodes); a ROI with more walks the hierarchy per tile instead.
 constexpr int kRoiListCap = 256;
+// Leaves the count pass keeps per tile (in walk order); the fill pass copies
+// them for tiles with at most this many instead of walking again.
+constexpr int kTileSlotCap = 64;
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
 struct TileShape { int tx, ty, tz; };
@@ -170,10 +173,12 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_roi_coords(TreeView tv, const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
                              double* coords, int32_t* roi_leaves, int32_t* roi_nl,
                              hipStream_t s);
+// tile_slots: kTileSlotCap int32 per tile
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                              const double* coords, const int32_t* roi_leaves,
                              const int32_t* roi_nl, TileShape ts, int grid_blocks,
-                             int32_t* tile_cnt, int32_t* tile_done, hipStream_t s);
+                             int32_t* tile_cnt, int32_t* tile_done, int32_t* tile_slots,
+                             hipStream_t s);
 // plan_tmp: 3 int64 per block of plan_blocks(max_tiles); max_tiles bounds
 // the header's tile count (the grid of a captured graph uses the capacity)
 int plan_blocks(int64_t max_tiles);
@@ -182,8 +187,8 @@ hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, 
                        int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s);
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                             const double* coords, const int32_t* roi_leaves,
-                            const int32_t* roi_nl, TileShape ts, int grid_blocks,
-                            const int32_t* tile_cnt, const int32_t* tile_fit,
+                            const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
+                            int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
                             int32_t* item_tile, hipStream_t s);
 hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,

@@ -55,7 +55,7 @@ struct DevBuf {
 struct Workspace {
   // hdr_rois = [BatchHdr][RoiDev x capacity]: staged by one host-to-device copy
   DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
-      item_tile, partials, claims, plan_tmp, roi_leaves, roi_nl;
+      item_tile, partials, claims, plan_tmp, roi_leaves, roi_nl, tile_slots;
   uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
@@ -598,6 +598,8 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)tiles, "tile counts"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)tiles, "tile flags"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)tiles, "tile counters"));
+  SFK_TRY(ws_reserve(c, ws, ws.tile_slots, sizeof(int32_t) * kTileSlotCap * (size_t)tiles,
+                     "tile leaf slots"));
   SFK_TRY(ws_reserve(c, ws, ws.leaf_off, sizeof(int64_t) * (size_t)(tiles + 1), "leaf offsets"));
   SFK_TRY(ws_reserve(c, ws, ws.partial_off, sizeof(int64_t) * (size_t)(tiles + 1), "partial offsets"));
   SFK_TRY(ws_reserve(c, ws, ws.chunk_off, sizeof(int64_t) * (size_t)(tiles + 1), "item offsets"));
@@ -617,6 +619,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                                    (int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_fit.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_done.bytes / sizeof(int32_t)),
+                                   (int64_t)(ws.tile_slots.bytes / (sizeof(int32_t) * kTileSlotCap)),
                                    (int64_t)(ws.leaf_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.partial_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.chunk_off.bytes / sizeof(int64_t)) - 1});
@@ -672,7 +675,7 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   {
     ProfScope p(c, PK_TILE_COUNT, s);
     SFK_HIP(c, sfk::launch_tile_count(tv, hdr, rois, coords, roi_leaves, roi_nl, ts, tile_grid,
-                                      tile_cnt, tile_done, s));
+                                      tile_cnt, tile_done, (int32_t*)ws.tile_slots.p, s));
   }
   {
     ProfScope p(c, PK_PLAN, s);
@@ -681,7 +684,8 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   }
   {
     ProfScope p(c, PK_TILE_FILL, s);
-    SFK_HIP(c, sfk::launch_tile_fill(tv, hdr, rois, coords, roi_leaves, roi_nl, ts, tile_grid,
+    SFK_HIP(c, sfk::launch_tile_fill(tv, hdr, rois, coords, roi_leaves, roi_nl,
+                                      (const int32_t*)ws.tile_slots.p, ts, tile_grid,
                                       tile_cnt, tile_fit,
                                       leaf_off, chunk_off, (int32_t*)ws.leaves.p,
                                       (int32_t*)ws.item_tile.p, s));
@@ -1409,7 +1413,8 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
 static void release_ws(sfk_ctx c, Workspace& ws) {
   DevBuf* bufs[] = {&ws.hdr_rois, &ws.coords, &ws.tile_cnt, &ws.tile_fit, &ws.tile_done,
                     &ws.leaf_off, &ws.partial_off, &ws.chunk_off, &ws.leaves, &ws.item_tile,
-                    &ws.partials, &ws.claims, &ws.plan_tmp, &ws.roi_leaves, &ws.roi_nl};
+                    &ws.partials, &ws.claims, &ws.plan_tmp, &ws.roi_leaves, &ws.roi_nl,
+                    &ws.tile_slots};
   for (DevBuf* b : bufs) ws_release(c, *b);
 }
 
@@ -2292,7 +2297,7 @@ static double request_bytes(const sfk_roi& r, TileShape ts) {
   const double m = (double)r.res[0] * r.res[1] * r.res[2];
   const double tiles = std::ceil((double)r.res[0] / ts.tx) * std::ceil((double)r.res[1] / ts.ty) *
                        std::ceil((double)r.res[2] / ts.tz);
-  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4);
+  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4 + kTileSlotCap * 4);
 }
 
 sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
