@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     int32_t* out = leaves + leaf_off[t];
     if (tc <= kTileSlotCap) {
       // the count pass kept the whole list, in walk order
-      if (lane < tc) out[lane] = tile_slots[t * kTileSlotCap + lane];
+      for (int i = lane; i < tc; i += 64) out[i] = tile_slots[t * kTileSlotCap + i];
       continue;
     }
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
