@@ -236,6 +236,29 @@ def test_split_chunks_and_walk_fallback_bitwise(ctx, torch):
     assert np.array_equal(outs["default"], outs["walk64"])
 
 
+def test_roi_lists_and_tile_slots_match_walks_bitwise(ctx, torch):
+    # small boxes reach few leaves: every tile takes its candidates from the
+    # ROI's leaf list and the fill pass copies the count pass's slots; the
+    # in-kernel walk (no stored lists at all) must give the same bits
+    pts = synth.clumpy_cloud(200_000, 11)
+    tree = ctx.build_tree(dev(torch, pts))
+    c = pts[np.argmax(np.linalg.norm(pts - pts.mean(0), axis=1) < 0.3)]
+    rois = [Roi(*synth.box_around(c, side), (res, res, res), kernel=k, bw="fixed",
+                h=(0.2 * side,) * 3)
+            for side, res, k in ((0.02, 33, "epanechnikov"), (0.05, 40, "gauss_trunc3"),
+                                 (0.1, 24, "epanechnikov"))]
+    for r in rois:
+        ctx.set_eval_opts()
+        a = ctx.eval_roi(tree, r).cpu().numpy()
+        ctx.set_eval_opts(list_capacity=1)
+        b = ctx.eval_roi(tree, r).cpu().numpy()
+        ctx.set_eval_opts()
+        assert np.array_equal(a, b), r
+        nodes = sample_nodes(a, r.n_nodes, 24, 1)
+        check_sampled(a, nodes, oracle.density(pts, r, nodes=nodes), "small box")
+    tree.close()
+
+
 # ---------------------------------------------------------------------------
 # per-point bandwidth (k-NN), Gaussian truncated at 3h
 # ---------------------------------------------------------------------------
