@@ -10,13 +10,63 @@
 
 namespace sfk {
 
-__global__ __launch_bounds__(256) void k_inbox_flags(const float4* __restrict__ pts, int64_t n,
+// Leaves whose box meets the closed box B (a particle in B lies in its
+// leaf's box, so no other leaf holds one); empty leaves never meet it.
+__global__ __launch_bounds__(256) void k_leaf_overlap(const NodeBox* __restrict__ leaf_box,
+                                                      int32_t n_leaves, double lx, double ly,
+                                                      double lz, double hx, double hy, double hz,
+                                                      int32_t* __restrict__ flags) {
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaves;
+       l += (int64_t)gridDim.x * blockDim.x) {
+    const NodeBox b = leaf_box[l];
+    const bool meet = (double)b.lo[0] <= hx && (double)b.hi[0] >= lx && (double)b.lo[1] <= hy &&
+                      (double)b.hi[1] >= ly && (double)b.lo[2] <= hz && (double)b.hi[2] >= lz;
+    flags[l] = meet ? 1 : 0;
+  }
+}
+
+hipError_t launch_leaf_overlap(const NodeBox* leaf_box, int32_t n_leaves, const double* lo,
+                               const double* hi, int32_t* flags, hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n_leaves + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_leaf_overlap, dim3((unsigned)nb), dim3(256), 0, s, leaf_box, n_leaves,
+                     lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], flags);
+  return hipGetLastError();
+}
+
+// Indices of the flagged leaves, ascending (pos: exclusive scan of flags).
+__global__ __launch_bounds__(256) void k_compact_leaves(const int32_t* __restrict__ flags,
+                                                        const int64_t* __restrict__ pos,
+                                                        int32_t n_leaves,
+                                                        int32_t* __restrict__ cand) {
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaves;
+       l += (int64_t)gridDim.x * blockDim.x)
+    if (flags[l]) cand[pos[l]] = (int32_t)l;
+}
+
+hipError_t launch_compact_leaves(const int32_t* flags, const int64_t* pos, int32_t n_leaves,
+                                 int32_t* cand, hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n_leaves + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_compact_leaves, dim3((unsigned)nb), dim3(256), 0, s, flags, pos, n_leaves,
+                     cand);
+  return hipGetLastError();
+}
+
+// Slot of the i-th particle examined: all slots in order, or the slots of
+// the candidate leaves in order (cand != nullptr).
+__device__ __forceinline__ int64_t examined_slot(const int32_t* __restrict__ cand, int64_t i) {
+  return cand ? (int64_t)cand[i >> 6] * SFK_LEAF + (i & (SFK_LEAF - 1)) : i;
+}
+
+__global__ __launch_bounds__(256) void k_inbox_flags(const float4* __restrict__ pts,
+                                                     const int32_t* __restrict__ cand, int64_t n,
                                                      double lx, double ly, double lz, double hx,
                                                      double hy, double hz,
                                                      int32_t* __restrict__ flags) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const float4 p = pts[i];
+    const float4 p = pts[examined_slot(cand, i)];
     const double x = p.x, y = p.y, z = p.z;
     const bool in = p.x < 1.0e29f && x >= lx && x <= hx && y >= ly && y <= hy && z >= lz &&
                     z <= hz;
@@ -24,17 +74,18 @@ __global__ __launch_bounds__(256) void k_inbox_flags(const float4* __restrict__ 
   }
 }
 
-hipError_t launch_inbox_flags(const float4* pts, int64_t n, const double* lo, const double* hi,
-                              int32_t* flags, hipStream_t s) {
+hipError_t launch_inbox_flags(const float4* pts, const int32_t* cand, int64_t n, const double* lo,
+                              const double* hi, int32_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_inbox_flags, dim3((unsigned)nb), dim3(256), 0, s, pts, n, lo[0], lo[1],
-                     lo[2], hi[0], hi[1], hi[2], flags);
+  hipLaunchKernelGGL(k_inbox_flags, dim3((unsigned)nb), dim3(256), 0, s, pts, cand, n, lo[0],
+                     lo[1], lo[2], hi[0], hi[1], hi[2], flags);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_compact(const float4* __restrict__ pts,
                                                  const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ cand,
                                                  const int32_t* __restrict__ flags,
                                                  const int64_t* __restrict__ pos, int64_t n,
                                                  int64_t n_slots_out, float4* __restrict__ out_pts,
@@ -44,9 +95,10 @@ __global__ __launch_bounds__(256) void k_compact(const float4* __restrict__ pts,
        i += (int64_t)gridDim.x * blockDim.x) {
     if (flags[i]) {
       const int64_t j = pos[i];
-      const float4 p = pts[i];
+      const int64_t src = examined_slot(cand, i);
+      const float4 p = pts[src];
       out_pts[j] = p;
-      out_perm[j] = perm[i];
+      out_perm[j] = perm[src];
       if (out_axes) {
         out_axes[j] = p.x;
         out_axes[n_b + j] = p.y;
@@ -59,14 +111,15 @@ __global__ __launch_bounds__(256) void k_compact(const float4* __restrict__ pts,
     out_pts[j] = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 0.0f);
 }
 
-hipError_t launch_compact(const float4* pts, const int32_t* perm, const int32_t* flags,
-                          const int64_t* pos, int64_t n, int64_t n_slots_out, float4* out_pts,
-                          int32_t* out_perm, float* out_axes, int64_t n_b, hipStream_t s) {
+hipError_t launch_compact(const float4* pts, const int32_t* perm, const int32_t* cand,
+                          const int32_t* flags, const int64_t* pos, int64_t n,
+                          int64_t n_slots_out, float4* out_pts, int32_t* out_perm,
+                          float* out_axes, int64_t n_b, hipStream_t s) {
   const int64_t m = std::max<int64_t>(n, n_slots_out);
   if (m <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((m + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, s, pts, perm, flags, pos, n,
-                     n_slots_out, out_pts, out_perm, out_axes, n_b);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, s, pts, perm, cand, flags, pos,
+                     n, n_slots_out, out_pts, out_perm, out_axes, n_b);
   return hipGetLastError();
 }
 

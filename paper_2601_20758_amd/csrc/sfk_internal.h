@@ -206,11 +206,21 @@ bool tile_shape_supported(TileShape ts);
 int tile_grid_blocks(int64_t n_tiles);
 
 // mbe.hip
-hipError_t launch_inbox_flags(const float4* pts, int64_t n, const double* lo, const double* hi,
-                              int32_t* flags, hipStream_t s);
-hipError_t launch_compact(const float4* pts, const int32_t* perm, const int32_t* flags,
-                          const int64_t* pos, int64_t n, int64_t n_slots_out, float4* out_pts,
-                          int32_t* out_perm, float* out_axes, int64_t n_b, hipStream_t s);
+// leaves whose box meets the closed box [lo, hi]: flags[n_leaves]; their
+// indices, ascending, from the flags' exclusive scan
+hipError_t launch_leaf_overlap(const NodeBox* leaf_box, int32_t n_leaves, const double* lo,
+                               const double* hi, int32_t* flags, hipStream_t s);
+hipError_t launch_compact_leaves(const int32_t* flags, const int64_t* pos, int32_t n_leaves,
+                                 int32_t* cand, hipStream_t s);
+// particles in the closed box among n examined slots: every slot in order
+// (cand == nullptr, n = slots) or the 64 slots of each candidate leaf in
+// order (n = 64 * candidates); flags and positions index examined slots
+hipError_t launch_inbox_flags(const float4* pts, const int32_t* cand, int64_t n, const double* lo,
+                              const double* hi, int32_t* flags, hipStream_t s);
+hipError_t launch_compact(const float4* pts, const int32_t* perm, const int32_t* cand,
+                          const int32_t* flags, const int64_t* pos, int64_t n,
+                          int64_t n_slots_out, float4* out_pts, int32_t* out_perm,
+                          float* out_axes, int64_t n_b, hipStream_t s);
 hipError_t launch_axis_keys(const float* axes, int64_t n_b, uint64_t* keys, uint32_t* vals,
                             hipStream_t s);
 hipError_t launch_mbe_ell(const uint64_t* sorted_keys_xyz, int64_t n_b, const double* lo,

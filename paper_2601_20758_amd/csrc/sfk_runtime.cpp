@@ -953,19 +953,43 @@ struct SubCloud {
 
 sfk_status make_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool want_axes, SubCloud& sc,
                          hipStream_t s) {
-  const int64_t n_slots = (int64_t)t->n_leaves * SFK_LEAF;
-  TmpBuf flags(c), pos(c), stmp(c), total(c);
+  // Only the leaves whose box meets B can hold particles in B: find them
+  // first, then examine their slots alone (in leaf order, so the particles
+  // come out in the tree's order as a scan of every slot would give them).
+  // Work and scratch then grow with the box's leaves, not with the cloud.
+  const int32_t nl = t->n_leaves;
+  TmpBuf lflags(c), lpos(c), ltotal(c), cand(c), flags(c), pos(c), stmp(c), total(c);
+  SFK_TRY(lflags.get(sizeof(int32_t) * (size_t)std::max(nl, 1), "leaf flags"));
+  SFK_TRY(lpos.get(sizeof(int64_t) * (size_t)std::max(nl, 1), "leaf positions"));
+  SFK_TRY(ltotal.get(sizeof(int64_t), "leaf total"));
+  SFK_TRY(stmp.get(sfk::scan_tmp_bytes((int64_t)nl * SFK_LEAF), "scan scratch"));
+  int64_t n_cand = 0;
+  if (nl > 0) {
+    SFK_HIP(c, sfk::launch_leaf_overlap((const NodeBox*)t->nodes.p + t->level_off[0], nl, r->lo,
+                                         r->hi, lflags.as<int32_t>(), s));
+    SFK_HIP(c, sfk::scan_exclusive_i32_i64(lflags.as<int32_t>(), lpos.as<int64_t>(), nl,
+                                            ltotal.as<int64_t>(), stmp.b.p, stmp.b.bytes, s));
+    SFK_HIP(c, hipMemcpyAsync(&n_cand, ltotal.b.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SFK_HIP(c, hipStreamSynchronize(s));
+  }
+  const int64_t n_slots = n_cand * SFK_LEAF;  // examined slots
+  SFK_TRY(cand.get(sizeof(int32_t) * (size_t)std::max<int64_t>(n_cand, 1), "candidate leaves"));
   SFK_TRY(flags.get(sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1), "in-box flags"));
   SFK_TRY(pos.get(sizeof(int64_t) * (size_t)std::max<int64_t>(n_slots, 1), "in-box positions"));
-  SFK_TRY(stmp.get(sfk::scan_tmp_bytes(n_slots), "scan scratch"));
   SFK_TRY(total.get(sizeof(int64_t), "in-box total"));
-  SFK_HIP(c, sfk::launch_inbox_flags((const float4*)t->pts.p, n_slots, r->lo, r->hi,
-                                      flags.as<int32_t>(), s));
-  SFK_HIP(c, sfk::scan_exclusive_i32_i64(flags.as<int32_t>(), pos.as<int64_t>(), n_slots,
-                                          total.as<int64_t>(), stmp.b.p, stmp.b.bytes, s));
+  if (n_cand > 0) {
+    SFK_HIP(c, sfk::launch_compact_leaves(lflags.as<int32_t>(), lpos.as<int64_t>(), nl,
+                                           cand.as<int32_t>(), s));
+    SFK_HIP(c, sfk::launch_inbox_flags((const float4*)t->pts.p, cand.as<int32_t>(), n_slots,
+                                        r->lo, r->hi, flags.as<int32_t>(), s));
+    SFK_HIP(c, sfk::scan_exclusive_i32_i64(flags.as<int32_t>(), pos.as<int64_t>(), n_slots,
+                                            total.as<int64_t>(), stmp.b.p, stmp.b.bytes, s));
+  }
   int64_t n_b = 0;
-  SFK_HIP(c, hipMemcpyAsync(&n_b, total.b.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  SFK_HIP(c, hipStreamSynchronize(s));
+  if (n_cand > 0) {
+    SFK_HIP(c, hipMemcpyAsync(&n_b, total.b.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SFK_HIP(c, hipStreamSynchronize(s));
+  }
   sc.n_b = n_b;
   sc.n_leaves = (int32_t)((n_b + SFK_LEAF - 1) / SFK_LEAF);
   level_layout(sc.n_leaves, sc.off, sc.cnt, &sc.n_levels, &sc.total_nodes);
@@ -978,7 +1002,8 @@ sfk_status make_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool want_axes
     SFK_TRY(sc.axes.get(sizeof(float) * 3 * (size_t)std::max<int64_t>(n_b, 1), "in-box axes"));
   if (n_b == 0) return SFK_OK;
   SFK_HIP(c, sfk::launch_compact((const float4*)t->pts.p, (const int32_t*)t->perm.p,
-                                  flags.as<int32_t>(), pos.as<int64_t>(), n_slots, out_slots,
+                                  cand.as<int32_t>(), flags.as<int32_t>(), pos.as<int64_t>(),
+                                  n_slots, out_slots,
                                   sc.pts.as<float4>(), sc.perm.as<int32_t>(),
                                   want_axes ? sc.axes.as<float>() : nullptr, n_b, s));
   SFK_TRY(build_boxes(c, sc.pts.as<float4>(), n_b, sc.n_leaves, sc.nodes.as<NodeBox>(), sc.off,
