@@ -342,6 +342,28 @@ def test_in_roi_set(ctx, torch):
     check_density(ctx.eval_roi(tree, r2).cpu().numpy(), oracle.density(pts, r2, h2=h2), "in_roi pp")
 
 
+def test_in_roi_edge_boxes(ctx, torch):
+    # the in-box set is taken from the leaves whose box meets B: a box that
+    # meets none, and a box around a single particle
+    pts = synth.c1_cloud(7)
+    tree = ctx.build_tree(dev(torch, pts))
+    far = Roi((2, 2, 2), (3, 3, 3), (9, 9, 9), bw="fixed", h=(0.1, 0.1, 0.1), set="in_roi")
+    assert float(ctx.eval_roi(tree, far).abs().max()) == 0.0
+    d = ctx.debug_mbe(tree, far.replace(bw="mbe"), per_particle=False)
+    assert d["n_b"] == 0 and float(d["final"].abs().max()) == 0.0
+    p = pts[1234].astype(np.float64)
+    one = Roi(tuple(p - 1e-6), tuple(p + 1e-6), (5, 5, 5), bw="fixed", h=(1e-5,) * 3,
+              set="in_roi")
+    inside = np.all((pts.astype(np.float64) >= np.array(one.lo)) &
+                    (pts.astype(np.float64) <= np.array(one.hi)), axis=1)
+    assert inside.sum() >= 1
+    check_density(ctx.eval_roi(tree, one).cpu().numpy(), oracle.density(pts, one), "one particle")
+    d = ctx.debug_mbe(tree, one.replace(bw="mbe"))
+    assert d["n_b"] == int(inside.sum())
+    assert np.array_equal(d["idx_b"], np.nonzero(inside)[0])
+    tree.close()
+
+
 @pytest.mark.parametrize("case", ["full", "sub", "tiny"])
 def test_mbe_stagewise(ctx, torch, case):
     pts = synth.clumpy_cloud(50_000, 11)
