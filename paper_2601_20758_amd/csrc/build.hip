@@ -374,9 +374,13 @@ hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int6
   return hipGetLastError();
 }
 
-// One wavefront per leaf: box of the real (non-sentinel) particles.
+// One wavefront per leaf: box of the real (non-sentinel) particles. With
+// only_if set, the launch does nothing unless *only_if is non-zero (a
+// refresh that only particles moved to the sentinel would make necessary).
 __global__ __launch_bounds__(256) void k_leaf_boxes(const float4* __restrict__ pts, int64_t n,
-                                                    int32_t n_leaves, NodeBox* __restrict__ out) {
+                                                    int32_t n_leaves, NodeBox* __restrict__ out,
+                                                    const int32_t* __restrict__ only_if) {
+  if (only_if && *only_if == 0) return;
   const int lane = lane_id();
   for (int leaf = blockIdx.x * 4 + (threadIdx.x >> 6); leaf < n_leaves; leaf += gridDim.x * 4) {
     const int64_t slot = (int64_t)leaf * SFK_LEAF + lane;
@@ -404,18 +408,21 @@ __global__ __launch_bounds__(256) void k_leaf_boxes(const float4* __restrict__ p
 }
 
 hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
-                             hipStream_t s) {
+                             const int32_t* only_if, hipStream_t s) {
   if (n_leaves <= 0) return hipSuccess;
   const int nb = std::min<int>((n_leaves + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_leaf_boxes, dim3(nb), dim3(256), 0, s, pts, n, n_leaves, out);
+  hipLaunchKernelGGL(k_leaf_boxes, dim3(nb), dim3(256), 0, s, pts, n, n_leaves, out, only_if);
   return hipGetLastError();
 }
 
-// One wavefront per parent: union of up to 64 child boxes.
+// One wavefront per parent: union of up to 64 child boxes (only_if as
+// for the leaves).
 __global__ __launch_bounds__(256) void k_level_boxes(const NodeBox* __restrict__ child,
                                                      int32_t n_child,
                                                      NodeBox* __restrict__ parent,
-                                                     int32_t n_parent) {
+                                                     int32_t n_parent,
+                                                     const int32_t* __restrict__ only_if) {
+  if (only_if && *only_if == 0) return;
   const int lane = lane_id();
   for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < n_parent; p += gridDim.x * 4) {
     const int c = p * SFK_FANOUT + lane;
@@ -451,10 +458,11 @@ __global__ __launch_bounds__(256) void k_level_boxes(const NodeBox* __restrict__
 }
 
 hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
-                              int32_t n_parent, hipStream_t s) {
+                              int32_t n_parent, const int32_t* only_if, hipStream_t s) {
   if (n_parent <= 0) return hipSuccess;
   const int nb = std::min<int>((n_parent + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_level_boxes, dim3(nb), dim3(256), 0, s, child, n_child, parent, n_parent);
+  hipLaunchKernelGGL(k_level_boxes, dim3(nb), dim3(256), 0, s, child, n_child, parent, n_parent,
+                     only_if);
   return hipGetLastError();
 }
 
@@ -972,7 +980,8 @@ size_t knn_sub_box_bytes(int32_t n_leaves) {
 __global__ __launch_bounds__(256) void k_iso_params(float4* __restrict__ pts,
                                                     const float* __restrict__ h2_sorted,
                                                     const float* __restrict__ h_user,
-                                                    const int32_t* __restrict__ perm, int64_t n) {
+                                                    const int32_t* __restrict__ perm, int64_t n,
+                                                    int32_t* __restrict__ moved) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     float4 p = pts[i];
@@ -981,21 +990,26 @@ __global__ __launch_bounds__(256) void k_iso_params(float4* __restrict__ pts,
       h = (double)h_user[perm[i]];
     else
       h = sqrt((double)h2_sorted[i]);
-    if (h > 0.0) {
+    const bool zero = !(h > 0.0);
+    if (!zero) {
       p.w = (float)(1.0 / h);
     } else {
       p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 1.0f);
+      *moved = 1;  // the same value from every such lane
     }
     pts[i] = p;
   }
 }
 
+__global__ void k_zero_i32(int32_t* p);
+
 hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
-                             const int32_t* perm, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+                             const int32_t* perm, int64_t n, int32_t* moved, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, moved);
+  if (n <= 0) return hipGetLastError();
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_iso_params, dim3((unsigned)nb), dim3(256), 0, s, pts, h2_sorted,
-                     h_user_orig, perm, n);
+                     h_user_orig, perm, n, moved);
   return hipGetLastError();
 }
 

@@ -149,10 +149,11 @@ hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_a
                                 size_t tmp_bytes, hipStream_t s, int* result_in_alt);
 hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
                          float4* pts, int32_t* perm_out, hipStream_t s);
+// only_if: nullptr, or a device flag; the launch does nothing while it is 0
 hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
-                             hipStream_t s);
+                             const int32_t* only_if, hipStream_t s);
 hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
-                              int32_t n_parent, hipStream_t s);
+                              int32_t n_parent, const int32_t* only_if, hipStream_t s);
 hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mode,
                           int64_t n, const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
@@ -160,8 +161,10 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // sub_box: knn_sub_box_bytes(n_leaves) of scratch for the sub-block boxes
 hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s);
 size_t knn_sub_box_bytes(int32_t n_leaves);
+// moved (device int32): set to 1 when a zero bandwidth moved a particle to
+// the sentinel position, else 0
 hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
-                             const int32_t* perm, int64_t n, hipStream_t s);
+                             const int32_t* perm, int64_t n, int32_t* moved, hipStream_t s);
 
 hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);

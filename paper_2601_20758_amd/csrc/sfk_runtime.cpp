@@ -414,13 +414,15 @@ void level_layout(int32_t n_leaves, int32_t* off, int32_t* cnt, int32_t* n_level
 }
 
 // Leaf boxes and the box hierarchy of a leaf layout.
+// only_if: nullptr, or a device flag that leaves the boxes as they are while 0
 sfk_status build_boxes(sfk_ctx c, const float4* pts, int64_t n, int32_t n_leaves,
                        NodeBox* nodes, const int32_t* off, const int32_t* cnt, int n_levels,
-                       hipStream_t s) {
+                       hipStream_t s, const int32_t* only_if = nullptr) {
   if (n_levels <= 0) return SFK_OK;
-  SFK_HIP(c, sfk::launch_leaf_boxes(pts, n, n_leaves, nodes + off[0], s));
+  SFK_HIP(c, sfk::launch_leaf_boxes(pts, n, n_leaves, nodes + off[0], only_if, s));
   for (int l = 1; l < n_levels; ++l)
-    SFK_HIP(c, sfk::launch_level_boxes(nodes + off[l - 1], cnt[l - 1], nodes + off[l], cnt[l], s));
+    SFK_HIP(c, sfk::launch_level_boxes(nodes + off[l - 1], cnt[l - 1], nodes + off[l], cnt[l],
+                                        only_if, s));
   return SFK_OK;
 }
 
@@ -1567,7 +1569,7 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
   // stage's buffers are taken while the GPU runs the stage before, so no
   // allocation (a host callback under a caller's allocator) or release sits
   // between two launches.
-  TmpBuf part(c), res(c), keys(c), keys2(c), vals(c), vals2(c), stmp(c), sub(c);
+  TmpBuf part(c), res(c), keys(c), keys2(c), vals(c), vals2(c), stmp(c), sub(c), moved(c);
   const bool per_point = o.knn_k > 0 || d_h;
   {
     // bounding box + finiteness
@@ -1619,7 +1621,8 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
     if (per_point) {
       // the per-point stage's buffers, while the sort runs
       if ((st = tree_alloc(c, t, t->node_ih, sizeof(float4) * (size_t)total_nodes,
-                           "node bandwidths")) != SFK_OK)
+                           "node bandwidths")) != SFK_OK ||
+          (st = moved.get(sizeof(int32_t), "moved-particle flag")) != SFK_OK)
         return fail(st);
       if (o.knn_k > 0 &&
           ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) !=
@@ -1637,11 +1640,14 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
     }
     if (sfk::launch_iso_params((float4*)t->pts.p, (const float*)t->h2.p, d_h,
-                               (const int32_t*)t->perm.p, n, s) != hipSuccess)
+                               (const int32_t*)t->perm.p, n, moved.as<int32_t>(),
+                               s) != hipSuccess)
       return fail((set_err(c, "bandwidth kernel failed"), SFK_E_DEVICE));
-    // zero-bandwidth particles moved to the sentinel: refresh the boxes
+    // zero-bandwidth particles moved to the sentinel: refresh the boxes (the
+    // kernels return at once when no particle moved)
     if ((st = build_boxes(c, (const float4*)t->pts.p, n, t->n_leaves, (NodeBox*)t->nodes.p,
-                          t->level_off, t->level_cnt, t->n_levels, s)) != SFK_OK)
+                          t->level_off, t->level_cnt, t->n_levels, s,
+                          moved.as<int32_t>())) != SFK_OK)
       return fail(st);
     if (sfk::launch_node_ih((const float4*)t->pts.p, nullptr, PP_ISO, n,
                             (const NodeBox*)t->nodes.p, t->level_off, t->level_cnt, t->n_levels,
