@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void k_leaf_boxes(const float4* __restrict__ p
 hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
                              const int32_t* only_if, hipStream_t s) {
   if (n_leaves <= 0) return hipSuccess;
-  const int nb = std::min<int>((n_leaves + 3) / 4, 65536);
+  // grid-stride: a launch that finds only_if clear ends after few blocks
+  const int nb = std::min<int>((n_leaves + 3) / 4, 4096);
   hipLaunchKernelGGL(k_leaf_boxes, dim3(nb), dim3(256), 0, s, pts, n, n_leaves, out, only_if);
   return hipGetLastError();
 }
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(256) void k_level_boxes(const NodeBox* __restrict__
 hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
                               int32_t n_parent, const int32_t* only_if, hipStream_t s) {
   if (n_parent <= 0) return hipSuccess;
-  const int nb = std::min<int>((n_parent + 3) / 4, 65536);
+  const int nb = std::min<int>((n_parent + 3) / 4, 4096);
   hipLaunchKernelGGL(k_level_boxes, dim3(nb), dim3(256), 0, s, child, n_child, parent, n_parent,
                      only_if);
   return hipGetLastError();
