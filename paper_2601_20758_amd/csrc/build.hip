@@ -14,22 +14,50 @@ namespace sfk {
 // bounding box + finiteness check
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ void bbox_take(float v, int axis, float (&mn)[3], float (&mx)[3],
+                                          float& bad) {
+  if (!isfinite(v)) {
+    bad += 1.0f;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (axis == k) {
+      mn[k] = fminf(mn[k], v);
+      mx[k] = fmaxf(mx[k], v);
+    }
+}
+
+// Per block: min and max per axis and the count of non-finite values. With
+// a 16-byte aligned array the 3n floats are read as float4 chunks (chunk j
+// starts on axis j mod 3) and the last 3n mod 4 floats one by one.
 __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ xyz, int64_t n,
-                                                      float* __restrict__ partial, int nblk) {
+                                                      int vec, float* __restrict__ partial,
+                                                      int nblk) {
   __shared__ float lds[7][4];
   float mn[3] = {3.0e38f, 3.0e38f, 3.0e38f}, mx[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
   float bad = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    const int64_t n4 = (3 * n) / 4;
+    const float4* x4 = reinterpret_cast<const float4*>(xyz);
+    int r = (int)(tid % 3);
+    const int dr = (int)(stride % 3);
+    for (int64_t j = tid; j < n4; j += stride) {
+      const float4 c = x4[j];
+      bbox_take(c.x, r, mn, mx, bad);
+      bbox_take(c.y, r + 1 == 3 ? 0 : r + 1, mn, mx, bad);
+      bbox_take(c.z, r == 0 ? 2 : r - 1, mn, mx, bad);
+      bbox_take(c.w, r, mn, mx, bad);
+      r += dr;
+      if (r >= 3) r -= 3;
+    }
+    for (int64_t e = 4 * n4 + tid; e < 3 * n; e += stride) bbox_take(xyz[e], (int)(e % 3), mn, mx, bad);
+  } else {
+    for (int64_t i = tid; i < n; i += stride) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float v = xyz[3 * i + k];
-      if (!isfinite(v)) {
-        bad += 1.0f;
-      } else {
-        mn[k] = fminf(mn[k], v);
-        mx[k] = fmaxf(mx[k], v);
-      }
+      for (int k = 0; k < 3; ++k) bbox_take(xyz[3 * i + k], k, mn, mx, bad);
     }
   }
   const int w = threadIdx.x >> 6;
@@ -58,23 +86,41 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(64) void k_bbox_final(const float* __restrict__ partial, int nblk,
-                                                   float* __restrict__ result) {
-  for (int k = 0; k < 7; ++k) {
-    float v = k < 3 ? 3.0e38f : (k < 6 ? -3.0e38f : 0.0f);
-    for (int i = lane_id(); i < nblk; i += 64) {
+// One block of 1024 threads combines the partials, all 7 components at once.
+__global__ __launch_bounds__(1024) void k_bbox_final(const float* __restrict__ partial, int nblk,
+                                                     float* __restrict__ result) {
+  __shared__ float lds[7][16];
+  float v[7] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f, 0.0f};
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
       const float u = partial[k * nblk + i];
-      v = k < 3 ? fminf(v, u) : (k < 6 ? fmaxf(v, u) : v + u);
+      v[k] = k < 3 ? fminf(v[k], u) : (k < 6 ? fmaxf(v[k], u) : v[k] + u);
     }
-    v = k < 3 ? wave_min(v) : (k < 6 ? wave_max(v) : wave_sum(v));
-    if (lane_id() == 0) result[k] = v;
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    v[k] = k < 3 ? wave_min(v[k]) : (k < 6 ? wave_max(v[k]) : wave_sum(v[k]));
+    if (lane_id() == 0) lds[k][w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    float r = lds[k][0];
+    for (int j = 1; j < (int)(blockDim.x >> 6); ++j) {
+      const float u = lds[k][j];
+      r = k < 3 ? fminf(r, u) : (k < 6 ? fmaxf(r, u) : r + u);
+    }
+    result[k] = r;
   }
 }
 
 hipError_t launch_bbox(const float* xyz, int64_t n, float* partial, int nblk, float* result,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(256), 0, s, xyz, n, partial, nblk);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, partial, nblk, result);
+  const int vec = ((uintptr_t)xyz & 15) == 0 ? 1 : 0;
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(256), 0, s, xyz, n, vec, partial, nblk);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(1024), 0, s, partial, nblk, result);
   return hipGetLastError();
 }
 
