@@ -562,12 +562,13 @@ __global__ __launch_bounds__(256) void k_level_ih(const float4* __restrict__ chi
 hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mode, int64_t n,
                           const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
-                          hipStream_t s) {
+                          int leaf_done, hipStream_t s) {
   (void)nodes;
   if (n_levels <= 0) return hipSuccess;
   int nb = std::min<int>((level_cnt[0] + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_leaf_ih, dim3(nb), dim3(256), 0, s, pts, pparam, pp_mode, n, level_cnt[0],
-                     node_ih + level_off[0]);
+  if (!leaf_done)
+    hipLaunchKernelGGL(k_leaf_ih, dim3(nb), dim3(256), 0, s, pts, pparam, pp_mode, n,
+                       level_cnt[0], node_ih + level_off[0]);
   for (int l = 1; l < n_levels; ++l) {
     nb = std::min<int>((level_cnt[l] + 3) / 4, 65536);
     hipLaunchKernelGGL(k_level_ih, dim3(nb), dim3(256), 0, s, node_ih + level_off[l - 1],
@@ -1024,39 +1025,50 @@ size_t knn_sub_box_bytes(int32_t n_leaves) {
 // ih = (float)(1 / (double)h) from a caller-given bandwidth (original order).
 // A zero bandwidth has an empty support: the particle is moved to the
 // sentinel position so it is never a member.
+// One wavefront per leaf: each particle's inverse bandwidth, and the leaf's
+// minimum inverse bandwidth (the leaf level of the node bandwidths, as
+// k_leaf_ih computes it from the updated particles).
 __global__ __launch_bounds__(256) void k_iso_params(float4* __restrict__ pts,
                                                     const float* __restrict__ h2_sorted,
                                                     const float* __restrict__ h_user,
                                                     const int32_t* __restrict__ perm, int64_t n,
+                                                    int32_t n_leaves, float4* __restrict__ leaf_ih,
                                                     int32_t* __restrict__ moved) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float4 p = pts[i];
-    double h;
-    if (h_user)
-      h = (double)h_user[perm[i]];
-    else
-      h = sqrt((double)h2_sorted[i]);
-    const bool zero = !(h > 0.0);
-    if (!zero) {
-      p.w = (float)(1.0 / h);
-    } else {
-      p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 1.0f);
-      *moved = 1;  // the same value from every such lane
+  const int lane = lane_id();
+  for (int leaf = blockIdx.x * 4 + (threadIdx.x >> 6); leaf < n_leaves; leaf += gridDim.x * 4) {
+    const int64_t i = (int64_t)leaf * SFK_LEAF + lane;
+    float m = 3.0e38f;
+    if (i < n) {
+      float4 p = pts[i];
+      double h;
+      if (h_user)
+        h = (double)h_user[perm[i]];
+      else
+        h = sqrt((double)h2_sorted[i]);
+      if (h > 0.0) {
+        p.w = (float)(1.0 / h);
+      } else {
+        p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 1.0f);
+        *moved = 1;  // the same value from every such lane
+      }
+      pts[i] = p;
+      if (p.x < 1.0e29f) m = p.w;
     }
-    pts[i] = p;
+    m = wave_min(m);
+    if (lane == 0) leaf_ih[leaf] = make_float4(m, m, m, 0.0f);
   }
 }
 
 __global__ void k_zero_i32(int32_t* p);
 
 hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
-                             const int32_t* perm, int64_t n, int32_t* moved, hipStream_t s) {
+                             const int32_t* perm, int64_t n, int32_t n_leaves, float4* leaf_ih,
+                             int32_t* moved, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, moved);
-  if (n <= 0) return hipGetLastError();
-  const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_iso_params, dim3((unsigned)nb), dim3(256), 0, s, pts, h2_sorted,
-                     h_user_orig, perm, n, moved);
+  if (n_leaves <= 0) return hipGetLastError();
+  const int nb = std::min<int>((n_leaves + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_iso_params, dim3(nb), dim3(256), 0, s, pts, h2_sorted, h_user_orig, perm,
+                     n, n_leaves, leaf_ih, moved);
   return hipGetLastError();
 }
 

@@ -154,17 +154,20 @@ hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, Nod
                              const int32_t* only_if, hipStream_t s);
 hipError_t launch_level_boxes(const NodeBox* child, int32_t n_child, NodeBox* parent,
                               int32_t n_parent, const int32_t* only_if, hipStream_t s);
+// leaf_done: the leaf level is already written (launch_iso_params)
 hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mode,
                           int64_t n, const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
-                          hipStream_t s);
+                          int leaf_done, hipStream_t s);
 // sub_box: knn_sub_box_bytes(n_leaves) of scratch for the sub-block boxes
 hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s);
 size_t knn_sub_box_bytes(int32_t n_leaves);
 // moved (device int32): set to 1 when a zero bandwidth moved a particle to
-// the sentinel position, else 0
+// the sentinel position, else 0; leaf_ih: the leaf level of the node
+// bandwidths (n_leaves float4), written from the updated particles
 hipError_t launch_iso_params(float4* pts, const float* h2_sorted, const float* h_user_orig,
-                             const int32_t* perm, int64_t n, int32_t* moved, hipStream_t s);
+                             const int32_t* perm, int64_t n, int32_t n_leaves, float4* leaf_ih,
+                             int32_t* moved, hipStream_t s);
 
 hipError_t launch_count_nonpositive(const float* h, int64_t n, int32_t* bad, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);

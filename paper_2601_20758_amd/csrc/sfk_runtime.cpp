@@ -1079,7 +1079,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
       g.scale = ck * nu;
       SFK_HIP(c, sfk::launch_node_ih(sc.pts.as<float4>(), nullptr, PP_ISO, n_b,
                                       sc.nodes.as<NodeBox>(), sc.off, sc.cnt, sc.n_levels,
-                                      sc.node_ih.as<float4>(), s));
+                                      sc.node_ih.as<float4>(), 0, s));
     } else {
       float h[3];
       for (int k = 0; k < 3; ++k)
@@ -1144,7 +1144,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
                                r->res, sc.pparam.as<float4>(), ellj_d.as<float>(), s));
   SFK_HIP(c, sfk::launch_node_ih(sc.pts.as<float4>(), sc.pparam.as<float4>(), PP_ANISO, n_b,
                                   sc.nodes.as<NodeBox>(), sc.off, sc.cnt, sc.n_levels,
-                                  sc.node_ih.as<float4>(), s));
+                                  sc.node_ih.as<float4>(), 0, s));
 
   // final grid (Eq. 7): per-particle ellipsoids
   GroupRoi gf{};
@@ -1640,7 +1640,8 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
     }
     if (sfk::launch_iso_params((float4*)t->pts.p, (const float*)t->h2.p, d_h,
-                               (const int32_t*)t->perm.p, n, moved.as<int32_t>(),
+                               (const int32_t*)t->perm.p, n, t->n_leaves,
+                               (float4*)t->node_ih.p + t->level_off[0], moved.as<int32_t>(),
                                s) != hipSuccess)
       return fail((set_err(c, "bandwidth kernel failed"), SFK_E_DEVICE));
     // zero-bandwidth particles moved to the sentinel: refresh the boxes (the
@@ -1651,7 +1652,7 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       return fail(st);
     if (sfk::launch_node_ih((const float4*)t->pts.p, nullptr, PP_ISO, n,
                             (const NodeBox*)t->nodes.p, t->level_off, t->level_cnt, t->n_levels,
-                            (float4*)t->node_ih.p, s) != hipSuccess)
+                            (float4*)t->node_ih.p, 1, s) != hipSuccess)
       return fail((set_err(c, "node bandwidth kernel failed"), SFK_E_DEVICE));
     t->pp_mode = PP_ISO;
     if (hipStreamSynchronize(s) != hipSuccess)
