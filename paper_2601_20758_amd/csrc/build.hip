@@ -394,29 +394,76 @@ hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_a
 // leaf layout
 // ---------------------------------------------------------------------------
 
+// Sub-blocks of 8 consecutive particles inside a leaf: the k-NN search
+// bounds a query's distance to each by the sub-block's box.
+constexpr int kKnnSub = 8;                          // particles per sub-block
+constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
+constexpr int kKnnBoxFloats = 8 * kKnnSubPerLeaf;   // a leaf's sub-block boxes, <= 64
+static_assert(kKnnBoxFloats <= 64, "a leaf's sub-block boxes are loaded one float per lane");
+
+// One wavefront per leaf. Particle perm[i] of the input goes to slot i as
+// (x, y, z, 0), slots from n on get the sentinel, and from the same registers
+// the kernel writes the leaf's box (the leaf level of the hierarchy, as
+// k_leaf_boxes computes it) and, with sub_box set, the boxes of the leaf's
+// sub-blocks: 8 floats per box (lo.xyz, 0, hi.xyz, 0), so one 256-byte line
+// holds a leaf's eight. A box without real particles is empty (lo > hi), and
+// its distance to any point is infinite.
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ xyz,
                                                 const uint32_t* __restrict__ perm, int64_t n,
-                                                int64_t n_slots, float4* __restrict__ pts,
-                                                int32_t* __restrict__ perm_out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_slots;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < n) {
-      const uint32_t j = perm[i];
-      pts[i] = make_float4(xyz[3 * (int64_t)j], xyz[3 * (int64_t)j + 1], xyz[3 * (int64_t)j + 2],
-                           0.0f);
-      perm_out[i] = (int32_t)j;
-    } else {
-      pts[i] = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 0.0f);
+                                                int32_t n_leaves, float4* __restrict__ pts,
+                                                int32_t* __restrict__ perm_out,
+                                                NodeBox* __restrict__ leaf_box,
+                                                float4* __restrict__ sub_box) {
+  const int lane = lane_id();
+  for (int leaf = blockIdx.x * 4 + (threadIdx.x >> 6); leaf < n_leaves; leaf += gridDim.x * 4) {
+    const int64_t slot = (int64_t)leaf * SFK_LEAF + lane;
+    float4 p = make_float4(SFK_SENTINEL, SFK_SENTINEL, SFK_SENTINEL, 0.0f);
+    if (slot < n) {
+      const uint32_t j = perm[slot];
+      p = make_float4(xyz[3 * (int64_t)j], xyz[3 * (int64_t)j + 1], xyz[3 * (int64_t)j + 2],
+                      0.0f);
+      perm_out[slot] = (int32_t)j;
     }
+    pts[slot] = p;
+    const bool real = slot < n && p.x < 1.0e29f;
+    const float lo[3] = {real ? p.x : 3.0e38f, real ? p.y : 3.0e38f, real ? p.z : 3.0e38f};
+    const float hi[3] = {real ? p.x : -3.0e38f, real ? p.y : -3.0e38f, real ? p.z : -3.0e38f};
+    if (sub_box) {  // uniform: every lane of the wave takes part in the shuffles
+      float v[6] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+#pragma unroll
+      for (int off = 1; off < kKnnSub; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          v[c] = fminf(v[c], __shfl_xor(v[c], off, 64));
+          v[c + 3] = fmaxf(v[c + 3], __shfl_xor(v[c + 3], off, 64));
+        }
+      }
+      if ((lane & (kKnnSub - 1)) == 0) {
+        float4* o = sub_box + (slot / kKnnSub) * 2;
+        o[0] = make_float4(v[0], v[1], v[2], 0.0f);
+        o[1] = make_float4(v[3], v[4], v[5], 0.0f);
+      }
+    }
+    NodeBox b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b.lo[k] = wave_min(lo[k]);
+      b.hi[k] = wave_max(hi[k]);
+    }
+    b.count = popc64(ballot(real));
+    b.first = leaf * SFK_LEAF;
+    if (lane == 0) leaf_box[leaf] = b;
   }
 }
 
-hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
-                         float4* pts, int32_t* perm_out, hipStream_t s) {
-  if (n_slots <= 0) return hipSuccess;
-  const int64_t nb = std::min<int64_t>((n_slots + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(256), 0, s, xyz, perm, n, n_slots, pts,
-                     perm_out);
+hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int32_t n_leaves,
+                         float4* pts, int32_t* perm_out, NodeBox* leaf_box, float* sub_box,
+                         hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  if (n > (int64_t)n_leaves * SFK_LEAF) return hipErrorInvalidValue;
+  const int nb = std::min<int>((n_leaves + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, s, xyz, perm, n, n_leaves, pts, perm_out,
+                     leaf_box, reinterpret_cast<float4*>(sub_box));
   return hipGetLastError();
 }
 
@@ -595,10 +642,6 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
 // exceeds a distance it stands for.
 // ---------------------------------------------------------------------------
 
-constexpr int kKnnSub = 8;                          // particles per sub-block
-constexpr int kKnnSubPerLeaf = SFK_LEAF / kKnnSub;  // sub-blocks per leaf
-constexpr int kKnnBoxFloats = 8 * kKnnSubPerLeaf;   // a leaf's sub-block boxes, <= 64
-static_assert(kKnnBoxFloats <= 64, "a leaf's sub-block boxes are loaded one float per lane");
 constexpr int kKnnList = 256;                       // leaves held for ordering
 constexpr int kKnnBands = 5;                        // distance bands of the visiting order
 // Curve neighbours of the query leaf visited first, on each side: more
@@ -608,34 +651,6 @@ constexpr int kKnnBands = 5;                        // distance bands of the vis
 template <int KM>
 constexpr int knn_near() {
   return KM >= 32 ? 4 : KM >= 16 ? 2 : 1;
-}
-
-// Boxes of the sub-blocks of 8 consecutive particles, 8 floats per box
-// (lo.xyz, 0, hi.xyz, 0) so one 256-byte line holds a leaf's eight boxes. A
-// sub-block without real particles gets an empty box, whose distance to any
-// point is infinite.
-__global__ __launch_bounds__(256) void k_sub_boxes(const float4* __restrict__ pts, int64_t n,
-                                                   int64_t n_slots, float4* __restrict__ out) {
-  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < n_slots;
-       slot += (int64_t)gridDim.x * blockDim.x) {
-    const float4 p = pts[slot];
-    const bool real = slot < n && p.x < 1.0e29f;
-    float v[6] = {real ? p.x : 3.0e38f,  real ? p.y : 3.0e38f,  real ? p.z : 3.0e38f,
-                  real ? p.x : -3.0e38f, real ? p.y : -3.0e38f, real ? p.z : -3.0e38f};
-#pragma unroll
-    for (int off = 1; off < kKnnSub; off <<= 1) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        v[c] = fminf(v[c], __shfl_xor(v[c], off, 64));
-        v[c + 3] = fmaxf(v[c + 3], __shfl_xor(v[c + 3], off, 64));
-      }
-    }
-    if ((slot & (kKnnSub - 1)) == 0) {
-      float4* o = out + (slot / kKnnSub) * 2;
-      o[0] = make_float4(v[0], v[1], v[2], 0.0f);
-      o[1] = make_float4(v[3], v[4], v[5], 0.0f);
-    }
-  }
 }
 
 // Insert x into the ascending array a, dropping the largest entry. Each new
@@ -1000,10 +1015,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
 
 hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s) {
   if (tv.n_leaves <= 0) return hipSuccess;
-  const int64_t n_slots = (int64_t)tv.n_leaves * SFK_LEAF;
-  const int64_t nbs = std::min<int64_t>((n_slots + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_sub_boxes, dim3((unsigned)nbs), dim3(256), 0, s, tv.pts, tv.n, n_slots,
-                     reinterpret_cast<float4*>(sub_box));
   const int nb = std::min<int>((tv.n_leaves + 3) / 4, 65536);
   if (k <= 8)
     hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);

@@ -147,8 +147,12 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
 hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                                 uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
                                 size_t tmp_bytes, hipStream_t s, int* result_in_alt);
-hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int64_t n_slots,
-                         float4* pts, int32_t* perm_out, hipStream_t s);
+// Sorted particles into n_leaves * SFK_LEAF slots (n <= that), the leaf
+// boxes into leaf_box[0, n_leaves), and with sub_box non-null the k-NN
+// sub-block boxes (knn_sub_box_bytes(n_leaves))
+hipError_t launch_gather(const float* xyz, const uint32_t* perm, int64_t n, int32_t n_leaves,
+                         float4* pts, int32_t* perm_out, NodeBox* leaf_box, float* sub_box,
+                         hipStream_t s);
 // only_if: nullptr, or a device flag; the launch does nothing while it is 0
 hipError_t launch_leaf_boxes(const float4* pts, int64_t n, int32_t n_leaves, NodeBox* out,
                              const int32_t* only_if, hipStream_t s);
@@ -159,7 +163,7 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
                           int64_t n, const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
                           int leaf_done, hipStream_t s);
-// sub_box: knn_sub_box_bytes(n_leaves) of scratch for the sub-block boxes
+// sub_box: the sub-block boxes launch_gather wrote for this leaf layout
 hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s);
 size_t knn_sub_box_bytes(int32_t n_leaves);
 // moved (device int32): set to 1 when a zero bandwidth moved a particle to

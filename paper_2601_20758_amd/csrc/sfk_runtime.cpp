@@ -415,11 +415,14 @@ void level_layout(int32_t n_leaves, int32_t* off, int32_t* cnt, int32_t* n_level
 
 // Leaf boxes and the box hierarchy of a leaf layout.
 // only_if: nullptr, or a device flag that leaves the boxes as they are while 0
+// leaves_done: the leaf level is already written (the gather writes it)
 sfk_status build_boxes(sfk_ctx c, const float4* pts, int64_t n, int32_t n_leaves,
                        NodeBox* nodes, const int32_t* off, const int32_t* cnt, int n_levels,
-                       hipStream_t s, const int32_t* only_if = nullptr) {
+                       hipStream_t s, const int32_t* only_if = nullptr,
+                       bool leaves_done = false) {
   if (n_levels <= 0) return SFK_OK;
-  SFK_HIP(c, sfk::launch_leaf_boxes(pts, n, n_leaves, nodes + off[0], only_if, s));
+  if (!leaves_done)
+    SFK_HIP(c, sfk::launch_leaf_boxes(pts, n, n_leaves, nodes + off[0], only_if, s));
   for (int l = 1; l < n_levels; ++l)
     SFK_HIP(c, sfk::launch_level_boxes(nodes + off[l - 1], cnt[l - 1], nodes + off[l], cnt[l],
                                         only_if, s));
@@ -1611,12 +1614,20 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
                                             3 * bits, stmp.b.p, stmp.b.bytes, s, &alt)
                 : sfk::radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(),
                                         keys2.as<uint64_t>(), vals2.as<uint32_t>(), n, 3 * bits,
-                                        stmp.b.p, stmp.b.bytes, s, &alt)) != hipSuccess ||
-        sfk::launch_gather(d_xyz, alt ? vals2.as<uint32_t>() : vals.as<uint32_t>(), n, n_slots,
-                           (float4*)t->pts.p, (int32_t*)t->perm.p, s) != hipSuccess)
-      return fail((set_err(c, "sort / gather failed"), SFK_E_DEVICE));
+                                        stmp.b.p, stmp.b.bytes, s, &alt)) != hipSuccess)
+      return fail((set_err(c, "sort failed"), SFK_E_DEVICE));
+    // the k-NN's sub-block boxes come out of the gather, from the same registers
+    const bool knn = per_point && o.knn_k > 0;
+    if (knn &&
+        (st = sub.get(sfk::knn_sub_box_bytes(t->n_leaves), "k-NN sub-block boxes")) != SFK_OK)
+      return fail(st);
+    if (sfk::launch_gather(d_xyz, alt ? vals2.as<uint32_t>() : vals.as<uint32_t>(), n,
+                           t->n_leaves, (float4*)t->pts.p, (int32_t*)t->perm.p,
+                           (NodeBox*)t->nodes.p + t->level_off[0],
+                           knn ? sub.as<float>() : nullptr, s) != hipSuccess)
+      return fail((set_err(c, "gather failed"), SFK_E_DEVICE));
     if ((st = build_boxes(c, (const float4*)t->pts.p, n, t->n_leaves, (NodeBox*)t->nodes.p,
-                          t->level_off, t->level_cnt, t->n_levels, s)) != SFK_OK)
+                          t->level_off, t->level_cnt, t->n_levels, s, nullptr, true)) != SFK_OK)
       return fail(st);
     if (per_point) {
       // the per-point stage's buffers, while the sort runs
@@ -1624,10 +1635,8 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
                            "node bandwidths")) != SFK_OK ||
           (st = moved.get(sizeof(int32_t), "moved-particle flag")) != SFK_OK)
         return fail(st);
-      if (o.knn_k > 0 &&
-          ((st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots, "k-NN distances")) !=
-               SFK_OK ||
-           (st = sub.get(sfk::knn_sub_box_bytes(t->n_leaves), "k-NN sub-block boxes")) != SFK_OK))
+      if (knn && (st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots,
+                                  "k-NN distances")) != SFK_OK)
         return fail(st);
     } else if (hipStreamSynchronize(s) != hipSuccess) {
       return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
