@@ -745,7 +745,9 @@ __device__ __forceinline__ float pt_box_d2(const float* b, float x, float y, flo
 
 template <int KM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 4 : 2))) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
-                                             float* __restrict__ h2_sorted) {
+                                             float* __restrict__ h2_sorted,
+                                             const float* __restrict__ skip_if) {
+  if (skip_if && *skip_if > 0.0f) return;  // the build fails: non-finite coordinates
   __shared__ float4 lds_pts[4][SFK_LEAF];
   __shared__ int32_t lds_stack[4][SFK_STACK];
   __shared__ float lds_d2[4][kKnnSub * 64];
@@ -1013,17 +1015,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
   }
 }
 
-hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s) {
+hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted,
+                      const float* skip_if, hipStream_t s) {
   if (tv.n_leaves <= 0) return hipSuccess;
   const int nb = std::min<int>((tv.n_leaves + 3) / 4, 65536);
   if (k <= 8)
-    hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<8>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted,
+                       skip_if);
   else if (k <= 16)
-    hipLaunchKernelGGL(k_knn<16>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<16>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted,
+                       skip_if);
   else if (k <= 32)
-    hipLaunchKernelGGL(k_knn<32>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<32>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted,
+                       skip_if);
   else
-    hipLaunchKernelGGL(k_knn<64>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted);
+    hipLaunchKernelGGL(k_knn<64>, dim3(nb), dim3(256), 0, s, tv, sub_box, k, h2_sorted,
+                       skip_if);
   return hipGetLastError();
 }
 

@@ -163,8 +163,11 @@ hipError_t launch_node_ih(const float4* pts, const float4* pparam, int32_t pp_mo
                           int64_t n, const NodeBox* nodes, const int32_t* level_off,
                           const int32_t* level_cnt, int n_levels, float4* node_ih,
                           int leaf_done, hipStream_t s);
-// sub_box: the sub-block boxes launch_gather wrote for this leaf layout
-hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted, hipStream_t s);
+// sub_box: the sub-block boxes launch_gather wrote for this leaf layout;
+// skip_if: nullptr, or a device float; while it is > 0 the kernel returns at
+// once and h2_sorted is left as it was
+hipError_t launch_knn(TreeView tv, float* sub_box, int k, float* h2_sorted,
+                      const float* skip_if, hipStream_t s);
 size_t knn_sub_box_bytes(int32_t n_leaves);
 // moved (device int32): set to 1 when a zero bandwidth moved a particle to
 // the sentinel position, else 0; leaf_ih: the leaf level of the node

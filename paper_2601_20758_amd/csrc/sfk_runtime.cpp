@@ -1574,15 +1574,18 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
   // between two launches.
   TmpBuf part(c), res(c), keys(c), keys2(c), vals(c), vals2(c), stmp(c), sub(c), moved(c);
   const bool per_point = o.knn_k > 0 || d_h;
+  // bounding box (6 floats) and the count of non-finite coordinates, read at
+  // the build's one synchronisation at the end: nothing before needs them on
+  // the host (the key kernel reads the box on the device, and the k-NN returns
+  // at once when the count is non-zero)
+  float bb[7];
   {
     // bounding box + finiteness
     const int nblk = 1024;
     if ((st = part.get(sizeof(float) * 7 * nblk, "bbox partials")) != SFK_OK ||
         (st = res.get(sizeof(float) * 8, "bbox")) != SFK_OK)
       return fail(st);
-    float bb[7];
-    if (sfk::launch_bbox(d_xyz, n, part.as<float>(), nblk, res.as<float>(), s) != hipSuccess ||
-        hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (sfk::launch_bbox(d_xyz, n, part.as<float>(), nblk, res.as<float>(), s) != hipSuccess)
       return fail((set_err(c, "bounding box kernel failed"), SFK_E_DEVICE));
     // curve keys and the sort
     // automatic: about 4x finer per axis than n^(1/3), at least 10 bits
@@ -1598,11 +1601,6 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
         (st = vals2.get(sizeof(uint32_t) * (size_t)n, "sort values")) != SFK_OK ||
         (st = stmp.get(sfk::radix_sort_tmp_bytes(n), "sort scratch")) != SFK_OK)
       return fail(st);
-    if (hipStreamSynchronize(s) != hipSuccess)
-      return fail((set_err(c, "bounding box kernel failed"), SFK_E_DEVICE));
-    if (bb[6] > 0.0f)
-      return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
-    for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
     int alt = 0;
     ProfScope prof(c, PK_BUILD, s);
     // keys of at most 32 bits are sorted as uint32 (a third less traffic per pass)
@@ -1638,14 +1636,13 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
       if (knn && (st = tree_alloc(c, t, t->h2, sizeof(float) * (size_t)n_slots,
                                   "k-NN distances")) != SFK_OK)
         return fail(st);
-    } else if (hipStreamSynchronize(s) != hipSuccess) {
-      return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
     }
   }
   if (per_point) {
     if (o.knn_k > 0) {
       ProfScope prof(c, PK_KNN, s);
-      if (sfk::launch_knn(view_of(t), sub.as<float>(), o.knn_k, (float*)t->h2.p, s) != hipSuccess)
+      if (sfk::launch_knn(view_of(t), sub.as<float>(), o.knn_k, (float*)t->h2.p,
+                          res.as<float>() + 6, s) != hipSuccess)
         return fail((set_err(c, "k-NN kernel failed"), SFK_E_DEVICE));
     }
     if (sfk::launch_iso_params((float4*)t->pts.p, (const float*)t->h2.p, d_h,
@@ -1664,9 +1661,14 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
                             (float4*)t->node_ih.p, 1, s) != hipSuccess)
       return fail((set_err(c, "node bandwidth kernel failed"), SFK_E_DEVICE));
     t->pp_mode = PP_ISO;
-    if (hipStreamSynchronize(s) != hipSuccess)
-      return fail((set_err(c, "per-point bandwidth failed on the device"), SFK_E_DEVICE));
   }
+  // pageable destination: the copy returns once the stream has run up to it
+  if (hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
+  if (bb[6] > 0.0f)
+    return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
+  for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
   if (c->prof_on) ++c->prof_builds;
   *out = t;
   return SFK_OK;

@@ -465,6 +465,30 @@ def test_errors(ctx, torch, sfk):
     check_density(ctx.eval_roi(tree, r).cpu().numpy(), oracle.density(pts, r), "after errors")
 
 
+@pytest.mark.gpu
+def test_non_finite_coordinates_fail_every_build_path(ctx, torch, sfk):
+    """A non-finite coordinate fails the build with SFK_E_INVAL on every
+    bandwidth path (found at the build's end; the k-NN returns at once on
+    such a cloud), and the next build on the same context is correct."""
+    pts = synth.uniform_cloud(5000, 7)
+    h = torch.full((len(pts),), 0.02, device="cuda")
+    for bad in (np.nan, np.inf, -np.inf):
+        for where in (0, 2500, 4999):
+            cloud = pts.copy()
+            cloud[where, where % 3] = bad
+            for kw in (dict(), dict(knn_k=32), dict(knn_k=8, curve="morton"), dict(h=h)):
+                with pytest.raises(sfk.SfkError) as e:
+                    ctx.build_tree(dev(torch, cloud), **kw)
+                assert e.value.name == "SFK_E_INVAL", (bad, where, kw)
+                assert "non-finite" in str(e.value), (bad, where, kw)
+    tree = ctx.build_tree(dev(torch, pts), knn_k=32)
+    h2 = ctx.debug_point_h2(tree)
+    assert np.array_equal(h2, oracle.knn_h2(pts, 32))
+    roi = Roi((0, 0, 0), (1, 1, 1), (17, 19, 21), kernel="gauss_trunc3", bw="per_point")
+    check_density(ctx.eval_roi(tree, roi).cpu().numpy(), oracle.density(pts, roi, h2=h2),
+                  "after non-finite clouds")
+
+
 # ---------------------------------------------------------------------------
 # the benchmarked workload at full size: 10M clumpy points, 128^3, Gaussian
 # truncated at 3h, per-point h from the 32nd neighbour (sampled checks)
