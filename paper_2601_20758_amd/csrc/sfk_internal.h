@@ -86,7 +86,7 @@ constexpr size_t kClaimBytes = sizeof(int32_t) * kClaimSlices * kClaimStride;
 constexpr int kRoiListCap = 256;
 // Leaves the count pass keeps per tile (in walk order); the fill pass copies
 // them for tiles with at most this many instead of walking again.
-constexpr int kTileSlotCap = 128;
+constexpr int kTileSlotCap = 256;
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
 struct TileShape { int tx, ty, tz; };

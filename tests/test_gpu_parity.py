@@ -257,6 +257,23 @@ def test_roi_lists_and_tile_slots_match_walks_bitwise(ctx, torch):
         nodes = sample_nodes(a, r.n_nodes, 24, 1)
         check_sampled(a, nodes, oracle.density(pts, r, nodes=nodes), "small box")
     tree.close()
+    # wide supports: tiles overlap more leaves than the count pass keeps, so
+    # the fill pass walks again for them (a node whose support holds more
+    # than 256 leaves' worth of particles proves that its tile does)
+    wpts = synth.uniform_cloud(40_000, 12)
+    wide = ctx.build_tree(dev(torch, wpts))
+    r = Roi((0, 0, 0), (1, 1, 1), (21, 22, 23), kernel="epanechnikov", bw="fixed",
+            h=(0.5,) * 3)
+    cnt = ctx.debug_support_counts(wide, r).cpu().numpy().astype(np.int64)
+    assert cnt.max() > 256 * 64
+    a = ctx.eval_roi(wide, r).cpu().numpy()
+    ctx.set_eval_opts(list_capacity=1)
+    b = ctx.eval_roi(wide, r).cpu().numpy()
+    ctx.set_eval_opts()
+    assert np.array_equal(a, b)
+    nodes = sample_nodes(a, r.n_nodes, 24, 2)
+    check_sampled(a, nodes, oracle.density(wpts, r, nodes=nodes), "wide supports")
+    wide.close()
 
 
 # ---------------------------------------------------------------------------
