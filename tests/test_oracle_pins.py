@@ -106,6 +106,80 @@ def test_single_particle_profile_anisotropic(kernel):
     assert rho[36, 9, 18] == pytest.approx(ck * w * prof(u2), rel=1e-14)
 
 
+# closed-form constants, written out here rather than taken from the oracle
+_CK_EPAN = 15.0 / (8.0 * math.pi)
+_CK_GAUSS3 = 1.0 / ((2.0 * math.pi) ** 1.5 * scipy.stats.chi2.cdf(9.0, 3))
+
+
+def _profile(kernel, r2_over_h2):
+    if kernel == "epanechnikov":
+        return max(0.0, 1.0 - r2_over_h2)
+    return math.exp(-0.5 * r2_over_h2) if r2_over_h2 < 9.0 else 0.0
+
+
+@pytest.mark.parametrize("kernel", ["epanechnikov", "gauss_trunc3"])
+@pytest.mark.parametrize("norm", ["paper", "count"])
+def test_single_particle_profile_per_point(kernel, norm):
+    # Per-point bandwidth (Eq. 7: each particle carries its own 1/(l_x l_y l_z)
+    # and its own scaled distance). Two particles far apart with given squared
+    # bandwidths 1/16 and 1/64 (h = 1/4 and 1/8, exact): along x from each
+    # particle the density is C_K / h^3 * K(r^2 / h^2), with C_K and K written
+    # out here; with norm = paper it is divided by N = 2.
+    roi = Roi((0, 0, 0), (3, 1, 1), (97, 33, 33), kernel=kernel, bw="per_point", norm=norm)
+    pts = np.array([[0.5, 0.5, 0.5], [2.5, 0.5, 0.5]], dtype=np.float32)
+    h = [0.25, 0.125]
+    h2 = np.array([h[0] ** 2, h[1] ** 2], dtype=np.float32)
+    rho = oracle.density(pts, roi, h2=h2).reshape(33, 33, 97)  # [z, y, x]
+    ck = _CK_EPAN if kernel == "epanechnikov" else _CK_GAUSS3
+    nu = 0.5 if norm == "paper" else 1.0
+    reach = 1.0 if kernel == "epanechnikov" else 3.0
+    for j, (ix0, hj) in enumerate(zip((16, 80), h)):
+        # node ix0 + k sits at distance k/32 from particle j on the x axis
+        for k in range(0, min(32, 97 - ix0)):
+            r = k / 32.0
+            other = 2.0 - r  # distance to the other particle, beyond its reach
+            assert other >= reach * h[1 - j]
+            want = nu * ck / hj ** 3 * _profile(kernel, (r / hj) ** 2)
+            got = rho[16, 16, ix0 + k]
+            assert got == pytest.approx(want, rel=1e-14, abs=1e-300), (j, k)
+    # an off-axis node of particle 0: (dx, dy, dz) = (1/32, 2/32, 2/32)
+    r2 = (1 / 32) ** 2 + 2 * (2 / 32) ** 2
+    want = nu * ck / h[0] ** 3 * _profile(kernel, r2 / h[0] ** 2)
+    assert rho[18, 18, 17] == pytest.approx(want, rel=1e-14)
+
+
+def test_given_bandwidth_params_profile():
+    # a given per-particle bandwidth h (not squared): ih = 1/h, w = 1/h^3
+    roi = Roi((0, 0, 0), (1, 1, 1), (33, 33, 33), kernel="epanechnikov", bw="per_point",
+              norm="count")
+    p = np.array([[0.5, 0.5, 0.5]], dtype=np.float32)
+    ih, w = oracle.params_from_h(np.array([0.5], dtype=np.float32))
+    rho = oracle.density_raw(p, roi, "epanechnikov", _CK_EPAN, ih_pp=ih, w_pp=w)
+    rho = rho.reshape(33, 33, 33)
+    for k in range(0, 17):
+        r = k / 32.0
+        want = _CK_EPAN / 0.5 ** 3 * _profile("epanechnikov", (r / 0.5) ** 2)
+        assert rho[16, 16, 16 + k] == pytest.approx(want, rel=1e-14, abs=1e-300)
+
+
+@pytest.mark.parametrize("kernel", ["epanechnikov", "gauss_trunc3"])
+def test_per_point_total_mass(kernel):
+    # a compact cloud with per-particle bandwidths spanning 2-4 node spacings:
+    # every support lies inside the grid, so the field integrates to 1
+    # (norm = paper) whatever each particle's h is
+    g = np.random.default_rng(11)
+    n = 300
+    pts = g.normal(0.5, 0.04, size=(n, 3)).astype(np.float32)
+    s = 1.0 / 60.0
+    h = g.uniform(2.0 * s, 4.0 * s, size=n)
+    if kernel == "gauss_trunc3":
+        h = h / 1.5
+    h2 = (h * h).astype(np.float32)
+    roi = Roi((0, 0, 0), (1, 1, 1), (61, 61, 61), kernel=kernel, bw="per_point")
+    mass = oracle.density(pts, roi, h2=h2).sum() * s ** 3
+    assert mass == pytest.approx(1.0, abs=2e-3)
+
+
 def test_support_boundary_golden():
     rows, _ = _golden("support_boundary.txt")
     roi = Roi((0, 0, 0), (1, 1, 1), (5, 5, 5), kernel="epanechnikov", bw="fixed",
@@ -382,6 +456,24 @@ def test_asl_mean_and_constant_ratio():
     pden, ave, ell_j = oracle.mbe_asl(pts, roi, pilot, ell0)
     ref = np.minimum(ell0[None, :].astype(np.float64) * np.cbrt(ave / pden)[:, None], 5.0 / 8.0)
     np.testing.assert_allclose(ell_j, ref.astype(np.float32), rtol=0, atol=0)
+
+
+def test_asl_eq6_golden():
+    # hand-worked Eq. 6 (tests/golden/asl_eq6.txt): a pilot ratio of 8 doubles
+    # every length (capped at 5 s), 1/8 halves it, 1 keeps it
+    rows, extra = _golden("asl_eq6.txt")
+    roi = Roi((0, 0, 0), (1, 1, 1), (9, 9, 9), bw="mbe", set="in_roi")
+    pilot = np.ones(9 ** 3)
+    pts = []
+    for i, j, k, v, *_ in rows:
+        pilot[int(i) + 9 * (int(j) + 9 * int(k))] = v
+        pts.append([i / 8.0, j / 8.0, k / 8.0])
+    pts = np.array(pts, dtype=np.float32)
+    ell0 = np.array(extra["lengths"], dtype=np.float32)
+    pden, ave, ell_j = oracle.mbe_asl(pts, roi, pilot, ell0)
+    assert ave == extra["mean"][0]
+    np.testing.assert_array_equal(pden, [r[3] for r in rows])
+    np.testing.assert_allclose(ell_j, np.array([r[4:7] for r in rows]), rtol=1e-7, atol=0)
 
 
 def test_mbe_all_capped_equals_fixed():
