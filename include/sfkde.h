@@ -166,6 +166,7 @@ sfk_status sfk_tree_destroy(sfk_tree tree);
  * This is sfk_submit of one ROI on the caller's stream: the same kernels. */
 sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hip_stream);
 
+
 /* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
  * launch on one of the context's streams. The descriptors are copied; the
  * d_out buffers must stay valid until the ticket completes. Returns at once
@@ -441,6 +442,16 @@ sfk_status sfk_eval_adaptive(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
 sfk_status sfk_debug_candidates(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t node_begin, int64_t node_end, int64_t* h_offsets,
                                 int64_t* h_idx, int64_t cap, int64_t* needed);
+/* Tests of the leaf-id checks: with bit 0 set, the count pass of every later
+ * batch of this context stores ids outside the tree in the leaf slots past
+ * the 64th of each tile; with bit 1, the fill pass stores them in the leaf
+ * lists past the 64th entry of each tile. The fill pass (bit 0) and the
+ * evaluation (bit 1) find them, read leaf 0 instead and flag the batch:
+ * sfk_wait / sfk_poll of its ticket and its serving requests report
+ * SFK_E_INTERNAL; a stream-ordered sfk_eval_roi reports it from the next
+ * sfk_eval_roi of the context (which then does no work). 0 turns it off.
+ * SFK_E_INVAL outside 0..3. */
+sfk_status sfk_debug_poison(sfk_ctx ctx, int32_t bits);
 /* Per-particle squared k-NN distance h_j^2 in original order (n floats). */
 sfk_status sfk_debug_point_h2(sfk_ctx ctx, sfk_tree tree, float* h_h2);
 /* The tree's particle order: h_perm[i] = original index of the i-th
@@ -452,6 +463,19 @@ sfk_status sfk_debug_tree_order(sfk_ctx ctx, sfk_tree tree, int32_t* h_perm);
  * bits outside 1..21, an unknown curve or a coordinate >= 2^bits. */
 sfk_status sfk_debug_curve_keys(int32_t curve, int32_t bits, const uint32_t* h_cells, int64_t n,
                                 uint64_t* h_keys);
+/* The tile range query of one ROI (CLOUD set, non-MBE) as the evaluation
+ * uses it: the ROI is evaluated on the stream-ordered path into roi->d_out
+ * (again with larger list capacities if its lists did not all fit), then
+ * h_shape[3] = the tile shape, h_tile_cnt[t] = candidate leaves of tile t
+ * (tiles x fastest over ceil(res / shape) tiles per axis; written if
+ * *n_tiles <= tiles_cap), h_leaves = every tile's leaf list in tile order,
+ * each ascending (written if *total <= cap). Blocks. */
+sfk_status sfk_debug_tile_leaves(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, int32_t* h_shape,
+                                 int64_t* h_tile_cnt, int64_t tiles_cap, int32_t* h_leaves,
+                                 int64_t cap, int64_t* n_tiles, int64_t* total);
+/* Leaf boxes of the tree: h_boxes[6 i .. 6 i + 5] = lo xyz, hi xyz of leaf i
+ * (leaf i holds particle slots 64 i .. 64 i + 63 in curve order). */
+sfk_status sfk_debug_leaf_boxes(sfk_ctx ctx, sfk_tree tree, float* h_boxes);
 /* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel. */
 sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* useful_pairs, int64_t* tested_pairs);

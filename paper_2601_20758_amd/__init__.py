@@ -88,6 +88,9 @@ class Context:
         self._views = weakref.WeakSet()
         self.device = device
         self._alloc = None
+        # tests: while True, the allocator callback returns NULL (as when the
+        # device is out of memory), which the library reports as SFK_E_NOMEM
+        self.fail_allocations = False
         ap = None
         if allocator == "torch":
             import torch
@@ -96,6 +99,8 @@ class Context:
             free_fn = torch.cuda.caching_allocator_delete
 
             def _a(nbytes, user):
+                if self.fail_allocations:
+                    return None
                 try:
                     return alloc_fn(int(nbytes), device)
                 except Exception:  # out of memory -> NULL -> SFK_E_NOMEM
@@ -366,6 +371,35 @@ class Context:
                                             cells.data_ptr(), cases.data_ptr(), nc, C.byref(cnt),
                                             _stream_ptr(stream)))
         return cells[:cnt.value], cases[:cnt.value]
+
+    def debug_poison(self, bits: int):
+        """sfk_debug_poison: test-only out-of-range leaf ids (see the header)."""
+        self._check(self._lib.sfk_debug_poison(self._h, int(bits)))
+
+    def debug_tile_leaves(self, tree: "Tree", roi, out=None):
+        """sfk_debug_tile_leaves: (tile shape, per-tile leaf counts, the
+        concatenated per-tile leaf lists)."""
+        out = self._out_for(roi, out)
+        r = roi_struct(roi, out.data_ptr())
+        nt, tot = C.c_int64(), C.c_int64()
+        shape = np.zeros(3, dtype=np.int32)
+        self._check(self._lib.sfk_debug_tile_leaves(self._h, tree._h, C.byref(r),
+                                                    shape.ctypes.data, None, 0, None, 0,
+                                                    C.byref(nt), C.byref(tot)))
+        cnt = np.zeros(max(1, nt.value), dtype=np.int64)
+        leaves = np.zeros(max(1, tot.value), dtype=np.int32)
+        self._check(self._lib.sfk_debug_tile_leaves(self._h, tree._h, C.byref(r),
+                                                    shape.ctypes.data, cnt.ctypes.data, nt.value,
+                                                    leaves.ctypes.data, tot.value,
+                                                    C.byref(nt), C.byref(tot)))
+        return tuple(int(v) for v in shape), cnt[:nt.value], leaves[:tot.value]
+
+    def debug_leaf_boxes(self, tree: "Tree") -> np.ndarray:
+        """sfk_debug_leaf_boxes: (n_leaves, 6) float32 (lo xyz, hi xyz)."""
+        n_leaves = (tree.info()[0] + 63) // 64
+        b = np.zeros((max(1, n_leaves), 6), dtype=np.float32)
+        self._check(self._lib.sfk_debug_leaf_boxes(self._h, tree._h, b.ctypes.data))
+        return b[:n_leaves]
 
     def debug_point_h2(self, tree: "Tree") -> np.ndarray:
         n = tree.info()[0]

@@ -147,6 +147,11 @@ EXPORTS = {
                                     C.POINTER(Brick), C.c_int32, C.POINTER(AdaptiveResult),
                                     C.c_void_p]),
     "sfk_debug_point_h2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sfk_debug_poison": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sfk_debug_tile_leaves": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_void_p,
+                                        C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sfk_debug_leaf_boxes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_tree_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_curve_keys": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),

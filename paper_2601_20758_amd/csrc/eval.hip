@@ -211,15 +211,18 @@ __global__ __launch_bounds__(256) void k_tile_count(TreeView tv, const BatchHdr*
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_tiles = hdr->n_tiles;
   const int n_rois = hdr->n_rois;
+  const int slot_cap = hdr->slot_cap;
+  const int poison = hdr->debug_poison;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
     const RoiDev& R = rois[g.r];
     int cnt = 0;
-    int32_t* slot = tile_slots + t * kTileSlotCap;
+    int32_t* slot = tile_slots + t * slot_cap;
     tile_leaves(tv, lds_stack[wave], R, g, roi_leaves, roi_nl,
                 [&](int child, bool pass, uint64_t mask) {
                   const int pos = cnt + popc64(mask & lanemask_lt());
-                  if (pass && pos < kTileSlotCap) slot[pos] = child;
+                  if (pass && pos < slot_cap)
+                    slot[pos] = (poison & 1) && pos >= 64 ? tv.n_leaves + child : child;
                   cnt += popc64(mask);
                 });
     if (lane == 0) {
@@ -247,20 +250,32 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
     const int64_t* __restrict__ leaf_off,
     const int64_t* __restrict__ chunk_off, int32_t* __restrict__ leaves,
-    int32_t* __restrict__ item_tile) {
+    int32_t* __restrict__ item_tile, int32_t* __restrict__ claims) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_tiles = hdr->n_tiles;
   const int n_rois = hdr->n_rois;
+  const int slot_cap = hdr->slot_cap;
+  const int poison = hdr->debug_poison;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += (int64_t)gridDim.x * 4) {
     const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], hdr->item_cap);
     for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
     const int tc = tile_cnt[t];
     if (tile_fit[t] != kModeLists || tc == 0) continue;
     int32_t* out = leaves + leaf_off[t];
-    if (tc <= kTileSlotCap) {
-      // the count pass kept the whole list, in walk order
-      for (int i = lane; i < tc; i += 64) out[i] = tile_slots[t * kTileSlotCap + i];
+    if (tc <= slot_cap) {
+      // the count pass kept the whole list, in walk order; an entry that is
+      // not a leaf of the tree is an internal error: flag it, copy leaf 0
+      bool bad = false;
+      for (int i = lane; i < tc; i += 64) {
+        int v = tile_slots[t * slot_cap + i];
+        if ((unsigned)v >= (unsigned)tv.n_leaves) {
+          bad = true;
+          v = 0;
+        }
+        out[i] = (poison & 2) && i >= 64 ? tv.n_leaves + v : v;
+      }
+      if (bad) claims[kErrWord] = 1;
       continue;
     }
     const TileGeo g = tile_geo<TX, TY, TZ>(rois, n_rois, coords, t);
@@ -799,7 +814,18 @@ __global__ __launch_bounds__(256) void k_eval(
       // first, so reading them never waits on the particle loads.
       for (int64_t b0 = lb; b0 < le; b0 += kIdBlock) {
         const int n = (int)min((int64_t)kIdBlock, le - b0);
-        for (int i = lane; i < n; i += 64) ids[i] = leaves[b0 + i];
+        // a list entry that is not a leaf of the tree is an internal error:
+        // flag it and read leaf 0 instead (never out of bounds)
+        bool bad = false;
+        for (int i = lane; i < n; i += 64) {
+          int v = leaves[b0 + i];
+          if ((unsigned)v >= (unsigned)tv.n_leaves) {
+            bad = true;
+            v = 0;
+          }
+          ids[i] = v;
+        }
+        if (bad) claims[kErrWord] = 1;
         wave_sync();
         // Every buffer is refilled unconditionally (past the end with the
         // block's last leaf, culled as empty), which keeps the count of
@@ -1083,12 +1109,12 @@ hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois
                             const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
                             int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
-                            int32_t* item_tile, hipStream_t s) {
+                            int32_t* item_tile, int32_t* claims, hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                     \
   hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
                      coords, roi_leaves, roi_nl, tile_slots, tile_cnt, tile_fit, leaf_off,  \
-                     chunk_off, leaves, item_tile)
+                     chunk_off, leaves, item_tile, claims)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();

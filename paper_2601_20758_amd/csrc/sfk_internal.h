@@ -67,12 +67,14 @@ struct alignas(16) BatchHdr {
   int64_t partial_cap;   // host: capacity of the split-tile partial slots
   int64_t item_cap;      // host: capacity of the item buffers
   int32_t n_rois;        // host: descriptors that follow the header
-  int32_t pad0_;
+  int32_t slot_cap;      // host: leaves the count pass keeps per tile (<= kTileSlotCap)
   int64_t total_leaves;  // plan: candidate leaves over all tiles
   int64_t n_items;       // plan: work items (tile chunks)
   int64_t total_partials;  // plan: partial-sum slots the split tiles need
   int32_t overflow;      // plan: 1 if some tile's lists did not fit (it walks the tree)
-  int32_t pad_;
+  int32_t debug_poison;  // host, tests only: bit 0 = the count pass stores out-of-range
+                         // ids in the slots past the 64th of a tile, bit 1 = the fill
+                         // pass stores them in the lists past the 64th entry
 };
 
 // Work-claim counters of the evaluation: kClaimSlices counters, one per
@@ -80,12 +82,20 @@ struct alignas(16) BatchHdr {
 // not contend; zeroed by the plan kernel of each batch.
 constexpr int kClaimSlices = 64;
 constexpr int kClaimStride = 32;
-constexpr size_t kClaimBytes = sizeof(int32_t) * kClaimSlices * kClaimStride;
+// After the counters, on a line of its own: the sticky error word of the
+// workspace. A kernel that reads a leaf id outside the tree from a slot or a
+// list sets it (and uses leaf 0 instead, so nothing is read out of bounds);
+// the host reads it back after each batch, reports SFK_E_INTERNAL and clears
+// it. No kernel clears it.
+constexpr int kErrWord = kClaimSlices * kClaimStride;
+constexpr size_t kClaimBytes = sizeof(int32_t) * (kClaimSlices + 1) * kClaimStride;
 // Leaves held per ROI list (the leaves that can reach any of the ROI's
 // nodes); a ROI with more walks the hierarchy per tile instead.
 constexpr int kRoiListCap = 256;
-// Leaves the count pass keeps per tile (in walk order); the fill pass copies
-// them for tiles with at most this many instead of walking again.
+// Largest number of leaves the count pass keeps per tile (in walk order);
+// the fill pass copies them for tiles with at most that many instead of
+// walking again. The capacity of a batch (BatchHdr::slot_cap) follows its
+// tile shape: tiles of fewer nodes meet fewer leaves.
 constexpr int kTileSlotCap = 256;
 
 // Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
@@ -186,7 +196,7 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_roi_coords(TreeView tv, const BatchHdr* hdr, const RoiDev* rois, int grid_rois,
                              double* coords, int32_t* roi_leaves, int32_t* roi_nl,
                              hipStream_t s);
-// tile_slots: kTileSlotCap int32 per tile
+// tile_slots: hdr->slot_cap int32 per tile
 hipError_t launch_tile_count(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                              const double* coords, const int32_t* roi_leaves,
                              const int32_t* roi_nl, TileShape ts, int grid_blocks,
@@ -198,12 +208,13 @@ int plan_blocks(int64_t max_tiles);
 hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, int chunk_leaves,
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
                        int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s);
+// claims: the work-claim counters, whose error word the slot copy may set
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                             const double* coords, const int32_t* roi_leaves,
                             const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
                             int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
-                            int32_t* item_tile, hipStream_t s);
+                            int32_t* item_tile, int32_t* claims, hipStream_t s);
 hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
                        const double* coords, TileShape ts, int kk, int pp, bool cnt,
                        int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,

@@ -57,6 +57,7 @@ struct Workspace {
   DevBuf hdr_rois, coords, tile_cnt, tile_fit, tile_done, leaf_off, partial_off, chunk_off, leaves,
       item_tile, partials, claims, plan_tmp, roi_leaves, roi_nl, tile_slots;
   uint64_t gen = 0;  // bumped whenever a buffer is replaced (captured graphs go stale)
+  void* claims_cleared = nullptr;  // the claims buffer whose error word is zeroed
   int64_t want_leaf_cap = 0;
   int64_t want_partial_cap = 0;
   // last enqueued use of the buffers: a buffer that must grow waits for it
@@ -68,7 +69,9 @@ struct Staging {
   char* host = nullptr;  // pinned: per group [BatchHdr][RoiDev...]
   size_t cap = 0;        // bytes
   uint64_t gen = 0;      // bumped when `host` is replaced (captured copies go stale)
-  BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header
+  BatchHdr* hdr_host = nullptr;  // pinned readback of the last group's header,
+                                 // followed by the workspace's error word
+  int32_t* err_host() const { return (int32_t*)((char*)hdr_host + sizeof(BatchHdr)); }
   hipEvent_t ev = nullptr;
   bool ev_valid = false;
   bool stats_pending = false;  // ev follows a header readback not yet absorbed
@@ -143,6 +146,7 @@ struct sfk_ctx_s {
   hipStream_t direct_last_stream = nullptr;
   // autotuner table: key -> tile shape id
   std::map<int, int> tune;
+  int32_t debug_poison = 0;  // sfk_debug_poison: test-only bits staged in every batch header
 };
 
 struct sfk_tree_s {
@@ -339,7 +343,10 @@ struct TmpBuf {
 
 sfk_status staging_reserve(sfk_ctx c, Staging& st, size_t bytes) {
   if (!st.ev) SFK_HIP(c, hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
-  if (!st.hdr_host) SFK_HIP(c, hipHostMalloc((void**)&st.hdr_host, sizeof(BatchHdr)));
+  if (!st.hdr_host) {
+    SFK_HIP(c, hipHostMalloc((void**)&st.hdr_host, sizeof(BatchHdr) + 64));
+    *st.err_host() = 0;
+  }
   if (st.cap >= bytes) return SFK_OK;
   if (st.host) {
     if (st.ev_valid) SFK_HIP(c, hipEventSynchronize(st.ev));
@@ -539,10 +546,10 @@ int chunk_leaves_of(sfk_ctx c) {
 }
 
 // Fill RoiDev descriptors for rois[0..n) and the per-group tile total.
-void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int64_t* n_tiles,
+void make_roidev(const GroupRoi* g, size_t n, TileShape ts, RoiDev* out, int64_t* n_tiles,
                  int64_t* n_coords) {
   int64_t tb = 0, co = 0;
-  for (size_t i = 0; i < g.size(); ++i) {
+  for (size_t i = 0; i < n; ++i) {
     const sfk_roi* r = g[i].roi;
     RoiDev d{};
     for (int k = 0; k < 3; ++k) {
@@ -570,9 +577,23 @@ void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int6
   *n_coords = co;
 }
 
+void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int64_t* n_tiles,
+                 int64_t* n_coords) {
+  make_roidev(g.data(), g.size(), ts, out, n_tiles, n_coords);
+}
+
 struct Caps {
   int64_t leaf_cap, partial_cap, item_cap, tiles_cap, rois_cap, coords_cap;
+  int32_t slot_cap;
 };
+
+// Leaves the count pass keeps per tile for a tile shape: four per node of
+// the tile, at least 32 and at most kTileSlotCap (a tile of few nodes meets
+// few leaves; 4x4x4 tiles of the 10M per-point workload average ~124).
+int32_t slot_cap_of(TileShape ts) {
+  const int t = ts.tx * ts.ty * ts.tz;
+  return std::min(kTileSlotCap, std::max(32, 4 * t));
+}
 
 // Reserve every buffer of a group (n_rois descriptors, n_tiles tiles,
 // n_coords coordinates; `headroom` > 1 over-allocates so later batches fit a
@@ -603,7 +624,8 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)tiles, "tile counts"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)tiles, "tile flags"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)tiles, "tile counters"));
-  SFK_TRY(ws_reserve(c, ws, ws.tile_slots, sizeof(int32_t) * kTileSlotCap * (size_t)tiles,
+  const int32_t slot_cap = slot_cap_of(ts);
+  SFK_TRY(ws_reserve(c, ws, ws.tile_slots, sizeof(int32_t) * slot_cap * (size_t)tiles,
                      "tile leaf slots"));
   SFK_TRY(ws_reserve(c, ws, ws.leaf_off, sizeof(int64_t) * (size_t)(tiles + 1), "leaf offsets"));
   SFK_TRY(ws_reserve(c, ws, ws.partial_off, sizeof(int64_t) * (size_t)(tiles + 1), "partial offsets"));
@@ -614,6 +636,12 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                      "ROI descriptors"));
   SFK_TRY(ws_reserve(c, ws, ws.coords, sizeof(double) * (size_t)nc, "node coordinates"));
   SFK_TRY(ws_reserve(c, ws, ws.claims, kClaimBytes, "work-claim counters"));
+  if (ws.claims_cleared != ws.claims.p) {
+    // a new buffer: its error word starts at zero (no kernel clears it)
+    SFK_HIP(c, hipMemsetAsync(ws.claims.p, 0, ws.claims.bytes, nullptr));
+    SFK_HIP(c, hipStreamSynchronize(nullptr));
+    ws.claims_cleared = ws.claims.p;
+  }
   SFK_TRY(ws_reserve(c, ws, ws.roi_leaves, sizeof(int32_t) * kRoiListCap * (size_t)nr,
                      "ROI leaf lists"));
   SFK_TRY(ws_reserve(c, ws, ws.roi_nl, sizeof(int32_t) * (size_t)nr, "ROI list lengths"));
@@ -624,7 +652,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                                    (int64_t)(ws.tile_cnt.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_fit.bytes / sizeof(int32_t)),
                                    (int64_t)(ws.tile_done.bytes / sizeof(int32_t)),
-                                   (int64_t)(ws.tile_slots.bytes / (sizeof(int32_t) * kTileSlotCap)),
+                                   (int64_t)(ws.tile_slots.bytes / (sizeof(int32_t) * slot_cap)),
                                    (int64_t)(ws.leaf_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.partial_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.chunk_off.bytes / sizeof(int64_t)) - 1});
@@ -636,6 +664,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                                   (int64_t)(ws.roi_leaves.bytes / (sizeof(int32_t) * kRoiListCap)),
                                   (int64_t)(ws.roi_nl.bytes / sizeof(int32_t))});
   k.coords_cap = (int64_t)(ws.coords.bytes / sizeof(double));
+  k.slot_cap = slot_cap;
   // work items: one per tile plus one per partial slot (a split tile has one
   // item per chunk and one partial slot per chunk, whether it evaluates its
   // list or walks per chunk), so the plan can never exceed this
@@ -646,13 +675,15 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
 }
 
 // The batch header a group stages in front of its descriptors.
-BatchHdr make_hdr(const Caps& k, int64_t n_rois, int64_t n_tiles) {
+BatchHdr make_hdr(sfk_ctx c, const Caps& k, int64_t n_rois, int64_t n_tiles) {
   BatchHdr h{};
+  h.debug_poison = c->debug_poison;
   h.n_tiles = n_tiles;
   h.leaf_cap = k.leaf_cap;
   h.partial_cap = k.partial_cap;
   h.item_cap = k.item_cap;
   h.n_rois = (int32_t)n_rois;
+  h.slot_cap = k.slot_cap;
   return h;
 }
 
@@ -693,7 +724,7 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
                                       (const int32_t*)ws.tile_slots.p, ts, tile_grid,
                                       tile_cnt, tile_fit,
                                       leaf_off, chunk_off, (int32_t*)ws.leaves.p,
-                                      (int32_t*)ws.item_tile.p, s));
+                                      (int32_t*)ws.item_tile.p, (int32_t*)ws.claims.p, s));
   }
   // 0: resident blocks per CU from the occupancy query, capped at one wave
   // per tile (the tile kernels' grid) but at least one block per CU, so a
@@ -797,7 +828,7 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
     make_roidev(groups[gi], keys[gi].ts, rd, &tiles[gi], &n_coords);
     Caps k;
     SFK_TRY(reserve_group(c, ws, keys[gi].ts, n, tiles[gi], n_coords, 1.0, t->n_leaves, &k));
-    *(BatchHdr*)(st.host + off) = make_hdr(k, n, tiles[gi]);
+    *(BatchHdr*)(st.host + off) = make_hdr(c, k, n, tiles[gi]);
     off += sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
   }
   off = 0;
@@ -810,6 +841,8 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
     off += gb;
   }
   SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+  SFK_HIP(c, hipMemcpyAsync(st.err_host(), (int32_t*)ws.claims.p + kErrWord, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
   SFK_HIP(c, hipEventRecord(st.ev, s));
   st.ev_valid = true;
   st.stats_pending = true;
@@ -857,7 +890,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   SFK_TRY(staging_reserve(c, sl.st, full));
   if (gc.valid && gc.st_gen != sl.st.gen) drop_graph(gc);
   BatchHdr* h = (BatchHdr*)sl.st.host;
-  *h = make_hdr(k, n, n_tiles);
+  *h = make_hdr(c, k, n, n_tiles);
   std::memcpy(sl.st.host + sizeof(BatchHdr), rd.data(), sizeof(RoiDev) * (size_t)n);
   if (!gc.valid) {
     // profiling events cannot be recorded inside a capture
@@ -873,6 +906,10 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
                           s);
     if (st == SFK_OK && hipMemcpyAsync(sl.st.hdr_host, sl.ws.hdr_rois.p, sizeof(BatchHdr),
                                        hipMemcpyDeviceToHost, s) != hipSuccess)
+      st = SFK_E_DEVICE;
+    if (st == SFK_OK &&
+        hipMemcpyAsync(sl.st.err_host(), (int32_t*)sl.ws.claims.p + kErrWord, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
       st = SFK_E_DEVICE;
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &graph);
@@ -910,25 +947,43 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
 // Grow the list capacities from the direct-path batches whose header
 // readback has completed, oldest first, stopping at the first one still in
 // flight (never blocks; about one event query per call in steady state).
-void absorb_stats(Workspace& ws, const Staging& st);
-void absorb_ready(Workspace& ws, Staging* ring, int n, int oldest) {
+bool absorb_stats(Workspace& ws, const Staging& st);
+// Returns true if one of the absorbed batches set the error word.
+bool absorb_ready(Workspace& ws, Staging* ring, int n, int oldest) {
+  bool err = false;
   for (int i = 0; i < n; ++i) {
     Staging& st = ring[(oldest + i) % n];
     if (!st.stats_pending || !st.ev_valid) continue;
     if (hipEventQuery(st.ev) != hipSuccess) break;
-    absorb_stats(ws, st);
+    err |= absorb_stats(ws, st);
     st.stats_pending = false;
   }
+  return err;
 }
 
 // After a batch completed: grow the list capacities if they overflowed.
-void absorb_stats(Workspace& ws, const Staging& st) {
-  if (!st.hdr_host) return;
+// Returns true (once) if the batch read back a set error word.
+bool absorb_stats(Workspace& ws, const Staging& st) {
+  if (!st.hdr_host) return false;
   const BatchHdr& h = *st.hdr_host;
   if (h.total_leaves > h.leaf_cap) ws.want_leaf_cap = h.total_leaves + h.total_leaves / 4;
   if (h.total_partials > h.partial_cap)
     ws.want_partial_cap = h.total_partials + h.total_partials / 4;
+  int32_t* e = st.err_host();
+  const bool err = *e != 0;
+  *e = 0;
+  return err;
 }
+
+// Clear the workspace's error word, stream-ordered (never inside a capture).
+sfk_status clear_err_word(sfk_ctx c, Workspace& ws, hipStream_t s) {
+  SFK_HIP(c, hipMemsetAsync((int32_t*)ws.claims.p + kErrWord, 0, sizeof(int32_t), s));
+  return SFK_OK;
+}
+
+constexpr const char* kErrLeafIds =
+    "internal error: a tile's leaf list held an id outside the tree (the batch's grids are "
+    "not valid)";
 
 // ---- IN_ROI set and MBE: a sub-cloud of the particles inside B ----
 
@@ -1062,7 +1117,7 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     make_roidev(v, ts, (RoiDev*)(st.host + sizeof(BatchHdr)), &n_tiles, &n_coords);
     Caps k;
     SFK_TRY(reserve_group(c, ws, ts, 1, n_tiles, n_coords, 1.0, tv.n_leaves, &k));
-    *(BatchHdr*)st.host = make_hdr(k, 1, n_tiles);
+    *(BatchHdr*)st.host = make_hdr(c, k, 1, n_tiles);
     SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host, gb, hipMemcpyHostToDevice, s));
     SFK_HIP(c, hipEventRecord(st.ev, s));
     st.ev_valid = true;
@@ -1200,6 +1255,15 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
     }
   }
   SFK_HIP(c, hipStreamSynchronize(s));
+  int32_t err = 0;
+  SFK_HIP(c, hipMemcpy(&err, (int32_t*)ws.claims.p + kErrWord, sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+  if (err) {
+    SFK_TRY(clear_err_word(c, ws, s));
+    SFK_HIP(c, hipStreamSynchronize(s));
+    set_err(c, "%s", kErrLeafIds);
+    return SFK_E_INTERNAL;
+  }
   return SFK_OK;
 }
 
@@ -1263,7 +1327,7 @@ sfk_status launch_ticket(sfk_ctx c, Ticket& tk, Slot& sl) {
   std::vector<const sfk_roi*> cloud;
   std::vector<const sfk_roi*> sub;
   for (const sfk_roi& r : tk.rois) (r.set == SFK_SET_IN_ROI ? sub : cloud).push_back(&r);
-  absorb_stats(sl.ws, sl.st);
+  (void)absorb_stats(sl.ws, sl.st);  // an error word was reported at completion
   if (!cloud.empty()) {
     if (c->opts.disable_graphs)
       SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, sl.ws, sl.st, sl.stream));
@@ -1300,8 +1364,15 @@ sfk_status pump(sfk_ctx c) {
       continue;
     }
     auto it = c->tickets.find(sl.ticket);
-    if (it != c->tickets.end()) it->second.state = 2;
-    absorb_stats(sl.ws, sl.st);
+    const bool bad = absorb_stats(sl.ws, sl.st);
+    if (it != c->tickets.end()) {
+      it->second.state = bad ? 4 : 2;
+      if (bad) it->second.status = SFK_E_INTERNAL;
+    }
+    if (bad) {
+      set_err(c, "%s", kErrLeafIds);
+      SFK_TRY(clear_err_word(c, sl.ws, sl.stream));
+    }
     sl.busy = false;
     sl.ticket = -1;
   }
@@ -1782,7 +1853,12 @@ static sfk_status eval_direct_cloud(sfk_ctx c, sfk_tree t, const std::vector<con
   const int oldest = c->direct_next;
   Staging& st = c->direct_st[c->direct_next];
   c->direct_next = (c->direct_next + 1) % kStagingRing;
-  absorb_ready(c->direct_ws, c->direct_st, kStagingRing, oldest);
+  if (absorb_ready(c->direct_ws, c->direct_st, kStagingRing, oldest)) {
+    // an earlier stream-ordered evaluation of this context found a bad leaf id
+    SFK_TRY(clear_err_word(c, c->direct_ws, s));
+    set_err(c, "%s (reported by the next call on the context)", kErrLeafIds);
+    return SFK_E_INTERNAL;
+  }
   SFK_TRY(enqueue_cloud_rois(c, t, v, count_mode, c->direct_ws, st, s, force_ts));
   SFK_HIP(c, hipEventRecord(c->direct_last, s));
   c->direct_last_valid = true;
@@ -2043,6 +2119,16 @@ sfk_status sfk_iso_cells(sfk_ctx c, const sfk_roi* roi, const float* d_grid, dou
   SFK_GUARD_END(c)
 }
 
+sfk_status sfk_debug_poison(sfk_ctx c, int32_t bits) {
+  SFK_TRY(check_ctx(c));
+  if (bits < 0 || bits > 3) {
+    set_err(c, "poison bits must be in 0..3");
+    return SFK_E_INVAL;
+  }
+  c->debug_poison = bits;
+  return SFK_OK;
+}
+
 sfk_status sfk_debug_tree_order(sfk_ctx c, sfk_tree t, int32_t* h_perm) {
   SFK_GUARD_BEGIN
   SFK_TRY(check_ctx(c));
@@ -2222,6 +2308,79 @@ sfk_status sfk_debug_eval_count(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   SFK_GUARD_END(c)
 }
 
+sfk_status sfk_debug_tile_leaves(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int32_t* h_shape,
+                                 int64_t* h_tile_cnt, int64_t tiles_cap, int32_t* h_leaves,
+                                 int64_t cap, int64_t* n_tiles_out, int64_t* total_out) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !n_tiles_out || !total_out || tiles_cap < 0 || cap < 0) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (roi->set != SFK_SET_CLOUD || roi->bw == SFK_BW_MBE) {
+    set_err(c, "tile leaf lists are exported for CLOUD-set, non-MBE ROIs");
+    return SFK_E_UNSUPPORTED;
+  }
+  hipStream_t s = c->slots[0].stream;
+  SFK_HIP(c, hipStreamSynchronize(s));
+  if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
+  const TileShape ts = choose_shape(c, t, roi);
+  BatchHdr hh{};
+  // the direct path's pipeline; a second run with room for every list if
+  // the first overflowed (every tile then keeps its list)
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    SFK_TRY(eval_direct(c, t, roi, s, false));
+    SFK_HIP(c, hipStreamSynchronize(s));
+    SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr_rois.p, sizeof hh, hipMemcpyDeviceToHost));
+    if (!hh.overflow) break;
+    c->direct_ws.want_leaf_cap = std::max(c->direct_ws.want_leaf_cap, hh.total_leaves);
+    c->direct_ws.want_partial_cap = std::max(c->direct_ws.want_partial_cap, hh.total_partials);
+  }
+  if (hh.overflow) {
+    set_err(c, "leaf lists overflowed twice");
+    return SFK_E_INTERNAL;
+  }
+  *n_tiles_out = hh.n_tiles;
+  *total_out = hh.total_leaves;
+  if (h_shape) {
+    h_shape[0] = ts.tx;
+    h_shape[1] = ts.ty;
+    h_shape[2] = ts.tz;
+  }
+  if (h_tile_cnt && hh.n_tiles <= tiles_cap) {
+    std::vector<int32_t> cnt((size_t)hh.n_tiles);
+    SFK_HIP(c, hipMemcpy(cnt.data(), c->direct_ws.tile_cnt.p, sizeof(int32_t) * hh.n_tiles,
+                         hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < hh.n_tiles; ++i) h_tile_cnt[i] = cnt[(size_t)i];
+  }
+  if (h_leaves && hh.total_leaves <= cap)
+    SFK_HIP(c, hipMemcpy(h_leaves, c->direct_ws.leaves.p, sizeof(int32_t) * hh.total_leaves,
+                         hipMemcpyDeviceToHost));
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_leaf_boxes(sfk_ctx c, sfk_tree t, float* h_boxes) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || (!h_boxes && t->n_leaves > 0)) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  if (t->n_leaves == 0) return SFK_OK;
+  std::vector<NodeBox> b((size_t)t->n_leaves);
+  SFK_HIP(c, hipMemcpy(b.data(), (const NodeBox*)t->nodes.p + t->level_off[0],
+                       sizeof(NodeBox) * t->n_leaves, hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < t->n_leaves; ++i)
+    for (int k = 0; k < 3; ++k) {
+      h_boxes[6 * (int64_t)i + k] = b[(size_t)i].lo[k];
+      h_boxes[6 * (int64_t)i + 3 + k] = b[(size_t)i].hi[k];
+    }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
 sfk_status sfk_debug_mbe(sfk_ctx c, sfk_tree t, const sfk_roi* roi, float* h_ell0, int64_t* n_b,
                          int64_t* h_idx_b, float* h_pilot, float* h_pden, double* aveden,
                          float* h_ell_j, int64_t cap_b) {
@@ -2340,7 +2499,7 @@ static double request_bytes(const sfk_roi& r, TileShape ts) {
   const double m = (double)r.res[0] * r.res[1] * r.res[2];
   const double tiles = std::ceil((double)r.res[0] / ts.tx) * std::ceil((double)r.res[1] / ts.ty) *
                        std::ceil((double)r.res[2] / ts.tz);
-  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4 + kTileSlotCap * 4);
+  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4 + 4.0 * slot_cap_of(ts));
 }
 
 sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
@@ -2461,16 +2620,20 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
           return SFK_E_DEVICE;
         }
         const double tnow = now_s() - t0;
+        const bool bad = absorb_stats(sl.ws, sl.st);
+        if (bad) {
+          set_err(c, "%s", kErrLeafIds);
+          SFK_TRY(clear_err_word(c, sl.ws, sl.stream));
+        }
         for (int64_t i : in_slot[si]) {
           res[i].done_s = tnow;
           res[i].latency_ms = (tnow - reqs[i].arrival_s) * 1e3;
-          res[i].status = SFK_OK;
+          res[i].status = bad ? SFK_E_INTERNAL : SFK_OK;
           ++done_cnt;
         }
         in_flight -= slot_bytes[si];
         slot_bytes[si] = 0.0;
         in_slot[si].clear();
-        absorb_stats(sl.ws, sl.st);
         sl.busy = false;
         acted = true;
       }
