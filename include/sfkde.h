@@ -166,6 +166,30 @@ sfk_status sfk_tree_destroy(sfk_tree tree);
  * This is sfk_submit of one ROI on the caller's stream: the same kernels. */
 sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hip_stream);
 
+/* Size of the static device array that holds the workspace of
+ * sfk_eval_roi_noalloc: one array per device the library runs on, held until
+ * the process ends. */
+#define SFK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * sfk_eval_roi without any allocation: the same kernels and the same grid,
+ * bitwise, stream-ordered on hip_stream (asynchronous), with the whole
+ * workspace (descriptors, node coordinates, per-tile counts, offsets and leaf
+ * slots, work items, partial sums, leaf lists) carved from the device's
+ * static array of SFK_NOALLOC_SCRATCH_BYTES. The caller still owns roi->d_out.
+ * Nothing starts at zero that must: each call's kernels clear what they use.
+ * Limits: CLOUD-set, non-MBE ROIs (SFK_E_UNSUPPORTED otherwise); a ROI whose
+ * per-tile arrays do not fit the array (about 1.5M tiles, e.g. 460^3 nodes
+ * with 4x4x4 tiles) returns SFK_E_BUDGET before any launch. Smaller list
+ * capacities than sfk_eval_roi's only make tiles walk the tree inside the
+ * evaluation (same leaves, same order, same sums).
+ * Concurrency: every call on a device shares that device's array. Calls of one
+ * context are ordered (a call on another stream waits for the previous one);
+ * calls from different contexts on one device that overlap in time race and
+ * corrupt each other's results. Other errors as sfk_eval_roi. */
+sfk_status sfk_eval_roi_noalloc(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
+                                void* hip_stream);
 
 /* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
  * launch on one of the context's streams. The descriptors are copied; the

@@ -185,6 +185,15 @@ class Context:
         self._check(self._lib.sfk_eval_roi(self._h, tree._h, C.byref(r), _stream_ptr(stream)))
         return out
 
+    def eval_roi_noalloc(self, tree: "Tree", roi, out, stream=None):
+        """sfk_eval_roi_noalloc: sfk_eval_roi with the workspace in the
+        library's static scratch array (no allocation); `out` is required."""
+        out = self._out_for(roi, out)
+        r = roi_struct(roi, out.data_ptr())
+        self._check(self._lib.sfk_eval_roi_noalloc(self._h, tree._h, C.byref(r),
+                                                   _stream_ptr(stream)))
+        return out
+
     def submit(self, tree: "Tree", rois: Sequence, outs: Sequence) -> int:
         """sfk_submit of a batch; outs[i] receives rois[i]."""
         arr = (L.RoiC * len(rois))()

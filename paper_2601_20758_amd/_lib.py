@@ -9,6 +9,8 @@ LIB_PATH = os.path.join(HERE, "libsfkde.so")
 
 # enums (include/sfkde.h)
 SFK_OK = 0
+# size of the static scratch array of sfk_eval_roi_noalloc (SFK_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS = {0: "SFK_OK", 1: "SFK_E_INVAL", 2: "SFK_E_NOMEM", 3: "SFK_E_BUDGET", 4: "SFK_E_DEVICE",
           5: "SFK_E_NOT_READY", 6: "SFK_E_CANCELLED", 7: "SFK_E_UNSUPPORTED", 8: "SFK_E_INTERNAL"}
 KERNEL = {"epanechnikov": 0, "gauss_trunc3": 1}
@@ -113,6 +115,7 @@ EXPORTS = {
                                 C.POINTER(C.c_size_t)]),
     "sfk_tree_destroy": (C.c_int, [C.c_void_p]),
     "sfk_eval_roi": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_void_p]),
+    "sfk_eval_roi_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_void_p]),
     "sfk_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_int32,
                              C.POINTER(C.c_int64)]),
     "sfk_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),

@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -49,6 +50,37 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
+
+}  // namespace
+
+// Workspace of sfk_eval_roi_noalloc: one static array per device, held until
+// the process ends. In host code `scratch` names a host-side stand-in, not
+// device memory: host code uses only the address hipGetSymbolAddress gives
+// for the current device (noalloc_scratch_of).
+static __device__ __align__(256) unsigned char scratch[SFK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of this device's scratch array, taken once per device
+// with that device current (nullptr if the runtime cannot give it).
+unsigned char* noalloc_scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    g_scratch_dev[device] = (unsigned char*)p;
+  }
+  return g_scratch_dev[device];
+}
 
 }  // namespace
 
@@ -146,7 +178,18 @@ struct sfk_ctx_s {
   hipStream_t direct_last_stream = nullptr;
   // autotuner table: key -> tile shape id
   std::map<int, int> tune;
+  // sfk_eval_roi_noalloc: this device's copy of the static scratch array
+  // (nullptr if its address could not be taken), a pinned staging ring set
+  // up at creation, and the stream order of consecutive calls
   int32_t debug_poison = 0;  // sfk_debug_poison: test-only bits staged in every batch header
+  unsigned char* na_scratch = nullptr;
+  char* na_host[kStagingRing] = {};
+  hipEvent_t na_ev[kStagingRing] = {};
+  bool na_ev_valid[kStagingRing] = {};
+  int na_next = 0;
+  hipEvent_t na_last = nullptr;
+  bool na_last_valid = false;
+  hipStream_t na_last_stream = nullptr;
 };
 
 struct sfk_tree_s {
@@ -1506,6 +1549,22 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
     sfk_ctx_destroy(c);
     return st_ok;
   }
+  // sfk_eval_roi_noalloc: the scratch address of this device (the device is
+  // current), a pinned descriptor ring and its events
+  c->na_scratch = noalloc_scratch_of(device);
+  if (hipEventCreateWithFlags(&c->na_last, hipEventDisableTiming) != hipSuccess) {
+    set_err(nullptr, "event creation failed");
+    sfk_ctx_destroy(c);
+    return SFK_E_DEVICE;
+  }
+  for (int i = 0; i < kStagingRing; ++i) {
+    if (hipHostMalloc((void**)&c->na_host[i], sizeof(BatchHdr) + sizeof(RoiDev)) != hipSuccess ||
+        hipEventCreateWithFlags(&c->na_ev[i], hipEventDisableTiming) != hipSuccess) {
+      set_err(nullptr, "pinned staging allocation failed");
+      sfk_ctx_destroy(c);
+      return SFK_E_NOMEM;
+    }
+  }
   *out = c;
   return SFK_OK;
   SFK_GUARD_END(nullptr)
@@ -1544,6 +1603,12 @@ sfk_status sfk_ctx_destroy(sfk_ctx c) {
   release_ws(c, c->direct_ws);
   for (int i = 0; i < kStagingRing; ++i) release_staging(c->direct_st[i]);
   if (c->direct_last) (void)hipEventDestroy(c->direct_last);
+  if (c->na_last_valid) (void)hipEventSynchronize(c->na_last);
+  if (c->na_last) (void)hipEventDestroy(c->na_last);
+  for (int i = 0; i < kStagingRing; ++i) {
+    if (c->na_ev[i]) (void)hipEventDestroy(c->na_ev[i]);
+    if (c->na_host[i]) (void)hipHostFree(c->na_host[i]);
+  }
   for (const ProfRec& r : c->prof_pending) {
     (void)hipEventSynchronize(r.b);
     (void)hipEventDestroy(r.a);
@@ -1896,6 +1961,128 @@ sfk_status sfk_eval_roi(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void* hip_str
   }
   SFK_TRY(validate_roi(c, t, roi, 0));
   return eval_direct(c, t, roi, (hipStream_t)hip_stream, false);
+  SFK_GUARD_END(c)
+}
+
+// sfk_eval_roi with its workspace carved from this device's static scratch
+// array: no device or host allocation. Layout, in order: descriptors, node
+// coordinates, claim counters, the ROI leaf list, plan block sums, the
+// per-tile arrays and leaf slots (fixed by the tile count), then the work
+// items, partial sums and leaf lists share what is left. Smaller list and
+// partial capacities than the allocating path's only move tiles to the
+// walking modes, which visit the same leaves in the same order and chunks,
+// so the grid is bitwise the same.
+sfk_status sfk_eval_roi_noalloc(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t) {
+    set_err(c, "NULL tree");
+    return SFK_E_INVAL;
+  }
+  SFK_TRY(validate_roi(c, t, roi, 0));
+  if (roi->set != SFK_SET_CLOUD || roi->bw == SFK_BW_MBE) {
+    set_err(c, "the no-allocation path evaluates CLOUD-set, non-MBE ROIs (the in-box "
+               "sub-cloud needs its own buffers)");
+    return SFK_E_UNSUPPORTED;
+  }
+  if (!c->na_scratch) {
+    set_err(c, "the scratch array of device %d has no device address", c->device);
+    return SFK_E_DEVICE;
+  }
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const GroupRoi g = resolve_cloud_roi(t, roi, false);
+  const TileShape ts = choose_shape(c, t, roi);
+  const int T = ts.tx * ts.ty * ts.tz;
+  RoiDev rd;
+  int64_t n_tiles = 0, n_coords = 0;
+  make_roidev(&g, 1, ts, &rd, &n_tiles, &n_coords);
+  const size_t cap = SFK_NOALLOC_SCRATCH_BYTES;
+  auto rb = [](size_t b) { return round_bytes(std::max<size_t>(b, 256)); };
+  const size_t nt = (size_t)n_tiles;
+  const size_t fixed0 = rb(sizeof(BatchHdr) + sizeof(RoiDev)) + rb(sizeof(double) * n_coords) +
+                        rb(kClaimBytes) + rb(sizeof(int32_t) * kRoiListCap) +
+                        rb(sizeof(int32_t)) +
+                        rb(3 * sizeof(int64_t) * (size_t)sfk::plan_blocks(n_tiles)) +
+                        3 * rb(sizeof(int32_t) * nt) + 3 * rb(sizeof(int64_t) * (nt + 1));
+  // leaf slots: the tile shape's capacity, halved until the fixed part
+  // leaves at least half of the array to the lists (0: the fill pass walks)
+  int32_t slot_cap = slot_cap_of(ts);
+  while (slot_cap > 0 && fixed0 + rb(sizeof(int32_t) * slot_cap * nt) > cap / 2)
+    slot_cap = slot_cap > 16 ? slot_cap / 2 : 0;
+  const size_t fixed = fixed0 + rb(sizeof(int32_t) * (size_t)slot_cap * nt);
+  const size_t min_var = rb(sizeof(int32_t) * (nt + 2)) + rb(sizeof(double) * T) + 256;
+  if (fixed + min_var > cap) {
+    set_err(c, "ROI of %lld tiles needs more than the %zu-byte scratch array of the "
+               "no-allocation path", (long long)n_tiles, cap);
+    return SFK_E_BUDGET;
+  }
+  // what is left: a quarter to partial slots (with their work items), the
+  // rest to leaf-list entries; 3 x 256 bytes of rounding slack
+  const size_t rest = cap - fixed - rb(sizeof(int32_t) * (nt + 1)) - 3 * 256;
+  const int64_t partial_cap =
+      std::max<int64_t>(1, (int64_t)(rest / 4 / (sizeof(double) * T + sizeof(int32_t))));
+  const int64_t leaf_cap = std::max<int64_t>(
+      1, (int64_t)((rest - (size_t)partial_cap * (sizeof(double) * T + sizeof(int32_t))) /
+                   sizeof(int32_t)));
+  const int64_t item_cap = n_tiles + partial_cap + 1;
+  Workspace wv;  // a view of the scratch array; owns nothing
+  size_t used = 0;
+  auto take = [&](DevBuf& b, size_t bytes) {
+    b.p = c->na_scratch + used;
+    b.bytes = bytes;
+    used += rb(bytes);
+  };
+  take(wv.hdr_rois, sizeof(BatchHdr) + sizeof(RoiDev));
+  take(wv.coords, sizeof(double) * (size_t)n_coords);
+  take(wv.claims, kClaimBytes);
+  take(wv.roi_leaves, sizeof(int32_t) * kRoiListCap);
+  take(wv.roi_nl, sizeof(int32_t));
+  take(wv.plan_tmp, 3 * sizeof(int64_t) * (size_t)sfk::plan_blocks(n_tiles));
+  take(wv.tile_cnt, sizeof(int32_t) * nt);
+  take(wv.tile_fit, sizeof(int32_t) * nt);
+  take(wv.tile_done, sizeof(int32_t) * nt);
+  take(wv.leaf_off, sizeof(int64_t) * (nt + 1));
+  take(wv.partial_off, sizeof(int64_t) * (nt + 1));
+  take(wv.chunk_off, sizeof(int64_t) * (nt + 1));
+  take(wv.tile_slots, sizeof(int32_t) * (size_t)slot_cap * nt);
+  take(wv.item_tile, sizeof(int32_t) * (size_t)item_cap);
+  take(wv.partials, sizeof(double) * (size_t)T * (size_t)partial_cap);
+  take(wv.leaves, sizeof(int32_t) * (size_t)leaf_cap);
+  if (used > cap) {
+    set_err(c, "internal: no-allocation layout of %zu bytes exceeds the scratch array", used);
+    return SFK_E_INTERNAL;
+  }
+  BatchHdr h{};
+  h.n_tiles = n_tiles;
+  h.leaf_cap = leaf_cap;
+  h.partial_cap = partial_cap;
+  h.item_cap = item_cap;
+  h.n_rois = 1;
+  h.slot_cap = slot_cap;
+  h.debug_poison = c->debug_poison;
+  // descriptors through a pinned ring set up at context creation
+  const int si = c->na_next;
+  c->na_next = (c->na_next + 1) % kStagingRing;
+  if (c->na_ev_valid[si]) SFK_HIP(c, hipEventSynchronize(c->na_ev[si]));
+  std::memcpy(c->na_host[si], &h, sizeof h);
+  std::memcpy(c->na_host[si] + sizeof(BatchHdr), &rd, sizeof rd);
+  // consecutive calls of this context share the array: order them
+  if (c->na_last_valid && c->na_last_stream != s)
+    SFK_HIP(c, hipStreamWaitEvent(s, c->na_last, 0));
+  SFK_HIP(c, hipMemcpyAsync(wv.hdr_rois.p, c->na_host[si], sizeof(BatchHdr) + sizeof(RoiDev),
+                            hipMemcpyHostToDevice, s));
+  // profiling events may be created on demand: none here
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  const sfk_status st = launch_kernels(c, view_of(t), ts, g.kk, g.pp, false, wv, 1, n_tiles, s);
+  c->prof_on = prof;
+  SFK_TRY(st);
+  SFK_HIP(c, hipEventRecord(c->na_ev[si], s));
+  c->na_ev_valid[si] = true;
+  SFK_HIP(c, hipEventRecord(c->na_last, s));
+  c->na_last_valid = true;
+  c->na_last_stream = s;
+  return SFK_OK;
   SFK_GUARD_END(c)
 }
 
