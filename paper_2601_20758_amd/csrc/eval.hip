@@ -261,7 +261,20 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], hdr->item_cap);
     for (int64_t c = c0 + lane; c < c1; c += 64) item_tile[c] = (int32_t)t;
     const int tc = tile_cnt[t];
-    if (tile_fit[t] != kModeLists || tc == 0) continue;
+    if (tc == 0) {
+      // no candidate leaf, hence no work item: the tile's nodes are zero
+      constexpr int T = TX * TY * TZ;
+      const int r = find_roi(rois, n_rois, t);
+      const RoiDev& R = rois[r];
+      const int64_t lt = t - R.tile_base;
+      const int gi = (int)(lt % R.ntile[0]) * TX + lane % TX;
+      const int gj = (int)((lt / R.ntile[0]) % R.ntile[1]) * TY + (lane / TX) % TY;
+      const int gk = (int)(lt / ((int64_t)R.ntile[0] * R.ntile[1])) * TZ + lane / (TX * TY);
+      if (lane < T && gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
+        R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = 0.0f;
+      continue;
+    }
+    if (tile_fit[t] != kModeLists) continue;
     int32_t* out = leaves + leaf_off[t];
     if (tc <= slot_cap) {
       // the count pass kept the whole list, in walk order; an entry that is
@@ -303,8 +316,10 @@ __global__ __launch_bounds__(256) void k_tile_fill(
 
 static constexpr int kPlanNT = 1024;
 
+// Work items of a tile: one per chunk of its leaves. A tile with no
+// candidate leaf has none: the fill pass writes its (zero) nodes.
 __device__ __forceinline__ int64_t plan_chunks(int64_t cnt, int chunk_leaves) {
-  return cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
+  return cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 0;
 }
 
 // sum of v over the block (every thread gets it)
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_modes(const int32_t* __restric
   const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
                    : (fit_p && nch > 1)            ? kModeWalkChunk
                                                    : kModeWalkTile;
-  const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
+  const int64_t nit = v && cnt > 0 ? (mode == kModeWalkTile ? 1 : nch) : 0;
   if (v) {
     leaf_off[t] = lo;
     partial_off[t] = po;
@@ -411,7 +426,8 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_items(const int32_t* __restric
   const int64_t t = (int64_t)blockIdx.x * kPlanNT + threadIdx.x;
   const bool v = t < n_tiles;
   int64_t nit = 0;
-  if (v) nit = tile_fit[t] == kModeWalkTile ? 1 : plan_chunks(tile_cnt[t], chunk_leaves);
+  if (v && tile_cnt[t] > 0)
+    nit = tile_fit[t] == kModeWalkTile ? 1 : plan_chunks(tile_cnt[t], chunk_leaves);
   int64_t tot;
   const int64_t co = base_c + block_excl_scan<kPlanNT>(nit, &tot, lds);
   if (v) chunk_off[t] = co;
@@ -564,8 +580,8 @@ __global__ __launch_bounds__(256) void k_eval(
     for (int k = 0; k < TZ; ++k) nz[k] = cz[min(g.k0 + k, R.res[2] - 1)];
     const float uih0 = R.ih[0], uih1 = R.ih[1], uih2 = R.ih[2];
     const double c2 = R.c2;
-    const int cnt = tile_cnt[t];
-    const int nch = cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 1;
+    const int cnt = tile_cnt[t];  // > 0: tiles with no candidate leaf have no work item
+    const int nch = (cnt + chunk_leaves - 1) / chunk_leaves;
 
     Acc acc[T];
 #pragma unroll
@@ -1060,7 +1076,7 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_one(const int32_t* __restrict_
   const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
                    : (fit_p && nch > 1)            ? kModeWalkChunk
                                                    : kModeWalkTile;
-  const int64_t nit = v ? (mode == kModeWalkTile ? 1 : nch) : 0;
+  const int64_t nit = v && cnt > 0 ? (mode == kModeWalkTile ? 1 : nch) : 0;
   const int64_t co = block_excl_scan<kPlanNT>(nit, &tc, lds);
   if (v) {
     leaf_off[t] = lo;

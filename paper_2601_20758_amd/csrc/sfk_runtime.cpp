@@ -1372,7 +1372,9 @@ sfk_status launch_ticket(sfk_ctx c, Ticket& tk, Slot& sl) {
   for (const sfk_roi& r : tk.rois) (r.set == SFK_SET_IN_ROI ? sub : cloud).push_back(&r);
   (void)absorb_stats(sl.ws, sl.st);  // an error word was reported at completion
   if (!cloud.empty()) {
-    if (c->opts.disable_graphs)
+    // profiling events cannot be recorded inside a captured graph: while
+    // profiling, batches use direct launches (the same kernels)
+    if (c->opts.disable_graphs || c->prof_on)
       SFK_TRY(enqueue_cloud_rois(c, tk.tree, cloud, false, sl.ws, sl.st, sl.stream));
     else
       SFK_TRY(enqueue_cloud_rois_graph(c, tk.tree, cloud, sl));
@@ -2853,7 +2855,7 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
         batched_reqs += (int64_t)batch.size();
         sl.busy = true;
         sl.ticket = -1;
-        if (c->opts.disable_graphs)
+        if (c->opts.disable_graphs || c->prof_on)
           SFK_TRY(enqueue_cloud_rois(c, t, batch, false, sl.ws, sl.st, sl.stream));
         else
           SFK_TRY(enqueue_cloud_rois_graph(c, t, batch, sl));
