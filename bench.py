@@ -1,19 +1,26 @@
 """Benchmark of the ROI kernel density estimation hot path on one MI355X.
 
-Default workload (the configuration the headline metric is quoted on):
-10M clustered float32 points (2,000 anisotropic Gaussian clumps with
-power-law masses plus 20% uniform background), ROI = unit box, 128^3 grid,
-Gaussian kernel truncated at 3h, per-point h from the 32nd nearest
-neighbour. One step = the whole hot path from points resident in HBM to the
-density grid: tree build (bounding box, Hilbert-curve sort, leaves, box hierarchy),
-k-NN bandwidths, tile range query and evaluation.
+Default workload (the configuration the headline metric is quoted on): the
+served request loop on a 1B-point clustered cloud (2,000 anisotropic Gaussian
+clumps with power-law masses plus 20% uniform background, drawn on the
+device, tree resident in HBM): 8 simulated VR streams with Poisson arrivals
+at 90 Hz each (sides log-uniform in [1e-4, 1], panning centres, grids
+32^3-128^3, Epanechnikov, h = 0.01 x side), admission by HBM budget (free
+HBM after the tree and the grids, minus a reserve).
 
-Prints one JSON line (rank 0): value = useful kernel evaluations (node,
-particle pairs inside the support) per second of step time. The line also
-carries, outside the timed steps, the batched vs one-ROI-per-launch
-comparison (256 uneven ROIs on a 100M-point cloud) and the served request
-trace (8 streams at 90 Hz on a 1B-point cloud, continuous batching vs one ROI
-per launch in FIFO order), both on clouds drawn on the device.
+One step = one second of that offered trace (about 720 requests) served at
+saturation: every request of the second is waiting when the step starts and
+the continuous-batching loop drains them (4 batches in flight on 4 streams,
+up to 64 ROIs per batch). value = useful kernel evaluations (node, particle
+pairs inside the support, counted exactly by an untimed pass) of the timed
+steps / their wall time. Outside the timed steps the line carries the same
+seconds served at saturation one ROI per launch (FIFO), the whole trace
+replayed in real time at 90 Hz for both arms (1 s warm-up, then p50 / p99
+latency against the 11.1 ms frame budget), bitwise alone-vs-mix checks of
+served grids, the oracle on sampled nodes (the CPU baseline), and the other
+configurations as sub-records: the 10M-point per-point Gaussian step, the
+batch of 256 uneven ROIs vs one launch per ROI and the nested zoom on 100M
+points.
 """
 import argparse
 import json
@@ -36,14 +43,17 @@ HBM_PEAK_GBS = 8000.0
 # peaks are this rate with an FMA counted as 2 flops); a transcendental
 # (exp2) issues at quarter rate and takes 4 slots.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU slots per useful evaluation, counted from the definition
-# of one (node, particle) term: per axis a difference and a scaling (6), the
-# squares and their sum (5), the support test (1), the kernel value
-# (Gaussian: scale + exp2 = 1 + 4; Epanechnikov: 1 - u2 = 1), the
-# per-particle weight (1) and the accumulation (1).
-SLOTS_PER_EVAL = {"gauss_trunc3": 19, "epanechnikov": 15}
-# kernel sources whose counter readings a traffic summary is valid for
+# Algorithmic VALU slots per useful evaluation (one (node, particle) term),
+# the minimum any evaluation order pays: Epanechnikov with a uniform
+# bandwidth 9 (3 differences, the squared distance as one multiply and two
+# FMAs, the support compare, 1 - u2 as an FMA, a select, the accumulation);
+# truncated Gaussian with a per-particle bandwidth 14 (10 VALU plus one exp2
+# at quarter rate = 4 slots).
+SLOTS_PER_EVAL = {"gauss_trunc3": 14, "epanechnikov": 9}
+# counter summaries of the evaluation kernel (valid only for the kernel
+# sources whose hash they record)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_gauss_per_point_10m_128_traffic.md")
+SERVED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_epan_served_1b_traffic.md")
 KERNEL_SOURCES = ("paper_2601_20758_amd/csrc/eval.hip", "paper_2601_20758_amd/csrc/sfk_device.h",
                   "paper_2601_20758_amd/csrc/sfk_internal.h")
 
@@ -72,14 +82,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the evaluation kernel from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of
-    a reference kernel of known size), or None when the summary is missing or
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of the evaluation kernel from a committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
+    reference kernel of known size), or None when the summary is missing or
     was taken on other kernel sources."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and line.startswith("- "):
                     k, v = line[2:].split(":", 1)
@@ -98,28 +108,35 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
-    p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="per_point_10m",
-                   choices=["per_point_10m", "small"])
+    p.add_argument("--steps", type=int, default=10,
+                   help="timed steps (seconds of the served trace at saturation)")
+    p.add_argument("--warmup", type=int, default=1,
+                   help="untimed warm-up steps (seconds of the trace)")
+    p.add_argument("--workload", default="served_1b",
+                   choices=["served_1b", "per_point_10m", "small"])
+    p.add_argument("--serve-points", type=int, default=1_000_000_000,
+                   help="cloud size of the served workload")
+    p.add_argument("--serve-reserve-gb", type=float, default=16.0,
+                   help="HBM kept out of the admission budget")
+    p.add_argument("--no-realtime", action="store_true",
+                   help="skip the real-time 90 Hz replays (latency arms)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-nodes", type=int, default=600)
+    p.add_argument("--no-per-point", action="store_true",
+                   help="skip the 10M-point per-point Gaussian step sub-record")
+    p.add_argument("--per-point-steps", type=int, default=5)
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batched vs one-ROI-per-launch comparison")
     p.add_argument("--n-batch", type=int, default=256)
     p.add_argument("--batch-points", type=int, default=100_000_000,
                    help="cloud size of the batched vs one-per-launch comparison")
-    p.add_argument("--serve-points", type=int, default=1_000_000_000,
-                   help="cloud size of the served request trace")
-    p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB fill and a 1 GiB elementwise scale first "
                         "(references for the hardware byte counters)")
-    p.add_argument("--no-serve", action="store_true")
     p.add_argument("--no-zoom", action="store_true",
                    help="skip the nested-zoom and MBE sections on the 100M cloud")
-    p.add_argument("--no-view", action="store_true",
-                   help="skip the view-cache comparison on the 100M cloud")
+    p.add_argument("--view", action="store_true",
+                   help="add the view-cache and adaptive-resolution sections on the 100M cloud")
     return p.parse_args()
 
 
@@ -479,6 +496,268 @@ def adaptive(ctx, tree, torch, label):
     }
 
 
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def served_cpu_baseline(pts_host, rois, outs, torch, ctx, tree, seed=11):
+    """The FP64 oracle (brute force over every particle of the cloud) on
+    sampled nodes of served requests: timed on all the host's threads and on
+    one thread, reported as useful evaluations per second (support sizes of
+    the sampled nodes from the evaluation kernel's counting pass, which the
+    parity tests pin to the oracle's); the oracle values are also compared
+    with the served grids."""
+    import oracle
+    g = np.random.default_rng(seed)
+    heavy = int(np.argmax([r.n_nodes * (r.hi[0] - r.lo[0]) ** 3 for r in rois]))
+    picks = [heavy] + [int(i) for i in g.choice(len(rois), size=2, replace=False)]
+    model, avail = cpu_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
+    threads = max(1, min(threads, avail))
+    rec = {"cpu_model": model, "host_threads_available": avail}
+    worst = 0.0
+    for label, nthr, per_req in (("all_threads", threads, 16), ("one_thread", 1, 2)):
+        oracle.set_threads(nthr)
+        t_tot, useful_tot, n_nodes = 0.0, 0, 0
+        for i in picks:
+            r = rois[i]
+            got = outs[i].cpu().numpy()
+            nodes = np.unique(np.concatenate([
+                [int(np.argmax(got))],
+                g.choice(r.n_nodes, size=per_req - 1, replace=False)])).astype(np.int64)
+            t0 = time.perf_counter()
+            ref = oracle.density(pts_host, r, nodes=nodes)
+            t_tot += time.perf_counter() - t0
+            cnt = ctx.debug_support_counts(tree, r)
+            torch.cuda.synchronize()
+            useful_tot += int(cnt[torch.from_numpy(nodes).cuda()].double().sum().item())
+            n_nodes += len(nodes)
+            peak = max(float(ref.max()), float(got.max()))
+            big = ref >= 1e-3 * peak
+            if big.any():
+                worst = max(worst, float(np.max(np.abs(got[nodes][big] - ref[big]) / ref[big])))
+        rec[label] = {"value": useful_tot / t_tot, "threads": nthr, "seconds": t_tot,
+                      "nodes": n_nodes, "useful_evals": useful_tot}
+    oracle.set_threads(threads)
+    rec["max_rel_err_served_vs_oracle"] = worst
+    a = rec["all_threads"]
+    return {"value": a["value"], "unit": "evals/s", "cores": a["threads"], "kind": "oracle",
+            "sample": "%d nodes (argmax + random) of 3 served requests (the heaviest + 2 random), "
+                      "each brute-forced in FP64 over all %d particles: %.1f s on %d threads; "
+                      "1 thread: %.3g evals/s over %d nodes; CPU %s"
+                      % (a["nodes"], len(pts_host), a["seconds"], a["threads"],
+                         rec["one_thread"]["value"], rec["one_thread"]["nodes"], model),
+            "detail": rec}
+
+
+def served_headline(ctx, torch, args):
+    """The served workload: returns (headline fields, sub-record)."""
+    import synth
+    n = args.serve_points
+    W, K = args.warmup, args.steps
+    log("drawing %d clumpy points on the device" % n)
+    xyz, info = synth.clumpy_cloud_device(n, 5)
+    tree = ctx.build_tree(xyz)
+    pts_host = None
+    if not args.no_cpu_baseline:
+        pts_host = xyz.cpu().numpy()
+    del xyz
+    torch.cuda.empty_cache()
+    label = "%dB" % (n // 10**9) if n % 10**9 == 0 else "%dM" % (n // 10**6)
+    arr, streams, rois = synth.serving_trace(seed=5, duration_s=float(W + K))
+    arr = np.asarray(arr)
+    log("trace: %d requests over %d s; counting useful pairs" % (len(rois), W + K))
+    useful = np.array([ctx.debug_eval_count(tree, r)[0] for r in rois], dtype=np.int64)
+    outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
+    torch.cuda.synchronize()
+    free, total = torch.cuda.mem_get_info()
+    reserve = args.serve_reserve_gb * 2**30
+    budget = max(float(free) - reserve, 1.0)
+    win = np.floor(arr).astype(np.int64)
+    idx_w = [np.nonzero(win == w)[0] for w in range(W + K)]
+
+    def serve_window(w, mode):
+        ids = idx_w[w]
+        res, s = ctx.serve(tree, np.zeros(len(ids)), [rois[i] for i in ids],
+                           [outs[i] for i in ids], mode=mode, n_slots=4, max_batch=64,
+                           budget_bytes=budget)
+        return s
+
+    # warm-up steps, then the same seconds one ROI per launch in FIFO order
+    # (an untimed comparison at saturation), then the timed region:
+    # continuous batching at saturation
+    for w in range(W):
+        serve_window(w, 0)
+        log("warm-up step", w + 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for w in range(W, W + K):
+        serve_window(w, 1)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batches = 0
+    for w in range(W, W + K):
+        batches += serve_window(w, 0).n_batches
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    timed = np.concatenate(idx_w[W:W + K])
+    e_timed = int(useful[timed].sum())
+    log("timed %d steps (%d requests) in %.3f s" % (K, len(timed), dt))
+    eval_ms = prof["eval_ms"]
+    launches = max(1, prof["eval_launches"])
+    slots = SLOTS_PER_EVAL["epanechnikov"] * e_timed
+    achieved = slots / (eval_ms * 1e-3) / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    sub = {
+        "workload": "%d requests in %d s of a trace from 8 streams at 90 Hz on the resident "
+                    "%s-point tree; sides log-uniform in [1e-4, 1], grids 32^3-128^3, "
+                    "Epanechnikov, h = 0.01 x side" % (len(rois), W + K, label),
+        "admission_budget_bytes": budget, "hbm_free_bytes": float(free),
+        "saturated": {
+            "continuous_batching": {"evals_per_s": e_timed / dt, "ms_per_second_of_trace":
+                                    dt * 1e3 / K, "batches": batches,
+                                    "requests": int(len(timed))},
+            "one_roi_per_launch": {"evals_per_s": e_timed / dt1,
+                                   "ms_per_second_of_trace": dt1 * 1e3 / K},
+            "throughput_ratio": dt1 / dt},
+        "phases_ms_per_step": {k: prof[k] / K for k in ("tile_count_ms", "plan_ms",
+                                                         "tile_fill_ms", "eval_ms")},
+        "eval_launches": int(prof["eval_launches"]),
+    }
+    if not args.no_realtime:
+        budget_ms = 1000.0 / 90.0
+        # continuous batching last, so the grids checked below are its results
+        for name, mode in (("one_roi_per_launch", 1), ("continuous_batching", 0)):
+            log("real-time replay at 90 Hz:", name)
+            res, sm = ctx.serve(tree, arr, rois, outs, mode=mode, n_slots=4, max_batch=64,
+                                budget_bytes=budget)
+            lat = np.array([res[i].latency_ms for i in range(len(rois))])
+            meas = arr >= W
+            done = np.array([res[i].done_s for i in range(len(rois))])
+            span = float(done[meas].max() - W)
+            sub.setdefault("realtime_90hz", {})[name] = {
+                "p50_ms": float(np.percentile(lat[meas], 50)),
+                "p99_ms": float(np.percentile(lat[meas], 99)),
+                "max_ms": float(lat[meas].max()),
+                "deadline_miss_rate": float(np.mean(lat[meas] > budget_ms)),
+                "evals_per_s": float(useful[meas].sum()) / span,
+                "requests": int(meas.sum()), "batches": int(sm.n_batches),
+                "mean_batch": sm.mean_batch, "mean_in_flight": sm.mean_in_flight,
+                "budget_waits": int(sm.budget_waits)}
+        sub["realtime_90hz"]["frame_budget_ms"] = budget_ms
+    # served grids (real-time continuous batching, else the saturated run)
+    # against each request evaluated alone, bitwise
+    g = np.random.default_rng(12)
+    check = sorted(set(int(i) for i in g.choice(len(rois), size=48, replace=False))
+                   | set(int(i) for i in np.argsort(-useful)[:8]))
+    alone = torch.empty(max(r.n_nodes for r in rois), device="cuda")
+    same = True
+    for i in check:
+        o = ctx.eval_roi(tree, rois[i], out=alone[:rois[i].n_nodes])
+        torch.cuda.synchronize()
+        same &= bool(torch.equal(o, outs[i]))
+    sub["bitwise_alone_vs_served"] = {"requests_checked": len(check), "equal": same}
+    head = {
+        "value": e_timed / dt, "ms_per_step": dt * 1e3 / K, "useful_evals": e_timed,
+        "roofline": {"bound": "alu", "kernel": "k_eval<4,4,4,epanechnikov,uniform>",
+                     "achieved": achieved, "peak": peak, "unit": "T VALU-slot/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(SERVED_TRAFFIC_FILE),
+                     "slots_per_eval": SLOTS_PER_EVAL["epanechnikov"],
+                     "evals_per_launch": e_timed / launches,
+                     "avg_launch_ms": eval_ms / launches, "launches": int(launches),
+                     "note": "achieved = 9 slots x useful evaluations of the timed steps / "
+                             "summed k_eval launch durations (HIP events on each batch's "
+                             "stream; batches on the 4 streams overlap); traffic from the "
+                             "committed counter summary while the kernel sources match"},
+    }
+    if pts_host is not None:
+        log("timing the oracle on sampled nodes of served requests")
+        head["cpu_baseline"] = served_cpu_baseline(pts_host, rois, outs, torch, ctx, tree)
+    tree.close()
+    del outs, alone
+    torch.cuda.empty_cache()
+    return head, sub
+
+
+def per_point_section(ctx, torch, args):
+    """The 10M-point per-point Gaussian step: tree build + k-NN bandwidths +
+    range query + evaluation of the unit-box 128^3 grid, from points resident
+    in HBM (its own roofline: the per-ROI evaluation kernel)."""
+    pts, roi, knn_k, config = workload("per_point_10m")
+    xyz = torch.from_numpy(pts).cuda()
+    out = torch.empty(roi.n_nodes, device="cuda")
+    ctx.profile_enable(True)
+
+    def step():
+        tree = ctx.build_tree(xyz, knn_k=knn_k)
+        ctx.eval_roi(tree, roi, out=out)
+        return tree
+
+    for _ in range(2):
+        step().close()
+        torch.cuda.synchronize()
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    steps = args.per_point_steps
+    t0 = time.perf_counter()
+    for i in range(steps):
+        tree = step()
+        if i + 1 < steps:
+            tree.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    useful, tested = ctx.debug_eval_count(tree, roi)
+    eval_ms = prof["eval_ms"] / max(1, prof["eval_launches"])
+    slots = SLOTS_PER_EVAL[roi.kernel] * useful
+    achieved = slots / (eval_ms * 1e-3) / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    rec = {
+        "config": config, "steps": steps, "ms_per_step": dt * 1e3 / steps,
+        "evals_per_s": useful * steps / dt,
+        "roofline": {"bound": "alu", "kernel": "k_eval<4,4,4,gauss,per-point>",
+                     "achieved": achieved, "peak": peak, "unit": "T VALU-slot/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(),
+                     "slots_per_eval": SLOTS_PER_EVAL[roi.kernel], "evals_per_launch": useful,
+                     "avg_launch_ms": eval_ms},
+        "phases_ms": {k: prof[k] / steps for k in
+                      ("build_ms", "knn_ms", "tile_count_ms", "plan_ms", "tile_fill_ms",
+                       "eval_ms")},
+        "dominant_kernel": {
+            "kernel": "k_knn<32>", "ms_per_step": prof["knn_ms"] / steps,
+            "share_of_step": prof["knn_ms"] / steps / (dt * 1e3 / steps),
+            "bound": "alu (VALU instruction issue)",
+            "valu_busy_profiled": profiled_valu_busy("k_knn<32>")},
+        "eval_only_evals_per_s": useful / (eval_ms * 1e-3),
+        "useful_evals": useful, "tested_pairs": tested,
+        "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
+        "consumers": consumers(ctx, torch, roi, out, xyz),
+    }
+    tree.close()
+    del xyz, out
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -497,100 +776,92 @@ def main():
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    pts, roi, knn_k, config = workload(args.workload)
-    log("workload ready:", config["workload"])
-    xyz = torch.from_numpy(pts).cuda()
     ctx = sfk.Context(0)
-    ctx.profile_enable(True)
-    out = torch.empty(roi.n_nodes, device="cuda")
+    result = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    if args.workload == "served_1b":
+        head, sub = served_headline(ctx, torch, args)
+        result.update({"value": head["value"], "ms_per_step": head["ms_per_step"],
+                       "config": {"workload": "served request loop, 1B clustered points "
+                                              "(tree resident), 8 VR streams x 90 Hz, sides "
+                                              "log-uniform 1e-4..1, grids 32^3-128^3, "
+                                              "Epanechnikov, h = 0.01 x side, HBM-budget "
+                                              "admission; step = 1 s of the trace served at "
+                                              "saturation by continuous batching",
+                                  "n_points": args.serve_points,
+                                  "trace_seconds": args.warmup + args.steps,
+                                  "particle_order": "hilbert"},
+                       "roofline": head["roofline"], "useful_evals": head["useful_evals"]})
+        if "cpu_baseline" in head:
+            result["cpu_baseline"] = head["cpu_baseline"]
+        result["serving"] = sub
+        if not args.no_per_point:
+            log("sub-record: 10M per-point step")
+            result["per_point_10m"] = per_point_section(ctx, torch, args)
+    else:
+        pts, roi, knn_k, config = workload(args.workload)
+        xyz = torch.from_numpy(pts).cuda()
+        out = torch.empty(roi.n_nodes, device="cuda")
+        ctx.profile_enable(True)
 
-    def step():
-        tree = ctx.build_tree(xyz, knn_k=knn_k)
-        ctx.eval_roi(tree, roi, out=out)
-        return tree
+        def step():
+            tree = ctx.build_tree(xyz, knn_k=knn_k)
+            ctx.eval_roi(tree, roi, out=out)
+            return tree
 
-    for i in range(args.warmup):
-        step().close()
+        for i in range(args.warmup):
+            step().close()
+            torch.cuda.synchronize()
+        ctx.profile_read(reset=True)
         torch.cuda.synchronize()
-        log("warmup step", i + 1)
-    ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        tree = step()
-        if i + 1 < args.steps:
-            tree.close()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = ctx.profile_read(reset=True)
-    log("timed %d steps in %.3f s" % (args.steps, dt))
-
-    # untimed: useful pairs of one evaluation and tested pairs
-    useful, tested = ctx.debug_eval_count(tree, roi)
-    ms_per_step = dt * 1e3 / args.steps
-    value = useful * args.steps / dt
-    eval_ms = prof["eval_ms"] / max(1, prof["eval_launches"])
-    slots = SLOTS_PER_EVAL[roi.kernel] * useful
-    achieved = slots / (eval_ms * 1e-3) / 1e12
-    peak = VALU_SLOTS_PER_S / 1e12
-    result = {
-        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic", "config": config,
-        "roofline": {"bound": "alu", "kernel": "k_eval", "achieved": achieved, "peak": peak,
-                     "unit": "T VALU-slot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(),
-                     "slots_per_eval": SLOTS_PER_EVAL[roi.kernel], "evals_per_launch": useful,
-                     "avg_launch_ms": eval_ms},
-        "phases_ms": {k: prof[k] / args.steps for k in
-                      ("build_ms", "knn_ms", "tile_count_ms", "plan_ms", "tile_fill_ms",
-                       "eval_ms")},
-        "dominant_kernel": {
-            "kernel": "k_knn<32>" if knn_k else "k_eval",
-            "ms_per_step": (prof["knn_ms"] if knn_k else prof["eval_ms"]) / args.steps,
-            "share_of_step": (prof["knn_ms"] if knn_k else prof["eval_ms"]) / args.steps
-                             / ms_per_step,
-            "bound": "alu (VALU instruction issue)",
-            "valu_busy_profiled": profiled_valu_busy("k_knn<32>" if knn_k else "k_eval<4, 4, 4, 1, 1"),
-            "note": "roofline above is the per-ROI evaluation kernel (the hot loop the metric "
-                    "counts); the k-NN bandwidth kernel runs once per tree build"},
-        "eval_only_evals_per_s": useful / (eval_ms * 1e-3),
-        "useful_evals": useful, "tested_pairs": tested,
-        "candidate_leaves": prof["last_total_leaves"], "work_items": prof["last_items"],
-    }
-    if args.workload == "per_point_10m":
-        result["consumers"] = consumers(ctx, torch, roi, out, xyz)
-    if not args.no_cpu_baseline:
-        h2 = ctx.debug_point_h2(tree) if knn_k else None
-        log("timing the oracle on a node sample")
-        result["cpu_baseline"] = cpu_baseline(pts, roi, h2, args.cpu_sample_nodes)
-    tree.close()
-    del xyz, out
-    torch.cuda.empty_cache()
-    if args.workload == "per_point_10m" and not (args.no_batch and args.no_view
-                                                 and args.no_zoom):
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            tree = step()
+            if i + 1 < args.steps:
+                tree.close()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read(reset=True)
+        useful, tested = ctx.debug_eval_count(tree, roi)
+        eval_ms = prof["eval_ms"] / max(1, prof["eval_launches"])
+        achieved = SLOTS_PER_EVAL[roi.kernel] * useful / (eval_ms * 1e-3) / 1e12
+        peak = VALU_SLOTS_PER_S / 1e12
+        result.update({"value": useful * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+                       "config": config,
+                       "roofline": {"bound": "alu", "kernel": "k_eval", "achieved": achieved,
+                                    "peak": peak, "unit": "T VALU-slot/s",
+                                    "frac": achieved / peak,
+                                    "traffic": measured_traffic() if knn_k else None,
+                                    "slots_per_eval": SLOTS_PER_EVAL[roi.kernel],
+                                    "evals_per_launch": useful, "avg_launch_ms": eval_ms},
+                       "useful_evals": useful, "tested_pairs": tested})
+        if not args.no_cpu_baseline:
+            h2 = ctx.debug_point_h2(tree) if knn_k else None
+            log("timing the oracle on a node sample")
+            result["cpu_baseline"] = cpu_baseline(pts, roi, h2, args.cpu_sample_nodes)
+        tree.close()
+        del xyz, out
+        torch.cuda.empty_cache()
+    if args.workload != "small" and not (args.no_batch and args.no_zoom and not args.view):
         def on_100m(t, lab, info):
             rec = {}
             if not args.no_batch:
                 rec["batch_vs_single"] = batch_vs_single(ctx, t, torch, args.n_batch, lab)
-            if not args.no_view:
+            if args.view:
                 rec["view_cache"] = view_cache(ctx, t, torch, lab, info)
                 rec["adaptive_resolution"] = adaptive(ctx, t, torch, lab)
             if not args.no_zoom:
                 rec["nested_zoom"] = nested_zoom(ctx, t, torch, lab, info)
                 ctx.profile_enable(True)
                 rec["mbe"] = mbe_rois(ctx, t, torch, lab, info)
+                ctx.profile_enable(False)
             return rec
         rec = large_section(ctx, torch, args.batch_points, 3, on_100m)
         if "error" in rec:
             result["batch_vs_single"] = rec
         else:
             result.update(rec)
-    if args.workload == "per_point_10m" and not args.no_serve:
-        result["serving"] = large_section(
-            ctx, torch, args.serve_points, 5,
-            lambda t, lab, info: serving(ctx, t, torch, args.serve_seconds, lab))
     ctx.close()
     print(json.dumps(result), flush=True)
 

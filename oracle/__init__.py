@@ -73,8 +73,26 @@ def _lib():
         lib.orc_select_points.restype = C.c_int64
         lib.orc_iso_cells.argtypes = [vp, vp, C.c_double, vp, vp]
         lib.orc_iso_cells.restype = C.c_int64
+        lib.orc_mc_case.argtypes = [C.c_int, vp]
+        lib.orc_mc_case.restype = C.c_int
+        lib.orc_iso_surface.argtypes = [vp, vp, vp, vp, C.c_double, vp, C.c_int64]
+        lib.orc_iso_surface.restype = C.c_int64
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = None
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = C.c_int
         _LIB = lib
     return _LIB
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (timing only; results do not
+    depend on it)."""
+    _lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_lib().orc_max_threads())
 
 
 def _ptr(a):
@@ -441,3 +459,21 @@ def iso_cells(grid: np.ndarray, roi, iso: float):
     cases = np.zeros(max(1, n_cells), dtype=np.uint8)
     m = _lib().orc_iso_cells(_ptr(grid), _ptr(res), float(iso), _ptr(cells), _ptr(cases))
     return cells[:m].copy(), cases[:m].copy()
+
+
+def mc_case(case: int) -> np.ndarray:
+    """Marching Cubes triangles of one 8-bit case as (n, 3) edge ids."""
+    e = np.zeros(36, dtype=np.int32)
+    n = _lib().orc_mc_case(int(case), _ptr(e))
+    return e[:3 * n].reshape(n, 3).copy()
+
+
+def iso_surface(grid: np.ndarray, roi, iso: float) -> np.ndarray:
+    """Marching Cubes iso-surface of a node grid: (n, 3, 3) float32
+    triangles (vertex, xyz), cells in ascending order."""
+    grid = _f64(grid).ravel()
+    lo, hi, res = _geom(roi)
+    n = _lib().orc_iso_surface(_ptr(grid), _ptr(lo), _ptr(hi), _ptr(res), float(iso), None, 0)
+    out = np.zeros((max(1, n), 3, 3), dtype=np.float32)
+    _lib().orc_iso_surface(_ptr(grid), _ptr(lo), _ptr(hi), _ptr(res), float(iso), _ptr(out), n)
+    return out[:n]

@@ -117,6 +117,12 @@ double orc_u2(double xn, double yn, double zn, float px, float py, float pz,
 /* include  n flags (nonzero = particle takes part), or NULL -> all         */
 /* nodes    node linear indices to evaluate (x fastest), count n_nodes      */
 /* scale    C_K * nu (nu = 1/N or 1)                                        */
+/* Threads of the OpenMP loops below (timing of the oracle on 1 thread and
+ * on all host cores); no effect on any result. */
+#include <omp.h>
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 /* ------------------------------------------------------------------------ */
 void orc_density_nodes(const float* pts, int64_t n, const float* ih_pp,
                        const double* w_pp, const float* ih_u, double w_u,
@@ -447,6 +453,189 @@ int64_t orc_iso_cells(const double* grid, const int* res, double iso, int64_t* c
           cells[m] = i + cx * (j + cy * k);
           cases[m] = (uint8_t)c;
           ++m;
+        }
+      }
+  return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marching Cubes triangles (Section 4.1: the selection volume is the        */
+/* iso-surface the grid's Marching Cubes extraction bounds; Lorensen and     */
+/* Cline 1987). The per-case triangles are derived here from the cube's      */
+/* faces rather than typed in as a table:                                     */
+/*  - corner c = dx + 2 dy + 4 dz is inside when its value is >= iso;        */
+/*  - edge ids: x edges dy + 2 dz, y edges 4 + dx + 2 dz, z edges            */
+/*    8 + dx + 2 dy (the coordinates of the edge's lower corner);            */
+/*  - face (k, v), k the normal axis and v its side, a = (k+1) mod 3,        */
+/*    b = (k+2) mod 3: its corners in counterclockwise order seen from       */
+/*    outside the cube, (a,b) = (0,0),(1,0),(1,1),(0,1) for v = 1 and        */
+/*    (0,0),(0,1),(1,1),(1,0) for v = 0;                                      */
+/*  - on each face every edge crossed from an inside to an outside corner    */
+/*    (in the face's order) is joined to the first crossed edge met going    */
+/*    backwards around the face: one segment on a face with two crossings,   */
+/*    and on a face with four the inside corners are cut off (a rule that    */
+/*    depends on the face alone, so the two cells sharing a face agree and   */
+/*    the surface is closed);                                                 */
+/*  - the segments form closed loops (each crossed edge leaves on one face   */
+/*    and arrives on the other); loops start at their smallest edge, in      */
+/*    ascending order. A loop v0 .. v(L-1) becomes the fan of triangles      */
+/*    (v(s), v(s+i+1), v(s+i)), i = 1 .. L-2 (indices mod L), whose normals  */
+/*    point from the inside to the outside; the apex s is the first vertex   */
+/*    whose fan has no diagonal joining two edges of one cube face (such a   */
+/*    diagonal would lie in the face and not match the neighbouring cell).   */
+/* The vertex on edge (corner p, corner q), p the lower corner along the     */
+/* edge's axis: t = (iso - f_p) / (f_q - f_p), coordinate                    */
+/* x_p + t (x_q - x_p) along that axis and the node coordinates on the       */
+/* other two, in double, rounded once to float.                              */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_MC_MAXT 12
+static int orc_mc_nt[256];
+static signed char orc_mc_edges[256][3 * ORC_MC_MAXT];
+static int orc_mc_built = 0;
+
+static int orc_edge_of(int c0, int c1) {
+  const int d = c0 ^ c1;
+  const int lo = c0 < c1 ? c0 : c1;
+  const int dx = lo & 1, dy = (lo >> 1) & 1, dz = (lo >> 2) & 1;
+  if (d == 1) return dy + 2 * dz;
+  if (d == 2) return 4 + dx + 2 * dz;
+  return 8 + dx + 2 * dy;
+}
+
+/* Do cube edges e and f lie on a common face? An edge along axis k lies on
+ * the faces normal to the other two axes at its own coordinates. */
+static int orc_edges_share_face(int e, int f) {
+  int fa[2][2], fb[2][2];
+  int (*fs[2])[2] = {fa, fb};
+  const int ed[2] = {e, f};
+  for (int w = 0; w < 2; ++w) {
+    const int ax = ed[w] / 4, r = ed[w] % 4;
+    const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+    fs[w][0][0] = o1;
+    fs[w][0][1] = r & 1;
+    fs[w][1][0] = o2;
+    fs[w][1][1] = r >> 1;
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (fa[i][0] == fb[j][0] && fa[i][1] == fb[j][1]) return 1;
+  return 0;
+}
+
+static void orc_mc_build_case(int cs) {
+  int succ[12];
+  int crossed[12];
+  for (int e = 0; e < 12; ++e) succ[e] = -1, crossed[e] = 0;
+  for (int k = 0; k < 3; ++k)
+    for (int v = 0; v < 2; ++v) {
+      const int a = (k + 1) % 3, b = (k + 2) % 3;
+      static const int up[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+      static const int dn[4][2] = {{0, 0}, {0, 1}, {1, 1}, {1, 0}};
+      int q[4], ein[4], fe[4], cr[4];
+      for (int i = 0; i < 4; ++i) {
+        const int* ab = v ? up[i] : dn[i];
+        q[i] = (v << k) | (ab[0] << a) | (ab[1] << b);
+        ein[i] = (cs >> q[i]) & 1;
+      }
+      for (int i = 0; i < 4; ++i) {
+        fe[i] = orc_edge_of(q[i], q[(i + 1) % 4]);
+        cr[i] = ein[i] != ein[(i + 1) % 4];
+        if (cr[i]) crossed[fe[i]] = 1;
+      }
+      for (int i = 0; i < 4; ++i) {
+        if (!(ein[i] && !ein[(i + 1) % 4])) continue;  /* inside -> outside */
+        for (int s = 1; s < 4; ++s) {
+          const int j = (i + 4 - s) % 4;
+          if (cr[j]) {
+            succ[fe[i]] = fe[j];
+            break;
+          }
+        }
+      }
+    }
+  int seen[12] = {0}, nt = 0;
+  for (int e = 0; e < 12; ++e) {
+    if (!crossed[e] || seen[e]) continue;
+    int loop[12], L = 0, x = e;
+    do {
+      seen[x] = 1;
+      loop[L++] = x;
+      x = succ[x];
+    } while (x != e && x >= 0 && L < 12);
+    int apex = 0;
+    for (int st = 0; st < L; ++st) {
+      int ok = 1;
+      for (int i = 2; i + 1 < L; ++i)
+        if (orc_edges_share_face(loop[st], loop[(st + i) % L])) ok = 0;
+      if (ok) {
+        apex = st;
+        break;
+      }
+    }
+    for (int i = 1; i + 1 < L; ++i) {
+      orc_mc_edges[cs][3 * nt] = (signed char)loop[apex];
+      orc_mc_edges[cs][3 * nt + 1] = (signed char)loop[(apex + i + 1) % L];
+      orc_mc_edges[cs][3 * nt + 2] = (signed char)loop[(apex + i) % L];
+      ++nt;
+    }
+  }
+  orc_mc_nt[cs] = nt;
+}
+
+static void orc_mc_build(void) {
+  if (orc_mc_built) return;
+  for (int cs = 0; cs < 256; ++cs) orc_mc_build_case(cs);
+  orc_mc_built = 1;
+}
+
+/* Triangles of one case: writes 3 * n edge ids and returns n. */
+int orc_mc_case(int cs, int* edges) {
+  orc_mc_build();
+  for (int i = 0; i < 3 * orc_mc_nt[cs]; ++i) edges[i] = orc_mc_edges[cs][i];
+  return orc_mc_nt[cs];
+}
+
+/* The iso-surface of the grid: triangles (9 floats each: three vertices)
+ * cell by cell in ascending linear cell index, in the case's order. Writes
+ * the first min(count, cap) and returns the count. */
+int64_t orc_iso_surface(const double* grid, const double* lo, const double* hi, const int* res,
+                        double iso, float* tris, int64_t cap) {
+  orc_mc_build();
+  const int64_t cx = res[0] - 1, cy = res[1] - 1, cz = res[2] - 1;
+  int64_t m = 0;
+  for (int64_t k = 0; k < cz; ++k)
+    for (int64_t j = 0; j < cy; ++j)
+      for (int64_t i = 0; i < cx; ++i) {
+        int cs = 0;
+        double f[8];
+        for (int c = 0; c < 8; ++c) {
+          const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+          f[c] = grid[(i + dx) + (int64_t)res[0] * ((j + dy) + (int64_t)res[1] * (k + dz))];
+          if (f[c] >= iso) cs |= 1 << c;
+        }
+        for (int t = 0; t < orc_mc_nt[cs]; ++t, ++m) {
+          if (m >= cap) continue;
+          for (int vtx = 0; vtx < 3; ++vtx) {
+            const int e = orc_mc_edges[cs][3 * t + vtx];
+            const int axis = e / 4, r = e % 4;
+            int p;
+            if (axis == 0) p = 2 * (r & 1) + 4 * (r >> 1);
+            else if (axis == 1) p = (r & 1) + 4 * (r >> 1);
+            else p = (r & 1) + 2 * (r >> 1);
+            const int q = p | (1 << axis);
+            const double tt = (iso - f[p]) / (f[q] - f[p]);
+            const int64_t ci[3] = {i + (p & 1), j + ((p >> 1) & 1), k + ((p >> 2) & 1)};
+            for (int d = 0; d < 3; ++d) {
+              const double x0 = orc_node_coord(lo[d], hi[d], res[d], (int)ci[d]);
+              double x = x0;
+              if (d == axis) {
+                const double x1 = orc_node_coord(lo[d], hi[d], res[d], (int)ci[d] + 1);
+                x = x0 + tt * (x1 - x0);
+              }
+              tris[9 * m + 3 * vtx + d] = (float)x;
+            }
+          }
         }
       }
   return m;
