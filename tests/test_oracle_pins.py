@@ -642,3 +642,110 @@ def test_iso_cells_closed_forms():
     # the threshold itself counts as inside (>=)
     cells, cases = oracle.iso_cells(grid, roi, 1.0)
     assert len(cells) == len(want)
+
+
+# ---------------------------------------------------------------------------
+# Marching Cubes iso-surface (Section 4.1): closed forms on a sphere, a closed
+# and consistently oriented mesh on random fields, a hand-worked cell
+# ---------------------------------------------------------------------------
+
+def _sphere_grid(res, centre, scale=1.0):
+    ax = np.arange(res) / (res - 1)
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
+    return (-scale * r2).astype(np.float32).ravel()
+
+
+def _area_volume(tris):
+    t = tris.astype(np.float64)
+    a, b, c = t[:, 0], t[:, 1], t[:, 2]
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1).sum()
+    vol = np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0  # outward normals: > 0
+    return area, vol
+
+
+def test_iso_surface_single_cell_golden():
+    # one cell, corner 0 at +1 (inside), the others at -1, iso 0: the three
+    # edges at corner 0 are cut at their midpoints; the triangle is
+    # (x-edge, y-edge, z-edge) = ((.5,0,0), (0,.5,0), (0,0,.5)), its normal
+    # (b - a) x (c - a) = (1,1,1)/4 pointing away from the inside corner
+    roi = Roi((0, 0, 0), (1, 1, 1), (2, 2, 2))
+    g = -np.ones(8, dtype=np.float32)
+    g[0] = 1.0
+    tris = oracle.iso_surface(g, roi, 0.0)
+    assert tris.shape == (1, 3, 3)
+    np.testing.assert_array_equal(tris[0], [[0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]])
+    assert np.array_equal(oracle.mc_case(1), [[0, 4, 8]])
+    # no surface in a cell whose corners are all inside or all outside
+    assert len(oracle.mc_case(0)) == 0 and len(oracle.mc_case(255)) == 0
+
+
+@pytest.mark.parametrize("res", [33, 65])
+def test_iso_surface_sphere_area_volume(res):
+    # f = -|x - c|^2, iso = -R^2: a sphere of radius R; the mesh's area and
+    # enclosed volume (divergence theorem) converge to 4 pi R^2 and
+    # 4/3 pi R^3 with the square of the spacing
+    R = 0.3
+    c = (0.5, 0.47, 0.52)
+    roi = Roi((0, 0, 0), (1, 1, 1), (res, res, res))
+    tris = oracle.iso_surface(_sphere_grid(res, c), roi, -R * R)
+    area, vol = _area_volume(tris)
+    s = 1.0 / (res - 1)
+    ea = abs(area / (4 * math.pi * R * R) - 1)
+    ev = abs(vol / (4 / 3 * math.pi * R ** 3) - 1)
+    bound = 2.0 * (s / R) ** 2
+    assert ea < bound and ev < bound, (ea, ev, bound)
+
+
+def _directed_edges(tris):
+    v = tris.reshape(-1, 3, 3)
+    keys = {}
+    for t in v:
+        pts = [tuple(p) for p in t]
+        for i in range(3):
+            e = (pts[i], pts[(i + 1) % 3])
+            keys[e] = keys.get(e, 0) + 1
+    return keys
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_iso_surface_closed_and_oriented(seed):
+    # a random smooth field that is below iso on the grid's faces: every
+    # mesh edge is shared by exactly two triangles traversing it in opposite
+    # directions (closed, consistently oriented; ambiguous faces are
+    # resolved alike by the two cells that share them); Euler
+    # characteristic V - E + F = 2 per closed component without handles
+    res = 21
+    g = np.random.default_rng(seed)
+    f = g.standard_normal((res, res, res))
+    for _ in range(2):  # smooth a little
+        f = (f + np.roll(f, 1, 0) + np.roll(f, 1, 1) + np.roll(f, 1, 2)) / 4
+    f[0, :, :] = f[-1, :, :] = f[:, 0, :] = f[:, -1, :] = f[:, :, 0] = f[:, :, -1] = -10.0
+    roi = Roi((0, 0, 0), (1, 1, 1), (res, res, res))
+    tris = oracle.iso_surface(f.astype(np.float32).ravel(), roi, 0.05)
+    assert len(tris) > 100
+    d = _directed_edges(tris)
+    for (a, b), k in d.items():
+        assert k == 1, "directed edge used %d times" % k
+        assert d.get((b, a), 0) == 1, "edge without its opposite"
+    verts = {p for t in tris for p in map(tuple, t)}
+    E = len(d) // 2
+    chi = len(verts) - E + len(tris)
+    assert chi % 2 == 0
+    # volume enclosed is positive with outward normals
+    assert _area_volume(tris)[1] > 0
+
+
+def test_iso_surface_two_spheres_euler():
+    res = 41
+    roi = Roi((0, 0, 0), (1, 1, 1), (res, res, res))
+    # centres and radius off the lattice, so no node value equals iso
+    a = _sphere_grid(res, (0.3103, 0.4971, 0.5033))
+    b = _sphere_grid(res, (0.7211, 0.5087, 0.4923))
+    f = np.maximum(a, b)
+    tris = oracle.iso_surface(f, roi, -0.1487 ** 2)
+    d = _directed_edges(tris)
+    assert all(k == 1 and d.get((b_, a_), 0) == 1 for (a_, b_), k in d.items())
+    verts = {p for t in tris for p in map(tuple, t)}
+    assert len(verts) - len(d) // 2 + len(tris) == 4  # two spheres
