@@ -334,6 +334,22 @@ sfk_status sfk_iso_cells(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid, d
                          int64_t* d_cells, uint8_t* d_cases, int64_t cap, int64_t* h_count,
                          void* hip_stream);
 
+/* The Marching Cubes iso-surface of the grid at iso (Section 4.1: the
+ * selection volume is the region this surface bounds; Lorensen and Cline
+ * 1987), as a triangle soup: 9 floats per triangle (three vertices x, y, z),
+ * cell by cell in ascending linear cell index, each cell's triangles in its
+ * case's order. The per-case triangles follow one rule computed from the
+ * cube's faces (case bits as sfk_iso_cells; on a face with four crossed
+ * edges the inside corners are cut off, so neighbouring cells agree and the
+ * surface is closed where it does not meet the grid's boundary); normals
+ * (v1 - v0) x (v2 - v0) point from values >= iso to values below. A vertex
+ * on the edge from corner p (lower along the edge) to corner q sits at
+ * x_p + t (x_q - x_p), t = (iso - f_p) / (f_q - f_p), in double, rounded once
+ * to float. Writes the first min(count, cap) triangles to d_tris (device,
+ * 9 * cap floats) and the count to *h_count; blocks on the stream. */
+sfk_status sfk_iso_surface(sfk_ctx ctx, const sfk_roi* roi, const float* d_grid, double iso,
+                           float* d_tris, int64_t cap, int64_t* h_count, void* hip_stream);
+
 /* ------------------------------------------------- view cache (reuse) */
 /* Recomputation policy of an interactive view (Section 6.3, limitations and
  * future work: recompute only when the scale changes by more than a
@@ -500,6 +516,11 @@ sfk_status sfk_debug_tile_leaves(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
 /* Leaf boxes of the tree: h_boxes[6 i .. 6 i + 5] = lo xyz, hi xyz of leaf i
  * (leaf i holds particle slots 64 i .. 64 i + 63 in curve order). */
 sfk_status sfk_debug_leaf_boxes(sfk_ctx ctx, sfk_tree tree, float* h_boxes);
+/* Host-only (no device work): the Marching Cubes triangles sfk_iso_surface
+ * uses for case cs (0..255): *n_tri triangles, 3 * n_tri edge ids in
+ * h_edges (room for 15; edge ids as sfk_iso_surface describes: along x
+ * dy + 2 dz, along y 4 + dx + 2 dz, along z 8 + dx + 2 dy). */
+sfk_status sfk_debug_mc_case(int32_t cs, int8_t* h_edges, int32_t* n_tri);
 /* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel. */
 sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* useful_pairs, int64_t* tested_pairs);

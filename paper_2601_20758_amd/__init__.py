@@ -381,6 +381,24 @@ class Context:
                                             _stream_ptr(stream)))
         return cells[:cnt.value], cases[:cnt.value]
 
+    def iso_surface(self, roi, grid, iso: float, cap: Optional[int] = None, stream=None):
+        """sfk_iso_surface: the Marching Cubes triangles as an (n, 3, 3)
+        float32 device tensor (a first call counts them when cap is None)."""
+        import torch
+        self._grid_args(roi, grid)
+        cnt = C.c_int64()
+        r = roi_struct(roi, 0)
+        if cap is None:
+            self._check(self._lib.sfk_iso_surface(self._h, C.byref(r), grid.data_ptr(),
+                                                  float(iso), None, 0, C.byref(cnt),
+                                                  _stream_ptr(stream)))
+            cap = cnt.value
+        tris = torch.empty((max(1, cap), 3, 3), dtype=torch.float32, device=grid.device)
+        self._check(self._lib.sfk_iso_surface(self._h, C.byref(r), grid.data_ptr(), float(iso),
+                                              tris.data_ptr(), cap, C.byref(cnt),
+                                              _stream_ptr(stream)))
+        return tris[:min(cnt.value, cap)]
+
     def debug_poison(self, bits: int):
         """sfk_debug_poison: test-only out-of-range leaf ids (see the header)."""
         self._check(self._lib.sfk_debug_poison(self._h, int(bits)))

@@ -140,6 +140,9 @@ EXPORTS = {
                                     C.POINTER(C.c_int64), C.c_void_p]),
     "sfk_iso_cells": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_double, C.c_void_p,
                                 C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
+    "sfk_debug_mc_case": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "sfk_iso_surface": (C.c_int, [C.c_void_p, C.POINTER(RoiC), C.c_void_p, C.c_double,
+                                  C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
     "sfk_view_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ViewOpts),
                                   C.POINTER(C.c_void_p)]),
     "sfk_view_destroy": (C.c_int, [C.c_void_p]),

@@ -131,6 +131,190 @@ __global__ __launch_bounds__(256) void k_compact_cells(const int32_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Marching Cubes triangles (Section 4.1; Lorensen and Cline 1987). The case
+// table is computed at compile time from the cube's faces:
+//   corner c = dx + 2 dy + 4 dz, inside when its value is >= iso;
+//   edge ids: along x dy + 2 dz, along y 4 + dx + 2 dz, along z 8 + dx + 2 dy;
+//   each face walked counterclockwise as seen from outside the cube
+//   (face normal k, side v, a = k+1, b = k+2 mod 3: (a, b) corners
+//   00, 10, 11, 01 for v = 1, 00, 01, 11, 10 for v = 0);
+//   an edge crossed inside -> outside in that walk is joined to the nearest
+//   crossed edge before it in the walk (faces with four crossings cut off
+//   their inside corners: the rule sees only the face, so both cells of a
+//   face agree and the surface is closed);
+//   the joins form loops, started at their smallest edge, in ascending
+//   order; a loop w0 .. w(L-1) is fanned from the first apex a whose
+//   diagonals never join two edges of one face, as the triangles
+//   (w(a), w(a+i+1), w(a+i)), i = 1 .. L-2: normals point outward (from
+//   values >= iso to values below).
+// Vertex on an edge from its lower corner p to q: t = (iso - f_p) /
+// (f_q - f_p), coordinate x_p + t (x_q - x_p) on the edge's axis, node
+// coordinates on the others, in double, rounded once to float.
+// ---------------------------------------------------------------------------
+
+struct McCases {
+  int8_t ntri[256];
+  int8_t edge[256][15];
+};
+
+// edge between corners c and c ^ (1 << axis)
+constexpr int mc_edge(int c, int axis) {
+  const int x = c & 1, y = (c >> 1) & 1, z = (c >> 2) & 1;
+  return axis == 0 ? y + 2 * z : axis == 1 ? 4 + x + 2 * z : 8 + x + 2 * y;
+}
+
+// the two faces (normal axis, side) an edge lies on, as axis * 2 + side
+constexpr bool mc_common_face(int e, int f) {
+  int fe[2] = {0, 0}, ff[2] = {0, 0};
+  const int es[2] = {e, f};
+  for (int w = 0; w < 2; ++w) {
+    const int axis = es[w] >> 2, bits = es[w] & 3;
+    const int n0 = axis == 0 ? 1 : 0;  // the lower of the two other axes
+    const int n1 = axis == 2 ? 1 : 2;  // the upper one
+    int* out = w == 0 ? fe : ff;
+    out[0] = n0 * 2 + (bits & 1);
+    out[1] = n1 * 2 + (bits >> 1);
+  }
+  return fe[0] == ff[0] || fe[0] == ff[1] || fe[1] == ff[0] || fe[1] == ff[1];
+}
+
+constexpr McCases mc_cases() {
+  McCases t{};
+  for (int cs = 0; cs < 256; ++cs) {
+    int next[12] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    bool cut[12] = {};
+    for (int k = 0; k < 3; ++k)
+      for (int v = 0; v < 2; ++v) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        int corner[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) {
+          // counterclockwise from outside: (0,0),(1,0),(1,1),(0,1) on the
+          // upper face, reversed (0,0),(0,1),(1,1),(1,0) on the lower one
+          const int ua = (i == 1 || i == 2) ? 1 : 0, ub = (i >= 2) ? 1 : 0;
+          const int ca = v ? ua : ub, cb = v ? ub : ua;
+          corner[i] = (v << k) | (ca << a) | (cb << b);
+        }
+        bool in[4] = {}, crossed[4] = {};
+        int edge[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) in[i] = ((cs >> corner[i]) & 1) != 0;
+        for (int i = 0; i < 4; ++i) {
+          const int c0 = corner[i], c1 = corner[(i + 1) & 3];
+          const int d = c0 ^ c1;
+          const int axis = d == 1 ? 0 : d == 2 ? 1 : 2;
+          edge[i] = mc_edge(c0 & ~d, axis);
+          crossed[i] = in[i] != in[(i + 1) & 3];
+          if (crossed[i]) cut[edge[i]] = true;
+        }
+        for (int i = 0; i < 4; ++i) {
+          if (!(in[i] && !in[(i + 1) & 3])) continue;
+          for (int back = 1; back < 4; ++back) {
+            const int j = (i + 4 - back) & 3;
+            if (crossed[j]) {
+              next[edge[i]] = edge[j];
+              break;
+            }
+          }
+        }
+      }
+    bool used[12] = {};
+    int n = 0;
+    for (int e0 = 0; e0 < 12; ++e0) {
+      if (!cut[e0] || used[e0]) continue;
+      int w[12] = {}, len = 0;
+      for (int x = e0; len < 12;) {
+        used[x] = true;
+        w[len++] = x;
+        x = next[x];
+        if (x == e0 || x < 0) break;
+      }
+      int apex = 0;
+      for (int a = 0; a < len; ++a) {
+        bool clean = true;
+        for (int i = 2; i + 1 < len; ++i)
+          if (mc_common_face(w[a], w[(a + i) % len])) clean = false;
+        if (clean) {
+          apex = a;
+          break;
+        }
+      }
+      for (int i = 1; i + 1 < len; ++i) {
+        t.edge[cs][3 * n] = (int8_t)w[apex];
+        t.edge[cs][3 * n + 1] = (int8_t)w[(apex + i + 1) % len];
+        t.edge[cs][3 * n + 2] = (int8_t)w[(apex + i) % len];
+        ++n;
+      }
+    }
+    t.ntri[cs] = (int8_t)n;
+  }
+  return t;
+}
+
+__constant__ McCases kMcCases = mc_cases();
+
+// the same table on the host (test export)
+int mc_case_host(int cs, int8_t* edges) {
+  static constexpr McCases t = mc_cases();
+  for (int i = 0; i < 3 * t.ntri[cs]; ++i) edges[i] = t.edge[cs][i];
+  return t.ntri[cs];
+}
+
+// triangles of each cell (from the cell's case)
+__global__ __launch_bounds__(256) void k_iso_tri_count(const uint8_t* __restrict__ case_all,
+                                                       int64_t n_cells,
+                                                       int32_t* __restrict__ cnt) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_cells;
+       q += (int64_t)gridDim.x * blockDim.x)
+    cnt[q] = kMcCases.ntri[case_all[q]];
+}
+
+__device__ __forceinline__ double node_x(const GridGeom& g, int k, int64_t i) {
+  return g.lo[k] + ((double)i * (g.hi[k] - g.lo[k])) / (double)(g.res[k] - 1);
+}
+
+// the triangles of every cell at their offsets (the first `cap` of them):
+// 9 floats each, three vertices (x, y, z)
+__global__ __launch_bounds__(256) void k_iso_emit(const float* __restrict__ grid, GridGeom g,
+                                                  double iso, const uint8_t* __restrict__ case_all,
+                                                  const int64_t* __restrict__ pos,
+                                                  int64_t n_cells, float* __restrict__ tris,
+                                                  int64_t cap) {
+  const int64_t cx = g.res[0] - 1, cy = g.res[1] - 1;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_cells;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int cs = case_all[q];
+    const int nt = kMcCases.ntri[cs];
+    if (nt == 0) continue;
+    const int64_t base = pos[q];
+    if (base >= cap) continue;
+    const int64_t ci[3] = {q % cx, (q / cx) % cy, q / (cx * cy)};
+    double f[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      f[c] = (double)grid[(ci[0] + (c & 1)) +
+                          (int64_t)g.res[0] * ((ci[1] + ((c >> 1) & 1)) +
+                                               (int64_t)g.res[1] * (ci[2] + ((c >> 2) & 1)))];
+    for (int tr = 0; tr < nt && base + tr < cap; ++tr) {
+      float* out = tris + 9 * (base + tr);
+      for (int vtx = 0; vtx < 3; ++vtx) {
+        const int e = kMcCases.edge[cs][3 * tr + vtx];
+        const int axis = e >> 2, bits = e & 3;
+        // lower corner of the edge: its two other coordinates from the id
+        const int o0 = axis == 0 ? 1 : 0, o1 = axis == 2 ? 1 : 2;
+        const int p = ((bits & 1) << o0) | ((bits >> 1) << o1);
+        const int qc = p | (1 << axis);
+        const double t = (iso - f[p]) / (f[qc] - f[p]);
+        for (int d = 0; d < 3; ++d) {
+          const int64_t idx = ci[d] + ((p >> d) & 1);
+          double x = node_x(g, d, idx);
+          if (d == axis) x = x + t * (node_x(g, d, idx + 1) - x);
+          out[3 * vtx + d] = (float)x;
+        }
+      }
+    }
+  }
+}
+
 // Lattice nodes g0 + (i, j, k) of a view, copied out of cached blocks of B^3
 // nodes (x fastest inside a block). table[] holds the cache slot of each
 // block of the range b0 .. b0 + nb - 1 (x fastest); every node of the grid
@@ -263,6 +447,24 @@ hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_compact_cells, dim3(grid_of(n)), dim3(256), 0, s, flags, pos, case_all, n,
                      cells, cases, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_tri_count(const uint8_t* case_all, int64_t n_cells, int32_t* cnt,
+                                hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iso_tri_count, dim3(grid_of(n_cells)), dim3(256), 0, s, case_all, n_cells,
+                     cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_emit(const float* grid, const double lo[3], const double hi[3],
+                           const int32_t res[3], double iso, const uint8_t* case_all,
+                           const int64_t* pos, int64_t n_cells, float* tris, int64_t cap,
+                           hipStream_t s) {
+  if (n_cells <= 0 || cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iso_emit, dim3(grid_of(n_cells)), dim3(256), 0, s, grid,
+                     geom_of(lo, hi, res), iso, case_all, pos, n_cells, tris, cap);
   return hipGetLastError();
 }
 

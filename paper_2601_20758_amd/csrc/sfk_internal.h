@@ -133,6 +133,17 @@ hipError_t launch_iso_flags(const float* grid, const int32_t res[3], double iso,
 hipError_t launch_compact_cells(const int32_t* flags, const int64_t* pos, const uint8_t* case_all,
                                 int64_t n, int64_t* cells, uint8_t* cases, int64_t cap,
                                 hipStream_t s);
+// Marching Cubes triangles: per-cell counts from the cases, then 9 floats per
+// triangle at the cells' exclusive-scan offsets (the first `cap` triangles)
+// the Marching Cubes case table the kernels use, read on the host:
+// 3 * n edge ids of case cs, returns n
+int mc_case_host(int cs, int8_t* edges);
+hipError_t launch_iso_tri_count(const uint8_t* case_all, int64_t n_cells, int32_t* cnt,
+                                hipStream_t s);
+hipError_t launch_iso_emit(const float* grid, const double lo[3], const double hi[3],
+                           const int32_t res[3], double iso, const uint8_t* case_all,
+                           const int64_t* pos, int64_t n_cells, float* tris, int64_t cap,
+                           hipStream_t s);
 
 // scan.hip
 hipError_t scan_exclusive_i32_i64(const int32_t* in, int64_t* out, int64_t n,

@@ -2308,6 +2308,54 @@ sfk_status sfk_iso_cells(sfk_ctx c, const sfk_roi* roi, const float* d_grid, dou
   SFK_GUARD_END(c)
 }
 
+sfk_status sfk_iso_surface(sfk_ctx c, const sfk_roi* roi, const float* d_grid, double iso,
+                           float* d_tris, int64_t cap, int64_t* h_count, void* hip_stream) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  SFK_TRY(validate_grid_args(c, roi, d_grid, 0, nullptr, nullptr));
+  if (!h_count || cap < 0 || (cap > 0 && !d_tris) || !std::isfinite(iso)) {
+    set_err(c, "invalid iso-surface arguments");
+    return SFK_E_INVAL;
+  }
+  const int64_t nc = (int64_t)(roi->res[0] - 1) * (roi->res[1] - 1) * (roi->res[2] - 1);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TmpBuf flags(c), cnt(c), pos(c), cases(c), tmp(c), total(c);
+  sfk_status st;
+  if ((st = flags.get(sizeof(int32_t) * (size_t)nc, "cell flags")) != SFK_OK ||
+      (st = cnt.get(sizeof(int32_t) * (size_t)nc, "cell triangle counts")) != SFK_OK ||
+      (st = pos.get(sizeof(int64_t) * (size_t)nc, "cell offsets")) != SFK_OK ||
+      (st = cases.get((size_t)nc, "cell cases")) != SFK_OK ||
+      (st = tmp.get(sfk::scan_tmp_bytes(nc), "scan scratch")) != SFK_OK ||
+      (st = total.get(sizeof(int64_t), "triangle count")) != SFK_OK)
+    return st;
+  int64_t n = 0;
+  if (sfk::launch_iso_flags(d_grid, roi->res, iso, nc, flags.as<int32_t>(), cases.as<uint8_t>(),
+                            s) != hipSuccess ||
+      sfk::launch_iso_tri_count(cases.as<uint8_t>(), nc, cnt.as<int32_t>(), s) != hipSuccess ||
+      sfk::scan_exclusive_i32_i64(cnt.as<int32_t>(), pos.as<int64_t>(), nc, total.as<int64_t>(),
+                                  tmp.b.p, tmp.b.bytes, s) != hipSuccess ||
+      sfk::launch_iso_emit(d_grid, roi->lo, roi->hi, roi->res, iso, cases.as<uint8_t>(),
+                           pos.as<int64_t>(), nc, d_tris, cap, s) != hipSuccess ||
+      hipMemcpyAsync(&n, total.b.p, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    set_err(c, "iso-surface kernels failed");
+    return SFK_E_DEVICE;
+  }
+  *h_count = n;
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_debug_mc_case(int32_t cs, int8_t* h_edges, int32_t* n_tri) {
+  if (cs < 0 || cs > 255 || !h_edges || !n_tri) {
+    set_err(nullptr, "case must be in 0..255, pointers non-NULL");
+    return SFK_E_INVAL;
+  }
+  *n_tri = sfk::mc_case_host(cs, h_edges);
+  return SFK_OK;
+}
+
 sfk_status sfk_debug_poison(sfk_ctx c, int32_t bits) {
   SFK_TRY(check_ctx(c));
   if (bits < 0 || bits > 3) {

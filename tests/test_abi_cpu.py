@@ -89,3 +89,18 @@ def test_roi_marshalling():
     assert list(r.res) == [128, 128, 128] and r.d_out == 1234
     with pytest.raises(ValueError):
         roi_struct(synth.c1_roi().replace(kernel="triangle"), 1)
+
+
+def test_marching_cubes_table_matches_oracle(lib):
+    # the library's case table (the one its kernels use, read on the host)
+    # against the oracle's own derivation of the same rule, all 256 cases
+    import ctypes as C
+    import numpy as np
+    import oracle
+    buf = (C.c_int8 * 15)()
+    n = C.c_int32()
+    for cs in range(256):
+        assert lib.sfk_debug_mc_case(cs, buf, C.byref(n)) == 0
+        got = np.array(buf[:3 * n.value], dtype=np.int32).reshape(-1, 3)
+        assert np.array_equal(got, oracle.mc_case(cs)), cs
+    assert lib.sfk_debug_mc_case(256, buf, C.byref(n)) == 1
