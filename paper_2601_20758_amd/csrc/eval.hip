@@ -250,7 +250,8 @@ __global__ __launch_bounds__(256) void k_tile_fill(
     const int32_t* __restrict__ tile_cnt, const int32_t* __restrict__ tile_fit,
     const int64_t* __restrict__ leaf_off,
     const int64_t* __restrict__ chunk_off, int32_t* __restrict__ leaves,
-    int32_t* __restrict__ item_tile, int32_t* __restrict__ claims) {
+    int32_t* __restrict__ item_tile, int32_t* __restrict__ claims, double* __restrict__ partials,
+    const int64_t* __restrict__ partial_off) {
   __shared__ int32_t lds_stack[4][SFK_STACK];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t n_tiles = hdr->n_tiles;
@@ -267,12 +268,20 @@ __global__ __launch_bounds__(256) void k_tile_fill(
       const int r = find_roi(rois, n_rois, t);
       const RoiDev& R = rois[r];
       const int64_t lt = t - R.tile_base;
-      const int gi = (int)(lt % R.ntile[0]) * TX + lane % TX;
-      const int gj = (int)((lt / R.ntile[0]) % R.ntile[1]) * TY + (lane / TX) % TY;
-      const int gk = (int)(lt / ((int64_t)R.ntile[0] * R.ntile[1])) * TZ + lane / (TX * TY);
-      if (lane < T && gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
-        R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = 0.0f;
+      const int ti = (int)(lt % R.ntile[0]) * TX, tj = (int)((lt / R.ntile[0]) % R.ntile[1]) * TY;
+      const int tk = (int)(lt / ((int64_t)R.ntile[0] * R.ntile[1])) * TZ;
+      for (int q = lane; q < T; q += 64) {
+        const int gi = ti + q % TX, gj = tj + (q / TX) % TY, gk = tk + q / (TX * TY);
+        if (gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
+          R.out[(int64_t)gi + (int64_t)R.res[0] * ((int64_t)gj + (int64_t)R.res[1] * gk)] = 0.0f;
+      }
       continue;
+    }
+    if (hdr->splat && tile_fit[t] != kModeWalkTile && chunk_off[t + 1] - c0 > 1) {
+      // a brick split over several work items: its integer node sums start at 0
+      constexpr int64_t T = (int64_t)TX * TY * TZ;
+      unsigned long long* sums = (unsigned long long*)(partials) + partial_off[t] * T;
+      for (int64_t i = lane; i < T; i += 64) sums[i] = 0ull;
     }
     if (tile_fit[t] != kModeLists) continue;
     int32_t* out = leaves + leaf_off[t];
@@ -322,6 +331,13 @@ __device__ __forceinline__ int64_t plan_chunks(int64_t cnt, int chunk_leaves) {
   return cnt > 0 ? (cnt + chunk_leaves - 1) / chunk_leaves : 0;
 }
 
+// Partial slots a tile needs: one per chunk when it is split (its chunks'
+// sums are combined in chunk order), or one for a split brick (its chunks
+// add integer node sums into that one slot).
+__device__ __forceinline__ int64_t plan_partials(int64_t nch, int splat) {
+  return nch > 1 ? (splat ? 1 : nch) : 0;
+}
+
 // sum of v over the block (every thread gets it)
 __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
   int64_t tot;
@@ -348,7 +364,7 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_sums(const int32_t* __restrict
   const int64_t cnt = t < n_tiles ? tile_cnt[t] : 0;
   const int64_t nch = plan_chunks(cnt, chunk_leaves);
   const int64_t sl = block_sum(cnt, lds);
-  const int64_t sp = block_sum(t < n_tiles && nch > 1 ? nch : 0, lds);
+  const int64_t sp = block_sum(t < n_tiles ? plan_partials(nch, hdr->splat) : 0, lds);
   if (threadIdx.x == 0) {
     bs[3 * blockIdx.x] = sl;
     bs[3 * blockIdx.x + 1] = sp;
@@ -372,14 +388,15 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_modes(const int32_t* __restric
   const bool v = t < n_tiles;
   const int64_t cnt = v ? tile_cnt[t] : 0;
   const int64_t nch = plan_chunks(cnt, chunk_leaves);
-  const int64_t pneed = v && nch > 1 ? nch : 0;
+  const int64_t pneed = v ? plan_partials(nch, hdr->splat) : 0;
   int64_t tot;
   const int64_t lo = base_l + block_excl_scan<kPlanNT>(cnt, &tot, lds);
   const int64_t po = base_p + block_excl_scan<kPlanNT>(pneed, &tot, lds);
   const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
-  const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
-                   : (fit_p && nch > 1)            ? kModeWalkChunk
-                                                   : kModeWalkTile;
+  // bricks never walk per chunk: their items stay within the list capacity
+  const int mode = (lo + cnt <= leaf_cap && fit_p)    ? kModeLists
+                   : (fit_p && nch > 1 && !hdr->splat) ? kModeWalkChunk
+                                                       : kModeWalkTile;
   const int64_t nit = v && cnt > 0 ? (mode == kModeWalkTile ? 1 : nch) : 0;
   if (v) {
     leaf_off[t] = lo;
@@ -944,6 +961,220 @@ __global__ __launch_bounds__(256) void k_eval(
 }
 
 // ---------------------------------------------------------------------------
+// Brick evaluation by scattering (uniform bandwidths). A workgroup owns a
+// brick of kBrick^3 nodes and keeps one 64-bit integer sum per node in LDS.
+// Each lane takes one particle of a candidate leaf, computes on each axis the
+// range of brick nodes whose distance can be inside the support (rounded
+// outwards by a relative 1e-9, so the range never misses a member), and
+// visits those nodes only: the canonical u2 = (ux^2 + uy^2) + uz^2 in double
+// decides membership exactly as the definition does, and a member adds its
+// kernel value v in [0, 1] as rint(v * 2^31) units with an LDS atomic. The
+// per-particle cost follows the support (about (2h/s)^3 nodes, twice the
+// members) instead of a whole tile, and integer sums are exact, so the grid
+// is the same whatever the order of particles, chunks or workgroups (alone,
+// in any batch, in any evaluation mode). The brick's chunks add their sums
+// into one 64-bit slot per node with global atomics; the last chunk to
+// finish writes the nodes: sum * 2^-31 * scale, rounded once to float.
+// Per term the fixed point adds at most 2^-32 (in units of the kernel's
+// peak) to a node sum.
+// ---------------------------------------------------------------------------
+
+// One wave claims the next work item (XCD-aware slices as in k_eval); -1
+// when every slice is exhausted. `cur` carries the wave's current slice.
+__device__ __forceinline__ int64_t claim_item(int32_t* __restrict__ claims, int64_t n_items,
+                                              int xcd, int sub, int& cur) {
+  const int lane = lane_id();
+  auto slice_at = [&](int pos) { return ((xcd + (pos >> 3)) & 7) * 8 + ((sub + pos) & 7); };
+  auto slice_begin = [&](int sl) { return n_items * sl / kClaimSlices; };
+  while (true) {
+    const int64_t b = slice_begin(cur), e = slice_begin(cur + 1);
+    int idx = 0;
+    if (b < e && lane == 0) idx = atomicAdd(&claims[cur * kClaimStride], 1);
+    idx = __shfl(idx, 0, 64);
+    if (b + idx < e) return b + idx;
+    const int my = slice_at(lane);
+    const int64_t mb = slice_begin(my), me = slice_begin(my + 1);
+    const int seen =
+        __hip_atomic_load(&claims[my * kClaimStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t open = __ballot(mb + seen < me);
+    if (open == 0) return -1;
+    cur = slice_at(__ffsll((unsigned long long)open) - 1);
+  }
+}
+
+// -log2(e)/2 (exp(-u2/2) = exp2(KG * u2)), as in k_eval
+#define SFK_KG64S (-0.72134752044448170368)
+
+template <int KK, bool CNT>
+__global__ __launch_bounds__(256) void k_splat(
+    TreeView tv, const RoiDev* __restrict__ rois, const double* __restrict__ coords,
+    int chunk_leaves, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ chunk_off,
+    const int64_t* __restrict__ partial_off, const int32_t* __restrict__ tile_cnt,
+    const int32_t* __restrict__ tile_fit, const int32_t* __restrict__ leaves,
+    const int32_t* __restrict__ item_tile, double* __restrict__ partials,
+    int32_t* __restrict__ tile_done, BatchHdr* __restrict__ hdr, int32_t* __restrict__ claims) {
+  constexpr int B = kBrick;
+  constexpr int T = B * B * B;
+  __shared__ unsigned long long sums[T];
+  __shared__ double lds_c[3][B];
+  __shared__ int32_t lds_stack[4][SFK_STACK];
+  __shared__ int64_t lds_item;
+  __shared__ int32_t lds_last;
+  unsigned long long* gsum = (unsigned long long*)partials;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t n_items = min(hdr->n_items, hdr->item_cap);
+  const int n_rois = hdr->n_rois;
+  const int xcd = blockIdx.x & 7;
+  const int sub = (int)((blockIdx.x >> 3) & 7);
+  int cur = ((xcd + 0) & 7) * 8 + (sub & 7);
+  while (true) {
+    if (wave == 0) {
+      const int64_t it = claim_item(claims, n_items, xcd, sub, cur);
+      if (lane == 0) lds_item = it;
+    }
+    __syncthreads();
+    const int64_t item = lds_item;
+    if (item < 0) break;
+    const int t = item_tile[item];
+    const TileGeo g = tile_geo<B, B, B>(rois, n_rois, coords, t);
+    const RoiDev& R = rois[g.r];
+    const int n_here[3] = {min(B, R.res[0] - g.i0), min(B, R.res[1] - g.j0),
+                           min(B, R.res[2] - g.k0)};
+    if (threadIdx.x < 3 * B) {
+      const int k = threadIdx.x / B, i = threadIdx.x % B;
+      const int o = k == 0 ? g.i0 : k == 1 ? g.j0 : g.k0;
+      const int off = R.coord_off + (k > 0 ? R.res[0] : 0) + (k > 1 ? R.res[1] : 0);
+      lds_c[k][i] = coords[off + min(o + i, R.res[k] - 1)];
+    }
+    for (int i = threadIdx.x; i < T; i += 256) sums[i] = 0ull;
+    __syncthreads();
+    const double c2 = R.c2;
+    const double lo[3] = {R.lo[0], R.lo[1], R.lo[2]};
+    double inv_s[3], half[3];
+    const int org[3] = {g.i0, g.j0, g.k0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      inv_s[k] = (double)(R.res[k] - 1) / (R.hi[k] - R.lo[k]);
+      // support half-width in node steps, rounded outwards
+      half[k] = sqrt(c2) * inv_s[k] / (double)R.ih[k];
+      half[k] = half[k] * (1.0 + 1e-9) + 1e-9;
+    }
+    const double ih[3] = {(double)R.ih[0], (double)R.ih[1], (double)R.ih[2]};
+
+    // scatter one particle (lane's own) into the brick's node sums
+    auto splat = [&](const float4 p) {
+      const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
+      int a[3], b[3];
+      bool empty = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double ic = (pp[k] - lo[k]) * inv_s[k] - (double)org[k];
+        const double fa = fmax(ceil(ic - half[k]), 0.0);
+        const double fb = fmin(floor(ic + half[k]), (double)(n_here[k] - 1));
+        empty |= !(fa <= fb);
+        a[k] = empty ? 0 : (int)fa;
+        b[k] = empty ? -1 : (int)fb;
+      }
+      if (empty) return;
+      for (int kz = a[2]; kz <= b[2]; ++kz) {
+        const double uz = (lds_c[2][kz] - pp[2]) * ih[2];
+        const double sz = uz * uz;
+        for (int jy = a[1]; jy <= b[1]; ++jy) {
+          const double uy = (lds_c[1][jy] - pp[1]) * ih[1];
+          const double sy = uy * uy;
+          for (int ix = a[0]; ix <= b[0]; ++ix) {
+            const double ux = (lds_c[0][ix] - pp[0]) * ih[0];
+            const double u2 = (ux * ux + sy) + sz;
+            if (u2 < c2) {
+              unsigned int q;
+              if constexpr (CNT) {
+                q = 1u;
+              } else if constexpr (KK == KK_EPAN) {
+                q = (unsigned int)rint((1.0 - u2) * kSplatUnit);
+              } else {
+                const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
+                q = (unsigned int)rint((double)e * kSplatUnit);
+              }
+              atomicAdd(&sums[ix + B * (jy + B * kz)], (unsigned long long)q);
+            }
+          }
+        }
+      }
+    };
+    auto do_leaf = [&](int lid) {
+      const float4 p = tv.pts[(int64_t)lid * SFK_LEAF + lane];
+      splat(p);
+    };
+
+    const int cnt = tile_cnt[t];
+    const int nch = (cnt + chunk_leaves - 1) / chunk_leaves;
+    const int mode = tile_fit[t];
+    const int c = (int)(item - chunk_off[t]);
+    if (mode == kModeLists) {
+      // the chunk's leaves, every fourth to each wave; ids outside the tree
+      // are an internal error (flagged, leaf 0 read instead)
+      const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
+      const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
+      for (int64_t q = lb + wave; q < le; q += 4) {
+        int lid = leaves[q];
+        if ((unsigned)lid >= (unsigned)tv.n_leaves) {
+          if (lane == 0) claims[kErrWord] = 1;
+          lid = 0;
+        }
+        do_leaf(__builtin_amdgcn_readfirstlane(lid));
+      }
+    } else {
+      // walking modes: every wave walks the hierarchy (same order) and takes
+      // every fourth leaf of the item's range
+      const int start = mode == kModeWalkChunk ? c * chunk_leaves : 0;
+      const int stop = mode == kModeWalkChunk ? min(start + chunk_leaves, cnt) : cnt;
+      int done = 0;
+      traverse_until(
+          tv, lds_stack[wave],
+          [&](const NodeBox& b, int gidx) { return tile_box_test(tv, R, g, b, gidx); },
+          [&](int child, bool pass, uint64_t mask) {
+            (void)pass;
+            uint64_t mm = mask;
+            while (mm && done < stop) {
+              const int bl = __ffsll((unsigned long long)mm) - 1;
+              mm &= mm - 1;
+              if (done >= start && ((done - start) & 3) == wave) do_leaf(__shfl(child, bl, 64));
+              ++done;
+            }
+            return done < stop;
+          });
+    }
+    __syncthreads();
+    const double unit = CNT ? 1.0 : 1.0 / kSplatUnit;
+    auto write_node = [&](int n, unsigned long long v) {
+      const int ix = n % B, jy = (n / B) % B, kz = n / (B * B);
+      if (ix < n_here[0] && jy < n_here[1] && kz < n_here[2]) {
+        const int64_t gi = g.i0 + ix, gj = g.j0 + jy, gk = g.k0 + kz;
+        R.out[gi + (int64_t)R.res[0] * (gj + (int64_t)R.res[1] * gk)] =
+            (float)(((double)v * unit) * R.scale);
+      }
+    };
+    if (mode == kModeWalkTile || nch == 1) {
+      for (int n = threadIdx.x; n < T; n += 256) write_node(n, sums[n]);
+    } else {
+      unsigned long long* slot = gsum + partial_off[t] * (int64_t)T;
+      for (int n = threadIdx.x; n < T; n += 256)
+        if (sums[n]) atomicAdd(&slot[n], sums[n]);
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) lds_last = atomicAdd(&tile_done[t], 1) == nch - 1 ? 1 : 0;
+      __syncthreads();
+      if (lds_last) {
+        __threadfence();
+        for (int n = threadIdx.x; n < T; n += 256)
+          write_node(n, __hip_atomic_load(&slot[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // debug: support sets of single nodes (one wavefront per node)
 // ---------------------------------------------------------------------------
 
@@ -1011,12 +1242,17 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
 bool tile_shape_supported(TileShape ts) {
   return (ts.tx == 4 && ts.ty == 4 && (ts.tz == 4 || ts.tz == 2)) ||
          (ts.tx == 4 && ts.ty == 2 && ts.tz == 2) || (ts.tx == 2 && ts.ty == 2 && ts.tz == 2) ||
-         (ts.tx == 1 && ts.ty == 1 && ts.tz == 1);
+         (ts.tx == 1 && ts.ty == 1 && ts.tz == 1) || is_brick(ts);
 }
 
+bool is_brick(TileShape ts) { return ts.tx == kBrick && ts.ty == kBrick && ts.tz == kBrick; }
+
+// every shape of the range query (wavefront tiles and bricks)
 #define SFK_SHAPE_SWITCH(ts, MACRO)                                  \
   do {                                                               \
-    if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 4) {              \
+    if ((ts).tx == kBrick && (ts).ty == kBrick && (ts).tz == kBrick) { \
+      MACRO(kBrick, kBrick, kBrick);                                 \
+    } else if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 4) {       \
       MACRO(4, 4, 4);                                                \
     } else if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 2) {       \
       MACRO(4, 4, 2);                                                \
@@ -1068,14 +1304,15 @@ __global__ __launch_bounds__(kPlanNT) void k_plan_one(const int32_t* __restrict_
   const bool v = t < n_tiles;
   const int64_t cnt = v ? tile_cnt[t] : 0;
   const int64_t nch = plan_chunks(cnt, chunk_leaves);
-  const int64_t pneed = v && nch > 1 ? nch : 0;
+  const int64_t pneed = v ? plan_partials(nch, hdr->splat) : 0;
   int64_t tl, tp, tc;
   const int64_t lo = block_excl_scan<kPlanNT>(cnt, &tl, lds);
   const int64_t po = block_excl_scan<kPlanNT>(pneed, &tp, lds);
   const bool fit_p = pneed == 0 || po + pneed <= partial_cap;
-  const int mode = (lo + cnt <= leaf_cap && fit_p) ? kModeLists
-                   : (fit_p && nch > 1)            ? kModeWalkChunk
-                                                   : kModeWalkTile;
+  // bricks never walk per chunk: their items stay within the list capacity
+  const int mode = (lo + cnt <= leaf_cap && fit_p)    ? kModeLists
+                   : (fit_p && nch > 1 && !hdr->splat) ? kModeWalkChunk
+                                                       : kModeWalkTile;
   const int64_t nit = v && cnt > 0 ? (mode == kModeWalkTile ? 1 : nch) : 0;
   const int64_t co = block_excl_scan<kPlanNT>(nit, &tc, lds);
   if (v) {
@@ -1125,12 +1362,13 @@ hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois
                             const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
                             int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
-                            int32_t* item_tile, int32_t* claims, hipStream_t s) {
+                            int32_t* item_tile, int32_t* claims, double* partials,
+                            const int64_t* partial_off, hipStream_t s) {
   const int nb = std::max(1, grid_blocks);
 #define SFK_L(X, Y, Z)                                                                     \
   hipLaunchKernelGGL((k_tile_fill<X, Y, Z>), dim3(nb), dim3(256), 0, s, tv, hdr, rois,  \
                      coords, roi_leaves, roi_nl, tile_slots, tile_cnt, tile_fit, leaf_off,  \
-                     chunk_off, leaves, item_tile, claims)
+                     chunk_off, leaves, item_tile, claims, partials, partial_off)
   SFK_SHAPE_SWITCH(ts, SFK_L);
 #undef SFK_L
   return hipGetLastError();
@@ -1186,13 +1424,50 @@ hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
                        double* partials, int32_t* tile_done, BatchHdr* hdr, int32_t* claims,
                        int grid_blocks, int n_cu, int max_blocks, hipStream_t s) {
   (void)hdr_c;
+  if (is_brick(ts)) {
+    if (pp != PP_UNIFORM) return hipErrorInvalidValue;
+#define SFK_S(KK, C)                                                                          \
+  do {                                                                                        \
+    static int occ_ = 0;                                                                      \
+    if (occ_ == 0) {                                                                          \
+      int b_ = 0;                                                                             \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b_, k_splat<KK, C>, 256, 0) !=        \
+              hipSuccess ||                                                                   \
+          b_ < 1)                                                                             \
+        b_ = 1;                                                                               \
+      occ_ = b_;                                                                              \
+    }                                                                                         \
+    const int g_ = grid_blocks > 0 ? grid_blocks : std::max(1, std::min(n_cu * occ_, max_blocks)); \
+    hipLaunchKernelGGL((k_splat<KK, C>), dim3(g_), dim3(256), 0, s, tv, rois, coords,         \
+                       chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, tile_fit,    \
+                       leaves, item_tile, partials, tile_done, hdr, claims);                  \
+  } while (0)
+    if (cnt)
+      SFK_S(KK_EPAN, true);
+    else if (kk == KK_EPAN)
+      SFK_S(KK_EPAN, false);
+    else
+      SFK_S(KK_GAUSS, false);
+#undef SFK_S
+    return hipGetLastError();
+  }
 #define SFK_L(X, Y, Z)                                                                        \
   return launch_eval_shape<X, Y, Z>(kk, pp, cnt, grid_blocks, n_cu, max_blocks, s, tv, rois, \
                                     coords,                                                   \
                                     chunk_leaves, leaf_off, chunk_off, partial_off, tile_cnt, \
                                     tile_fit, leaves, item_tile, partials, tile_done, hdr,    \
                                     claims)
-  SFK_SHAPE_SWITCH(ts, SFK_L);
+  if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 4) {
+    SFK_L(4, 4, 4);
+  } else if ((ts).tx == 4 && (ts).ty == 4 && (ts).tz == 2) {
+    SFK_L(4, 4, 2);
+  } else if ((ts).tx == 4 && (ts).ty == 2 && (ts).tz == 2) {
+    SFK_L(4, 2, 2);
+  } else if ((ts).tx == 2 && (ts).ty == 2 && (ts).tz == 2) {
+    SFK_L(2, 2, 2);
+  } else if ((ts).tx == 1 && (ts).ty == 1 && (ts).tz == 1) {
+    SFK_L(1, 1, 1);
+  }
 #undef SFK_L
   return hipErrorInvalidValue;
 }

@@ -75,6 +75,10 @@ struct alignas(16) BatchHdr {
   int32_t debug_poison;  // host, tests only: bit 0 = the count pass stores out-of-range
                          // ids in the slots past the 64th of a tile, bit 1 = the fill
                          // pass stores them in the lists past the 64th entry
+  int32_t splat;         // host: 1 = the tiles are bricks evaluated by scattering into
+                         // integer node sums; a split brick then needs one partial
+                         // slot (its node sums), not one per chunk
+  int32_t pad_;
 };
 
 // Work-claim counters of the evaluation: kClaimSlices counters, one per
@@ -98,8 +102,14 @@ constexpr int kRoiListCap = 256;
 // tile shape: tiles of fewer nodes meet fewer leaves.
 constexpr int kTileSlotCap = 256;
 
-// Tile shapes (wavefront = tx*ty*tz nodes, powers of two).
+// Tile shapes (wavefront = tx*ty*tz nodes, powers of two). The brick shape
+// kBrick^3 is not a wavefront's tile: a workgroup scatters particles into
+// the brick's node sums (uniform bandwidths only).
 struct TileShape { int tx, ty, tz; };
+constexpr int kBrick = 16;
+// Fixed point of the brick's integer node sums: a term v in [0, 1] counts
+// rint(v * 2^31) units (so a sum of up to 2^32 terms fits in 64 bits).
+constexpr double kSplatUnit = 2147483648.0;
 
 // ---- host-side launch wrappers (defined in the .hip files) ----
 namespace sfk {
@@ -220,12 +230,15 @@ hipError_t launch_plan(const int32_t* tile_cnt, BatchHdr* hdr, int32_t* claims, 
                        int64_t* leaf_off, int64_t* partial_off, int64_t* chunk_off,
                        int32_t* tile_fit, int64_t* plan_tmp, int64_t max_tiles, hipStream_t s);
 // claims: the work-claim counters, whose error word the slot copy may set
+// partials/partial_off: bricks (hdr->splat) zero the node sums of their
+// partial slot here when they are split into several work items
 hipError_t launch_tile_fill(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
                             const double* coords, const int32_t* roi_leaves,
                             const int32_t* roi_nl, const int32_t* tile_slots, TileShape ts,
                             int grid_blocks, const int32_t* tile_cnt, const int32_t* tile_fit,
                             const int64_t* leaf_off, const int64_t* chunk_off, int32_t* leaves,
-                            int32_t* item_tile, int32_t* claims, hipStream_t s);
+                            int32_t* item_tile, int32_t* claims, double* partials,
+                            const int64_t* partial_off, hipStream_t s);
 hipError_t launch_eval(TreeView tv, const BatchHdr* hdr_c, const RoiDev* rois,
                        const double* coords, TileShape ts, int kk, int pp, bool cnt,
                        int chunk_leaves, const int64_t* leaf_off, const int64_t* chunk_off,
@@ -238,6 +251,7 @@ hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiD
                                     int64_t node_end, int64_t* cnt, const int64_t* off,
                                     int32_t* idx_out, hipStream_t s);
 bool tile_shape_supported(TileShape ts);
+bool is_brick(TileShape ts);
 int tile_grid_blocks(int64_t n_tiles);
 
 // mbe.hip

@@ -412,7 +412,8 @@ double ck_gauss_trunc3() {
   return 1.0 / (std::pow(2.0 * M_PI, 1.5) * p);
 }
 
-constexpr int kNumShapes = 5;  // tile shapes 1..5 of sfk_eval_opts.tile_shape
+constexpr int kNumShapes = 6;  // tile shapes 1..6 of sfk_eval_opts.tile_shape
+constexpr int kBrickShape = 6;  // bricks of kBrick^3 nodes, scatter evaluation
 
 TileShape shape_of(int id) {
   switch (id) {
@@ -420,9 +421,13 @@ TileShape shape_of(int id) {
     case 3: return TileShape{4, 2, 2};
     case 4: return TileShape{2, 2, 2};
     case 5: return TileShape{1, 1, 1};
+    case 6: return TileShape{kBrick, kBrick, kBrick};
     default: return TileShape{4, 4, 4};
   }
 }
+
+// Bricks evaluate uniform bandwidths only (fixed or ROI-scaled)
+bool uniform_bw(const sfk_roi* r) { return r->bw == SFK_BW_FIXED || r->bw == SFK_BW_ROI_SCALED; }
 
 TreeView view_of(sfk_tree t) {
   TreeView tv{};
@@ -628,6 +633,7 @@ void make_roidev(const std::vector<GroupRoi>& g, TileShape ts, RoiDev* out, int6
 struct Caps {
   int64_t leaf_cap, partial_cap, item_cap, tiles_cap, rois_cap, coords_cap;
   int32_t slot_cap;
+  int32_t splat;
 };
 
 // Leaves the count pass keeps per tile for a tile shape: four per node of
@@ -657,8 +663,14 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   // partial slots are small (T doubles per chunk): room for twice the
   // chunks the leaf lists hold, so a batch whose lists overflow still splits
   // its heavy tiles over work items (walking per chunk)
-  int64_t partial_cap = std::max<int64_t>({ws.want_partial_cap, (int64_t)1 << 14, tiles / 4,
-                                           2 * leaf_cap / CH});
+  const bool brick = sfk::is_brick(ts);
+  // a brick's partial slot holds its kBrick^3 node sums (32 KB): one per
+  // split brick, up to 8192 of them; bricks beyond walk their whole tile in
+  // one work item (which needs no slot)
+  int64_t partial_cap =
+      brick ? std::max<int64_t>(64, std::min<int64_t>(tiles, 8192))
+            : std::max<int64_t>({ws.want_partial_cap, (int64_t)1 << 14, tiles / 4,
+                                 2 * leaf_cap / CH});
   if (c->opts.list_capacity > 0) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
@@ -710,8 +722,11 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   k.slot_cap = slot_cap;
   // work items: one per tile plus one per partial slot (a split tile has one
   // item per chunk and one partial slot per chunk, whether it evaluates its
-  // list or walks per chunk), so the plan can never exceed this
-  k.item_cap = k.tiles_cap + k.partial_cap + 1;
+  // list or walks per chunk), so the plan can never exceed this. A split
+  // brick has one slot for all its chunks and never walks per chunk, so its
+  // extra items are bounded by the listed leaves / chunk_leaves.
+  k.item_cap = k.tiles_cap + k.partial_cap + 1 + (brick ? k.leaf_cap / CH + 1 : 0);
+  k.splat = brick ? 1 : 0;
   SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)k.item_cap, "work items"));
   *caps = k;
   return SFK_OK;
@@ -727,6 +742,7 @@ BatchHdr make_hdr(sfk_ctx c, const Caps& k, int64_t n_rois, int64_t n_tiles) {
   h.item_cap = k.item_cap;
   h.n_rois = (int32_t)n_rois;
   h.slot_cap = k.slot_cap;
+  h.splat = k.splat;
   return h;
 }
 
@@ -767,7 +783,8 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
                                       (const int32_t*)ws.tile_slots.p, ts, tile_grid,
                                       tile_cnt, tile_fit,
                                       leaf_off, chunk_off, (int32_t*)ws.leaves.p,
-                                      (int32_t*)ws.item_tile.p, (int32_t*)ws.claims.p, s));
+                                      (int32_t*)ws.item_tile.p, (int32_t*)ws.claims.p,
+                                      (double*)ws.partials.p, partial_off, s));
   }
   // 0: resident blocks per CU from the occupancy query, capped at one wave
   // per tile (the tile kernels' grid) but at least one block per CU, so a
@@ -1356,11 +1373,16 @@ double particles_per_support(sfk_tree t, const sfk_roi* r) {
 }
 
 TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
-  if (c->opts.tile_shape > 0) return shape_of(c->opts.tile_shape);
-  const int key = tune_key(r);
-  auto it = c->tune.find(key);
-  if (it != c->tune.end()) return shape_of(it->second);
-  return shape_of(default_shape(key, particles_per_support(t, r)));
+  int id = 0;
+  if (c->opts.tile_shape > 0) {
+    id = c->opts.tile_shape;
+  } else {
+    const int key = tune_key(r);
+    auto it = c->tune.find(key);
+    id = it != c->tune.end() ? it->second : default_shape(key, particles_per_support(t, r));
+  }
+  if (id == kBrickShape && !uniform_bw(r)) id = 1;  // bricks need a uniform bandwidth
+  return shape_of(id);
 }
 
 // Launch everything a ticket needs on a slot. CLOUD ROIs go through one
@@ -2019,14 +2041,18 @@ sfk_status sfk_eval_roi_noalloc(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void*
     return SFK_E_BUDGET;
   }
   // what is left: a quarter to partial slots (with their work items), the
-  // rest to leaf-list entries; 3 x 256 bytes of rounding slack
-  const size_t rest = cap - fixed - rb(sizeof(int32_t) * (nt + 1)) - 3 * 256;
+  // rest to leaf-list entries (for bricks, with one work item per
+  // chunk_leaves entries); 4 x 256 bytes of rounding and item slack
+  const bool brick = sfk::is_brick(ts);
+  const int CH = chunk_leaves_of(c);
+  const size_t rest = cap - fixed - rb(sizeof(int32_t) * (nt + 1)) - 4 * 256;
   const int64_t partial_cap =
       std::max<int64_t>(1, (int64_t)(rest / 4 / (sizeof(double) * T + sizeof(int32_t))));
+  const double per_leaf = sizeof(int32_t) * (1.0 + (brick ? 1.0 / CH : 0.0));
   const int64_t leaf_cap = std::max<int64_t>(
-      1, (int64_t)((rest - (size_t)partial_cap * (sizeof(double) * T + sizeof(int32_t))) /
-                   sizeof(int32_t)));
-  const int64_t item_cap = n_tiles + partial_cap + 1;
+      1, (int64_t)((double)(rest - (size_t)partial_cap * (sizeof(double) * T + sizeof(int32_t))) /
+                   per_leaf));
+  const int64_t item_cap = n_tiles + partial_cap + 1 + (brick ? leaf_cap / CH + 1 : 0);
   Workspace wv;  // a view of the scratch array; owns nothing
   size_t used = 0;
   auto take = [&](DevBuf& b, size_t bytes) {
@@ -2062,6 +2088,7 @@ sfk_status sfk_eval_roi_noalloc(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void*
   h.n_rois = 1;
   h.slot_cap = slot_cap;
   h.debug_poison = c->debug_poison;
+  h.splat = brick ? 1 : 0;
   // descriptors through a pinned ring set up at context creation
   const int si = c->na_next;
   c->na_next = (c->na_next + 1) % kStagingRing;
@@ -2682,6 +2709,10 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
     auto& v = cost[key];
     if (v.empty()) v.assign(kNumShapes + 1, 0.0);
     for (int shape = 1; shape <= kNumShapes && st == SFK_OK; ++shape) {
+      if (shape == kBrickShape && !uniform_bw(&sample[i])) {
+        v[shape] = 1e30;  // bricks take uniform bandwidths only
+        continue;
+      }
       c->opts.tile_shape = shape;
       float best = 1e30f;
       for (int rep = 0; rep < 3 && st == SFK_OK; ++rep) {
