@@ -211,7 +211,10 @@ sfk_status sfk_cancel(sfk_ctx ctx, sfk_ticket t);
 /* Tile shape used for tile-granular range queries and evaluation: one
  * wavefront owns tx*ty*tz grid nodes. 0 = chosen by the autotuner table. */
 typedef struct {
-  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2, 5 = 1x1x1 */
+  int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2, 5 = 1x1x1
+                            (a wavefront per tile, gathering), 6 = bricks of 16^3 nodes
+                            (a workgroup per brick scattering particles into exact
+                            integer node sums; uniform bandwidths only, others take 1) */
   int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 256 */
   int32_t persistent_waves_per_cu; /* 0 = automatic */
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
@@ -229,9 +232,23 @@ sfk_status sfk_set_eval_opts(sfk_ctx ctx, const sfk_eval_opts* opts);
  * (kernel, bandwidth mode, support-to-spacing bucket) for later batches. */
 sfk_status sfk_autotune(sfk_ctx ctx, sfk_tree tree, const sfk_roi* sample, int32_t n);
 /* The autotuner's table: up to cap (key, tile shape) pairs, *n_out = entries.
- * key = (kernel * 4 + bandwidth mode) * 8 + support-in-spacings bucket. */
+ * key = ((kernel * 4 + bandwidth mode) * 8 + support-in-spacings bucket) * 8
+ * + particles-per-node bucket (uniform bandwidths: log2 of the particles
+ * estimated in the box widened by the support, per node, plus 4, clamped to
+ * 0..7; 0 for per-point bandwidths). */
 sfk_status sfk_autotune_table(sfk_ctx ctx, int32_t* keys, int32_t* shapes, int32_t cap,
                               int32_t* n_out);
+/* The times the last sfk_autotune measured: per key, ms[i * 6 + s - 1] = the
+ * summed best-of-3 time of tile shape s over that key's samples (1e30 for a
+ * shape the key cannot take). *n_out = keys. */
+sfk_status sfk_autotune_costs(sfk_ctx ctx, int32_t* keys, double* ms, int32_t cap,
+                              int32_t* n_out);
+/* Persist the table to a text file, with the device architecture (e.g.
+ * gfx950) it was measured on; loading a table merges its entries, and a
+ * table of another architecture is refused (SFK_E_UNSUPPORTED). SFK_E_INVAL
+ * for unreadable or malformed files. */
+sfk_status sfk_autotune_save(sfk_ctx ctx, const char* path);
+sfk_status sfk_autotune_load(sfk_ctx ctx, const char* path);
 
 /* -------------------------------------------------------------- profiling */
 

@@ -235,6 +235,21 @@ class Context:
         self._check(self._lib.sfk_autotune_table(self._h, keys, shapes, n.value, C.byref(n)))
         return {keys[i]: shapes[i] for i in range(n.value)}
 
+    def autotune_costs(self) -> dict:
+        """sfk_autotune_costs: key -> [ms of shapes 1..6]."""
+        n = C.c_int32()
+        self._check(self._lib.sfk_autotune_costs(self._h, None, None, 0, C.byref(n)))
+        keys = (C.c_int32 * max(1, n.value))()
+        ms = (C.c_double * (6 * max(1, n.value)))()
+        self._check(self._lib.sfk_autotune_costs(self._h, keys, ms, n.value, C.byref(n)))
+        return {keys[i]: [ms[6 * i + j] for j in range(6)] for i in range(n.value)}
+
+    def autotune_save(self, path: str):
+        self._check(self._lib.sfk_autotune_save(self._h, path.encode()))
+
+    def autotune_load(self, path: str):
+        self._check(self._lib.sfk_autotune_load(self._h, path.encode()))
+
     def serve(self, tree: "Tree", arrivals: Sequence[float], rois: Sequence, outs: Sequence,
               mode: int = 0, n_slots: int = 4, max_batch: int = 64, budget_bytes: float = 0.0):
         """sfk_serve over a request trace; returns (per-request results, summary)."""

@@ -125,6 +125,10 @@ EXPORTS = {
     "sfk_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_int32]),
     "sfk_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.c_int32, C.POINTER(C.c_int32)]),
+    "sfk_autotune_costs": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.c_int32, C.POINTER(C.c_int32)]),
+    "sfk_autotune_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "sfk_autotune_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "sfk_serve": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Request), C.c_int64,
                             C.POINTER(ServeOpts), C.POINTER(RequestResult),
                             C.POINTER(ServeSummary)]),

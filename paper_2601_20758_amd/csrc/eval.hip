@@ -1076,13 +1076,27 @@ __global__ __launch_bounds__(256) void k_splat(
         b[k] = empty ? -1 : (int)fb;
       }
       if (empty) return;
-      for (int kz = a[2]; kz <= b[2]; ++kz) {
+      // Lanes of a leaf often share their range: each lane starts its walk
+      // over the range at its own rotation (lane mod the range size per
+      // axis), so the atomics of one instruction spread over the range's
+      // nodes instead of queueing on one.
+      const int nx = b[0] - a[0] + 1, ny = b[1] - a[1] + 1, nz = b[2] - a[2] + 1;
+      const int rx = lane % nx, ry = (lane >> 2) % ny, rz = (lane >> 4) % nz;
+      for (int dz = 0; dz < nz; ++dz) {
+        int kz = a[2] + dz + rz;
+        kz = kz > b[2] ? kz - nz : kz;
         const double uz = (lds_c[2][kz] - pp[2]) * ih[2];
         const double sz = uz * uz;
-        for (int jy = a[1]; jy <= b[1]; ++jy) {
+        for (int dy = 0; dy < ny; ++dy) {
+          int jy = a[1] + dy + ry;
+          jy = jy > b[1] ? jy - ny : jy;
           const double uy = (lds_c[1][jy] - pp[1]) * ih[1];
           const double sy = uy * uy;
-          for (int ix = a[0]; ix <= b[0]; ++ix) {
+          const int row = B * (jy + B * kz);
+          const int sw = (3 * jy + 5 * kz) & (B - 1);  // bank swizzle of the row
+          for (int dx = 0; dx < nx; ++dx) {
+            int ix = a[0] + dx + rx;
+            ix = ix > b[0] ? ix - nx : ix;
             const double ux = (lds_c[0][ix] - pp[0]) * ih[0];
             const double u2 = (ux * ux + sy) + sz;
             if (u2 < c2) {
@@ -1095,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_splat(
                 const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
                 q = (unsigned int)rint((double)e * kSplatUnit);
               }
-              atomicAdd(&sums[ix + B * (jy + B * kz)], (unsigned long long)q);
+              atomicAdd(&sums[row + ((ix + sw) & (B - 1))], (unsigned long long)q);
             }
           }
         }
@@ -1115,13 +1129,23 @@ __global__ __launch_bounds__(256) void k_splat(
       // are an internal error (flagged, leaf 0 read instead)
       const int64_t lb = leaf_off[t] + (int64_t)c * chunk_leaves;
       const int64_t le = min(lb + chunk_leaves, leaf_off[t] + cnt);
-      for (int64_t q = lb + wave; q < le; q += 4) {
+      auto leaf_at = [&](int64_t q) {
         int lid = leaves[q];
         if ((unsigned)lid >= (unsigned)tv.n_leaves) {
           if (lane == 0) claims[kErrWord] = 1;
           lid = 0;
         }
-        do_leaf(__builtin_amdgcn_readfirstlane(lid));
+        return __builtin_amdgcn_readfirstlane(lid);
+      };
+      // the next leaf's particle is in flight while this one is scattered
+      if (lb + wave < le) {
+        float4 p = tv.pts[(int64_t)leaf_at(lb + wave) * SFK_LEAF + lane];
+        for (int64_t q = lb + wave; q < le; q += 4) {
+          float4 pn = p;
+          if (q + 4 < le) pn = tv.pts[(int64_t)leaf_at(q + 4) * SFK_LEAF + lane];
+          splat(p);
+          p = pn;
+        }
       }
     } else {
       // walking modes: every wave walks the hierarchy (same order) and takes
@@ -1146,8 +1170,10 @@ __global__ __launch_bounds__(256) void k_splat(
     }
     __syncthreads();
     const double unit = CNT ? 1.0 : 1.0 / kSplatUnit;
+    // LDS slot n holds node (ix, jy, kz) with n = B (jy + B kz) + ((ix + sw) mod B)
     auto write_node = [&](int n, unsigned long long v) {
-      const int ix = n % B, jy = (n / B) % B, kz = n / (B * B);
+      const int jy = (n / B) % B, kz = n / (B * B);
+      const int ix = ((n % B) - ((3 * jy + 5 * kz) & (B - 1))) & (B - 1);
       if (ix < n_here[0] && jy < n_here[1] && kz < n_here[2]) {
         const int64_t gi = g.i0 + ix, gj = g.j0 + jy, gk = g.k0 + kz;
         R.out[gi + (int64_t)R.res[0] * (gj + (int64_t)R.res[1] * gk)] =

@@ -176,8 +176,11 @@ struct sfk_ctx_s {
   hipEvent_t direct_last = nullptr;
   bool direct_last_valid = false;
   hipStream_t direct_last_stream = nullptr;
-  // autotuner table: key -> tile shape id
+  // autotuner table: key -> tile shape id, and the summed time of every
+  // shape over the key's samples (ms; index = shape id, 0 unused)
   std::map<int, int> tune;
+  std::map<int, std::vector<double>> tune_cost;
+  std::string arch;  // gcnArchName of the device (the tuning table's key)
   // sfk_eval_roi_noalloc: this device's copy of the static scratch array
   // (nullptr if its address could not be taken), a pinned staging ring set
   // up at creation, and the stream order of consecutive calls
@@ -200,6 +203,11 @@ struct sfk_tree_s {
   int32_t level_off[SFK_MAX_LEVELS] = {0};
   int32_t level_cnt[SFK_MAX_LEVELS] = {0};
   DevBuf pts, perm, nodes, node_ih, h2;
+  // host copy of the coarse box levels (the finest with at most
+  // kHostLevelNodes boxes and those above it), for particle-count estimates
+  std::vector<NodeBox> host_nodes;
+  int32_t host_level = 0;   // finest level held on the host
+  int32_t host_base = 0;    // device node index of host_nodes[0]
   int32_t pp_mode = PP_UNIFORM;  // PP_ISO when a per-point bandwidth exists
   int32_t knn_k = 0;
   size_t bytes = 0;
@@ -412,6 +420,7 @@ double ck_gauss_trunc3() {
   return 1.0 / (std::pow(2.0 * M_PI, 1.5) * p);
 }
 
+constexpr int kHostLevelNodes = 32768;  // boxes of the finest level kept on the host
 constexpr int kNumShapes = 6;  // tile shapes 1..6 of sfk_eval_opts.tile_shape
 constexpr int kBrickShape = 6;  // bricks of kBrick^3 nodes, scatter evaluation
 
@@ -1327,9 +1336,60 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
   return SFK_OK;
 }
 
-// Autotuner key: kernel, bandwidth mode and the support radius measured in
-// node spacings (log2 bucket; per-point bandwidths share one bucket).
-int tune_key(const sfk_roi* r) {
+// Particles of the tree in the closed box [lo, hi], estimated from the box
+// levels held on the host: a box inside counts whole, a disjoint box not at
+// all, a box that straddles the border is split into its children, down to
+// the finest host level, where it counts in proportion to the overlap of
+// its extent (a flat extent counts whole when it lies inside).
+double est_node(const sfk_tree_s* t, int level, int idx, const double* lo, const double* hi) {
+  const NodeBox& b = t->host_nodes[(size_t)(t->level_off[level] - t->host_base + idx)];
+  if (b.count <= 0) return 0.0;
+  bool inside = true;
+  double frac = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const double bl = b.lo[k], bh = b.hi[k];
+    if (bh < lo[k] || bl > hi[k]) return 0.0;
+    if (bl < lo[k] || bh > hi[k]) inside = false;
+    const double ext = bh - bl;
+    if (ext > 0.0) frac *= (std::min(bh, hi[k]) - std::max(bl, lo[k])) / ext;
+  }
+  if (inside) return (double)b.count;
+  if (level == t->host_level) return (double)b.count * frac;
+  double sum = 0.0;
+  const int c0 = b.first, c1 = std::min(c0 + SFK_FANOUT, t->level_cnt[level - 1]);
+  for (int ch = c0; ch < c1; ++ch) sum += est_node(t, level - 1, ch, lo, hi);
+  return sum;
+}
+
+double est_particles(const sfk_tree_s* t, const double* lo, const double* hi) {
+  if (t->n_levels <= 0 || t->host_nodes.empty()) return 0.0;
+  const int top = t->n_levels - 1;
+  double sum = 0.0;
+  for (int i = 0; i < t->level_cnt[top]; ++i) sum += est_node(t, top, i, lo, hi);
+  return sum;
+}
+
+// Estimated particles per grid node of a ROI: the particles in its box
+// widened by the support, over its nodes (sparse ROIs below about one).
+double particles_per_node(sfk_tree t, const sfk_roi* r) {
+  if (!t || !uniform_bw(r)) return 0.0;
+  double lo[3], hi[3], m = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const double h = r->bw == SFK_BW_FIXED ? (double)r->h[k]
+                                           : (double)r->h[0] * (r->hi[k] - r->lo[k]);
+    const double reach = h * (r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 : 1.0);
+    lo[k] = r->lo[k] - reach;
+    hi[k] = r->hi[k] + reach;
+    m *= (double)r->res[k];
+  }
+  return est_particles(t, lo, hi) / m;
+}
+
+// Autotuner key: kernel, bandwidth mode, the support radius measured in
+// node spacings (log2 bucket; per-point bandwidths share one bucket) and,
+// for uniform bandwidths, the estimated particles per grid node (log2
+// bucket, 0 = below 1/8 ... 7 = 16 or more).
+int tune_key(sfk_tree t, const sfk_roi* r) {
   double hs = 0.0;
   if (r->bw == SFK_BW_FIXED || r->bw == SFK_BW_ROI_SCALED) {
     double rs = 0.0;
@@ -1340,7 +1400,9 @@ int tune_key(const sfk_roi* r) {
     hs = r->kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 * rs : rs;
   }
   const int bucket = hs <= 0.0 ? 0 : std::min(7, std::max(1, (int)std::floor(std::log2(hs)) + 4));
-  return (r->kernel * 4 + r->bw) * 8 + bucket;
+  const double ppn = particles_per_node(t, r);
+  const int dens = ppn <= 0.0 ? 0 : std::min(7, std::max(0, (int)std::floor(std::log2(ppn)) + 4));
+  return ((r->kernel * 4 + r->bw) * 8 + bucket) * 8 + dens;
 }
 
 // Untuned default tile shape. Smaller tiles pay off only where a node's
@@ -1351,11 +1413,22 @@ int tune_key(const sfk_roi* r) {
 // most one node per particle, so one node per wavefront reads only the
 // particles near nodes; larger supports share each particle among more nodes.
 int default_shape(int key, double particles_per_support) {
-  const int bucket = key & 7;
-  if (bucket == 0 || particles_per_support < 2048.0) return 1;
-  if (bucket <= 2) return 5;  // support < 0.5 spacing
-  if (bucket == 3) return 4;  // [0.5, 1)
-  if (bucket == 4) return 3;  // [1, 2)
+  // sparse uniform-bandwidth ROIs (under about one particle per node) take
+  // bricks: a tile's fixed costs (claim, range query, reduction) would
+  // dominate its few pairs (measured: a 256^3 box of side 1/64 around a
+  // clump of a 100M cloud, 0.27 ms in bricks vs 1.40 ms in 4x4x4 tiles)
+  const int dens = key & 7, kb = (key >> 6) & 3;
+  if ((kb == SFK_BW_FIXED || kb == SFK_BW_ROI_SCALED) && dens < 4) return kBrickShape;
+  // Dense ROIs keep wavefront tiles, by support/spacing ratio: below 0.5 a
+  // particle reaches at most one node, so one node per wavefront reads only
+  // the particles near nodes (where a node's support holds many particles);
+  // between 0.5 and 2, 4x2x2 tiles waste fewer pairs than 4x4x4 (measured on
+  // 1e8 and 1e9-point clouds: 10-30% less time for boxes of side 0.6-1 at
+  // 75^3-128^3); above 2, 4x4x4.
+  const int bucket = (key >> 3) & 7;
+  if (bucket == 0) return 1;
+  if (bucket <= 2) return particles_per_support >= 2048.0 ? 5 : 1;
+  if (bucket <= 4) return 3;
   return 1;
 }
 
@@ -1377,7 +1450,7 @@ TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
   if (c->opts.tile_shape > 0) {
     id = c->opts.tile_shape;
   } else {
-    const int key = tune_key(r);
+    const int key = tune_key(t, r);
     auto it = c->tune.find(key);
     id = it != c->tune.end() ? it->second : default_shape(key, particles_per_support(t, r));
   }
@@ -1544,8 +1617,12 @@ sfk_status sfk_ctx_create(int device, const sfk_allocator* alloc, size_t hbm_bud
   }
   c->budget = hbm_budget_bytes;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-    c->n_cu = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    if (prop.multiProcessorCount > 0) c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);  // drop feature suffixes
+  }
   for (int i = 0; i < kNumSlots; ++i) {
     if (hipStreamCreateWithFlags(&c->slots[i].stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming) != hipSuccess) {
@@ -1821,6 +1898,18 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
                             (float4*)t->node_ih.p, 1, s) != hipSuccess)
       return fail((set_err(c, "node bandwidth kernel failed"), SFK_E_DEVICE));
     t->pp_mode = PP_ISO;
+  }
+  // the coarse box levels for host-side particle-count estimates
+  if (t->n_levels > 0) {
+    int hl = 0;
+    while (hl + 1 < t->n_levels && t->level_cnt[hl] > kHostLevelNodes) ++hl;
+    t->host_level = hl;
+    t->host_base = t->level_off[hl];
+    t->host_nodes.resize((size_t)(total_nodes - t->host_base));
+    if (hipMemcpyAsync(t->host_nodes.data(), (const NodeBox*)t->nodes.p + t->host_base,
+                       sizeof(NodeBox) * t->host_nodes.size(), hipMemcpyDeviceToHost,
+                       s) != hipSuccess)
+      return fail((set_err(c, "tree build failed on the device"), SFK_E_DEVICE));
   }
   // pageable destination: the copy returns once the stream has run up to it
   if (hipMemcpyAsync(bb, res.b.p, sizeof bb, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -2705,7 +2794,7 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
   std::map<int, std::vector<double>> cost;
   sfk_status st = SFK_OK;
   for (int i = 0; i < n && st == SFK_OK; ++i) {
-    const int key = tune_key(&sample[i]);
+    const int key = tune_key(t, &sample[i]);
     auto& v = cost[key];
     if (v.empty()) v.assign(kNumShapes + 1, 0.0);
     for (int shape = 1; shape <= kNumShapes && st == SFK_OK; ++shape) {
@@ -2736,7 +2825,94 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
     for (int shape = 1; shape <= kNumShapes; ++shape)
       if (kv.second[shape] < kv.second[best]) best = shape;
     c->tune[kv.first] = best;
+    c->tune_cost[kv.first] = kv.second;
   }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_autotune_costs(sfk_ctx c, int32_t* keys, double* ms, int32_t cap, int32_t* n_out) {
+  SFK_TRY(check_ctx(c));
+  if (!n_out || cap < 0) {
+    set_err(c, "invalid arguments");
+    return SFK_E_INVAL;
+  }
+  int32_t i = 0;
+  for (auto& kv : c->tune_cost) {
+    if (keys && ms && i < cap) {
+      keys[i] = kv.first;
+      for (int sh = 1; sh <= kNumShapes; ++sh)
+        ms[(size_t)i * kNumShapes + sh - 1] = sh < (int)kv.second.size() ? kv.second[sh] : 0.0;
+    }
+    ++i;
+  }
+  *n_out = i;
+  return SFK_OK;
+}
+
+// Text file: a header line "sfkde-autotune 2 <arch> <shapes>", then one line
+// per key: "<key> <shape>".
+sfk_status sfk_autotune_save(sfk_ctx c, const char* path) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!path) {
+    set_err(c, "path is NULL");
+    return SFK_E_INVAL;
+  }
+  FILE* f = std::fopen(path, "w");
+  if (!f) {
+    set_err(c, "cannot write %s", path);
+    return SFK_E_INVAL;
+  }
+  std::fprintf(f, "sfkde-autotune 2 %s %d\n", c->arch.empty() ? "unknown" : c->arch.c_str(),
+               kNumShapes);
+  for (auto& kv : c->tune) std::fprintf(f, "%d %d\n", kv.first, kv.second);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) {
+    set_err(c, "cannot write %s", path);
+    return SFK_E_INVAL;
+  }
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
+sfk_status sfk_autotune_load(sfk_ctx c, const char* path) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!path) {
+    set_err(c, "path is NULL");
+    return SFK_E_INVAL;
+  }
+  FILE* f = std::fopen(path, "r");
+  if (!f) {
+    set_err(c, "cannot read %s", path);
+    return SFK_E_INVAL;
+  }
+  char magic[32] = {0}, arch[64] = {0};
+  int ver = 0, shapes = 0;
+  if (std::fscanf(f, "%31s %d %63s %d", magic, &ver, arch, &shapes) != 4 ||
+      std::strcmp(magic, "sfkde-autotune") != 0 || ver != 2 || shapes != kNumShapes) {
+    std::fclose(f);
+    set_err(c, "%s is not a tuning table of this library version", path);
+    return SFK_E_INVAL;
+  }
+  if (c->arch != arch) {
+    std::fclose(f);
+    set_err(c, "%s was tuned on %s, this device is %s", path, arch, c->arch.c_str());
+    return SFK_E_UNSUPPORTED;
+  }
+  std::map<int, int> t;
+  int key = 0, shape = 0;
+  while (std::fscanf(f, "%d %d", &key, &shape) == 2) {
+    if (shape < 1 || shape > kNumShapes || key < 0) {
+      std::fclose(f);
+      set_err(c, "%s: entry %d %d out of range", path, key, shape);
+      return SFK_E_INVAL;
+    }
+    t[key] = shape;
+  }
+  std::fclose(f);
+  for (auto& kv : t) c->tune[kv.first] = kv.second;
   return SFK_OK;
   SFK_GUARD_END(c)
 }

@@ -603,7 +603,29 @@ def test_autotune(ctx, torch):
     outs = [torch.empty(r.n_nodes, device="cuda") for r in rois]
     ctx.autotune(tree, rois, outs)
     table = ctx.autotune_table()
-    assert len(table) >= 1 and all(1 <= s <= 4 for s in table.values())
+    costs = ctx.autotune_costs()
+    assert len(table) >= 1 and set(table) == set(costs)
+    for key, shape in table.items():
+        assert 1 <= shape <= 6
+        # the pick is the fastest shape measured for that key
+        assert costs[key][shape - 1] == min(costs[key]), (key, shape, costs[key])
+    # persisted with the device architecture, reloaded into a fresh context
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = d + "/tune.txt"
+        ctx.autotune_save(path)
+        head = open(path).read().split("\n")[0].split()
+        assert head[0] == "sfkde-autotune" and head[2].startswith("gfx")
+        c2 = type(ctx)(0)
+        c2.autotune_load(path)
+        assert c2.autotune_table() == table
+        # another architecture is refused
+        lines = open(path).read().split("\n")
+        lines[0] = "sfkde-autotune 2 gfx000 6"
+        open(path, "w").write("\n".join(lines))
+        with pytest.raises(Exception):
+            c2.autotune_load(path)
+        c2.close()
     for r in rois:
         nodes = sample_nodes(None, r.n_nodes, 16, 1)
         check_sampled(ctx.eval_roi(tree, r).cpu().numpy(), nodes,

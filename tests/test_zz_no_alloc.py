@@ -46,6 +46,9 @@ def test_noalloc_matches_eval_roi(ctx, torch, cloud):
         # small again, fixed anisotropic bandwidth
         Roi((0.4, 0.1, 0.3), (0.6, 0.9, 0.7), (17, 29, 23), kernel="epanechnikov",
             bw="fixed", h=(0.02, 0.05, 0.03)),
+        # sparse: 16^3 bricks (scatter evaluation)
+        Roi((0.45, 0.45, 0.45), (0.55, 0.55, 0.55), (150, 150, 150), kernel="epanechnikov",
+            bw="roi_scaled", h=(0.01,) * 3),
     ]
     for i, roi in enumerate(rois):
         say("noalloc roi", i, roi.res, roi.kernel, roi.bw)
@@ -66,6 +69,9 @@ def test_noalloc_rejections(ctx, torch, cloud, sfk):
     from paper_2601_20758_amd import _lib as L
     tree = ctx.build_tree(dev(torch, cloud[:20000]))
     # 600^3 nodes = 3.4M tiles of 4x4x4: the per-tile arrays exceed the array
+    # (forced tiles: this sparse ROI would otherwise take 16^3 bricks, 54k of
+    # which fit)
+    ctx.set_eval_opts(tile_shape=1)
     big = Roi((0, 0, 0), (1, 1, 1), (600, 600, 600), kernel="epanechnikov", bw="fixed",
               h=(0.01,) * 3)
     out = torch.full((big.n_nodes,), 7.0, device="cuda")
@@ -75,6 +81,7 @@ def test_noalloc_rejections(ctx, torch, cloud, sfk):
     torch.cuda.synchronize()
     assert bool(torch.all(out == 7.0))  # nothing was launched
     del out
+    ctx.set_eval_opts()
     inbox = Roi((0.2, 0.2, 0.2), (0.6, 0.6, 0.6), (16, 16, 16), bw="fixed", h=(0.02,) * 3,
                 set="in_roi")
     with pytest.raises(sfk.SfkError) as e:
