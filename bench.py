@@ -626,6 +626,19 @@ def served_headline(ctx, torch, args):
     slots = SLOTS_PER_EVAL["epanechnikov"] * e_timed
     achieved = slots / (eval_ms * 1e-3) / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
+    # the same seconds again on one stream (no batch overlaps another), so
+    # each phase's event-timed duration is its own: an untimed breakdown
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    t2 = time.perf_counter()
+    for w in range(W, W + K):
+        ids = idx_w[w]
+        ctx.serve(tree, np.zeros(len(ids)), [rois[i] for i in ids], [outs[i] for i in ids],
+                  mode=0, n_slots=1, max_batch=64, budget_bytes=budget)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t2
+    prof1 = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
     sub = {
         "workload": "%d requests in %d s of a trace from 8 streams at 90 Hz on the resident "
                     "%s-point tree; sides log-uniform in [1e-4, 1], grids 32^3-128^3, "
@@ -638,8 +651,17 @@ def served_headline(ctx, torch, args):
             "one_roi_per_launch": {"evals_per_s": e_timed / dt1,
                                    "ms_per_second_of_trace": dt1 * 1e3 / K},
             "throughput_ratio": dt1 / dt},
-        "phases_ms_per_step": {k: prof[k] / K for k in ("tile_count_ms", "plan_ms",
-                                                         "tile_fill_ms", "eval_ms")},
+        "phases_ms_per_step_4_streams": {k: prof[k] / K for k in (
+            "tile_count_ms", "plan_ms", "tile_fill_ms", "eval_ms")},
+        "one_stream": {
+            "evals_per_s": e_timed / dt2, "ms_per_second_of_trace": dt2 * 1e3 / K,
+            "phases_ms_per_step": {k: prof1[k] / K for k in (
+                "tile_count_ms", "plan_ms", "tile_fill_ms", "eval_ms")},
+            "eval_frac_of_valu_ceiling": SLOTS_PER_EVAL["epanechnikov"] * e_timed
+                                         / (prof1["eval_ms"] * 1e-3) / VALU_SLOTS_PER_S,
+            "note": "batches one after another on one stream: each phase's HIP-event "
+                    "duration is its own (on 4 streams a batch's events also span the "
+                    "other streams' kernels that share the device)"},
         "eval_launches": int(prof["eval_launches"]),
     }
     if not args.no_realtime:
@@ -677,16 +699,20 @@ def served_headline(ctx, torch, args):
     sub["bitwise_alone_vs_served"] = {"requests_checked": len(check), "equal": same}
     head = {
         "value": e_timed / dt, "ms_per_step": dt * 1e3 / K, "useful_evals": e_timed,
-        "roofline": {"bound": "alu", "kernel": "k_eval<4,4,4,epanechnikov,uniform>",
+        "roofline": {"bound": "alu",
+                     "kernel": "evaluation (k_eval tiles and k_splat bricks, Epanechnikov, "
+                               "uniform bandwidth)",
                      "achieved": achieved, "peak": peak, "unit": "T VALU-slot/s",
                      "frac": achieved / peak, "traffic": measured_traffic(SERVED_TRAFFIC_FILE),
                      "slots_per_eval": SLOTS_PER_EVAL["epanechnikov"],
                      "evals_per_launch": e_timed / launches,
                      "avg_launch_ms": eval_ms / launches, "launches": int(launches),
                      "note": "achieved = 9 slots x useful evaluations of the timed steps / "
-                             "summed k_eval launch durations (HIP events on each batch's "
-                             "stream; batches on the 4 streams overlap); traffic from the "
-                             "committed counter summary while the kernel sources match"},
+                             "summed evaluation-kernel durations (HIP events on each batch's "
+                             "stream; batches on the 4 streams overlap, so a duration also "
+                             "covers other streams' kernels: serving.one_stream gives the "
+                             "same seconds without overlap); traffic from the committed "
+                             "counter summary while the kernel sources match"},
     }
     if pts_host is not None:
         log("timing the oracle on sampled nodes of served requests")

@@ -193,8 +193,13 @@ sfk_status sfk_eval_roi_noalloc(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
 
 /* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
  * launch on one of the context's streams. The descriptors are copied; the
- * d_out buffers must stay valid until the ticket completes. Returns at once
- * with a ticket. SFK_E_BUDGET if the batch's workspace exceeds the budget.
+ * d_out buffers must stay valid until the ticket completes. Returns with a
+ * ticket without waiting for the batch to run, except when a free slot's
+ * buffers must grow for the batch: replacing a workspace or staging buffer
+ * first waits for that slot's previous batch, and the device allocation and
+ * release themselves may synchronise the device. Batches that fit the slots'
+ * buffers (every batch after a warm-up of the largest shape) never block.
+ * SFK_E_BUDGET if the batch's workspace exceeds the budget.
  * A batch of one (kernel, bandwidth) group replays the slot's captured
  * hipGraph (descriptor copy -> node coordinates -> tile range query -> work
  * plan -> leaf lists -> evaluation -> header readback), recaptured only when
@@ -285,8 +290,16 @@ typedef struct {
   int32_t mode;          /* 0 continuous batching, 1 one ROI per launch in FIFO order */
   int32_t n_slots;       /* batches in flight at once (each on its own stream), >= 1 */
   int32_t max_batch;     /* ROIs per batch, >= 1 */
-  int32_t reserved;
+  int32_t interleave;    /* 0: persistent evaluation grids, as sfk_submit uses; 1: grids of
+                            one wavefront per tile, whose workgroups retire as they finish
+                            so the kernels of requests on other streams interleave */
   double budget_bytes;   /* workspace + grid bytes admitted at once (0 = context budget) */
+  double max_batch_work; /* continuous batching: a batch closes before the request that
+                            would take its estimated useful pairs past this (a request
+                            above it runs alone, so light requests never wait for a heavy
+                            one's completion); 0 = 2e8, < 0 = no limit. The estimate is
+                            the particles the tree's coarse boxes put in the request's box
+                            (widened by the support) times the nodes one support covers */
 } sfk_serve_opts;
 
 typedef struct {

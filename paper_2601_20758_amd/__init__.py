@@ -251,14 +251,16 @@ class Context:
         self._check(self._lib.sfk_autotune_load(self._h, path.encode()))
 
     def serve(self, tree: "Tree", arrivals: Sequence[float], rois: Sequence, outs: Sequence,
-              mode: int = 0, n_slots: int = 4, max_batch: int = 64, budget_bytes: float = 0.0):
+              mode: int = 0, n_slots: int = 4, max_batch: int = 64, budget_bytes: float = 0.0,
+              max_batch_work: float = 0.0, interleave: bool = False):
         """sfk_serve over a request trace; returns (per-request results, summary)."""
         n = len(rois)
         reqs = (L.Request * n)()
         for i in range(n):
             reqs[i].arrival_s = float(arrivals[i])
             reqs[i].roi = roi_struct(rois[i], outs[i].data_ptr())
-        opts = L.ServeOpts(int(mode), int(n_slots), int(max_batch), 0, float(budget_bytes))
+        opts = L.ServeOpts(int(mode), int(n_slots), int(max_batch), 1 if interleave else 0,
+                           float(budget_bytes), float(max_batch_work))
         res = (L.RequestResult * n)()
         summ = L.ServeSummary()
         self._check(self._lib.sfk_serve(self._h, tree._h, reqs, n, C.byref(opts), res,

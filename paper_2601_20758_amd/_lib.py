@@ -51,7 +51,8 @@ class Request(C.Structure):
 
 class ServeOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_slots", C.c_int32), ("max_batch", C.c_int32),
-                ("reserved", C.c_int32), ("budget_bytes", C.c_double)]
+                ("interleave", C.c_int32), ("budget_bytes", C.c_double),
+                ("max_batch_work", C.c_double)]
 
 
 class RequestResult(C.Structure):

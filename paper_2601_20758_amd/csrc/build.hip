@@ -743,8 +743,15 @@ __device__ __forceinline__ float pt_box_d2(const float* b, float x, float y, flo
   return __fadd_rn(__fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy)), __fmul_rn(gz, gz));
 }
 
+#ifndef SFK_KNN_WAVES
+#define SFK_KNN_WAVES 4
+#endif
+#ifndef SFK_KNN_RUN
+#define SFK_KNN_RUN 16
+#endif
+
 template <int KM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 4 : 2))) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? SFK_KNN_WAVES : 2))) void k_knn(TreeView tv, const float* __restrict__ sub_box, int k,
                                              float* __restrict__ h2_sorted,
                                              const float* __restrict__ skip_if) {
   if (skip_if && *skip_if > 0.0f) return;  // the build fails: non-finite coordinates
@@ -969,7 +976,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 
           // registers (10M points, k = 32: k-NN 9.09 -> 8.75 ms against the
           // insertion; whole runs of 32: 8.79 ms; the first 32 sorted and the
           // rest inserted: 8.90 ms)
-          constexpr int R = KM > 16 ? 16 : KM;
+          constexpr int R = KM > SFK_KNN_RUN ? SFK_KNN_RUN : KM;
 #pragma unroll
           for (int c0 = KM; c0 < SFK_LEAF; c0 += R) {
             float b[R];

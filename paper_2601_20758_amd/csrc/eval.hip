@@ -535,7 +535,10 @@ __global__ __launch_bounds__(256) void k_eval(
   // Per-lane node accumulators are float32: a lane adds one term per drained
   // batch of 64 particles (at most chunk_leaves terms per work item), the 64
   // lanes are combined by a 6-level tree and the chunks of a tile in double.
-  using Acc = float;
+  // Uniform-bandwidth Epanechnikov tiles of at most 16 nodes accumulate in
+  // double (registers allow it), which also saves the per-pair conversion.
+  constexpr bool kDoubleAcc = T <= 16 && KK == KK_EPAN && PP == PP_UNIFORM && !CNT;
+  using Acc = std::conditional_t<kDoubleAcc, double, float>;
   // particle buffers of the leaf pipeline; each pipeline round appends up to
   // NB leaves to the queue before draining it, hence its capacity
   constexpr int NB = 3;
@@ -649,16 +652,38 @@ __global__ __launch_bounds__(256) void k_eval(
         const double u = (nz[k] - pz) * (double)ihz;
         sz[k] = u * u;
       }
+      // A row (i, j) of nodes where no lane's particle reaches (sx + sy >= c2
+      // for all 64; u2 only grows with sz) adds exact zeros: skipped.
       if constexpr (CNT) {
 #pragma unroll
         for (int j = 0; j < TY; ++j)
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
             const double tt = sx[i] + sy[j];
+            if (!ballot(tt < c2)) continue;
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
               const double u2 = tt + sz[k];
               acc[i + TX * (j + TY * k)] += (u2 < c2) ? 1.0f : 0.0f;
+            }
+          }
+      } else if constexpr (KK == KK_EPAN && PP == PP_UNIFORM) {
+        // 1 - u2 = (1 - (sx + sy)) - sz: one subtraction per node (the
+        // rounding differs from 1 - ((sx + sy) + sz) by at most an ulp of
+        // double; a term at the support's edge is then +-1e-16, not 0)
+#pragma unroll
+        for (int j = 0; j < TY; ++j)
+#pragma unroll
+          for (int i = 0; i < TX; ++i) {
+            const double om = 1.0 - (sx[i] + sy[j]);
+            if (!ballot(om > 0.0)) continue;
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+              Acc& a = acc[i + TX * (j + TY * k)];
+              if constexpr (kDoubleAcc)
+                a = a + fmax(om - sz[k], 0.0);
+              else
+                a = a + (float)fmax(om - sz[k], 0.0);
             }
           }
       } else if constexpr (KK == KK_EPAN) {
@@ -668,15 +693,13 @@ __global__ __launch_bounds__(256) void k_eval(
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
             const double tt = sx[i] + sy[j];
+            if (!ballot(tt < c2)) continue;
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {
               const double u2 = tt + sz[k];
               const float v = (float)fmax(1.0 - u2, 0.0);
               Acc& a = acc[i + TX * (j + TY * k)];
-              if constexpr (PP == PP_UNIFORM)
-                a = a + v;
-              else
-                a = fmaf(wf, v, a);
+              a = fmaf(wf, v, a);
             }
           }
       } else {
@@ -696,6 +719,7 @@ __global__ __launch_bounds__(256) void k_eval(
 #pragma unroll
           for (int i = 0; i < TX; ++i) {
             const double tt = sx[i] + sy[j];
+            if (!ballot(tt < c2)) continue;
             const float exy = ex[i] * ey[j];
 #pragma unroll
             for (int k = 0; k < TZ; ++k) {

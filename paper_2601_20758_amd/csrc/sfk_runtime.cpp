@@ -116,6 +116,7 @@ struct GraphCache {
   TileShape ts{0, 0, 0};
   int kk = 0, pp = 0, ch = 0;
   bool cnt = false;
+  bool interleave = false;  // captured with one-wave-per-tile evaluation grids
   sfk_tree tree = nullptr;
   uint64_t gen = 0, st_gen = 0;
   int64_t tiles_cap = 0, rois_cap = 0, coords_cap = 0;
@@ -185,6 +186,7 @@ struct sfk_ctx_s {
   // (nullptr if its address could not be taken), a pinned staging ring set
   // up at creation, and the stream order of consecutive calls
   int32_t debug_poison = 0;  // sfk_debug_poison: test-only bits staged in every batch header
+  bool serve_interleave = false;  // sfk_serve: evaluation grids of one wave per tile
   unsigned char* na_scratch = nullptr;
   char* na_host[kStagingRing] = {};
   hipEvent_t na_ev[kStagingRing] = {};
@@ -645,12 +647,14 @@ struct Caps {
   int32_t splat;
 };
 
-// Leaves the count pass keeps per tile for a tile shape: four per node of
-// the tile, at least 32 and at most kTileSlotCap (a tile of few nodes meets
-// few leaves; 4x4x4 tiles of the 10M per-point workload average ~124).
+// Leaves the count pass keeps per tile for a tile shape: 16 per node of the
+// tile, at least 32 and at most kTileSlotCap (a tile of few nodes meets few
+// leaves: 1x1x1 keeps 32, 2x2x2 128, larger tiles 256; 4x4x4 tiles of the
+// 10M per-point workload average ~124 leaves, 4x2x2 tiles of dense 1e9-point
+// ROIs several hundred).
 int32_t slot_cap_of(TileShape ts) {
   const int t = ts.tx * ts.ty * ts.tz;
-  return std::min(kTileSlotCap, std::max(32, 4 * t));
+  return std::min(kTileSlotCap, std::max(32, 16 * t));
 }
 
 // Reserve every buffer of a group (n_rois descriptors, n_tiles tiles,
@@ -798,7 +802,13 @@ sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, i
   // 0: resident blocks per CU from the occupancy query, capped at one wave
   // per tile (the tile kernels' grid) but at least one block per CU, so a
   // small batch does not launch (and drain) a full-device persistent grid
-  const int grid = c->opts.persistent_waves_per_cu > 0
+  // Serving with `interleave`: one wave per tile, so the workgroups of a
+  // heavy request retire as they finish their items and the hardware can
+  // interleave the kernels of requests on the other streams (measured on the
+  // 1B-point trace: p50 0.54 -> 3.7 ms, saturated throughput -12%, p99 no
+  // better, so persistent grids stay the default).
+  const int grid = c->serve_interleave ? std::max(1, tile_grid)
+                   : c->opts.persistent_waves_per_cu > 0
                        ? c->n_cu * std::max(1, c->opts.persistent_waves_per_cu / 4)
                        : 0;
   {
@@ -941,7 +951,8 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   GraphCache& gc = sl.gc;
   const bool fits = gc.valid && gc.gen == sl.ws.gen && gc.st_gen == sl.st.gen && gc.tree == t &&
                     gc.kk == kk &&
-                    gc.pp == pp && gc.ch == ch && !gc.cnt && gc.ts.tx == ts.tx &&
+                    gc.pp == pp && gc.ch == ch && !gc.cnt && gc.interleave == c->serve_interleave &&
+                    gc.ts.tx == ts.tx &&
                     gc.ts.ty == ts.ty && gc.ts.tz == ts.tz && n <= gc.rois_cap &&
                     n_tiles <= gc.tiles_cap && n_coords <= gc.coords_cap;
   Caps k;
@@ -1000,6 +1011,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
     gc.pp = pp;
     gc.ch = ch;
     gc.cnt = false;
+    gc.interleave = c->serve_interleave;
     gc.tree = t;
     gc.gen = sl.ws.gen;
     gc.st_gen = sl.st.gen;
@@ -2937,6 +2949,25 @@ sfk_status sfk_autotune_table(sfk_ctx c, int32_t* keys, int32_t* shapes, int32_t
   return SFK_OK;
 }
 
+// Estimated useful pairs of a request: the particles the host box levels put
+// in its box widened by the support, times the nodes one support covers
+// (an ellipsoid of semi-axes reach_k / s_k node steps, at least one node).
+static double est_useful(sfk_tree t, const sfk_roi& r) {
+  double lo[3], hi[3], vol = 4.0 / 3.0 * M_PI;
+  const double c = r.kernel == SFK_KERNEL_GAUSS_TRUNC3 ? 3.0 : 1.0;
+  for (int k = 0; k < 3; ++k) {
+    double h = 0.0;
+    if (r.bw == SFK_BW_FIXED) h = r.h[k];
+    else if (r.bw == SFK_BW_ROI_SCALED) h = (double)r.h[0] * (r.hi[k] - r.lo[k]);
+    else h = (r.hi[k] - r.lo[k]) / 64.0;  // per-point: a guess of one 64th of the box
+    const double s = (r.hi[k] - r.lo[k]) / (double)(r.res[k] - 1);
+    lo[k] = r.lo[k] - c * h;
+    hi[k] = r.hi[k] + c * h;
+    vol *= c * h / s;
+  }
+  return est_particles(t, lo, hi) * std::max(1.0, vol);
+}
+
 // Device bytes one request holds while in flight: its grid plus an estimate
 // of its share of the batch workspace (per-tile arrays and leaf lists).
 static double request_bytes(const sfk_roi& r, TileShape ts) {
@@ -2956,7 +2987,8 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
     return SFK_E_INVAL;
   }
   if (opts->mode < 0 || opts->mode > 1 || opts->n_slots < 1 || opts->n_slots > kNumSlots ||
-      opts->max_batch < 1 || !(opts->budget_bytes >= 0.0)) {
+      opts->max_batch < 1 || !(opts->budget_bytes >= 0.0) || opts->interleave < 0 ||
+      opts->interleave > 1 || !std::isfinite(opts->max_batch_work)) {
     set_err(c, "serve options out of range (mode 0|1, 1 <= n_slots <= %d, max_batch >= 1)",
             kNumSlots);
     return SFK_E_INVAL;
@@ -2982,6 +3014,12 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
   if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
 
   const double budget = opts->budget_bytes > 0 ? opts->budget_bytes : (double)c->budget;
+  struct Interleave {
+    sfk_ctx c;
+    bool saved;
+    Interleave(sfk_ctx cc, bool on) : c(cc), saved(cc->serve_interleave) { c->serve_interleave = on; }
+    ~Interleave() { c->serve_interleave = saved; }
+  } interleave(c, opts->interleave != 0);
   for (int64_t i = 0; i < n; ++i) {
     res[i] = sfk_request_result{};
     res[i].arrival_s = reqs[i].arrival_s;
@@ -3040,6 +3078,9 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
     batched_reqs = n;
   } else {
     const int ns = opts->n_slots;
+    const double work_cap = opts->max_batch_work == 0.0 ? 2e8 : opts->max_batch_work;
+    std::vector<double> work((size_t)n);
+    for (int64_t i = 0; i < n; ++i) work[(size_t)i] = est_useful(t, rois[(size_t)i]);
     std::vector<std::vector<int64_t>> in_slot((size_t)ns);
     std::vector<double> slot_bytes((size_t)ns, 0.0);
     std::deque<int64_t> pending;
@@ -3086,12 +3127,15 @@ sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,
         Slot& sl = c->slots[si];
         if (sl.busy) continue;
         batch.clear();
-        double bytes = 0.0;
+        double bytes = 0.0, bwork = 0.0;
         while (!pending.empty() && (int)batch.size() < opts->max_batch) {
           const int64_t i = pending.front();
           const double rb = request_bytes(rois[i], choose_shape(c, t, &rois[i]));
           const bool fits = budget <= 0.0 || in_flight + bytes + rb <= budget;
           if (!fits && !(batch.empty() && in_flight == 0.0)) break;
+          // a heavy request closes the batch (it runs alone or starts the next)
+          if (!batch.empty() && work_cap > 0.0 && bwork + work[(size_t)i] > work_cap) break;
+          bwork += work[(size_t)i];
           batch.push_back(&rois[i]);
           in_slot[si].push_back(i);
           bytes += rb;

@@ -572,11 +572,34 @@ def test_serve_alone_vs_mix(ctx, torch, mode):
         check_sampled(outs[i].cpu().numpy(), nodes, oracle.density(pts, r, nodes=nodes), "serve")
 
 
+def test_serve_binding_budget_and_heavy_requests(ctx, torch):
+    # an admission budget that binds (requests wait for memory), a work cap
+    # that splits heavy requests into batches of their own, saturating
+    # arrivals: every grid still equals the request evaluated alone
+    pts = synth.clumpy_cloud(400_000, 15)
+    tree = ctx.build_tree(dev(torch, pts))
+    arr, _, rois = synth.serving_trace(seed=8, duration_s=0.3, res_choices=(32, 48, 64))
+    arr = [0.0] * len(rois)  # everything waiting at the start
+    outs = [torch.full((r.n_nodes,), -1.0, device="cuda") for r in rois]
+    res, summ = ctx.serve(tree, arr, rois, outs, mode=0, n_slots=4, max_batch=16,
+                          budget_bytes=6 << 20, max_batch_work=2e6)
+    torch.cuda.synchronize()
+    say("binding budget: requests", len(rois), "batches", summ.n_batches, "waits",
+        summ.budget_waits, "mean batch", summ.mean_batch)
+    assert summ.budget_waits > 0
+    assert summ.n_batches > len(rois) / 16
+    for i, r in enumerate(rois):
+        assert res[i].status == 0
+        alone = ctx.eval_roi(tree, r).cpu().numpy()
+        assert np.array_equal(alone, outs[i].cpu().numpy()), i
+    tree.close()
+
+
 # ---------------------------------------------------------------------------
 # every tile shape, and the autotuner that picks among them
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6])
 def test_every_tile_shape(ctx, torch, shape):
     pts = synth.clumpy_cloud(80_000, 8)
     ctx.set_eval_opts(tile_shape=shape)
