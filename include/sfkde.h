@@ -183,7 +183,11 @@ sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hi
  * per-tile arrays do not fit the array (about 1.5M tiles, e.g. 460^3 nodes
  * with 4x4x4 tiles) returns SFK_E_BUDGET before any launch. Smaller list
  * capacities than sfk_eval_roi's only make tiles walk the tree inside the
- * evaluation (same leaves, same order, same sums).
+ * evaluation (same leaves, same order, same sums). A ROI that takes the
+ * particle sweep (tile shape 7) needs 8 bytes per node of its 8^3-node tiles
+ * and 8 bytes per 4096 particles of the tree; when that does not fit (about
+ * 7.5M nodes) it takes the tile shape it would take without the sweep, and
+ * its grid then equals sfk_eval_roi's within rounding, not bit for bit.
  * Concurrency: every call on a device shares that device's array. Calls of one
  * context are ordered (a call on another stream waits for the previous one);
  * calls from different contexts on one device that overlap in time race and
@@ -219,7 +223,12 @@ typedef struct {
   int32_t tile_shape;    /* 0 auto, 1 = 4x4x4, 2 = 4x4x2, 3 = 4x2x2, 4 = 2x2x2, 5 = 1x1x1
                             (a wavefront per tile, gathering), 6 = bricks of 16^3 nodes
                             (a workgroup per brick scattering particles into exact
-                            integer node sums; uniform bandwidths only, others take 1) */
+                            integer node sums; uniform bandwidths only, others take 1),
+                            7 = particle sweep (a workgroup per box of 4096 particles
+                            scattering them once into the same integer node sums, so
+                            its grids equal the bricks' bit for bit; uniform bandwidths
+                            whose support spans at most 5 nodes per axis, others take
+                            the default of their key without the sweep) */
   int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 256 */
   int32_t persistent_waves_per_cu; /* 0 = automatic */
   int32_t list_capacity; /* leaf-list entries per batch, 0 = automatic; tiles whose
@@ -243,9 +252,12 @@ sfk_status sfk_autotune(sfk_ctx ctx, sfk_tree tree, const sfk_roi* sample, int32
  * 0..7; 0 for per-point bandwidths). */
 sfk_status sfk_autotune_table(sfk_ctx ctx, int32_t* keys, int32_t* shapes, int32_t cap,
                               int32_t* n_out);
-/* The times the last sfk_autotune measured: per key, ms[i * 6 + s - 1] = the
- * summed best-of-3 time of tile shape s over that key's samples (1e30 for a
- * shape the key cannot take). *n_out = keys. */
+/* Tile shapes sfk_eval_opts.tile_shape can name (1..SFK_NUM_TILE_SHAPES). */
+#define SFK_NUM_TILE_SHAPES 7
+/* The times the last sfk_autotune measured: per key,
+ * ms[i * SFK_NUM_TILE_SHAPES + s - 1] = the summed best-of-3 time of tile
+ * shape s over that key's samples (1e30 for a shape the key cannot take).
+ * *n_out = keys. */
 sfk_status sfk_autotune_costs(sfk_ctx ctx, int32_t* keys, double* ms, int32_t cap,
                               int32_t* n_out);
 /* Persist the table to a text file, with the device architecture (e.g.
@@ -539,7 +551,12 @@ sfk_status sfk_debug_curve_keys(int32_t curve, int32_t bits, const uint32_t* h_c
  * h_shape[3] = the tile shape, h_tile_cnt[t] = candidate leaves of tile t
  * (tiles x fastest over ceil(res / shape) tiles per axis; written if
  * *n_tiles <= tiles_cap), h_leaves = every tile's leaf list in tile order,
- * each ascending (written if *total <= cap). Blocks. */
+ * each ascending (written if *total <= cap). For the particle sweep
+ * (shape 8x8x8) the tiles keep no lists (h_tile_cnt all 0) and h_leaves
+ * holds the sweep's work items instead: the ascending indices of the boxes
+ * of the hierarchy's first interior level (of the leaves when the tree has
+ * at most 64) that pass the box test against the ROI's nodes, *total of
+ * them. Blocks. */
 sfk_status sfk_debug_tile_leaves(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, int32_t* h_shape,
                                  int64_t* h_tile_cnt, int64_t tiles_cap, int32_t* h_leaves,
                                  int64_t cap, int64_t* n_tiles, int64_t* total);
@@ -551,7 +568,9 @@ sfk_status sfk_debug_leaf_boxes(sfk_ctx ctx, sfk_tree tree, float* h_boxes);
  * h_edges (room for 15; edge ids as sfk_iso_surface describes: along x
  * dy + 2 dz, along y 4 + dx + 2 dz, along z 8 + dx + 2 dy). */
 sfk_status sfk_debug_mc_case(int32_t cs, int8_t* h_edges, int32_t* n_tri);
-/* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel. */
+/* Useful pairs E = sum_n #S(n) and pairs tested by the evaluation kernel
+ * (tiles: listed leaves x 64 x nodes per tile; the particle sweep: listed
+ * boxes x 4096 particles x the unrolled node span NM^3, an upper bound). */
 sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* useful_pairs, int64_t* tested_pairs);
 /* Per-node support counts #S(n) (res product floats, device, x fastest). */

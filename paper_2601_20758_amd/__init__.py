@@ -15,8 +15,10 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib as L
+from ._lib import NOALLOC_SCRATCH_BYTES, NUM_TILE_SHAPES
 
-__all__ = ["SfkError", "Context", "Tree", "curve_keys", "roi_struct", "version"]
+__all__ = ["SfkError", "Context", "Tree", "curve_keys", "roi_struct", "version",
+           "NOALLOC_SCRATCH_BYTES", "NUM_TILE_SHAPES"]
 
 
 class SfkError(RuntimeError):
@@ -236,13 +238,14 @@ class Context:
         return {keys[i]: shapes[i] for i in range(n.value)}
 
     def autotune_costs(self) -> dict:
-        """sfk_autotune_costs: key -> [ms of shapes 1..6]."""
+        """sfk_autotune_costs: key -> [ms of shapes 1..NUM_TILE_SHAPES]."""
         n = C.c_int32()
         self._check(self._lib.sfk_autotune_costs(self._h, None, None, 0, C.byref(n)))
         keys = (C.c_int32 * max(1, n.value))()
-        ms = (C.c_double * (6 * max(1, n.value)))()
+        S = NUM_TILE_SHAPES
+        ms = (C.c_double * (S * max(1, n.value)))()
         self._check(self._lib.sfk_autotune_costs(self._h, keys, ms, n.value, C.byref(n)))
-        return {keys[i]: [ms[6 * i + j] for j in range(6)] for i in range(n.value)}
+        return {keys[i]: [ms[S * i + j] for j in range(S)] for i in range(n.value)}
 
     def autotune_save(self, path: str):
         self._check(self._lib.sfk_autotune_save(self._h, path.encode()))

@@ -11,6 +11,8 @@ LIB_PATH = os.path.join(HERE, "libsfkde.so")
 SFK_OK = 0
 # size of the static scratch array of sfk_eval_roi_noalloc (SFK_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
+# tile shapes sfk_eval_opts.tile_shape can name, 1..NUM_TILE_SHAPES (SFK_NUM_TILE_SHAPES)
+NUM_TILE_SHAPES = 7
 STATUS = {0: "SFK_OK", 1: "SFK_E_INVAL", 2: "SFK_E_NOMEM", 3: "SFK_E_BUDGET", 4: "SFK_E_DEVICE",
           5: "SFK_E_NOT_READY", 6: "SFK_E_CANCELLED", 7: "SFK_E_UNSUPPORTED", 8: "SFK_E_INTERNAL"}
 KERNEL = {"epanechnikov": 0, "gauss_trunc3": 1}

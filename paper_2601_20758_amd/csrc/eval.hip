@@ -1225,6 +1225,303 @@ __global__ __launch_bounds__(256) void k_splat(
 }
 
 // ---------------------------------------------------------------------------
+// Particle sweep (uniform bandwidths, dense ROIs). Where a ROI holds many
+// particles per node, a tile re-reads each particle in every tile whose
+// support-widened box holds it (about (t + 2h/s)^3 / t^3 tiles for a tile
+// of t^3 nodes) and tests it against all the tile's nodes, and each tile
+// pays a range query. The sweep reads every particle of the ROI's support
+// once. A work item is a (ROI, box) pair, the box taken from the
+// hierarchy's first interior level (64 leaves, 4096 particles, compact in
+// curve order); the workgroup scatters the box's particles into an LDS
+// window of the ROI's nodes that the box's support can reach, with the
+// brick's membership (canonical u2 in double), the brick's fixed-point
+// terms rint(v * 2^31) and LDS atomics, then adds the window's nonzero sums
+// into the batch's 64-bit node sums with global atomics. Integer sums make
+// the grid independent of the order of items, particles and workgroups, and
+// equal to the brick's grid bit for bit. Lanes of a wavefront take
+// particles of different leaves of the box, so one instruction's atomics
+// spread over the window instead of queueing on the few nodes one leaf
+// reaches. Windows wider than kSweepWin nodes on some axis are swept in
+// blocks of kSweepWin^3 nodes, each reading the box's particles again.
+// ---------------------------------------------------------------------------
+
+// Level of the hierarchy whose boxes are the sweep's work items: the first
+// interior level (64 leaves a box) when the tree has one, else the leaves.
+__device__ __forceinline__ int sweep_level(const TreeView& tv) { return tv.n_levels >= 2 ? 1 : 0; }
+
+// Support half-width of a ROI in node steps on axis k, rounded outwards so
+// that a particle's node range never misses a member (as the brick's).
+__device__ __forceinline__ double sweep_half(const RoiDev& R, int k, double* inv_s) {
+  *inv_s = (double)(R.res[k] - 1) / (R.hi[k] - R.lo[k]);
+  const double h = sqrt((double)R.c2) * *inv_s / (double)R.ih[k];
+  return h * (1.0 + 1e-9) + 1e-9;
+}
+
+// Block 0 zeroes the claim counters (never the error word), every block a
+// stride of the node sums of the header's tiles.
+__global__ __launch_bounds__(256) void k_sweep_zero(const BatchHdr* __restrict__ hdr,
+                                                    unsigned long long* __restrict__ acc,
+                                                    int32_t* __restrict__ claims) {
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kClaimSlices * kClaimStride; i += blockDim.x) claims[i] = 0;
+  constexpr int T = kSweep * kSweep * kSweep;
+  const int64_t n = hdr->n_tiles * T;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc[i] = 0ull;
+}
+
+// One wavefront per (ROI, group of 64 item boxes): the group's parent box
+// first (when the level above exists), then one box per lane, with the
+// tiles' box test against the box of all the ROI's nodes; passing boxes are
+// appended as (ROI << 32 | box).
+__global__ __launch_bounds__(256) void k_sweep_list(TreeView tv, BatchHdr* __restrict__ hdr,
+                                                    const RoiDev* __restrict__ rois,
+                                                    const double* __restrict__ coords,
+                                                    int64_t* __restrict__ items,
+                                                    int32_t* __restrict__ claims) {
+  const int lane = lane_id();
+  const int L = sweep_level(tv);
+  const int nb = tv.level_cnt[L];
+  const int ng = (nb + 63) >> 6;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ng == 0 || w >= (int64_t)hdr->n_rois * ng) return;
+  const int r = (int)(w / ng), grp = (int)(w % ng);
+  const RoiDev& R = rois[r];
+  TileGeo g;
+  g.r = r;
+  g.i0 = g.j0 = g.k0 = 0;
+  {
+    const double* cx = coords + R.coord_off;
+    const double* cy = cx + R.res[0];
+    const double* cz = cy + R.res[1];
+    g.lo[0] = cx[0];
+    g.hi[0] = cx[R.res[0] - 1];
+    g.lo[1] = cy[0];
+    g.hi[1] = cy[R.res[1] - 1];
+    g.lo[2] = cz[0];
+    g.hi[2] = cz[R.res[2] - 1];
+  }
+  if (L + 1 < tv.n_levels) {
+    const int gp = tv.level_off[L + 1] + grp;
+    if (!tile_box_test(tv, R, g, tv.nodes[gp], gp)) return;
+  }
+  const int b = grp * 64 + lane;
+  bool pass = false;
+  if (b < nb) {
+    const int gi = tv.level_off[L] + b;
+    pass = tv.nodes[gi].count > 0 && tile_box_test(tv, R, g, tv.nodes[gi], gi);
+  }
+  const uint64_t m = ballot(pass);
+  if (m == 0) return;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd((unsigned long long*)&hdr->n_items, (unsigned long long)popc64(m));
+  base = __shfl(base, 0, 64);
+  const int64_t pos = (int64_t)base + popc64(m & lanemask_lt());
+  if (pass) {
+    if (pos < hdr->item_cap)
+      items[pos] = ((int64_t)r << 32) | (int64_t)(uint32_t)b;
+    else
+      claims[kErrWord] = 1;
+  }
+}
+
+template <int KK, bool CNT, int NM>
+__global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
+                                               const RoiDev* __restrict__ rois,
+                                               const int64_t* __restrict__ items,
+                                               unsigned long long* __restrict__ acc,
+                                               int32_t* __restrict__ claims) {
+  constexpr int W = kSweepWin;
+  constexpr int S = kSweep;
+  __shared__ unsigned long long sums[W * W * W];
+  __shared__ double lds_c[3][W];
+  __shared__ int64_t lds_item;
+  const int lane = lane_id();
+  const int tid = threadIdx.x;
+  const int64_t n_items = min((int64_t)hdr->n_items, hdr->item_cap);
+  const int L = sweep_level(tv);
+  const int xcd = blockIdx.x & 7;
+  const int sub = (int)((blockIdx.x >> 3) & 7);
+  int cur = ((xcd + 0) & 7) * 8 + (sub & 7);
+  bool bad = false;
+  while (true) {
+    if (tid < 64) {
+      const int64_t it = claim_item(claims, n_items, xcd, sub, cur);
+      if (lane == 0) lds_item = it;
+    }
+    __syncthreads();
+    const int64_t pos = lds_item;
+    __syncthreads();  // lds_item is rewritten by the next claim
+    if (pos < 0) break;
+    const int64_t item = items[pos];
+    const int r = (int)(item >> 32);
+    const int b = (int)(item & 0xffffffff);
+    // an item outside the batch or the tree is an internal error (flagged,
+    // skipped: nothing is read out of bounds)
+    if ((unsigned)r >= (unsigned)hdr->n_rois || (unsigned)b >= (unsigned)tv.level_cnt[L]) {
+      bad = true;
+      continue;
+    }
+    const RoiDev& R = rois[r];
+    const NodeBox box = tv.nodes[tv.level_off[L] + b];
+    const int l0 = L == 1 ? b * SFK_FANOUT : b;
+    const int nl = L == 1 ? min(SFK_FANOUT, tv.n_leaves - l0) : 1;
+    double inv_s[3], half[3], lo[3], ih[3];
+    int w0[3], w1[3];
+    bool empty = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      half[k] = sweep_half(R, k, &inv_s[k]);
+      lo[k] = R.lo[k];
+      ih[k] = (double)R.ih[k];
+      const double fa = fmax(ceil(((double)box.lo[k] - lo[k]) * inv_s[k] - half[k]), 0.0);
+      const double fb =
+          fmin(floor(((double)box.hi[k] - lo[k]) * inv_s[k] + half[k]), (double)(R.res[k] - 1));
+      empty |= !(fa <= fb);
+      w0[k] = empty ? 0 : (int)fa;
+      w1[k] = empty ? -1 : (int)fb;
+    }
+    if (empty) continue;
+    const double c2 = (double)R.c2;
+    const float4* pts = tv.pts + (int64_t)l0 * SFK_LEAF;
+    // thread tid takes particles q = tid + 256 i of the box in the order
+    // "leaf q mod nl, slot q / nl": the lanes of a wavefront read 64
+    // different leaves
+    const int step_slot = 256 / nl, step_leaf = 256 % nl;
+    for (int bz = w0[2]; bz <= w1[2]; bz += W)
+      for (int by = w0[1]; by <= w1[1]; by += W)
+        for (int bx = w0[0]; bx <= w1[0]; bx += W) {
+          const int blk0[3] = {bx, by, bz};
+          const int nbk[3] = {min(W, w1[0] - bx + 1), min(W, w1[1] - by + 1),
+                              min(W, w1[2] - bz + 1)};
+          const int nxy = nbk[0] * nbk[1];
+          const int nn = nxy * nbk[2];
+          if (tid < 3 * W) {
+            const int k = tid / W, i = tid % W;
+            if (i < nbk[k]) lds_c[k][i] = node_coord(R, k, blk0[k] + i);
+          }
+          for (int i = tid; i < nn; i += 256) sums[i] = 0ull;
+          __syncthreads();
+          auto splat = [&](const float4 p) {
+            const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
+            int a[3], n[3];
+            bool ok = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              const double ic = (pp[k] - lo[k]) * inv_s[k];
+              const double fa = fmax(ceil(ic - half[k]), (double)blk0[k]);
+              const double fb = fmin(floor(ic + half[k]), (double)(blk0[k] + nbk[k] - 1));
+              ok &= fa <= fb;
+              a[k] = ok ? (int)fa - blk0[k] : 0;
+              n[k] = ok ? (int)(fb - fa) + 1 : 0;
+            }
+            if (!ok) return;
+            if (n[0] > NM || n[1] > NM || n[2] > NM) {
+              bad = true;
+              return;
+            }
+            double sx[NM], sy[NM], sz[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+              const double ux = (lds_c[0][min(a[0] + m, nbk[0] - 1)] - pp[0]) * ih[0];
+              const double uy = (lds_c[1][min(a[1] + m, nbk[1] - 1)] - pp[1]) * ih[1];
+              const double uz = (lds_c[2][min(a[2] + m, nbk[2] - 1)] - pp[2]) * ih[2];
+              sx[m] = ux * ux;
+              sy[m] = uy * uy;
+              sz[m] = uz * uz;
+            }
+#pragma unroll
+            for (int my = 0; my < NM; ++my) {
+#pragma unroll
+              for (int mx = 0; mx < NM; ++mx) {
+                if (mx < n[0] && my < n[1]) {
+                  const double sxy = sx[mx] + sy[my];
+                  const int row = (a[0] + mx) + nbk[0] * (a[1] + my) + nxy * a[2];
+#pragma unroll
+                  for (int mz = 0; mz < NM; ++mz) {
+                    const double u2 = sxy + sz[mz];
+                    if (mz < n[2] && u2 < c2) {
+                      unsigned int q;
+                      if constexpr (CNT) {
+                        q = 1u;
+                      } else if constexpr (KK == KK_EPAN) {
+                        q = (unsigned int)rint((1.0 - u2) * kSplatUnit);
+                      } else {
+                        const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
+                        q = (unsigned int)rint((double)e * kSplatUnit);
+                      }
+                      atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
+                    }
+                  }
+                }
+              }
+            }
+          };
+          int leaf = tid % nl, slot = tid / nl;
+          if (slot < SFK_LEAF) {
+            float4 p = pts[(int64_t)leaf * SFK_LEAF + slot];
+            while (true) {
+              int nleaf = leaf + step_leaf, nslot = slot + step_slot;
+              if (nleaf >= nl) {
+                nleaf -= nl;
+                ++nslot;
+              }
+              const bool more = nslot < SFK_LEAF;
+              float4 pn = p;
+              if (more) pn = pts[(int64_t)nleaf * SFK_LEAF + nslot];
+              splat(p);
+              if (!more) break;
+              p = pn;
+              leaf = nleaf;
+              slot = nslot;
+            }
+          }
+          __syncthreads();
+          // the window's nonzero sums into the batch's node sums
+          for (int i = tid; i < nn; i += 256) {
+            const unsigned long long v = sums[i];
+            if (v == 0ull) continue;
+            const int gi = blk0[0] + i % nbk[0];
+            const int gj = blk0[1] + (i / nbk[0]) % nbk[1];
+            const int gk = blk0[2] + i / nxy;
+            const int64_t t = R.tile_base + (gi / S) +
+                              (int64_t)R.ntile[0] * ((gj / S) + (int64_t)R.ntile[1] * (gk / S));
+            atomicAdd(&acc[t * (S * S * S) + (gi % S) + S * ((gj % S) + S * (gk % S))], v);
+          }
+          __syncthreads();
+        }
+  }
+  if (bad) claims[kErrWord] = 1;
+}
+
+// One block per tile of kSweep^3 nodes: sum * 2^-31 * scale, rounded once to
+// float (the brick's conversion).
+template <bool CNT>
+__global__ __launch_bounds__(256) void k_sweep_write(const BatchHdr* __restrict__ hdr,
+                                                     const RoiDev* __restrict__ rois,
+                                                     const unsigned long long* __restrict__ acc) {
+  constexpr int S = kSweep;
+  const int64_t n_tiles = hdr->n_tiles;
+  const int n_rois = hdr->n_rois;
+  const double unit = CNT ? 1.0 : 1.0 / kSplatUnit;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int r = find_roi(rois, n_rois, t);
+    const RoiDev& R = rois[r];
+    const int64_t lt = t - R.tile_base;
+    const int i0 = (int)(lt % R.ntile[0]) * S;
+    const int j0 = (int)((lt / R.ntile[0]) % R.ntile[1]) * S;
+    const int k0 = (int)(lt / ((int64_t)R.ntile[0] * R.ntile[1])) * S;
+    for (int n = threadIdx.x; n < S * S * S; n += 256) {
+      const int gi = i0 + n % S, gj = j0 + (n / S) % S, gk = k0 + n / (S * S);
+      if (gi < R.res[0] && gj < R.res[1] && gk < R.res[2])
+        R.out[gi + (int64_t)R.res[0] * (gj + (int64_t)R.res[1] * gk)] =
+            (float)(((double)acc[t * (S * S * S) + n] * unit) * R.scale);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // debug: support sets of single nodes (one wavefront per node)
 // ---------------------------------------------------------------------------
 
@@ -1292,10 +1589,74 @@ __global__ __launch_bounds__(256) void k_debug_candidates(TreeView tv, const int
 bool tile_shape_supported(TileShape ts) {
   return (ts.tx == 4 && ts.ty == 4 && (ts.tz == 4 || ts.tz == 2)) ||
          (ts.tx == 4 && ts.ty == 2 && ts.tz == 2) || (ts.tx == 2 && ts.ty == 2 && ts.tz == 2) ||
-         (ts.tx == 1 && ts.ty == 1 && ts.tz == 1) || is_brick(ts);
+         (ts.tx == 1 && ts.ty == 1 && ts.tz == 1) || is_brick(ts) || is_sweep(ts);
 }
 
 bool is_brick(TileShape ts) { return ts.tx == kBrick && ts.ty == kBrick && ts.tz == kBrick; }
+bool is_sweep(TileShape ts) { return ts.tx == kSweep && ts.ty == kSweep && ts.tz == kSweep; }
+
+hipError_t launch_sweep_list(TreeView tv, BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, int64_t* items, unsigned long long* acc,
+                             int32_t* claims, int max_rois, int64_t max_tiles, hipStream_t s) {
+  constexpr int64_t T = kSweep * kSweep * kSweep;
+  const int zb = (int)std::max<int64_t>(1, std::min<int64_t>((max_tiles * T + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_sweep_zero, dim3(zb), dim3(256), 0, s, hdr, acc, claims);
+  const int L = tv.n_levels >= 2 ? 1 : 0;
+  const int64_t ng = ((int64_t)tv.level_cnt[L] + 63) / 64;
+  const int64_t waves = ng * std::max(1, max_rois);
+  if (waves > 0)
+    hipLaunchKernelGGL(k_sweep_list, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, tv, hdr,
+                       rois, coords, items, claims);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_eval(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, int kk, bool cnt, int nm,
+                             const int64_t* items, unsigned long long* acc, int32_t* claims,
+                             int grid_blocks, int n_cu, int64_t max_tiles, hipStream_t s) {
+  (void)coords;
+  if (nm < 1 || nm > kSweepMaxNM) return hipErrorInvalidValue;
+#define SFK_W(KK, C, NM)                                                                      \
+  do {                                                                                        \
+    static int occ_ = 0;                                                                      \
+    if (occ_ == 0) {                                                                          \
+      int b_ = 0;                                                                             \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b_, k_sweep<KK, C, NM>, 256, 0) !=    \
+              hipSuccess ||                                                                   \
+          b_ < 1)                                                                             \
+        b_ = 1;                                                                               \
+      occ_ = b_;                                                                              \
+    }                                                                                         \
+    const int g_ = grid_blocks > 0 ? grid_blocks : n_cu * occ_;                               \
+    hipLaunchKernelGGL((k_sweep<KK, C, NM>), dim3(g_), dim3(256), 0, s, tv, hdr, rois, items, \
+                       acc, claims);                                                          \
+  } while (0)
+#define SFK_W_NM(KK, C)        \
+  switch (nm) {                \
+    case 1: SFK_W(KK, C, 1); break; \
+    case 2: SFK_W(KK, C, 2); break; \
+    case 3: SFK_W(KK, C, 3); break; \
+    case 4: SFK_W(KK, C, 4); break; \
+    default: SFK_W(KK, C, 5); break; \
+  }
+  if (cnt) {
+    SFK_W_NM(KK_EPAN, true);
+  } else if (kk == KK_EPAN) {
+    SFK_W_NM(KK_EPAN, false);
+  } else {
+    SFK_W_NM(KK_GAUSS, false);
+  }
+#undef SFK_W_NM
+#undef SFK_W
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int wb = (int)std::max<int64_t>(1, std::min<int64_t>(max_tiles, 16384));
+  if (cnt)
+    hipLaunchKernelGGL(k_sweep_write<true>, dim3(wb), dim3(256), 0, s, hdr, rois, acc);
+  else
+    hipLaunchKernelGGL(k_sweep_write<false>, dim3(wb), dim3(256), 0, s, hdr, rois, acc);
+  return hipGetLastError();
+}
 
 // every shape of the range query (wavefront tiles and bricks)
 #define SFK_SHAPE_SWITCH(ts, MACRO)                                  \

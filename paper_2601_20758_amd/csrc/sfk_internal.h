@@ -110,6 +110,15 @@ constexpr int kBrick = 16;
 // Fixed point of the brick's integer node sums: a term v in [0, 1] counts
 // rint(v * 2^31) units (so a sum of up to 2^32 terms fits in 64 bits).
 constexpr double kSplatUnit = 2147483648.0;
+// Particle sweep (dense uniform-bandwidth ROIs): work items are boxes of the
+// hierarchy's first interior level (64 leaves), each scattered once into
+// an LDS window of at most kSweepWin^3 nodes and flushed into 64-bit integer
+// node sums kept per tile of kSweep^3 nodes (the shape's "tiles": they only
+// lay out the sums and the final conversion). A particle's support spans at
+// most kSweepMaxNM nodes per axis.
+constexpr int kSweep = 8;
+constexpr int kSweepWin = 16;
+constexpr int kSweepMaxNM = 5;
 
 // ---- host-side launch wrappers (defined in the .hip files) ----
 namespace sfk {
@@ -252,7 +261,24 @@ hipError_t launch_debug_candidates2(TreeView tv, const int32_t* perm, const RoiD
                                     int32_t* idx_out, hipStream_t s);
 bool tile_shape_supported(TileShape ts);
 bool is_brick(TileShape ts);
+bool is_sweep(TileShape ts);
 int tile_grid_blocks(int64_t n_tiles);
+// Particle sweep of a batch (uniform bandwidths), in two launches.
+// launch_sweep_list: zero the integer node sums of hdr->n_tiles tiles (acc,
+// kSweep^3 64-bit sums per tile) and the claim counters, and list the
+// (ROI, box) work items into items[0, hdr->item_cap) (count in
+// hdr->n_items); max_rois / max_tiles bound the header's counts (the grids
+// of a captured graph use the capacities).
+// launch_sweep_eval: scatter the items and write every node of every ROI.
+// nm: nodes per axis a support can span (1..kSweepMaxNM). A listing past
+// the capacity or a support wider than nm sets the error word.
+hipError_t launch_sweep_list(TreeView tv, BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, int64_t* items, unsigned long long* acc,
+                             int32_t* claims, int max_rois, int64_t max_tiles, hipStream_t s);
+hipError_t launch_sweep_eval(TreeView tv, const BatchHdr* hdr, const RoiDev* rois,
+                             const double* coords, int kk, bool cnt, int nm,
+                             const int64_t* items, unsigned long long* acc, int32_t* claims,
+                             int grid_blocks, int n_cu, int64_t max_tiles, hipStream_t s);
 
 // mbe.hip
 // leaves whose box meets the closed box [lo, hi]: flags[n_leaves]; their

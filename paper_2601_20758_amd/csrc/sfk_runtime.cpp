@@ -114,7 +114,7 @@ struct Staging {
 struct GraphCache {
   bool valid = false;
   TileShape ts{0, 0, 0};
-  int kk = 0, pp = 0, ch = 0;
+  int kk = 0, pp = 0, ch = 0, nm = 0;
   bool cnt = false;
   bool interleave = false;  // captured with one-wave-per-tile evaluation grids
   sfk_tree tree = nullptr;
@@ -423,8 +423,10 @@ double ck_gauss_trunc3() {
 }
 
 constexpr int kHostLevelNodes = 32768;  // boxes of the finest level kept on the host
-constexpr int kNumShapes = 6;  // tile shapes 1..6 of sfk_eval_opts.tile_shape
+constexpr int kNumShapes = SFK_NUM_TILE_SHAPES;  // tile shapes 1..7 of sfk_eval_opts.tile_shape
+static_assert(SFK_NUM_TILE_SHAPES == 7, "tile shape table");
 constexpr int kBrickShape = 6;  // bricks of kBrick^3 nodes, scatter evaluation
+constexpr int kSweepShape = 7;  // particle sweep over the hierarchy's boxes
 
 TileShape shape_of(int id) {
   switch (id) {
@@ -433,6 +435,7 @@ TileShape shape_of(int id) {
     case 4: return TileShape{2, 2, 2};
     case 5: return TileShape{1, 1, 1};
     case 6: return TileShape{kBrick, kBrick, kBrick};
+    case 7: return TileShape{kSweep, kSweep, kSweep};
     default: return TileShape{4, 4, 4};
   }
 }
@@ -600,6 +603,23 @@ struct GroupRoi {
   double scale;
 };
 
+// Nodes per axis one particle's support can span in the particle sweep (the
+// kernel's half-width in node steps, rounded outwards as the kernel rounds
+// it, with a further 1e-6 margin; the kernel reports a wider span as an
+// internal error). 0 for per-particle bandwidths.
+int sweep_nm(const GroupRoi& g) {
+  if (g.pp != PP_UNIFORM) return 0;
+  int nm = 1;
+  for (int k = 0; k < 3; ++k) {
+    const sfk_roi* r = g.roi;
+    const double inv_s = (double)(r->res[k] - 1) / (r->hi[k] - r->lo[k]);
+    const double h = std::sqrt((double)g.c2) * inv_s / (double)g.ih[k];
+    const double half = h * (1.0 + 1e-9) + 1e-9;
+    nm = std::max(nm, (int)std::floor(2.0 * half + 1e-6) + 1);
+  }
+  return nm;
+}
+
 int chunk_leaves_of(sfk_ctx c) {
   return c->opts.chunk_leaves > 0 ? c->opts.chunk_leaves : kDefaultChunkLeaves;
 }
@@ -653,6 +673,7 @@ struct Caps {
 // 10M per-point workload average ~124 leaves, 4x2x2 tiles of dense 1e9-point
 // ROIs several hundred).
 int32_t slot_cap_of(TileShape ts) {
+  if (sfk::is_sweep(ts)) return 32;  // the sweep keeps no per-tile lists
   const int t = ts.tx * ts.ty * ts.tz;
   return std::min(kTileSlotCap, std::max(32, 16 * t));
 }
@@ -677,6 +698,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   // chunks the leaf lists hold, so a batch whose lists overflow still splits
   // its heavy tiles over work items (walking per chunk)
   const bool brick = sfk::is_brick(ts);
+  const bool sweep = sfk::is_sweep(ts);
   // a brick's partial slot holds its kBrick^3 node sums (32 KB): one per
   // split brick, up to 8192 of them; bricks beyond walk their whole tile in
   // one work item (which needs no slot)
@@ -684,11 +706,20 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
       brick ? std::max<int64_t>(64, std::min<int64_t>(tiles, 8192))
             : std::max<int64_t>({ws.want_partial_cap, (int64_t)1 << 14, tiles / 4,
                                  2 * leaf_cap / CH});
-  if (c->opts.list_capacity > 0) {
+  // the sweep: the node sums of every tile, and the (ROI, box) items of
+  // every descriptor the header may hold (two int32 per item)
+  const int64_t sweep_boxes = tree_leaves > SFK_FANOUT
+                                  ? (tree_leaves + SFK_FANOUT - 1) / SFK_FANOUT
+                                  : tree_leaves;
+  if (sweep) {
+    partial_cap = std::max<int64_t>(1, tiles);
+    leaf_cap = std::max<int64_t>(leaf_cap, 2 * nr * std::max<int64_t>(1, sweep_boxes));
+  }
+  if (c->opts.list_capacity > 0 && !sweep) {
     leaf_cap = c->opts.list_capacity;
     partial_cap = std::max<int64_t>(1, c->opts.list_capacity / CH);
   }
-  if (c->opts.partial_capacity > 0) partial_cap = c->opts.partial_capacity;
+  if (c->opts.partial_capacity > 0 && !sweep) partial_cap = c->opts.partial_capacity;
   SFK_TRY(ws_reserve(c, ws, ws.tile_cnt, sizeof(int32_t) * (size_t)tiles, "tile counts"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_fit, sizeof(int32_t) * (size_t)tiles, "tile flags"));
   SFK_TRY(ws_reserve(c, ws, ws.tile_done, sizeof(int32_t) * (size_t)tiles, "tile counters"));
@@ -724,10 +755,13 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
                                    (int64_t)(ws.leaf_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.partial_off.bytes / sizeof(int64_t)) - 1,
                                    (int64_t)(ws.chunk_off.bytes / sizeof(int64_t)) - 1});
-  k.leaf_cap = c->opts.list_capacity > 0 ? leaf_cap : (int64_t)(ws.leaves.bytes / sizeof(int32_t));
-  k.partial_cap = c->opts.list_capacity > 0
+  k.leaf_cap = c->opts.list_capacity > 0 && !sweep ? leaf_cap
+                                                  : (int64_t)(ws.leaves.bytes / sizeof(int32_t));
+  k.partial_cap = c->opts.list_capacity > 0 && !sweep
                       ? partial_cap
                       : (int64_t)(ws.partials.bytes / (sizeof(double) * (size_t)T));
+  // the sweep's node sums live in the partial slots: one slot per tile
+  if (sweep) k.tiles_cap = std::min(k.tiles_cap, k.partial_cap);
   k.rois_cap = std::min<int64_t>({(int64_t)((ws.hdr_rois.bytes - sizeof(BatchHdr)) / sizeof(RoiDev)),
                                   (int64_t)(ws.roi_leaves.bytes / (sizeof(int32_t) * kRoiListCap)),
                                   (int64_t)(ws.roi_nl.bytes / sizeof(int32_t))});
@@ -739,6 +773,7 @@ sfk_status reserve_group(sfk_ctx c, Workspace& ws, TileShape ts, int64_t n_rois,
   // brick has one slot for all its chunks and never walks per chunk, so its
   // extra items are bounded by the listed leaves / chunk_leaves.
   k.item_cap = k.tiles_cap + k.partial_cap + 1 + (brick ? k.leaf_cap / CH + 1 : 0);
+  if (sweep) k.item_cap = k.leaf_cap / 2;  // the item list lives in the leaf-list buffer
   k.splat = brick ? 1 : 0;
   SFK_TRY(ws_reserve(c, ws, ws.item_tile, sizeof(int32_t) * (size_t)k.item_cap, "work items"));
   *caps = k;
@@ -765,7 +800,29 @@ BatchHdr make_hdr(sfk_ctx c, const Caps& k, int64_t n_rois, int64_t n_tiles) {
 // tile and plan grids (exact for direct launches, the capacities for a
 // captured graph).
 sfk_status launch_kernels(sfk_ctx c, const TreeView& tv, TileShape ts, int kk, int pp, bool cnt,
-                          Workspace& ws, int roi_grid, int64_t max_tiles, hipStream_t s) {
+                          Workspace& ws, int roi_grid, int64_t max_tiles, hipStream_t s,
+                          int nm = 0) {
+  if (sfk::is_sweep(ts)) {
+    BatchHdr* hdr = (BatchHdr*)ws.hdr_rois.p;
+    const RoiDev* rois = (const RoiDev*)((char*)ws.hdr_rois.p + sizeof(BatchHdr));
+    double* coords = (double*)ws.coords.p;
+    SFK_HIP(c, sfk::launch_roi_coords(tv, hdr, rois, roi_grid, coords, (int32_t*)ws.roi_leaves.p,
+                                      (int32_t*)ws.roi_nl.p, s));
+    {
+      ProfScope p(c, PK_TILE_COUNT, s);
+      SFK_HIP(c, sfk::launch_sweep_list(tv, hdr, rois, coords, (int64_t*)ws.leaves.p,
+                                        (unsigned long long*)ws.partials.p, (int32_t*)ws.claims.p,
+                                        roi_grid, max_tiles, s));
+    }
+    const int grid = c->opts.persistent_waves_per_cu > 0
+                         ? c->n_cu * std::max(1, c->opts.persistent_waves_per_cu / 4)
+                         : 0;
+    ProfScope p(c, PK_EVAL, s, hdr);
+    SFK_HIP(c, sfk::launch_sweep_eval(tv, hdr, rois, coords, kk, cnt, nm, (const int64_t*)ws.leaves.p,
+                                      (unsigned long long*)ws.partials.p, (int32_t*)ws.claims.p,
+                                      grid, c->n_cu, max_tiles, s));
+    return SFK_OK;
+  }
   const int tile_grid = sfk::tile_grid_blocks(max_tiles);
   const int CH = chunk_leaves_of(c);
   BatchHdr* hdr = (BatchHdr*)ws.hdr_rois.p;
@@ -859,8 +916,10 @@ GroupRoi resolve_cloud_roi(sfk_tree t, const sfk_roi* r, bool count_mode) {
 struct GroupKey {
   int kk, pp;
   TileShape ts;
+  int nm;  // particle sweep: nodes per axis a support spans (0 otherwise)
   bool operator==(const GroupKey& o) const {
-    return kk == o.kk && pp == o.pp && ts.tx == o.ts.tx && ts.ty == o.ts.ty && ts.tz == o.ts.tz;
+    return kk == o.kk && pp == o.pp && ts.tx == o.ts.tx && ts.ty == o.ts.ty &&
+           ts.tz == o.ts.tz && nm == o.nm;
   }
 };
 
@@ -871,7 +930,8 @@ void group_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois, 
                 const TileShape* force_ts = nullptr) {
   for (const sfk_roi* r : rois) {
     GroupRoi g = resolve_cloud_roi(t, r, count_mode);
-    const GroupKey key{count_mode ? 0 : g.kk, g.pp, force_ts ? *force_ts : choose_shape(c, t, r)};
+    const TileShape ts = force_ts ? *force_ts : choose_shape(c, t, r);
+    const GroupKey key{count_mode ? 0 : g.kk, g.pp, ts, sfk::is_sweep(ts) ? sweep_nm(g) : 0};
     size_t gi = 0;
     while (gi < keys->size() && !((*keys)[gi] == key)) ++gi;
     if (gi == keys->size()) {
@@ -916,7 +976,7 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
     const size_t gb = sizeof(BatchHdr) + sizeof(RoiDev) * (size_t)n;
     SFK_HIP(c, hipMemcpyAsync(ws.hdr_rois.p, st.host + off, gb, hipMemcpyHostToDevice, s));
     SFK_TRY(launch_kernels(c, tv, keys[gi].ts, keys[gi].kk, keys[gi].pp, count_mode, ws, (int)n,
-                           tiles[gi], s));
+                           tiles[gi], s, keys[gi].nm));
     off += gb;
   }
   SFK_HIP(c, hipMemcpyAsync(st.hdr_host, ws.hdr_rois.p, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
@@ -944,13 +1004,13 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   if (groups.size() != 1) return enqueue_cloud_rois(c, t, rois, false, sl.ws, sl.st, sl.stream);
   const int64_t n = (int64_t)groups[0].size();
   const TileShape ts = keys[0].ts;
-  const int kk = keys[0].kk, pp = keys[0].pp, ch = chunk_leaves_of(c);
+  const int kk = keys[0].kk, pp = keys[0].pp, ch = chunk_leaves_of(c), nm = keys[0].nm;
   std::vector<RoiDev> rd((size_t)n);
   int64_t n_tiles = 0, n_coords = 0;
   make_roidev(groups[0], ts, rd.data(), &n_tiles, &n_coords);
   GraphCache& gc = sl.gc;
   const bool fits = gc.valid && gc.gen == sl.ws.gen && gc.st_gen == sl.st.gen && gc.tree == t &&
-                    gc.kk == kk &&
+                    gc.kk == kk && gc.nm == nm &&
                     gc.pp == pp && gc.ch == ch && !gc.cnt && gc.interleave == c->serve_interleave &&
                     gc.ts.tx == ts.tx &&
                     gc.ts.ty == ts.ty && gc.ts.tz == ts.tz && n <= gc.rois_cap &&
@@ -983,7 +1043,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
       st = SFK_E_DEVICE;
     if (st == SFK_OK)
       st = launch_kernels(c, view_of(t), ts, kk, pp, false, sl.ws, (int)k.rois_cap, k.tiles_cap,
-                          s);
+                          s, nm);
     if (st == SFK_OK && hipMemcpyAsync(sl.st.hdr_host, sl.ws.hdr_rois.p, sizeof(BatchHdr),
                                        hipMemcpyDeviceToHost, s) != hipSuccess)
       st = SFK_E_DEVICE;
@@ -1008,6 +1068,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
     gc.valid = true;
     gc.ts = ts;
     gc.kk = kk;
+    gc.nm = nm;
     gc.pp = pp;
     gc.ch = ch;
     gc.cnt = false;
@@ -1424,13 +1485,17 @@ int tune_key(sfk_tree t, const sfk_roi* r) {
 // support/spacing bucket: a support below half the node spacing reaches at
 // most one node per particle, so one node per wavefront reads only the
 // particles near nodes; larger supports share each particle among more nodes.
-int default_shape(int key, double particles_per_support) {
+int default_shape(int key, double particles_per_support, bool sweep_ok) {
   // sparse uniform-bandwidth ROIs (under about one particle per node) take
   // bricks: a tile's fixed costs (claim, range query, reduction) would
   // dominate its few pairs (measured: a 256^3 box of side 1/64 around a
   // clump of a 100M cloud, 0.27 ms in bricks vs 1.40 ms in 4x4x4 tiles)
   const int dens = key & 7, kb = (key >> 6) & 3;
-  if ((kb == SFK_BW_FIXED || kb == SFK_BW_ROI_SCALED) && dens < 4) return kBrickShape;
+  const bool uniform = kb == SFK_BW_FIXED || kb == SFK_BW_ROI_SCALED;
+  if (uniform && dens < 4) return kBrickShape;
+  // dense uniform-bandwidth ROIs (2 or more particles per node) whose
+  // supports span at most kSweepMaxNM nodes per axis: the particle sweep
+  if (uniform && sweep_ok && dens >= 5) return kSweepShape;
   // Dense ROIs keep wavefront tiles, by support/spacing ratio: below 0.5 a
   // particle reaches at most one node, so one node per wavefront reads only
   // the particles near nodes (where a node's support holds many particles);
@@ -1457,6 +1522,19 @@ double particles_per_support(sfk_tree t, const sfk_roi* r) {
   return (double)t->n * sup / vol;
 }
 
+// The particle sweep takes uniform bandwidths whose supports span at most
+// kSweepMaxNM nodes per axis.
+bool sweep_ok(sfk_tree t, const sfk_roi* r) {
+  if (!uniform_bw(r)) return false;
+  const int nm = sweep_nm(resolve_cloud_roi(t, r, false));
+  return nm >= 1 && nm <= kSweepMaxNM;
+}
+
+// The untuned default of a ROI when the sweep is not an option.
+int default_shape_no_sweep(sfk_tree t, const sfk_roi* r) {
+  return default_shape(tune_key(t, r), particles_per_support(t, r), false);
+}
+
 TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
   int id = 0;
   if (c->opts.tile_shape > 0) {
@@ -1464,9 +1542,11 @@ TileShape choose_shape(sfk_ctx c, sfk_tree t, const sfk_roi* r) {
   } else {
     const int key = tune_key(t, r);
     auto it = c->tune.find(key);
-    id = it != c->tune.end() ? it->second : default_shape(key, particles_per_support(t, r));
+    id = it != c->tune.end() ? it->second
+                             : default_shape(key, particles_per_support(t, r), sweep_ok(t, r));
   }
   if (id == kBrickShape && !uniform_bw(r)) id = 1;  // bricks need a uniform bandwidth
+  if (id == kSweepShape && !sweep_ok(t, r)) id = default_shape_no_sweep(t, r);
   return shape_of(id);
 }
 
@@ -2116,13 +2196,70 @@ sfk_status sfk_eval_roi_noalloc(sfk_ctx c, sfk_tree t, const sfk_roi* roi, void*
   }
   const hipStream_t s = (hipStream_t)hip_stream;
   const GroupRoi g = resolve_cloud_roi(t, roi, false);
-  const TileShape ts = choose_shape(c, t, roi);
-  const int T = ts.tx * ts.ty * ts.tz;
+  TileShape ts = choose_shape(c, t, roi);
+  const size_t cap = SFK_NOALLOC_SCRATCH_BYTES;
+  auto rb = [](size_t b) { return round_bytes(std::max<size_t>(b, 256)); };
   RoiDev rd;
   int64_t n_tiles = 0, n_coords = 0;
   make_roidev(&g, 1, ts, &rd, &n_tiles, &n_coords);
-  const size_t cap = SFK_NOALLOC_SCRATCH_BYTES;
-  auto rb = [](size_t b) { return round_bytes(std::max<size_t>(b, 256)); };
+  if (sfk::is_sweep(ts)) {
+    // the particle sweep needs the node sums of all its tiles and one item
+    // per box of the hierarchy's first interior level
+    const int64_t boxes = t->n_leaves > SFK_FANOUT
+                              ? ((int64_t)t->n_leaves + SFK_FANOUT - 1) / SFK_FANOUT
+                              : (int64_t)t->n_leaves;
+    const size_t need = rb(sizeof(BatchHdr) + sizeof(RoiDev)) + rb(sizeof(double) * n_coords) +
+                        rb(kClaimBytes) + rb(sizeof(int32_t) * kRoiListCap) + rb(sizeof(int32_t)) +
+                        rb(sizeof(unsigned long long) * kSweep * kSweep * kSweep * (size_t)n_tiles) +
+                        rb(sizeof(int64_t) * (size_t)std::max<int64_t>(1, boxes));
+    if (need <= cap) {
+      Workspace wv;
+      size_t used = 0;
+      auto take = [&](DevBuf& b, size_t bytes) {
+        b.p = c->na_scratch + used;
+        b.bytes = bytes;
+        used += rb(bytes);
+      };
+      take(wv.hdr_rois, sizeof(BatchHdr) + sizeof(RoiDev));
+      take(wv.coords, sizeof(double) * (size_t)n_coords);
+      take(wv.claims, kClaimBytes);
+      take(wv.roi_leaves, sizeof(int32_t) * kRoiListCap);
+      take(wv.roi_nl, sizeof(int32_t));
+      take(wv.partials, sizeof(unsigned long long) * kSweep * kSweep * kSweep * (size_t)n_tiles);
+      take(wv.leaves, sizeof(int64_t) * (size_t)std::max<int64_t>(1, boxes));
+      BatchHdr h{};
+      h.n_tiles = n_tiles;
+      h.item_cap = std::max<int64_t>(1, boxes);
+      h.n_rois = 1;
+      h.slot_cap = slot_cap_of(ts);
+      h.debug_poison = c->debug_poison;
+      const int si = c->na_next;
+      c->na_next = (c->na_next + 1) % kStagingRing;
+      if (c->na_ev_valid[si]) SFK_HIP(c, hipEventSynchronize(c->na_ev[si]));
+      std::memcpy(c->na_host[si], &h, sizeof h);
+      std::memcpy(c->na_host[si] + sizeof(BatchHdr), &rd, sizeof rd);
+      if (c->na_last_valid && c->na_last_stream != s)
+        SFK_HIP(c, hipStreamWaitEvent(s, c->na_last, 0));
+      SFK_HIP(c, hipMemcpyAsync(wv.hdr_rois.p, c->na_host[si], sizeof(BatchHdr) + sizeof(RoiDev),
+                                hipMemcpyHostToDevice, s));
+      const bool prof = c->prof_on;
+      c->prof_on = false;
+      const sfk_status st =
+          launch_kernels(c, view_of(t), ts, g.kk, g.pp, false, wv, 1, n_tiles, s, sweep_nm(g));
+      c->prof_on = prof;
+      SFK_TRY(st);
+      SFK_HIP(c, hipEventRecord(c->na_ev[si], s));
+      c->na_ev_valid[si] = true;
+      SFK_HIP(c, hipEventRecord(c->na_last, s));
+      c->na_last_valid = true;
+      c->na_last_stream = s;
+      return SFK_OK;
+    }
+    // too large for the array: the shape the ROI would take without the sweep
+    ts = shape_of(default_shape_no_sweep(t, roi));
+    make_roidev(&g, 1, ts, &rd, &n_tiles, &n_coords);
+  }
+  const int T = ts.tx * ts.ty * ts.tz;
   const size_t nt = (size_t)n_tiles;
   const size_t fixed0 = rb(sizeof(BatchHdr) + sizeof(RoiDev)) + rb(sizeof(double) * n_coords) +
                         rb(kClaimBytes) + rb(sizeof(int32_t) * kRoiListCap) +
@@ -2567,7 +2704,10 @@ sfk_status sfk_debug_candidates(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
   const int64_t nn = node_end - node_begin;
   hipStream_t s = c->slots[0].stream;
   SFK_HIP(c, hipStreamSynchronize(s));
-  const TileShape ts = choose_shape(c, t, roi);
+  TileShape ts = choose_shape(c, t, roi);
+  // the sweep has no tiles: its support sets are found with the brick's
+  // (support sets do not depend on the tile shape)
+  if (sfk::is_sweep(ts)) ts = shape_of(kBrickShape);
   GroupRoi g = resolve_cloud_roi(t, roi, false);
   std::vector<GroupRoi> v{g};
   RoiDev rd;
@@ -2665,7 +2805,14 @@ sfk_status sfk_debug_eval_count(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64
       BatchHdr hh;
       SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr_rois.p, sizeof hh, hipMemcpyDeviceToHost));
       const TileShape ts = choose_shape(c, t, roi);
-      tested = hh.total_leaves * SFK_LEAF * (int64_t)(ts.tx * ts.ty * ts.tz);
+      if (sfk::is_sweep(ts)) {
+        // listed boxes x their particles x the unrolled node span
+        const int nm = sweep_nm(resolve_cloud_roi(t, roi, false));
+        const int64_t per_box = t->n_leaves > SFK_FANOUT ? (int64_t)SFK_FANOUT * SFK_LEAF : SFK_LEAF;
+        tested = hh.n_items * per_box * (int64_t)(nm * nm * nm);
+      } else {
+        tested = hh.total_leaves * SFK_LEAF * (int64_t)(ts.tx * ts.ty * ts.tz);
+      }
     }
     *tested_pairs = tested;
   }
@@ -2692,6 +2839,38 @@ sfk_status sfk_debug_tile_leaves(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int3
   if (c->direct_last_valid) SFK_HIP(c, hipEventSynchronize(c->direct_last));
   const TileShape ts = choose_shape(c, t, roi);
   BatchHdr hh{};
+  if (sfk::is_sweep(ts)) {
+    // the sweep keeps no tile lists: its work items, the boxes of the
+    // hierarchy's first interior level (the leaves for a tree of at most 64
+    // leaves) that pass the box test, ascending
+    SFK_TRY(eval_direct(c, t, roi, s, false));
+    SFK_HIP(c, hipStreamSynchronize(s));
+    SFK_HIP(c, hipMemcpy(&hh, c->direct_ws.hdr_rois.p, sizeof hh, hipMemcpyDeviceToHost));
+    if (hh.n_items > hh.item_cap) {
+      set_err(c, "sweep item list overflowed");
+      return SFK_E_INTERNAL;
+    }
+    *n_tiles_out = hh.n_tiles;
+    *total_out = hh.n_items;
+    if (h_shape) {
+      h_shape[0] = ts.tx;
+      h_shape[1] = ts.ty;
+      h_shape[2] = ts.tz;
+    }
+    if (h_tile_cnt && hh.n_tiles <= tiles_cap)
+      for (int64_t i = 0; i < hh.n_tiles; ++i) h_tile_cnt[i] = 0;
+    if (h_leaves && hh.n_items <= cap) {
+      std::vector<int64_t> it((size_t)hh.n_items);
+      if (hh.n_items > 0)
+        SFK_HIP(c, hipMemcpy(it.data(), c->direct_ws.leaves.p, sizeof(int64_t) * hh.n_items,
+                             hipMemcpyDeviceToHost));
+      std::vector<int32_t> boxes((size_t)hh.n_items);
+      for (size_t i = 0; i < it.size(); ++i) boxes[i] = (int32_t)(it[i] & 0xffffffff);
+      std::sort(boxes.begin(), boxes.end());
+      std::copy(boxes.begin(), boxes.end(), h_leaves);
+    }
+    return SFK_OK;
+  }
   // the direct path's pipeline; a second run with room for every list if
   // the first overflowed (every tile then keeps its list)
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -2810,8 +2989,9 @@ sfk_status sfk_autotune(sfk_ctx c, sfk_tree t, const sfk_roi* sample, int32_t n)
     auto& v = cost[key];
     if (v.empty()) v.assign(kNumShapes + 1, 0.0);
     for (int shape = 1; shape <= kNumShapes && st == SFK_OK; ++shape) {
-      if (shape == kBrickShape && !uniform_bw(&sample[i])) {
-        v[shape] = 1e30;  // bricks take uniform bandwidths only
+      if ((shape == kBrickShape && !uniform_bw(&sample[i])) ||
+          (shape == kSweepShape && !sweep_ok(t, &sample[i]))) {
+        v[shape] = 1e30;  // bricks and the sweep take uniform bandwidths only
         continue;
       }
       c->opts.tile_shape = shape;
@@ -2974,7 +3154,8 @@ static double request_bytes(const sfk_roi& r, TileShape ts) {
   const double m = (double)r.res[0] * r.res[1] * r.res[2];
   const double tiles = std::ceil((double)r.res[0] / ts.tx) * std::ceil((double)r.res[1] / ts.ty) *
                        std::ceil((double)r.res[2] / ts.tz);
-  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4 + 4.0 * slot_cap_of(ts));
+  const double sums = sfk::is_sweep(ts) ? 8.0 * kSweep * kSweep * kSweep : 0.0;
+  return 4.0 * m + tiles * (3 * 4 + 3 * 8 + 64 * 4 + 4.0 * slot_cap_of(ts) + sums);
 }
 
 sfk_status sfk_serve(sfk_ctx c, sfk_tree t, const sfk_request* reqs, int64_t n,

@@ -41,7 +41,27 @@ def _cpu_tile_lists(roi, boxes, ih, c2, shape):
     return out
 
 
-@pytest.mark.parametrize("shape_id", [0, 2, 4, 5])
+def _cpu_sweep_items(roi, boxes, ih, c2):
+    """The particle sweep's work items: the boxes of 64 consecutive leaves
+    (each leaf alone for a tree of at most 64 leaves), bounded by their
+    leaves' boxes, that pass the same test against the box of all the ROI's
+    nodes; ascending."""
+    n = boxes.shape[0]
+    if n > 64:
+        g = [boxes[i:i + 64] for i in range(0, n, 64)]
+        boxes = np.array([np.concatenate([b[:, :3].min(0), b[:, 3:].max(0)]) for b in g],
+                         dtype=np.float32)
+    ax = [oracle.axis_coords(roi.lo[k], roi.hi[k], int(roi.res[k])) for k in range(3)]
+    tlo = np.array([ax[k][0] for k in range(3)])
+    thi = np.array([ax[k][-1] for k in range(3)])
+    gap = np.maximum(np.maximum(boxes[:, :3].astype(np.float64) - thi,
+                                tlo - boxes[:, 3:].astype(np.float64)), 0.0)
+    u = gap * np.asarray(ih, dtype=np.float32).astype(np.float64)
+    u2 = (u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1]) + u[:, 2] * u[:, 2]
+    return np.nonzero(u2 < c2)[0].astype(np.int32)
+
+
+@pytest.mark.parametrize("shape_id", [0, 2, 4, 5, 7])
 def test_tile_lists_match_cpu_walk(ctx, torch, shape_id):
     pts = synth.clumpy_cloud(200_000, 7)
     tree = ctx.build_tree(dev(torch, pts))
@@ -60,6 +80,12 @@ def test_tile_lists_match_cpu_walk(ctx, torch, shape_id):
         h = oracle.roi_h(roi)
         ih = (1.0 / h.astype(np.float64)).astype(np.float32)
         c2 = 1.0 if roi.kernel == "epanechnikov" else 9.0
+        if shape == (8, 8, 8):
+            # the sweep (chosen, or by default for the dense ROI): its items
+            assert np.all(cnt == 0)
+            assert np.array_equal(leaves, _cpu_sweep_items(roi, boxes, ih, c2)), "roi %d" % i
+            say("roi", i, "sweep items", len(leaves))
+            continue
         want = _cpu_tile_lists(roi, boxes, ih, c2, shape)
         assert len(cnt) == len(want)
         assert np.array_equal(cnt, [len(w) for w in want]), "roi %d counts" % i
@@ -74,6 +100,7 @@ def test_poisoned_leaf_ids_are_reported(ctx, torch, sfk):
     # wide supports so that tiles hold 65-256 candidate leaves
     roi = Roi((0.2, 0.2, 0.2), (0.8, 0.8, 0.8), (24, 24, 24), kernel="epanechnikov", bw="fixed",
               h=(0.15, 0.15, 0.15))
+    ctx.set_eval_opts(tile_shape=1)  # wavefront tiles (the default would sweep this ROI)
     _, cnt, _ = ctx.debug_tile_leaves(tree, roi)
     assert np.any((cnt > 64) & (cnt <= 256)), "no tile exercises the slot copy past 64"
     ref = ctx.eval_roi(tree, roi)

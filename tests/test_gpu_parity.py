@@ -599,7 +599,7 @@ def test_serve_binding_budget_and_heavy_requests(ctx, torch):
 # every tile shape, and the autotuner that picks among them
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6, 7])
 def test_every_tile_shape(ctx, torch, shape):
     pts = synth.clumpy_cloud(80_000, 8)
     ctx.set_eval_opts(tile_shape=shape)
@@ -619,7 +619,7 @@ def test_every_tile_shape(ctx, torch, shape):
     ctx.set_eval_opts()
 
 
-def test_autotune(ctx, torch):
+def test_autotune(ctx, torch, sfk):
     pts = synth.clumpy_cloud(200_000, 9)
     tree = ctx.build_tree(dev(torch, pts))
     rois = synth.random_batch_rois(6, seed=2, res_lo=16, res_hi=40)
@@ -629,7 +629,7 @@ def test_autotune(ctx, torch):
     costs = ctx.autotune_costs()
     assert len(table) >= 1 and set(table) == set(costs)
     for key, shape in table.items():
-        assert 1 <= shape <= 6
+        assert 1 <= shape <= sfk.NUM_TILE_SHAPES
         # the pick is the fastest shape measured for that key
         assert costs[key][shape - 1] == min(costs[key]), (key, shape, costs[key])
     # persisted with the device architecture, reloaded into a fresh context
@@ -644,7 +644,7 @@ def test_autotune(ctx, torch):
         assert c2.autotune_table() == table
         # another architecture is refused
         lines = open(path).read().split("\n")
-        lines[0] = "sfkde-autotune 2 gfx000 6"
+        lines[0] = "sfkde-autotune 2 gfx000 %d" % sfk.NUM_TILE_SHAPES
         open(path, "w").write("\n".join(lines))
         with pytest.raises(Exception):
             c2.autotune_load(path)

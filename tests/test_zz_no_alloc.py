@@ -49,6 +49,9 @@ def test_noalloc_matches_eval_roi(ctx, torch, cloud):
         # sparse: 16^3 bricks (scatter evaluation)
         Roi((0.45, 0.45, 0.45), (0.55, 0.55, 0.55), (150, 150, 150), kernel="epanechnikov",
             bw="roi_scaled", h=(0.01,) * 3),
+        # dense (several particles per node): the particle sweep
+        Roi((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (44, 40, 48), kernel="epanechnikov",
+            bw="roi_scaled", h=(0.02,) * 3),
     ]
     for i, roi in enumerate(rois):
         say("noalloc roi", i, roi.res, roi.kernel, roi.bw)
