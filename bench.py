@@ -53,7 +53,7 @@ SLOTS_PER_EVAL = {"gauss_trunc3": 14, "epanechnikov": 9}
 # counter summaries of the evaluation kernel (valid only for the kernel
 # sources whose hash they record)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_gauss_per_point_10m_128_traffic.md")
-SERVED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_epan_served_1b_traffic.md")
+SERVED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_served_1b_traffic.md")
 KERNEL_SOURCES = ("paper_2601_20758_amd/csrc/eval.hip", "paper_2601_20758_amd/csrc/sfk_device.h",
                   "paper_2601_20758_amd/csrc/sfk_internal.h")
 
@@ -137,7 +137,15 @@ def parse():
                    help="skip the nested-zoom and MBE sections on the 100M cloud")
     p.add_argument("--view", action="store_true",
                    help="add the view-cache and adaptive-resolution sections on the 100M cloud")
-    return p.parse_args()
+    p.add_argument("--profile-served", action="store_true",
+                   help="for counter runs: only the timed continuous-batching steps of the "
+                        "served workload (no comparison passes, checks or sub-records), so the "
+                        "evaluation kernels of the run are exactly the timed launches")
+    a = p.parse_args()
+    if a.profile_served:
+        a.no_realtime = a.no_cpu_baseline = a.no_per_point = a.no_batch = a.no_zoom = True
+        a.view = False
+    return a
 
 
 def workload(name):
@@ -603,8 +611,9 @@ def served_headline(ctx, torch, args):
         log("warm-up step", w + 1)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for w in range(W, W + K):
-        serve_window(w, 1)
+    if not args.profile_served:
+        for w in range(W, W + K):
+            serve_window(w, 1)
     torch.cuda.synchronize()
     dt1 = time.perf_counter() - t1
     ctx.profile_enable(True)
@@ -631,7 +640,7 @@ def served_headline(ctx, torch, args):
     ctx.profile_enable(True)
     ctx.profile_read(reset=True)
     t2 = time.perf_counter()
-    for w in range(W, W + K):
+    for w in range(W, W + K) if not args.profile_served else ():
         ids = idx_w[w]
         ctx.serve(tree, np.zeros(len(ids)), [rois[i] for i in ids], [outs[i] for i in ids],
                   mode=0, n_slots=1, max_batch=64, budget_bytes=budget)
@@ -648,12 +657,12 @@ def served_headline(ctx, torch, args):
             "continuous_batching": {"evals_per_s": e_timed / dt, "ms_per_second_of_trace":
                                     dt * 1e3 / K, "batches": batches,
                                     "requests": int(len(timed))},
-            "one_roi_per_launch": {"evals_per_s": e_timed / dt1,
-                                   "ms_per_second_of_trace": dt1 * 1e3 / K},
-            "throughput_ratio": dt1 / dt},
+            "one_roi_per_launch": None if args.profile_served else {
+                "evals_per_s": e_timed / dt1, "ms_per_second_of_trace": dt1 * 1e3 / K},
+            "throughput_ratio": None if args.profile_served else dt1 / dt},
         "phases_ms_per_step_4_streams": {k: prof[k] / K for k in (
             "tile_count_ms", "plan_ms", "tile_fill_ms", "eval_ms")},
-        "one_stream": {
+        "one_stream": None if args.profile_served else {
             "evals_per_s": e_timed / dt2, "ms_per_second_of_trace": dt2 * 1e3 / K,
             "phases_ms_per_step": {k: prof1[k] / K for k in (
                 "tile_count_ms", "plan_ms", "tile_fill_ms", "eval_ms")},
@@ -690,6 +699,8 @@ def served_headline(ctx, torch, args):
     g = np.random.default_rng(12)
     check = sorted(set(int(i) for i in g.choice(len(rois), size=48, replace=False))
                    | set(int(i) for i in np.argsort(-useful)[:8]))
+    if args.profile_served:
+        check = []
     alone = torch.empty(max(r.n_nodes for r in rois), device="cuda")
     same = True
     for i in check:
@@ -700,7 +711,8 @@ def served_headline(ctx, torch, args):
     head = {
         "value": e_timed / dt, "ms_per_step": dt * 1e3 / K, "useful_evals": e_timed,
         "roofline": {"bound": "alu",
-                     "kernel": "evaluation (k_eval tiles and k_splat bricks, Epanechnikov, "
+                     "kernel": "evaluation (k_eval tiles, k_splat bricks, k_sweep particle "
+                               "sweep; Epanechnikov, "
                                "uniform bandwidth)",
                      "achieved": achieved, "peak": peak, "unit": "T VALU-slot/s",
                      "frac": achieved / peak, "traffic": measured_traffic(SERVED_TRAFFIC_FILE),

@@ -990,18 +990,26 @@ __global__ __launch_bounds__(256) void k_eval(
 // Each lane takes one particle of a candidate leaf, computes on each axis the
 // range of brick nodes whose distance can be inside the support (rounded
 // outwards by a relative 1e-9, so the range never misses a member), and
-// visits those nodes only: the canonical u2 = (ux^2 + uy^2) + uz^2 in double
-// decides membership exactly as the definition does, and a member adds its
-// kernel value v in [0, 1] as rint(v * 2^31) units with an LDS atomic. The
+// visits those nodes only. An Epanechnikov term is (1 - (ux^2 + uy^2)) - uz^2
+// in double, counted as floor(v * 2^31 + 1/2) units (0 when v <= 0) with
+// an LDS atomic; the support counts and the truncated Gaussian decide
+// membership by the canonical u2 = (ux^2 + uy^2) + uz^2 < c2 as the
+// definition does (the Gaussian's term is exp(-u2/2) in float). The
 // per-particle cost follows the support (about (2h/s)^3 nodes, twice the
 // members) instead of a whole tile, and integer sums are exact, so the grid
 // is the same whatever the order of particles, chunks or workgroups (alone,
 // in any batch, in any evaluation mode). The brick's chunks add their sums
 // into one 64-bit slot per node with global atomics; the last chunk to
 // finish writes the nodes: sum * 2^-31 * scale, rounded once to float.
-// Per term the fixed point adds at most 2^-32 (in units of the kernel's
-// peak) to a node sum.
+// Per term the fixed point adds about 2^-32 at most (in units of the
+// kernel's peak) to a node sum.
 // ---------------------------------------------------------------------------
+
+// Fixed-point units of a scattered term v in [0, 1]: floor(v * 2^31 + 1/2)
+// with one rounding (a fused multiply-add), 0 for v <= 0.
+__device__ __forceinline__ unsigned int splat_units(double v) {
+  return (unsigned int)fma(fmax(v, 0.0), kSplatUnit, 0.5);
+}
 
 // One wave claims the next work item (XCD-aware slices as in k_eval); -1
 // when every slice is exhausted. `cur` carries the wave's current slice.
@@ -1122,18 +1130,22 @@ __global__ __launch_bounds__(256) void k_splat(
             int ix = a[0] + dx + rx;
             ix = ix > b[0] ? ix - nx : ix;
             const double ux = (lds_c[0][ix] - pp[0]) * ih[0];
-            const double u2 = (ux * ux + sy) + sz;
-            if (u2 < c2) {
-              unsigned int q;
-              if constexpr (CNT) {
-                q = 1u;
-              } else if constexpr (KK == KK_EPAN) {
-                q = (unsigned int)rint((1.0 - u2) * kSplatUnit);
-              } else {
-                const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
-                q = (unsigned int)rint((double)e * kSplatUnit);
+            if constexpr (KK == KK_EPAN && !CNT) {
+              // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2, quantised
+              const unsigned int q = splat_units((1.0 - (ux * ux + sy)) - sz);
+              if (q != 0u) atomicAdd(&sums[row + ((ix + sw) & (B - 1))], (unsigned long long)q);
+            } else {
+              const double u2 = (ux * ux + sy) + sz;
+              if (u2 < c2) {
+                unsigned int q;
+                if constexpr (CNT) {
+                  q = 1u;
+                } else {
+                  const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
+                  q = splat_units((double)e);
+                }
+                atomicAdd(&sums[row + ((ix + sw) & (B - 1))], (unsigned long long)q);
               }
-              atomicAdd(&sums[row + ((ix + sw) & (B - 1))], (unsigned long long)q);
             }
           }
         }
@@ -1234,9 +1246,12 @@ __global__ __launch_bounds__(256) void k_splat(
 // hierarchy's first interior level (64 leaves, 4096 particles, compact in
 // curve order); the workgroup scatters the box's particles into an LDS
 // window of the ROI's nodes that the box's support can reach, with the
-// brick's membership (canonical u2 in double), the brick's fixed-point
-// terms rint(v * 2^31) and LDS atomics, then adds the window's nonzero sums
-// into the batch's 64-bit node sums with global atomics. Integer sums make
+// brick's terms and fixed point (the same operations in the same order)
+// and LDS atomics into private copies of the window (lane l adds to copy
+// l mod ncp), then adds the window's nonzero sums into the batch's 64-bit
+// node sums with global atomics. Per node row the Epanechnikov term takes
+// one subtraction from 1 - (ux^2 + uy^2), with no membership branch.
+// Integer sums make
 // the grid independent of the order of items, particles and workgroups, and
 // equal to the brick's grid bit for bit. Lanes of a wavefront take
 // particles of different leaves of the box, so one instruction's atomics
@@ -1397,11 +1412,19 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                               min(W, w1[2] - bz + 1)};
           const int nxy = nbk[0] * nbk[1];
           const int nn = nxy * nbk[2];
+          // ncp private copies of the window's sums (odd stride, so the
+          // copies of one node fall in different banks): lane l adds to copy
+          // l mod ncp, so lanes whose particles reach the same node seldom
+          // add to the same word
+          int ncp = 16;
+          while (ncp > 1 && ncp * (nn | 1) > W * W * W) ncp >>= 1;
+          const int cs = ncp > 1 ? (nn | 1) : nn;
+          const int my_copy = (lane % ncp) * cs;
           if (tid < 3 * W) {
             const int k = tid / W, i = tid % W;
             if (i < nbk[k]) lds_c[k][i] = node_coord(R, k, blk0[k] + i);
           }
-          for (int i = tid; i < nn; i += 256) sums[i] = 0ull;
+          for (int i = tid; i < ncp * cs; i += 256) sums[i] = 0ull;
           __syncthreads();
           auto splat = [&](const float4 p) {
             const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
@@ -1437,21 +1460,32 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               for (int mx = 0; mx < NM; ++mx) {
                 if (mx < n[0] && my < n[1]) {
                   const double sxy = sx[mx] + sy[my];
-                  const int row = (a[0] + mx) + nbk[0] * (a[1] + my) + nxy * a[2];
+                  const int row = my_copy + (a[0] + mx) + nbk[0] * (a[1] + my) + nxy * a[2];
+                  if constexpr (KK == KK_EPAN && !CNT) {
+                    // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2,
+                    // quantised: no membership test (a non-member's term
+                    // is <= 0 and counts 0)
+                    const double arow = 1.0 - sxy;
 #pragma unroll
-                  for (int mz = 0; mz < NM; ++mz) {
-                    const double u2 = sxy + sz[mz];
-                    if (mz < n[2] && u2 < c2) {
-                      unsigned int q;
-                      if constexpr (CNT) {
-                        q = 1u;
-                      } else if constexpr (KK == KK_EPAN) {
-                        q = (unsigned int)rint((1.0 - u2) * kSplatUnit);
-                      } else {
-                        const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
-                        q = (unsigned int)rint((double)e * kSplatUnit);
+                    for (int mz = 0; mz < NM; ++mz) {
+                      const unsigned int q = splat_units(arow - sz[mz]);
+                      if (mz < n[2] && q != 0u)
+                        atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
+                    }
+                  } else {
+#pragma unroll
+                    for (int mz = 0; mz < NM; ++mz) {
+                      const double u2 = sxy + sz[mz];
+                      if (mz < n[2] && u2 < c2) {
+                        unsigned int q;
+                        if constexpr (CNT) {
+                          q = 1u;
+                        } else {
+                          const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
+                          q = splat_units((double)e);
+                        }
+                        atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
                       }
-                      atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
                     }
                   }
                 }
@@ -1480,7 +1514,8 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
           __syncthreads();
           // the window's nonzero sums into the batch's node sums
           for (int i = tid; i < nn; i += 256) {
-            const unsigned long long v = sums[i];
+            unsigned long long v = 0ull;
+            for (int c = 0; c < ncp; ++c) v += sums[c * cs + i];
             if (v == 0ull) continue;
             const int gi = blk0[0] + i % nbk[0];
             const int gj = blk0[1] + (i / nbk[0]) % nbk[1];

@@ -108,7 +108,7 @@ constexpr int kTileSlotCap = 256;
 struct TileShape { int tx, ty, tz; };
 constexpr int kBrick = 16;
 // Fixed point of the brick's integer node sums: a term v in [0, 1] counts
-// rint(v * 2^31) units (so a sum of up to 2^32 terms fits in 64 bits).
+// floor(v * 2^31 + 1/2) units (so a sum of up to 2^32 terms fits in 64 bits).
 constexpr double kSplatUnit = 2147483648.0;
 // Particle sweep (dense uniform-bandwidth ROIs): work items are boxes of the
 // hierarchy's first interior level (64 leaves), each scattered once into
