@@ -1430,19 +1430,34 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
             const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
             int a[3], n[3];
             bool ok = true;
+            if constexpr (NM == 1) {
+              // a support under half a spacing reaches at most the nearest
+              // node: per axis the node rint(ic), if within the half-width
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              const double ic = (pp[k] - lo[k]) * inv_s[k];
-              const double fa = fmax(ceil(ic - half[k]), (double)blk0[k]);
-              const double fb = fmin(floor(ic + half[k]), (double)(blk0[k] + nbk[k] - 1));
-              ok &= fa <= fb;
-              a[k] = ok ? (int)fa - blk0[k] : 0;
-              n[k] = ok ? (int)(fb - fa) + 1 : 0;
-            }
-            if (!ok) return;
-            if (n[0] > NM || n[1] > NM || n[2] > NM) {
-              bad = true;
-              return;
+              for (int k = 0; k < 3; ++k) {
+                const double ic = (pp[k] - lo[k]) * inv_s[k];
+                const double r = rint(ic);
+                ok &= fabs(ic - r) <= half[k] && r >= (double)blk0[k] &&
+                      r <= (double)(blk0[k] + nbk[k] - 1);
+                a[k] = ok ? (int)r - blk0[k] : 0;
+                n[k] = 1;
+              }
+              if (!ok) return;
+            } else {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                const double ic = (pp[k] - lo[k]) * inv_s[k];
+                const double fa = fmax(ceil(ic - half[k]), (double)blk0[k]);
+                const double fb = fmin(floor(ic + half[k]), (double)(blk0[k] + nbk[k] - 1));
+                ok &= fa <= fb;
+                a[k] = ok ? (int)fa - blk0[k] : 0;
+                n[k] = ok ? (int)(fb - fa) + 1 : 0;
+              }
+              if (!ok) return;
+              if (n[0] > NM || n[1] > NM || n[2] > NM) {
+                bad = true;
+                return;
+              }
             }
             double sx[NM], sy[NM], sz[NM];
 #pragma unroll

@@ -419,6 +419,42 @@ def test_mbe_stagewise(ctx, torch, case):
     assert np.array_equal(again, d["final"].cpu().numpy())
 
 
+@pytest.mark.parametrize("side,res", [(0.03, 64), (0.06, 96)])
+def test_mbe_at_scale_sampled(ctx, torch, side, res):
+    # the MBE chain on a 10M-point cloud, in a box around its most massive
+    # clump (8e4-3e5 particles in B): every stage against the oracle, the
+    # grids on sampled nodes (a full oracle grid would take hours)
+    pts, info = synth.clumpy_cloud(10_000_000, 3, with_info=True)
+    c = info.centres[int(np.argmax(info.counts))]
+    roi = Roi(tuple(c - side / 2), tuple(c + side / 2), (res,) * 3, bw="mbe", set="in_roi")
+    tree = ctx.build_tree(dev(torch, pts))
+    d = ctx.debug_mbe(tree, roi, cap_b=4_000_000)
+    torch.cuda.synchronize()
+    idx_b = np.nonzero(oracle.in_box_mask(pts, roi.lo, roi.hi))[0]
+    say("mbe at scale: N_B =", len(idx_b))
+    assert d["n_b"] == len(idx_b) > 50_000 and np.array_equal(d["idx_b"], idx_b)
+    pts_b = pts[idx_b]
+    ell0, _ = oracle.mbe_initial_ell(pts_b, roi)
+    assert np.array_equal(d["ell0"], ell0)  # Eq. 1, bit-exact
+    scale = oracle.kernel_ck("epanechnikov") * oracle._nu(roi, len(idx_b))
+    ih, w = oracle.uniform_params(ell0)
+    pilot = d["pilot"].astype(np.float64)
+    nodes = sample_nodes(None, roi.n_nodes, 64, 7, extra=[int(np.argmax(pilot))])
+    want = oracle.density_raw(pts_b, roi, "epanechnikov", scale, ih_u=ih, w_u=w, nodes=nodes)
+    check_sampled(pilot, nodes, want, "pilot at scale")
+    # Eqs. 5-6 given the GPU pilot, every particle of B
+    pden, ave, ell_j = oracle.mbe_asl(pts_b, roi, pilot, ell0)
+    np.testing.assert_allclose(d["pden"], pden, rtol=1e-6, atol=1e-12 * max(pden.max(), 1e-30))
+    assert d["aveden"] == pytest.approx(ave, rel=1e-6)
+    np.testing.assert_allclose(d["ell_j"], ell_j, rtol=1e-6)
+    # Eq. 7 given the GPU's adaptive lengths, on sampled nodes
+    final = d["final"].cpu().numpy()
+    nodes = sample_nodes(None, roi.n_nodes, 64, 8, extra=[int(np.argmax(final))])
+    ref = oracle.mbe(pts, roi, nodes=nodes, pilot_in=pilot, ell_j_in=d["ell_j"])["final"]
+    check_sampled(final, nodes, ref, "final at scale")
+    tree.close()
+
+
 # ---------------------------------------------------------------------------
 # batches: each grid is the same alone and in the mix
 # ---------------------------------------------------------------------------
