@@ -1352,6 +1352,8 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
   __shared__ unsigned long long sums[W * W * W];
   __shared__ double lds_c[3][W];
   __shared__ int64_t lds_item;
+  __shared__ int32_t lds_surv[SFK_FANOUT];
+  __shared__ int32_t lds_nsurv;
   const int lane = lane_id();
   const int tid = threadIdx.x;
   const int64_t n_items = min((int64_t)hdr->n_items, hdr->item_cap);
@@ -1400,10 +1402,6 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
     if (empty) continue;
     const double c2 = (double)R.c2;
     const float4* pts = tv.pts + (int64_t)l0 * SFK_LEAF;
-    // thread tid takes particles q = tid + 256 i of the box in the order
-    // "leaf q mod nl, slot q / nl": the lanes of a wavefront read 64
-    // different leaves
-    const int step_slot = 256 / nl, step_leaf = 256 % nl;
     for (int bz = w0[2]; bz <= w1[2]; bz += W)
       for (int by = w0[1]; by <= w1[1]; by += W)
         for (int bx = w0[0]; bx <= w1[0]; bx += W) {
@@ -1425,7 +1423,28 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
             if (i < nbk[k]) lds_c[k][i] = node_coord(R, k, blk0[k] + i);
           }
           for (int i = tid; i < ncp * cs; i += 256) sums[i] = 0ull;
+          // the box's leaves whose box can reach the block (a particle's node
+          // range lies inside its leaf's, so the others add nothing here)
+          if (tid < 64) {
+            bool reach = false;
+            if (lane < nl) {
+              const NodeBox lb = tv.nodes[tv.level_off[0] + l0 + lane];
+              reach = lb.count > 0;
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                const double fa = fmax(ceil(((double)lb.lo[k] - lo[k]) * inv_s[k] - half[k]),
+                                       (double)blk0[k]);
+                const double fb = fmin(floor(((double)lb.hi[k] - lo[k]) * inv_s[k] + half[k]),
+                                       (double)(blk0[k] + nbk[k] - 1));
+                reach &= fa <= fb;
+              }
+            }
+            const uint64_t m = ballot(reach);
+            if (reach) lds_surv[popc64(m & lanemask_lt())] = lane;
+            if (lane == 0) lds_nsurv = popc64(m);
+          }
           __syncthreads();
+          const int ns = lds_nsurv;
           auto splat = [&](const float4 p) {
             const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
             int a[3], n[3];
@@ -1507,23 +1526,31 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               }
             }
           };
-          int leaf = tid % nl, slot = tid / nl;
-          if (slot < SFK_LEAF) {
-            float4 p = pts[(int64_t)leaf * SFK_LEAF + slot];
-            while (true) {
-              int nleaf = leaf + step_leaf, nslot = slot + step_slot;
-              if (nleaf >= nl) {
-                nleaf -= nl;
-                ++nslot;
+          // thread tid takes particles q = tid + 256 i of the surviving
+          // leaves in the order "leaf q mod ns, slot q / ns": the lanes of a
+          // wavefront read different leaves
+          if (ns > 0) {
+            const int step_slot = 256 / ns, step_leaf = 256 % ns;
+            const bool all = ns == nl;  // every leaf reaches: no indirection
+            auto leaf_id = [&](int q) { return all ? q : lds_surv[q]; };
+            int leaf = tid % ns, slot = tid / ns;
+            if (slot < SFK_LEAF) {
+              float4 p = pts[(int64_t)leaf_id(leaf) * SFK_LEAF + slot];
+              while (true) {
+                int nleaf = leaf + step_leaf, nslot = slot + step_slot;
+                if (nleaf >= ns) {
+                  nleaf -= ns;
+                  ++nslot;
+                }
+                const bool more = nslot < SFK_LEAF;
+                float4 pn = p;
+                if (more) pn = pts[(int64_t)leaf_id(nleaf) * SFK_LEAF + nslot];
+                splat(p);
+                if (!more) break;
+                p = pn;
+                leaf = nleaf;
+                slot = nslot;
               }
-              const bool more = nslot < SFK_LEAF;
-              float4 pn = p;
-              if (more) pn = pts[(int64_t)nleaf * SFK_LEAF + nslot];
-              splat(p);
-              if (!more) break;
-              p = pn;
-              leaf = nleaf;
-              slot = nslot;
             }
           }
           __syncthreads();

@@ -95,3 +95,24 @@ def test_noalloc_rejections(ctx, torch, cloud, sfk):
     assert L.lib().sfk_eval_roi_noalloc(ctx._h, None, C.byref(r), None) == 1
     assert L.NOALLOC_SCRATCH_BYTES == 64 << 20
     tree.close()
+
+
+def test_noalloc_sweep_too_large_takes_the_default_without_it(ctx, torch, cloud):
+    # a ROI forced to the particle sweep whose 8^3-node sums (8 B a node)
+    # do not fit the array: the entry point takes the shape the ROI would
+    # take without the sweep (here sparse: bricks), which sum the same
+    # integer terms, so the grid still equals the sweep's bit for bit
+    tree = ctx.build_tree(dev(torch, cloud))
+    roi = Roi((0, 0, 0), (1, 1, 1), (216, 208, 200), kernel="epanechnikov", bw="fixed",
+              h=(0.006,) * 3)
+    ctx.set_eval_opts(tile_shape=7)
+    a = torch.full((roi.n_nodes,), -1.0, device="cuda")
+    ctx.eval_roi_noalloc(tree, roi, a)
+    b = ctx.eval_roi(tree, roi)
+    torch.cuda.synchronize()
+    ctx.set_eval_opts()
+    got, ref = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(got, ref)
+    nodes = sample_nodes(None, roi.n_nodes, 48, 21, extra=[int(np.argmax(got))])
+    check_sampled(got, nodes, oracle.density(cloud, roi, nodes=nodes), "noalloc sweep fallback")
+    tree.close()
