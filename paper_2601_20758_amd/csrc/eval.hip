@@ -1350,7 +1350,10 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
   constexpr int W = kSweepWin;
   constexpr int S = kSweep;
   __shared__ unsigned long long sums[W * W * W];
-  __shared__ double lds_c[3][W];
+  // node coordinates of a block, with kSweepMaxNM more past its end so the
+  // unrolled per-particle loops read them without clamping
+  constexpr int WC = W + kSweepMaxNM;
+  __shared__ double lds_c[3][WC];
   __shared__ int64_t lds_item;
   __shared__ int32_t lds_surv[SFK_FANOUT];
   __shared__ int32_t lds_nsurv;
@@ -1418,9 +1421,9 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
           while (ncp > 1 && ncp * (nn | 1) > W * W * W) ncp >>= 1;
           const int cs = ncp > 1 ? (nn | 1) : nn;
           const int my_copy = (lane % ncp) * cs;
-          if (tid < 3 * W) {
-            const int k = tid / W, i = tid % W;
-            if (i < nbk[k]) lds_c[k][i] = node_coord(R, k, blk0[k] + i);
+          if (tid < 3 * WC) {
+            const int k = tid / WC, i = tid % WC;
+            lds_c[k][i] = node_coord(R, k, blk0[k] + i);
           }
           for (int i = tid; i < ncp * cs; i += 256) sums[i] = 0ull;
           // the box's leaves whose box can reach the block (a particle's node
@@ -1478,12 +1481,15 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                 return;
               }
             }
+            // the particle's first node in this lane's copy of the window;
+            // a node (mx, my, mz) past it is base + mx + nbk0 my + nxy mz
+            const int base = my_copy + a[0] + nbk[0] * a[1] + nxy * a[2];
             double sx[NM], sy[NM], sz[NM];
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-              const double ux = (lds_c[0][min(a[0] + m, nbk[0] - 1)] - pp[0]) * ih[0];
-              const double uy = (lds_c[1][min(a[1] + m, nbk[1] - 1)] - pp[1]) * ih[1];
-              const double uz = (lds_c[2][min(a[2] + m, nbk[2] - 1)] - pp[2]) * ih[2];
+              const double ux = (lds_c[0][a[0] + m] - pp[0]) * ih[0];
+              const double uy = (lds_c[1][a[1] + m] - pp[1]) * ih[1];
+              const double uz = (lds_c[2][a[2] + m] - pp[2]) * ih[2];
               sx[m] = ux * ux;
               sy[m] = uy * uy;
               sz[m] = uz * uz;
@@ -1494,7 +1500,7 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               for (int mx = 0; mx < NM; ++mx) {
                 if (mx < n[0] && my < n[1]) {
                   const double sxy = sx[mx] + sy[my];
-                  const int row = my_copy + (a[0] + mx) + nbk[0] * (a[1] + my) + nxy * a[2];
+                  const int row = base + mx + nbk[0] * my;
                   if constexpr (KK == KK_EPAN && !CNT) {
                     // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2,
                     // quantised: no membership test (a non-member's term
