@@ -838,7 +838,7 @@ def main():
     ctx = sfk.Context(0)
     result = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
-              "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+              "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
     if args.workload == "served_1b":
         head, sub = served_headline(ctx, torch, args)
         result.update({"value": head["value"], "ms_per_step": head["ms_per_step"],

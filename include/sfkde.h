@@ -304,14 +304,17 @@ typedef struct {
   int32_t max_batch;     /* ROIs per batch, >= 1 */
   int32_t interleave;    /* 0: persistent evaluation grids, as sfk_submit uses; 1: grids of
                             one wavefront per tile, whose workgroups retire as they finish
-                            so the kernels of requests on other streams interleave */
+                            so the kernels of requests on other streams interleave (tiles
+                            and bricks; the particle sweep keeps its persistent grid) */
   double budget_bytes;   /* workspace + grid bytes admitted at once (0 = context budget) */
   double max_batch_work; /* continuous batching: a batch closes before the request that
                             would take its estimated useful pairs past this (a request
-                            above it runs alone, so light requests never wait for a heavy
-                            one's completion); 0 = 2e8, < 0 = no limit. The estimate is
-                            the particles the tree's coarse boxes put in the request's box
-                            (widened by the support) times the nodes one support covers */
+                            above it runs in a batch of its own, so light requests are not
+                            held until a heavy batch-mate completes; they may still wait
+                            for the CUs its kernel holds); 0 = 2e8, < 0 = no limit. The
+                            estimate is the particles the tree's coarse boxes put in the
+                            request's box (widened by the support) times the nodes one
+                            support covers */
 } sfk_serve_opts;
 
 typedef struct {

@@ -104,3 +104,12 @@ def test_marching_cubes_table_matches_oracle(lib):
         got = np.array(buf[:3 * n.value], dtype=np.int32).reshape(-1, 3)
         assert np.array_equal(got, oracle.mc_case(cs)), cs
     assert lib.sfk_debug_mc_case(256, buf, C.byref(n)) == 1
+
+
+def test_header_constants_match_the_binding():
+    text = open(HEADER).read()
+    from paper_2601_20758_amd import _lib
+    m = re.search(r"#define SFK_NUM_TILE_SHAPES (\d+)", text)
+    assert m and int(m.group(1)) == _lib.NUM_TILE_SHAPES
+    m = re.search(r"#define SFK_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and (int(m.group(1)) << int(m.group(2))) == _lib.NOALLOC_SCRATCH_BYTES

@@ -168,3 +168,27 @@ def test_sweep_default_batch_and_graph_bitwise(ctx, torch):
     for o, a in zip(outs, alone + [pp_alone]):
         assert np.array_equal(o.cpu().numpy(), a)
     tree.close()
+
+
+@pytest.mark.parametrize("shape", [7, 6, 1])
+def test_sub_roi_window_consistency(ctx, torch, shape):
+    # a sub-box whose nodes coincide with the full box's (dyadic spacing
+    # 1/64 on both) has the full grid's values there: bit for bit where the
+    # terms are summed as integers (sweep, bricks), within the bar for tiles
+    pts = synth.clumpy_cloud(300_000, 9)
+    tree = ctx.build_tree(dev(torch, pts))
+    full = Roi((0, 0, 0), (1, 1, 1), (65, 65, 65), kernel="epanechnikov", bw="fixed",
+               h=(0.03, 0.03, 0.03))
+    sub = Roi((0.25, 0.125, 0.5), (0.75, 0.5, 1.0), (33, 25, 33), kernel="epanechnikov",
+              bw="fixed", h=(0.03, 0.03, 0.03))
+    ctx.set_eval_opts(tile_shape=shape)
+    g_full = ctx.eval_roi(tree, full).cpu().numpy().reshape(65, 65, 65)  # z, y, x
+    g_sub = ctx.eval_roi(tree, sub).cpu().numpy().reshape(33, 25, 33)
+    torch.cuda.synchronize()
+    ctx.set_eval_opts()
+    window = g_full[32:65, 8:33, 16:49]
+    if shape in (6, 7):
+        assert np.array_equal(g_sub, window)
+    else:
+        check_density(g_sub.ravel(), window.ravel().astype(np.float64), "sub-ROI window")
+    tree.close()
