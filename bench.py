@@ -139,8 +139,9 @@ def parse():
                    help="add the view-cache and adaptive-resolution sections on the 100M cloud")
     p.add_argument("--profile-served", action="store_true",
                    help="for counter runs: only the timed continuous-batching steps of the "
-                        "served workload (no comparison passes, checks or sub-records), so the "
-                        "evaluation kernels of the run are exactly the timed launches")
+                        "served workload (the same trace windows; no warm-up, comparison "
+                        "passes, checks or sub-records), so the evaluation kernels of the run "
+                        "are exactly the timed launches")
     a = p.parse_args()
     if a.profile_served:
         a.no_realtime = a.no_cpu_baseline = a.no_per_point = a.no_batch = a.no_zoom = True
@@ -607,6 +608,8 @@ def served_headline(ctx, torch, args):
     # (an untimed comparison at saturation), then the timed region:
     # continuous batching at saturation
     for w in range(W):
+        if args.profile_served:
+            break  # counter runs: only the timed windows (the same seconds of the trace)
         serve_window(w, 0)
         log("warm-up step", w + 1)
     torch.cuda.synchronize()

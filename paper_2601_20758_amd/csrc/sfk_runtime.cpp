@@ -210,6 +210,10 @@ struct sfk_tree_s {
   std::vector<NodeBox> host_nodes;
   int32_t host_level = 0;   // finest level held on the host
   int32_t host_base = 0;    // device node index of host_nodes[0]
+  // summed counts of the finest host level's boxes, each counted in the cell
+  // of a kEstGrid^3 lattice over the bounding box that holds its centre:
+  // est_sat[(i + (G+1) (j + (G+1) k))] = the count in cells below (i, j, k)
+  std::vector<double> est_sat;
   int32_t pp_mode = PP_UNIFORM;  // PP_ISO when a per-point bandwidth exists
   int32_t knn_k = 0;
   size_t bytes = 0;
@@ -946,6 +950,10 @@ void group_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois, 
 // to the batch. Every group's buffers are reserved before the first launch:
 // the groups run one after another on the same workspace, and growing a
 // buffer frees the old one.
+sfk_status enqueue_groups(sfk_ctx c, sfk_tree t, std::vector<std::vector<GroupRoi>>& groups,
+                          std::vector<GroupKey>& keys, bool count_mode, Workspace& ws,
+                          Staging& st, hipStream_t s);
+
 sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk_roi*>& rois,
                               bool count_mode, Workspace& ws, Staging& st, hipStream_t s,
                               const TileShape* force_ts = nullptr) {
@@ -953,6 +961,14 @@ sfk_status enqueue_cloud_rois(sfk_ctx c, sfk_tree t, const std::vector<const sfk
   std::vector<std::vector<GroupRoi>> groups;
   std::vector<GroupKey> keys;
   group_rois(c, t, rois, count_mode, &groups, &keys, force_ts);
+  return enqueue_groups(c, t, groups, keys, count_mode, ws, st, s);
+}
+
+// Enqueue groups formed by group_rois (one pipeline per group, direct
+// launches, every group's buffers reserved before the first launch).
+sfk_status enqueue_groups(sfk_ctx c, sfk_tree t, std::vector<std::vector<GroupRoi>>& groups,
+                          std::vector<GroupKey>& keys, bool count_mode, Workspace& ws,
+                          Staging& st, hipStream_t s) {
   size_t bytes = 0;
   for (auto& g : groups) bytes += sizeof(BatchHdr) + sizeof(RoiDev) * g.size();
   SFK_TRY(staging_reserve(c, st, bytes));
@@ -1001,7 +1017,7 @@ sfk_status enqueue_cloud_rois_graph(sfk_ctx c, sfk_tree t,
   std::vector<std::vector<GroupRoi>> groups;
   std::vector<GroupKey> keys;
   group_rois(c, t, rois, false, &groups, &keys);
-  if (groups.size() != 1) return enqueue_cloud_rois(c, t, rois, false, sl.ws, sl.st, sl.stream);
+  if (groups.size() != 1) return enqueue_groups(c, t, groups, keys, false, sl.ws, sl.st, sl.stream);
   const int64_t n = (int64_t)groups[0].size();
   const TileShape ts = keys[0].ts;
   const int kk = keys[0].kk, pp = keys[0].pp, ch = chunk_leaves_of(c), nm = keys[0].nm;
@@ -1409,37 +1425,98 @@ sfk_status eval_subcloud(sfk_ctx c, sfk_tree t, const sfk_roi* r, bool count_mod
   return SFK_OK;
 }
 
-// Particles of the tree in the closed box [lo, hi], estimated from the box
-// levels held on the host: a box inside counts whole, a disjoint box not at
-// all, a box that straddles the border is split into its children, down to
-// the finest host level, where it counts in proportion to the overlap of
-// its extent (a flat extent counts whole when it lies inside).
-double est_node(const sfk_tree_s* t, int level, int idx, const double* lo, const double* hi) {
-  const NodeBox& b = t->host_nodes[(size_t)(t->level_off[level] - t->host_base + idx)];
-  if (b.count <= 0) return 0.0;
-  bool inside = true;
-  double frac = 1.0;
-  for (int k = 0; k < 3; ++k) {
-    const double bl = b.lo[k], bh = b.hi[k];
-    if (bh < lo[k] || bl > hi[k]) return 0.0;
-    if (bl < lo[k] || bh > hi[k]) inside = false;
-    const double ext = bh - bl;
-    if (ext > 0.0) frac *= (std::min(bh, hi[k]) - std::max(bl, lo[k])) / ext;
+constexpr int kEstGrid = 32;  // cells per axis of the particle-count table
+
+// The count table of a tree: the finest host level's box counts spread over
+// a kEstGrid^3 lattice of cells on the bounding box, each box's count shared
+// among the cells it overlaps in proportion to the overlap (a flat box axis
+// goes whole to its cell), then summed into a summed-volume table. Boxes of
+// one level partition the particles, so the spreading touches about
+// kEstGrid^3 cells plus the boxes' boundary cells.
+void build_est_table(sfk_tree_s* t) {
+  constexpr int G = kEstGrid, G1 = kEstGrid + 1;
+  t->est_sat.assign((size_t)G1 * G1 * G1, 0.0);
+  if (t->n_levels <= 0 || t->host_nodes.empty()) return;
+  std::vector<double> h((size_t)G * G * G, 0.0);
+  const int lvl = t->host_level;
+  std::vector<double> w[3];
+  int c0[3];
+  for (int i = 0; i < t->level_cnt[lvl]; ++i) {
+    const NodeBox& b = t->host_nodes[(size_t)(t->level_off[lvl] - t->host_base + i)];
+    if (b.count <= 0) continue;
+    for (int k = 0; k < 3; ++k) {
+      const double ext = t->bbox[3 + k] - t->bbox[k];
+      const double u0 = ext > 0.0 ? ((double)b.lo[k] - t->bbox[k]) / ext * G : 0.0;
+      const double u1 = ext > 0.0 ? ((double)b.hi[k] - t->bbox[k]) / ext * G : 0.0;
+      const double a0 = std::min<double>(G, std::max(0.0, u0));
+      const double a1 = std::min<double>(G, std::max(a0, u1));
+      const int i0 = std::min(G - 1, (int)a0), i1 = std::min(G - 1, std::max(i0, (int)a1));
+      c0[k] = i0;
+      w[k].assign((size_t)(i1 - i0 + 1), 0.0);
+      if (a1 - a0 <= 0.0) {
+        w[k][0] = 1.0;
+        continue;
+      }
+      for (int c = i0; c <= i1; ++c)
+        w[k][(size_t)(c - i0)] =
+            (std::min<double>(a1, c + 1) - std::max<double>(a0, c)) / (a1 - a0);
+    }
+    const double n = (double)b.count;
+    for (size_t z = 0; z < w[2].size(); ++z)
+      for (size_t y = 0; y < w[1].size(); ++y) {
+        const double wyz = n * w[1][y] * w[2][z];
+        double* row = &h[(size_t)c0[0] + G * ((size_t)(c0[1] + y) + G * (size_t)(c0[2] + z))];
+        for (size_t x = 0; x < w[0].size(); ++x) row[x] += wyz * w[0][x];
+      }
   }
-  if (inside) return (double)b.count;
-  if (level == t->host_level) return (double)b.count * frac;
-  double sum = 0.0;
-  const int c0 = b.first, c1 = std::min(c0 + SFK_FANOUT, t->level_cnt[level - 1]);
-  for (int ch = c0; ch < c1; ++ch) sum += est_node(t, level - 1, ch, lo, hi);
-  return sum;
+  auto S = [&](int i, int j, int k) -> double& {
+    return t->est_sat[(size_t)i + G1 * ((size_t)j + G1 * (size_t)k)];
+  };
+  for (int k = 1; k <= G; ++k)
+    for (int j = 1; j <= G; ++j)
+      for (int i = 1; i <= G; ++i)
+        S(i, j, k) = h[(size_t)(i - 1) + G * ((size_t)(j - 1) + G * (size_t)(k - 1))] +
+                     S(i - 1, j, k) + S(i, j - 1, k) + S(i, j, k - 1) - S(i - 1, j - 1, k) -
+                     S(i - 1, j, k - 1) - S(i, j - 1, k - 1) + S(i - 1, j - 1, k - 1);
 }
 
+// Particles of the tree in the closed box [lo, hi], estimated in O(1) from
+// the count table: counts spread evenly over their cells, so the count below
+// a point is the table interpolated multilinearly, and a box's count is the
+// eight-corner difference. A flat axis of the bounding box counts whole when
+// [lo, hi] holds it. The estimate feeds log2 buckets (the tile shape's key)
+// and the serving loop's work estimate.
 double est_particles(const sfk_tree_s* t, const double* lo, const double* hi) {
-  if (t->n_levels <= 0 || t->host_nodes.empty()) return 0.0;
-  const int top = t->n_levels - 1;
-  double sum = 0.0;
-  for (int i = 0; i < t->level_cnt[top]; ++i) sum += est_node(t, top, i, lo, hi);
-  return sum;
+  if (t->est_sat.empty()) return 0.0;
+  constexpr int G = kEstGrid, G1 = kEstGrid + 1;
+  double a[3], b[3];
+  for (int k = 0; k < 3; ++k) {
+    const double ext = t->bbox[3 + k] - t->bbox[k];
+    if (ext > 0.0) {
+      a[k] = std::min<double>(G, std::max(0.0, (lo[k] - t->bbox[k]) / ext * G));
+      b[k] = std::min<double>(G, std::max(0.0, (hi[k] - t->bbox[k]) / ext * G));
+    } else {
+      const bool in = lo[k] <= t->bbox[k] && t->bbox[k] <= hi[k];
+      a[k] = 0.0;
+      b[k] = in ? G : 0.0;
+    }
+    if (!(b[k] > a[k])) return 0.0;
+  }
+  auto F = [&](double x, double y, double z) {
+    const int i = std::min(G - 1, (int)x), j = std::min(G - 1, (int)y), k = std::min(G - 1, (int)z);
+    const double fx = x - i, fy = y - j, fz = z - k;
+    double v = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+          v += (dx ? fx : 1.0 - fx) * (dy ? fy : 1.0 - fy) * (dz ? fz : 1.0 - fz) *
+               t->est_sat[(size_t)(i + dx) + G1 * ((size_t)(j + dy) + G1 * (size_t)(k + dz))];
+    return v;
+  };
+  const double c = F(b[0], b[1], b[2]) - F(a[0], b[1], b[2]) - F(b[0], a[1], b[2]) -
+                   F(b[0], b[1], a[2]) + F(a[0], a[1], b[2]) + F(a[0], b[1], a[2]) +
+                   F(b[0], a[1], a[2]) - F(a[0], a[1], a[2]);
+  return std::max(0.0, c);
 }
 
 // Estimated particles per grid node of a ROI: the particles in its box
@@ -2013,6 +2090,7 @@ sfk_status sfk_build_tree(sfk_ctx c, const float* d_xyz, int64_t n, const float*
   if (bb[6] > 0.0f)
     return fail((set_err(c, "%.0f non-finite coordinates", (double)bb[6]), SFK_E_INVAL));
   for (int k = 0; k < 6; ++k) t->bbox[k] = bb[k];
+  build_est_table(t);
   if (c->prof_on) ++c->prof_builds;
   *out = t;
   return SFK_OK;
