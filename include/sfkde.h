@@ -227,7 +227,7 @@ typedef struct {
                             7 = particle sweep (a workgroup per box of 4096 particles
                             scattering them once into the same integer node sums, so
                             its grids equal the bricks' bit for bit; uniform bandwidths
-                            whose support spans at most 5 nodes per axis, others take
+                            whose support spans at most 8 nodes per axis, others take
                             the default of their key without the sweep) */
   int32_t chunk_leaves;  /* leaves per work item (heavy tiles are split), 0 = 256 */
   int32_t persistent_waves_per_cu; /* 0 = automatic */

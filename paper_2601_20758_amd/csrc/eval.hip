@@ -1260,6 +1260,10 @@ __global__ __launch_bounds__(256) void k_splat(
 // blocks of kSweepWin^3 nodes, each reading the box's particles again.
 // ---------------------------------------------------------------------------
 
+// A squared offset past any support (c^2 <= 9): the sweep gives the nodes
+// past a particle's z range this value, so their terms are 0.
+constexpr double kSweepFar = 1e300;
+
 // Level of the hierarchy whose boxes are the sweep's work items: the first
 // interior level (64 leaves a box) when the tree has one, else the leaves.
 __device__ __forceinline__ int sweep_level(const TreeView& tv) { return tv.n_levels >= 2 ? 1 : 0; }
@@ -1349,7 +1353,10 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                                                int32_t* __restrict__ claims) {
   constexpr int W = kSweepWin;
   constexpr int S = kSweep;
-  __shared__ unsigned long long sums[W * W * W];
+  // the window's node sums, z fastest, with an odd x stride (W^2 + 1 at
+  // most) so that threads reading consecutive x fall in different banks
+  constexpr int WN = W * (W * W + 1);
+  __shared__ unsigned long long sums[WN];
   // node coordinates of a block, with kSweepMaxNM more past its end so the
   // unrolled per-particle loops read them without clamping
   constexpr int WC = W + kSweepMaxNM;
@@ -1411,15 +1418,14 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
           const int blk0[3] = {bx, by, bz};
           const int nbk[3] = {min(W, w1[0] - bx + 1), min(W, w1[1] - by + 1),
                               min(W, w1[2] - bz + 1)};
-          const int nxy = nbk[0] * nbk[1];
-          const int nn = nxy * nbk[2];
+          const int nyz = (nbk[1] * nbk[2]) | 1, nw = nbk[0] * nyz;
           // ncp private copies of the window's sums (odd stride, so the
           // copies of one node fall in different banks): lane l adds to copy
           // l mod ncp, so lanes whose particles reach the same node seldom
           // add to the same word
           int ncp = 16;
-          while (ncp > 1 && ncp * (nn | 1) > W * W * W) ncp >>= 1;
-          const int cs = ncp > 1 ? (nn | 1) : nn;
+          while (ncp > 1 && ncp * (nw | 1) > WN) ncp >>= 1;
+          const int cs = ncp > 1 ? (nw | 1) : nw;
           const int my_copy = (lane % ncp) * cs;
           if (tid < 3 * WC) {
             const int k = tid / WC, i = tid % WC;
@@ -1481,9 +1487,11 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                 return;
               }
             }
-            // the particle's first node in this lane's copy of the window;
-            // a node (mx, my, mz) past it is base + mx + nbk0 my + nxy mz
-            const int base = my_copy + a[0] + nbk[0] * a[1] + nxy * a[2];
+            // the particle's first node in this lane's copy of the window
+            // (stored z fastest, x stride nyz); a node (mx, my, mz) past it
+            // is base + mz + nbk2 my + nyz mx, so a row's adds differ only
+            // in the immediate offset
+            const int base = my_copy + a[2] + nbk[2] * a[1] + nyz * a[0];
             double sx[NM], sy[NM], sz[NM];
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
@@ -1492,7 +1500,9 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               const double uz = (lds_c[2][a[2] + m] - pp[2]) * ih[2];
               sx[m] = ux * ux;
               sy[m] = uy * uy;
-              sz[m] = uz * uz;
+              // past the particle's z range a huge square makes every term
+              // 0 (no add), so the inner loop needs no range test
+              sz[m] = m < n[2] ? uz * uz : kSweepFar;
             }
 #pragma unroll
             for (int my = 0; my < NM; ++my) {
@@ -1500,7 +1510,7 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               for (int mx = 0; mx < NM; ++mx) {
                 if (mx < n[0] && my < n[1]) {
                   const double sxy = sx[mx] + sy[my];
-                  const int row = base + mx + nbk[0] * my;
+                  const int row = base + nbk[2] * my + nyz * mx;
                   if constexpr (KK == KK_EPAN && !CNT) {
                     // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2,
                     // quantised: no membership test (a non-member's term
@@ -1509,14 +1519,13 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
 #pragma unroll
                     for (int mz = 0; mz < NM; ++mz) {
                       const unsigned int q = splat_units(arow - sz[mz]);
-                      if (mz < n[2] && q != 0u)
-                        atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
+                      if (q != 0u) atomicAdd(&sums[row + mz], (unsigned long long)q);
                     }
                   } else {
 #pragma unroll
                     for (int mz = 0; mz < NM; ++mz) {
                       const double u2 = sxy + sz[mz];
-                      if (mz < n[2] && u2 < c2) {
+                      if (u2 < c2) {
                         unsigned int q;
                         if constexpr (CNT) {
                           q = 1u;
@@ -1524,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                           const float e = __builtin_amdgcn_exp2f((float)(SFK_KG64S * u2));
                           q = splat_units((double)e);
                         }
-                        atomicAdd(&sums[row + nxy * mz], (unsigned long long)q);
+                        atomicAdd(&sums[row + mz], (unsigned long long)q);
                       }
                     }
                   }
@@ -1560,17 +1569,34 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
             }
           }
           __syncthreads();
-          // the window's nonzero sums into the batch's node sums
-          for (int i = tid; i < nn; i += 256) {
-            unsigned long long v = 0ull;
-            for (int c = 0; c < ncp; ++c) v += sums[c * cs + i];
-            if (v == 0ull) continue;
-            const int gi = blk0[0] + i % nbk[0];
-            const int gj = blk0[1] + (i / nbk[0]) % nbk[1];
-            const int gk = blk0[2] + i / nxy;
-            const int64_t t = R.tile_base + (gi / S) +
-                              (int64_t)R.ntile[0] * ((gj / S) + (int64_t)R.ntile[1] * (gk / S));
-            atomicAdd(&acc[t * (S * S * S) + (gi % S) + S * ((gj % S) + S * (gk % S))], v);
+          // the window's nonzero sums into the batch's node sums: thread t
+          // takes x = t mod W of the x rows t / W, t / W + 256 / W, ...
+          // (consecutive threads add to consecutive nodes; the row's (y, z)
+          // advances without divisions)
+          if ((tid & (W - 1)) < nbk[0]) {
+            constexpr int RS = 256 / W;
+            const int li = tid & (W - 1);
+            int lj = tid / W, lk = 0;
+            while (lj >= nbk[1]) {
+              lj -= nbk[1];
+              ++lk;
+            }
+            while (lk < nbk[2]) {
+              const int w = lk + nbk[2] * lj + nyz * li;
+              unsigned long long v = 0ull;
+              for (int c = 0; c < ncp; ++c) v += sums[c * cs + w];
+              if (v != 0ull) {
+                const int gi = blk0[0] + li, gj = blk0[1] + lj, gk = blk0[2] + lk;
+                const int64_t t = R.tile_base + (gi / S) +
+                                  (int64_t)R.ntile[0] * ((gj / S) + (int64_t)R.ntile[1] * (gk / S));
+                atomicAdd(&acc[t * (S * S * S) + (gi % S) + S * ((gj % S) + S * (gk % S))], v);
+              }
+              lj += RS;
+              while (lj >= nbk[1]) {
+                lj -= nbk[1];
+                ++lk;
+              }
+            }
           }
           __syncthreads();
         }
@@ -1720,7 +1746,10 @@ hipError_t launch_sweep_eval(TreeView tv, const BatchHdr* hdr, const RoiDev* roi
     case 2: SFK_W(KK, C, 2); break; \
     case 3: SFK_W(KK, C, 3); break; \
     case 4: SFK_W(KK, C, 4); break; \
-    default: SFK_W(KK, C, 5); break; \
+    case 5: SFK_W(KK, C, 5); break; \
+    case 6: SFK_W(KK, C, 6); break; \
+    case 7: SFK_W(KK, C, 7); break; \
+    default: SFK_W(KK, C, 8); break; \
   }
   if (cnt) {
     SFK_W_NM(KK_EPAN, true);

@@ -118,7 +118,7 @@ constexpr double kSplatUnit = 2147483648.0;
 // most kSweepMaxNM nodes per axis.
 constexpr int kSweep = 8;
 constexpr int kSweepWin = 16;
-constexpr int kSweepMaxNM = 5;
+constexpr int kSweepMaxNM = 8;
 
 // ---- host-side launch wrappers (defined in the .hip files) ----
 namespace sfk {

@@ -1567,15 +1567,21 @@ int default_shape(int key, double particles_per_support, bool sweep_ok) {
   // bricks: a tile's fixed costs (claim, range query, reduction) would
   // dominate its few pairs (measured: a 256^3 box of side 1/64 around a
   // clump of a 100M cloud, 0.27 ms in bricks vs 1.40 ms in 4x4x4 tiles)
-  const int dens = key & 7, kb = (key >> 6) & 3;
+  const int dens = key & 7, kb = (key >> 6) & 3, hs_bucket = (key >> 3) & 7;
   const bool uniform = kb == SFK_BW_FIXED || kb == SFK_BW_ROI_SCALED;
-  if (uniform && dens < 4) return kBrickShape;
   // dense uniform-bandwidth ROIs (1 or more particles per node) whose
   // supports span at most kSweepMaxNM nodes per axis: the particle sweep
   // (autotuned on the served 1e9-point trace, 108 requests: the sweep is
   // fastest in 8 of the 10 keys from 1 particle per node up, by 1.6-7x at
-  // 16 or more; below 1, bricks or 4x4x4 tiles)
-  if (uniform && sweep_ok && dens >= 4) return kSweepShape;
+  // 16 or more; below 1, bricks or 4x4x4 tiles). Supports of radius 2
+  // spacings or more give each particle 30 or more nodes, which pays for
+  // the sweep's per-box costs from half a particle per node (measured on a
+  // 100M cloud at 256^3 and radius 2.55 spacings: a box of side 0.5 at 0.8
+  // particles per node, 2.1 ms in the sweep vs 2.9 in tiles and 4.2 in
+  // bricks; at radius 1.27 and 0.74 particles per node bricks still win)
+  if (uniform && sweep_ok && (dens >= 4 || (dens == 3 && hs_bucket >= 5)))
+    return kSweepShape;
+  if (uniform && dens < 4) return kBrickShape;
   // Dense ROIs keep wavefront tiles, by support/spacing ratio: below 0.5 a
   // particle reaches at most one node, so one node per wavefront reads only
   // the particles near nodes (where a node's support holds many particles);

@@ -49,10 +49,17 @@ def test_sweep_c1_full_grid_counts_and_bricks(ctx, torch):
         bw="roi_scaled", h=(0.02,) * 3),
     # supports under half a spacing (one node per axis at most) ...
     Roi((0, 0, 0), (1, 1, 1), (41, 41, 41), kernel="epanechnikov", bw="fixed", h=(0.01,) * 3),
-    # ... and spanning the widest the sweep takes (5 nodes per axis)
+    # ... and spanning 5, 6, 7 and 8 nodes per axis (8 is the widest the
+    # sweep takes) ...
     Roi((0, 0, 0), (1, 1, 1), (21, 21, 21), kernel="epanechnikov", bw="fixed", h=(0.12,) * 3),
     Roi((0.05, 0.05, 0.05), (0.95, 0.95, 0.95), (19, 19, 19), kernel="gauss_trunc3",
         bw="fixed", h=(0.039,) * 3),
+    Roi((0, 0, 0), (1, 1, 1), (21, 21, 21), kernel="epanechnikov", bw="fixed", h=(0.13,) * 3),
+    Roi((0.05, 0.05, 0.05), (0.95, 0.95, 0.95), (25, 23, 21), kernel="gauss_trunc3",
+        bw="fixed", h=(0.04, 0.035, 0.045)),
+    Roi((0.1, 0.0, 0.05), (0.9, 1.0, 0.95), (18, 22, 20), kernel="epanechnikov",
+        bw="roi_scaled", h=(0.16,) * 3),
+    Roi((0, 0, 0), (1, 1, 1), (21, 21, 21), kernel="epanechnikov", bw="fixed", h=(0.18,) * 3),
     # a box smaller than one spacing of the cloud's structure, 2 nodes on an axis
     Roi((0.45, 0.45, 0.45), (0.47, 0.46, 0.48), (2, 3, 2), kernel="epanechnikov", bw="fixed",
         h=(0.01,) * 3),
@@ -65,6 +72,25 @@ def test_sweep_vs_oracle_and_bricks(ctx, torch, roi):
     assert np.array_equal(cnt, oracle.support_counts(pts, roi))
     brk, bcnt = _eval(ctx, torch, tree, roi, BRICK)
     assert np.array_equal(got, brk) and np.array_equal(cnt, bcnt)
+    tree.close()
+
+
+def test_sweep_forced_past_its_widest_takes_the_default(ctx, torch):
+    # supports spanning 9 nodes per axis: a forced sweep runs the default
+    # shape instead (tiles here), with the default's result bit for bit
+    pts = synth.c1_cloud(2)
+    tree = ctx.build_tree(dev(torch, pts))
+    roi = Roi((0, 0, 0), (1, 1, 1), (21, 21, 21), kernel="epanechnikov", bw="fixed",
+              h=(0.2,) * 3)
+    got, cnt = _eval(ctx, torch, tree, roi, SWEEP)
+    check_density(got, oracle.density(pts, roi), "forced sweep, 9 nodes")
+    assert np.array_equal(cnt, oracle.support_counts(pts, roi))
+    ref, _ = _eval(ctx, torch, tree, roi, 0)
+    assert np.array_equal(got, ref)
+    ctx.set_eval_opts(tile_shape=SWEEP)
+    shape, _, _ = ctx.debug_tile_leaves(tree, roi)
+    ctx.set_eval_opts()
+    assert tuple(shape) != (8, 8, 8)
     tree.close()
 
 
