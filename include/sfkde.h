@@ -195,8 +195,10 @@ sfk_status sfk_eval_roi(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi, void* hi
 sfk_status sfk_eval_roi_noalloc(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 void* hip_stream);
 
-/* Evaluate a batch of ROIs with uneven grids in one persistent, work-stealing
- * launch on one of the context's streams. The descriptors are copied; the
+/* Evaluate a batch of ROIs with uneven grids on one of the context's streams:
+ * one persistent, work-stealing launch per group of ROIs that share the
+ * kernel, bandwidth mode, tile shape and (for the particle sweep) node span,
+ * the groups one after another. The descriptors are copied; the
  * d_out buffers must stay valid until the ticket completes. Returns with a
  * ticket without waiting for the batch to run, except when a free slot's
  * buffers must grow for the batch: replacing a workspace or staging buffer
@@ -204,7 +206,7 @@ sfk_status sfk_eval_roi_noalloc(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
  * release themselves may synchronise the device. Batches that fit the slots'
  * buffers (every batch after a warm-up of the largest shape) never block.
  * SFK_E_BUDGET if the batch's workspace exceeds the budget.
- * A batch of one (kernel, bandwidth) group replays the slot's captured
+ * A batch of one group replays the slot's captured
  * hipGraph (descriptor copy -> node coordinates -> tile range query -> work
  * plan -> leaf lists -> evaluation -> header readback), recaptured only when
  * the batch outgrows the graph's buffers. */
