@@ -1011,6 +1011,19 @@ __device__ __forceinline__ unsigned int splat_units(double v) {
   return (unsigned int)fma(fmax(v, 0.0), kSplatUnit, 0.5);
 }
 
+// The Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2 in fixed point, from the
+// units of its two parts: the row part a = 1 - (ux^2 + uy^2) counts
+// splat_units(a) (at most 2^31), uz^2 counts floor(uz^2 2^31 + 1/2) saturated
+// at 2^32 - 1, and the term is their difference, 0 when it is not positive
+// (one saturating subtraction per node; a pair outside the support counts 0
+// up to one unit at its edge).
+__device__ __forceinline__ unsigned int epan_z_units(double sz) {
+  return (unsigned int)fmin(fma(sz, kSplatUnit, 0.5), 4294967295.0);
+}
+__device__ __forceinline__ unsigned int epan_units(unsigned int row, unsigned int z) {
+  return row > z ? row - z : 0u;
+}
+
 // One wave claims the next work item (XCD-aware slices as in k_eval); -1
 // when every slice is exhausted. `cur` carries the wave's current slice.
 __device__ __forceinline__ int64_t claim_item(int32_t* __restrict__ claims, int64_t n_items,
@@ -1119,6 +1132,7 @@ __global__ __launch_bounds__(256) void k_splat(
         kz = kz > b[2] ? kz - nz : kz;
         const double uz = (lds_c[2][kz] - pp[2]) * ih[2];
         const double sz = uz * uz;
+        const unsigned int zq = epan_z_units(sz);
         for (int dy = 0; dy < ny; ++dy) {
           int jy = a[1] + dy + ry;
           jy = jy > b[1] ? jy - ny : jy;
@@ -1132,7 +1146,7 @@ __global__ __launch_bounds__(256) void k_splat(
             const double ux = (lds_c[0][ix] - pp[0]) * ih[0];
             if constexpr (KK == KK_EPAN && !CNT) {
               // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2, quantised
-              const unsigned int q = splat_units((1.0 - (ux * ux + sy)) - sz);
+              const unsigned int q = epan_units(splat_units(1.0 - (ux * ux + sy)), zq);
               if (q != 0u) atomicAdd(&sums[row + ((ix + sw) & (B - 1))], (unsigned long long)q);
             } else {
               const double u2 = (ux * ux + sy) + sz;
@@ -1249,8 +1263,9 @@ __global__ __launch_bounds__(256) void k_splat(
 // brick's terms and fixed point (the same operations in the same order)
 // and LDS atomics into private copies of the window (lane l adds to copy
 // l mod ncp), then adds the window's nonzero sums into the batch's 64-bit
-// node sums with global atomics. Per node row the Epanechnikov term takes
-// one subtraction from 1 - (ux^2 + uy^2), with no membership branch.
+// node sums with global atomics. Per node the Epanechnikov term is one
+// saturating subtraction of fixed-point units (those of 1 - (ux^2 + uy^2),
+// taken once per node row, minus those of uz^2), with no membership branch.
 // Integer sums make
 // the grid independent of the order of items, particles and workgroups, and
 // equal to the brick's grid bit for bit. Lanes of a wavefront take
@@ -1504,6 +1519,9 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
               // 0 (no add), so the inner loop needs no range test
               sz[m] = m < n[2] ? uz * uz : kSweepFar;
             }
+            unsigned int zq[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) zq[m] = epan_z_units(sz[m]);
 #pragma unroll
             for (int my = 0; my < NM; ++my) {
 #pragma unroll
@@ -1514,11 +1532,11 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                   if constexpr (KK == KK_EPAN && !CNT) {
                     // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2,
                     // quantised: no membership test (a non-member's term
-                    // is <= 0 and counts 0)
-                    const double arow = 1.0 - sxy;
+                    // counts 0); one saturating subtraction per node
+                    const unsigned int aq = splat_units(1.0 - sxy);
 #pragma unroll
                     for (int mz = 0; mz < NM; ++mz) {
-                      const unsigned int q = splat_units(arow - sz[mz]);
+                      const unsigned int q = epan_units(aq, zq[mz]);
                       if (q != 0u) atomicAdd(&sums[row + mz], (unsigned long long)q);
                     }
                   } else {
