@@ -1371,7 +1371,10 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
   // the window's node sums, z fastest, with an odd x stride (W^2 + 1 at
   // most) so that threads reading consecutive x fall in different banks
   constexpr int WN = W * (W * W + 1);
-  __shared__ unsigned long long sums[WN];
+  // (the Epanechnikov adds of spans up to 3 nodes are unmasked: a
+  // particle's nodes past its z range add 0 up to kSweepMaxNM - 1 words past
+  // a copy, hence the padding, which is never read)
+  __shared__ unsigned long long sums[WN + kSweepMaxNM];
   // node coordinates of a block, with kSweepMaxNM more past its end so the
   // unrolled per-particle loops read them without clamping
   constexpr int WC = W + kSweepMaxNM;
@@ -1533,11 +1536,17 @@ __global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __re
                     // the Epanechnikov term (1 - (ux^2 + uy^2)) - uz^2,
                     // quantised: no membership test (a non-member's term
                     // counts 0); one saturating subtraction per node
+                    // Up to 3 nodes per axis every lane adds, a zero where
+                    // its term is 0 (no lane mask per node; the LDS has room
+                    // for the extra adds). Wider spans add only nonzero
+                    // terms: with 216 or more pairs per particle the unmasked
+                    // adds made the LDS the bound (6 nodes: 5.9 -> 10 ms on
+                    // a full 100M-point box at 256^3).
                     const unsigned int aq = splat_units(1.0 - sxy);
 #pragma unroll
                     for (int mz = 0; mz < NM; ++mz) {
                       const unsigned int q = epan_units(aq, zq[mz]);
-                      if (q != 0u) atomicAdd(&sums[row + mz], (unsigned long long)q);
+                      if (NM <= 3 || q != 0u) atomicAdd(&sums[row + mz], (unsigned long long)q);
                     }
                   } else {
 #pragma unroll
