@@ -1361,12 +1361,18 @@ __global__ __launch_bounds__(256) void k_sweep_list(TreeView tv, BatchHdr* __res
 }
 
 template <int KK, bool CNT, int NM>
-__global__ __launch_bounds__(256) void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 1 ? 6 : 1)))
+void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
                                                const RoiDev* __restrict__ rois,
                                                const int64_t* __restrict__ items,
                                                unsigned long long* __restrict__ acc,
                                                int32_t* __restrict__ claims) {
-  constexpr int W = kSweepWin;
+  // Windows of 1-node spans are blocked at 8^3 nodes: their boxes' windows
+  // seldom exceed that, and the smaller LDS array lets 6 blocks share a CU
+  // (the register bound) to hide more of the memory latency these light
+  // particles wait on (2-node spans lost more to re-read blocks than they
+  // gained).
+  constexpr int W = NM == 1 ? kSweepWin / 2 : kSweepWin;
   constexpr int S = kSweep;
   // the window's node sums, z fastest, with an odd x stride (W^2 + 1 at
   // most) so that threads reading consecutive x fall in different banks
