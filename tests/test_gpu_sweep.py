@@ -109,14 +109,20 @@ def test_sweep_tree_of_few_leaves(ctx, torch):
     tree.close()
 
 
-def test_sweep_wide_windows_in_blocks(ctx, torch):
+@pytest.mark.parametrize("roi", [
+    # 2-node supports: windows blocked at 16^3 nodes
+    Roi((0, 0, 0), (1, 1, 1), (160, 150, 140), kernel="epanechnikov", bw="fixed",
+        h=(0.004, 0.004, 0.0045)),
+    # 1-node supports: windows blocked at 8^3 nodes
+    Roi((0, 0, 0), (1, 1, 1), (200, 190, 180), kernel="epanechnikov", bw="fixed",
+        h=(0.002, 0.002, 0.0022)),
+])
+def test_sweep_wide_windows_in_blocks(ctx, torch, roi):
     # fine grids over sparse regions: the 4096-particle boxes of the uniform
     # background span tens of nodes per axis, so their windows are swept in
-    # blocks of 16^3 nodes, each reading the box again
+    # blocks, each reading the box again
     pts = synth.clumpy_cloud(400_000, 6)
     tree = ctx.build_tree(dev(torch, pts))
-    roi = Roi((0, 0, 0), (1, 1, 1), (160, 150, 140), kernel="epanechnikov", bw="fixed",
-              h=(0.004, 0.004, 0.0045))
     got, cnt = _eval(ctx, torch, tree, roi, SWEEP)
     brk, bcnt = _eval(ctx, torch, tree, roi, BRICK)
     assert np.array_equal(got, brk) and np.array_equal(cnt, bcnt)
