@@ -1496,16 +1496,22 @@ void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
               }
               if (!ok) return;
             } else {
+              // the ranges of all three axes first, one exit, then the
+              // conversions (no lane mask per axis)
+              double fa[3], fb[3];
 #pragma unroll
               for (int k = 0; k < 3; ++k) {
                 const double ic = (pp[k] - lo[k]) * inv_s[k];
-                const double fa = fmax(ceil(ic - half[k]), (double)blk0[k]);
-                const double fb = fmin(floor(ic + half[k]), (double)(blk0[k] + nbk[k] - 1));
-                ok &= fa <= fb;
-                a[k] = ok ? (int)fa - blk0[k] : 0;
-                n[k] = ok ? (int)(fb - fa) + 1 : 0;
+                fa[k] = fmax(ceil(ic - half[k]), (double)blk0[k]);
+                fb[k] = fmin(floor(ic + half[k]), (double)(blk0[k] + nbk[k] - 1));
+                ok &= fa[k] <= fb[k];
               }
               if (!ok) return;
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                a[k] = (int)fa[k] - blk0[k];
+                n[k] = (int)(fb[k] - fa[k]) + 1;
+              }
               if (n[0] > NM || n[1] > NM || n[2] > NM) {
                 bad = true;
                 return;
