@@ -1581,9 +1581,34 @@ void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
             }
           };
           // thread tid takes particles q = tid + 256 i of the surviving
-          // leaves in the order "leaf q mod ns, slot q / ns": the lanes of a
-          // wavefront read different leaves
-          if (ns > 0) {
+          // leaves, in one of two orders
+          if (ns > 0 && NM <= 2) {
+            // Spans of 1 and 2 nodes add few terms per particle, so the LDS
+            // atomics of one leaf's particles seldom meet (16 private copies
+            // for their small windows): consecutive lanes take consecutive
+            // particles of one leaf, and a wavefront's load is one 1 KB run
+            // instead of 64 cache lines (3-node spans lost more to meeting
+            // atomics than they gained)
+            const bool all = ns == nl;
+            const int total = ns * SFK_LEAF;
+            int q = tid;
+            if (q < total) {
+              float4 p = pts[(int64_t)(all ? q >> 6 : lds_surv[q >> 6]) * SFK_LEAF + (q & 63)];
+              while (true) {
+                const int qn = q + 256;
+                const bool more = qn < total;
+                float4 pn = p;
+                if (more) pn = pts[(int64_t)(all ? qn >> 6 : lds_surv[qn >> 6]) * SFK_LEAF + (qn & 63)];
+                splat(p);
+                if (!more) break;
+                p = pn;
+                q = qn;
+              }
+            }
+          } else if (ns > 0) {
+            // wider spans: "leaf q mod ns, slot q / ns", so the lanes of a
+            // wavefront take particles of different leaves and one
+            // instruction's atomics spread over the window
             const int step_slot = 256 / ns, step_leaf = 256 % ns;
             const bool all = ns == nl;  // every leaf reaches: no indirection
             auto leaf_id = [&](int q) { return all ? q : lds_surv[q]; };
