@@ -1266,13 +1266,14 @@ __global__ __launch_bounds__(256) void k_splat(
 // node sums with global atomics. Per node the Epanechnikov term is one
 // saturating subtraction of fixed-point units (those of 1 - (ux^2 + uy^2),
 // taken once per node row, minus those of uz^2), with no membership branch.
-// Integer sums make
-// the grid independent of the order of items, particles and workgroups, and
-// equal to the brick's grid bit for bit. Lanes of a wavefront take
-// particles of different leaves of the box, so one instruction's atomics
-// spread over the window instead of queueing on the few nodes one leaf
-// reaches. Windows wider than kSweepWin nodes on some axis are swept in
-// blocks of kSweepWin^3 nodes, each reading the box's particles again.
+// Integer sums make the grid independent of the order of items, particles
+// and workgroups, and equal to the brick's grid bit for bit. For spans of 3
+// nodes or more the lanes of a wavefront take particles of different leaves
+// of the box, so one instruction's atomics spread over the window instead
+// of queueing on the few nodes one leaf reaches; spans of 1 and 2 nodes add
+// few terms and take one leaf per wavefront, for coalesced loads. Windows
+// wider than W nodes on some axis (W = kSweepWin, half that for 1-node
+// spans) are swept in blocks of W^3 nodes, each reading the box again.
 // ---------------------------------------------------------------------------
 
 // A squared offset past any support (c^2 <= 9): the sweep gives the nodes
@@ -1360,13 +1361,13 @@ __global__ __launch_bounds__(256) void k_sweep_list(TreeView tv, BatchHdr* __res
   }
 }
 
+// (1-node spans ask for 6 waves per SIMD, their register bound without
+// spills; more waves spilled and were slower)
 template <int KK, bool CNT, int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 1 ? 6 : 1)))
-void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr,
-                                               const RoiDev* __restrict__ rois,
-                                               const int64_t* __restrict__ items,
-                                               unsigned long long* __restrict__ acc,
-                                               int32_t* __restrict__ claims) {
+void k_sweep(TreeView tv, const BatchHdr* __restrict__ hdr, const RoiDev* __restrict__ rois,
+             const int64_t* __restrict__ items, unsigned long long* __restrict__ acc,
+             int32_t* __restrict__ claims) {
   // Windows of 1-node spans are blocked at 8^3 nodes: their boxes' windows
   // seldom exceed that, and the smaller LDS array lets 6 blocks share a CU
   // (the register bound) to hide more of the memory latency these light
