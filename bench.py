@@ -142,6 +142,10 @@ def parse():
                         "served workload (the same trace windows; no warm-up, comparison "
                         "passes, checks or sub-records), so the evaluation kernels of the run "
                         "are exactly the timed launches")
+    p.add_argument("--profile-section", choices=["zoom", "batch"],
+                   help="for counter runs: only the nested-zoom series or only the 256-ROI "
+                        "batch comparison on the 100M cloud (no served workload, no other "
+                        "sub-record); prints that record")
     a = p.parse_args()
     if a.profile_served:
         a.no_realtime = a.no_cpu_baseline = a.no_per_point = a.no_batch = a.no_zoom = True
@@ -839,6 +843,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = sfk.Context(0)
+    if args.profile_section:
+        def only(t, lab, info):
+            if args.profile_section == "batch":
+                return {"batch_vs_single": batch_vs_single(ctx, t, torch, args.n_batch, lab)}
+            return {"nested_zoom": nested_zoom(ctx, t, torch, lab, info)}
+        rec = large_section(ctx, torch, args.batch_points, 3, only)
+        ctx.close()
+        print(json.dumps({"profile_section": args.profile_section, **rec}), flush=True)
+        return
     result = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
