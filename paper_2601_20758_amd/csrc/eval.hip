@@ -1165,6 +1165,48 @@ __global__ __launch_bounds__(256) void k_splat(
         }
       }
     };
+    // Listed leaves: a leaf's particles that reach the brick (the same
+    // outward-rounded ranges as splat) are queued and scattered 64 at a time,
+    // so every lane has a particle. In the leaves of sparse and deep ROIs
+    // most particles reach no node of the brick, and a lane per leaf
+    // particle left most lanes idle. The order of the integer adds does not
+    // change the sums. The queue (particle indices, at most 127) lives in the
+    // wave's traversal stack, which listed leaves do not use.
+    uint32_t* qi = reinterpret_cast<uint32_t*>(lds_stack[wave]);
+    static_assert(SFK_STACK >= 2 * SFK_LEAF, "the queue shares the traversal stack");
+    int qn = 0;
+    auto reaches = [&](const float4 p) {
+      const double pp[3] = {(double)p.x, (double)p.y, (double)p.z};
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double ic = (pp[k] - lo[k]) * inv_s[k] - (double)org[k];
+        ok &= fmax(ceil(ic - half[k]), 0.0) <= fmin(floor(ic + half[k]), (double)(n_here[k] - 1));
+      }
+      return ok;
+    };
+    auto offer = [&](const float4 p, int64_t idx) {
+      const bool ok = reaches(p);
+      const uint64_t m = ballot(ok);
+      if (ok) qi[qn + popc64(m & lanemask_lt())] = (uint32_t)idx;
+      qn += popc64(m);
+      wave_sync();
+      if (qn >= 64) {
+        const uint32_t mine = qi[lane];
+        for (int e = lane; e + 64 < qn; e += 64) qi[e] = qi[e + 64];
+        qn -= 64;
+        wave_sync();
+        splat(tv.pts[mine]);
+      }
+    };
+    auto drain_rest = [&]() {
+      if (qn == 0) return;
+      const bool have = lane < qn;
+      const uint32_t mine = have ? qi[lane] : 0u;
+      qn = 0;
+      wave_sync();
+      if (have) splat(tv.pts[mine]);
+    };
     auto do_leaf = [&](int lid) {
       const float4 p = tv.pts[(int64_t)lid * SFK_LEAF + lane];
       splat(p);
@@ -1187,16 +1229,23 @@ __global__ __launch_bounds__(256) void k_splat(
         }
         return __builtin_amdgcn_readfirstlane(lid);
       };
-      // the next leaf's particle is in flight while this one is scattered
+      // the next leaf's particle is in flight while this one is offered
       if (lb + wave < le) {
-        float4 p = tv.pts[(int64_t)leaf_at(lb + wave) * SFK_LEAF + lane];
+        int64_t idx = (int64_t)leaf_at(lb + wave) * SFK_LEAF + lane;
+        float4 p = tv.pts[idx];
         for (int64_t q = lb + wave; q < le; q += 4) {
           float4 pn = p;
-          if (q + 4 < le) pn = tv.pts[(int64_t)leaf_at(q + 4) * SFK_LEAF + lane];
-          splat(p);
+          int64_t nidx = idx;
+          if (q + 4 < le) {
+            nidx = (int64_t)leaf_at(q + 4) * SFK_LEAF + lane;
+            pn = tv.pts[nidx];
+          }
+          offer(p, idx);
           p = pn;
+          idx = nidx;
         }
       }
+      drain_rest();
     } else {
       // walking modes: every wave walks the hierarchy (same order) and takes
       // every fourth leaf of the item's range
