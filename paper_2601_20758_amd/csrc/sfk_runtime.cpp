@@ -1581,7 +1581,14 @@ int default_shape(int key, double particles_per_support, bool sweep_ok) {
   // bricks; at radius 1.27 and 0.74 particles per node bricks still win)
   if (uniform && sweep_ok && (dens >= 4 || (dens == 3 && hs_bucket >= 5)))
     return kSweepShape;
-  if (uniform && dens < 4) return kBrickShape;
+  // Supports of radius 2 spacings or more from 1/8 to 1/2 particle per node
+  // take 4x4x4 tiles (shape 1): a 100M cloud at 256^3, box of side 1/4, 1.97
+  // ms vs 2.41 in bricks. Sparser ROIs keep bricks (side 1/16: 0.95 vs 1.63
+  // ms). (Radius 1-2 spacings at 1/2 to 1 particle per node also favoured
+  // tiles on zoom boxes, but the served trace and the 256-ROI batch, whose
+  // requests fall there, were faster with bricks: 5.52e11 vs 5.42e11 evals/s
+  // and 12.7 vs 13.6 ms.)
+  if (uniform && dens < 4) return dens >= 1 && hs_bucket >= 5 ? 1 : kBrickShape;
   // Dense ROIs keep wavefront tiles, by support/spacing ratio: below 0.5 a
   // particle reaches at most one node, so one node per wavefront reads only
   // the particles near nodes (where a node's support holds many particles);
