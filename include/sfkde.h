@@ -578,6 +578,14 @@ sfk_status sfk_debug_mc_case(int32_t cs, int8_t* h_edges, int32_t* n_tri);
  * boxes x 4096 particles x the unrolled node span NM^3, an upper bound). */
 sfk_status sfk_debug_eval_count(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                 int64_t* useful_pairs, int64_t* tested_pairs);
+/* Host-only: the tree's estimate of its particles in the closed box
+ * [h_lo, h_hi] (3 doubles each, h_lo <= h_hi), as the runtime uses it to
+ * choose tile shapes and to cap serving batches: the counts of the finest
+ * host-held box level spread over a 32^3 lattice on the tree's bounding box
+ * and summed (evenly within each cell). SFK_E_INVAL on a NULL or non-finite
+ * argument or h_lo > h_hi. */
+sfk_status sfk_debug_particle_estimate(sfk_ctx ctx, sfk_tree tree, const double* h_lo,
+                                       const double* h_hi, double* particles);
 /* Per-node support counts #S(n) (res product floats, device, x fastest). */
 sfk_status sfk_debug_support_counts(sfk_ctx ctx, sfk_tree tree, const sfk_roi* roi,
                                     float* d_counts, void* hip_stream);

@@ -461,6 +461,16 @@ class Context:
         self._check(self._lib.sfk_debug_tree_order(self._h, tree._h, out.ctypes.data))
         return out[:n]
 
+    def debug_particle_estimate(self, tree: "Tree", lo, hi) -> float:
+        """sfk_debug_particle_estimate: the tree's particle estimate for the
+        closed box [lo, hi]."""
+        a = np.ascontiguousarray(lo, dtype=np.float64)
+        b = np.ascontiguousarray(hi, dtype=np.float64)
+        out = C.c_double()
+        self._check(self._lib.sfk_debug_particle_estimate(self._h, tree._h, a.ctypes.data,
+                                                          b.ctypes.data, C.byref(out)))
+        return out.value
+
     def debug_eval_count(self, tree: "Tree", roi):
         u = C.c_int64()
         t = C.c_int64()

@@ -167,6 +167,8 @@ EXPORTS = {
     "sfk_debug_leaf_boxes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_tree_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sfk_debug_curve_keys": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
+    "sfk_debug_particle_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.POINTER(C.c_double)]),
     "sfk_debug_eval_count": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sfk_debug_support_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RoiC), C.c_void_p,

@@ -2869,6 +2869,24 @@ sfk_status sfk_debug_support_counts(sfk_ctx c, sfk_tree t, const sfk_roi* roi, f
   SFK_GUARD_END(c)
 }
 
+sfk_status sfk_debug_particle_estimate(sfk_ctx c, sfk_tree t, const double* lo, const double* hi,
+                                       double* particles) {
+  SFK_GUARD_BEGIN
+  SFK_TRY(check_ctx(c));
+  if (!t || !lo || !hi || !particles) {
+    set_err(c, "NULL argument");
+    return SFK_E_INVAL;
+  }
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || lo[k] > hi[k]) {
+      set_err(c, "box must be finite with lo <= hi");
+      return SFK_E_INVAL;
+    }
+  *particles = est_particles(t, lo, hi);
+  return SFK_OK;
+  SFK_GUARD_END(c)
+}
+
 sfk_status sfk_debug_eval_count(sfk_ctx c, sfk_tree t, const sfk_roi* roi, int64_t* useful_pairs,
                                 int64_t* tested_pairs) {
   SFK_GUARD_BEGIN
