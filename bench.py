@@ -262,6 +262,8 @@ def batch_vs_single(ctx, tree, torch, n_rois, label):
         "nodes": int(sum(r.n_nodes for r in rois)), "useful_evals": int(useful),
         "batched_ms": batch_ms, "single_launch_ms": single_ms,
         "batched_evals_per_s": useful / (batch_ms * 1e-3),
+        "batched_frac_of_valu_ceiling": useful / (batch_ms * 1e-3)
+                                        * SLOTS_PER_EVAL["epanechnikov"] / VALU_SLOTS_PER_S,
         "single_launch_evals_per_s": useful / (single_ms * 1e-3),
         "speedup": single_ms / batch_ms,
         "single_launch_latency_p50_ms": float(np.percentile(lat_single, 50)),
